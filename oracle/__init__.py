@@ -1,0 +1,233 @@
+"""CPU reference (oracle) for TPC sector track finding -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It loads `oracle/_oracle.so`, built from
+`oracle/tpc_oracle.c` (plain C, FP64 fit, int64 decisions), and shares nothing
+with the HIP library: it is handed the same input arrays and the same
+parameter values (a plain dict) and computes everything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(HERE, "tpc_oracle.c")
+_LIB = os.path.join(HERE, "_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c11", "-D_POSIX_C_SOURCE=200809L",
+                               "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("q_shift", ctypes.c_int32), ("tan_half_q16", ctypes.c_int32),
+        ("bin_y_q", ctypes.c_int32), ("bin_occ", ctypes.c_int32), ("bin_zmin_q", ctypes.c_int32),
+        ("win_y_q", ctypes.c_int32), ("win_z_q", ctypes.c_int32),
+        ("w_y", ctypes.c_int32), ("w_z", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("smax_k", ctypes.c_int64),
+        ("l_min", ctypes.c_int32), ("ext_win_y_q", ctypes.c_int32), ("ext_win_z_q", ctypes.c_int32),
+        ("ext_edge_q", ctypes.c_int32), ("max_miss", ctypes.c_int32), ("n_min", ctypes.c_int32),
+        ("f_min_q8", ctypes.c_int32), ("brute", ctypes.c_int32),
+        ("sinphi_max", ctypes.c_double), ("sigma_y", ctypes.c_double), ("sigma_z", ctypes.c_double),
+        ("cov0", ctypes.c_double * 5), ("fragile_eps", ctypes.c_double),
+    ]
+
+
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_U32P = ctypes.POINTER(ctypes.c_uint32)
+_F64P = ctypes.POINTER(ctypes.c_double)
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("n_units", ctypes.c_int64), ("n_rows", ctypes.c_int64),
+        ("n_seg", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("n_tracklets", ctypes.c_int64),
+        ("n_tracks", ctypes.c_int64), ("n_track_hits", ctypes.c_int64),
+        ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("perm", _I32P), ("up", _I32P), ("dn", _I32P), ("upc", _I32P), ("dnc", _I32P),
+        ("owner", _U32P), ("cluster_track", _I32P),
+        ("seg_start", _I32P), ("seg_count", _I32P), ("seg_zmin", _I32P), ("seg_zmax", _I32P),
+        ("seg_ny", _I32P), ("seg_nz", _I32P), ("seg_by", _I32P), ("seg_bz", _I32P),
+        ("seg_cell_base", _I32P), ("cell_start", _I32P),
+        ("trk_start", _I32P), ("trk_unit", _I32P), ("trk_len", _I32P), ("trk_nfit", _I32P),
+        ("trk_p1n", _I32P), ("trk_owned", _I32P), ("trk_keep", _I32P), ("trk_fragile", _I32P),
+        ("trk_key", _U32P),
+        ("trk_params", _F64P), ("trk_cov", _F64P), ("trk_xref", _F64P), ("trk_chi2", _F64P),
+        ("trk_hits", _I32P),
+        ("track_tracklet", _I32P), ("track_first_hit", _I32P), ("track_n_hits", _I32P),
+        ("track_hits", _I32P),
+        ("time_s", ctypes.c_double * 8),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        vp = ctypes.c_void_p
+        lib.orc_run.restype = ctypes.c_int
+        lib.orc_run.argtypes = [ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int64, vp,
+                                ctypes.c_float, ctypes.POINTER(Params), ctypes.POINTER(_Result)]
+        lib.orc_free.argtypes = [ctypes.POINTER(_Result)]
+        lib.orc_propagate.restype = ctypes.c_int
+        lib.orc_propagate.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, vp, vp]
+        lib.orc_seed.restype = ctypes.c_int
+        lib.orc_seed.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
+        lib.orc_fit_two_pass.restype = ctypes.c_int
+        lib.orc_fit_two_pass.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_double,
+                                         ctypes.POINTER(Params), vp, vp, vp, vp]
+        lib.orc_kf_update.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, vp]
+        lib.orc_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def make_params(values: dict, brute: bool = False, fragile_eps: float = 0.0) -> Params:
+    """Oracle parameter block from a plain dict of parameter values."""
+    p = Params()
+    for name in ("q_shift", "tan_half_q16", "bin_y_q", "bin_occ", "bin_zmin_q", "win_y_q",
+                 "win_z_q", "w_y", "w_z", "smax_k", "l_min", "ext_win_y_q", "ext_win_z_q",
+                 "ext_edge_q", "max_miss", "n_min", "f_min_q8"):
+        setattr(p, name, int(values[name]))
+    # float parameters are float32 values; the oracle reads their exact doubles
+    for name in ("sinphi_max", "sigma_y", "sigma_z"):
+        setattr(p, name, float(np.float32(values[name])))
+    for i, v in enumerate(values["cov0"]):
+        p.cov0[i] = float(np.float32(v))
+    p.brute = 1 if brute else 0
+    p.fragile_eps = float(fragile_eps)
+    return p
+
+
+def _arr(ptr, n, dtype):
+    if n == 0 or not ptr:
+        return np.zeros(0, dtype)
+    return np.ctypeslib.as_array(ptr, shape=(int(n),)).astype(dtype, copy=True)
+
+
+def run(y, z, row, unit_offsets, row_x, bz, values: dict, brute=False, fragile_eps=0.0):
+    """Run the reference on host arrays.  Returns a dict of numpy arrays (see
+    orc_result_t in tpc_oracle.c), or raises ValueError on invalid input."""
+    lib = _load()
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    row = np.ascontiguousarray(row, np.uint16)
+    off = np.ascontiguousarray(unit_offsets, np.int64)
+    rx = np.ascontiguousarray(row_x, np.float32)
+    P = make_params(values, brute, fragile_eps)
+    R = _Result()
+    st = lib.orc_run(len(y), len(off) - 1, off.ctypes.data, y.ctypes.data, z.ctypes.data,
+                     row.ctypes.data, len(rx), rx.ctypes.data, ctypes.c_float(bz),
+                     ctypes.byref(P), ctypes.byref(R))
+    if st != 0:
+        lib.orc_free(ctypes.byref(R))
+        raise ValueError("oracle: invalid input (status %d)" % st)
+    n, S, C, K, T, TH, NR = (R.n, R.n_seg, R.n_cells, R.n_tracklets, R.n_tracks, R.n_track_hits,
+                             R.n_rows)
+    out = dict(n=n, n_seg=S, n_cells=C, n_tracklets=K, n_tracks=T, n_track_hits=TH,
+               time_s=np.array(R.time_s[:]))
+    for f in ("perm", "up", "dn", "upc", "dnc"):
+        out[f] = _arr(getattr(R, f), n, np.int32)
+    out["owner"] = _arr(R.owner, n, np.uint32)
+    out["cluster_track"] = _arr(R.cluster_track, n, np.int32)
+    for f in ("seg_start", "seg_count", "seg_zmin", "seg_zmax", "seg_ny", "seg_nz", "seg_by",
+              "seg_bz", "seg_cell_base"):
+        out[f] = _arr(getattr(R, f), S, np.int32)
+    out["cell_start"] = _arr(R.cell_start, C + 1, np.int32)
+    for f in ("trk_start", "trk_unit", "trk_len", "trk_nfit", "trk_p1n", "trk_owned", "trk_keep",
+              "trk_fragile"):
+        out[f] = _arr(getattr(R, f), K, np.int32)
+    out["trk_key"] = _arr(R.trk_key, K, np.uint32)
+    out["trk_params"] = _arr(R.trk_params, K * 5, np.float64).reshape(K, 5)
+    out["trk_cov"] = _arr(R.trk_cov, K * 15, np.float64).reshape(K, 15)
+    out["trk_xref"] = _arr(R.trk_xref, K, np.float64)
+    out["trk_chi2"] = _arr(R.trk_chi2, K, np.float64)
+    out["trk_hits"] = _arr(R.trk_hits, K * NR, np.int32).reshape(K, NR)
+    for f in ("track_tracklet", "track_first_hit", "track_n_hits"):
+        out[f] = _arr(getattr(R, f), T, np.int32)
+    out["track_hits"] = _arr(R.track_hits, TH, np.int32)
+    lib.orc_free(ctypes.byref(R))
+    return out
+
+
+def run_event(ev, values: dict, **kw):
+    return run(ev.y, ev.z, ev.row, ev.unit_offsets, ev.row_x, ev.bz, values, **kw)
+
+
+# ---- single-step helpers used by the pins ---------------------------------------
+
+def propagate(p, x1, x2, k, sinphi_max=0.95, jacobian=False):
+    lib = _load()
+    p = np.ascontiguousarray(p, np.float64)
+    out = np.zeros(5)
+    F = np.zeros(25)
+    st = lib.orc_propagate(p.ctypes.data, x1, x2, k, sinphi_max, out.ctypes.data,
+                           F.ctypes.data if jacobian else None)
+    if st != 0:
+        return None if not jacobian else (None, None)
+    return (out, F.reshape(5, 5)) if jacobian else out
+
+
+def seed(x, y, z, k, sinphi_max=0.95):
+    lib = _load()
+    x, y, z = (np.ascontiguousarray(a, np.float64) for a in (x, y, z))
+    p = np.zeros(5)
+    st = lib.orc_seed(x.ctypes.data, y.ctypes.data, z.ctypes.data, k, sinphi_max, p.ctypes.data)
+    return p if st == 0 else None
+
+
+def fit_two_pass(x, y, z, k, values: dict):
+    lib = _load()
+    x, y, z = (np.ascontiguousarray(a, np.float64) for a in (x, y, z))
+    P = make_params(values)
+    p = np.zeros(5)
+    cov = np.zeros(15)
+    chi2 = np.zeros(1)
+    p1 = np.zeros(5)
+    st = lib.orc_fit_two_pass(len(x), x.ctypes.data, y.ctypes.data, z.ctypes.data, k,
+                              ctypes.byref(P), p.ctypes.data, cov.ctypes.data, chi2.ctypes.data,
+                              p1.ctypes.data)
+    if st != 0:
+        return None
+    return dict(p=p, cov=cov, chi2=float(chi2[0]), p_pass1=p1)
+
+
+def kf_update(p, cov15, my, mz, sy, sz):
+    lib = _load()
+    p = np.array(p, np.float64)
+    c = np.array(cov15, np.float64)
+    chi2 = np.zeros(1)
+    lib.orc_kf_update(p.ctypes.data, c.ctypes.data, my, mz, sy, sz, chi2.ctypes.data)
+    return p, c, float(chi2[0])
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def unpack_cov(c15):
+    """15 packed lower-triangle entries (row-major, (i,j<=i)) -> symmetric 5x5."""
+    M = np.zeros((5, 5))
+    k = 0
+    for i in range(5):
+        for j in range(i + 1):
+            M[i, j] = M[j, i] = c15[k]
+            k += 1
+    return M

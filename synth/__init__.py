@@ -1,0 +1,386 @@
+"""Seeded synthetic TPC inputs shaped like the workloads of arXiv 2106.03636.
+
+The paper's inputs are ALICE Pb-Pb / pp time frames (paper §2, §3.1.3, §3.2),
+which are not available; these generators stand in for them.  They produce
+TPC clusters of closed-form helices crossing the pad rows of 2 x 18 sectors,
+smeared, plus uniform noise, and in continuous-readout form (collision times
+spread over a slice and folded into z as the paper's §2 describes: a time
+shift appears as a shift along the beam axis).
+
+This module holds no step of the tracking method: it only draws random
+numbers (numpy PCG64) and evaluates helix / pad-row intersections (in C, for
+speed).  Both the HIP path and the CPU oracle consume its output.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "_crossings.so")
+
+# --- detector geometry -------------------------------------------------------
+N_ROWS = 152
+N_SECTORS = 36
+ROW_X0, ROW_X1 = 85.0, 247.0
+ROW_X_F32 = (ROW_X0 + np.arange(N_ROWS, dtype=np.float64) * (ROW_X1 - ROW_X0) / (N_ROWS - 1)).astype(np.float32)
+ROW_X = ROW_X_F32.astype(np.float64)  # the row planes sit exactly at the float32 positions
+HALF_OPEN_DEG = 10.0
+TAN_HALF = math.tan(math.radians(HALF_OPEN_DEG))
+Z_MAX = 250.0  # drift length, cm
+V_DRIFT = 2.58  # cm / us
+KAPPA = 0.00299792458  # GeV / (T cm)
+SIGMA_Y, SIGMA_Z = 0.1, 0.15  # cm
+VERTEX_SIGMA = (0.01, 0.01, 5.0)
+NOISE_FRACTION = 0.05
+ETA_MAX = 0.9
+
+
+def sector_alpha(sector: int) -> float:
+    return math.radians((sector % 18) * 20.0 + 10.0)
+
+
+def build(force: bool = False) -> str:
+    """Compile the crossing routine (gcc, OpenMP) next to this file."""
+    src = os.path.join(HERE, "crossings.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        d = ctypes.POINTER(ctypes.c_double)
+        lib.synth_crossings.restype = ctypes.c_int64
+        lib.synth_crossings.argtypes = [ctypes.c_int64, d, d, d, d, d, d, ctypes.c_int, d,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Tracks:
+    """Truth of generated primaries (global frame)."""
+    vx: np.ndarray
+    vy: np.ndarray
+    vz: np.ndarray
+    pt: np.ndarray
+    phi0: np.ndarray
+    tgl: np.ndarray
+    q: np.ndarray
+    t0: np.ndarray  # collision time, us
+
+    def __len__(self):
+        return len(self.pt)
+
+    def curvature(self, bz: float) -> np.ndarray:
+        return -KAPPA * bz * self.q / self.pt
+
+    @staticmethod
+    def concat(parts):
+        return Tracks(*[np.concatenate([getattr(p, f) for p in parts]) for f in
+                        ("vx", "vy", "vz", "pt", "phi0", "tgl", "q", "t0")])
+
+
+def helix_crossings(tr: Tracks, bz: float, max_turns: float = 2.0, z_max: float = Z_MAX):
+    """All (sector, row) crossings of the helices, noise-free, FP64, true z.
+
+    Returns a dict of arrays ordered by (track, sector, row, arc length).
+    """
+    lib = _load()
+    n = len(tr)
+    args = [np.ascontiguousarray(a, dtype=np.float64) for a in
+            (tr.vx, tr.vy, tr.vz, tr.curvature(bz), tr.phi0, tr.tgl)]
+    counts = np.zeros(n, dtype=np.int64)
+    lib.synth_crossings(n, *[_dptr(a) for a in args], N_ROWS, _dptr(ROW_X), TAN_HALF, z_max,
+                        max_turns, _ptr(counts), None, None, None, None, None, None, None, None)
+    tot = int(counts.sum())
+    out = dict(sector=np.empty(tot, np.int32), row=np.empty(tot, np.int32),
+               track=np.empty(tot, np.int32), y=np.empty(tot), z=np.empty(tot),
+               s=np.empty(tot), sinphi=np.empty(tot), cosphi=np.empty(tot))
+    lib.synth_crossings(n, *[_dptr(a) for a in args], N_ROWS, _dptr(ROW_X), TAN_HALF, z_max,
+                        max_turns, _ptr(counts), _ptr(out["sector"]), _ptr(out["row"]),
+                        _ptr(out["track"]), _ptr(out["y"]), _ptr(out["z"]), _ptr(out["s"]),
+                        _ptr(out["sinphi"]), _ptr(out["cosphi"]))
+    return out
+
+
+# --- primaries ----------------------------------------------------------------
+
+def _eta_to_tgl(eta):
+    return np.sinh(eta)
+
+
+def _vertex(rng, n):
+    return (rng.normal(0, VERTEX_SIGMA[0], n), rng.normal(0, VERTEX_SIGMA[1], n),
+            rng.normal(0, VERTEX_SIGMA[2], n))
+
+
+def primaries_pp_sector(rng, n, sector=0, eta_range=(0.0, ETA_MAX), pt_range=(0.1, 10.0), vz=None):
+    """pp-like tracks aimed into one sector; pT log-uniform."""
+    vx, vy, vz_ = _vertex(rng, n)
+    if vz is not None:
+        vz_ = vz_ + vz
+    a = sector_alpha(sector)
+    half = math.radians(HALF_OPEN_DEG)
+    phi0 = rng.uniform(a - half, a + half, n)
+    lo, hi = np.log(pt_range[0]), np.log(pt_range[1])
+    pt = np.exp(rng.uniform(lo, hi, n))
+    eta = rng.uniform(eta_range[0], eta_range[1], n)
+    q = rng.choice(np.array([-1.0, 1.0]), n)
+    return Tracks(vx, vy, vz_, pt, phi0, _eta_to_tgl(eta), q, np.zeros(n))
+
+
+def _pt_pbpb(rng, n):
+    """90% exp(-pT / 0.3 GeV), 10% power-law tail p(pT) ~ (1 + pT/1 GeV)^-6."""
+    soft = rng.random(n) < 0.9
+    pt = np.empty(n)
+    ns = int(soft.sum())
+    pt[soft] = rng.exponential(0.3, ns)
+    # inverse CDF of (1+x)^-6 on [0, inf): F = 1 - (1+x)^-5
+    u = rng.random(n - ns)
+    pt[~soft] = (1.0 - u) ** (-1.0 / 5.0) - 1.0
+    return np.maximum(pt, 1e-3)
+
+
+def primaries_pbpb(rng, n, t0=0.0, phi_range=None):
+    vx, vy, vz = _vertex(rng, n)
+    if phi_range is None:
+        phi0 = rng.uniform(-math.pi, math.pi, n)
+    else:
+        phi0 = rng.uniform(phi_range[0], phi_range[1], n)
+    eta = rng.uniform(-ETA_MAX, ETA_MAX, n)
+    q = rng.choice(np.array([-1.0, 1.0]), n)
+    return Tracks(vx, vy, vz, _pt_pbpb(rng, n), phi0, _eta_to_tgl(eta), q, np.full(n, float(t0)))
+
+
+# --- events --------------------------------------------------------------------
+
+@dataclass
+class Event:
+    """Clusters grouped by unit (one unit = one sector here), FP32 coordinates.
+
+    Order inside a unit is random.  label = index of the generating track in
+    `tracks`, or -1 for noise.  z is the continuous-readout coordinate z'.
+    """
+    y: np.ndarray
+    z: np.ndarray
+    row: np.ndarray
+    unit_offsets: np.ndarray
+    unit_sector: np.ndarray
+    label: np.ndarray
+    tracks: Tracks
+    bz: float
+    name: str = ""
+    row_x: np.ndarray = field(default_factory=lambda: ROW_X_F32.copy())
+
+    @property
+    def n(self):
+        return int(len(self.y))
+
+    @property
+    def n_units(self):
+        return int(len(self.unit_offsets) - 1)
+
+    def unit(self, u):
+        a, b = int(self.unit_offsets[u]), int(self.unit_offsets[u + 1])
+        return slice(a, b)
+
+    def subset_units(self, units):
+        """A new event made of the given units (clusters copied, order kept)."""
+        parts = [self.unit(int(u)) for u in units]
+        y = np.concatenate([self.y[s] for s in parts]) if parts else np.zeros(0, np.float32)
+        z = np.concatenate([self.z[s] for s in parts]) if parts else np.zeros(0, np.float32)
+        row = np.concatenate([self.row[s] for s in parts]) if parts else np.zeros(0, np.uint16)
+        lab = np.concatenate([self.label[s] for s in parts]) if parts else np.zeros(0, np.int32)
+        off = np.zeros(len(parts) + 1, np.int64)
+        off[1:] = np.cumsum([s.stop - s.start for s in parts])
+        return Event(y, z, row, off, self.unit_sector[np.asarray(units, dtype=np.int64)].copy(),
+                     lab, self.tracks, self.bz, self.name + "[sub]", self.row_x)
+
+
+def _assemble(rng, xs, tracks, bz, units_sectors, z_span_of_unit, shift_z, name):
+    """Smear crossings, add noise per unit, group by unit, shuffle inside units."""
+    sector = xs["sector"]
+    keep_unit = np.full(N_SECTORS, -1, np.int64)
+    for u, s in enumerate(units_sectors):
+        keep_unit[s] = u
+    unit = keep_unit[sector]
+    m = unit >= 0
+    unit = unit[m]
+    row = xs["row"][m]
+    trk = xs["track"][m]
+    y = xs["y"][m] + rng.normal(0, SIGMA_Y, int(m.sum()))
+    zt = xs["z"][m]
+    side = np.where(sector[m] < 18, 1.0, -1.0)
+    z = zt + shift_z(trk, side) + rng.normal(0, SIGMA_Z, int(m.sum()))
+    n_units = len(units_sectors)
+    ys, zs, rows, labs, units = [y], [z], [row], [trk], [unit]
+    sig_per_unit = np.bincount(unit, minlength=n_units)
+    for u in range(n_units):
+        nn = int(round(NOISE_FRACTION * sig_per_unit[u]))
+        if nn == 0:
+            continue
+        r = rng.integers(0, N_ROWS, nn)
+        hw = ROW_X[r] * TAN_HALF
+        ys.append(rng.uniform(-1.0, 1.0, nn) * hw)
+        zlo, zhi = z_span_of_unit(u)
+        zs.append(rng.uniform(zlo, zhi, nn))
+        rows.append(r.astype(np.int32))
+        labs.append(np.full(nn, -1, np.int32))
+        units.append(np.full(nn, u, np.int64))
+    y = np.concatenate(ys)
+    z = np.concatenate(zs)
+    row = np.concatenate(rows)
+    lab = np.concatenate(labs)
+    unit = np.concatenate(units)
+    key = (unit.astype(np.uint64) << np.uint64(40)) | rng.integers(0, 1 << 40, len(unit), dtype=np.uint64)
+    order = np.argsort(key, kind="stable")
+    off = np.zeros(n_units + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(unit, minlength=n_units))
+    return Event(y[order].astype(np.float32), z[order].astype(np.float32),
+                 row[order].astype(np.uint16), off, np.asarray(units_sectors, np.int16),
+                 lab[order].astype(np.int32), tracks, bz, name)
+
+
+def _side_span(sector, t_max_us):
+    shift = V_DRIFT * t_max_us
+    return (0.0 - shift, Z_MAX) if sector < 18 else (-Z_MAX, 0.0 + shift)
+
+
+def event_pp_sector(seed: int, n_tracks: int = 200, sector: int = 0, bz: float = 0.5) -> Event:
+    """One TPC sector, one pp-like event: pT log-uniform 0.1-10 GeV, tracks aimed
+    into the sector, |eta| < 0.9 on the sector's side."""
+    rng = np.random.default_rng(seed)
+    eta_range = (0.0, ETA_MAX) if sector < 18 else (-ETA_MAX, 0.0)
+    tr = primaries_pp_sector(rng, n_tracks, sector, eta_range)
+    xs = helix_crossings(tr, bz)
+    return _assemble(rng, xs, tr, bz, [sector], lambda u: _side_span(sector, 0.0),
+                     lambda trk, side: 0.0, "pp_sector")
+
+
+def event_pbpb_central(seed: int, n_primaries: int = 15000, bz: float = 0.5) -> Event:
+    """One central Pb-Pb collision, 36 sector units."""
+    rng = np.random.default_rng(seed)
+    tr = primaries_pbpb(rng, n_primaries)
+    xs = helix_crossings(tr, bz)
+    return _assemble(rng, xs, tr, bz, list(range(N_SECTORS)), lambda u: _side_span(u, 0.0),
+                     lambda trk, side: 0.0, "pbpb_central")
+
+
+def pbpb_multiplicity(rng, n):
+    """Charged primaries of min-bias Pb-Pb: b with p(b) ~ b on [0, 15] fm,
+    N_ch = 15000 (1 - b/15)^1.7 (mean ~3000)."""
+    b = 15.0 * np.sqrt(rng.random(n))
+    return np.round(15000.0 * (1.0 - b / 15.0) ** 1.7).astype(np.int64)
+
+
+def event_pbpb_timeframe(seed: int, n_collisions: int = 50, slice_us: float = None,
+                         bz: float = 0.5) -> Event:
+    """Continuous-readout slice: n_collisions min-bias Pb-Pb collisions at times
+    uniform over the slice (default n / 50 kHz); z' = z - side * v_drift * t0."""
+    rng = np.random.default_rng(seed)
+    if slice_us is None:
+        slice_us = n_collisions / 50e3 * 1e6
+    mult = pbpb_multiplicity(rng, n_collisions)
+    t0s = rng.uniform(0.0, slice_us, n_collisions)
+    parts = [primaries_pbpb(rng, int(m), t0=t) for m, t in zip(mult, t0s)]
+    tr = Tracks.concat(parts)
+    xs = helix_crossings(tr, bz)
+    t0 = tr.t0
+
+    def shift(trk, side):
+        return -side * V_DRIFT * t0[trk]
+
+    return _assemble(rng, xs, tr, bz, list(range(N_SECTORS)),
+                     lambda u: _side_span(u, slice_us), shift, "pbpb_timeframe")
+
+
+def event_uneven_chunks(seed: int, n_units: int = 512, n_lo: float = 1e3, n_hi: float = 1e5,
+                        bz: float = 0.5) -> Event:
+    """Batched workload: n_units sector chunks of log-uniform size [n_lo, n_hi]
+    clusters, each from a pp-like (log-uniform pT) or a Pb-Pb-like (soft
+    spectrum) generator, 50/50."""
+    rng = np.random.default_rng(seed)
+    target = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), n_units))
+    kinds = rng.random(n_units) < 0.5
+    ev_parts = []
+    all_tracks = []
+    trk_base = 0
+    for u in range(n_units):
+        sector = int(rng.integers(0, N_SECTORS))
+        a = sector_alpha(sector)
+        half = math.radians(HALF_OPEN_DEG)
+        eta_range = (0.0, ETA_MAX) if sector < 18 else (-ETA_MAX, 0.0)
+        want = target[u] / (1.0 + NOISE_FRACTION)
+        est = max(4, int(want / 60.0))
+        while True:
+            if kinds[u]:
+                tr = primaries_pp_sector(rng, est, sector, eta_range)
+            else:
+                tr = primaries_pbpb(rng, est, phi_range=(a - half, a + half))
+                tr.tgl = np.abs(tr.tgl) * (1.0 if sector < 18 else -1.0)
+            xs = helix_crossings(tr, bz)
+            m = xs["sector"] == sector
+            per_trk = np.bincount(xs["track"][m], minlength=est)
+            cum = np.cumsum(per_trk)
+            if cum[-1] >= want or est > 200000:
+                k = int(np.searchsorted(cum, want)) + 1
+                k = min(k, est)
+                break
+            est *= 2
+        sel = m & (xs["track"] < k)
+        sub = {key: v[sel] for key, v in xs.items()}
+        sub["track"] = sub["track"] + trk_base
+        trk_base += k
+        all_tracks.append(Tracks(*[getattr(tr, f)[:k] for f in
+                                   ("vx", "vy", "vz", "pt", "phi0", "tgl", "q", "t0")]))
+        ev_parts.append((sector, sub))
+    # assemble each unit separately (units may repeat a sector)
+    ys, zs, rows, labs, offs, secs = [], [], [], [], [0], []
+    tracks = Tracks.concat(all_tracks)
+    for u, (sector, sub) in enumerate(ev_parts):
+        sub = dict(sub)
+        sub["sector"] = np.zeros_like(sub["sector"])  # unit-local: map the sector to slot 0
+        e = _assemble(rng, sub, tracks, bz, [0], lambda _u, s=sector: _side_span(s, 0.0),
+                      lambda trk, side: 0.0, "chunk")
+        # _assemble used slot 0 (A side) for the side test only through sector ids; z kept
+        ys.append(e.y); zs.append(e.z); rows.append(e.row); labs.append(e.label)
+        offs.append(offs[-1] + e.n)
+        secs.append(sector)
+    return Event(np.concatenate(ys), np.concatenate(zs), np.concatenate(rows),
+                 np.asarray(offs, np.int64), np.asarray(secs, np.int16), np.concatenate(labs),
+                 tracks, bz, "uneven_chunks")
+
+
+WORKLOADS = {
+    "pp_sector": lambda seed=1001: event_pp_sector(seed),
+    "pbpb_central": lambda seed=2001: event_pbpb_central(seed),
+    "pbpb_timeframe_50": lambda seed=3001: event_pbpb_timeframe(seed),
+    "uneven_chunks_512": lambda seed=4001: event_uneven_chunks(seed),
+}
