@@ -1,0 +1,226 @@
+"""Benchmark: TPC clusters tracked per second on one MI355X, with p50/p99 latency.
+
+A step is one call of the whole hot path (hit grid, neighbours, cleaner,
+chains, Kalman tracklet construction, selection) over one batch that is
+already resident in HBM: by default a continuous-readout slice of 50 min-bias
+Pb-Pb collisions (36 sector units, ~23 M clusters), generated synthetically
+with a fixed seed.
+
+Prints ONE JSON line (rank 0).  Besides the contract fields it carries:
+  roofline      the dominant kernel: algorithmic bytes per launch / its mean
+                duration from HIP events recorded on the library's stream;
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
+  plain_per_sector  the same work as one call per sector (the plain form).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TPC clusters tracked/sec on 1 MI355X; p50/p99 time-frame latency"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per cluster of each kernel family: every array the method
+# defines is written once and read once per consuming step at its narrowest
+# type (hit grid 24, neighbours 14, cleaner 12, tracklet constructor 27,
+# selector 17: 94 in total).
+B_ALG = {"grid": 24, "neighbours": 14, "cleaner": 12, "constructor": 27, "selector": 17}
+B_ALG_TOTAL = sum(B_ALG.values())
+KERNEL_FAMILY = {
+    "k_init": None, "k_units": None, "k_tile_hist": "grid", "k_seg_plan": "grid",
+    "k_cell_base": "grid", "k_tile_offsets": "grid", "k_tile_scatter": "grid", "k_bin_sort": "grid",
+    "k_neighbours": "neighbours", "k_clean": "cleaner", "k_scan_blocks": "cleaner",
+    "k_compact_starts": "cleaner", "k_construct": "constructor", "k_select": "selector",
+    "k_emit": "selector",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _hip():
+    import torch  # noqa: F401 -- the runtime torch loaded
+    lib = ctypes.CDLL("libamdhip64.so.7")
+    lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    lib.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+    lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+def make_workload(name, seed=None):
+    import synth
+    t = time.time()
+    ev = synth.WORKLOADS[name]() if seed is None else synth.WORKLOADS[name](seed)
+    log("bench: generated %s: %d clusters in %d units (%.1f s)" % (name, ev.n, ev.n_units, time.time() - t))
+    return ev
+
+
+def src_digest():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2106_03636_amd", "csrc", "tpc_track.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    e = d.get(workload, {}).get(kernel)
+    if not e or e.get("src_digest") != src_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(ev, n_units_sample, values):
+    """The CPU oracle, as it stands, on the first n_units_sample units."""
+    import oracle
+    sub = ev.subset_units(list(range(n_units_sample)))
+    oracle.build()
+    threads = oracle.num_threads()
+    t = time.time()
+    r = oracle.run_event(sub, values)
+    dt = time.time() - t
+    return dict(value=sub.n / dt, unit="clusters/s", cores=threads, kind="oracle",
+                sample="%d of %d sector units of the same workload (%d clusters), one call, %.1f s"
+                       % (n_units_sample, ev.n_units, sub.n, dt),
+                seconds=dt, n_tracks=int(r["n_tracks"]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pbpb_timeframe_50")
+    ap.add_argument("--cpu-units", type=int, default=4, help="units in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X; --gpus %d is not supported (units are independent, "
+              "see the sharding note in DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2106_03636_amd as T
+    from paper_2106_03636_amd.runtime import Batch, Tracker
+
+    ev = make_workload(args.workload)
+    dev = torch.device("cuda:0")
+    batch = Batch.from_event(ev, dev)
+    tr = Tracker(batch.n, batch.n_units, batch.n_rows, device=dev)
+    log("bench: workspace %.2f GB" % (tr.ws_bytes / 1e9))
+    stream = torch.cuda.current_stream(dev)
+
+    # warmup
+    for _ in range(args.warmup):
+        tr.launch(batch)
+    res = tr.result()
+    log("bench: %d tracklets, %d tracks, %d assigned clusters" %
+        (res["n_tracklets"], res["n_tracks"], res["n_track_hits"]))
+
+    # timed region: K steps, per-step events and per-kernel events on the same stream
+    hip = _hip()
+    nk = T.tpc_kernel_count()
+    names = [T.tpc_kernel_name(i) for i in range(nk)]
+    evs = []
+    for _ in range(args.steps):
+        row = []
+        for _ in range(nk + 1):
+            e = ctypes.c_void_p()
+            assert hip.hipEventCreate(ctypes.byref(e)) == 0
+            row.append(e.value)
+        evs.append(row)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        tr.launch_profiled(batch, evs[k])
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    assert tr.status() == T.TPC_OK
+
+    def el(a, b):
+        ms = ctypes.c_float()
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a), ctypes.c_void_p(b)) == 0
+        return ms.value
+
+    step_ms = np.array([el(evs[k][0], evs[k][nk]) for k in range(args.steps)])
+    kern_ms = np.array([[el(evs[k][i], evs[k][i + 1]) for i in range(nk)] for k in range(args.steps)])
+    for row in evs:
+        for e in row:
+            hip.hipEventDestroy(ctypes.c_void_p(e))
+    mean_k = kern_ms.mean(axis=0)
+    per_kernel = {}
+    for i, n in enumerate(names):
+        key = n if n not in per_kernel else n + "_2"
+        per_kernel[key] = round(float(mean_k[i]), 4)
+    dom = int(np.argmax(mean_k))
+    dom_name = names[dom]
+    fam = KERNEL_FAMILY.get(dom_name)
+    algo_bytes = (B_ALG[fam] if fam else 0) * batch.n
+    achieved = algo_bytes / (mean_k[dom] * 1e-3) / 1e9
+    ms_per_step = wall / args.steps * 1e3
+    value = batch.n * args.steps / wall
+    traffic = measured_traffic(dom_name, args.workload)
+    log("bench: per-kernel ms " + json.dumps(per_kernel))
+
+    out = dict(
+        metric=METRIC, value=value, unit="clusters/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32+i64", data="synthetic",
+        config=dict(workload=args.workload, clusters=batch.n, units=batch.n_units, rows=batch.n_rows,
+                    bz_tesla=batch.bz, collisions=50 if args.workload.startswith("pbpb_timeframe") else None),
+        p50_ms=float(np.percentile(step_ms, 50)), p99_ms=float(np.percentile(step_ms, 99)),
+        roofline=dict(bound="hbm", kernel=dom_name, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                      algorithmic_bytes_per_launch=algo_bytes, mean_ms=float(mean_k[dom])),
+        pipeline_roofline=dict(bytes_per_cluster=B_ALG_TOTAL,
+                               achieved=B_ALG_TOTAL * value / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=B_ALG_TOTAL * value / 1e9 / HBM_PEAK_GBS),
+        kernel_ms=per_kernel,
+        tracks=res["n_tracks"], tracklets=res["n_tracklets"],
+    )
+
+    # the plain form: one call per sector unit, same stream, same work
+    if not args.no_plain:
+        subs = [Batch.from_event(ev.subset_units([u]), dev) for u in range(ev.n_units)]
+        trp = Tracker(max(s.n for s in subs), 1, batch.n_rows, device=dev)
+        for s in subs[:2]:
+            trp.launch(s)
+        torch.cuda.synchronize(dev)
+        reps = max(1, min(5, args.steps))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for s in subs:
+                trp.launch(s)
+        torch.cuda.synchronize(dev)
+        dtp = (time.perf_counter() - t0) / reps
+        out["plain_per_sector"] = dict(value=batch.n / dtp, unit="clusters/s", ms_per_step=dtp * 1e3,
+                                       calls_per_step=len(subs))
+        del trp
+
+    if args.cpu_units > 0:
+        from paper_2106_03636_amd.params import DEFAULT_PARAMS
+        log("bench: timing the CPU oracle on %d units" % args.cpu_units)
+        out["cpu_baseline"] = cpu_baseline(ev, args.cpu_units, DEFAULT_PARAMS)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

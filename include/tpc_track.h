@@ -1,0 +1,206 @@
+/*
+ * tpc_track.h -- C ABI of the MI355X (gfx950) TPC sector track finder.
+ *
+ * The operation: find the tracks of charged particles in the clusters (hits)
+ * of a TPC time frame.  Paper §2.1 states that TPC track finding over all
+ * collisions of a time frame is the dominant synchronous GPU workload and that
+ * it needs no other detector; paper §2.3 states that in continuous readout the
+ * collisions overlap and hits carry no a-priori absolute z, which is why this
+ * interface takes z' as measured (drift time times drift velocity) and never a
+ * vertex z.  The clusters come from the clusterizer (paper §2.1); this library
+ * consumes them and returns tracks plus a cluster-to-track map, per unit
+ * (a TPC sector, or a chunk of one).  Units are independent.
+ *
+ * Steps, all on the GPU:
+ *   1. ingest and validate;
+ *   2. hit grid: per (unit, pad row) the clusters are binned in (y, z') and
+ *      sorted by (row, bin, cluster id);
+ *   3. neighbour finder: each cluster of rows 1..n_rows-2 keeps the best pair
+ *      (one cluster in the row below, one in the row above) by an integer
+ *      straight-line residual;
+ *   4. cleaner: only mutual links survive; clusters with an upward link and no
+ *      downward link start chains (a cellular automaton over pad rows);
+ *   5. tracklet constructor: FP32 Kalman filter, two passes with pickup of
+ *      further clusters; every cluster is owned by the tracklet with most hits;
+ *   6. selector: tracklets that own enough of their hits become tracks.
+ *
+ * Conventions
+ *   - Every pointer inside the structs is a DEVICE pointer (memory visible to
+ *     the GPU), allocated and freed by the caller.  The library never
+ *     allocates, frees or synchronizes.
+ *   - Coordinates are in cm, in the local frame of the unit's sector: x along
+ *     the sector's centre line (given per pad row), y across it, z' along the
+ *     beam.  Decisions use coordinates rounded to 1/256 cm.
+ *   - Calls are asynchronous on the given HIP stream (a hipStream_t passed as
+ *     void*; NULL = the default stream).  Results are valid once that stream
+ *     has completed the work.
+ *   - The return value reports errors the host can see (bad arguments, too
+ *     small workspace, launch failures).  Errors that depend on the data
+ *     (invalid clusters, capacities exceeded) are written to *out->status on
+ *     the device; read it after the stream completes.  When it is not TPC_OK,
+ *     no track output is valid; out->counts still reports required sizes for
+ *     TPC_E_CAPACITY.
+ */
+#ifndef TPC_TRACK_H
+#define TPC_TRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPC_PARAMS_VERSION 1
+
+/* status codes */
+#define TPC_OK 0
+#define TPC_E_INVALID (-1)  /* malformed arguments or input data */
+#define TPC_E_CAPACITY (-2) /* an output or internal capacity is too small */
+#define TPC_E_NOMEM (-3)    /* the workspace is smaller than tpc_workspace_size() */
+#define TPC_E_HIP (-4)      /* a HIP runtime call failed */
+#define TPC_E_BUSY (-5)     /* reserved for callers that queue work */
+
+/* Clusters of one batch.  Units are contiguous ranges of the arrays; the order
+ * of clusters inside a unit is arbitrary.  A cluster's id is its index in the
+ * arrays; ids break ties, so results do not depend on how the grid is binned. */
+typedef struct tpc_clusters {
+  int64_t n;                   /* number of clusters, 0 <= n < 2^30 */
+  int32_t n_units;             /* >= 1 */
+  int32_t reserved;
+  const int64_t *unit_offsets; /* [n_units + 1], non-decreasing, [0] = 0, [n_units] = n;
+                                  each unit holds fewer than 2^24 clusters */
+  const float *y;              /* [n] local y, |y| <= 8192 */
+  const float *z;              /* [n] z' (continuous readout), |z'| <= 8192 */
+  const uint16_t *row;         /* [n] pad row, < n_rows */
+} tpc_clusters_t;
+
+/* Pad-row geometry shared by all units. */
+typedef struct tpc_geometry {
+  int32_t n_rows;              /* 3 <= n_rows <= 255 */
+  int32_t reserved;
+  const float *row_x;          /* [n_rows] row positions x_i (cm), increasing, 0 < x < 8192 */
+} tpc_geometry_t;
+
+/* Solenoid field along z. */
+typedef struct tpc_field {
+  float bz_tesla;              /* 0 is allowed: straight tracks, q/pT not measured */
+} tpc_field_t;
+
+/* Tracking parameters.  Integer lengths are in quanta of 1/256 cm. */
+typedef struct tpc_params {
+  int32_t version;             /* TPC_PARAMS_VERSION */
+  int32_t q_shift;             /* must be 8 */
+  int32_t tan_half_q16;        /* tan(half sector opening) * 2^16; row half width
+                                  H_i = (X_i * tan_half_q16) >> 16, X_i = rint(256 x_i) */
+  int32_t bin_y_q;             /* grid: y bin width (at most 63 bins per row) */
+  int32_t bin_occ;             /* grid: target clusters per bin (z bins adapt) */
+  int32_t bin_zmin_q;          /* grid: shortest z bin */
+  int32_t win_y_q, win_z_q;    /* neighbour windows: |Y_n X_i - Y_m X_j| <= win_y X_i,
+                                  |Z_n - Z_m| <= win_z */
+  int32_t w_y, w_z;            /* residual weights of the neighbour and pickup scores */
+  int64_t smax_k;              /* neighbour cut: score <= smax_k (X_{i+1} - X_{i-1})^2 */
+  int32_t l_min;               /* shortest chain that seeds a tracklet (>= 3) */
+  int32_t ext_win_y_q;         /* pickup window around the rounded prediction */
+  int32_t ext_win_z_q;
+  int32_t ext_edge_q;          /* a walk stops once |Y_pred| > H_i + ext_edge_q */
+  int32_t max_miss;            /* ... or after more than max_miss consecutive misses */
+  int32_t n_min;               /* selector: at least n_min owned hits */
+  int32_t f_min_q8;            /* selector: owned * 256 >= f_min_q8 * hits */
+  int32_t tracklet_cap_div;    /* internal tracklet capacity = n / div + 64 (>= 2) */
+  float sinphi_max;            /* walks stop when |sin(phi)| reaches this (0 < . < 1) */
+  float sigma_y, sigma_z;      /* cluster resolution (cm), Kalman measurement errors */
+  float cov0[5];               /* diagonal of the initial covariance */
+  int32_t reserved;
+} tpc_params_t;
+
+/* Outputs.  Tracks are ordered by (unit, grid position of the chain's first
+ * cluster); a track's hits are contiguous in `hits`, in increasing row order. */
+typedef struct tpc_tracks {
+  int64_t cap_tracks;          /* capacity of the per-track arrays */
+  int64_t cap_hits;            /* capacity of `hits` */
+  int32_t *cluster_track;      /* [n] track index of each cluster, -1 = none */
+  float *params;               /* [cap_tracks][5] y, z, sin(phi), tan(lambda), q/pT at x_ref */
+  float *cov;                  /* [cap_tracks][15] lower triangle, row-major */
+  float *x_ref;                /* [cap_tracks] x of the innermost fitted hit */
+  float *chi2;                 /* [cap_tracks] */
+  int32_t *unit;               /* [cap_tracks] */
+  int32_t *n_hits;             /* [cap_tracks] hits assigned to the track */
+  int32_t *n_fit;              /* [cap_tracks] hits used by the fit (ndf = 2 n_fit - 5) */
+  int32_t *first_hit;          /* [cap_tracks] offset into hits */
+  int32_t *hits;               /* [cap_hits] cluster ids */
+  int64_t *counts;             /* [4] n_tracks, n_track_hits, n_tracklets, n_grid_cells */
+  int32_t *status;             /* [1] TPC_OK or a negative status (see above) */
+} tpc_tracks_t;
+
+/* Bytes of device workspace tpc_track_sectors needs for a batch of n_clusters
+ * clusters in n_units units (an upper bound; host-only, pure).  0 on bad
+ * arguments. */
+size_t tpc_workspace_size(int64_t n_clusters, int32_t n_units, int32_t n_rows,
+                          const tpc_params_t *params);
+
+/* Track all units of a batch.  `workspace` is device memory of at least
+ * tpc_workspace_size() bytes, aligned to 256 bytes, owned by the caller and
+ * reused freely between calls (it holds no state across calls).  Calls that
+ * share a workspace must be ordered on one stream.  Returns TPC_OK when the
+ * work was enqueued. */
+int tpc_track_sectors(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry,
+                      const tpc_field_t *field, const tpc_params_t *params, tpc_tracks_t *out,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Same as tpc_track_sectors, and records HIP events (hipEvent_t passed as
+ * void*, created by the caller) on the stream around every kernel the call
+ * launches: events[k] right before kernel k, events[tpc_kernel_count()] after
+ * the last one.  n_events must be tpc_kernel_count() + 1.  For measurement;
+ * results are those of tpc_track_sectors. */
+int tpc_track_sectors_profiled(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry,
+                               const tpc_field_t *field, const tpc_params_t *params,
+                               tpc_tracks_t *out, void *workspace, size_t workspace_bytes,
+                               void *stream, void *const *events, int32_t n_events);
+
+/* Number of kernels one call launches, and the name of kernel i (host-only). */
+int32_t tpc_kernel_count(void);
+const char *tpc_kernel_name(int32_t i);
+
+/* Human-readable text of a status code (static storage). */
+const char *tpc_status_string(int status);
+
+/* Intermediate arrays kept in the workspace after a call, for inspection and
+ * tests.  Valid until the workspace is reused.  `what` selects the array:
+ *   TPC_VIEW_PERM      int32 [n]  sorted position -> cluster id
+ *   TPC_VIEW_CELL      int32 [cells+1] first sorted position of each grid cell
+ *   TPC_VIEW_SEG       int32 [units*n_rows][12] per (unit,row): start, count,
+ *                      zmin, zmax, H, by, ny, bz, nz, first cell, 0, 0
+ *   TPC_VIEW_UP/DN     int32 [n]  neighbour links (sorted positions, -1 none)
+ *   TPC_VIEW_UPC/DNC   int32 [n]  links after cleaning
+ *   TPC_VIEW_OWNER     uint32 [n] owner key per sorted position
+ *   TPC_VIEW_TRK_*     per tracklet (capacity entries, the first counts[2] valid):
+ *     START int32, UNIT int32, LEN int32, NFIT int32, RLO int32, RHI int32,
+ *     KEY uint32, OWNED int32, KEEP int32, PARAMS float[5], COV float[15],
+ *     XREF float, CHI2 float,
+ *     HITS int32 [n_rows][capacity] hit of each row (-1 none), rows RLO..RHI. */
+enum {
+  TPC_VIEW_PERM = 1, TPC_VIEW_CELL, TPC_VIEW_SEG, TPC_VIEW_UP, TPC_VIEW_DN, TPC_VIEW_UPC,
+  TPC_VIEW_DNC, TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN,
+  TPC_VIEW_TRK_NFIT, TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI, TPC_VIEW_TRK_KEY,
+  TPC_VIEW_TRK_OWNED, TPC_VIEW_TRK_KEEP, TPC_VIEW_TRK_PARAMS, TPC_VIEW_TRK_COV,
+  TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2, TPC_VIEW_TRK_HITS
+};
+
+typedef struct tpc_view {
+  void *ptr;                   /* device pointer into the workspace */
+  int64_t count;               /* number of elements (capacity for tracklet arrays) */
+  int32_t elem_bytes;
+  int32_t reserved;
+} tpc_view_t;
+
+/* Locate an intermediate array.  The batch shape and params must be those of
+ * the call that filled the workspace.  Host-only. */
+int tpc_inspect(const tpc_clusters_t *clusters, int32_t n_rows, const tpc_params_t *params,
+                const void *workspace, int what, tpc_view_t *view);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPC_TRACK_H */

@@ -277,8 +277,9 @@ static void find_neighbours(const unit_ctx_t *u, int32_t *up, int32_t *dn) {
           if (!in_window(u, w, m, Xi, Xu)) continue;
           const int64_t Ry = (u->Ys[d] - u->Ys[m]) * dxu + (u->Ys[w] - u->Ys[m]) * dxd;
           const int64_t Rz = (u->Zs[d] - u->Zs[m]) * dxu + (u->Zs[w] - u->Zs[m]) * dxd;
-          const int64_t s = (int64_t)P->w_y * Ry * Ry + (int64_t)P->w_z * Rz * Rz;
-          if (s > smax) continue;
+          const __int128 s128 = (__int128)P->w_y * Ry * Ry + (__int128)P->w_z * Rz * Rz;
+          if (s128 > smax) continue;
+          const int64_t s = (int64_t)s128;
           const int64_t idd = u->perm[d], idu = u->perm[w];
           if (s < best_s || (s == best_s && (idd < best_id_d || (idd == best_id_d && idu < best_id_u)))) {
             best_s = s;
@@ -754,8 +755,9 @@ void orc_free(orc_result_t *r) {
 
 static int valid_params(const orc_params_t *P) {
   return P->q_shift == 8 && P->tan_half_q16 > 0 && P->bin_y_q > 0 && P->bin_occ > 0 &&
-         P->bin_zmin_q > 0 && P->win_y_q >= 0 && P->win_z_q >= 0 && P->w_y >= 0 && P->w_z >= 0 &&
-         P->smax_k >= 0 && P->l_min >= 3 && P->ext_win_y_q >= 0 && P->ext_win_z_q >= 0 &&
+         P->bin_zmin_q > 0 && P->win_y_q >= 0 && P->win_z_q >= 0 && P->w_y >= 0 && P->w_y <= 15 &&
+         P->w_z >= 0 && P->w_z <= 15 && P->smax_k >= 0 && P->smax_k < ((int64_t)1 << 30) &&
+         P->l_min >= 3 && P->ext_win_y_q >= 0 && P->ext_win_z_q >= 0 &&
          P->max_miss >= 0 && P->n_min >= 0 && P->f_min_q8 >= 0 && P->sinphi_max > 0 &&
          P->sinphi_max < 1 && P->sigma_y > 0 && P->sigma_z > 0;
 }
@@ -784,6 +786,9 @@ int orc_run(int64_t n, int64_t n_units, const int64_t *unit_offsets, const float
   for (int64_t r = 0; r < n_rows; ++r)
     if (!(row_x[r] > 0.0f) || !(row_x[r] < 8192.0f) || (r > 0 && !(row_x[r] > row_x[r - 1])))
       return ORC_INVALID;
+  /* rows two apart at most 32 cm apart: keeps the neighbour cut below 2^56 */
+  for (int64_t r = 1; r + 1 < n_rows; ++r)
+    if (quantize((double)row_x[r + 1]) - quantize((double)row_x[r - 1]) >= 8192) return ORC_INVALID;
   for (int64_t i = 0; i < n; ++i)
     if (row[i] >= n_rows || !(fabsf(y[i]) <= 8192.0f) || !(fabsf(z[i]) <= 8192.0f)) return ORC_INVALID;
   res->status = ORC_OK;

@@ -1,0 +1,170 @@
+"""MI355X TPC sector track finder: Python binding of the C ABI in include/tpc_track.h.
+
+The functions here carry the C names and only marshal arguments: every step
+of the tracking runs in the HIP kernels of `_tpctrack.so`.  torch provides
+device memory and streams.  There is no CPU fallback: if the library is not
+built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .params import DEFAULT_PARAMS
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_tpctrack.so")
+
+TPC_PARAMS_VERSION = 1
+TPC_OK, TPC_E_INVALID, TPC_E_CAPACITY, TPC_E_NOMEM, TPC_E_HIP, TPC_E_BUSY = 0, -1, -2, -3, -4, -5
+
+(TPC_VIEW_PERM, TPC_VIEW_CELL, TPC_VIEW_SEG, TPC_VIEW_UP, TPC_VIEW_DN, TPC_VIEW_UPC, TPC_VIEW_DNC,
+ TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN, TPC_VIEW_TRK_NFIT,
+ TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI, TPC_VIEW_TRK_KEY, TPC_VIEW_TRK_OWNED, TPC_VIEW_TRK_KEEP,
+ TPC_VIEW_TRK_PARAMS, TPC_VIEW_TRK_COV, TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2,
+ TPC_VIEW_TRK_HITS) = range(1, 23)
+
+_vp = ctypes.c_void_p
+
+
+class tpc_clusters_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_units", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("unit_offsets", _vp), ("y", _vp), ("z", _vp), ("row", _vp)]
+
+
+class tpc_geometry_t(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("reserved", ctypes.c_int32), ("row_x", _vp)]
+
+
+class tpc_field_t(ctypes.Structure):
+    _fields_ = [("bz_tesla", ctypes.c_float)]
+
+
+class tpc_params_t(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("q_shift", ctypes.c_int32),
+                ("tan_half_q16", ctypes.c_int32), ("bin_y_q", ctypes.c_int32),
+                ("bin_occ", ctypes.c_int32), ("bin_zmin_q", ctypes.c_int32),
+                ("win_y_q", ctypes.c_int32), ("win_z_q", ctypes.c_int32),
+                ("w_y", ctypes.c_int32), ("w_z", ctypes.c_int32), ("smax_k", ctypes.c_int64),
+                ("l_min", ctypes.c_int32), ("ext_win_y_q", ctypes.c_int32),
+                ("ext_win_z_q", ctypes.c_int32), ("ext_edge_q", ctypes.c_int32),
+                ("max_miss", ctypes.c_int32), ("n_min", ctypes.c_int32),
+                ("f_min_q8", ctypes.c_int32), ("tracklet_cap_div", ctypes.c_int32),
+                ("sinphi_max", ctypes.c_float), ("sigma_y", ctypes.c_float),
+                ("sigma_z", ctypes.c_float), ("cov0", ctypes.c_float * 5),
+                ("reserved", ctypes.c_int32)]
+
+
+class tpc_tracks_t(ctypes.Structure):
+    _fields_ = [("cap_tracks", ctypes.c_int64), ("cap_hits", ctypes.c_int64),
+                ("cluster_track", _vp), ("params", _vp), ("cov", _vp), ("x_ref", _vp),
+                ("chi2", _vp), ("unit", _vp), ("n_hits", _vp), ("n_fit", _vp),
+                ("first_hit", _vp), ("hits", _vp), ("counts", _vp), ("status", _vp)]
+
+
+class tpc_view_t(ctypes.Structure):
+    _fields_ = [("ptr", _vp), ("count", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load the HIP library.  Raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is not built (run __graft_entry__.build() or "
+                               "python paper_2106_03636_amd/build.py)" % LIB_PATH)
+        import torch  # noqa: F401  -- share torch's HIP runtime
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.tpc_workspace_size.restype = ctypes.c_size_t
+        lib.tpc_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(tpc_params_t)]
+        lib.tpc_track_sectors.restype = ctypes.c_int
+        lib.tpc_track_sectors.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
+                                          ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_params_t),
+                                          ctypes.POINTER(tpc_tracks_t), _vp, ctypes.c_size_t, _vp]
+        lib.tpc_track_sectors_profiled.restype = ctypes.c_int
+        lib.tpc_track_sectors_profiled.argtypes = lib.tpc_track_sectors.argtypes + [
+            ctypes.POINTER(_vp), ctypes.c_int32]
+        lib.tpc_kernel_count.restype = ctypes.c_int32
+        lib.tpc_kernel_name.restype = ctypes.c_char_p
+        lib.tpc_kernel_name.argtypes = [ctypes.c_int32]
+        lib.tpc_status_string.restype = ctypes.c_char_p
+        lib.tpc_status_string.argtypes = [ctypes.c_int]
+        lib.tpc_inspect.restype = ctypes.c_int
+        lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
+                                    ctypes.POINTER(tpc_params_t), _vp, ctypes.c_int,
+                                    ctypes.POINTER(tpc_view_t)]
+        _lib = lib
+    return _lib
+
+
+def make_params(values: dict | None = None, **overrides) -> tpc_params_t:
+    """C parameter block from a dict of values (defaults: DEFAULT_PARAMS)."""
+    v = dict(DEFAULT_PARAMS if values is None else values)
+    v.update(overrides)
+    p = tpc_params_t()
+    p.version = TPC_PARAMS_VERSION
+    for name in ("q_shift", "tan_half_q16", "bin_y_q", "bin_occ", "bin_zmin_q", "win_y_q", "win_z_q",
+                 "w_y", "w_z", "smax_k", "l_min", "ext_win_y_q", "ext_win_z_q", "ext_edge_q",
+                 "max_miss", "n_min", "f_min_q8"):
+        setattr(p, name, int(v[name]))
+    p.tracklet_cap_div = int(v.get("tracklet_cap_div", 4))
+    p.sinphi_max = float(v["sinphi_max"])
+    p.sigma_y = float(v["sigma_y"])
+    p.sigma_z = float(v["sigma_z"])
+    for i, c in enumerate(v["cov0"]):
+        p.cov0[i] = float(c)
+    return p
+
+
+# --- C names ---------------------------------------------------------------------
+
+def tpc_workspace_size(n_clusters: int, n_units: int, n_rows: int, params: tpc_params_t) -> int:
+    return int(load_library().tpc_workspace_size(n_clusters, n_units, n_rows, ctypes.byref(params)))
+
+
+def tpc_track_sectors(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t,
+                      params: tpc_params_t, out: tpc_tracks_t, workspace: int, workspace_bytes: int,
+                      stream: int) -> int:
+    return int(load_library().tpc_track_sectors(ctypes.byref(clusters), ctypes.byref(geometry),
+                                                ctypes.byref(field), ctypes.byref(params),
+                                                ctypes.byref(out), workspace, workspace_bytes, stream))
+
+
+def tpc_track_sectors_profiled(clusters, geometry, field, params, out, workspace, workspace_bytes,
+                               stream, events) -> int:
+    arr = (_vp * len(events))(*events)
+    return int(load_library().tpc_track_sectors_profiled(
+        ctypes.byref(clusters), ctypes.byref(geometry), ctypes.byref(field), ctypes.byref(params),
+        ctypes.byref(out), workspace, workspace_bytes, stream, arr, len(events)))
+
+
+def tpc_kernel_count() -> int:
+    return int(load_library().tpc_kernel_count())
+
+
+def tpc_kernel_name(i: int) -> str:
+    return load_library().tpc_kernel_name(i).decode()
+
+
+def tpc_status_string(status: int) -> str:
+    return load_library().tpc_status_string(status).decode()
+
+
+def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, workspace: int,
+                what: int) -> tpc_view_t:
+    v = tpc_view_t()
+    st = load_library().tpc_inspect(ctypes.byref(clusters), n_rows, ctypes.byref(params), workspace,
+                                    what, ctypes.byref(v))
+    if st != TPC_OK:
+        raise ValueError("tpc_inspect: %s" % tpc_status_string(st))
+    return v
+
+
+# --- torch convenience ---------------------------------------------------------------
+
+from .runtime import Tracker, track  # noqa: E402,F401

@@ -1,0 +1,1288 @@
+// TPC sector track finding for MI355X (gfx950): kernels and the C ABI.
+//
+// The method (paper §2.1, §2.3): tracks of all collisions of a continuous-
+// readout time frame, found per TPC sector without an a-priori z.  The steps
+// and their integer / FP32 arithmetic are described in include/tpc_track.h;
+// each kernel below restates the step it implements.
+//
+// Design for CDNA4: wave64 throughout.  The hit grid is a two-level stable
+// counting sort (rows per 2048-hit tile, then bins per (unit,row) segment in
+// LDS) using ballot-based peer matching for stable ranks; the neighbour finder
+// and the cleaner are one-pass streaming kernels over the sorted hits; start
+// hits are compacted with a reduce-then-scan; the Kalman tracklet constructor
+// runs one tracklet per lane (the walk along the pad rows is sequential, so
+// concurrency comes from tracklets); ownership is an order-independent 32-bit
+// atomicMax of (hits << 24 | ~start id), which makes the result independent of
+// scheduling.  No kernel allocates; every buffer lives in a caller workspace.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "tpc_track.h"
+
+namespace {
+
+constexpr int TPB = 256;          // threads per block of the streaming kernels
+constexpr int TILE = 2048;        // hits per tile of the row pass
+constexpr int ELEMS = 2048;       // elements per block of the start-flag scan
+constexpr int BINS_LDS = 8192;    // bin counters the bin sort keeps in LDS
+constexpr int SEGW = 12;          // int32 per (unit,row) record
+constexpr int CTB = 128;          // threads per block of the constructor
+constexpr float KAPPA = 0.00299792458f;
+
+// (unit,row) record fields
+enum { S_START = 0, S_COUNT, S_ZMIN, S_ZMAX, S_H, S_BY, S_NY, S_BZ, S_NZ, S_CBASE };
+// internal counters
+enum { C_K = 0, C_CELLS = 1, C_TRACKS = 2, C_HITS = 3, C_TILES = 4, C_N = 8 };
+
+struct Workspace {
+  int64_t *ctr;
+  int32_t *seg, *seg_cnt, *seg_zmin, *seg_zmax, *seg_nbins;
+  int32_t *unit_tiles, *tile_hist;
+  int32_t *rs_idx;
+  int2 *rs_yz;
+  int32_t *perm;
+  int2 *syz;
+  int32_t *up, *dn, *upc, *dnc;
+  uint8_t *flag;
+  uint32_t *owner;
+  int32_t *cell, *cursor;
+  int32_t *blk, *blk_keep, *blk_own;
+  int32_t *trk_start, *trk_unit, *trk_len, *trk_nfit, *trk_rlo, *trk_rhi, *trk_owned, *trk_keep;
+  uint32_t *trk_key;
+  float *trk_par, *trk_cov, *trk_x, *trk_chi2;
+  int32_t *trk_hits;
+  int64_t N, S, T_max, C_max, K_cap, NB, KB;
+  size_t total;
+};
+
+struct Args {
+  Workspace w;
+  const int64_t *off;
+  const float *y, *z;
+  const uint16_t *row;
+  const float *row_x;
+  int64_t n;
+  int32_t n_units, n_rows;
+  float kcurv;  // -KAPPA * Bz: curvature per unit q/pT
+  tpc_params_t p;
+  tpc_tracks_t out;
+};
+
+// ---------------------------------------------------------------------------
+// workspace layout (host and device agree through this one function)
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, char *base,
+            Workspace *w) {
+  if (n < 0 || n >= (int64_t(1) << 30) || n_units < 1 || n_rows < 3 || n_rows > 255 || !p ||
+      p->bin_occ < 1 || p->tracklet_cap_div < 2)
+    return false;
+  Workspace L{};
+  L.N = n;
+  L.S = int64_t(n_units) * n_rows;
+  L.T_max = n / TILE + n_units + 1;
+  L.C_max = n / p->bin_occ + 65 * L.S + 1;
+  L.K_cap = n / p->tracklet_cap_div + 64;
+  L.NB = (n + ELEMS - 1) / ELEMS + 1;
+  L.KB = (L.K_cap + TPB - 1) / TPB;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return base ? base + at : nullptr;
+  };
+  const size_t N = size_t(n), S = size_t(L.S), K = size_t(L.K_cap);
+  L.ctr = (int64_t *)take(sizeof(int64_t) * C_N);
+  L.seg = (int32_t *)take(4 * S * SEGW);
+  L.seg_cnt = (int32_t *)take(4 * S);
+  L.seg_zmin = (int32_t *)take(4 * S);
+  L.seg_zmax = (int32_t *)take(4 * S);
+  L.seg_nbins = (int32_t *)take(4 * S);
+  L.unit_tiles = (int32_t *)take(4 * (size_t(n_units) + 1));
+  L.tile_hist = (int32_t *)take(4 * size_t(n_rows) * size_t(L.T_max));
+  L.rs_idx = (int32_t *)take(4 * N);
+  L.rs_yz = (int2 *)take(8 * N);
+  L.perm = (int32_t *)take(4 * N);
+  L.syz = (int2 *)take(8 * N);
+  L.up = (int32_t *)take(4 * N);
+  L.dn = (int32_t *)take(4 * N);
+  L.upc = (int32_t *)take(4 * N);
+  L.dnc = (int32_t *)take(4 * N);
+  L.flag = (uint8_t *)take(N + 16);
+  L.owner = (uint32_t *)take(4 * N);
+  L.cell = (int32_t *)take(4 * (size_t(L.C_max) + 1));
+  L.cursor = (int32_t *)take(4 * size_t(L.C_max));
+  L.blk = (int32_t *)take(4 * size_t(L.NB));
+  L.blk_keep = (int32_t *)take(4 * size_t(L.KB));
+  L.blk_own = (int32_t *)take(4 * size_t(L.KB));
+  L.trk_start = (int32_t *)take(4 * K);
+  L.trk_unit = (int32_t *)take(4 * K);
+  L.trk_len = (int32_t *)take(4 * K);
+  L.trk_nfit = (int32_t *)take(4 * K);
+  L.trk_rlo = (int32_t *)take(4 * K);
+  L.trk_rhi = (int32_t *)take(4 * K);
+  L.trk_owned = (int32_t *)take(4 * K);
+  L.trk_keep = (int32_t *)take(4 * K);
+  L.trk_key = (uint32_t *)take(4 * K);
+  L.trk_par = (float *)take(4 * 5 * K);
+  L.trk_cov = (float *)take(4 * 15 * K);
+  L.trk_x = (float *)take(4 * K);
+  L.trk_chi2 = (float *)take(4 * K);
+  L.trk_hits = (int32_t *)take(4 * size_t(n_rows) * K);
+  L.total = o;
+  *w = L;
+  return true;
+}
+
+bool params_ok(const tpc_params_t *p) {
+  return p && p->version == TPC_PARAMS_VERSION && p->q_shift == 8 && p->tan_half_q16 > 0 &&
+         p->tan_half_q16 < (1 << 20) && p->bin_y_q > 0 && p->bin_occ > 0 && p->bin_zmin_q > 0 &&
+         p->win_y_q >= 0 && p->win_y_q < (1 << 16) && p->win_z_q >= 0 && p->win_z_q < (1 << 16) &&
+         p->w_y >= 0 && p->w_y <= 15 && p->w_z >= 0 && p->w_z <= 15 && p->smax_k >= 0 &&
+         p->smax_k < (int64_t(1) << 30) && p->l_min >= 3 && p->ext_win_y_q >= 0 &&
+         p->ext_win_y_q < (1 << 16) && p->ext_win_z_q >= 0 && p->ext_win_z_q < (1 << 16) &&
+         p->ext_edge_q >= 0 && p->ext_edge_q < (1 << 20) && p->max_miss >= 0 && p->n_min >= 0 &&
+         p->f_min_q8 >= 0 && p->f_min_q8 <= 256 * 256 && p->tracklet_cap_div >= 2 &&
+         p->sinphi_max > 0.f && p->sinphi_max < 1.f && p->sigma_y > 0.f && p->sigma_z > 0.f &&
+         p->cov0[0] > 0.f && p->cov0[1] > 0.f && p->cov0[2] > 0.f && p->cov0[3] > 0.f &&
+         p->cov0[4] > 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+__device__ __forceinline__ void set_status(int32_t *st, int32_t code) {
+  atomicCAS(st, 0, code);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (uint64_t(1) << __lane_id()) - 1;
+}
+
+// Exclusive scan over the block (NT threads, NT/64 waves).  tmp: NT/64 ints of LDS.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int v, int *tmp, int *total) {
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wid] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const int t = tmp[i];
+    before += (i < wid) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + x - v;
+}
+
+// Lanes of the wave holding the same key (bits of the key below 2^nbits).
+__device__ __forceinline__ uint64_t peer_mask(uint32_t key, int nbits, bool active) {
+  uint64_t m = __ballot(active);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (key >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ __forceinline__ int quant(float v) { return __float2int_rn(v * 256.0f); }
+
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && (a < 0)) --q;
+  return q;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// unit of tile b (largest u with unit_tiles[u] <= b)
+__device__ __forceinline__ int unit_of_tile(const int32_t *ut, int n_units, int b) {
+  int lo = 0, hi = n_units - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ut[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// step 1: clear what must start at zero, validate geometry and offsets
+
+__global__ void k_init(Args A) {
+  const Workspace &w = A.w;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < w.S) {
+    w.seg_cnt[i] = 0;
+    w.seg_zmin[i] = INT32_MAX;
+    w.seg_zmax[i] = INT32_MIN;
+  }
+  if (i < A.n) {
+    w.owner[i] = 0u;
+    A.out.cluster_track[i] = -1;
+  }
+  if (i < C_N) w.ctr[i] = 0;
+  if (i < 4) A.out.counts[i] = 0;
+  if (i == 0) *A.out.status = TPC_OK;
+}
+
+__global__ void __launch_bounds__(1024) k_units(Args A) {
+  __shared__ int tmp[16];
+  const Workspace &w = A.w;
+  bool bad = false;
+  for (int r = threadIdx.x; r < A.n_rows; r += blockDim.x) {
+    const float x = A.row_x[r];
+    if (!(x > 0.f && x < 8192.f)) bad = true;
+    if (r > 0 && !(x > A.row_x[r - 1])) bad = true;
+    // rows two apart at most 32 cm apart: keeps the neighbour cut below 2^56
+    if (r > 0 && r + 1 < A.n_rows && x > 0.f && x < 8192.f &&
+        __float2ll_rn(A.row_x[r + 1] * 256.f) - __float2ll_rn(A.row_x[r - 1] * 256.f) >= 8192)
+      bad = true;
+  }
+  if (threadIdx.x == 0 && (A.off[0] != 0 || A.off[A.n_units] != A.n)) bad = true;
+  int carry = 0;
+  for (int base = 0; base < A.n_units; base += blockDim.x) {
+    const int u = base + threadIdx.x;
+    int tiles = 0;
+    if (u < A.n_units) {
+      const int64_t a = A.off[u], b = A.off[u + 1];
+      if (b < a || b - a >= (int64_t(1) << 24) || a < 0 || b > A.n) bad = true;
+      else tiles = int((b - a + TILE - 1) / TILE);
+    }
+    int tot;
+    const int ex = block_exclusive_scan<1024>(tiles, tmp, &tot);
+    if (u < A.n_units) w.unit_tiles[u] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    w.unit_tiles[A.n_units] = carry;
+    w.ctr[C_TILES] = carry;
+  }
+  if (bad) set_status(A.out.status, TPC_E_INVALID);
+}
+
+// ---------------------------------------------------------------------------
+// step 2a: per tile, row histogram and z extent (also validates the clusters)
+
+__global__ void __launch_bounds__(TPB) k_tile_hist(Args A) {
+  __shared__ int cnt[256], zmn[256], zmx[256];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int b = blockIdx.x;
+  if (b >= w.ctr[C_TILES]) return;
+  const int u = unit_of_tile(w.unit_tiles, A.n_units, b);
+  const int64_t beg = A.off[u] + int64_t(b - w.unit_tiles[u]) * TILE;
+  const int64_t end = min(beg + TILE, A.off[u + 1]);
+  for (int r = threadIdx.x; r < 256; r += TPB) {
+    cnt[r] = 0;
+    zmn[r] = INT32_MAX;
+    zmx[r] = INT32_MIN;
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int64_t i = beg + threadIdx.x; i < end; i += TPB) {
+    const int r = A.row[i];
+    const float yf = A.y[i], zf = A.z[i];
+    if (r >= A.n_rows || !(fabsf(yf) <= 8192.f) || !(fabsf(zf) <= 8192.f)) {
+      bad = true;
+      continue;
+    }
+    const int Z = quant(zf);
+    atomicAdd(&cnt[r], 1);
+    atomicMin(&zmn[r], Z);
+    atomicMax(&zmx[r], Z);
+  }
+  if (bad) set_status(A.out.status, TPC_E_INVALID);
+  __syncthreads();
+  for (int r = threadIdx.x; r < A.n_rows; r += TPB) {
+    const int c = cnt[r];
+    w.tile_hist[int64_t(r) * w.T_max + b] = c;
+    if (c) {
+      const int64_t s = int64_t(u) * A.n_rows + r;
+      atomicAdd(&w.seg_cnt[s], c);
+      atomicMin(&w.seg_zmin[s], zmn[r]);
+      atomicMax(&w.seg_zmax[s], zmx[r]);
+    }
+  }
+}
+
+// step 2b: per unit, row starts and the grid shape of every (unit,row).
+// y: [-H, H] in bins of by (at most 63); z: data-driven [zmin, zmax] (no
+// a-priori z in continuous readout, paper §2.3), cut into as many bins as
+// give about bin_occ hits per bin, none shorter than bin_zmin.
+__global__ void __launch_bounds__(256) k_seg_plan(Args A) {
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int u = blockIdx.x, r = threadIdx.x;
+  const int64_t s = int64_t(u) * A.n_rows + r;
+  const int cnt = r < A.n_rows ? w.seg_cnt[s] : 0;
+  int tot;
+  const int pre = block_exclusive_scan<256>(cnt, tmp, &tot);
+  if (r >= A.n_rows) return;
+  const tpc_params_t &P = A.p;
+  const int64_t X = __float2ll_rn(A.row_x[r] * 256.0f);
+  const int64_t H = (X * P.tan_half_q16) >> 16;
+  int64_t by = P.bin_y_q;
+  if (by < 2 * H / 63 + 1) by = 2 * H / 63 + 1;
+  const int64_t ny = 2 * H / by + 1;
+  const int64_t zmin = cnt ? w.seg_zmin[s] : 0, zmax = cnt ? w.seg_zmax[s] : 0;
+  const int64_t span = zmax - zmin;
+  const int64_t per = int64_t(P.bin_occ) * ny;
+  int64_t nz_occ = (cnt + per - 1) / per;
+  if (nz_occ < 1) nz_occ = 1;
+  const int64_t nz_span = span / P.bin_zmin_q + 1;
+  int64_t nz = nz_occ < nz_span ? nz_occ : nz_span;
+  if (nz < 1) nz = 1;
+  const int64_t bz = span / nz + 1;
+  int32_t *rec = w.seg + s * SEGW;
+  rec[S_START] = int32_t(A.off[u] + pre);
+  rec[S_COUNT] = cnt;
+  rec[S_ZMIN] = int32_t(zmin);
+  rec[S_ZMAX] = int32_t(zmax);
+  rec[S_H] = int32_t(H);
+  rec[S_BY] = int32_t(by);
+  rec[S_NY] = int32_t(ny);
+  rec[S_BZ] = int32_t(bz);
+  rec[S_NZ] = int32_t(nz);
+  rec[10] = 0;
+  rec[11] = 0;
+  w.seg_nbins[s] = int32_t(ny * nz);
+}
+
+// step 2c: first cell of every (unit,row), and the end sentinel
+__global__ void __launch_bounds__(1024) k_cell_base(Args A) {
+  __shared__ int tmp[16];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  int carry = 0;
+  for (int64_t base = 0; base < w.S; base += 1024) {
+    const int64_t s = base + threadIdx.x;
+    const int v = s < w.S ? w.seg_nbins[s] : 0;
+    int tot;
+    const int ex = block_exclusive_scan<1024>(v, tmp, &tot);
+    if (s < w.S) w.seg[s * SEGW + S_CBASE] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    w.ctr[C_CELLS] = carry;
+    A.out.counts[3] = carry;
+    w.cell[carry] = int32_t(A.n);
+  }
+}
+
+// step 2d: output position of each tile's first hit of each row
+__global__ void __launch_bounds__(64) k_tile_offsets(Args A) {
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t s = blockIdx.x;
+  const int u = int(s / A.n_rows), r = int(s % A.n_rows);
+  const int t0 = w.unit_tiles[u], t1 = w.unit_tiles[u + 1];
+  int carry = w.seg[s * SEGW + S_START];
+  int32_t *h = w.tile_hist + int64_t(r) * w.T_max;
+  const int lane = __lane_id();
+  for (int t = t0; t < t1; t += 64) {
+    const int i = t + lane;
+    const int v = i < t1 ? h[i] : 0;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (i < t1) h[i] = carry + x - v;
+    carry += __shfl(x, 63);
+  }
+}
+
+// step 2e: stable scatter of every tile's hits to row order.  Each wave owns a
+// contiguous quarter of the tile and ranks equal rows with ballots, so hits of
+// one row keep the order of their ids.
+__global__ void __launch_bounds__(TPB) k_tile_scatter(Args A) {
+  __shared__ int wcnt[4][256];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int b = blockIdx.x;
+  if (b >= w.ctr[C_TILES]) return;
+  const int u = unit_of_tile(w.unit_tiles, A.n_units, b);
+  const int64_t beg = A.off[u] + int64_t(b - w.unit_tiles[u]) * TILE;
+  const int64_t end = min(beg + TILE, A.off[u + 1]);
+  const int wid = threadIdx.x >> 6, lane = __lane_id();
+  for (int r = threadIdx.x; r < 4 * 256; r += TPB) (&wcnt[0][0])[r] = 0;
+  __syncthreads();
+  const int64_t sub_beg = beg + int64_t(wid) * (TILE / 4);
+  const int64_t sub_end = min(sub_beg + TILE / 4, end);
+  for (int64_t i = sub_beg + lane; i < sub_end; i += 64) atomicAdd(&wcnt[wid][A.row[i]], 1);
+  __syncthreads();
+  for (int r = threadIdx.x; r < A.n_rows; r += TPB) {
+    int base = w.tile_hist[int64_t(r) * w.T_max + b];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = wcnt[k][r];
+      wcnt[k][r] = base;
+      base += t;
+    }
+  }
+  __syncthreads();
+  for (int64_t c = sub_beg; c < sub_end; c += 64) {
+    const int64_t i = c + lane;
+    const bool act = i < sub_end;
+    const int r = act ? A.row[i] : 0;
+    const uint64_t peers = peer_mask(uint32_t(r), 8, act);
+    int pos = 0;
+    if (act) pos = wcnt[wid][r] + __popcll(peers & lanemask_lt());
+    __builtin_amdgcn_wave_barrier();
+    if (act && (63 - __clzll(peers)) == lane) wcnt[wid][r] += __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+      w.rs_idx[pos] = int32_t(i);
+      w.rs_yz[pos] = make_int2(quant(A.y[i]), quant(A.z[i]));
+    }
+  }
+}
+
+__device__ __forceinline__ int bin_of(const int32_t *rec, int Y, int Z) {
+  const int H = rec[S_H];
+  const int iy = clampi(Y + H, 0, 2 * H) / rec[S_BY];
+  const int iz = (Z - rec[S_ZMIN]) / rec[S_BZ];
+  return iz * rec[S_NY] + iy;
+}
+
+// step 2f: per (unit,row), counting sort by bin (stable: hits arrive in id
+// order and one wave ranks them chunk by chunk), and the cell table.
+__global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
+  __shared__ int hist_lds[BINS_LDS];
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t s = blockIdx.x;
+  const int32_t *rec = w.seg + s * SEGW;
+  const int start = rec[S_START], count = rec[S_COUNT], cbase = rec[S_CBASE];
+  const int nbins = rec[S_NY] * rec[S_NZ];
+  int *hist = nbins <= BINS_LDS ? hist_lds : (w.cursor + cbase);
+  for (int b = threadIdx.x; b < nbins; b += TPB) hist[b] = 0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < count; p += TPB) {
+    const int2 yz = w.rs_yz[start + p];
+    atomicAdd(&hist[bin_of(rec, yz.x, yz.y)], 1);
+  }
+  __syncthreads();
+  // exclusive scan over the bins: each thread takes a contiguous run
+  const int per = (nbins + TPB - 1) / TPB;
+  const int b0 = min(nbins, int(threadIdx.x) * per), b1 = min(nbins, b0 + per);
+  int run = 0;
+  for (int b = b0; b < b1; ++b) run += hist[b];
+  int tot;
+  int pre = block_exclusive_scan<TPB>(run, tmp, &tot);
+  for (int b = b0; b < b1; ++b) {
+    const int v = hist[b];
+    hist[b] = pre;
+    w.cell[cbase + b] = start + pre;
+    pre += v;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  int nbits = 1;
+  while ((1 << nbits) < nbins) ++nbits;
+  const int lane = __lane_id();
+  for (int c = 0; c < count; c += 64) {
+    const int p = c + lane;
+    const bool act = p < count;
+    int2 yz = make_int2(0, 0);
+    int idx = 0, bn = 0;
+    if (act) {
+      yz = w.rs_yz[start + p];
+      idx = w.rs_idx[start + p];
+      bn = bin_of(rec, yz.x, yz.y);
+    }
+    const uint64_t peers = peer_mask(uint32_t(bn), nbits, act);
+    int pos = 0;
+    if (act) pos = start + hist[bn] + __popcll(peers & lanemask_lt());
+    __builtin_amdgcn_wave_barrier();
+    if (act && (63 - __clzll(peers)) == lane) hist[bn] += __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+      w.perm[pos] = idx;
+      w.syz[pos] = yz;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step 3: neighbour finder.  For hit m of row i (0 < i < n_rows-1): candidates
+// n of rows j = i-1, i+1 with |Y_n X_i - Y_m X_j| <= win_y X_i (origin-pointing
+// in the bending plane) and |Z_n - Z_m| <= win_z (no vertex pointing in z).  Of
+// all pairs (d below, u above), the least (score, id_d, id_u) with
+// score = w_y R_y^2 + w_z R_z^2, R = (V_d - V_m)(X_u - X_i) + (V_u - V_m)(X_i - X_d),
+// is kept when score <= smax_k (X_{i+1} - X_{i-1})^2.
+
+struct Win {
+  int iy0, iy1, iz0, iz1, ny, cbase;
+  bool empty;
+};
+
+__device__ __forceinline__ Win window_cells(const int32_t *rec, int64_t ylo, int64_t yhi, int64_t zlo,
+                                            int64_t zhi) {
+  Win c;
+  const int count = rec[S_COUNT];
+  const int64_t zmin = rec[S_ZMIN], zmax = rec[S_ZMAX];
+  c.empty = count == 0 || zhi < zmin || zlo > zmax || yhi < ylo;
+  if (c.empty) return c;
+  const int64_t H = rec[S_H], span = zmax - zmin;
+  const int by = rec[S_BY], bz = rec[S_BZ];
+  auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  c.iy0 = int(cl(ylo + H, 0, 2 * H)) / by;
+  c.iy1 = int(cl(yhi + H, 0, 2 * H)) / by;
+  c.iz0 = int(cl(zlo - zmin, 0, span)) / bz;
+  c.iz1 = int(cl(zhi - zmin, 0, span)) / bz;
+  c.ny = rec[S_NY];
+  c.cbase = rec[S_CBASE];
+  return c;
+}
+
+__global__ void __launch_bounds__(TPB) k_neighbours(Args A) {
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t s = blockIdx.x;
+  const int r = int(s % A.n_rows);
+  const int32_t *rec = w.seg + s * SEGW;
+  const int start = rec[S_START], count = rec[S_COUNT];
+  if (r == 0 || r == A.n_rows - 1) {
+    for (int p = threadIdx.x; p < count; p += TPB) {
+      w.up[start + p] = -1;
+      w.dn[start + p] = -1;
+    }
+    return;
+  }
+  const int32_t *recd = rec - SEGW, *recu = rec + SEGW;
+  const int64_t Xi = __float2ll_rn(A.row_x[r] * 256.0f);
+  const int64_t Xd = __float2ll_rn(A.row_x[r - 1] * 256.0f);
+  const int64_t Xu = __float2ll_rn(A.row_x[r + 1] * 256.0f);
+  const int64_t dxd = Xi - Xd, dxu = Xu - Xi;
+  const int64_t smax = A.p.smax_k * (Xu - Xd) * (Xu - Xd);
+  const int64_t WY = A.p.win_y_q, WZ = A.p.win_z_q, wy = A.p.w_y, wz = A.p.w_z;
+  for (int p = threadIdx.x; p < count; p += TPB) {
+    const int m = start + p;
+    const int2 hm = w.syz[m];
+    const int64_t Ym = hm.x, Zm = hm.y;
+    const Win wd = window_cells(recd, floor_div64(Ym * Xd - WY * Xi, Xi),
+                                floor_div64(Ym * Xd + WY * Xi, Xi) + 1, Zm - WZ, Zm + WZ);
+    const Win wu = window_cells(recu, floor_div64(Ym * Xu - WY * Xi, Xi),
+                                floor_div64(Ym * Xu + WY * Xi, Xi) + 1, Zm - WZ, Zm + WZ);
+    int64_t best_s = INT64_MAX;
+    int best_d = -1, best_u = -1;
+    if (!wd.empty && !wu.empty) {
+      for (int izd = wd.iz0; izd <= wd.iz1; ++izd) {
+        const int cd = wd.cbase + izd * wd.ny;
+        const int q0 = w.cell[cd + wd.iy0], q1 = w.cell[cd + wd.iy1 + 1];
+        for (int d = q0; d < q1; ++d) {
+          const int2 hd = w.syz[d];
+          if (llabs(int64_t(hd.x) * Xi - Ym * Xd) > WY * Xi || llabs(int64_t(hd.y) - Zm) > WZ) continue;
+          const int64_t ay = (int64_t(hd.x) - Ym) * dxu, az = (int64_t(hd.y) - Zm) * dxu;
+          for (int izu = wu.iz0; izu <= wu.iz1; ++izu) {
+            const int cu = wu.cbase + izu * wu.ny;
+            const int v0 = w.cell[cu + wu.iy0], v1 = w.cell[cu + wu.iy1 + 1];
+            for (int uu = v0; uu < v1; ++uu) {
+              const int2 hu = w.syz[uu];
+              if (llabs(int64_t(hu.x) * Xi - Ym * Xu) > WY * Xi || llabs(int64_t(hu.y) - Zm) > WZ) continue;
+              const int64_t ry = ay + (int64_t(hu.x) - Ym) * dxd;
+              const int64_t rz = az + (int64_t(hu.y) - Zm) * dxd;
+              // a residual of 2^28 or more puts the score above 2^56 > smax
+              if ((wy && llabs(ry) >= (int64_t(1) << 28)) || (wz && llabs(rz) >= (int64_t(1) << 28)))
+                continue;
+              const int64_t sc = wy * ry * ry + wz * rz * rz;
+              if (sc > smax || sc > best_s) continue;
+              bool take = sc < best_s;
+              if (!take) {  // equal score: smaller ids win
+                const int idd = w.perm[d], idb = w.perm[best_d];
+                take = idd < idb || (idd == idb && w.perm[uu] < w.perm[best_u]);
+              }
+              if (take) {
+                best_s = sc;
+                best_d = d;
+                best_u = uu;
+              }
+            }
+          }
+        }
+      }
+    }
+    w.dn[m] = best_d;
+    w.up[m] = best_u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step 4: cleaner (only mutual links survive), start flags and their count per
+// block of ELEMS positions.
+
+__global__ void __launch_bounds__(TPB) k_clean(Args A) {
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t base = int64_t(blockIdx.x) * ELEMS;
+  int cnt = 0;
+#pragma unroll
+  for (int e = 0; e < ELEMS / TPB; ++e) {
+    const int64_t p = base + e * TPB + threadIdx.x;
+    if (p < A.n) {
+      const int u = w.up[p], d = w.dn[p];
+      const int uc = (u >= 0 && w.dn[u] == p) ? u : -1;
+      const int dc = (d >= 0 && w.up[d] == p) ? d : -1;
+      w.upc[p] = uc;
+      w.dnc[p] = dc;
+      const int f = (uc >= 0 && dc < 0) ? 1 : 0;
+      w.flag[p] = uint8_t(f);
+      cnt += f;
+    }
+  }
+  int tot;
+  block_exclusive_scan<TPB>(cnt, tmp, &tot);
+  if (threadIdx.x == 0) w.blk[blockIdx.x] = tot;
+}
+
+// one-block exclusive scan of per-block counts; total into counters, capacity check
+__global__ void __launch_bounds__(1024) k_scan_blocks(int32_t *blk, int64_t nb, int64_t *ctr_total,
+                                                      int64_t *out_total, int64_t cap,
+                                                      int32_t *status, int32_t *blk2,
+                                                      int64_t *ctr_total2, int64_t *out_total2,
+                                                      int64_t cap2) {
+  __shared__ int tmp[16];
+  if (*status != TPC_OK) return;
+  for (int which = 0; which < (blk2 ? 2 : 1); ++which) {
+    int32_t *b = which ? blk2 : blk;
+    int carry = 0;
+    for (int64_t base = 0; base < nb; base += 1024) {
+      const int64_t i = base + threadIdx.x;
+      const int v = i < nb ? b[i] : 0;
+      int tot;
+      const int ex = block_exclusive_scan<1024>(v, tmp, &tot);
+      if (i < nb) b[i] = carry + ex;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) {
+      int64_t *ct = which ? ctr_total2 : ctr_total;
+      int64_t *ot = which ? out_total2 : out_total;
+      const int64_t c = which ? cap2 : cap;
+      *ct = carry;
+      if (ot) *ot = carry;
+      if (carry > c) set_status(status, TPC_E_CAPACITY);
+    }
+  }
+}
+
+// step 4b: compaction of start hits in position order -> tracklet list
+__global__ void __launch_bounds__(TPB) k_compact_starts(Args A) {
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t base = int64_t(blockIdx.x) * ELEMS;
+  int carry = w.blk[blockIdx.x];
+#pragma unroll 1
+  for (int e = 0; e < ELEMS / TPB; ++e) {
+    const int64_t p = base + e * TPB + threadIdx.x;
+    const int f = p < A.n ? w.flag[p] : 0;
+    int tot;
+    const int ex = block_exclusive_scan<TPB>(f, tmp, &tot);
+    if (f) {
+      const int t = carry + ex;
+      int lo = 0, hi = A.n_units - 1;  // unit: largest u with off[u] <= p
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.off[mid] <= p) lo = mid; else hi = mid - 1;
+      }
+      w.trk_start[t] = int32_t(p);
+      w.trk_unit[t] = lo;
+    }
+    carry += tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step 5: tracklet constructor (FP32 Kalman filter, one tracklet per lane).
+// State at plane x: (y, z, sin(phi), tan(lambda), q/pT); curvature C = k q/pT.
+// Exact helix transport: sin2 = sin1 + C dx, dy = dx (sin1+sin2)/(cos1+cos2),
+// dz = tan(lambda) s_T with s_T = sign(dx) L asin(u)/u, L = |(dx,dy)|, u = |C|L/2;
+// analytic Jacobian for the covariance; no process noise.
+
+struct KState {
+  float p[5];
+  float c[15];  // lower triangle, row-major
+  float x, chi2;
+};
+
+__device__ __forceinline__ float asin_over(float u) {  // asin(u)/u
+  const float u2 = u * u;
+  if (u < 0.03f) return 1.f + u2 * (1.f / 6.f + u2 * (3.f / 40.f));
+  return asinf(u) / u;
+}
+__device__ __forceinline__ float asin_over_dd(float u) {  // (d/du asin(u)/u) / u
+  const float u2 = u * u;
+  if (u < 0.2f) return 1.f / 3.f + u2 * (0.3f + u2 * (15.f / 56.f + u2 * (35.f / 144.f)));
+  return (u / sqrtf(1.f - u2) - asinf(u)) / (u2 * u);
+}
+
+__device__ bool propagate(KState &s, float x2, float k, float sinmax) {
+  const float dx = x2 - s.x;
+  const float C = k * s.p[4];
+  const float s1 = s.p[2], s2 = s1 + C * dx;
+  if (!(fabsf(s1) < sinmax) || !(fabsf(s2) < sinmax)) return false;
+  const float c1 = sqrtf(1.f - s1 * s1), c2 = sqrtf(1.f - s2 * s2);
+  const float D = c1 + c2, N = s1 + s2;
+  const float iD = 1.f / D;
+  const float dy = dx * N * iD;
+  const float L = sqrtf(dx * dx + dy * dy);
+  const float u = fabsf(C) * L * 0.5f;
+  if (!(u < 1.f)) return false;
+  const float sg = dx < 0.f ? -1.f : 1.f;
+  const float fu = asin_over(u);
+  const float sT = sg * L * fu;
+  const float tgl = s.p[3];
+  // Jacobian entries
+  const float iD2 = iD * iD;
+  const float a = dx * (2.f * D + N * (s1 / c1 + s2 / c2)) * iD2;
+  const float b = dx * k * dx * (D + N * s2 / c2) * iD2;
+  const float g = asin_over_dd(u);
+  const float dsdy = L > 0.f ? sg * (dy / L) * (fu + u * u * g) : 0.f;
+  const float dsdC = sg * C * L * L * L * g * 0.25f;
+  const float cc = tgl * dsdy * a;
+  const float d = sT;
+  const float e = tgl * (dsdy * b + dsdC * k);
+  const float f = k * dx;
+  s.p[0] += dy;
+  s.p[1] += tgl * sT;
+  s.p[2] = s2;
+  s.x = x2;
+  // cov <- F cov F^T, F = I + {(0,2)=a, (0,4)=b, (1,2)=cc, (1,3)=d, (1,4)=e, (2,4)=f}
+  float *c = s.c;
+  const float P00 = c[0], P10 = c[1], P11 = c[2], P20 = c[3], P21 = c[4], P22 = c[5], P30 = c[6],
+              P31 = c[7], P32 = c[8], P33 = c[9], P40 = c[10], P41 = c[11], P42 = c[12],
+              P43 = c[13], P44 = c[14];
+  // T = F P, rows 0..2
+  const float T00 = P00 + a * P20 + b * P40, T02 = P20 + a * P22 + b * P42,
+              T04 = P40 + a * P42 + b * P44;
+  const float T10 = P10 + cc * P20 + d * P30 + e * P40, T11 = P11 + cc * P21 + d * P31 + e * P41,
+              T12 = P21 + cc * P22 + d * P32 + e * P42, T13 = P31 + cc * P32 + d * P33 + e * P43,
+              T14 = P41 + cc * P42 + d * P43 + e * P44;
+  const float T20 = P20 + f * P40, T21 = P21 + f * P41, T22 = P22 + f * P42, T23 = P32 + f * P43,
+              T24 = P42 + f * P44;
+  c[0] = T00 + a * T02 + b * T04;
+  c[1] = T10 + a * T12 + b * T14;
+  c[2] = T11 + cc * T12 + d * T13 + e * T14;
+  c[3] = T20 + a * T22 + b * T24;
+  c[4] = T21 + cc * T22 + d * T23 + e * T24;
+  c[5] = T22 + f * T24;
+  c[6] = P30 + a * P32 + b * P43;
+  c[7] = P31 + cc * P32 + d * P33 + e * P43;
+  c[8] = P32 + f * P43;
+  // c[9] = P33 unchanged
+  c[10] = P40 + a * P42 + b * P44;
+  c[11] = P41 + cc * P42 + d * P43 + e * P44;
+  c[12] = P42 + f * P44;
+  // c[13], c[14] unchanged
+  return true;
+}
+
+__device__ __forceinline__ void kf_update(KState &s, float my, float mz, float sy2, float sz2) {
+  float *c = s.c;
+  const float r0 = my - s.p[0], r1 = mz - s.p[1];
+  const float S00 = c[0] + sy2, S01 = c[1], S11 = c[2] + sz2;
+  const float idet = 1.f / (S00 * S11 - S01 * S01);
+  const float I00 = S11 * idet, I01 = -S01 * idet, I11 = S00 * idet;
+  // columns 0 and 1 of P (P_i0, P_i1)
+  const float q0[5] = {c[0], c[1], c[3], c[6], c[10]};
+  const float q1[5] = {c[1], c[2], c[4], c[7], c[11]};
+  float K0[5], K1[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    K0[i] = q0[i] * I00 + q1[i] * I01;
+    K1[i] = q0[i] * I01 + q1[i] * I11;
+    s.p[i] += K0[i] * r0 + K1[i] * r1;
+  }
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++k) c[k] -= K0[i] * q0[j] + K1[i] * q1[j];
+  s.chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
+}
+
+// Least (w_y dY^2 + w_z dZ^2, id) inside the pickup window of the rounded
+// prediction.  stop = 1 when the prediction has left the sector.
+__device__ int pick(const Args &A, const int32_t *rec, float yp, float zp, bool &stop) {
+  const Workspace &w = A.w;
+  const float vy = yp * 256.f, vz = zp * 256.f;
+  if (!(fabsf(vy) < 2.0e9f)) {
+    stop = true;
+    return -1;
+  }
+  const int Yp = __float2int_rn(vy);
+  const int H = rec[S_H];
+  if (abs(Yp) > H + A.p.ext_edge_q) {
+    stop = true;
+    return -1;
+  }
+  if (!(fabsf(vz) < 1.0e9f)) return -1;  // beyond every cluster: a miss
+  const int Zp = __float2int_rn(vz);
+  const int WY = A.p.ext_win_y_q, WZ = A.p.ext_win_z_q;
+  const Win c = window_cells(rec, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);
+  if (c.empty) return -1;
+  int64_t best_s = INT64_MAX;
+  int best = -1;
+  for (int iz = c.iz0; iz <= c.iz1; ++iz) {
+    const int cb = c.cbase + iz * c.ny;
+    const int q0 = w.cell[cb + c.iy0], q1 = w.cell[cb + c.iy1 + 1];
+    for (int q = q0; q < q1; ++q) {
+      const int2 h = w.syz[q];
+      const int dY = h.x - Yp, dZ = h.y - Zp;
+      if (abs(dY) > WY || abs(dZ) > WZ) continue;
+      const int64_t sc = int64_t(A.p.w_y) * dY * dY + int64_t(A.p.w_z) * dZ * dZ;
+      if (sc < best_s || (sc == best_s && w.perm[q] < w.perm[best])) {
+        best_s = sc;
+        best = q;
+      }
+    }
+  }
+  return best;
+}
+
+__device__ __forceinline__ void cov_reset(KState &s, const float *cov0) {
+#pragma unroll
+  for (int i = 0; i < 15; ++i) s.c[i] = 0.f;
+  s.c[0] = cov0[0];
+  s.c[2] = cov0[1];
+  s.c[5] = cov0[2];
+  s.c[9] = cov0[3];
+  s.c[14] = cov0[4];
+}
+
+__device__ __forceinline__ void upd_hit(const Args &A, KState &s, int h, float sy2, float sz2) {
+  const int2 yz = A.w.syz[h];
+  kf_update(s, float(yz.x) * (1.f / 256.f), float(yz.y) * (1.f / 256.f), sy2, sz2);
+}
+
+__global__ void __launch_bounds__(CTB) k_construct(Args A) {
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t t = int64_t(blockIdx.x) * CTB + threadIdx.x;
+  if (t >= w.ctr[C_K]) return;
+  const tpc_params_t &P = A.p;
+  const int64_t Kc = w.K_cap;
+  const int nr = A.n_rows;
+  const int h0 = w.trk_start[t], u = w.trk_unit[t];
+  const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
+  int32_t *hits = w.trk_hits + t;  // row r at hits[r * Kc]
+  // row of the start hit: last row whose start <= h0
+  int lo = 0, hi = nr - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
+  }
+  const int r1 = lo;
+  // chain walk (cellular-automaton chain along the cleaned upward links)
+  int L = 0;
+  for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
+    hits[int64_t(r1 + L) * Kc] = h;
+    ++L;
+  }
+  w.trk_len[t] = L;
+  int nfit = 0, rlo = -1, rhi = -1;
+  KState last;
+  last.chi2 = 0.f;
+  last.x = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) last.p[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 15; ++i) last.c[i] = 0.f;
+  const float sy2 = P.sigma_y * P.sigma_y, sz2 = P.sigma_z * P.sigma_z;
+  const float k = A.kcurv, smx = P.sinphi_max;
+  bool ok = L >= P.l_min;
+  KState s;
+  if (ok) {
+    // seed: circle through the first, middle and last chain hits
+    const int ha = hits[int64_t(r1) * Kc], hm = hits[int64_t(r1 + L / 2) * Kc],
+              hb = hits[int64_t(r1 + L - 1) * Kc];
+    const int2 ya = w.syz[ha], ym = w.syz[hm], yb = w.syz[hb];
+    const float x0 = A.row_x[r1], x1 = A.row_x[r1 + L / 2], x2 = A.row_x[r1 + L - 1];
+    const float y0 = ya.x * (1.f / 256.f), y1 = ym.x * (1.f / 256.f), y2 = yb.x * (1.f / 256.f);
+    const float z0 = ya.y * (1.f / 256.f), z2 = yb.y * (1.f / 256.f);
+    const float ax = x1 - x0, ay = y1 - y0, bx = x2 - x0, by = y2 - y0, cx = x2 - x1, cy = y2 - y1;
+    const float d12 = sqrtf(ax * ax + ay * ay), d13 = sqrtf(bx * bx + by * by),
+                d23 = sqrtf(cx * cx + cy * cy);
+    ok = d12 > 0.f && d13 > 0.f && d23 > 0.f;
+    if (ok) {
+      const float C = 2.f * (ax * by - ay * bx) / (d12 * d13 * d23);
+      const float sa = C * d13 * 0.5f;
+      ok = fabsf(sa) < 1.f;
+      if (ok) {
+        const float ca = sqrtf(1.f - sa * sa);
+        const float sphi = (by / d13) * ca - (bx / d13) * sa;
+        ok = fabsf(sphi) < smx;
+        const float sT = d13 * asin_over(fabsf(sa));
+        s.p[0] = y0;
+        s.p[1] = z0;
+        s.p[2] = sphi;
+        s.p[3] = (z2 - z0) / sT;
+        s.p[4] = k != 0.f ? C / k : 0.f;
+        s.x = x0;
+        s.chi2 = 0.f;
+        cov_reset(s, P.cov0);
+      }
+    }
+  }
+  if (ok) {
+    // pass 1: the chain, inner to outer
+    int r_out = r1;
+    bool chain_ok = true;
+    for (int j = 0; j < L; ++j) {
+      if (j > 0 && !propagate(s, A.row_x[r1 + j], k, smx)) {
+        chain_ok = false;
+        break;
+      }
+      upd_hit(A, s, hits[int64_t(r1 + j) * Kc], sy2, sz2);
+      last = s;
+      r_out = r1 + j;
+    }
+    // pass 1: extension to the outer rows
+    if (chain_ok) {
+      int misses = 0;
+      for (int r = r1 + L; r < nr; ++r) {
+        if (!propagate(s, A.row_x[r], k, smx)) break;
+        bool stop = false;
+        const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], stop);
+        if (stop) break;
+        hits[int64_t(r) * Kc] = f;
+        if (f >= 0) {
+          upd_hit(A, s, f, sy2, sz2);
+          last = s;
+          r_out = r;
+          misses = 0;
+        } else if (++misses > P.max_miss) {
+          break;
+        }
+      }
+    }
+    // pass 2: from the outermost hit down to row 0, covariance reset
+    s = last;
+    cov_reset(s, P.cov0);
+    s.chi2 = 0.f;
+    upd_hit(A, s, hits[int64_t(r_out) * Kc], sy2, sz2);
+    last = s;
+    nfit = 1;
+    rhi = r_out;
+    rlo = r_out;
+    int misses = 0;
+    for (int r = r_out - 1; r >= 0; --r) {
+      if (!propagate(s, A.row_x[r], k, smx)) break;
+      if (r >= r1) {
+        const int h = hits[int64_t(r) * Kc];
+        if (h >= 0) {
+          upd_hit(A, s, h, sy2, sz2);
+          last = s;
+          ++nfit;
+          rlo = r;
+          continue;
+        }
+      }
+      bool stop = false;
+      const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], stop);
+      if (stop) break;
+      hits[int64_t(r) * Kc] = f;
+      rlo = r;
+      if (f >= 0) {
+        upd_hit(A, s, f, sy2, sz2);
+        last = s;
+        ++nfit;
+        misses = 0;
+      } else if (r < r1 && ++misses > P.max_miss) {
+        break;
+      }
+    }
+  }
+  uint32_t key = 0;
+  if (nfit > 0) {
+    const uint32_t local = uint32_t(w.perm[h0] - A.off[u]);
+    key = (uint32_t(nfit) << 24) | (0xFFFFFFu - local);
+  }
+  w.trk_nfit[t] = nfit;
+  w.trk_rlo[t] = rlo;
+  w.trk_rhi[t] = rhi;
+  w.trk_key[t] = key;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) w.trk_par[t * 5 + i] = last.p[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) w.trk_cov[t * 15 + i] = last.c[i];
+  w.trk_x[t] = last.x;
+  w.trk_chi2[t] = last.chi2;
+  // ownership: every hit goes to the tracklet with the largest key
+  if (nfit > 0)
+    for (int r = rlo; r <= rhi; ++r) {
+      const int h = hits[int64_t(r) * Kc];
+      if (h >= 0) atomicMax(&w.owner[h], key);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// step 6: selector.  Keep a tracklet that owns >= n_min of its hits and at
+// least f_min of them; tracks keep the tracklet order; no refit.
+
+__global__ void __launch_bounds__(TPB) k_select(Args A) {
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  int keep = 0, owned = 0;
+  if (t < w.ctr[C_K]) {
+    const int nfit = w.trk_nfit[t];
+    if (nfit > 0) {
+      const uint32_t key = w.trk_key[t];
+      const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
+      for (int r = rlo; r <= rhi; ++r) {
+        const int h = w.trk_hits[int64_t(r) * w.K_cap + t];
+        if (h >= 0 && w.owner[h] == key) ++owned;
+      }
+      keep = owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
+    }
+    w.trk_owned[t] = owned;
+    w.trk_keep[t] = keep;
+  }
+  int tk, to;
+  block_exclusive_scan<TPB>(keep, tmp, &tk);
+  block_exclusive_scan<TPB>(keep ? owned : 0, tmp, &to);
+  if (threadIdx.x == 0) {
+    w.blk_keep[blockIdx.x] = tk;
+    w.blk_own[blockIdx.x] = to;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_emit(Args A) {
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  const bool valid = t < w.ctr[C_K];
+  const int keep = valid ? w.trk_keep[t] : 0;
+  const int owned = keep ? w.trk_owned[t] : 0;
+  int tk, to;
+  const int ek = block_exclusive_scan<TPB>(keep, tmp, &tk);
+  const int eo = block_exclusive_scan<TPB>(owned, tmp, &to);
+  if (!keep) return;
+  const int tr = w.blk_keep[blockIdx.x] + ek;
+  int off = w.blk_own[blockIdx.x] + eo;
+  const tpc_tracks_t &O = A.out;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) O.params[int64_t(tr) * 5 + i] = w.trk_par[t * 5 + i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) O.cov[int64_t(tr) * 15 + i] = w.trk_cov[t * 15 + i];
+  O.x_ref[tr] = w.trk_x[t];
+  O.chi2[tr] = w.trk_chi2[t];
+  O.unit[tr] = w.trk_unit[t];
+  O.n_hits[tr] = owned;
+  O.n_fit[tr] = w.trk_nfit[t];
+  O.first_hit[tr] = off;
+  const uint32_t key = w.trk_key[t];
+  const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
+  for (int r = rlo; r <= rhi; ++r) {
+    const int h = w.trk_hits[int64_t(r) * w.K_cap + t];
+    if (h >= 0 && w.owner[h] == key) {
+      const int id = w.perm[h];
+      O.hits[off++] = id;
+      O.cluster_track[id] = tr;
+    }
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" size_t tpc_workspace_size(int64_t n_clusters, int32_t n_units, int32_t n_rows,
+                                     const tpc_params_t *params) {
+  if (!params_ok(params)) return 0;
+  Workspace w;
+  if (!layout(n_clusters, n_units, n_rows, params, nullptr, &w)) return 0;
+  return w.total;
+}
+
+extern "C" const char *tpc_status_string(int status) {
+  switch (status) {
+    case TPC_OK: return "ok";
+    case TPC_E_INVALID: return "invalid argument or input data";
+    case TPC_E_CAPACITY: return "capacity exceeded (see counts for the required sizes)";
+    case TPC_E_NOMEM: return "workspace too small";
+    case TPC_E_HIP: return "HIP runtime error";
+    case TPC_E_BUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+namespace {
+
+const char *const kKernelNames[] = {
+    "k_init",        "k_units",      "k_tile_hist",  "k_seg_plan",      "k_cell_base",
+    "k_tile_offsets", "k_tile_scatter", "k_bin_sort",  "k_neighbours",    "k_clean",
+    "k_scan_blocks", "k_compact_starts", "k_construct", "k_select",       "k_scan_blocks",
+    "k_emit"};
+constexpr int kNumKernels = int(sizeof(kKernelNames) / sizeof(kKernelNames[0]));
+
+int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field_t *f,
+               const tpc_params_t *p, tpc_tracks_t *out, void *workspace, size_t ws_bytes,
+               void *stream, void *const *events, int n_events) {
+  if (!c || !g || !f || !p || !out || !params_ok(p)) return TPC_E_INVALID;
+  if (c->n < 0 || c->n >= (int64_t(1) << 30) || c->n_units < 1 || !c->unit_offsets) return TPC_E_INVALID;
+  if (c->n > 0 && (!c->y || !c->z || !c->row)) return TPC_E_INVALID;
+  if (g->n_rows < 3 || g->n_rows > 255 || !g->row_x) return TPC_E_INVALID;
+  if (!(f->bz_tesla == f->bz_tesla) || fabsf(f->bz_tesla) > 100.f) return TPC_E_INVALID;
+  if (!out->counts || !out->status || out->cap_tracks < 0 || out->cap_hits < 0) return TPC_E_INVALID;
+  if (c->n > 0 && !out->cluster_track) return TPC_E_INVALID;
+  if (out->cap_tracks > 0 && (!out->params || !out->cov || !out->x_ref || !out->chi2 || !out->unit ||
+                              !out->n_hits || !out->n_fit || !out->first_hit))
+    return TPC_E_INVALID;
+  if (out->cap_hits > 0 && !out->hits) return TPC_E_INVALID;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return TPC_E_INVALID;
+  if (events && n_events != kNumKernels + 1) return TPC_E_INVALID;
+  Args A;
+  memset(&A, 0, sizeof(A));
+  if (!layout(c->n, c->n_units, g->n_rows, p, static_cast<char *>(workspace), &A.w)) return TPC_E_INVALID;
+  if (A.w.total > ws_bytes) return TPC_E_NOMEM;
+  A.off = c->unit_offsets;
+  A.y = c->y;
+  A.z = c->z;
+  A.row = c->row;
+  A.row_x = g->row_x;
+  A.n = c->n;
+  A.n_units = c->n_units;
+  A.n_rows = g->n_rows;
+  A.kcurv = -KAPPA * f->bz_tesla;
+  A.p = *p;
+  A.out = *out;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Workspace &w = A.w;
+  (void)hipGetLastError();
+  int ki = 0;
+  // profiling: event k is recorded right before kernel k, the last one after the last kernel
+  auto mark = [&]() {
+    if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[ki]), st);
+    ++ki;
+  };
+  const int64_t init_n = w.S > c->n ? w.S : (c->n > C_N ? c->n : int64_t(C_N));
+  mark();
+  hipLaunchKernelGGL(k_init, dim3(blocks_for(init_n, TPB)), dim3(TPB), 0, st, A);
+  mark();
+  hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, st, A);
+  if (c->n > 0) {
+    mark();
+    hipLaunchKernelGGL(k_tile_hist, dim3(unsigned(w.T_max)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_seg_plan, dim3(unsigned(c->n_units)), dim3(256), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_cell_base, dim3(1), dim3(1024), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_tile_offsets, dim3(unsigned(w.S)), dim3(64), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_tile_scatter, dim3(unsigned(w.T_max)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_bin_sort, dim3(unsigned(w.S)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_neighbours, dim3(unsigned(w.S)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_clean, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, w.blk, w.NB, w.ctr + C_K,
+                       out->counts + 2, w.K_cap, out->status, (int32_t *)nullptr, (int64_t *)nullptr,
+                       (int64_t *)nullptr, int64_t(0));
+    mark();
+    hipLaunchKernelGGL(k_compact_starts, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_construct, dim3(blocks_for(w.K_cap, CTB)), dim3(CTB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_select, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, w.blk_keep, w.KB, w.ctr + C_TRACKS,
+                       out->counts + 0, out->cap_tracks, out->status, w.blk_own, w.ctr + C_HITS,
+                       out->counts + 1, out->cap_hits);
+    mark();
+    hipLaunchKernelGGL(k_emit, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+  }
+  while (ki <= kNumKernels) mark();  // empty batch: the remaining events mark the same point
+  if (hipGetLastError() != hipSuccess) return TPC_E_HIP;
+  return TPC_OK;
+}
+
+}  // namespace
+
+extern "C" int tpc_track_sectors(const tpc_clusters_t *c, const tpc_geometry_t *g,
+                                 const tpc_field_t *f, const tpc_params_t *p, tpc_tracks_t *out,
+                                 void *workspace, size_t ws_bytes, void *stream) {
+  return track_impl(c, g, f, p, out, workspace, ws_bytes, stream, nullptr, 0);
+}
+
+extern "C" int tpc_track_sectors_profiled(const tpc_clusters_t *c, const tpc_geometry_t *g,
+                                          const tpc_field_t *f, const tpc_params_t *p,
+                                          tpc_tracks_t *out, void *workspace, size_t ws_bytes,
+                                          void *stream, void *const *events, int32_t n_events) {
+  if (!events) return TPC_E_INVALID;
+  return track_impl(c, g, f, p, out, workspace, ws_bytes, stream, events, n_events);
+}
+
+extern "C" int32_t tpc_kernel_count(void) { return kNumKernels; }
+
+extern "C" const char *tpc_kernel_name(int32_t i) {
+  return (i >= 0 && i < kNumKernels) ? kKernelNames[i] : "";
+}
+
+extern "C" int tpc_inspect(const tpc_clusters_t *c, int32_t n_rows, const tpc_params_t *p,
+                           const void *workspace, int what, tpc_view_t *v) {
+  if (!c || !p || !v || !workspace || !params_ok(p)) return TPC_E_INVALID;
+  Workspace w;
+  if (!layout(c->n, c->n_units, n_rows, p, (char *)workspace, &w)) return TPC_E_INVALID;
+  const int64_t N = c->n, K = w.K_cap;
+  void *ptr = nullptr;
+  int64_t cnt = 0;
+  int eb = 4;
+  switch (what) {
+    case TPC_VIEW_PERM: ptr = w.perm; cnt = N; break;
+    case TPC_VIEW_CELL: ptr = w.cell; cnt = w.C_max + 1; break;
+    case TPC_VIEW_SEG: ptr = w.seg; cnt = w.S * SEGW; break;
+    case TPC_VIEW_UP: ptr = w.up; cnt = N; break;
+    case TPC_VIEW_DN: ptr = w.dn; cnt = N; break;
+    case TPC_VIEW_UPC: ptr = w.upc; cnt = N; break;
+    case TPC_VIEW_DNC: ptr = w.dnc; cnt = N; break;
+    case TPC_VIEW_OWNER: ptr = w.owner; cnt = N; break;
+    case TPC_VIEW_TRK_START: ptr = w.trk_start; cnt = K; break;
+    case TPC_VIEW_TRK_UNIT: ptr = w.trk_unit; cnt = K; break;
+    case TPC_VIEW_TRK_LEN: ptr = w.trk_len; cnt = K; break;
+    case TPC_VIEW_TRK_NFIT: ptr = w.trk_nfit; cnt = K; break;
+    case TPC_VIEW_TRK_RLO: ptr = w.trk_rlo; cnt = K; break;
+    case TPC_VIEW_TRK_RHI: ptr = w.trk_rhi; cnt = K; break;
+    case TPC_VIEW_TRK_KEY: ptr = w.trk_key; cnt = K; break;
+    case TPC_VIEW_TRK_OWNED: ptr = w.trk_owned; cnt = K; break;
+    case TPC_VIEW_TRK_KEEP: ptr = w.trk_keep; cnt = K; break;
+    case TPC_VIEW_TRK_PARAMS: ptr = w.trk_par; cnt = K * 5; break;
+    case TPC_VIEW_TRK_COV: ptr = w.trk_cov; cnt = K * 15; break;
+    case TPC_VIEW_TRK_XREF: ptr = w.trk_x; cnt = K; break;
+    case TPC_VIEW_TRK_CHI2: ptr = w.trk_chi2; cnt = K; break;
+    case TPC_VIEW_TRK_HITS: ptr = w.trk_hits; cnt = K * n_rows; break;
+    default: return TPC_E_INVALID;
+  }
+  v->ptr = ptr;
+  v->count = cnt;
+  v->elem_bytes = eb;
+  v->reserved = 0;
+  return TPC_OK;
+}

@@ -1,0 +1,182 @@
+"""torch-side plumbing around the C ABI: device buffers and streams only.
+
+`Tracker` owns the workspace and output buffers for batches up to a given
+size and calls `tpc_track_sectors` on a torch stream.  Nothing here computes
+any step of the method.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import (DEFAULT_PARAMS, TPC_OK, tpc_clusters_t, tpc_field_t, tpc_geometry_t, tpc_inspect,
+               tpc_status_string, tpc_track_sectors, tpc_tracks_t, tpc_workspace_size, make_params)
+
+_VIEW_DTYPE = {
+    "float": torch.float32, "int": torch.int32,
+}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+class TrackingError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class Batch:
+    """Clusters of one batch resident on the device (what the C ABI consumes)."""
+
+    def __init__(self, y, z, row, unit_offsets, row_x, bz, device="cuda"):
+        dev = torch.device(device)
+        self.y = torch.as_tensor(np.ascontiguousarray(y, np.float32)).to(dev)
+        self.z = torch.as_tensor(np.ascontiguousarray(z, np.float32)).to(dev)
+        self.row = torch.as_tensor(np.ascontiguousarray(row, np.uint16).view(np.int16)).to(dev)
+        self.unit_offsets = torch.as_tensor(np.ascontiguousarray(unit_offsets, np.int64)).to(dev)
+        self.row_x = torch.as_tensor(np.ascontiguousarray(row_x, np.float32)).to(dev)
+        self.n = int(len(y))
+        self.n_units = int(len(unit_offsets) - 1)
+        self.n_rows = int(len(row_x))
+        self.bz = float(bz)
+
+    @staticmethod
+    def from_event(ev, device="cuda"):
+        return Batch(ev.y, ev.z, ev.row, ev.unit_offsets, ev.row_x, ev.bz, device)
+
+    def clusters_struct(self):
+        c = tpc_clusters_t()
+        c.n = self.n
+        c.n_units = self.n_units
+        c.unit_offsets = _ptr(self.unit_offsets)
+        c.y, c.z, c.row = _ptr(self.y), _ptr(self.z), _ptr(self.row)
+        return c
+
+    def geometry_struct(self):
+        g = tpc_geometry_t()
+        g.n_rows = self.n_rows
+        g.row_x = _ptr(self.row_x)
+        return g
+
+
+class Tracker:
+    """Workspace + outputs for batches of up to max_n clusters / max_units units."""
+
+    def __init__(self, max_n, max_units, n_rows=152, params=None, device="cuda", cap_tracks=None,
+                 cap_hits=None):
+        self.values = dict(DEFAULT_PARAMS if params is None else params)
+        self.params = make_params(self.values)
+        self.device = torch.device(device)
+        self.max_n, self.max_units, self.n_rows = int(max_n), int(max_units), int(n_rows)
+        ws = tpc_workspace_size(self.max_n, self.max_units, self.n_rows, self.params)
+        if ws == 0:
+            raise ValueError("invalid batch shape or parameters")
+        self.ws_bytes = ws
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        n_min = max(1, int(self.values["n_min"]))
+        self.cap_tracks = int(cap_tracks if cap_tracks is not None else self.max_n // n_min + 1)
+        self.cap_hits = int(cap_hits if cap_hits is not None else self.max_n)
+        d, i32, f32 = self.device, torch.int32, torch.float32
+        ct = max(1, self.cap_tracks)
+        self.o_cluster_track = torch.empty(max(1, self.max_n), dtype=i32, device=d)
+        self.o_params = torch.empty((ct, 5), dtype=f32, device=d)
+        self.o_cov = torch.empty((ct, 15), dtype=f32, device=d)
+        self.o_x_ref = torch.empty(ct, dtype=f32, device=d)
+        self.o_chi2 = torch.empty(ct, dtype=f32, device=d)
+        self.o_unit = torch.empty(ct, dtype=i32, device=d)
+        self.o_n_hits = torch.empty(ct, dtype=i32, device=d)
+        self.o_n_fit = torch.empty(ct, dtype=i32, device=d)
+        self.o_first_hit = torch.empty(ct, dtype=i32, device=d)
+        self.o_hits = torch.empty(max(1, self.cap_hits), dtype=i32, device=d)
+        self.o_counts = torch.zeros(4, dtype=torch.int64, device=d)
+        self.o_status = torch.zeros(1, dtype=i32, device=d)
+        self._last = None
+
+    def tracks_struct(self):
+        o = tpc_tracks_t()
+        o.cap_tracks, o.cap_hits = self.cap_tracks, self.cap_hits
+        o.cluster_track = _ptr(self.o_cluster_track)
+        o.params, o.cov = _ptr(self.o_params), _ptr(self.o_cov)
+        o.x_ref, o.chi2 = _ptr(self.o_x_ref), _ptr(self.o_chi2)
+        o.unit, o.n_hits, o.n_fit = _ptr(self.o_unit), _ptr(self.o_n_hits), _ptr(self.o_n_fit)
+        o.first_hit, o.hits = _ptr(self.o_first_hit), _ptr(self.o_hits)
+        o.counts, o.status = _ptr(self.o_counts), _ptr(self.o_status)
+        return o
+
+    def launch(self, batch: Batch, stream=None):
+        """Enqueue tracking of `batch` on `stream` (default: torch's current stream)."""
+        if batch.n > self.max_n or batch.n_units > self.max_units or batch.n_rows != self.n_rows:
+            raise ValueError("batch larger than this tracker was sized for")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        c, g = batch.clusters_struct(), batch.geometry_struct()
+        f = tpc_field_t()
+        f.bz_tesla = batch.bz
+        o = self.tracks_struct()
+        st = tpc_track_sectors(c, g, f, self.params, o, self.workspace.data_ptr(), self.ws_bytes,
+                               s.cuda_stream)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_track_sectors: %s" % tpc_status_string(st))
+        self._last = batch
+        return st
+
+    def launch_profiled(self, batch: Batch, events, stream=None):
+        """As launch, recording `events` (raw hipEvent_t handles, tpc_kernel_count()+1
+        of them) around every kernel on the same stream."""
+        from . import tpc_track_sectors_profiled
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        c, g = batch.clusters_struct(), batch.geometry_struct()
+        f = tpc_field_t()
+        f.bz_tesla = batch.bz
+        o = self.tracks_struct()
+        st = tpc_track_sectors_profiled(c, g, f, self.params, o, self.workspace.data_ptr(),
+                                        self.ws_bytes, s.cuda_stream, events)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_track_sectors_profiled: %s" % tpc_status_string(st))
+        self._last = batch
+        return st
+
+    def status(self):
+        return int(self.o_status.item())
+
+    def result(self, sync=True):
+        """Trimmed outputs of the last launch (synchronizes)."""
+        if sync:
+            torch.cuda.synchronize(self.device)
+        st = int(self.o_status.item())
+        counts = self.o_counts.cpu().numpy()
+        if st != TPC_OK:
+            raise TrackingError(st, "tracking failed on the device: %s (counts %s)"
+                                % (tpc_status_string(st), counts.tolist()))
+        T, H = int(counts[0]), int(counts[1])
+        n = self._last.n
+        return dict(n_tracks=T, n_track_hits=H, n_tracklets=int(counts[2]), n_cells=int(counts[3]),
+                    cluster_track=self.o_cluster_track[:n], params=self.o_params[:T], cov=self.o_cov[:T],
+                    x_ref=self.o_x_ref[:T], chi2=self.o_chi2[:T], unit=self.o_unit[:T],
+                    n_hits=self.o_n_hits[:T], n_fit=self.o_n_fit[:T], first_hit=self.o_first_hit[:T],
+                    hits=self.o_hits[:H])
+
+    def inspect(self, what, dtype=torch.int32, shape=None):
+        """Copy of an intermediate workspace array of the last launch (tpc_inspect)."""
+        b = self._last
+        v = tpc_inspect(b.clusters_struct(), b.n_rows, self.params, self.workspace.data_ptr(), what)
+        base = self.workspace.data_ptr()
+        off = v.ptr - base
+        nbytes = v.count * v.elem_bytes
+        raw = self.workspace[off:off + nbytes]
+        t = raw.view(dtype)
+        if shape is not None:
+            t = t.view(*shape)
+        return t.clone()
+
+
+def track(y, z, row, unit_offsets, row_x, bz, params=None, device="cuda"):
+    """One-shot convenience: track host arrays on the GPU, return host numpy arrays."""
+    b = Batch(y, z, row, unit_offsets, row_x, bz, device)
+    tr = Tracker(max(1, b.n), b.n_units, b.n_rows, params, device)
+    tr.launch(b)
+    r = tr.result()
+    return {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in r.items()}

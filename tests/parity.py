@@ -1,0 +1,210 @@
+"""Element-by-element comparison of the HIP path with the CPU oracle.
+
+Bars (the FP32 GPU fit against the FP64 oracle fit):
+  * hit grid (permutation, cell table, per-row grid shape), neighbour links,
+    cleaned links, start hits / tracklet list, chain lengths: bit-exact;
+  * tracklet hit sets: identical for >= 99.9% of the tracklets; a tracklet may
+    differ only if the oracle flagged one of its decisions as fragile (a
+    rounded prediction within `fragile_eps` quanta of a rounding boundary
+    whose other rounding changes the pick, or sin(phi) within 1e-5 of the
+    limit);
+  * fitted parameters of identical hit sets: |dp_k| <= 1e-4 max(|p_k|, f_k)
+    with floors f = (1 cm, 1 cm, 1e-2, 1e-2, 0.1 /GeV); covariance diagonal
+    and chi2 within 1e-3 relative (plus a small absolute floor);
+  * owner keys, keep flags and the cluster-to-track map: bit-exact for every
+    cluster and tracklet not touched by a differing tracklet.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PARAM_FLOORS = np.array([1.0, 1.0, 1e-2, 1e-2, 0.1])
+PARAM_RTOL = 1e-4
+COV_RTOL = 1e-3
+CHI2_RTOL = 1e-3
+MIN_MATCHED_FRACTION = 0.999
+
+SEG_FIELDS = ["seg_start", "seg_count", "seg_zmin", "seg_zmax", None, "seg_by", "seg_ny", "seg_bz",
+              "seg_nz", "seg_cell_base"]
+
+
+def gpu_state(tracker, result):
+    """Pull intermediates of the last launch to host numpy arrays."""
+    import torch
+    import paper_2106_03636_amd as T
+    n_rows = tracker.n_rows
+    K = result["n_tracklets"]
+    g = {}
+    g["perm"] = tracker.inspect(T.TPC_VIEW_PERM).cpu().numpy()
+    g["cell"] = tracker.inspect(T.TPC_VIEW_CELL).cpu().numpy()[:result["n_cells"] + 1]
+    g["seg"] = tracker.inspect(T.TPC_VIEW_SEG).cpu().numpy().reshape(-1, 12)
+    for name, what in (("up", T.TPC_VIEW_UP), ("dn", T.TPC_VIEW_DN), ("upc", T.TPC_VIEW_UPC),
+                       ("dnc", T.TPC_VIEW_DNC)):
+        g[name] = tracker.inspect(what).cpu().numpy()
+    g["owner"] = tracker.inspect(T.TPC_VIEW_OWNER).cpu().numpy().view(np.uint32)
+    for name, what in (("trk_start", T.TPC_VIEW_TRK_START), ("trk_unit", T.TPC_VIEW_TRK_UNIT),
+                       ("trk_len", T.TPC_VIEW_TRK_LEN), ("trk_nfit", T.TPC_VIEW_TRK_NFIT),
+                       ("trk_rlo", T.TPC_VIEW_TRK_RLO), ("trk_rhi", T.TPC_VIEW_TRK_RHI),
+                       ("trk_owned", T.TPC_VIEW_TRK_OWNED), ("trk_keep", T.TPC_VIEW_TRK_KEEP)):
+        g[name] = tracker.inspect(what).cpu().numpy()[:K]
+    g["trk_key"] = tracker.inspect(T.TPC_VIEW_TRK_KEY).cpu().numpy().view(np.uint32)[:K]
+    g["trk_params"] = tracker.inspect(T.TPC_VIEW_TRK_PARAMS, torch.float32).cpu().numpy().reshape(-1, 5)[:K]
+    g["trk_cov"] = tracker.inspect(T.TPC_VIEW_TRK_COV, torch.float32).cpu().numpy().reshape(-1, 15)[:K]
+    g["trk_xref"] = tracker.inspect(T.TPC_VIEW_TRK_XREF, torch.float32).cpu().numpy()[:K]
+    g["trk_chi2"] = tracker.inspect(T.TPC_VIEW_TRK_CHI2, torch.float32).cpu().numpy()[:K]
+    hits = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(n_rows, -1)[:, :K]
+    g["trk_hitrows"] = hits
+    for k in ("n_tracks", "n_track_hits", "n_tracklets", "n_cells"):
+        g[k] = result[k]
+    for k in ("cluster_track", "params", "cov", "x_ref", "chi2", "unit", "n_hits", "n_fit",
+              "first_hit", "hits"):
+        g["out_" + k] = result[k].cpu().numpy()
+    return g
+
+
+def gpu_hit_sets(g):
+    """Per tracklet: sorted array of hit positions from the by-row store."""
+    K = g["n_tracklets"]
+    H = g["trk_hitrows"]
+    out = []
+    for t in range(K):
+        lo, hi = g["trk_rlo"][t], g["trk_rhi"][t]
+        if g["trk_nfit"][t] <= 0 or lo < 0:
+            out.append(np.zeros(0, np.int64))
+            continue
+        h = H[lo:hi + 1, t]
+        out.append(np.sort(h[h >= 0]).astype(np.int64))
+    return out
+
+
+def oracle_hit_sets(o):
+    out = []
+    for t in range(o["n_tracklets"]):
+        out.append(np.sort(o["trk_hits"][t, :o["trk_nfit"][t]]).astype(np.int64))
+    return out
+
+
+class ParityReport(dict):
+    def fail(self, msg):
+        self.setdefault("failures", []).append(msg)
+
+    @property
+    def ok(self):
+        return not self.get("failures")
+
+
+def compare(g, o, check_outputs=True, rtol_scale=1.0):
+    """Compare GPU state g (gpu_state) with oracle result o.  Returns a report;
+    report.ok is the verdict, report['failures'] lists what broke."""
+    rep = ParityReport()
+    # --- grid
+    for k in ("perm", "up", "dn", "upc", "dnc"):
+        if not np.array_equal(g[k], o[k]):
+            bad = int(np.sum(g[k] != o[k])) if g[k].shape == o[k].shape else -1
+            rep.fail("%s differs at %d positions" % (k, bad))
+    if g["n_cells"] != o["n_cells"] or not np.array_equal(g["cell"], o["cell_start"]):
+        rep.fail("cell table differs")
+    for j, f in enumerate(SEG_FIELDS):
+        if f is not None and not np.array_equal(g["seg"][:, j], o[f]):
+            rep.fail("segment field %s differs" % f)
+    # --- tracklets
+    K = g["n_tracklets"]
+    rep["n_tracklets"] = K
+    if K != o["n_tracklets"]:
+        rep.fail("tracklet count %d vs %d" % (K, o["n_tracklets"]))
+        return rep
+    for k in ("trk_start", "trk_unit", "trk_len"):
+        if not np.array_equal(g[k], o[k]):
+            rep.fail("%s differs" % k)
+    gs, os_ = gpu_hit_sets(g), oracle_hit_sets(o)
+    same = np.array([len(a) == len(b) and np.array_equal(a, b) for a, b in zip(gs, os_)], bool)
+    same &= g["trk_nfit"] == o["trk_nfit"]
+    diff = np.nonzero(~same)[0]
+    rep["n_hitset_diff"] = int(len(diff))
+    rep["n_fragile"] = int(o["trk_fragile"].sum())
+    seeded = int((o["trk_nfit"] > 0).sum())
+    rep["matched_fraction"] = 1.0 - len(diff) / max(1, seeded)
+    if rep["matched_fraction"] < MIN_MATCHED_FRACTION:
+        rep.fail("only %.5f of tracklet hit sets match" % rep["matched_fraction"])
+    unflagged = [int(t) for t in diff if not o["trk_fragile"][t]]
+    if unflagged:
+        rep.fail("%d differing tracklets not flagged fragile (e.g. %s)" % (len(unflagged), unflagged[:5]))
+    # --- fitted parameters of identical hit sets
+    m = same & (o["trk_nfit"] > 0)
+    if m.any():
+        gp, op = g["trk_params"][m].astype(np.float64), o["trk_params"][m]
+        scale = np.maximum(np.abs(op), PARAM_FLOORS)
+        rel = np.abs(gp - op) / scale
+        rep["param_max_rel"] = rel.max(axis=0).tolist()
+        if np.any(rel > PARAM_RTOL * rtol_scale):
+            worst = np.unravel_index(np.argmax(rel), rel.shape)
+            rep.fail("params outside 1e-4: worst %.3g at component %d" % (rel[worst], worst[1]))
+        diag = [0, 2, 5, 9, 14]
+        gc, oc = g["trk_cov"][m][:, diag].astype(np.float64), o["trk_cov"][m][:, diag]
+        crel = np.abs(gc - oc) / np.maximum(np.abs(oc), 1e-12)
+        rep["cov_max_rel"] = float(crel.max())
+        if crel.max() > COV_RTOL * rtol_scale:
+            rep.fail("covariance outside 1e-3: %.3g" % crel.max())
+        gx, ox = g["trk_chi2"][m].astype(np.float64), o["trk_chi2"][m]
+        xrel = np.abs(gx - ox) / np.maximum(np.abs(ox), 1.0)
+        rep["chi2_max_rel"] = float(xrel.max())
+        if xrel.max() > CHI2_RTOL * rtol_scale:
+            rep.fail("chi2 outside 1e-3: %.3g" % xrel.max())
+        if not np.allclose(g["trk_xref"][m], o["trk_xref"][m], rtol=0, atol=1e-4):
+            rep.fail("x_ref differs")
+    # --- ownership and selection away from differing tracklets
+    touched = np.zeros(len(g["perm"]), bool)
+    for t in diff:
+        touched[gs[t]] = True
+        touched[os_[t]] = True
+    # tracklets sharing a touched hit may change their owned count
+    affected = np.zeros(K, bool)
+    affected[diff] = True
+    for t in range(K):
+        if not affected[t] and (np.any(touched[gs[t]]) or np.any(touched[os_[t]])):
+            affected[t] = True
+    rep["n_affected"] = int(affected.sum())
+    ok_t = ~affected
+    if not np.array_equal(g["trk_key"][ok_t], o["trk_key"][ok_t]):
+        rep.fail("tracklet keys differ")
+    own_ok = ~touched
+    if not np.array_equal(g["owner"][own_ok], o["owner"][own_ok]):
+        rep.fail("owner keys differ on untouched hits")
+    if not np.array_equal(g["trk_keep"][ok_t], o["trk_keep"][ok_t]) or \
+            not np.array_equal(g["trk_owned"][ok_t], o["trk_owned"][ok_t]):
+        rep.fail("selection differs on unaffected tracklets")
+    if check_outputs:
+        # cluster -> tracklet (through the track list) must agree away from affected tracklets
+        g_kept = np.nonzero(g["trk_keep"])[0]
+        o_kept = o["track_tracklet"]
+        def _through(ct, kept):
+            r = np.full(len(ct), -1, np.int64)
+            m = ct >= 0
+            r[m] = kept[ct[m]]
+            return r
+        gct = _through(g["out_cluster_track"], g_kept)
+        oct_ = _through(o["cluster_track"], o_kept)
+        perm = g["perm"]
+        aff_cluster = np.zeros(len(perm), bool)
+        aff_pos = np.zeros(len(perm), bool)
+        for t in np.nonzero(affected)[0]:
+            aff_pos[gs[t]] = True
+            aff_pos[os_[t]] = True
+        aff_cluster[perm[aff_pos]] = True
+        bad = (gct != oct_) & ~aff_cluster
+        rep["cluster_track_mismatch"] = int(bad.sum())
+        if bad.any():
+            rep.fail("cluster_track differs on %d unaffected clusters" % int(bad.sum()))
+        if not affected.any():
+            if not np.array_equal(g["out_cluster_track"], o["cluster_track"]):
+                rep.fail("cluster_track not bit-exact")
+            if g["n_tracks"] != o["n_tracks"] or not np.array_equal(g["out_hits"], o["track_hits"]):
+                rep.fail("track hit lists differ")
+            if not np.array_equal(g["out_n_hits"], o["track_n_hits"]) or \
+                    not np.array_equal(g["out_first_hit"], o["track_first_hit"]):
+                rep.fail("track hit counts / offsets differ")
+        # output params are the kept tracklets' params
+        if len(g_kept) == g["n_tracks"] and g["n_tracks"]:
+            if not np.array_equal(g["out_params"], g["trk_params"][g_kept]):
+                rep.fail("output params are not the kept tracklets' params")
+    return rep

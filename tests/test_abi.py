@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/tpc_track.h declares, sizes workspaces sanely and rejects bad
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2106_03636_amd as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "tpc_track.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = T.load_library()
+    names = _declared_functions()
+    assert {"tpc_track_sectors", "tpc_workspace_size", "tpc_status_string", "tpc_inspect"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the structs have the sizes and field offsets the C
+    compiler gives the header's structs."""
+    import subprocess
+    structs = {"tpc_clusters_t": T.tpc_clusters_t, "tpc_geometry_t": T.tpc_geometry_t,
+               "tpc_field_t": T.tpc_field_t, "tpc_params_t": T.tpc_params_t,
+               "tpc_tracks_t": T.tpc_tracks_t, "tpc_view_t": T.tpc_view_t}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tpc_track.h"', 'int main(void){']
+    for name, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (name, f)]) == getattr(cls, f).offset, (name, f)
+
+
+def test_workspace_size_monotone_and_rejects_bad_shapes():
+    p = T.make_params()
+    a = T.tpc_workspace_size(1000, 1, 152, p)
+    b = T.tpc_workspace_size(100000, 1, 152, p)
+    c = T.tpc_workspace_size(100000, 36, 152, p)
+    assert 0 < a < b < c
+    assert T.tpc_workspace_size(0, 1, 152, p) > 0
+    assert T.tpc_workspace_size(-1, 1, 152, p) == 0
+    assert T.tpc_workspace_size(10, 0, 152, p) == 0
+    assert T.tpc_workspace_size(10, 1, 2, p) == 0
+    assert T.tpc_workspace_size(10, 1, 256, p) == 0
+    assert T.tpc_workspace_size(1 << 30, 1, 152, p) == 0
+    bad = T.make_params()
+    bad.version = 99
+    assert T.tpc_workspace_size(10, 1, 152, bad) == 0
+
+
+def test_invalid_arguments_rejected_on_host():
+    p = T.make_params()
+    c, g, f, o = T.tpc_clusters_t(), T.tpc_geometry_t(), T.tpc_field_t(), T.tpc_tracks_t()
+    assert T.tpc_track_sectors(c, g, f, p, o, 0, 0, 0) == T.TPC_E_INVALID
+    c.n, c.n_units, c.unit_offsets = 10, 1, 0x1000
+    c.y = c.z = c.row = 0x2000
+    g.n_rows, g.row_x = 152, 0x3000
+    f.bz_tesla = 0.5
+    o.counts, o.status, o.cluster_track = 0x4000, 0x5000, 0x6000
+    # misaligned workspace
+    assert T.tpc_track_sectors(c, g, f, p, o, 0x7001, 1 << 30, 0) == T.TPC_E_INVALID
+    # too small workspace
+    assert T.tpc_track_sectors(c, g, f, p, o, 0x7000, 16, 0) == T.TPC_E_NOMEM
+    bad = T.make_params(sinphi_max=1.5)
+    assert T.tpc_track_sectors(c, g, f, bad, o, 0x7000, 1 << 30, 0) == T.TPC_E_INVALID
+    g.n_rows = 300
+    assert T.tpc_track_sectors(c, g, f, p, o, 0x7000, 1 << 30, 0) == T.TPC_E_INVALID
+
+
+def test_status_strings():
+    for s in (T.TPC_OK, T.TPC_E_INVALID, T.TPC_E_CAPACITY, T.TPC_E_NOMEM, T.TPC_E_HIP, T.TPC_E_BUSY):
+        assert T.tpc_status_string(s) and T.tpc_status_string(s) != "unknown status"
+    assert T.tpc_status_string(12345) == "unknown status"
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The library and its binding never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_2106_03636_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, fn
+                assert "tpc_oracle" not in txt, fn

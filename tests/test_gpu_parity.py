@@ -1,0 +1,284 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on the GPU."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import cached_event, cached_oracle
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    import paper_2106_03636_amd as T
+    T.load_library()
+    return T
+
+
+def _run(T, ev, params=None, **kw):
+    from paper_2106_03636_amd.runtime import Batch, Tracker
+    b = Batch.from_event(ev)
+    tr = Tracker(max(1, b.n), b.n_units, b.n_rows, params, **kw)
+    tr.launch(b)
+    res = tr.result()
+    return tr, res
+
+
+def _compare(T, ev, o, params=None):
+    import parity
+    tr, res = _run(T, ev, params)
+    g = parity.gpu_state(tr, res)
+    rep = parity.compare(g, o)
+    _say("parity", ev.name, {k: v for k, v in rep.items() if k != "failures"})
+    assert rep.ok, rep.get("failures")
+    return g, rep
+
+
+class _Ev:
+    """Minimal event from arrays."""
+
+    def __init__(self, y, z, row, off, row_x, bz, name="toy"):
+        self.y, self.z = np.asarray(y, np.float32), np.asarray(z, np.float32)
+        self.row = np.asarray(row, np.uint16)
+        self.unit_offsets = np.asarray(off, np.int64)
+        self.row_x = np.asarray(row_x, np.float32)
+        self.bz = bz
+        self.name = name
+
+    @property
+    def n(self):
+        return len(self.y)
+
+    @property
+    def n_units(self):
+        return len(self.unit_offsets) - 1
+
+
+def test_golden_neighbour_rule_gpu(T):
+    import oracle
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    g = json.load(open(os.path.join(HERE, "golden", "neighbour_rule.json")))
+    c = g["clusters"]
+    ev = _Ev(np.asarray(c["Y"]) / 256.0, np.asarray(c["Z"]) / 256.0, c["row"], [0, len(c["row"])],
+             g["row_x_cm"], g["bz_tesla"], "golden")
+    tr, res = _run(T, ev)
+    perm = tr.inspect(T.TPC_VIEW_PERM).cpu().numpy()
+    for view, key in ((T.TPC_VIEW_DN, "dn_id"), (T.TPC_VIEW_UP, "up_id"), (T.TPC_VIEW_UPC, "clean_up_id"),
+                      (T.TPC_VIEW_DNC, "clean_dn_id")):
+        lk = tr.inspect(view).cpu().numpy()
+        by_id = np.full(ev.n, -1)
+        m = lk >= 0
+        by_id[perm[m]] = perm[lk[m]]
+        assert by_id.tolist() == g["expected"][key], key
+    o = oracle.run_event(ev, P, fragile_eps=0.05)
+    _compare(T, ev, o)
+
+
+def test_parity_pp_sector(T):
+    _say("case pp_sector")
+    _compare(T, cached_event("pp_sector"), cached_oracle("pp_sector"))
+
+
+def test_parity_pbpb_central(T):
+    _say("case pbpb_central")
+    _compare(T, cached_event("pbpb_central"), cached_oracle("pbpb_central"))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_parity_tiny_crowded(T, seed):
+    import oracle
+    from test_oracle_pins import _tiny_inputs
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    row, y, z, row_x = _tiny_inputs(seed)
+    ev = _Ev(y, z, row, [0, len(y)], row_x, 0.5, "tiny%d" % seed)
+    _say("case tiny", seed)
+    _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
+
+
+def test_parity_ragged_units(T):
+    """Units of very different sizes: empty, single cluster, one row only,
+    several tiles with a ragged tail, and a full sector."""
+    import oracle
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    full = cached_event("pbpb_central")
+    pp = cached_event("pp_sector")
+    parts = []
+    parts.append((np.zeros(0), np.zeros(0), np.zeros(0)))                       # empty
+    parts.append((pp.y[:1], pp.z[:1], pp.row[:1]))                              # one cluster
+    one_row = pp.row == 40
+    parts.append((pp.y[one_row], pp.z[one_row], pp.row[one_row]))               # one row
+    parts.append((pp.y[:4097], pp.z[:4097], pp.row[:4097]))                     # 2 tiles + 1
+    s = full.unit(5)
+    parts.append((full.y[s], full.z[s], full.row[s]))                           # a Pb-Pb sector
+    parts.append((pp.y, pp.z, pp.row))                                          # a pp sector
+    parts.append((np.zeros(0), np.zeros(0), np.zeros(0)))                       # empty at the end
+    y = np.concatenate([p[0] for p in parts]).astype(np.float32)
+    z = np.concatenate([p[1] for p in parts]).astype(np.float32)
+    row = np.concatenate([p[2] for p in parts]).astype(np.uint16)
+    off = np.concatenate([[0], np.cumsum([len(p[0]) for p in parts])])
+    ev = _Ev(y, z, row, off, pp.row_x, 0.5, "ragged")
+    _say("case ragged")
+    _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
+
+
+def test_parity_zero_field(T):
+    import oracle
+    import synth
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    rng = np.random.default_rng(5)
+    tr = synth.primaries_pp_sector(rng, 60, 0)
+    xs = synth.helix_crossings(tr, 0.0)
+    m = xs["sector"] == 0
+    y = xs["y"][m] + rng.normal(0, 0.1, m.sum())
+    z = xs["z"][m] + rng.normal(0, 0.15, m.sum())
+    ev = _Ev(y, z, xs["row"][m], [0, int(m.sum())], synth.ROW_X_F32, 0.0, "bz0")
+    _say("case bz0")
+    _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
+
+
+@pytest.mark.parametrize("bins", [(256, 1, 64), (4096, 8, 128)])
+def test_parity_other_bin_sizes(T, bins):
+    import oracle
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    q = dict(P, bin_y_q=bins[0], bin_occ=bins[1], bin_zmin_q=bins[2])
+    ev = cached_event("pp_sector")
+    _say("case bins", bins)
+    _compare(T, ev, oracle.run_event(ev, q, fragile_eps=0.05), params=q)
+
+
+def test_empty_batch(T):
+    import synth
+    ev = _Ev(np.zeros(0), np.zeros(0), np.zeros(0), [0, 0], synth.ROW_X_F32, 0.5, "empty")
+    tr, res = _run(T, ev)
+    assert res["n_tracks"] == 0 and res["n_tracklets"] == 0
+
+
+def test_invalid_input_reports_status_and_next_call_works(T):
+    import torch
+    from paper_2106_03636_amd.runtime import Batch, Tracker, TrackingError
+    pp = cached_event("pp_sector")
+    row = pp.row.copy()
+    row[100] = 200  # beyond the 152 rows
+    bad = Batch(pp.y, pp.z, row, pp.unit_offsets, pp.row_x, pp.bz)
+    tr = Tracker(pp.n, 1)
+    tr.launch(bad)
+    with pytest.raises(TrackingError) as e:
+        tr.result()
+    assert e.value.status == T.TPC_E_INVALID
+    y = pp.y.copy()
+    y[7] = np.nan
+    tr.launch(Batch(y, pp.z, pp.row, pp.unit_offsets, pp.row_x, pp.bz))
+    with pytest.raises(TrackingError):
+        tr.result()
+    good = Batch.from_event(pp)
+    tr.launch(good)
+    res = tr.result()
+    assert res["n_tracks"] == cached_oracle("pp_sector")["n_tracks"]
+
+
+def test_capacity_exceeded_then_retry(T):
+    from paper_2106_03636_amd.runtime import Batch, Tracker, TrackingError
+    pp = cached_event("pp_sector")
+    o = cached_oracle("pp_sector")
+    b = Batch.from_event(pp)
+    tr = Tracker(pp.n, 1, cap_tracks=5)
+    tr.launch(b)
+    with pytest.raises(TrackingError) as e:
+        tr.result()
+    assert e.value.status == T.TPC_E_CAPACITY
+    counts = tr.o_counts.cpu().numpy()
+    assert counts[0] == o["n_tracks"]  # required size reported
+    tr2 = Tracker(pp.n, 1, cap_tracks=int(counts[0]), cap_hits=int(counts[1]))
+    tr2.launch(b)
+    assert tr2.result()["n_tracks"] == o["n_tracks"]
+
+
+def test_rerun_is_bit_identical(T):
+    """Order-independent merges: two runs give identical bits (race check)."""
+    import torch
+    ev = cached_event("pbpb_central")
+    from paper_2106_03636_amd.runtime import Batch, Tracker
+    b = Batch.from_event(ev)
+    tr = Tracker(b.n, b.n_units)
+    outs = []
+    for _ in range(2):
+        tr.launch(b)
+        r = tr.result()
+        outs.append({k: (v.clone() if isinstance(v, torch.Tensor) else v) for k, v in r.items()})
+    for k in outs[0]:
+        a, c = outs[0][k], outs[1][k]
+        if isinstance(a, torch.Tensor):
+            assert torch.equal(a, c), k
+        else:
+            assert a == c, k
+
+
+def _unit_tracks(ev, g, units):
+    """Per cluster of the given units: (local id of the track's start hit) or -1;
+    and per track of those units: its params keyed by the start's local id."""
+    perm = g["perm"]
+    kept = np.nonzero(g["trk_keep"])[0]
+    out_ct, out_params = g["out_cluster_track"], g["out_params"]
+    res_ct, res_par = [], {}
+    for u in units:
+        a, b = int(ev.unit_offsets[u]), int(ev.unit_offsets[u + 1])
+        ct = out_ct[a:b]
+        key = np.full(b - a, -1, np.int64)
+        m = ct >= 0
+        starts = g["trk_start"][kept[ct[m]]]
+        key[m] = perm[starts] - a
+        res_ct.append(key)
+        for t_idx, tl in enumerate(kept):
+            if g["trk_unit"][tl] == u:
+                res_par[(u, int(perm[g["trk_start"][tl]] - a))] = out_params[t_idx]
+    return res_ct, res_par
+
+
+def _full_size_case(T, name, sample_units):
+    """Full-size batch on the GPU (as timed by the benchmark); the oracle runs
+    on a sample of units, which are independent.  Checks (1) GPU(full batch)
+    restricted to the sample == GPU(sample batch), bit for bit, and (2)
+    GPU(sample batch) against the oracle at the parity bars."""
+    import oracle
+    import parity
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    ev = cached_event(name)
+    _say("case full-size", name, ev.n, "clusters")
+    trf, resf = _run(T, ev)
+    gf = parity.gpu_state(trf, resf)
+    sub = ev.subset_units(sample_units)
+    trs, ress = _run(T, sub)
+    gs = parity.gpu_state(trs, ress)
+    ct_f, par_f = _unit_tracks(ev, gf, sample_units)
+    ct_s, par_s = _unit_tracks(sub, gs, range(len(sample_units)))
+    for a, b in zip(ct_f, ct_s):
+        assert np.array_equal(a, b)
+    assert len(par_f) == len(par_s)
+    for (u, k), v in par_f.items():
+        j = list(sample_units).index(u)
+        assert np.array_equal(v, par_s[(j, k)])
+    o = oracle.run_event(sub, P, fragile_eps=0.05)
+    rep = parity.compare(gs, o)
+    _say("parity", name, "sample", list(sample_units), {k: v for k, v in rep.items() if k != "failures"})
+    assert rep.ok, rep.get("failures")
+
+
+def test_parity_timeframe_full_size(T):
+    _full_size_case(T, "pbpb_timeframe_50", [0, 13, 27])
+
+
+def test_parity_uneven_chunks_full_size(T):
+    _full_size_case(T, "uneven_chunks_512", list(range(0, 512, 16)))
