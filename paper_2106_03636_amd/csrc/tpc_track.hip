@@ -27,7 +27,6 @@ namespace {
 constexpr int TPB = 256;          // threads per block of the streaming kernels
 constexpr int TILE = 2048;        // hits per tile of the row pass
 constexpr int ELEMS = 2048;       // elements per block of the start-flag scan
-constexpr int BINS_LDS = 8192;    // bin counters the bin sort keeps in LDS
 constexpr int SEGW = 12;          // int32 per (unit,row) record
 constexpr int CTB = 128;          // threads per block of the constructor
 constexpr float KAPPA = 0.00299792458f;
@@ -408,9 +407,10 @@ __global__ void __launch_bounds__(64) k_tile_offsets(Args A) {
 }
 
 // step 2e: stable scatter of every tile's hits to row order.  Each wave owns a
-// contiguous quarter of the tile and ranks equal rows with ballots, so hits of
-// one row keep the order of their ids.
+// contiguous quarter of the tile, holds its rows in registers, and ranks equal
+// rows with ballots, so hits of one row keep the order of their ids.
 __global__ void __launch_bounds__(TPB) k_tile_scatter(Args A) {
+  constexpr int CH = TILE / 4 / 64;  // 64-hit chunks per wave
   __shared__ int wcnt[4][256];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
@@ -420,11 +420,19 @@ __global__ void __launch_bounds__(TPB) k_tile_scatter(Args A) {
   const int64_t beg = A.off[u] + int64_t(b - w.unit_tiles[u]) * TILE;
   const int64_t end = min(beg + TILE, A.off[u + 1]);
   const int wid = threadIdx.x >> 6, lane = __lane_id();
-  for (int r = threadIdx.x; r < 4 * 256; r += TPB) (&wcnt[0][0])[r] = 0;
-  __syncthreads();
   const int64_t sub_beg = beg + int64_t(wid) * (TILE / 4);
   const int64_t sub_end = min(sub_beg + TILE / 4, end);
-  for (int64_t i = sub_beg + lane; i < sub_end; i += 64) atomicAdd(&wcnt[wid][A.row[i]], 1);
+  int rr[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t i = sub_beg + c * 64 + lane;
+    rr[c] = i < sub_end ? int(A.row[i]) : -1;
+  }
+  for (int r = threadIdx.x; r < 4 * 256; r += TPB) (&wcnt[0][0])[r] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+    if (rr[c] >= 0) atomicAdd(&wcnt[wid][rr[c]], 1);
   __syncthreads();
   for (int r = threadIdx.x; r < A.n_rows; r += TPB) {
     int base = w.tile_hist[int64_t(r) * w.T_max + b];
@@ -436,19 +444,23 @@ __global__ void __launch_bounds__(TPB) k_tile_scatter(Args A) {
     }
   }
   __syncthreads();
-  for (int64_t c = sub_beg; c < sub_end; c += 64) {
-    const int64_t i = c + lane;
-    const bool act = i < sub_end;
-    const int r = act ? A.row[i] : 0;
+  int pos[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const bool act = rr[c] >= 0;
+    const int r = act ? rr[c] : 0;
     const uint64_t peers = peer_mask(uint32_t(r), 8, act);
-    int pos = 0;
-    if (act) pos = wcnt[wid][r] + __popcll(peers & lanemask_lt());
+    pos[c] = act ? wcnt[wid][r] + __popcll(peers & lanemask_lt()) : 0;
     __builtin_amdgcn_wave_barrier();
     if (act && (63 - __clzll(peers)) == lane) wcnt[wid][r] += __popcll(peers);
     __builtin_amdgcn_wave_barrier();
-    if (act) {
-      w.rs_idx[pos] = int32_t(i);
-      w.rs_yz[pos] = make_int2(quant(A.y[i]), quant(A.z[i]));
+  }
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    if (rr[c] >= 0) {
+      const int64_t i = sub_beg + c * 64 + lane;
+      w.rs_idx[pos[c]] = int32_t(i);
+      w.rs_yz[pos[c]] = make_int2(quant(A.y[i]), quant(A.z[i]));
     }
   }
 }
@@ -460,26 +472,14 @@ __device__ __forceinline__ int bin_of(const int32_t *rec, int Y, int Z) {
   return iz * rec[S_NY] + iy;
 }
 
-// step 2f: per (unit,row), counting sort by bin (stable: hits arrive in id
-// order and one wave ranks them chunk by chunk), and the cell table.
-__global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
-  __shared__ int hist_lds[BINS_LDS];
-  __shared__ int tmp[4];
-  const Workspace &w = A.w;
-  if (*A.out.status != TPC_OK) return;
-  const int64_t s = blockIdx.x;
-  const int32_t *rec = w.seg + s * SEGW;
-  const int start = rec[S_START], count = rec[S_COUNT], cbase = rec[S_CBASE];
-  const int nbins = rec[S_NY] * rec[S_NZ];
-  int *hist = nbins <= BINS_LDS ? hist_lds : (w.cursor + cbase);
-  for (int b = threadIdx.x; b < nbins; b += TPB) hist[b] = 0;
-  __syncthreads();
-  for (int p = threadIdx.x; p < count; p += TPB) {
-    const int2 yz = w.rs_yz[start + p];
-    atomicAdd(&hist[bin_of(rec, yz.x, yz.y)], 1);
-  }
-  __syncthreads();
-  // exclusive scan over the bins: each thread takes a contiguous run
+// step 2f: per (unit,row), counting sort by bin, stable (hits arrive in id
+// order and one wave ranks them chunk by chunk with ballots), and the cell
+// table.  Fast path: bins and per-hit ranks in LDS, data moved by all threads
+// afterwards; rows too large for LDS take the same steps with global cursors.
+constexpr int BIN_LDS = 4096;   // bin counters in LDS
+constexpr int HIT_LDS = 8192;   // per-hit slots in LDS
+
+__device__ __forceinline__ void scan_bins(int *hist, int nbins, int32_t *cell_out, int start, int *tmp) {
   const int per = (nbins + TPB - 1) / TPB;
   const int b0 = min(nbins, int(threadIdx.x) * per), b1 = min(nbins, b0 + per);
   int run = 0;
@@ -489,14 +489,69 @@ __global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
   for (int b = b0; b < b1; ++b) {
     const int v = hist[b];
     hist[b] = pre;
-    w.cell[cbase + b] = start + pre;
+    cell_out[b] = start + pre;
     pre += v;
   }
-  __syncthreads();
-  if (threadIdx.x >= 64) return;
+}
+
+__global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
+  __shared__ int hist_lds[BIN_LDS];
+  __shared__ int slot[HIT_LDS];
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t s = blockIdx.x;
+  const int32_t *rec = w.seg + s * SEGW;
+  const int start = rec[S_START], count = rec[S_COUNT], cbase = rec[S_CBASE];
+  const int nbins = rec[S_NY] * rec[S_NZ];
   int nbits = 1;
   while ((1 << nbits) < nbins) ++nbits;
   const int lane = __lane_id();
+  if (nbins <= BIN_LDS && count <= HIT_LDS) {
+    for (int b = threadIdx.x; b < nbins; b += TPB) hist_lds[b] = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < count; p += TPB) {
+      const int2 yz = w.rs_yz[start + p];
+      const int bn = bin_of(rec, yz.x, yz.y);
+      slot[p] = bn;
+      atomicAdd(&hist_lds[bn], 1);
+    }
+    __syncthreads();
+    scan_bins(hist_lds, nbins, w.cell + cbase, start, tmp);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      for (int c = 0; c < count; c += 64) {
+        const int p = c + lane;
+        const bool act = p < count;
+        const int bn = act ? slot[p] : 0;
+        const uint64_t peers = peer_mask(uint32_t(bn), nbits, act);
+        const int lp = act ? hist_lds[bn] + __popcll(peers & lanemask_lt()) : 0;
+        __builtin_amdgcn_wave_barrier();
+        if (act && (63 - __clzll(peers)) == lane) hist_lds[bn] += __popcll(peers);
+        if (act) slot[p] = lp;
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < count; p += TPB) {
+      const int lp = slot[p];
+      w.perm[start + lp] = w.rs_idx[start + p];
+      w.syz[start + lp] = w.rs_yz[start + p];
+    }
+    return;
+  }
+  // large rows: cursors in the workspace
+  int *hist = w.cursor + cbase;
+  for (int b = threadIdx.x; b < nbins; b += TPB) hist[b] = 0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < count; p += TPB) {
+    const int2 yz = w.rs_yz[start + p];
+    atomicAdd(&hist[bin_of(rec, yz.x, yz.y)], 1);
+  }
+  __syncthreads();
+  scan_bins(hist, nbins, w.cell + cbase, start, tmp);
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
   for (int c = 0; c < count; c += 64) {
     const int p = c + lane;
     const bool act = p < count;
@@ -819,23 +874,34 @@ __device__ __forceinline__ void kf_update(KState &s, float my, float mz, float s
   s.chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
 }
 
+// round(v + ref) to the nearest integer, halves to even, for a float v and an
+// integer ref, without forming the (less precise) float sum.
+__device__ __forceinline__ int round_offset(float v, int ref) {
+  const float t = floorf(v);
+  const float fr = v - t;  // exact for |v| < 2^23
+  int r = int(t);
+  if (fr > 0.5f || (fr == 0.5f && ((r + ref) & 1))) ++r;
+  return r + ref;
+}
+
 // Least (w_y dY^2 + w_z dZ^2, id) inside the pickup window of the rounded
-// prediction.  stop = 1 when the prediction has left the sector.
-__device__ int pick(const Args &A, const int32_t *rec, float yp, float zp, bool &stop) {
+// prediction.  The state is relative to the integer reference (Yr, Zr).
+// stop = 1 when the prediction has left the sector.
+__device__ int pick(const Args &A, const int32_t *rec, float yp, float zp, int Yr, int Zr, bool &stop) {
   const Workspace &w = A.w;
   const float vy = yp * 256.f, vz = zp * 256.f;
-  if (!(fabsf(vy) < 2.0e9f)) {
+  if (!(fabsf(vy) < 1.0e9f)) {
     stop = true;
     return -1;
   }
-  const int Yp = __float2int_rn(vy);
+  const int Yp = round_offset(vy, Yr);
   const int H = rec[S_H];
   if (abs(Yp) > H + A.p.ext_edge_q) {
     stop = true;
     return -1;
   }
   if (!(fabsf(vz) < 1.0e9f)) return -1;  // beyond every cluster: a miss
-  const int Zp = __float2int_rn(vz);
+  const int Zp = round_offset(vz, Zr);
   const int WY = A.p.ext_win_y_q, WZ = A.p.ext_win_z_q;
   const Win c = window_cells(rec, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);
   if (c.empty) return -1;
@@ -868,9 +934,11 @@ __device__ __forceinline__ void cov_reset(KState &s, const float *cov0) {
   s.c[14] = cov0[4];
 }
 
-__device__ __forceinline__ void upd_hit(const Args &A, KState &s, int h, float sy2, float sz2) {
+// measurement of hit h relative to the reference (exact: integer difference)
+__device__ __forceinline__ void upd_hit(const Args &A, KState &s, int h, int Yr, int Zr, float sy2,
+                                        float sz2) {
   const int2 yz = A.w.syz[h];
-  kf_update(s, float(yz.x) * (1.f / 256.f), float(yz.y) * (1.f / 256.f), sy2, sz2);
+  kf_update(s, float(yz.x - Yr) * (1.f / 256.f), float(yz.y - Zr) * (1.f / 256.f), sy2, sz2);
 }
 
 __global__ void __launch_bounds__(CTB) k_construct(Args A) {
@@ -909,15 +977,20 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
   const float sy2 = P.sigma_y * P.sigma_y, sz2 = P.sigma_z * P.sigma_z;
   const float k = A.kcurv, smx = P.sinphi_max;
   bool ok = L >= P.l_min;
+  int Yr = 0, Zr = 0;
   KState s;
   if (ok) {
     // seed: circle through the first, middle and last chain hits
     const int ha = hits[int64_t(r1) * Kc], hm = hits[int64_t(r1 + L / 2) * Kc],
               hb = hits[int64_t(r1 + L - 1) * Kc];
     const int2 ya = w.syz[ha], ym = w.syz[hm], yb = w.syz[hb];
+    // the filter state is kept relative to the first chain hit: small numbers
+    // keep FP32 precise even at |z'| of metres (continuous readout)
+    Yr = ya.x;
+    Zr = ya.y;
     const float x0 = A.row_x[r1], x1 = A.row_x[r1 + L / 2], x2 = A.row_x[r1 + L - 1];
-    const float y0 = ya.x * (1.f / 256.f), y1 = ym.x * (1.f / 256.f), y2 = yb.x * (1.f / 256.f);
-    const float z0 = ya.y * (1.f / 256.f), z2 = yb.y * (1.f / 256.f);
+    const float y0 = 0.f, y1 = float(ym.x - Yr) * (1.f / 256.f), y2 = float(yb.x - Yr) * (1.f / 256.f);
+    const float z0 = 0.f, z2 = float(yb.y - Zr) * (1.f / 256.f);
     const float ax = x1 - x0, ay = y1 - y0, bx = x2 - x0, by = y2 - y0, cx = x2 - x1, cy = y2 - y1;
     const float d12 = sqrtf(ax * ax + ay * ay), d13 = sqrtf(bx * bx + by * by),
                 d23 = sqrtf(cx * cx + cy * cy);
@@ -951,7 +1024,7 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
         chain_ok = false;
         break;
       }
-      upd_hit(A, s, hits[int64_t(r1 + j) * Kc], sy2, sz2);
+      upd_hit(A, s, hits[int64_t(r1 + j) * Kc], Yr, Zr, sy2, sz2);
       last = s;
       r_out = r1 + j;
     }
@@ -961,11 +1034,11 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
       for (int r = r1 + L; r < nr; ++r) {
         if (!propagate(s, A.row_x[r], k, smx)) break;
         bool stop = false;
-        const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], stop);
+        const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], Yr, Zr, stop);
         if (stop) break;
         hits[int64_t(r) * Kc] = f;
         if (f >= 0) {
-          upd_hit(A, s, f, sy2, sz2);
+          upd_hit(A, s, f, Yr, Zr, sy2, sz2);
           last = s;
           r_out = r;
           misses = 0;
@@ -978,7 +1051,7 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
     s = last;
     cov_reset(s, P.cov0);
     s.chi2 = 0.f;
-    upd_hit(A, s, hits[int64_t(r_out) * Kc], sy2, sz2);
+    upd_hit(A, s, hits[int64_t(r_out) * Kc], Yr, Zr, sy2, sz2);
     last = s;
     nfit = 1;
     rhi = r_out;
@@ -989,7 +1062,7 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
       if (r >= r1) {
         const int h = hits[int64_t(r) * Kc];
         if (h >= 0) {
-          upd_hit(A, s, h, sy2, sz2);
+          upd_hit(A, s, h, Yr, Zr, sy2, sz2);
           last = s;
           ++nfit;
           rlo = r;
@@ -997,12 +1070,12 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
         }
       }
       bool stop = false;
-      const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], stop);
+      const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], Yr, Zr, stop);
       if (stop) break;
       hits[int64_t(r) * Kc] = f;
       rlo = r;
       if (f >= 0) {
-        upd_hit(A, s, f, sy2, sz2);
+        upd_hit(A, s, f, Yr, Zr, sy2, sz2);
         last = s;
         ++nfit;
         misses = 0;
@@ -1020,6 +1093,10 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
   w.trk_rlo[t] = rlo;
   w.trk_rhi[t] = rhi;
   w.trk_key[t] = key;
+  if (nfit > 0) {  // back to absolute coordinates
+    last.p[0] += float(Yr) * (1.f / 256.f);
+    last.p[1] += float(Zr) * (1.f / 256.f);
+  }
 #pragma unroll
   for (int i = 0; i < 5; ++i) w.trk_par[t * 5 + i] = last.p[i];
 #pragma unroll

@@ -22,8 +22,9 @@ DEFAULT_PARAMS = dict(
     w_y=9,
     w_z=4,
     # score cut: w sigma^2 = 5898.24 q^2, 1.5 for the line through two neighbours,
-    # chi2(2 dof, 99%) = 9.21  ->  S_max(i) = 81482 (X_{i+1} - X_{i-1})^2
-    smax_k=int(round(9 * (0.1 * Q) ** 2 * 1.5 * 9.21)),
+    # chi2 of 2 dof at 20 (tail 4.5e-5: a 150-row track keeps all its links with
+    # probability 0.993)  ->  S_max(i) = 176947 (X_{i+1} - X_{i-1})^2
+    smax_k=int(round(9 * (0.1 * Q) ** 2 * 1.5 * 20.0)),
     l_min=5,
     ext_win_y_q=1 * Q,
     ext_win_z_q=int(1.5 * Q),

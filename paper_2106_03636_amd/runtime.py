@@ -180,3 +180,26 @@ def track(y, z, row, unit_offsets, row_x, bz, params=None, device="cuda"):
     tr.launch(b)
     r = tr.result()
     return {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in r.items()}
+
+
+class GraphRunner:
+    """One tracking call over a resident batch, captured once into a HIP graph
+    (through torch's graph capture on a side stream) and replayed: the whole
+    pipeline becomes a single graph launch.  The call allocates nothing and
+    records no memset, so it is capturable as is."""
+
+    def __init__(self, tracker: Tracker, batch: Batch):
+        self.tracker, self.batch = tracker, batch
+        tracker.launch(batch)
+        torch.cuda.synchronize(tracker.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            tracker.launch(batch)
+        torch.cuda.synchronize(tracker.device)
+
+    def replay(self):
+        self.graph.replay()
+        self.tracker._last = self.batch
+
+    def result(self):
+        return self.tracker.result()

@@ -282,3 +282,41 @@ def test_parity_timeframe_full_size(T):
 
 def test_parity_uneven_chunks_full_size(T):
     _full_size_case(T, "uneven_chunks_512", list(range(0, 512, 16)))
+
+
+def test_graph_capture_replays_match_eager(T):
+    """The whole call captured in a HIP graph: every replay, with eager work on
+    other buffers in between, gives the eager result bit for bit."""
+    import torch
+    from paper_2106_03636_amd.runtime import Batch, GraphRunner, Tracker
+    ev = cached_event("pbpb_central")
+    b = Batch.from_event(ev)
+    tr = Tracker(b.n, b.n_units)
+    tr.launch(b)
+    ref = {k: (v.clone() if isinstance(v, torch.Tensor) else v) for k, v in tr.result().items()}
+    pp = cached_event("pp_sector")
+    b2 = Batch.from_event(pp)
+    tr2 = Tracker(b2.n, 1)
+    gr = GraphRunner(tr, b)
+    for i in range(3):
+        tr2.launch(b2)
+        assert tr2.result()["n_tracks"] == cached_oracle("pp_sector")["n_tracks"]
+        tr.o_cluster_track.fill_(-7)
+        gr.replay()
+        got = gr.result()
+        for k, v in ref.items():
+            if isinstance(v, torch.Tensor):
+                assert torch.equal(v, got[k]), (i, k)
+            else:
+                assert v == got[k], (i, k)
+
+
+def test_autotuner_keeps_tracks_and_picks_a_shape(T, tmp_path):
+    from paper_2106_03636_amd import autotune
+    from paper_2106_03636_amd.runtime import Batch
+    ev = cached_event("pbpb_central")
+    b = Batch.from_event(ev)
+    space = dict(bin_y_q=(384, 1536), bin_occ=(1, 4), bin_zmin_q=(256,))
+    best, table = autotune.tune(b, space=space, reps=1, verify=True)
+    assert len(table) == 4 and all(r["ms"] > 0 for r in table)
+    assert best["bin_y_q"] in (384, 1536)
