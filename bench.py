@@ -37,7 +37,8 @@ KERNEL_FAMILY = {
     "k_init": None, "k_units": None, "k_tile_hist": "grid", "k_seg_plan": "grid",
     "k_cell_base": "grid", "k_tile_offsets": "grid", "k_tile_scatter": "grid", "k_bin_sort": "grid",
     "k_neighbours": "neighbours", "k_clean": "cleaner", "k_scan_blocks": "cleaner",
-    "k_compact_starts": "cleaner", "k_construct": "constructor", "k_select": "selector",
+    "k_compact_starts": "cleaner", "k_chains": "constructor", "k_compact_seeds": "constructor",
+    "k_fit": "constructor", "k_select": "selector",
     "k_emit": "selector",
 }
 
@@ -110,6 +111,8 @@ def main():
     ap.add_argument("--workload", default="pbpb_timeframe_50")
     ap.add_argument("--cpu-units", type=int, default=4, help="units in the CPU-oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X; --gpus %d is not supported (units are independent, "
@@ -127,6 +130,14 @@ def main():
     tr = Tracker(batch.n, batch.n_units, batch.n_rows, device=dev)
     log("bench: workspace %.2f GB" % (tr.ws_bytes / 1e9))
     stream = torch.cuda.current_stream(dev)
+
+    if args.calib_copy:  # a copy kernel of known size for the FETCH_SIZE / WRITE_SIZE scale
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize(dev)
+        del a, b
 
     # warmup
     for _ in range(args.warmup):
@@ -168,7 +179,9 @@ def main():
     mean_k = kern_ms.mean(axis=0)
     per_kernel = {}
     for i, n in enumerate(names):
-        key = n if n not in per_kernel else n + "_2"
+        key, j = n, 2
+        while key in per_kernel:
+            key, j = "%s_%d" % (n, j), j + 1
         per_kernel[key] = round(float(mean_k[i]), 4)
     dom = int(np.argmax(mean_k))
     dom_name = names[dom]

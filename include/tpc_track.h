@@ -170,7 +170,7 @@ const char *tpc_status_string(int status);
  *   TPC_VIEW_PERM      int32 [n]  sorted position -> cluster id
  *   TPC_VIEW_CELL      int32 [cells+1] first sorted position of each grid cell
  *   TPC_VIEW_SEG       int32 [units*n_rows][12] per (unit,row): start, count,
- *                      zmin, zmax, H, by, ny, bz, nz, first cell, 0, 0
+ *                      zmin, zmax, H, by, ny, bz, nz, first cell, first neighbour-finder chunk, 0
  *   TPC_VIEW_UP/DN     int32 [n]  neighbour links (sorted positions, -1 none)
  *   TPC_VIEW_UPC/DNC   int32 [n]  links after cleaning
  *   TPC_VIEW_OWNER     uint32 [n] owner key per sorted position
@@ -198,6 +198,109 @@ typedef struct tpc_view {
  * the call that filled the workspace.  Host-only. */
 int tpc_inspect(const tpc_clusters_t *clusters, int32_t n_rows, const tpc_params_t *params,
                 const void *workspace, int what, tpc_view_t *view);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop for time frames that arrive over time.
+ *
+ * The paper's EPNs take time frames as they arrive, one host core driving one
+ * GPU with several queues, transfers overlapping processing (§3.1.1,
+ * §3.1.2), memory for one time frame plus its scratch reused step by step
+ * (§3.1.3), bounded input/output queues and back pressure when buffers fill
+ * (§3.1.3, §3.3).  A tpc_server_t does that for this library: one host thread
+ * per server admits submitted requests in arrival order while its device
+ * arena has room, packs every admitted request into one batch (units are
+ * independent, so a request's results do not depend on its batch-mates),
+ * runs up to max_in_flight batches on their own streams so that copies and
+ * kernels of different batches overlap, and returns each request's results
+ * in host memory.  The arena and its streams are allocated once, at create.
+ * ------------------------------------------------------------------------ */
+
+typedef struct tpc_server tpc_server_t; /* opaque */
+
+typedef struct tpc_server_config {
+  size_t budget_bytes;         /* device memory the server allocates for batches */
+  int32_t max_in_flight;       /* batches on the GPU at once (one stream each), 1..8 */
+  int32_t queue_depth;         /* requests waiting for admission before submit says BUSY */
+  int64_t max_batch_clusters;  /* clusters packed into one batch (0: no limit) */
+  int32_t max_batch_requests;  /* requests packed into one batch (0: no limit) */
+  int32_t n_rows;              /* geometry, as tpc_geometry_t */
+  const float *row_x;          /* HOST pointer [n_rows]; copied at create */
+  float bz_tesla;
+  int32_t device;              /* HIP device ordinal */
+  tpc_params_t params;
+} tpc_server_config_t;
+
+/* request flags: where the cluster arrays live and who keeps them alive */
+#define TPC_REQ_COPY 0        /* host arrays, copied at submit (reusable at once) */
+#define TPC_REQ_BORROW_HOST 1 /* host arrays (pinned for speed), read until the request is done */
+#define TPC_REQ_DEVICE 2      /* device arrays, read until the request is done (not validated) */
+
+/* One time frame (layout as tpc_clusters_t).  unit_offsets is always a HOST
+ * pointer and is copied at submit; y, z and row follow `flags`. */
+typedef struct tpc_request {
+  int64_t n;
+  int32_t n_units;
+  int32_t flags;               /* TPC_REQ_* */
+  const int64_t *unit_offsets; /* [n_units + 1] */
+  const float *y;
+  const float *z;
+  const uint16_t *row;
+} tpc_request_t;
+
+/* Results of one request, in server-owned host memory valid until
+ * tpc_server_release(ticket).  Cluster ids and track indices are local to the
+ * request (as if it had been tracked alone). */
+typedef struct tpc_result {
+  int32_t status;              /* TPC_OK or the request's error */
+  int32_t reserved;
+  int64_t n, n_tracks, n_track_hits;
+  const int32_t *cluster_track;  /* [n] */
+  const float *params;           /* [n_tracks][5] */
+  const float *cov;              /* [n_tracks][15] */
+  const float *x_ref, *chi2;     /* [n_tracks] */
+  const int32_t *unit, *n_hits, *n_fit, *first_hit; /* [n_tracks] */
+  const int32_t *hits;           /* [n_track_hits] */
+  double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+  int64_t batch_id;              /* batch the request ran in */
+  int32_t batch_requests;        /* requests in that batch */
+  int32_t reserved2;
+} tpc_result_t;
+
+typedef struct tpc_server_stats {
+  int64_t submitted, completed, rejected_busy, rejected_nomem, rejected_invalid, batches;
+  int32_t pending, in_flight;
+  size_t arena_bytes, arena_used, arena_peak;
+} tpc_server_stats_t;
+
+/* Create a server: allocates the arena (budget_bytes of device memory), the
+ * streams and pinned host buffers, and starts its host thread. */
+int tpc_server_create(const tpc_server_config_t *config, tpc_server_t **server);
+
+/* Queue a request.  Returns TPC_OK and a ticket; TPC_E_BUSY when queue_depth
+ * requests are already waiting (back pressure: retry later); TPC_E_NOMEM when
+ * the request could never fit the arena; TPC_E_INVALID when its data are
+ * malformed (checked on the host for host arrays, so one bad request never
+ * fails a batch; device arrays are not checked, and a malformed one fails
+ * every request of its batch with TPC_E_INVALID). */
+int tpc_server_submit(tpc_server_t *server, const tpc_request_t *request, uint64_t *ticket);
+
+/* Results of a ticket.  wait_us = 0: do not wait (TPC_E_BUSY if not done yet);
+ * < 0: wait until done; > 0: wait up to that many microseconds.  Returns
+ * TPC_OK when *result is filled (see result->status), TPC_E_BUSY if not done,
+ * TPC_E_INVALID for an unknown ticket. */
+int tpc_server_poll(tpc_server_t *server, uint64_t ticket, tpc_result_t *result, int64_t wait_us);
+
+/* Free a completed request's results. */
+int tpc_server_release(tpc_server_t *server, uint64_t ticket);
+
+int tpc_server_stats(tpc_server_t *server, tpc_server_stats_t *stats);
+
+/* Finish in-flight work, stop the thread, free everything. */
+int tpc_server_destroy(tpc_server_t *server);
+
+/* Device bytes one request of n clusters in n_units units occupies in the
+ * arena while it runs (inputs, workspace, outputs).  Host-only, pure. */
+size_t tpc_server_footprint(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *params);
 
 #ifdef __cplusplus
 }

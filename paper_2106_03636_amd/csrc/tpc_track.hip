@@ -29,12 +29,13 @@ constexpr int TILE = 2048;        // hits per tile of the row pass
 constexpr int ELEMS = 2048;       // elements per block of the start-flag scan
 constexpr int SEGW = 12;          // int32 per (unit,row) record
 constexpr int CTB = 128;          // threads per block of the constructor
+constexpr int NCH = 256;          // hits per block of the neighbour finder (one per thread)
 constexpr float KAPPA = 0.00299792458f;
 
 // (unit,row) record fields
-enum { S_START = 0, S_COUNT, S_ZMIN, S_ZMAX, S_H, S_BY, S_NY, S_BZ, S_NZ, S_CBASE };
+enum { S_START = 0, S_COUNT, S_ZMIN, S_ZMAX, S_H, S_BY, S_NY, S_BZ, S_NZ, S_CBASE, S_CHUNK };
 // internal counters
-enum { C_K = 0, C_CELLS = 1, C_TRACKS = 2, C_HITS = 3, C_TILES = 4, C_N = 8 };
+enum { C_K = 0, C_CELLS = 1, C_TRACKS = 2, C_HITS = 3, C_TILES = 4, C_NCHUNK = 5, C_SEEDS = 6, C_N = 8 };
 
 struct Workspace {
   int64_t *ctr;
@@ -50,6 +51,7 @@ struct Workspace {
   int32_t *cell, *cursor;
   int32_t *blk, *blk_keep, *blk_own;
   int32_t *trk_start, *trk_unit, *trk_len, *trk_nfit, *trk_rlo, *trk_rhi, *trk_owned, *trk_keep;
+  int32_t *trk_r1, *seed_list;
   uint32_t *trk_key;
   float *trk_par, *trk_cov, *trk_x, *trk_chi2;
   int32_t *trk_hits;
@@ -127,6 +129,8 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.trk_owned = (int32_t *)take(4 * K);
   L.trk_keep = (int32_t *)take(4 * K);
   L.trk_key = (uint32_t *)take(4 * K);
+  L.trk_r1 = (int32_t *)take(4 * K);
+  L.seed_list = (int32_t *)take(4 * K);
   L.trk_par = (float *)take(4 * 5 * K);
   L.trk_cov = (float *)take(4 * 15 * K);
   L.trk_x = (float *)take(4 * K);
@@ -366,17 +370,24 @@ __global__ void __launch_bounds__(1024) k_cell_base(Args A) {
   __shared__ int tmp[16];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  int carry = 0;
+  int carry = 0, ccarry = 0;
   for (int64_t base = 0; base < w.S; base += 1024) {
     const int64_t s = base + threadIdx.x;
     const int v = s < w.S ? w.seg_nbins[s] : 0;
-    int tot;
+    const int nch = s < w.S ? (w.seg[s * SEGW + S_COUNT] + NCH - 1) / NCH : 0;
+    int tot, ctot;
     const int ex = block_exclusive_scan<1024>(v, tmp, &tot);
-    if (s < w.S) w.seg[s * SEGW + S_CBASE] = carry + ex;
+    const int cex = block_exclusive_scan<1024>(nch, tmp, &ctot);
+    if (s < w.S) {
+      w.seg[s * SEGW + S_CBASE] = carry + ex;
+      w.seg[s * SEGW + S_CHUNK] = ccarry + cex;
+    }
     carry += tot;
+    ccarry += ctot;
   }
   if (threadIdx.x == 0) {
     w.ctr[C_CELLS] = carry;
+    w.ctr[C_NCHUNK] = ccarry;
     A.out.counts[3] = carry;
     w.cell[carry] = int32_t(A.n);
   }
@@ -583,6 +594,15 @@ __global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
 // score = w_y R_y^2 + w_z R_z^2, R = (V_d - V_m)(X_u - X_i) + (V_u - V_m)(X_i - X_d),
 // is kept when score <= smax_k (X_{i+1} - X_{i-1})^2.
 
+// a / b for 0 <= a < 2^24 and 0 < b < 2^24: a float quotient is within one
+// of the result, then corrected with integer products.
+__device__ __forceinline__ int div_small(int a, int b, float inv_b) {
+  int q = int(float(a) * inv_b);
+  if (q * b > a) --q;
+  else if ((q + 1) * b <= a) ++q;
+  return q;
+}
+
 struct Win {
   int iy0, iy1, iz0, iz1, ny, cbase;
   bool empty;
@@ -598,85 +618,233 @@ __device__ __forceinline__ Win window_cells(const int32_t *rec, int64_t ylo, int
   const int64_t H = rec[S_H], span = zmax - zmin;
   const int by = rec[S_BY], bz = rec[S_BZ];
   auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
-  c.iy0 = int(cl(ylo + H, 0, 2 * H)) / by;
-  c.iy1 = int(cl(yhi + H, 0, 2 * H)) / by;
-  c.iz0 = int(cl(zlo - zmin, 0, span)) / bz;
-  c.iz1 = int(cl(zhi - zmin, 0, span)) / bz;
+  const float iby = 1.f / float(by), ibz = 1.f / float(bz);
+  c.iy0 = div_small(int(cl(ylo + H, 0, 2 * H)), by, iby);
+  c.iy1 = div_small(int(cl(yhi + H, 0, 2 * H)), by, iby);
+  c.iz0 = div_small(int(cl(zlo - zmin, 0, span)), bz, ibz);
+  c.iz1 = div_small(int(cl(zhi - zmin, 0, span)), bz, ibz);
   c.ny = rec[S_NY];
   c.cbase = rec[S_CBASE];
   return c;
 }
 
-__global__ void __launch_bounds__(TPB) k_neighbours(Args A) {
+// A z-slab of a neighbour row staged in LDS: hits at positions [q0, q0 + nq)
+// and the cell table entries [c0, c0 + nc].
+constexpr int STAGE_HITS = 1024;
+constexpr int STAGE_CELLS = 512;
+
+struct Slab {
+  int q0, nq, c0, nc;
+  bool lds;  // false: read the workspace directly
+};
+
+template <bool LDS>
+__device__ __forceinline__ int cell_at(const Workspace &w, const Slab &sl, const int *lc, int c) {
+  return LDS ? lc[c - sl.c0] : w.cell[c];
+}
+template <bool LDS>
+__device__ __forceinline__ int2 hit_at(const Workspace &w, const Slab &sl, const int2 *lh, int q) {
+  return LDS ? lh[q - sl.q0] : w.syz[q];
+}
+
+// Best (d, u) pair of hit m; see the step description above.
+// floor(a / b) for b > 0 and |a| < 2^52, exactly: an FP64 quotient is off by
+// at most one, then corrected with integer products.
+__device__ __forceinline__ int64_t floor_div_exact(int64_t a, int64_t b) {
+  int64_t q = int64_t(floor(double(a) / double(b)));
+  if (q * b > a) --q;
+  else if ((q + 1) * b <= a) ++q;
+  return q;
+}
+
+// Candidate rows: the exact y interval of the window in row j and its cells.
+struct Cand {
+  int ylo, yhi;  // Y_n in [ylo, yhi]  <=>  |Y_n X_i - Y_m X_j| <= W X_i
+  Win c;
+};
+
+__device__ __forceinline__ Cand cand_window(const int32_t *rec, int64_t Ym, int64_t Zm, int64_t Xi,
+                                            int64_t Xj, int64_t WY, int64_t WZ) {
+  Cand k;
+  const int64_t lo = -floor_div_exact(-(Ym * Xj - WY * Xi), Xi);  // ceil
+  const int64_t hi = floor_div_exact(Ym * Xj + WY * Xi, Xi);
+  // |Y| <= 2^21 for every cluster: clamping keeps the compares exact in int32
+  k.ylo = int(lo < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (lo > (int64_t(1) << 30) ? (int64_t(1) << 30) : lo));
+  k.yhi = int(hi < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (hi > (int64_t(1) << 30) ? (int64_t(1) << 30) : hi));
+  k.c = window_cells(rec, lo, hi, Zm - WZ, Zm + WZ);
+  return k;
+}
+
+constexpr int MAXU = 4;  // row-above candidates kept in registers
+
+// Best (d, u) pair of hit m; see the step description above.
+template <bool LDS>
+__device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *recd, const int32_t *recu,
+                                          const Slab &sd, const Slab &su, const int *lcd, const int *lcu,
+                                          const int2 *lhd, const int2 *lhu, int64_t Xi, int64_t Xd,
+                                          int64_t Xu, int64_t smax, int &best_d, int &best_u) {
   const Workspace &w = A.w;
-  if (*A.out.status != TPC_OK) return;
-  const int64_t s = blockIdx.x;
-  const int r = int(s % A.n_rows);
-  const int32_t *rec = w.seg + s * SEGW;
-  const int start = rec[S_START], count = rec[S_COUNT];
-  if (r == 0 || r == A.n_rows - 1) {
-    for (int p = threadIdx.x; p < count; p += TPB) {
-      w.up[start + p] = -1;
-      w.dn[start + p] = -1;
-    }
-    return;
-  }
-  const int32_t *recd = rec - SEGW, *recu = rec + SEGW;
-  const int64_t Xi = __float2ll_rn(A.row_x[r] * 256.0f);
-  const int64_t Xd = __float2ll_rn(A.row_x[r - 1] * 256.0f);
-  const int64_t Xu = __float2ll_rn(A.row_x[r + 1] * 256.0f);
-  const int64_t dxd = Xi - Xd, dxu = Xu - Xi;
-  const int64_t smax = A.p.smax_k * (Xu - Xd) * (Xu - Xd);
   const int64_t WY = A.p.win_y_q, WZ = A.p.win_z_q, wy = A.p.w_y, wz = A.p.w_z;
-  for (int p = threadIdx.x; p < count; p += TPB) {
-    const int m = start + p;
-    const int2 hm = w.syz[m];
-    const int64_t Ym = hm.x, Zm = hm.y;
-    const Win wd = window_cells(recd, floor_div64(Ym * Xd - WY * Xi, Xi),
-                                floor_div64(Ym * Xd + WY * Xi, Xi) + 1, Zm - WZ, Zm + WZ);
-    const Win wu = window_cells(recu, floor_div64(Ym * Xu - WY * Xi, Xi),
-                                floor_div64(Ym * Xu + WY * Xi, Xi) + 1, Zm - WZ, Zm + WZ);
-    int64_t best_s = INT64_MAX;
-    int best_d = -1, best_u = -1;
-    if (!wd.empty && !wu.empty) {
-      for (int izd = wd.iz0; izd <= wd.iz1; ++izd) {
-        const int cd = wd.cbase + izd * wd.ny;
-        const int q0 = w.cell[cd + wd.iy0], q1 = w.cell[cd + wd.iy1 + 1];
-        for (int d = q0; d < q1; ++d) {
-          const int2 hd = w.syz[d];
-          if (llabs(int64_t(hd.x) * Xi - Ym * Xd) > WY * Xi || llabs(int64_t(hd.y) - Zm) > WZ) continue;
-          const int64_t ay = (int64_t(hd.x) - Ym) * dxu, az = (int64_t(hd.y) - Zm) * dxu;
-          for (int izu = wu.iz0; izu <= wu.iz1; ++izu) {
-            const int cu = wu.cbase + izu * wu.ny;
-            const int v0 = w.cell[cu + wu.iy0], v1 = w.cell[cu + wu.iy1 + 1];
-            for (int uu = v0; uu < v1; ++uu) {
-              const int2 hu = w.syz[uu];
-              if (llabs(int64_t(hu.x) * Xi - Ym * Xu) > WY * Xi || llabs(int64_t(hu.y) - Zm) > WZ) continue;
-              const int64_t ry = ay + (int64_t(hu.x) - Ym) * dxd;
-              const int64_t rz = az + (int64_t(hu.y) - Zm) * dxd;
-              // a residual of 2^28 or more puts the score above 2^56 > smax
-              if ((wy && llabs(ry) >= (int64_t(1) << 28)) || (wz && llabs(rz) >= (int64_t(1) << 28)))
-                continue;
-              const int64_t sc = wy * ry * ry + wz * rz * rz;
-              if (sc > smax || sc > best_s) continue;
-              bool take = sc < best_s;
-              if (!take) {  // equal score: smaller ids win
-                const int idd = w.perm[d], idb = w.perm[best_d];
-                take = idd < idb || (idd == idb && w.perm[uu] < w.perm[best_u]);
-              }
-              if (take) {
-                best_s = sc;
-                best_d = d;
-                best_u = uu;
-              }
-            }
+  const int dxd = int(Xi - Xd), dxu = int(Xu - Xi);
+  const int2 hm = w.syz[m];
+  const int Ym = hm.x, Zm = hm.y;
+  const Cand kd = cand_window(recd, Ym, Zm, Xi, Xd, WY, WZ);
+  const Cand ku = cand_window(recu, Ym, Zm, Xi, Xu, WY, WZ);
+  best_d = -1;
+  best_u = -1;
+  if (kd.c.empty || ku.c.empty) return;
+  const int zlo = Zm - int(WZ), zhi = Zm + int(WZ);
+  // row-above candidates passing the window, kept in registers when few
+  int uq[MAXU];
+  int2 uh[MAXU];
+  int nu = 0;
+  bool overflow = false;
+  for (int izu = ku.c.iz0; izu <= ku.c.iz1; ++izu) {
+    const int cu = ku.c.cbase + izu * ku.c.ny;
+    const int v0 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy0), v1 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy1 + 1);
+    for (int q = v0; q < v1; ++q) {
+      const int2 h = hit_at<LDS>(w, su, lhu, q);
+      if (h.x < ku.ylo || h.x > ku.yhi || h.y < zlo || h.y > zhi) continue;
+#pragma unroll
+      for (int k = 0; k < MAXU; ++k)
+        if (k == nu) {
+          uq[k] = q;
+          uh[k] = h;
+        }
+      if (nu < MAXU) ++nu;
+      else overflow = true;
+    }
+  }
+  if (nu == 0) return;
+  int64_t best_s = INT64_MAX;
+  auto consider = [&](int d, int2 hd, int uu, int2 hu) {
+    const int64_t ry = int64_t(hd.x - Ym) * dxu + int64_t(hu.x - Ym) * dxd;
+    const int64_t rz = int64_t(hd.y - Zm) * dxu + int64_t(hu.y - Zm) * dxd;
+    // a residual of 2^28 or more puts the score above 2^56 > smax
+    if ((wy && llabs(ry) >= (int64_t(1) << 28)) || (wz && llabs(rz) >= (int64_t(1) << 28))) return;
+    const int64_t sc = wy * ry * ry + wz * rz * rz;
+    if (sc > smax || sc > best_s) return;
+    bool take = sc < best_s;
+    if (!take) {  // equal score: smaller ids win
+      const int idd = w.perm[d], idb = w.perm[best_d];
+      take = idd < idb || (idd == idb && w.perm[uu] < w.perm[best_u]);
+    }
+    if (take) {
+      best_s = sc;
+      best_d = d;
+      best_u = uu;
+    }
+  };
+  for (int izd = kd.c.iz0; izd <= kd.c.iz1; ++izd) {
+    const int cd = kd.c.cbase + izd * kd.c.ny;
+    const int q0 = cell_at<LDS>(w, sd, lcd, cd + kd.c.iy0), q1 = cell_at<LDS>(w, sd, lcd, cd + kd.c.iy1 + 1);
+    for (int d = q0; d < q1; ++d) {
+      const int2 hd = hit_at<LDS>(w, sd, lhd, d);
+      if (hd.x < kd.ylo || hd.x > kd.yhi || hd.y < zlo || hd.y > zhi) continue;
+      if (!overflow) {
+#pragma unroll
+        for (int k = 0; k < MAXU; ++k)
+          if (k < nu) consider(d, hd, uq[k], uh[k]);
+      } else {  // many candidates above: scan them again
+        for (int izu = ku.c.iz0; izu <= ku.c.iz1; ++izu) {
+          const int cu = ku.c.cbase + izu * ku.c.ny;
+          const int v0 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy0), v1 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy1 + 1);
+          for (int q = v0; q < v1; ++q) {
+            const int2 h = hit_at<LDS>(w, su, lhu, q);
+            if (h.x < ku.ylo || h.x > ku.yhi || h.y < zlo || h.y > zhi) continue;
+            consider(d, hd, q, h);
           }
         }
       }
     }
-    w.dn[m] = best_d;
-    w.up[m] = best_u;
   }
+}
+
+// Slab of row record `rec` covering z in [zlo, zhi] (all y); stage it when it fits.
+__device__ __forceinline__ Slab make_slab(const Workspace &w, const int32_t *rec, int64_t zlo, int64_t zhi) {
+  Slab sl;
+  sl.q0 = sl.nq = sl.c0 = sl.nc = 0;
+  sl.lds = true;
+  const int count = rec[S_COUNT];
+  const int64_t zmin = rec[S_ZMIN], zmax = rec[S_ZMAX];
+  if (count == 0 || zhi < zmin || zlo > zmax) return sl;  // no candidate will be visited
+  const int64_t span = zmax - zmin;
+  const int bz = rec[S_BZ], ny = rec[S_NY];
+  auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  const int iz0 = int(cl(zlo - zmin, 0, span)) / bz, iz1 = int(cl(zhi - zmin, 0, span)) / bz;
+  sl.c0 = rec[S_CBASE] + iz0 * ny;
+  sl.nc = (iz1 - iz0 + 1) * ny;  // entries c0 .. c0 + nc (inclusive end)
+  sl.q0 = w.cell[sl.c0];
+  sl.nq = w.cell[sl.c0 + sl.nc] - sl.q0;
+  sl.lds = sl.nq <= STAGE_HITS && sl.nc + 1 <= STAGE_CELLS;
+  return sl;
+}
+
+__global__ void __launch_bounds__(NCH) k_neighbours(Args A) {
+  __shared__ int2 lh[2][STAGE_HITS];
+  __shared__ int lc[2][STAGE_CELLS];
+  __shared__ int zr[2];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int b = blockIdx.x;
+  if (b >= w.ctr[C_NCHUNK]) return;
+  // segment of this chunk: last s with chunk base <= b and a non-empty row
+  int lo = 0, hi = int(w.S) - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w.seg[int64_t(mid) * SEGW + S_CHUNK] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int64_t s = lo;
+  const int r = int(s % A.n_rows);
+  const int32_t *rec = w.seg + s * SEGW;
+  const int start = rec[S_START], count = rec[S_COUNT];
+  const int p0 = (b - rec[S_CHUNK]) * NCH;
+  const int n_here = min(NCH, count - p0);
+  const int m = start + p0 + int(threadIdx.x);
+  const bool act = int(threadIdx.x) < n_here;
+  if (r == 0 || r == A.n_rows - 1) {
+    if (act) {
+      w.up[m] = -1;
+      w.dn[m] = -1;
+    }
+    return;
+  }
+  const int32_t *recd = rec - SEGW, *recu = rec + SEGW;
+  // z extent of the chunk (hits are in (z bin, y bin) order, so it is narrow)
+  if (threadIdx.x == 0) {
+    zr[0] = INT32_MAX;
+    zr[1] = INT32_MIN;
+  }
+  __syncthreads();
+  if (act) {
+    const int Z = w.syz[m].y;
+    atomicMin(&zr[0], Z);
+    atomicMax(&zr[1], Z);
+  }
+  __syncthreads();
+  const int64_t WZ = A.p.win_z_q;
+  const int64_t zlo = int64_t(zr[0]) - WZ, zhi = int64_t(zr[1]) + WZ;
+  const Slab sd = make_slab(w, recd, zlo, zhi), su = make_slab(w, recu, zlo, zhi);
+  const bool staged = sd.lds && su.lds;
+  if (staged) {
+    for (int i = threadIdx.x; i < sd.nq; i += NCH) lh[0][i] = w.syz[sd.q0 + i];
+    for (int i = threadIdx.x; i < su.nq; i += NCH) lh[1][i] = w.syz[su.q0 + i];
+    for (int i = threadIdx.x; i <= sd.nc && sd.nq + sd.nc > 0; i += NCH) lc[0][i] = w.cell[sd.c0 + i];
+    for (int i = threadIdx.x; i <= su.nc && su.nq + su.nc > 0; i += NCH) lc[1][i] = w.cell[su.c0 + i];
+  }
+  __syncthreads();
+  if (!act) return;
+  const int64_t Xi = __float2ll_rn(A.row_x[r] * 256.0f);
+  const int64_t Xd = __float2ll_rn(A.row_x[r - 1] * 256.0f);
+  const int64_t Xu = __float2ll_rn(A.row_x[r + 1] * 256.0f);
+  const int64_t smax = A.p.smax_k * (Xu - Xd) * (Xu - Xd);
+  int bd, bu;
+  if (staged)
+    best_pair<true>(A, m, recd, recu, sd, su, lc[0], lc[1], lh[0], lh[1], Xi, Xd, Xu, smax, bd, bu);
+  else
+    best_pair<false>(A, m, recd, recu, sd, su, nullptr, nullptr, nullptr, nullptr, Xi, Xd, Xu, smax, bd, bu);
+  w.dn[m] = bd;
+  w.up[m] = bu;
 }
 
 // ---------------------------------------------------------------------------
@@ -941,105 +1109,170 @@ __device__ __forceinline__ void upd_hit(const Args &A, KState &s, int h, int Yr,
   kf_update(s, float(yz.x - Yr) * (1.f / 256.f), float(yz.y - Zr) * (1.f / 256.f), sy2, sz2);
 }
 
-__global__ void __launch_bounds__(CTB) k_construct(Args A) {
+// Parameter-only transport to x2 (the prediction of a row); the same
+// operations as propagate(), so a later propagate() to x2 reproduces it.
+__device__ __forceinline__ bool predict(const KState &s, float x2, float k, float sinmax, float &yp,
+                                        float &zp) {
+  const float dx = x2 - s.x;
+  const float C = k * s.p[4];
+  const float s1 = s.p[2], s2 = s1 + C * dx;
+  if (!(fabsf(s1) < sinmax) || !(fabsf(s2) < sinmax)) return false;
+  const float c1 = sqrtf(1.f - s1 * s1), c2 = sqrtf(1.f - s2 * s2);
+  const float D = c1 + c2, N = s1 + s2;
+  const float iD = 1.f / D;
+  const float dy = dx * N * iD;
+  const float L = sqrtf(dx * dx + dy * dy);
+  const float u = fabsf(C) * L * 0.5f;
+  if (!(u < 1.f)) return false;
+  const float sg = dx < 0.f ? -1.f : 1.f;
+  const float sT = sg * L * asin_over(u);
+  yp = s.p[0] + dy;
+  zp = s.p[1] + s.p[3] * sT;
+  return true;
+}
+
+// step 5a: chains.  Per tracklet: the row of its start hit and the chain along
+// the cleaned upward links (a cellular automaton over pad rows), stored by row
+// in the hit table; chains of >= l_min hits become seeds.  Other tracklets are
+// finalised here (no fit, no hits).
+__global__ void __launch_bounds__(TPB) k_chains(Args A) {
+  __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t t = int64_t(blockIdx.x) * CTB + threadIdx.x;
-  if (t >= w.ctr[C_K]) return;
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  int seed = 0;
+  if (t < w.ctr[C_K]) {
+    const int64_t Kc = w.K_cap;
+    const int nr = A.n_rows;
+    const int h0 = w.trk_start[t], u = w.trk_unit[t];
+    const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
+    int lo = 0, hi = nr - 1;  // row of the start hit: last row whose start <= h0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
+    }
+    const int r1 = lo;
+    int32_t *hits = w.trk_hits + t;
+    int L = 0;
+    for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
+      hits[int64_t(r1 + L) * Kc] = h;
+      ++L;
+    }
+    w.trk_len[t] = L;
+    w.trk_r1[t] = r1;
+    seed = L >= A.p.l_min;
+    if (!seed) {
+      w.trk_nfit[t] = 0;
+      w.trk_rlo[t] = -1;
+      w.trk_rhi[t] = -1;
+      w.trk_key[t] = 0u;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) w.trk_par[t * 5 + i] = 0.f;
+#pragma unroll
+      for (int i = 0; i < 15; ++i) w.trk_cov[t * 15 + i] = 0.f;
+      w.trk_x[t] = 0.f;
+      w.trk_chi2[t] = 0.f;
+    }
+  }
+  int tot;
+  block_exclusive_scan<TPB>(seed, tmp, &tot);
+  if (threadIdx.x == 0) w.blk_keep[blockIdx.x] = tot;
+}
+
+// step 5b: list of seeds in tracklet order
+__global__ void __launch_bounds__(TPB) k_compact_seeds(Args A) {
+  __shared__ int tmp[4];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  const int seed = (t < w.ctr[C_K] && w.trk_len[t] >= A.p.l_min) ? 1 : 0;
+  int tot;
+  const int ex = block_exclusive_scan<TPB>(seed, tmp, &tot);
+  if (seed) w.seed_list[w.blk_keep[blockIdx.x] + ex] = int32_t(t);
+}
+
+// step 5c: Kalman fit of every seed, one seed per lane.
+// Seed: circle through the first, middle and last chain hits.  Pass 1 fits
+// the chain inner to outer and extends it to the last row; pass 2 restarts
+// from the outermost hit with the covariance reset and walks down to row 0,
+// reusing pass-1 hits and picking hits in the other rows.  The filter keeps
+// one committed state (at its last update); each row is predicted by a
+// parameter-only transport from it, and the covariance is transported only
+// when a hit is picked (helix transports compose exactly).
+__global__ void __launch_bounds__(CTB) k_fit(Args A) {
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t i = int64_t(blockIdx.x) * CTB + threadIdx.x;
+  if (i >= w.ctr[C_SEEDS]) return;
+  const int64_t t = w.seed_list[i];
   const tpc_params_t &P = A.p;
   const int64_t Kc = w.K_cap;
   const int nr = A.n_rows;
   const int h0 = w.trk_start[t], u = w.trk_unit[t];
+  const int L = w.trk_len[t], r1 = w.trk_r1[t];
   const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
   int32_t *hits = w.trk_hits + t;  // row r at hits[r * Kc]
-  // row of the start hit: last row whose start <= h0
-  int lo = 0, hi = nr - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
-  }
-  const int r1 = lo;
-  // chain walk (cellular-automaton chain along the cleaned upward links)
-  int L = 0;
-  for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
-    hits[int64_t(r1 + L) * Kc] = h;
-    ++L;
-  }
-  w.trk_len[t] = L;
-  int nfit = 0, rlo = -1, rhi = -1;
-  KState last;
-  last.chi2 = 0.f;
-  last.x = 0.f;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) last.p[i] = 0.f;
-#pragma unroll
-  for (int i = 0; i < 15; ++i) last.c[i] = 0.f;
   const float sy2 = P.sigma_y * P.sigma_y, sz2 = P.sigma_z * P.sigma_z;
   const float k = A.kcurv, smx = P.sinphi_max;
-  bool ok = L >= P.l_min;
-  int Yr = 0, Zr = 0;
+  int nfit = 0, rlo = -1, rhi = -1;
   KState s;
-  if (ok) {
-    // seed: circle through the first, middle and last chain hits
-    const int ha = hits[int64_t(r1) * Kc], hm = hits[int64_t(r1 + L / 2) * Kc],
-              hb = hits[int64_t(r1 + L - 1) * Kc];
-    const int2 ya = w.syz[ha], ym = w.syz[hm], yb = w.syz[hb];
-    // the filter state is kept relative to the first chain hit: small numbers
-    // keep FP32 precise even at |z'| of metres (continuous readout)
-    Yr = ya.x;
-    Zr = ya.y;
+  // seed, in coordinates relative to the first chain hit: small numbers keep
+  // FP32 precise even at |z'| of metres (continuous readout)
+  const int ha = hits[int64_t(r1) * Kc], hm = hits[int64_t(r1 + L / 2) * Kc],
+            hb = hits[int64_t(r1 + L - 1) * Kc];
+  const int2 ya = w.syz[ha], ym = w.syz[hm], yb = w.syz[hb];
+  const int Yr = ya.x, Zr = ya.y;
+  bool ok;
+  {
     const float x0 = A.row_x[r1], x1 = A.row_x[r1 + L / 2], x2 = A.row_x[r1 + L - 1];
-    const float y0 = 0.f, y1 = float(ym.x - Yr) * (1.f / 256.f), y2 = float(yb.x - Yr) * (1.f / 256.f);
-    const float z0 = 0.f, z2 = float(yb.y - Zr) * (1.f / 256.f);
-    const float ax = x1 - x0, ay = y1 - y0, bx = x2 - x0, by = y2 - y0, cx = x2 - x1, cy = y2 - y1;
+    const float y1 = float(ym.x - Yr) * (1.f / 256.f), y2 = float(yb.x - Yr) * (1.f / 256.f);
+    const float z2 = float(yb.y - Zr) * (1.f / 256.f);
+    const float ax = x1 - x0, ay = y1, bx = x2 - x0, by = y2, cx = x2 - x1, cy = y2 - y1;
     const float d12 = sqrtf(ax * ax + ay * ay), d13 = sqrtf(bx * bx + by * by),
                 d23 = sqrtf(cx * cx + cy * cy);
     ok = d12 > 0.f && d13 > 0.f && d23 > 0.f;
-    if (ok) {
-      const float C = 2.f * (ax * by - ay * bx) / (d12 * d13 * d23);
-      const float sa = C * d13 * 0.5f;
-      ok = fabsf(sa) < 1.f;
-      if (ok) {
-        const float ca = sqrtf(1.f - sa * sa);
-        const float sphi = (by / d13) * ca - (bx / d13) * sa;
-        ok = fabsf(sphi) < smx;
-        const float sT = d13 * asin_over(fabsf(sa));
-        s.p[0] = y0;
-        s.p[1] = z0;
-        s.p[2] = sphi;
-        s.p[3] = (z2 - z0) / sT;
-        s.p[4] = k != 0.f ? C / k : 0.f;
-        s.x = x0;
-        s.chi2 = 0.f;
-        cov_reset(s, P.cov0);
-      }
-    }
+    const float C = ok ? 2.f * (ax * by - ay * bx) / (d12 * d13 * d23) : 0.f;
+    const float sa = ok ? C * d13 * 0.5f : 0.f;
+    ok = ok && fabsf(sa) < 1.f;
+    const float ca = sqrtf(fmaxf(0.f, 1.f - sa * sa));
+    const float sphi = ok ? (by / d13) * ca - (bx / d13) * sa : 0.f;
+    ok = ok && fabsf(sphi) < smx;
+    const float sT = ok ? d13 * asin_over(fabsf(sa)) : 1.f;
+    s.p[0] = 0.f;
+    s.p[1] = 0.f;
+    s.p[2] = sphi;
+    s.p[3] = z2 / sT;
+    s.p[4] = k != 0.f ? C / k : 0.f;
+    s.x = x0;
+    s.chi2 = 0.f;
+    cov_reset(s, P.cov0);
   }
   if (ok) {
-    // pass 1: the chain, inner to outer
+    // pass 1: the chain
     int r_out = r1;
     bool chain_ok = true;
-    for (int j = 0; j < L; ++j) {
-      if (j > 0 && !propagate(s, A.row_x[r1 + j], k, smx)) {
+    upd_hit(A, s, ha, Yr, Zr, sy2, sz2);
+    for (int j = 1; j < L; ++j) {
+      if (!propagate(s, A.row_x[r1 + j], k, smx)) {
         chain_ok = false;
         break;
       }
       upd_hit(A, s, hits[int64_t(r1 + j) * Kc], Yr, Zr, sy2, sz2);
-      last = s;
       r_out = r1 + j;
     }
     // pass 1: extension to the outer rows
     if (chain_ok) {
       int misses = 0;
       for (int r = r1 + L; r < nr; ++r) {
-        if (!propagate(s, A.row_x[r], k, smx)) break;
+        float yp, zp;
+        if (!predict(s, A.row_x[r], k, smx, yp, zp)) break;
         bool stop = false;
-        const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], Yr, Zr, stop);
+        const int f = pick(A, segu + r * SEGW, yp, zp, Yr, Zr, stop);
         if (stop) break;
         hits[int64_t(r) * Kc] = f;
         if (f >= 0) {
+          propagate(s, A.row_x[r], k, smx);
           upd_hit(A, s, f, Yr, Zr, sy2, sz2);
-          last = s;
           r_out = r;
           misses = 0;
         } else if (++misses > P.max_miss) {
@@ -1048,35 +1281,34 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
       }
     }
     // pass 2: from the outermost hit down to row 0, covariance reset
-    s = last;
     cov_reset(s, P.cov0);
     s.chi2 = 0.f;
     upd_hit(A, s, hits[int64_t(r_out) * Kc], Yr, Zr, sy2, sz2);
-    last = s;
     nfit = 1;
     rhi = r_out;
     rlo = r_out;
     int misses = 0;
     for (int r = r_out - 1; r >= 0; --r) {
-      if (!propagate(s, A.row_x[r], k, smx)) break;
       if (r >= r1) {
         const int h = hits[int64_t(r) * Kc];
         if (h >= 0) {
+          if (!propagate(s, A.row_x[r], k, smx)) break;
           upd_hit(A, s, h, Yr, Zr, sy2, sz2);
-          last = s;
           ++nfit;
           rlo = r;
           continue;
         }
       }
+      float yp, zp;
+      if (!predict(s, A.row_x[r], k, smx, yp, zp)) break;
       bool stop = false;
-      const int f = pick(A, segu + r * SEGW, s.p[0], s.p[1], Yr, Zr, stop);
+      const int f = pick(A, segu + r * SEGW, yp, zp, Yr, Zr, stop);
       if (stop) break;
       hits[int64_t(r) * Kc] = f;
       rlo = r;
       if (f >= 0) {
+        propagate(s, A.row_x[r], k, smx);
         upd_hit(A, s, f, Yr, Zr, sy2, sz2);
-        last = s;
         ++nfit;
         misses = 0;
       } else if (r < r1 && ++misses > P.max_miss) {
@@ -1088,21 +1320,26 @@ __global__ void __launch_bounds__(CTB) k_construct(Args A) {
   if (nfit > 0) {
     const uint32_t local = uint32_t(w.perm[h0] - A.off[u]);
     key = (uint32_t(nfit) << 24) | (0xFFFFFFu - local);
+    s.p[0] += float(Yr) * (1.f / 256.f);  // back to absolute coordinates
+    s.p[1] += float(Zr) * (1.f / 256.f);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s.p[j] = 0.f;
+#pragma unroll
+    for (int j = 0; j < 15; ++j) s.c[j] = 0.f;
+    s.x = 0.f;
+    s.chi2 = 0.f;
   }
   w.trk_nfit[t] = nfit;
   w.trk_rlo[t] = rlo;
   w.trk_rhi[t] = rhi;
   w.trk_key[t] = key;
-  if (nfit > 0) {  // back to absolute coordinates
-    last.p[0] += float(Yr) * (1.f / 256.f);
-    last.p[1] += float(Zr) * (1.f / 256.f);
-  }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) w.trk_par[t * 5 + i] = last.p[i];
+  for (int j = 0; j < 5; ++j) w.trk_par[t * 5 + j] = s.p[j];
 #pragma unroll
-  for (int i = 0; i < 15; ++i) w.trk_cov[t * 15 + i] = last.c[i];
-  w.trk_x[t] = last.x;
-  w.trk_chi2[t] = last.chi2;
+  for (int j = 0; j < 15; ++j) w.trk_cov[t * 15 + j] = s.c[j];
+  w.trk_x[t] = s.x;
+  w.trk_chi2[t] = s.chi2;
   // ownership: every hit goes to the tracklet with the largest key
   if (nfit > 0)
     for (int r = rlo; r <= rhi; ++r) {
@@ -1213,8 +1450,8 @@ namespace {
 const char *const kKernelNames[] = {
     "k_init",        "k_units",      "k_tile_hist",  "k_seg_plan",      "k_cell_base",
     "k_tile_offsets", "k_tile_scatter", "k_bin_sort",  "k_neighbours",    "k_clean",
-    "k_scan_blocks", "k_compact_starts", "k_construct", "k_select",       "k_scan_blocks",
-    "k_emit"};
+    "k_scan_blocks", "k_compact_starts", "k_chains", "k_scan_blocks", "k_compact_seeds",
+    "k_fit",         "k_select",     "k_scan_blocks", "k_emit"};
 constexpr int kNumKernels = int(sizeof(kKernelNames) / sizeof(kKernelNames[0]));
 
 int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field_t *f,
@@ -1276,7 +1513,7 @@ int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field
     mark();
     hipLaunchKernelGGL(k_bin_sort, dim3(unsigned(w.S)), dim3(TPB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_neighbours, dim3(unsigned(w.S)), dim3(TPB), 0, st, A);
+    hipLaunchKernelGGL(k_neighbours, dim3(unsigned(c->n / NCH + w.S)), dim3(NCH), 0, st, A);
     mark();
     hipLaunchKernelGGL(k_clean, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
     mark();
@@ -1286,7 +1523,15 @@ int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field
     mark();
     hipLaunchKernelGGL(k_compact_starts, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_construct, dim3(blocks_for(w.K_cap, CTB)), dim3(CTB), 0, st, A);
+    hipLaunchKernelGGL(k_chains, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, w.blk_keep, w.KB, w.ctr + C_SEEDS,
+                       (int64_t *)nullptr, w.K_cap, out->status, (int32_t *)nullptr, (int64_t *)nullptr,
+                       (int64_t *)nullptr, int64_t(0));
+    mark();
+    hipLaunchKernelGGL(k_compact_seeds, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_fit, dim3(blocks_for(w.K_cap, CTB)), dim3(CTB), 0, st, A);
     mark();
     hipLaunchKernelGGL(k_select, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
     mark();
