@@ -178,7 +178,7 @@ const char *tpc_status_string(int status);
  *     START int32, UNIT int32, LEN int32, NFIT int32, RLO int32, RHI int32,
  *     KEY uint32, OWNED int32, KEEP int32, PARAMS float[5], COV float[15],
  *     XREF float, CHI2 float,
- *     HITS int32 [n_rows][capacity] hit of each row (-1 none), rows RLO..RHI. */
+ *     HITS int32 [capacity][n_rows] hit of each row (-1 none), rows RLO..RHI. */
 enum {
   TPC_VIEW_PERM = 1, TPC_VIEW_CELL, TPC_VIEW_SEG, TPC_VIEW_UP, TPC_VIEW_DN, TPC_VIEW_UPC,
   TPC_VIEW_DNC, TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN,

@@ -1142,7 +1142,6 @@ __global__ void __launch_bounds__(TPB) k_chains(Args A) {
   const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
   int seed = 0;
   if (t < w.ctr[C_K]) {
-    const int64_t Kc = w.K_cap;
     const int nr = A.n_rows;
     const int h0 = w.trk_start[t], u = w.trk_unit[t];
     const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
@@ -1152,10 +1151,10 @@ __global__ void __launch_bounds__(TPB) k_chains(Args A) {
       if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
     }
     const int r1 = lo;
-    int32_t *hits = w.trk_hits + t;
+    int32_t *hits = w.trk_hits + t * nr;  // tracklet-major: row r at hits[r]
     int L = 0;
     for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
-      hits[int64_t(r1 + L) * Kc] = h;
+      hits[r1 + L] = h;
       ++L;
     }
     w.trk_len[t] = L;
@@ -1172,6 +1171,8 @@ __global__ void __launch_bounds__(TPB) k_chains(Args A) {
       for (int i = 0; i < 15; ++i) w.trk_cov[t * 15 + i] = 0.f;
       w.trk_x[t] = 0.f;
       w.trk_chi2[t] = 0.f;
+      w.trk_owned[t] = 0;
+      w.trk_keep[t] = 0;
     }
   }
   int tot;
@@ -1206,20 +1207,18 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
   if (i >= w.ctr[C_SEEDS]) return;
   const int64_t t = w.seed_list[i];
   const tpc_params_t &P = A.p;
-  const int64_t Kc = w.K_cap;
   const int nr = A.n_rows;
   const int h0 = w.trk_start[t], u = w.trk_unit[t];
   const int L = w.trk_len[t], r1 = w.trk_r1[t];
   const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
-  int32_t *hits = w.trk_hits + t;  // row r at hits[r * Kc]
+  int32_t *hits = w.trk_hits + t * nr;  // tracklet-major: row r at hits[r]
   const float sy2 = P.sigma_y * P.sigma_y, sz2 = P.sigma_z * P.sigma_z;
   const float k = A.kcurv, smx = P.sinphi_max;
   int nfit = 0, rlo = -1, rhi = -1;
   KState s;
   // seed, in coordinates relative to the first chain hit: small numbers keep
   // FP32 precise even at |z'| of metres (continuous readout)
-  const int ha = hits[int64_t(r1) * Kc], hm = hits[int64_t(r1 + L / 2) * Kc],
-            hb = hits[int64_t(r1 + L - 1) * Kc];
+  const int ha = hits[r1], hm = hits[r1 + L / 2], hb = hits[r1 + L - 1];
   const int2 ya = w.syz[ha], ym = w.syz[hm], yb = w.syz[hb];
   const int Yr = ya.x, Zr = ya.y;
   bool ok;
@@ -1257,7 +1256,7 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
         chain_ok = false;
         break;
       }
-      upd_hit(A, s, hits[int64_t(r1 + j) * Kc], Yr, Zr, sy2, sz2);
+      upd_hit(A, s, hits[r1 + j], Yr, Zr, sy2, sz2);
       r_out = r1 + j;
     }
     // pass 1: extension to the outer rows
@@ -1269,7 +1268,7 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
         bool stop = false;
         const int f = pick(A, segu + r * SEGW, yp, zp, Yr, Zr, stop);
         if (stop) break;
-        hits[int64_t(r) * Kc] = f;
+        hits[r] = f;
         if (f >= 0) {
           propagate(s, A.row_x[r], k, smx);
           upd_hit(A, s, f, Yr, Zr, sy2, sz2);
@@ -1283,14 +1282,14 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
     // pass 2: from the outermost hit down to row 0, covariance reset
     cov_reset(s, P.cov0);
     s.chi2 = 0.f;
-    upd_hit(A, s, hits[int64_t(r_out) * Kc], Yr, Zr, sy2, sz2);
+    upd_hit(A, s, hits[r_out], Yr, Zr, sy2, sz2);
     nfit = 1;
     rhi = r_out;
     rlo = r_out;
     int misses = 0;
     for (int r = r_out - 1; r >= 0; --r) {
       if (r >= r1) {
-        const int h = hits[int64_t(r) * Kc];
+        const int h = hits[r];
         if (h >= 0) {
           if (!propagate(s, A.row_x[r], k, smx)) break;
           upd_hit(A, s, h, Yr, Zr, sy2, sz2);
@@ -1304,7 +1303,7 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
       bool stop = false;
       const int f = pick(A, segu + r * SEGW, yp, zp, Yr, Zr, stop);
       if (stop) break;
-      hits[int64_t(r) * Kc] = f;
+      hits[r] = f;
       rlo = r;
       if (f >= 0) {
         propagate(s, A.row_x[r], k, smx);
@@ -1343,7 +1342,7 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
   // ownership: every hit goes to the tracklet with the largest key
   if (nfit > 0)
     for (int r = rlo; r <= rhi; ++r) {
-      const int h = hits[int64_t(r) * Kc];
+      const int h = hits[r];
       if (h >= 0) atomicMax(&w.owner[h], key);
     }
 }
@@ -1352,19 +1351,24 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
 // step 6: selector.  Keep a tracklet that owns >= n_min of its hits and at
 // least f_min of them; tracks keep the tracklet order; no refit.
 
+// Runs over the seed list (tracklets that are not seeds own nothing and are
+// never kept; k_chains set their owned = keep = 0).  Seeds are in tracklet
+// order, so scans over seed order number the tracks in tracklet order.
 __global__ void __launch_bounds__(TPB) k_select(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  const int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x;
   int keep = 0, owned = 0;
-  if (t < w.ctr[C_K]) {
+  if (i < w.ctr[C_SEEDS]) {
+    const int64_t t = w.seed_list[i];
     const int nfit = w.trk_nfit[t];
     if (nfit > 0) {
       const uint32_t key = w.trk_key[t];
       const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
+      const int32_t *hits = w.trk_hits + t * A.n_rows;
       for (int r = rlo; r <= rhi; ++r) {
-        const int h = w.trk_hits[int64_t(r) * w.K_cap + t];
+        const int h = hits[r];
         if (h >= 0 && w.owner[h] == key) ++owned;
       }
       keep = owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
@@ -1385,8 +1389,9 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  const bool valid = t < w.ctr[C_K];
+  const int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  const bool valid = i < w.ctr[C_SEEDS];
+  const int64_t t = valid ? w.seed_list[i] : 0;
   const int keep = valid ? w.trk_keep[t] : 0;
   const int owned = keep ? w.trk_owned[t] : 0;
   int tk, to;
@@ -1397,9 +1402,9 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   int off = w.blk_own[blockIdx.x] + eo;
   const tpc_tracks_t &O = A.out;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) O.params[int64_t(tr) * 5 + i] = w.trk_par[t * 5 + i];
+  for (int j = 0; j < 5; ++j) O.params[int64_t(tr) * 5 + j] = w.trk_par[t * 5 + j];
 #pragma unroll
-  for (int i = 0; i < 15; ++i) O.cov[int64_t(tr) * 15 + i] = w.trk_cov[t * 15 + i];
+  for (int j = 0; j < 15; ++j) O.cov[int64_t(tr) * 15 + j] = w.trk_cov[t * 15 + j];
   O.x_ref[tr] = w.trk_x[t];
   O.chi2[tr] = w.trk_chi2[t];
   O.unit[tr] = w.trk_unit[t];
@@ -1408,8 +1413,9 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   O.first_hit[tr] = off;
   const uint32_t key = w.trk_key[t];
   const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
+  const int32_t *hits = w.trk_hits + t * A.n_rows;
   for (int r = rlo; r <= rhi; ++r) {
-    const int h = w.trk_hits[int64_t(r) * w.K_cap + t];
+    const int h = hits[r];
     if (h >= 0 && w.owner[h] == key) {
       const int id = w.perm[h];
       O.hits[off++] = id;

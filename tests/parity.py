@@ -62,8 +62,8 @@ def gpu_state(tracker, result):
     g["trk_cov"] = tracker.inspect(T.TPC_VIEW_TRK_COV, torch.float32).cpu().numpy().reshape(-1, 15)[:K]
     g["trk_xref"] = tracker.inspect(T.TPC_VIEW_TRK_XREF, torch.float32).cpu().numpy()[:K]
     g["trk_chi2"] = tracker.inspect(T.TPC_VIEW_TRK_CHI2, torch.float32).cpu().numpy()[:K]
-    hits = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(n_rows, -1)[:, :K]
-    g["trk_hitrows"] = hits
+    hits = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(-1, n_rows)[:K]
+    g["trk_hitrows"] = hits.T  # [row][tracklet]
     for k in ("n_tracks", "n_track_hits", "n_tracklets", "n_cells"):
         g[k] = result[k]
     for k in ("cluster_track", "params", "cov", "x_ref", "chi2", "unit", "n_hits", "n_fit",
