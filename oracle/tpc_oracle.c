@@ -757,7 +757,8 @@ static int valid_params(const orc_params_t *P) {
   return P->q_shift == 8 && P->tan_half_q16 > 0 && P->bin_y_q > 0 && P->bin_occ > 0 &&
          P->bin_zmin_q > 0 && P->win_y_q >= 0 && P->win_z_q >= 0 && P->w_y >= 0 && P->w_y <= 15 &&
          P->w_z >= 0 && P->w_z <= 15 && P->smax_k >= 0 && P->smax_k < ((int64_t)1 << 30) &&
-         P->l_min >= 3 && P->ext_win_y_q >= 0 && P->ext_win_z_q >= 0 &&
+         P->l_min >= 3 && P->ext_win_y_q >= 0 && P->ext_win_y_q < 8192 && P->ext_win_z_q >= 0 &&
+         P->ext_win_z_q < 8192 &&
          P->max_miss >= 0 && P->n_min >= 0 && P->f_min_q8 >= 0 && P->sinphi_max > 0 &&
          P->sinphi_max < 1 && P->sigma_y > 0 && P->sigma_z > 0;
 }

@@ -147,7 +147,7 @@ bool params_ok(const tpc_params_t *p) {
          p->win_y_q >= 0 && p->win_y_q < (1 << 16) && p->win_z_q >= 0 && p->win_z_q < (1 << 16) &&
          p->w_y >= 0 && p->w_y <= 15 && p->w_z >= 0 && p->w_z <= 15 && p->smax_k >= 0 &&
          p->smax_k < (int64_t(1) << 30) && p->l_min >= 3 && p->ext_win_y_q >= 0 &&
-         p->ext_win_y_q < (1 << 16) && p->ext_win_z_q >= 0 && p->ext_win_z_q < (1 << 16) &&
+         p->ext_win_y_q < (1 << 13) && p->ext_win_z_q >= 0 && p->ext_win_z_q < (1 << 13) &&
          p->ext_edge_q >= 0 && p->ext_edge_q < (1 << 20) && p->max_miss >= 0 && p->n_min >= 0 &&
          p->f_min_q8 >= 0 && p->f_min_q8 <= 256 * 256 && p->tracklet_cap_div >= 2 &&
          p->sinphi_max > 0.f && p->sinphi_max < 1.f && p->sigma_y > 0.f && p->sigma_z > 0.f &&
@@ -957,23 +957,39 @@ __device__ __forceinline__ float asin_over_dd(float u) {  // (d/du asin(u)/u) / 
   return (u / sqrtf(1.f - u2) - asinf(u)) / (u2 * u);
 }
 
-__device__ bool propagate(KState &s, float x2, float k, float sinmax) {
-  const float dx = x2 - s.x;
-  const float C = k * s.p[4];
-  const float s1 = s.p[2], s2 = s1 + C * dx;
-  if (!(fabsf(s1) < sinmax) || !(fabsf(s2) < sinmax)) return false;
-  const float c1 = sqrtf(1.f - s1 * s1), c2 = sqrtf(1.f - s2 * s2);
-  const float D = c1 + c2, N = s1 + s2;
-  const float iD = 1.f / D;
-  const float dy = dx * N * iD;
-  const float L = sqrtf(dx * dx + dy * dy);
-  const float u = fabsf(C) * L * 0.5f;
-  if (!(u < 1.f)) return false;
-  const float sg = dx < 0.f ? -1.f : 1.f;
-  const float fu = asin_over(u);
-  const float sT = sg * L * fu;
+// Transport of the state to a plane x2, parameter part; kept so that the
+// covariance part can follow once a hit is found in that row.
+struct Step {
+  float dx, C, s1, s2, c1, c2, D, N, iD, dy, L, u, fu, sT, sg;
+};
+
+__device__ __forceinline__ bool step_prepare(const KState &s, float x2, float k, float sinmax, Step &t) {
+  t.dx = x2 - s.x;
+  t.C = k * s.p[4];
+  t.s1 = s.p[2];
+  t.s2 = t.s1 + t.C * t.dx;
+  if (!(fabsf(t.s1) < sinmax) || !(fabsf(t.s2) < sinmax)) return false;
+  t.c1 = sqrtf(1.f - t.s1 * t.s1);
+  t.c2 = sqrtf(1.f - t.s2 * t.s2);
+  t.D = t.c1 + t.c2;
+  t.N = t.s1 + t.s2;
+  t.iD = 1.f / t.D;
+  t.dy = t.dx * t.N * t.iD;
+  t.L = sqrtf(t.dx * t.dx + t.dy * t.dy);
+  t.u = fabsf(t.C) * t.L * 0.5f;
+  if (!(t.u < 1.f)) return false;
+  t.sg = t.dx < 0.f ? -1.f : 1.f;
+  t.fu = asin_over(t.u);
+  t.sT = t.sg * t.L * t.fu;
+  return true;
+}
+
+// Apply a prepared step: parameters, and the covariance through the analytic
+// Jacobian.
+__device__ __forceinline__ void step_apply(KState &s, const Step &t, float x2, float k) {
+  const float dx = t.dx, s1 = t.s1, s2 = t.s2, c1 = t.c1, c2 = t.c2, D = t.D, N = t.N, iD = t.iD;
+  const float dy = t.dy, L = t.L, u = t.u, fu = t.fu, sT = t.sT, sg = t.sg, C = t.C;
   const float tgl = s.p[3];
-  // Jacobian entries
   const float iD2 = iD * iD;
   const float a = dx * (2.f * D + N * (s1 / c1 + s2 / c2)) * iD2;
   const float b = dx * k * dx * (D + N * s2 / c2) * iD2;
@@ -1010,11 +1026,15 @@ __device__ bool propagate(KState &s, float x2, float k, float sinmax) {
   c[6] = P30 + a * P32 + b * P43;
   c[7] = P31 + cc * P32 + d * P33 + e * P43;
   c[8] = P32 + f * P43;
-  // c[9] = P33 unchanged
   c[10] = P40 + a * P42 + b * P44;
   c[11] = P41 + cc * P42 + d * P43 + e * P44;
   c[12] = P42 + f * P44;
-  // c[13], c[14] unchanged
+}
+
+__device__ __forceinline__ bool propagate(KState &s, float x2, float k, float sinmax) {
+  Step t;
+  if (!step_prepare(s, x2, k, sinmax, t)) return false;
+  step_apply(s, t, x2, k);
   return true;
 }
 
@@ -1073,7 +1093,8 @@ __device__ int pick(const Args &A, const int32_t *rec, float yp, float zp, int Y
   const int WY = A.p.ext_win_y_q, WZ = A.p.ext_win_z_q;
   const Win c = window_cells(rec, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);
   if (c.empty) return -1;
-  int64_t best_s = INT64_MAX;
+  // windows < 2^13 and weights <= 15 keep the score below 2^31
+  int best_s = INT32_MAX;
   int best = -1;
   for (int iz = c.iz0; iz <= c.iz1; ++iz) {
     const int cb = c.cbase + iz * c.ny;
@@ -1082,7 +1103,7 @@ __device__ int pick(const Args &A, const int32_t *rec, float yp, float zp, int Y
       const int2 h = w.syz[q];
       const int dY = h.x - Yp, dZ = h.y - Zp;
       if (abs(dY) > WY || abs(dZ) > WZ) continue;
-      const int64_t sc = int64_t(A.p.w_y) * dY * dY + int64_t(A.p.w_z) * dZ * dZ;
+      const int sc = A.p.w_y * dY * dY + A.p.w_z * dZ * dZ;
       if (sc < best_s || (sc == best_s && w.perm[q] < w.perm[best])) {
         best_s = sc;
         best = q;
@@ -1107,28 +1128,6 @@ __device__ __forceinline__ void upd_hit(const Args &A, KState &s, int h, int Yr,
                                         float sz2) {
   const int2 yz = A.w.syz[h];
   kf_update(s, float(yz.x - Yr) * (1.f / 256.f), float(yz.y - Zr) * (1.f / 256.f), sy2, sz2);
-}
-
-// Parameter-only transport to x2 (the prediction of a row); the same
-// operations as propagate(), so a later propagate() to x2 reproduces it.
-__device__ __forceinline__ bool predict(const KState &s, float x2, float k, float sinmax, float &yp,
-                                        float &zp) {
-  const float dx = x2 - s.x;
-  const float C = k * s.p[4];
-  const float s1 = s.p[2], s2 = s1 + C * dx;
-  if (!(fabsf(s1) < sinmax) || !(fabsf(s2) < sinmax)) return false;
-  const float c1 = sqrtf(1.f - s1 * s1), c2 = sqrtf(1.f - s2 * s2);
-  const float D = c1 + c2, N = s1 + s2;
-  const float iD = 1.f / D;
-  const float dy = dx * N * iD;
-  const float L = sqrtf(dx * dx + dy * dy);
-  const float u = fabsf(C) * L * 0.5f;
-  if (!(u < 1.f)) return false;
-  const float sg = dx < 0.f ? -1.f : 1.f;
-  const float sT = sg * L * asin_over(u);
-  yp = s.p[0] + dy;
-  zp = s.p[1] + s.p[3] * sT;
-  return true;
 }
 
 // step 5a: chains.  Per tracklet: the row of its start hit and the chain along
@@ -1200,7 +1199,9 @@ __global__ void __launch_bounds__(TPB) k_compact_seeds(Args A) {
 // one committed state (at its last update); each row is predicted by a
 // parameter-only transport from it, and the covariance is transported only
 // when a hit is picked (helix transports compose exactly).
-__global__ void __launch_bounds__(CTB) k_fit(Args A) {
+// 6 waves per SIMD: the walk is bound by dependent gathers, and the extra
+// waves hide more of their latency than the few spilled registers cost
+__global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))) k_fit(Args A) {
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int64_t i = int64_t(blockIdx.x) * CTB + threadIdx.x;
@@ -1247,36 +1248,31 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
     cov_reset(s, P.cov0);
   }
   if (ok) {
-    // pass 1: the chain
+    // pass 1: the chain rows, then extension rows, in one walk up the rows;
+    // one propagate/update site serves both kinds of row
     int r_out = r1;
-    bool chain_ok = true;
+    int misses = 0;
     upd_hit(A, s, ha, Yr, Zr, sy2, sz2);
-    for (int j = 1; j < L; ++j) {
-      if (!propagate(s, A.row_x[r1 + j], k, smx)) {
-        chain_ok = false;
-        break;
-      }
-      upd_hit(A, s, hits[r1 + j], Yr, Zr, sy2, sz2);
-      r_out = r1 + j;
-    }
-    // pass 1: extension to the outer rows
-    if (chain_ok) {
-      int misses = 0;
-      for (int r = r1 + L; r < nr; ++r) {
-        float yp, zp;
-        if (!predict(s, A.row_x[r], k, smx, yp, zp)) break;
+    for (int r = r1 + 1; r < nr; ++r) {
+      Step st;
+      const float xr = A.row_x[r];
+      if (!step_prepare(s, xr, k, smx, st)) break;
+      int h;
+      if (r < r1 + L) {
+        h = hits[r];
+      } else {
         bool stop = false;
-        const int f = pick(A, segu + r * SEGW, yp, zp, Yr, Zr, stop);
+        h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
         if (stop) break;
-        hits[r] = f;
-        if (f >= 0) {
-          propagate(s, A.row_x[r], k, smx);
-          upd_hit(A, s, f, Yr, Zr, sy2, sz2);
-          r_out = r;
-          misses = 0;
-        } else if (++misses > P.max_miss) {
-          break;
-        }
+        hits[r] = h;
+      }
+      if (h >= 0) {
+        step_apply(s, st, xr, k);
+        upd_hit(A, s, h, Yr, Zr, sy2, sz2);
+        r_out = r;
+        misses = 0;
+      } else if (++misses > P.max_miss) {
+        break;
       }
     }
     // pass 2: from the outermost hit down to row 0, covariance reset
@@ -1286,33 +1282,28 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
     nfit = 1;
     rhi = r_out;
     rlo = r_out;
-    int misses = 0;
+    misses = 0;
     for (int r = r_out - 1; r >= 0; --r) {
-      if (r >= r1) {
-        const int h = hits[r];
-        if (h >= 0) {
-          if (!propagate(s, A.row_x[r], k, smx)) break;
-          upd_hit(A, s, h, Yr, Zr, sy2, sz2);
-          ++nfit;
+      Step st;
+      const float xr = A.row_x[r];
+      if (!step_prepare(s, xr, k, smx, st)) break;
+      int h = r >= r1 ? hits[r] : -1;  // pass-1 hit of this row, if any
+      if (h < 0) {
+        bool stop = false;
+        h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
+        if (stop) break;
+        hits[r] = h;
+        if (h < 0) {
           rlo = r;
+          if (r < r1 && ++misses > P.max_miss) break;
           continue;
         }
-      }
-      float yp, zp;
-      if (!predict(s, A.row_x[r], k, smx, yp, zp)) break;
-      bool stop = false;
-      const int f = pick(A, segu + r * SEGW, yp, zp, Yr, Zr, stop);
-      if (stop) break;
-      hits[r] = f;
-      rlo = r;
-      if (f >= 0) {
-        propagate(s, A.row_x[r], k, smx);
-        upd_hit(A, s, f, Yr, Zr, sy2, sz2);
-        ++nfit;
         misses = 0;
-      } else if (r < r1 && ++misses > P.max_miss) {
-        break;
       }
+      step_apply(s, st, xr, k);
+      upd_hit(A, s, h, Yr, Zr, sy2, sz2);
+      ++nfit;
+      rlo = r;
     }
   }
   uint32_t key = 0;
@@ -1340,11 +1331,13 @@ __global__ void __launch_bounds__(CTB) k_fit(Args A) {
   w.trk_x[t] = s.x;
   w.trk_chi2[t] = s.chi2;
   // ownership: every hit goes to the tracklet with the largest key
-  if (nfit > 0)
+  if (nfit > 0) {
+#pragma unroll 8
     for (int r = rlo; r <= rhi; ++r) {
       const int h = hits[r];
       if (h >= 0) atomicMax(&w.owner[h], key);
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1367,6 +1360,7 @@ __global__ void __launch_bounds__(TPB) k_select(Args A) {
       const uint32_t key = w.trk_key[t];
       const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
       const int32_t *hits = w.trk_hits + t * A.n_rows;
+#pragma unroll 8
       for (int r = rlo; r <= rhi; ++r) {
         const int h = hits[r];
         if (h >= 0 && w.owner[h] == key) ++owned;
@@ -1414,6 +1408,7 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   const uint32_t key = w.trk_key[t];
   const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
   const int32_t *hits = w.trk_hits + t * A.n_rows;
+#pragma unroll 4
   for (int r = rlo; r <= rhi; ++r) {
     const int h = hits[r];
     if (h >= 0 && w.owner[h] == key) {
