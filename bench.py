@@ -88,6 +88,87 @@ def measured_traffic(kernel, workload):
     return e.get("bytes_per_launch")
 
 
+def _short(name):
+    n = name.replace("(anonymous namespace)::", "")
+    if "neg_kernel" in n:
+        return "copy_calib"
+    return n.split("(")[0].strip()
+
+
+def _csv(pattern_dir, suffix):
+    import csv
+    import glob
+    paths = sorted(glob.glob(os.path.join(pattern_dir, "**", "*" + suffix), recursive=True))
+    if not paths:
+        raise SystemExit("no *%s under %s" % (suffix, pattern_dir))
+    with open(paths[0], newline="") as f:
+        return [{k.lower(): v for k, v in r.items()} for r in csv.DictReader(f)]
+
+
+def _counter_means(d, counter):
+    """Mean per dispatch of one counter (summed over its dimensions), by kernel name."""
+    per, names = {}, {}
+    for r in _csv(d, "counter_collection.csv"):
+        if r["counter_name"] != counter:
+            continue
+        key = r["dispatch_id"]
+        per[key] = per.get(key, 0.0) + float(r["counter_value"])
+        names[key] = _short(r["kernel_name"])
+    acc = {}
+    for key, v in per.items():
+        acc.setdefault(names[key], []).append(v)
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def summarize_profiles(prof_dir, workload):
+    """Turn rocprofv3 runs of this script into the committed summaries.
+
+    prof_dir holds trace/ (--kernel-trace --stats), fetch/ (--pmc FETCH_SIZE)
+    and write/ (--pmc WRITE_SIZE), each from a run with --calib-copy and
+    --output-format csv, a cmd.txt with the command line and bench.json with
+    the run's output line.  FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are
+    scaled by what they read for the 1 GiB-in / 1 GiB-out copy kernel.
+    Writes profiles/<workload>_kernels.txt and profiles/traffic.json."""
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    stats = {_short(r["name"]): r for r in _csv(os.path.join(prof_dir, "trace"), "kernel_stats.csv")}
+    fetch = _counter_means(os.path.join(prof_dir, "fetch"), "FETCH_SIZE")
+    write = _counter_means(os.path.join(prof_dir, "write"), "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    f_fac = fetch["copy_calib"] / gib_kib
+    w_fac = write["copy_calib"] / gib_kib
+    run = json.loads(open(os.path.join(prof_dir, "trace", "bench.json")).read().strip().splitlines()[-1])
+    n = run["config"]["clusters"]
+    digest = src_digest()
+    lines = ["rocprofv3 summary: %s (%d clusters per launch), kernel source digest %s" % (workload, n, digest), ""]
+    for sub in ("trace", "fetch", "write"):
+        lines.append("%-5s: %s" % (sub, open(os.path.join(prof_dir, sub, "cmd.txt")).read().strip()))
+    lines.append("summary: python bench.py --summarize-profiles <dir of the three runs> --workload %s" % workload)
+    lines += ["", "copy kernel (1 GiB read, 1 GiB written): FETCH_SIZE %.6g KiB -> scale %.4f, "
+              "WRITE_SIZE %.6g KiB -> scale %.4f" % (fetch["copy_calib"], f_fac, write["copy_calib"], w_fac), "",
+              "%-18s %6s %10s %10s %10s %8s %8s %8s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB",
+                                                       "B/clus", "GB/s", "alg_B/c")]
+    traffic = {}
+    for k, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["totaldurationns"])):
+        if k not in KERNEL_FAMILY:
+            continue
+        avg_us = float(r["averagens"]) / 1e3
+        fb = fetch.get(k, 0.0) * 1024 / f_fac
+        wb = write.get(k, 0.0) * 1024 / w_fac
+        alg = B_ALG.get(KERNEL_FAMILY[k], 0) if KERNEL_FAMILY[k] else 0
+        lines.append("%-18s %6s %10.1f %10.1f %10.1f %8.2f %8.0f %8s" % (
+            k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / n, (fb + wb) / 1e3 / avg_us, alg or "-"))
+        traffic[k] = dict(src_digest=digest, bytes_per_launch=fb + wb, fetch_bytes=fb, write_bytes=wb,
+                          avg_us=avg_us)
+    txt = os.path.join(out_dir, "%s_kernels.txt" % workload)
+    open(txt, "w").write("\n".join(lines) + "\n")
+    tj = os.path.join(out_dir, "traffic.json")
+    d = json.load(open(tj)) if os.path.exists(tj) else {}
+    d[workload] = traffic
+    json.dump(d, open(tj, "w"), indent=1, sort_keys=True)
+    print("\n".join(lines))
+
+
 def cpu_baseline(ev, n_units_sample, values):
     """The CPU oracle, as it stands, on the first n_units_sample units."""
     import oracle
@@ -109,11 +190,17 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pbpb_timeframe_50")
-    ap.add_argument("--cpu-units", type=int, default=4, help="units in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--cpu-units", type=int, default=-1,
+                    help="units in the CPU-oracle sample (-1: all, 0: skip)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 runs of this script and exit")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.workload)
+        return
     if args.gpus != 1:
         print("bench.py measures one MI355X; --gpus %d is not supported (units are independent, "
               "see the sharding note in DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -228,10 +315,11 @@ def main():
                                        calls_per_step=len(subs))
         del trp
 
-    if args.cpu_units > 0:
+    if args.cpu_units != 0:
         from paper_2106_03636_amd.params import DEFAULT_PARAMS
-        log("bench: timing the CPU oracle on %d units" % args.cpu_units)
-        out["cpu_baseline"] = cpu_baseline(ev, args.cpu_units, DEFAULT_PARAMS)
+        nu = ev.n_units if args.cpu_units < 0 else min(args.cpu_units, ev.n_units)
+        log("bench: timing the CPU oracle on %d units" % nu)
+        out["cpu_baseline"] = cpu_baseline(ev, nu, DEFAULT_PARAMS)
     print(json.dumps(out), flush=True)
 
 
