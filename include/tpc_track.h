@@ -177,14 +177,18 @@ const char *tpc_status_string(int status);
  *   TPC_VIEW_TRK_*     per tracklet (capacity entries, the first counts[2] valid):
  *     START int32, UNIT int32, LEN int32, NFIT int32, RLO int32, RHI int32,
  *     KEY uint32, OWNED int32, KEEP int32, PARAMS float[5], COV float[15],
- *     XREF float, CHI2 float,
- *     HITS int32 [capacity][n_rows] hit of each row (-1 none), rows RLO..RHI. */
+ *     XREF float, CHI2 float.
+ *   TPC_VIEW_SEED_LIST int32 [capacity] the seeds (tracklets with LEN >= l_min)
+ *                      in tracklet order; the first (number of seeds) valid.
+ *   TPC_VIEW_TRK_HITS  int32 [ceil(capacity/64)][n_rows][64] hit of each row
+ *                      (-1 none) of seed i at [i/64][row][i%64], rows RLO..RHI
+ *                      of its tracklet valid. */
 enum {
   TPC_VIEW_PERM = 1, TPC_VIEW_CELL, TPC_VIEW_SEG, TPC_VIEW_UP, TPC_VIEW_DN, TPC_VIEW_UPC,
   TPC_VIEW_DNC, TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN,
   TPC_VIEW_TRK_NFIT, TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI, TPC_VIEW_TRK_KEY,
   TPC_VIEW_TRK_OWNED, TPC_VIEW_TRK_KEEP, TPC_VIEW_TRK_PARAMS, TPC_VIEW_TRK_COV,
-  TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2, TPC_VIEW_TRK_HITS
+  TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2, TPC_VIEW_TRK_HITS, TPC_VIEW_SEED_LIST
 };
 
 typedef struct tpc_view {
@@ -247,9 +251,11 @@ typedef struct tpc_request {
   const uint16_t *row;
 } tpc_request_t;
 
-/* Results of one request, in server-owned host memory valid until
+/* Results of one request, in server-owned host memory (pinned) valid until
  * tpc_server_release(ticket).  Cluster ids and track indices are local to the
- * request (as if it had been tracked alone). */
+ * request (as if it had been tracked alone); for a request that shared its
+ * batch they are made local by its first poll, on the polling thread.  Do not
+ * release a ticket while another thread polls it. */
 typedef struct tpc_result {
   int32_t status;              /* TPC_OK or the request's error */
   int32_t reserved;
@@ -279,9 +285,12 @@ int tpc_server_create(const tpc_server_config_t *config, tpc_server_t **server);
 /* Queue a request.  Returns TPC_OK and a ticket; TPC_E_BUSY when queue_depth
  * requests are already waiting (back pressure: retry later); TPC_E_NOMEM when
  * the request could never fit the arena; TPC_E_INVALID when its data are
- * malformed (checked on the host for host arrays, so one bad request never
- * fails a batch; device arrays are not checked, and a malformed one fails
- * every request of its batch with TPC_E_INVALID). */
+ * malformed (host arrays are checked here; device arrays are checked by the
+ * kernels).  A batch of several requests that fails on the device (invalid
+ * data, capacity) is run again one request per batch, so a bad request fails
+ * alone and the others still get the results they would get alone.  With
+ * TPC_REQ_DEVICE the caller makes the arrays ready before submitting (the
+ * server's streams do not wait on the caller's). */
 int tpc_server_submit(tpc_server_t *server, const tpc_request_t *request, uint64_t *ticket);
 
 /* Results of a ticket.  wait_us = 0: do not wait (TPC_E_BUSY if not done yet);

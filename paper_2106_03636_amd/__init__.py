@@ -22,7 +22,7 @@ TPC_OK, TPC_E_INVALID, TPC_E_CAPACITY, TPC_E_NOMEM, TPC_E_HIP, TPC_E_BUSY = 0, -
  TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN, TPC_VIEW_TRK_NFIT,
  TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI, TPC_VIEW_TRK_KEY, TPC_VIEW_TRK_OWNED, TPC_VIEW_TRK_KEEP,
  TPC_VIEW_TRK_PARAMS, TPC_VIEW_TRK_COV, TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2,
- TPC_VIEW_TRK_HITS) = range(1, 23)
+ TPC_VIEW_TRK_HITS, TPC_VIEW_SEED_LIST) = range(1, 24)
 
 _vp = ctypes.c_void_p
 

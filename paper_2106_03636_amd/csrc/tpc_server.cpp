@@ -135,6 +135,18 @@ class PinnedPool {
 
 // ---------------------------------------------------------------------------
 
+// Pinned result blocks of one batch; shared by its requests until the last
+// of them is released.
+struct BatchOut {
+  PinnedPool *pool = nullptr;
+  void *h_head = nullptr;  // counts[4] + status
+  void *h_out = nullptr;   // the batch's results, packed
+  ~BatchOut() {
+    pool->put(h_head);
+    pool->put(h_out);
+  }
+};
+
 struct Request {
   uint64_t ticket = 0;
   int64_t n = 0;
@@ -150,10 +162,19 @@ struct Request {
   int64_t batch_id = -1;
   int32_t batch_requests = 0;
   size_t footprint = 0;
-  // results
+  bool solo = false;  // runs in a batch of its own (after its batch failed)
+  // results: the request's slice of its batch's packed results.  Indices in
+  // them are batch-wide; when the batch held other requests they are made
+  // request-local on the first poll (on the caller's thread, under rmu).
+  std::shared_ptr<BatchOut> out;
   int64_t n_tracks = 0, n_track_hits = 0;
-  std::vector<int32_t> cluster_track, unit, n_hits, n_fit, first_hit, hits;
-  std::vector<float> params, cov, x_ref, chi2;
+  int64_t cb = 0, ub = 0, t0 = 0, h0 = 0;  // cluster, unit, track and hit bases in the batch
+  const int32_t *b_ct = nullptr, *b_unit = nullptr, *b_nhits = nullptr, *b_nfit = nullptr,
+                *b_first = nullptr, *b_hits = nullptr;
+  const float *b_params = nullptr, *b_cov = nullptr, *b_xref = nullptr, *b_chi2 = nullptr;
+  std::mutex rmu;
+  bool local = false;  // the request-local index arrays below are filled
+  std::vector<int32_t> cluster_track, unit, first_hit, hits;
 };
 
 struct OutLayout {  // device outputs of a batch, offsets inside its arena block
@@ -207,10 +228,9 @@ struct Batch {
   size_t arena_off = 0;
   OutLayout L{};
   int slot = -1;
-  int phase = 0;            // 0: kernels queued, 1: result copies queued
+  int phase = 0;              // 0: kernels queued, 1: result copies queued
   void *h_offsets = nullptr;  // pinned [n_units + 1]
-  void *h_head = nullptr;     // pinned counts[4] + status
-  void *h_out = nullptr;      // pinned results
+  std::shared_ptr<BatchOut> out;
   size_t out_bytes = 0;
 };
 
@@ -245,6 +265,7 @@ struct tpc_server {
   void launch(Batch *b);   // without mu
   bool progress_slot(Slot &s);
   void finish(Batch *b);
+  void requeue_solo(Batch *b);
 };
 
 namespace {
@@ -283,6 +304,7 @@ bool tpc_server::form_and_launch() {
   size_t take = 0;
   for (size_t i = 0; i < pending.size(); ++i) {
     Request *r = pending[i];
+    if (i > 0 && (r->solo || pending[0]->solo)) break;
     if (cfg.max_batch_requests > 0 && int32_t(i) >= cfg.max_batch_requests) break;
     if (i > 0 && cfg.max_batch_clusters > 0 && n + r->n > cfg.max_batch_clusters) break;
     OutLayout L2{};
@@ -378,8 +400,10 @@ void tpc_server::launch(Batch *b) {
   o.counts = reinterpret_cast<int64_t *>(base + L.off_counts);
   o.status = reinterpret_cast<int32_t *>(base + L.off_status);
   const int rc = tpc_track_sectors(&c, &g, &f, &cfg.params, &o, base + L.off_ws, L.ws_bytes, s.stream);
-  b->h_head = pinned.get(64);
-  int64_t *hh = static_cast<int64_t *>(b->h_head);
+  b->out = std::make_shared<BatchOut>();
+  b->out->pool = &pinned;
+  b->out->h_head = pinned.get(64);
+  int64_t *hh = static_cast<int64_t *>(b->out->h_head);
   hh[0] = hh[1] = hh[2] = hh[3] = 0;
   hh[4] = rc;  // launch status if the call failed on the host
   if (rc == TPC_OK) {
@@ -396,9 +420,13 @@ bool tpc_server::progress_slot(Slot &s) {
   if (!b) return false;
   if (b->phase == 0) {
     if (hipEventQuery(s.ev_kernel) != hipSuccess) return false;
-    const int64_t *hh = static_cast<const int64_t *>(b->h_head);
+    const int64_t *hh = static_cast<const int64_t *>(b->out->h_head);
     const int32_t status = int32_t(reinterpret_cast<const int32_t *>(hh + 4)[0]);
     if (status != TPC_OK) {
+      if (b->reqs.size() > 1 && (status == TPC_E_INVALID || status == TPC_E_CAPACITY)) {
+        requeue_solo(b);  // find which request it was: each runs again alone
+        return true;
+      }
       for (Request *r : b->reqs) r->status = status;
       finish(b);
       return true;
@@ -407,8 +435,8 @@ bool tpc_server::progress_slot(Slot &s) {
     const OutLayout &L = b->L;
     const size_t N = size_t(b->n);
     b->out_bytes = 4 * N + 4 * size_t(T) * (5 + 15 + 1 + 1 + 4) + 4 * size_t(H) + 64;
-    b->h_out = pinned.get(b->out_bytes);
-    char *ho = static_cast<char *>(b->h_out);
+    b->out->h_out = pinned.get(b->out_bytes);
+    char *ho = static_cast<char *>(b->out->h_out);
     char *base = d_arena + b->arena_off;
     size_t o = 0;
     auto cp = [&](size_t dev_off, size_t bytes) {
@@ -425,16 +453,14 @@ bool tpc_server::progress_slot(Slot &s) {
     cp(L.off_nfit, 4 * size_t(T));
     cp(L.off_first, 4 * size_t(T));
     cp(L.off_hits, 4 * size_t(H));
-    hh = static_cast<const int64_t *>(b->h_head);
     (void)hipEventRecord(s.ev_copy, s.stream);
     b->phase = 1;
     return true;
   }
   if (hipEventQuery(s.ev_copy) != hipSuccess) return false;
-  // split the batch's results into its requests
-  const int64_t *hh = static_cast<const int64_t *>(b->h_head);
-  const int64_t T = hh[0];
-  const char *ho = static_cast<const char *>(b->h_out);
+  // each request's slice of the packed results (tracks are in unit order)
+  const int64_t T = static_cast<const int64_t *>(b->out->h_head)[0];
+  const char *ho = static_cast<const char *>(b->out->h_out);
   const size_t N = size_t(b->n);
   const int32_t *ct = reinterpret_cast<const int32_t *>(ho);
   const float *par = reinterpret_cast<const float *>(ho + 4 * N);
@@ -448,33 +474,24 @@ bool tpc_server::progress_slot(Slot &s) {
   const int32_t *hits = fh + T;
   for (size_t i = 0; i < b->reqs.size(); ++i) {
     Request *r = b->reqs[i];
-    const int64_t ub = b->unit_base[i], cb = b->cluster_base[i];
-    const int64_t t0 = std::lower_bound(un, un + T, int32_t(ub)) - un;
-    const int64_t t1 = std::lower_bound(un, un + T, int32_t(ub + r->n_units)) - un;
-    const int64_t nt = t1 - t0;
-    r->n_tracks = nt;
-    const int64_t h0 = nt ? fh[t0] : 0;
-    const int64_t h1 = nt ? fh[t1 - 1] + nh[t1 - 1] : 0;
-    r->n_track_hits = h1 - h0;
-    r->cluster_track.resize(size_t(r->n));
-    for (int64_t k = 0; k < r->n; ++k) {
-      const int32_t v = ct[cb + k];
-      r->cluster_track[size_t(k)] = v >= 0 ? int32_t(v - t0) : -1;
-    }
-    r->params.assign(par + 5 * t0, par + 5 * t1);
-    r->cov.assign(cov + 15 * t0, cov + 15 * t1);
-    r->x_ref.assign(xr + t0, xr + t1);
-    r->chi2.assign(c2 + t0, c2 + t1);
-    r->unit.resize(size_t(nt));
-    r->n_hits.assign(nh + t0, nh + t1);
-    r->n_fit.assign(nf + t0, nf + t1);
-    r->first_hit.resize(size_t(nt));
-    for (int64_t k = 0; k < nt; ++k) {
-      r->unit[size_t(k)] = int32_t(un[t0 + k] - ub);
-      r->first_hit[size_t(k)] = int32_t(fh[t0 + k] - h0);
-    }
-    r->hits.resize(size_t(r->n_track_hits));
-    for (int64_t k = 0; k < r->n_track_hits; ++k) r->hits[size_t(k)] = int32_t(hits[h0 + k] - cb);
+    r->cb = b->cluster_base[i];
+    r->ub = b->unit_base[i];
+    r->t0 = std::lower_bound(un, un + T, int32_t(r->ub)) - un;
+    const int64_t t1 = std::lower_bound(un, un + T, int32_t(r->ub + r->n_units)) - un;
+    r->n_tracks = t1 - r->t0;
+    r->h0 = r->n_tracks ? fh[r->t0] : 0;
+    r->n_track_hits = r->n_tracks ? fh[t1 - 1] + nh[t1 - 1] - r->h0 : 0;
+    r->b_ct = ct + r->cb;
+    r->b_params = par + 5 * r->t0;
+    r->b_cov = cov + 15 * r->t0;
+    r->b_xref = xr + r->t0;
+    r->b_chi2 = c2 + r->t0;
+    r->b_unit = un + r->t0;
+    r->b_nhits = nh + r->t0;
+    r->b_nfit = nf + r->t0;
+    r->b_first = fh + r->t0;
+    r->b_hits = hits + r->h0;
+    r->out = b->out;
     r->status = TPC_OK;
   }
   finish(b);
@@ -484,8 +501,7 @@ bool tpc_server::progress_slot(Slot &s) {
 void tpc_server::finish(Batch *b) {
   const double t = now_s();
   pinned.put(b->h_offsets);
-  pinned.put(b->h_head);
-  pinned.put(b->h_out);
+  b->out.reset();
   std::lock_guard<std::mutex> g(mu);
   for (Request *r : b->reqs) {
     pinned.put(r->staging);
@@ -498,6 +514,22 @@ void tpc_server::finish(Batch *b) {
   slots[b->slot].batch = nullptr;
   delete b;
   cv_done.notify_all();
+}
+
+void tpc_server::requeue_solo(Batch *b) {
+  pinned.put(b->h_offsets);
+  b->out.reset();
+  std::lock_guard<std::mutex> g(mu);
+  for (auto it = b->reqs.rbegin(); it != b->reqs.rend(); ++it) {
+    Request *r = *it;
+    r->solo = true;
+    r->state = Request::PENDING;
+    r->batch_id = -1;
+    pending.push_front(r);
+  }
+  arena.release(b->arena_off, b->L.total);
+  slots[b->slot].batch = nullptr;
+  delete b;
 }
 
 void tpc_server::loop() {
@@ -611,36 +643,67 @@ extern "C" int tpc_server_submit(tpc_server_t *s, const tpc_request_t *r, uint64
 
 extern "C" int tpc_server_poll(tpc_server_t *s, uint64_t ticket, tpc_result_t *res, int64_t wait_us) {
   if (!s || !res) return TPC_E_INVALID;
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return TPC_E_INVALID;
-  Request *r = it->second.get();
-  if (r->state != Request::DONE) {
-    if (wait_us == 0) return TPC_E_BUSY;
-    auto done = [r] { return r->state == Request::DONE; };
-    if (wait_us < 0) s->cv_done.wait(lk, done);
-    else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), done)) return TPC_E_BUSY;
+  Request *r = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return TPC_E_INVALID;
+    r = it->second.get();
+    if (r->state != Request::DONE) {
+      if (wait_us == 0) return TPC_E_BUSY;
+      auto done = [r] { return r->state == Request::DONE; };
+      if (wait_us < 0) s->cv_done.wait(lk, done);
+      else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), done)) return TPC_E_BUSY;
+    }
   }
+  // a done request is only erased by tpc_server_release, which the caller
+  // does not run concurrently with a poll of the same ticket
   memset(res, 0, sizeof(*res));
   res->status = r->status;
   res->n = r->n;
-  res->n_tracks = r->n_tracks;
-  res->n_track_hits = r->n_track_hits;
-  res->cluster_track = r->cluster_track.data();
-  res->params = r->params.data();
-  res->cov = r->cov.data();
-  res->x_ref = r->x_ref.data();
-  res->chi2 = r->chi2.data();
-  res->unit = r->unit.data();
-  res->n_hits = r->n_hits.data();
-  res->n_fit = r->n_fit.data();
-  res->first_hit = r->first_hit.data();
-  res->hits = r->hits.data();
   res->t_submit = r->t_submit;
   res->t_admit = r->t_admit;
   res->t_done = r->t_done;
   res->batch_id = r->batch_id;
   res->batch_requests = r->batch_requests;
+  if (r->status != TPC_OK) return TPC_OK;
+  res->n_tracks = r->n_tracks;
+  res->n_track_hits = r->n_track_hits;
+  res->params = r->b_params;
+  res->cov = r->b_cov;
+  res->x_ref = r->b_xref;
+  res->chi2 = r->b_chi2;
+  res->n_hits = r->b_nhits;
+  res->n_fit = r->b_nfit;
+  if (r->batch_requests == 1) {  // alone in its batch: the indices are already its own
+    res->cluster_track = r->b_ct;
+    res->unit = r->b_unit;
+    res->first_hit = r->b_first;
+    res->hits = r->b_hits;
+    return TPC_OK;
+  }
+  std::lock_guard<std::mutex> g(r->rmu);
+  if (!r->local) {  // make the batch-wide indices request-local, once
+    const int64_t n = r->n, T = r->n_tracks, H = r->n_track_hits;
+    r->cluster_track.resize(size_t(n));
+    for (int64_t k = 0; k < n; ++k) {
+      const int32_t v = r->b_ct[k];
+      r->cluster_track[size_t(k)] = v >= 0 ? int32_t(v - r->t0) : -1;
+    }
+    r->unit.resize(size_t(T));
+    r->first_hit.resize(size_t(T));
+    for (int64_t k = 0; k < T; ++k) {
+      r->unit[size_t(k)] = int32_t(r->b_unit[k] - r->ub);
+      r->first_hit[size_t(k)] = int32_t(r->b_first[k] - r->h0);
+    }
+    r->hits.resize(size_t(H));
+    for (int64_t k = 0; k < H; ++k) r->hits[size_t(k)] = int32_t(r->b_hits[k] - r->cb);
+    r->local = true;
+  }
+  res->cluster_track = r->cluster_track.data();
+  res->unit = r->unit.data();
+  res->first_hit = r->first_hit.data();
+  res->hits = r->hits.data();
   return TPC_OK;
 }
 

@@ -51,11 +51,11 @@ struct Workspace {
   int32_t *cell, *cursor;
   int32_t *blk, *blk_keep, *blk_own;
   int32_t *trk_start, *trk_unit, *trk_len, *trk_nfit, *trk_rlo, *trk_rhi, *trk_owned, *trk_keep;
-  int32_t *trk_r1, *seed_list;
+  int32_t *trk_r1, *trk_hm, *trk_hb, *seed_list;
   uint32_t *trk_key;
   float *trk_par, *trk_cov, *trk_x, *trk_chi2;
   int32_t *trk_hits;
-  int64_t N, S, T_max, C_max, K_cap, NB, KB;
+  int64_t N, S, T_max, C_max, K_cap, NB, KB, KW;
   size_t total;
 };
 
@@ -90,6 +90,7 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.K_cap = n / p->tracklet_cap_div + 64;
   L.NB = (n + ELEMS - 1) / ELEMS + 1;
   L.KB = (L.K_cap + TPB - 1) / TPB;
+  L.KW = (L.K_cap + 63) / 64;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -130,12 +131,14 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.trk_keep = (int32_t *)take(4 * K);
   L.trk_key = (uint32_t *)take(4 * K);
   L.trk_r1 = (int32_t *)take(4 * K);
+  L.trk_hm = (int32_t *)take(4 * K);
+  L.trk_hb = (int32_t *)take(4 * K);
   L.seed_list = (int32_t *)take(4 * K);
   L.trk_par = (float *)take(4 * 5 * K);
   L.trk_cov = (float *)take(4 * 15 * K);
   L.trk_x = (float *)take(4 * K);
   L.trk_chi2 = (float *)take(4 * K);
-  L.trk_hits = (int32_t *)take(4 * size_t(n_rows) * K);
+  L.trk_hits = (int32_t *)take(4 * size_t(n_rows) * 64 * size_t(L.KW));
   L.total = o;
   *w = L;
   return true;
@@ -223,6 +226,36 @@ __device__ __forceinline__ int unit_of_tile(const int32_t *ut, int n_units, int 
 
 // ---------------------------------------------------------------------------
 // step 1: clear what must start at zero, validate geometry and offsets
+
+// Blocks are dealt to the 8 XCDs in turn.  Renumber the first n_work
+// (rounded up to 8) blocks so that each XCD runs one contiguous range of work
+// chunks: neighbouring chunks read the same rows, which then stay in that
+// XCD's L2.  Blocks past them keep their number.  A bijection on [0, grid)
+// when the grid is a multiple of 8.
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t n_work) {
+  const int64_t n8 = (n_work + 7) & ~int64_t(7);
+  if (b >= n8) return b;
+  return (b & 7) * (n8 >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Hit table of the seeds: [seed / 64][row][seed % 64], so the 64 lanes of a
+// wave (64 consecutive seeds) at one row touch one contiguous 256-byte run.
+// Returns the column of seed i; its row r is at col[r * 64].
+__device__ __forceinline__ int32_t *seed_column(const Workspace &w, int64_t i, int nr) {
+  return w.trk_hits + ((i >> 6) * nr) * 64 + (i & 63);
+}
 
 __global__ void k_init(Args A) {
   const Workspace &w = A.w;
@@ -786,8 +819,9 @@ __global__ void __launch_bounds__(NCH) k_neighbours(Args A) {
   __shared__ int zr[2];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int b = blockIdx.x;
-  if (b >= w.ctr[C_NCHUNK]) return;
+  const int64_t n_chunks = w.ctr[C_NCHUNK];
+  const int b = int(xcd_chunk(blockIdx.x, n_chunks));
+  if (b >= n_chunks) return;
   // segment of this chunk: last s with chunk base <= b and a non-empty row
   int lo = 0, hi = int(w.S) - 1;
   while (lo < hi) {
@@ -1130,10 +1164,11 @@ __device__ __forceinline__ void upd_hit(const Args &A, KState &s, int h, int Yr,
   kf_update(s, float(yz.x - Yr) * (1.f / 256.f), float(yz.y - Zr) * (1.f / 256.f), sy2, sz2);
 }
 
-// step 5a: chains.  Per tracklet: the row of its start hit and the chain along
-// the cleaned upward links (a cellular automaton over pad rows), stored by row
-// in the hit table; chains of >= l_min hits become seeds.  Other tracklets are
-// finalised here (no fit, no hits).
+// step 5a: chains.  Per tracklet: the row of its start hit and the length of
+// the chain along the cleaned upward links (a cellular automaton over pad
+// rows); chains of >= l_min hits become seeds, and their middle and last hits
+// are kept for the seed fit.  Other tracklets are finalised here (no fit, no
+// hits).
 __global__ void __launch_bounds__(TPB) k_chains(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
@@ -1150,11 +1185,16 @@ __global__ void __launch_bounds__(TPB) k_chains(Args A) {
       if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
     }
     const int r1 = lo;
-    int32_t *hits = w.trk_hits + t * nr;  // tracklet-major: row r at hits[r]
-    int L = 0;
+    int L = 0, hb = h0;
     for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
-      hits[r1 + L] = h;
+      hb = h;
       ++L;
+    }
+    if (L >= A.p.l_min) {
+      int hm = h0;
+      for (int j = 0; j < L / 2; ++j) hm = w.upc[hm];
+      w.trk_hm[t] = hm;
+      w.trk_hb[t] = hb;
     }
     w.trk_len[t] = L;
     w.trk_r1[t] = r1;
@@ -1193,37 +1233,47 @@ __global__ void __launch_bounds__(TPB) k_compact_seeds(Args A) {
 
 // step 5c: Kalman fit of every seed, one seed per lane.
 // Seed: circle through the first, middle and last chain hits.  Pass 1 fits
-// the chain inner to outer and extends it to the last row; pass 2 restarts
-// from the outermost hit with the covariance reset and walks down to row 0,
-// reusing pass-1 hits and picking hits in the other rows.  The filter keeps
-// one committed state (at its last update); each row is predicted by a
-// parameter-only transport from it, and the covariance is transported only
-// when a hit is picked (helix transports compose exactly).
+// the chain inner to outer (following the cleaned links) and extends it to
+// the last row; pass 2 restarts from the outermost hit with the covariance
+// reset and walks down to row 0, reusing pass-1 hits and picking hits in the
+// other rows.  The filter keeps one committed state (at its last update);
+// each row is predicted by a parameter-only transport from it, and the
+// covariance is transported only when a hit is picked (helix transports
+// compose exactly).  The lanes of a wave step through the rows together (a
+// lane idles on rows outside its walk), so their hit-table accesses and
+// (unit,row) records coalesce; each lane's own sequence of operations is that
+// of its walk alone.
 // 6 waves per SIMD: the walk is bound by dependent gathers, and the extra
 // waves hide more of their latency than the few spilled registers cost
 __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))) k_fit(Args A) {
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t i = int64_t(blockIdx.x) * CTB + threadIdx.x;
-  if (i >= w.ctr[C_SEEDS]) return;
-  const int64_t t = w.seed_list[i];
+  const int64_t n_seeds = w.ctr[C_SEEDS];
+  const int64_t i = xcd_chunk(blockIdx.x, (n_seeds + CTB - 1) / CTB) * CTB + threadIdx.x;
+  if ((i & ~int64_t(63)) >= n_seeds) return;  // whole wave past the seeds
+  const bool valid = i < n_seeds;
+  const int64_t t = valid ? w.seed_list[i] : 0;
   const tpc_params_t &P = A.p;
   const int nr = A.n_rows;
-  const int h0 = w.trk_start[t], u = w.trk_unit[t];
-  const int L = w.trk_len[t], r1 = w.trk_r1[t];
-  const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
-  int32_t *hits = w.trk_hits + t * nr;  // tracklet-major: row r at hits[r]
+  int32_t *col = seed_column(w, i, nr);
   const float sy2 = P.sigma_y * P.sigma_y, sz2 = P.sigma_z * P.sigma_z;
   const float k = A.kcurv, smx = P.sinphi_max;
   int nfit = 0, rlo = -1, rhi = -1;
+  int h0 = 0, u = 0, L = 0, r1 = 0, Yr = 0, Zr = 0;
+  const int32_t *segu = w.seg;
   KState s;
-  // seed, in coordinates relative to the first chain hit: small numbers keep
-  // FP32 precise even at |z'| of metres (continuous readout)
-  const int ha = hits[r1], hm = hits[r1 + L / 2], hb = hits[r1 + L - 1];
-  const int2 ya = w.syz[ha], ym = w.syz[hm], yb = w.syz[hb];
-  const int Yr = ya.x, Zr = ya.y;
-  bool ok;
-  {
+  bool ok = false;
+  if (valid) {
+    h0 = w.trk_start[t];
+    u = w.trk_unit[t];
+    L = w.trk_len[t];
+    r1 = w.trk_r1[t];
+    segu = w.seg + int64_t(u) * nr * SEGW;
+    // seed, in coordinates relative to the first chain hit: small numbers
+    // keep FP32 precise even at |z'| of metres (continuous readout)
+    const int2 ya = w.syz[h0], ym = w.syz[w.trk_hm[t]], yb = w.syz[w.trk_hb[t]];
+    Yr = ya.x;
+    Zr = ya.y;
     const float x0 = A.row_x[r1], x1 = A.row_x[r1 + L / 2], x2 = A.row_x[r1 + L - 1];
     const float y1 = float(ym.x - Yr) * (1.f / 256.f), y2 = float(yb.x - Yr) * (1.f / 256.f);
     const float z2 = float(yb.y - Zr) * (1.f / 256.f);
@@ -1247,64 +1297,85 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))
     s.chi2 = 0.f;
     cov_reset(s, P.cov0);
   }
+  // pass 1: the chain rows, then extension rows, in one walk up the rows;
+  // one propagate/update site serves both kinds of row
+  int r_out = r1, misses = 0, hc = h0;
+  bool act = ok;
   if (ok) {
-    // pass 1: the chain rows, then extension rows, in one walk up the rows;
-    // one propagate/update site serves both kinds of row
-    int r_out = r1;
-    int misses = 0;
-    upd_hit(A, s, ha, Yr, Zr, sy2, sz2);
-    for (int r = r1 + 1; r < nr; ++r) {
-      Step st;
-      const float xr = A.row_x[r];
-      if (!step_prepare(s, xr, k, smx, st)) break;
-      int h;
-      if (r < r1 + L) {
-        h = hits[r];
-      } else {
-        bool stop = false;
-        h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
-        if (stop) break;
-        hits[r] = h;
-      }
-      if (h >= 0) {
-        step_apply(s, st, xr, k);
-        upd_hit(A, s, h, Yr, Zr, sy2, sz2);
-        r_out = r;
-        misses = 0;
-      } else if (++misses > P.max_miss) {
-        break;
+    col[r1 * 64] = h0;
+    upd_hit(A, s, h0, Yr, Zr, sy2, sz2);
+  }
+  for (int r = wave_min(ok ? r1 : nr) + 1; r < nr; ++r) {
+    if (!__any(act)) break;
+    if (!act || r <= r1) continue;
+    Step st;
+    const float xr = A.row_x[r];
+    if (!step_prepare(s, xr, k, smx, st)) {
+      act = false;
+      continue;
+    }
+    int h;
+    if (r < r1 + L) {
+      hc = w.upc[hc];
+      h = hc;
+    } else {
+      bool stop = false;
+      h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
+      if (stop) {
+        act = false;
+        continue;
       }
     }
-    // pass 2: from the outermost hit down to row 0, covariance reset
+    col[r * 64] = h;
+    if (h >= 0) {
+      step_apply(s, st, xr, k);
+      upd_hit(A, s, h, Yr, Zr, sy2, sz2);
+      r_out = r;
+      misses = 0;
+    } else if (++misses > P.max_miss) {
+      act = false;
+    }
+  }
+  // pass 2: from the outermost hit down to row 0, covariance reset
+  act = ok;
+  if (ok) {
     cov_reset(s, P.cov0);
     s.chi2 = 0.f;
-    upd_hit(A, s, hits[r_out], Yr, Zr, sy2, sz2);
+    upd_hit(A, s, col[r_out * 64], Yr, Zr, sy2, sz2);
     nfit = 1;
     rhi = r_out;
     rlo = r_out;
     misses = 0;
-    for (int r = r_out - 1; r >= 0; --r) {
-      Step st;
-      const float xr = A.row_x[r];
-      if (!step_prepare(s, xr, k, smx, st)) break;
-      int h = r >= r1 ? hits[r] : -1;  // pass-1 hit of this row, if any
-      if (h < 0) {
-        bool stop = false;
-        h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
-        if (stop) break;
-        hits[r] = h;
-        if (h < 0) {
-          rlo = r;
-          if (r < r1 && ++misses > P.max_miss) break;
-          continue;
-        }
-        misses = 0;
-      }
-      step_apply(s, st, xr, k);
-      upd_hit(A, s, h, Yr, Zr, sy2, sz2);
-      ++nfit;
-      rlo = r;
+  }
+  for (int r = wave_max(ok ? r_out - 1 : -1); r >= 0; --r) {
+    if (!__any(act)) break;
+    if (!act || r >= r_out) continue;
+    Step st;
+    const float xr = A.row_x[r];
+    if (!step_prepare(s, xr, k, smx, st)) {
+      act = false;
+      continue;
     }
+    int h = r >= r1 ? col[r * 64] : -1;  // pass-1 hit of this row, if any
+    if (h < 0) {
+      bool stop = false;
+      h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
+      if (stop) {
+        act = false;
+        continue;
+      }
+      col[r * 64] = h;
+      if (h < 0) {
+        rlo = r;
+        if (r < r1 && ++misses > P.max_miss) act = false;
+        continue;
+      }
+      misses = 0;
+    }
+    step_apply(s, st, xr, k);
+    upd_hit(A, s, h, Yr, Zr, sy2, sz2);
+    ++nfit;
+    rlo = r;
   }
   uint32_t key = 0;
   if (nfit > 0) {
@@ -1320,21 +1391,24 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))
     s.x = 0.f;
     s.chi2 = 0.f;
   }
-  w.trk_nfit[t] = nfit;
-  w.trk_rlo[t] = rlo;
-  w.trk_rhi[t] = rhi;
-  w.trk_key[t] = key;
+  if (valid) {
+    w.trk_nfit[t] = nfit;
+    w.trk_rlo[t] = rlo;
+    w.trk_rhi[t] = rhi;
+    w.trk_key[t] = key;
 #pragma unroll
-  for (int j = 0; j < 5; ++j) w.trk_par[t * 5 + j] = s.p[j];
+    for (int j = 0; j < 5; ++j) w.trk_par[t * 5 + j] = s.p[j];
 #pragma unroll
-  for (int j = 0; j < 15; ++j) w.trk_cov[t * 15 + j] = s.c[j];
-  w.trk_x[t] = s.x;
-  w.trk_chi2[t] = s.chi2;
+    for (int j = 0; j < 15; ++j) w.trk_cov[t * 15 + j] = s.c[j];
+    w.trk_x[t] = s.x;
+    w.trk_chi2[t] = s.chi2;
+  }
   // ownership: every hit goes to the tracklet with the largest key
-  if (nfit > 0) {
-#pragma unroll 8
-    for (int r = rlo; r <= rhi; ++r) {
-      const int h = hits[r];
+  const bool has = nfit > 0;
+  const int rb = wave_max(has ? rhi : -1);
+  for (int r = wave_min(has ? rlo : nr); r <= rb; ++r) {
+    if (has && r >= rlo && r <= rhi) {
+      const int h = col[r * 64];
       if (h >= 0) atomicMax(&w.owner[h], key);
     }
   }
@@ -1351,22 +1425,28 @@ __global__ void __launch_bounds__(TPB) k_select(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  int keep = 0, owned = 0;
-  if (i < w.ctr[C_SEEDS]) {
-    const int64_t t = w.seed_list[i];
-    const int nfit = w.trk_nfit[t];
-    if (nfit > 0) {
-      const uint32_t key = w.trk_key[t];
-      const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
-      const int32_t *hits = w.trk_hits + t * A.n_rows;
-#pragma unroll 8
-      for (int r = rlo; r <= rhi; ++r) {
-        const int h = hits[r];
-        if (h >= 0 && w.owner[h] == key) ++owned;
-      }
-      keep = owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
+  const int64_t n_seeds = w.ctr[C_SEEDS];
+  const int64_t b = xcd_chunk(blockIdx.x, (n_seeds + TPB - 1) / TPB);
+  if (b >= w.KB) return;
+  const int64_t i = b * TPB + threadIdx.x;
+  const bool valid = i < n_seeds;
+  const int64_t t = valid ? w.seed_list[i] : 0;
+  const int nfit = valid ? w.trk_nfit[t] : 0;
+  const bool has = nfit > 0;
+  const uint32_t key = has ? w.trk_key[t] : 0u;
+  const int rlo = has ? w.trk_rlo[t] : 0, rhi = has ? w.trk_rhi[t] : -1;
+  const int nr = A.n_rows;
+  const int32_t *col = seed_column(w, i, nr);
+  int owned = 0;
+  const int rb = wave_max(has ? rhi : -1);
+  for (int r = wave_min(has ? rlo : nr); r <= rb; ++r) {
+    if (r >= rlo && r <= rhi) {
+      const int h = col[r * 64];
+      if (h >= 0 && w.owner[h] == key) ++owned;
     }
+  }
+  const int keep = has && owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
+  if (valid) {
     w.trk_owned[t] = owned;
     w.trk_keep[t] = keep;
   }
@@ -1374,8 +1454,8 @@ __global__ void __launch_bounds__(TPB) k_select(Args A) {
   block_exclusive_scan<TPB>(keep, tmp, &tk);
   block_exclusive_scan<TPB>(keep ? owned : 0, tmp, &to);
   if (threadIdx.x == 0) {
-    w.blk_keep[blockIdx.x] = tk;
-    w.blk_own[blockIdx.x] = to;
+    w.blk_keep[b] = tk;
+    w.blk_own[b] = to;
   }
 }
 
@@ -1383,43 +1463,54 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  const bool valid = i < w.ctr[C_SEEDS];
+  const int64_t n_seeds = w.ctr[C_SEEDS];
+  const int64_t b = xcd_chunk(blockIdx.x, (n_seeds + TPB - 1) / TPB);
+  if (b >= w.KB) return;
+  const int64_t i = b * TPB + threadIdx.x;
+  const bool valid = i < n_seeds;
   const int64_t t = valid ? w.seed_list[i] : 0;
   const int keep = valid ? w.trk_keep[t] : 0;
   const int owned = keep ? w.trk_owned[t] : 0;
   int tk, to;
   const int ek = block_exclusive_scan<TPB>(keep, tmp, &tk);
   const int eo = block_exclusive_scan<TPB>(owned, tmp, &to);
-  if (!keep) return;
-  const int tr = w.blk_keep[blockIdx.x] + ek;
-  int off = w.blk_own[blockIdx.x] + eo;
+  const int tr = w.blk_keep[b] + ek;
+  int off = w.blk_own[b] + eo;
   const tpc_tracks_t &O = A.out;
+  uint32_t key = 0u;
+  int rlo = 0, rhi = -1;
+  if (keep) {
 #pragma unroll
-  for (int j = 0; j < 5; ++j) O.params[int64_t(tr) * 5 + j] = w.trk_par[t * 5 + j];
+    for (int j = 0; j < 5; ++j) O.params[int64_t(tr) * 5 + j] = w.trk_par[t * 5 + j];
 #pragma unroll
-  for (int j = 0; j < 15; ++j) O.cov[int64_t(tr) * 15 + j] = w.trk_cov[t * 15 + j];
-  O.x_ref[tr] = w.trk_x[t];
-  O.chi2[tr] = w.trk_chi2[t];
-  O.unit[tr] = w.trk_unit[t];
-  O.n_hits[tr] = owned;
-  O.n_fit[tr] = w.trk_nfit[t];
-  O.first_hit[tr] = off;
-  const uint32_t key = w.trk_key[t];
-  const int rlo = w.trk_rlo[t], rhi = w.trk_rhi[t];
-  const int32_t *hits = w.trk_hits + t * A.n_rows;
-#pragma unroll 4
-  for (int r = rlo; r <= rhi; ++r) {
-    const int h = hits[r];
-    if (h >= 0 && w.owner[h] == key) {
-      const int id = w.perm[h];
-      O.hits[off++] = id;
-      O.cluster_track[id] = tr;
+    for (int j = 0; j < 15; ++j) O.cov[int64_t(tr) * 15 + j] = w.trk_cov[t * 15 + j];
+    O.x_ref[tr] = w.trk_x[t];
+    O.chi2[tr] = w.trk_chi2[t];
+    O.unit[tr] = w.trk_unit[t];
+    O.n_hits[tr] = owned;
+    O.n_fit[tr] = w.trk_nfit[t];
+    O.first_hit[tr] = off;
+    key = w.trk_key[t];
+    rlo = w.trk_rlo[t];
+    rhi = w.trk_rhi[t];
+  }
+  const int nr = A.n_rows;
+  const int32_t *col = seed_column(w, i, nr);
+  const int rb = wave_max(keep ? rhi : -1);
+  for (int r = wave_min(keep ? rlo : nr); r <= rb; ++r) {
+    if (r >= rlo && r <= rhi) {
+      const int h = col[r * 64];
+      if (h >= 0 && w.owner[h] == key) {
+        const int id = w.perm[h];
+        O.hits[off++] = id;
+        O.cluster_track[id] = tr;
+      }
     }
   }
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+inline unsigned round8(int64_t b) { return unsigned((b + 7) & ~int64_t(7)); }
 
 }  // namespace
 
@@ -1514,7 +1605,7 @@ int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field
     mark();
     hipLaunchKernelGGL(k_bin_sort, dim3(unsigned(w.S)), dim3(TPB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_neighbours, dim3(unsigned(c->n / NCH + w.S)), dim3(NCH), 0, st, A);
+    hipLaunchKernelGGL(k_neighbours, dim3(round8(c->n / NCH + w.S)), dim3(NCH), 0, st, A);
     mark();
     hipLaunchKernelGGL(k_clean, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
     mark();
@@ -1532,15 +1623,15 @@ int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field
     mark();
     hipLaunchKernelGGL(k_compact_seeds, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_fit, dim3(blocks_for(w.K_cap, CTB)), dim3(CTB), 0, st, A);
+    hipLaunchKernelGGL(k_fit, dim3(round8(blocks_for(w.K_cap, CTB))), dim3(CTB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_select, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+    hipLaunchKernelGGL(k_select, dim3(round8(w.KB)), dim3(TPB), 0, st, A);
     mark();
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, w.blk_keep, w.KB, w.ctr + C_TRACKS,
                        out->counts + 0, out->cap_tracks, out->status, w.blk_own, w.ctr + C_HITS,
                        out->counts + 1, out->cap_hits);
     mark();
-    hipLaunchKernelGGL(k_emit, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+    hipLaunchKernelGGL(k_emit, dim3(round8(w.KB)), dim3(TPB), 0, st, A);
   }
   while (ki <= kNumKernels) mark();  // empty batch: the remaining events mark the same point
   if (hipGetLastError() != hipSuccess) return TPC_E_HIP;
@@ -1600,7 +1691,8 @@ extern "C" int tpc_inspect(const tpc_clusters_t *c, int32_t n_rows, const tpc_pa
     case TPC_VIEW_TRK_COV: ptr = w.trk_cov; cnt = K * 15; break;
     case TPC_VIEW_TRK_XREF: ptr = w.trk_x; cnt = K; break;
     case TPC_VIEW_TRK_CHI2: ptr = w.trk_chi2; cnt = K; break;
-    case TPC_VIEW_TRK_HITS: ptr = w.trk_hits; cnt = K * n_rows; break;
+    case TPC_VIEW_TRK_HITS: ptr = w.trk_hits; cnt = w.KW * 64 * n_rows; break;
+    case TPC_VIEW_SEED_LIST: ptr = w.seed_list; cnt = K; break;
     default: return TPC_E_INVALID;
   }
   v->ptr = ptr;

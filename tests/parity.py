@@ -62,8 +62,15 @@ def gpu_state(tracker, result):
     g["trk_cov"] = tracker.inspect(T.TPC_VIEW_TRK_COV, torch.float32).cpu().numpy().reshape(-1, 15)[:K]
     g["trk_xref"] = tracker.inspect(T.TPC_VIEW_TRK_XREF, torch.float32).cpu().numpy()[:K]
     g["trk_chi2"] = tracker.inspect(T.TPC_VIEW_TRK_CHI2, torch.float32).cpu().numpy()[:K]
-    hits = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(-1, n_rows)[:K]
-    g["trk_hitrows"] = hits.T  # [row][tracklet]
+    # seeds: tracklets with a chain of >= l_min hits, in tracklet order
+    seeds = np.nonzero(g["trk_len"] >= int(tracker.params.l_min))[0]
+    g["seed_list"] = tracker.inspect(T.TPC_VIEW_SEED_LIST).cpu().numpy()[:len(seeds)]
+    g["seeds_expected"] = seeds
+    raw = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(-1, n_rows, 64)
+    per_seed = raw.transpose(0, 2, 1).reshape(-1, n_rows)[:len(seeds)]  # [seed][row]
+    hitrows = np.full((n_rows, K), -1, np.int32)
+    hitrows[:, seeds] = per_seed.T
+    g["trk_hitrows"] = hitrows  # [row][tracklet]
     for k in ("n_tracks", "n_track_hits", "n_tracklets", "n_cells"):
         g[k] = result[k]
     for k in ("cluster_track", "params", "cov", "x_ref", "chi2", "unit", "n_hits", "n_fit",
@@ -126,6 +133,8 @@ def compare(g, o, check_outputs=True, rtol_scale=1.0):
     for k in ("trk_start", "trk_unit", "trk_len"):
         if not np.array_equal(g[k], o[k]):
             rep.fail("%s differs" % k)
+    if "seed_list" in g and not np.array_equal(g["seed_list"], g["seeds_expected"]):
+        rep.fail("seed list is not the tracklets with a chain of >= l_min hits")
     gs, os_ = gpu_hit_sets(g), oracle_hit_sets(o)
     same = np.array([len(a) == len(b) and np.array_equal(a, b) for a, b in zip(gs, os_)], bool)
     same &= g["trk_nfit"] == o["trk_nfit"]

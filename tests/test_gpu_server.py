@@ -1,0 +1,216 @@
+"""Serving loop (tpc_server_* in include/tpc_track.h) on the GPU.
+
+Each request's results must be those of tracking it alone (bit for bit:
+units are independent and every step is deterministic), whether it ran alone
+or packed into a batch with others; admission holds requests until the arena
+has room; a full queue answers BUSY; a malformed request fails alone.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("cluster_track", "params", "cov", "x_ref", "chi2", "unit", "n_hits", "n_fit", "first_hit", "hits")
+
+
+@pytest.fixture(scope="module")
+def frames():
+    import synth
+    from paper_2106_03636_amd.runtime import track
+    evs = [synth.event_pp_sector(31 + i, sector=i) for i in range(3)]
+    evs.append(synth.event_pbpb_timeframe(41, n_collisions=2))
+    evs.append(synth.event_uneven_chunks(51, n_units=6, n_lo=1e3, n_hi=2e4))
+    alone = []
+    for e in evs:
+        r = track(e.y, e.z, e.row, e.unit_offsets, e.row_x, e.bz)
+        alone.append({k: (np.asarray(v) if k in KEYS else v) for k, v in r.items()})
+        print("frame %d: %d clusters, %d units, %d tracks" % (len(alone) - 1, e.n, e.n_units, r["n_tracks"]),
+              flush=True)
+    return evs, alone
+
+
+def _same(res, ref, tag=""):
+    import paper_2106_03636_amd as T
+    assert res["status"] == T.TPC_OK, tag
+    assert res["n_tracks"] == ref["n_tracks"], tag
+    assert res["n_track_hits"] == ref["n_track_hits"], tag
+    for k in KEYS:
+        np.testing.assert_array_equal(res[k], ref[k], err_msg="%s %s" % (tag, k))
+
+
+def _server(evs, **kw):
+    from paper_2106_03636_amd.server import Server
+    return Server(evs[0].row_x, evs[0].bz, **kw)
+
+
+def test_served_alone_matches_standalone(frames):
+    evs, alone = frames
+    srv = _server(evs, budget_bytes=2 << 30, max_batch_requests=1)
+    try:
+        for i, e in enumerate(evs):
+            st, t = srv.submit(e.y, e.z, e.row, e.unit_offsets)
+            assert st == 0
+            res = srv.poll(t)
+            assert res["batch_requests"] == 1
+            _same(res, alone[i], "frame %d" % i)
+            srv.release(t)
+    finally:
+        srv.close()
+
+
+def test_served_in_mix_matches_alone(frames):
+    """Requests queued together are packed into shared batches; every result
+    is still the one the request gets alone."""
+    evs, alone = frames
+    srv = _server(evs, budget_bytes=4 << 30, max_in_flight=2, queue_depth=64)
+    order = [0, 3, 1, 4, 2, 2, 0, 4, 1, 3, 0, 1, 2]
+    try:
+        tickets = []
+        for i in order:
+            e = evs[i]
+            st, t = srv.submit(e.y, e.z, e.row, e.unit_offsets)
+            assert st == 0
+            tickets.append((i, t))
+        shared = 0
+        for i, t in tickets:
+            res = srv.poll(t)
+            shared += res["batch_requests"] > 1
+            _same(res, alone[i], "frame %d ticket %d (batch of %d)" % (i, t, res["batch_requests"]))
+            assert res["t_submit"] <= res["t_admit"] <= res["t_done"]
+            srv.release(t)
+        assert shared > 0, "no request shared a batch"
+        st = srv.stats()
+        assert st["completed"] == len(order) and st["pending"] == 0 and st["in_flight"] == 0
+        assert st["batches"] < len(order)
+    finally:
+        srv.close()
+
+
+def test_device_and_borrowed_inputs(frames):
+    import torch
+    from paper_2106_03636_amd.server import TPC_REQ_BORROW_HOST, TPC_REQ_DEVICE
+    evs, alone = frames
+    srv = _server(evs, budget_bytes=2 << 30, max_in_flight=2)
+    try:
+        e = evs[3]
+        dev = [torch.as_tensor(e.y).cuda(), torch.as_tensor(e.z).cuda(),
+               torch.as_tensor(e.row.view(np.int16)).cuda()]
+        torch.cuda.synchronize()
+        st, t1 = srv.submit(*dev, e.unit_offsets, flags=TPC_REQ_DEVICE)
+        assert st == 0
+        pin = [torch.as_tensor(a).pin_memory().numpy() for a in (evs[4].y, evs[4].z, evs[4].row.view(np.int16))]
+        st, t2 = srv.submit(pin[0], pin[1], pin[2].view(np.uint16), evs[4].unit_offsets,
+                            flags=TPC_REQ_BORROW_HOST)
+        assert st == 0
+        _same(srv.poll(t1), alone[3], "device")
+        _same(srv.poll(t2), alone[4], "borrowed")
+        srv.release(t1)
+        srv.release(t2)
+    finally:
+        srv.close()
+
+
+def test_admission_waits_for_memory(frames):
+    """A budget that holds one large frame at a time: requests wait for the
+    arena, none is refused, and the arena never overflows."""
+    import paper_2106_03636_amd as T
+    evs, alone = frames
+    big = evs[3]
+    probe = _server(evs, budget_bytes=1 << 20)
+    need = probe.footprint(big.n, big.n_units)
+    st, _ = probe.submit(big.y, big.z, big.row, big.unit_offsets)
+    assert st == T.TPC_E_NOMEM  # could never fit a 1 MiB arena
+    assert probe.stats()["rejected_nomem"] == 1
+    probe.close()
+    srv = _server(evs, budget_bytes=int(need * 1.5), max_in_flight=2)
+    try:
+        tickets = []
+        for _ in range(3):
+            st, t = srv.submit(big.y, big.z, big.row, big.unit_offsets)
+            assert st == 0
+            tickets.append(t)
+        res = [srv.poll(t) for t in tickets]
+        for r in res:
+            _same(r, alone[3], "big")
+            assert r["batch_requests"] == 1
+        # one at a time: each starts after the previous one finished
+        for a, b in zip(res, res[1:]):
+            assert b["t_admit"] >= a["t_done"]
+        st = srv.stats()
+        assert st["arena_peak"] <= st["arena_bytes"]
+        for t in tickets:
+            srv.release(t)
+    finally:
+        srv.close()
+
+
+def test_back_pressure_then_all_complete(frames):
+    """Device-resident requests are queued in microseconds while each takes
+    milliseconds on the GPU, so a queue of depth 2 fills and pushes back."""
+    import torch
+    import paper_2106_03636_amd as T
+    from paper_2106_03636_amd.server import TPC_REQ_DEVICE
+    evs, alone = frames
+    e = evs[3]
+    dev = [torch.as_tensor(e.y).cuda(), torch.as_tensor(e.z).cuda(),
+           torch.as_tensor(e.row.view(np.int16)).cuda()]
+    torch.cuda.synchronize()
+    srv = _server(evs, budget_bytes=4 << 30, max_in_flight=1, queue_depth=2, max_batch_requests=1)
+    try:
+        accepted, busy = [], 0
+        for _ in range(8):
+            st, t = srv.submit(*dev, e.unit_offsets, flags=TPC_REQ_DEVICE)
+            if st == T.TPC_E_BUSY:
+                busy += 1
+            else:
+                assert st == 0
+                accepted.append(t)
+        assert busy > 0, "queue_depth 2 never pushed back"
+        for t in accepted:
+            _same(srv.poll(t), alone[3], "accepted")
+            srv.release(t)
+        assert srv.stats()["rejected_busy"] == busy
+    finally:
+        srv.close()
+
+
+def test_malformed_requests_fail_alone(frames):
+    """A host request with a row beyond the geometry is refused at submit; a
+    device request with one fails on the GPU, alone: its batch-mates get their
+    own results."""
+    import torch
+    import paper_2106_03636_amd as T
+    from paper_2106_03636_amd.server import TPC_REQ_DEVICE
+    evs, alone = frames
+    srv = _server(evs, budget_bytes=4 << 30, max_in_flight=1, queue_depth=16)
+    try:
+        e = evs[0]
+        row = e.row.copy()
+        row[5] = 200
+        st, _ = srv.submit(e.y, e.z, row, e.unit_offsets)
+        assert st == T.TPC_E_INVALID
+        bad = [torch.as_tensor(e.y).cuda(), torch.as_tensor(e.z).cuda(),
+               torch.as_tensor(row.view(np.int16)).cuda()]
+        torch.cuda.synchronize()
+        # hold the single slot with a large frame so the next three queue up
+        # and are packed into one batch
+        st, t_big = srv.submit(evs[3].y, evs[3].z, evs[3].row, evs[3].unit_offsets)
+        assert st == 0
+        st, t_a = srv.submit(evs[1].y, evs[1].z, evs[1].row, evs[1].unit_offsets)
+        st2, t_bad = srv.submit(*bad, e.unit_offsets, flags=TPC_REQ_DEVICE)
+        st3, t_b = srv.submit(evs[2].y, evs[2].z, evs[2].row, evs[2].unit_offsets)
+        assert st == st2 == st3 == 0
+        _same(srv.poll(t_big), alone[3], "big")
+        _same(srv.poll(t_a), alone[1], "before the bad one")
+        r = srv.poll(t_bad)
+        assert r["status"] == T.TPC_E_INVALID
+        _same(srv.poll(t_b), alone[2], "after the bad one")
+        for t in (t_big, t_a, t_bad, t_b):
+            srv.release(t)
+        # the server still works
+        st, t = srv.submit(e.y, e.z, e.row, e.unit_offsets)
+        assert st == 0
+        _same(srv.poll(t), alone[0], "after")
+        assert srv.stats()["rejected_invalid"] == 1
+    finally:
+        srv.close()
