@@ -36,7 +36,7 @@ B_ALG_TOTAL = sum(B_ALG.values())
 KERNEL_FAMILY = {
     "k_init": None, "k_units": None, "k_tile_hist": "grid", "k_seg_plan": "grid",
     "k_cell_base": "grid", "k_tile_offsets": "grid", "k_tile_scatter": "grid", "k_bin_sort": "grid",
-    "k_neighbours": "neighbours", "k_clean": "cleaner", "k_scan_blocks": "cleaner",
+    "k_neighbours": "neighbours", "k_neighbours_wide": "neighbours", "k_clean": "cleaner", "k_scan_blocks": "cleaner",
     "k_compact_starts": "cleaner", "k_chains": "constructor", "k_compact_seeds": "constructor",
     "k_fit": "constructor", "k_select": "selector",
     "k_emit": "selector",

@@ -35,7 +35,8 @@ constexpr float KAPPA = 0.00299792458f;
 // (unit,row) record fields
 enum { S_START = 0, S_COUNT, S_ZMIN, S_ZMAX, S_H, S_BY, S_NY, S_BZ, S_NZ, S_CBASE, S_CHUNK };
 // internal counters
-enum { C_K = 0, C_CELLS = 1, C_TRACKS = 2, C_HITS = 3, C_TILES = 4, C_NCHUNK = 5, C_SEEDS = 6, C_N = 8 };
+enum { C_K = 0, C_CELLS = 1, C_TRACKS = 2, C_HITS = 3, C_TILES = 4, C_NCHUNK = 5, C_SEEDS = 6, C_NWIDE = 7,
+       C_N = 8 };
 
 struct Workspace {
   int64_t *ctr;
@@ -49,13 +50,14 @@ struct Workspace {
   uint8_t *flag;
   uint32_t *owner;
   int32_t *cell, *cursor;
+  int32_t *chunk_seg, *wide;  // neighbour-finder chunk -> (unit,row); chunks too wide for LDS
   int32_t *blk, *blk_keep, *blk_own;
   int32_t *trk_start, *trk_unit, *trk_len, *trk_nfit, *trk_rlo, *trk_rhi, *trk_owned, *trk_keep;
   int32_t *trk_r1, *trk_hm, *trk_hb, *seed_list;
   uint32_t *trk_key;
   float *trk_par, *trk_cov, *trk_x, *trk_chi2;
   int32_t *trk_hits;
-  int64_t N, S, T_max, C_max, K_cap, NB, KB, KW;
+  int64_t N, S, T_max, C_max, K_cap, NB, KB, KW, CH_max;
   size_t total;
 };
 
@@ -91,6 +93,7 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.NB = (n + ELEMS - 1) / ELEMS + 1;
   L.KB = (L.K_cap + TPB - 1) / TPB;
   L.KW = (L.K_cap + 63) / 64;
+  L.CH_max = n / NCH + L.S;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -118,6 +121,8 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.owner = (uint32_t *)take(4 * N);
   L.cell = (int32_t *)take(4 * (size_t(L.C_max) + 1));
   L.cursor = (int32_t *)take(4 * size_t(L.C_max));
+  L.chunk_seg = (int32_t *)take(4 * size_t(L.CH_max));
+  L.wide = (int32_t *)take(4 * size_t(L.CH_max));
   L.blk = (int32_t *)take(4 * size_t(L.NB));
   L.blk_keep = (int32_t *)take(4 * size_t(L.KB));
   L.blk_own = (int32_t *)take(4 * size_t(L.KB));
@@ -426,7 +431,8 @@ __global__ void __launch_bounds__(1024) k_cell_base(Args A) {
   }
 }
 
-// step 2d: output position of each tile's first hit of each row
+// step 2d: output position of each tile's first hit of each row; the
+// (unit,row) of every neighbour-finder chunk
 __global__ void __launch_bounds__(64) k_tile_offsets(Args A) {
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
@@ -436,6 +442,9 @@ __global__ void __launch_bounds__(64) k_tile_offsets(Args A) {
   int carry = w.seg[s * SEGW + S_START];
   int32_t *h = w.tile_hist + int64_t(r) * w.T_max;
   const int lane = __lane_id();
+  // neighbour-finder chunks of this (unit,row) point back to it
+  const int c0 = w.seg[s * SEGW + S_CHUNK], nch = (w.seg[s * SEGW + S_COUNT] + NCH - 1) / NCH;
+  for (int j = lane; j < nch; j += 64) w.chunk_seg[c0 + j] = int32_t(s);
   for (int t = t0; t < t1; t += 64) {
     const int i = t + lane;
     const int v = i < t1 ? h[i] : 0;
@@ -680,11 +689,11 @@ __device__ __forceinline__ int2 hit_at(const Workspace &w, const Slab &sl, const
   return LDS ? lh[q - sl.q0] : w.syz[q];
 }
 
-// Best (d, u) pair of hit m; see the step description above.
-// floor(a / b) for b > 0 and |a| < 2^52, exactly: an FP64 quotient is off by
-// at most one, then corrected with integer products.
-__device__ __forceinline__ int64_t floor_div_exact(int64_t a, int64_t b) {
-  int64_t q = int64_t(floor(double(a) / double(b)));
+// floor(a / b) for 0 < b and |a| < 2^50, exactly: a times the rounded
+// reciprocal of b is within one of the quotient, then corrected with integer
+// products.
+__device__ __forceinline__ int64_t floor_div_exact(int64_t a, int64_t b, double inv_b) {
+  int64_t q = int64_t(floor(double(a) * inv_b));
   if (q * b > a) --q;
   else if ((q + 1) * b <= a) ++q;
   return q;
@@ -697,10 +706,10 @@ struct Cand {
 };
 
 __device__ __forceinline__ Cand cand_window(const int32_t *rec, int64_t Ym, int64_t Zm, int64_t Xi,
-                                            int64_t Xj, int64_t WY, int64_t WZ) {
+                                            double inv_xi, int64_t Xj, int64_t WY, int64_t WZ) {
   Cand k;
-  const int64_t lo = -floor_div_exact(-(Ym * Xj - WY * Xi), Xi);  // ceil
-  const int64_t hi = floor_div_exact(Ym * Xj + WY * Xi, Xi);
+  const int64_t lo = -floor_div_exact(-(Ym * Xj - WY * Xi), Xi, inv_xi);  // ceil
+  const int64_t hi = floor_div_exact(Ym * Xj + WY * Xi, Xi, inv_xi);
   // |Y| <= 2^21 for every cluster: clamping keeps the compares exact in int32
   k.ylo = int(lo < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (lo > (int64_t(1) << 30) ? (int64_t(1) << 30) : lo));
   k.yhi = int(hi < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (hi > (int64_t(1) << 30) ? (int64_t(1) << 30) : hi));
@@ -714,15 +723,15 @@ constexpr int MAXU = 4;  // row-above candidates kept in registers
 template <bool LDS>
 __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *recd, const int32_t *recu,
                                           const Slab &sd, const Slab &su, const int *lcd, const int *lcu,
-                                          const int2 *lhd, const int2 *lhu, int64_t Xi, int64_t Xd,
-                                          int64_t Xu, int64_t smax, int &best_d, int &best_u) {
+                                          const int2 *lhd, const int2 *lhu, int64_t Xi, double inv_xi,
+                                          int64_t Xd, int64_t Xu, int64_t smax, int &best_d, int &best_u) {
   const Workspace &w = A.w;
   const int64_t WY = A.p.win_y_q, WZ = A.p.win_z_q, wy = A.p.w_y, wz = A.p.w_z;
   const int dxd = int(Xi - Xd), dxu = int(Xu - Xi);
   const int2 hm = w.syz[m];
   const int Ym = hm.x, Zm = hm.y;
-  const Cand kd = cand_window(recd, Ym, Zm, Xi, Xd, WY, WZ);
-  const Cand ku = cand_window(recu, Ym, Zm, Xi, Xu, WY, WZ);
+  const Cand kd = cand_window(recd, Ym, Zm, Xi, inv_xi, Xd, WY, WZ);
+  const Cand ku = cand_window(recu, Ym, Zm, Xi, inv_xi, Xu, WY, WZ);
   best_d = -1;
   best_u = -1;
   if (kd.c.empty || ku.c.empty) return;
@@ -813,72 +822,124 @@ __device__ __forceinline__ Slab make_slab(const Workspace &w, const int32_t *rec
   return sl;
 }
 
-__global__ void __launch_bounds__(NCH) k_neighbours(Args A) {
-  __shared__ int2 lh[2][STAGE_HITS];
-  __shared__ int lc[2][STAGE_CELLS];
-  __shared__ int zr[2];
+// One chunk of NCH hits of one (unit,row): which hits, and the z slabs of
+// the two neighbour rows that hold every candidate of every hit of the chunk.
+// The z range comes from the z bins of the chunk's first and last hits (hits
+// are in (z bin, y bin) order and bins are exact floors), widened by the
+// window.
+struct Chunk {
+  int64_t s;
+  int r, m, n_here;
+  const int32_t *rec;
+  Slab sd, su;
+};
+
+__device__ __forceinline__ Chunk chunk_setup(const Args &A, int b) {
   const Workspace &w = A.w;
-  if (*A.out.status != TPC_OK) return;
-  const int64_t n_chunks = w.ctr[C_NCHUNK];
-  const int b = int(xcd_chunk(blockIdx.x, n_chunks));
-  if (b >= n_chunks) return;
-  // segment of this chunk: last s with chunk base <= b and a non-empty row
-  int lo = 0, hi = int(w.S) - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (w.seg[int64_t(mid) * SEGW + S_CHUNK] <= b) lo = mid; else hi = mid - 1;
-  }
-  const int64_t s = lo;
-  const int r = int(s % A.n_rows);
-  const int32_t *rec = w.seg + s * SEGW;
-  const int start = rec[S_START], count = rec[S_COUNT];
-  const int p0 = (b - rec[S_CHUNK]) * NCH;
-  const int n_here = min(NCH, count - p0);
-  const int m = start + p0 + int(threadIdx.x);
-  const bool act = int(threadIdx.x) < n_here;
-  if (r == 0 || r == A.n_rows - 1) {
-    if (act) {
-      w.up[m] = -1;
-      w.dn[m] = -1;
-    }
-    return;
-  }
-  const int32_t *recd = rec - SEGW, *recu = rec + SEGW;
-  // z extent of the chunk (hits are in (z bin, y bin) order, so it is narrow)
-  if (threadIdx.x == 0) {
-    zr[0] = INT32_MAX;
-    zr[1] = INT32_MIN;
-  }
-  __syncthreads();
-  if (act) {
-    const int Z = w.syz[m].y;
-    atomicMin(&zr[0], Z);
-    atomicMax(&zr[1], Z);
-  }
-  __syncthreads();
+  Chunk c;
+  c.s = w.chunk_seg[b];
+  c.r = int(c.s % A.n_rows);
+  c.rec = w.seg + c.s * SEGW;
+  const int start = c.rec[S_START], count = c.rec[S_COUNT];
+  const int p0 = (b - c.rec[S_CHUNK]) * NCH;
+  c.n_here = min(NCH, count - p0);
+  c.m = start + p0 + int(threadIdx.x);
+  c.sd.lds = c.su.lds = true;
+  c.sd.nq = c.su.nq = 0;
+  if (c.r == 0 || c.r == A.n_rows - 1) return c;
+  const int zmin = c.rec[S_ZMIN], bz = c.rec[S_BZ];
+  const int za = w.syz[start + p0].y, zb = w.syz[start + p0 + c.n_here - 1].y;
   const int64_t WZ = A.p.win_z_q;
-  const int64_t zlo = int64_t(zr[0]) - WZ, zhi = int64_t(zr[1]) + WZ;
-  const Slab sd = make_slab(w, recd, zlo, zhi), su = make_slab(w, recu, zlo, zhi);
-  const bool staged = sd.lds && su.lds;
-  if (staged) {
-    for (int i = threadIdx.x; i < sd.nq; i += NCH) lh[0][i] = w.syz[sd.q0 + i];
-    for (int i = threadIdx.x; i < su.nq; i += NCH) lh[1][i] = w.syz[su.q0 + i];
-    for (int i = threadIdx.x; i <= sd.nc && sd.nq + sd.nc > 0; i += NCH) lc[0][i] = w.cell[sd.c0 + i];
-    for (int i = threadIdx.x; i <= su.nc && su.nq + su.nc > 0; i += NCH) lc[1][i] = w.cell[su.c0 + i];
-  }
-  __syncthreads();
-  if (!act) return;
+  const int64_t zlo = int64_t(zmin) + int64_t((za - zmin) / bz) * bz - WZ;
+  const int64_t zhi = int64_t(zmin) + int64_t((zb - zmin) / bz + 1) * bz - 1 + WZ;
+  c.sd = make_slab(w, c.rec - SEGW, zlo, zhi);
+  c.su = make_slab(w, c.rec + SEGW, zlo, zhi);
+  return c;
+}
+
+template <bool LDS>
+__device__ __forceinline__ void chunk_links(const Args &A, const Chunk &c, const int *lcd, const int *lcu,
+                                            const int2 *lhd, const int2 *lhu) {
+  const Workspace &w = A.w;
+  const int r = c.r;
   const int64_t Xi = __float2ll_rn(A.row_x[r] * 256.0f);
   const int64_t Xd = __float2ll_rn(A.row_x[r - 1] * 256.0f);
   const int64_t Xu = __float2ll_rn(A.row_x[r + 1] * 256.0f);
   const int64_t smax = A.p.smax_k * (Xu - Xd) * (Xu - Xd);
   int bd, bu;
-  if (staged)
-    best_pair<true>(A, m, recd, recu, sd, su, lc[0], lc[1], lh[0], lh[1], Xi, Xd, Xu, smax, bd, bu);
-  else
-    best_pair<false>(A, m, recd, recu, sd, su, nullptr, nullptr, nullptr, nullptr, Xi, Xd, Xu, smax, bd, bu);
-  w.dn[m] = bd;
-  w.up[m] = bu;
+  best_pair<LDS>(A, c.m, c.rec - SEGW, c.rec + SEGW, c.sd, c.su, lcd, lcu, lhd, lhu, Xi, 1.0 / double(Xi), Xd,
+                 Xu, smax, bd, bu);
+  w.dn[c.m] = bd;
+  w.up[c.m] = bu;
+}
+
+// Chunks whose slabs fit in LDS; the others are listed for k_neighbours_wide.
+// 8 waves per SIMD (the LDS of 8 blocks is exactly one CU's): the candidate
+// loops wait on LDS, and twice the waves hide that better than the few
+// spilled registers cost.
+__global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(8, 8))) k_neighbours(Args A) {
+  __shared__ int2 lh[2][STAGE_HITS];
+  __shared__ int lc[2][STAGE_CELLS];
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t n_chunks = w.ctr[C_NCHUNK];
+  const int b = int(xcd_chunk(blockIdx.x, n_chunks));
+  if (b >= n_chunks) return;
+  const Chunk c = chunk_setup(A, b);
+  const bool act = int(threadIdx.x) < c.n_here;
+  if (c.r == 0 || c.r == A.n_rows - 1) {
+    if (act) {
+      w.up[c.m] = -1;
+      w.dn[c.m] = -1;
+    }
+    return;
+  }
+  if (!(c.sd.lds && c.su.lds)) {
+    if (threadIdx.x == 0) w.wide[atomicAdd(reinterpret_cast<unsigned long long *>(&w.ctr[C_NWIDE]), 1ull)] = b;
+    return;
+  }
+  {  // stage both slabs: every load issued before the first LDS store
+    constexpr int KH = STAGE_HITS / NCH, KC = STAGE_CELLS / NCH;
+    int2 vd[KH], vu[KH];
+    int cd[KC], cu[KC];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int i = int(threadIdx.x) + k * NCH;
+      if (i < c.sd.nq) vd[k] = w.syz[c.sd.q0 + i];
+      if (i < c.su.nq) vu[k] = w.syz[c.su.q0 + i];
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int i = int(threadIdx.x) + k * NCH;
+      if (i <= c.sd.nc && c.sd.nq + c.sd.nc > 0) cd[k] = w.cell[c.sd.c0 + i];
+      if (i <= c.su.nc && c.su.nq + c.su.nc > 0) cu[k] = w.cell[c.su.c0 + i];
+    }
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int i = int(threadIdx.x) + k * NCH;
+      if (i < c.sd.nq) lh[0][i] = vd[k];
+      if (i < c.su.nq) lh[1][i] = vu[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int i = int(threadIdx.x) + k * NCH;
+      if (i <= c.sd.nc && c.sd.nq + c.sd.nc > 0) lc[0][i] = cd[k];
+      if (i <= c.su.nc && c.su.nq + c.su.nc > 0) lc[1][i] = cu[k];
+    }
+  }
+  __syncthreads();
+  if (act) chunk_links<true>(A, c, lc[0], lc[1], lh[0], lh[1]);
+}
+
+// The listed chunks, reading the neighbour rows from the workspace.
+__global__ void __launch_bounds__(NCH) k_neighbours_wide(Args A) {
+  const Workspace &w = A.w;
+  if (*A.out.status != TPC_OK) return;
+  const int64_t n_wide = w.ctr[C_NWIDE];
+  for (int64_t j = blockIdx.x; j < n_wide; j += gridDim.x) {
+    const Chunk c = chunk_setup(A, w.wide[j]);
+    if (int(threadIdx.x) < c.n_here) chunk_links<false>(A, c, nullptr, nullptr, nullptr, nullptr);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1541,7 +1602,7 @@ namespace {
 
 const char *const kKernelNames[] = {
     "k_init",        "k_units",      "k_tile_hist",  "k_seg_plan",      "k_cell_base",
-    "k_tile_offsets", "k_tile_scatter", "k_bin_sort",  "k_neighbours",    "k_clean",
+    "k_tile_offsets", "k_tile_scatter", "k_bin_sort",  "k_neighbours",    "k_neighbours_wide", "k_clean",
     "k_scan_blocks", "k_compact_starts", "k_chains", "k_scan_blocks", "k_compact_seeds",
     "k_fit",         "k_select",     "k_scan_blocks", "k_emit"};
 constexpr int kNumKernels = int(sizeof(kKernelNames) / sizeof(kKernelNames[0]));
@@ -1605,7 +1666,9 @@ int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field
     mark();
     hipLaunchKernelGGL(k_bin_sort, dim3(unsigned(w.S)), dim3(TPB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_neighbours, dim3(round8(c->n / NCH + w.S)), dim3(NCH), 0, st, A);
+    hipLaunchKernelGGL(k_neighbours, dim3(round8(w.CH_max)), dim3(NCH), 0, st, A);
+    mark();
+    hipLaunchKernelGGL(k_neighbours_wide, dim3(1024), dim3(NCH), 0, st, A);
     mark();
     hipLaunchKernelGGL(k_clean, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
     mark();
