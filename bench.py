@@ -33,6 +33,11 @@ HBM_PEAK_GBS = 8000.0
 # selector 17: 94 in total).
 B_ALG = {"grid": 24, "neighbours": 14, "cleaner": 12, "constructor": 27, "selector": 17}
 B_ALG_TOTAL = sum(B_ALG.values())
+# VALU issue: 256 CUs x 4 SIMDs; a wave64 VALU instruction holds a 16-lane SIMD 4 cycles
+N_SIMD = 1024
+CLOCK_GHZ = 2.4
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
+               "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY")
 KERNEL_FAMILY = {
     "k_init": None, "k_units": None, "k_tile_hist": "grid", "k_seg_plan": "grid",
     "k_cell_base": "grid", "k_tile_offsets": "grid", "k_tile_scatter": "grid", "k_bin_sort": "grid",
@@ -137,17 +142,25 @@ def summarize_profiles(prof_dir, workload):
     gib_kib = float(1 << 20)
     f_fac = fetch["copy_calib"] / gib_kib
     w_fac = write["copy_calib"] / gib_kib
+    sq_dir = os.path.join(prof_dir, "sq")
+    sq = {}
+    if os.path.isdir(sq_dir):
+        for cn in SQ_COUNTERS:
+            for k, v in _counter_means(sq_dir, cn).items():
+                sq.setdefault(k, {})[cn] = v
     run = json.loads(open(os.path.join(prof_dir, "trace", "bench.json")).read().strip().splitlines()[-1])
     n = run["config"]["clusters"]
     digest = src_digest()
     lines = ["rocprofv3 summary: %s (%d clusters per launch), kernel source digest %s" % (workload, n, digest), ""]
-    for sub in ("trace", "fetch", "write"):
+    for sub in ("trace", "fetch", "write") + (("sq",) if sq else ()):
         lines.append("%-5s: %s" % (sub, open(os.path.join(prof_dir, sub, "cmd.txt")).read().strip()))
-    lines.append("summary: python bench.py --summarize-profiles <dir of the three runs> --workload %s" % workload)
+    lines.append("summary: python bench.py --summarize-profiles <dir of the runs above> --workload %s" % workload)
     lines += ["", "copy kernel (1 GiB read, 1 GiB written): FETCH_SIZE %.6g KiB -> scale %.4f, "
               "WRITE_SIZE %.6g KiB -> scale %.4f" % (fetch["copy_calib"], f_fac, write["copy_calib"], w_fac), "",
-              "%-18s %6s %10s %10s %10s %8s %8s %8s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB",
-                                                       "B/clus", "GB/s", "alg_B/c")]
+              "VALU%: wave64 VALU instructions x 4 cycles / (duration x 1024 SIMDs x " + "%.1f GHz)" % CLOCK_GHZ, "",
+              "%-18s %6s %10s %10s %10s %8s %8s %8s %9s %9s %6s" % (
+                  "kernel", "calls", "avg_us", "fetch_MB", "write_MB", "B/clus", "GB/s", "alg_B/c", "waves",
+                  "valu/wave", "VALU%")]
     traffic = {}
     for k, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["totaldurationns"])):
         if k not in KERNEL_FAMILY:
@@ -156,10 +169,17 @@ def summarize_profiles(prof_dir, workload):
         fb = fetch.get(k, 0.0) * 1024 / f_fac
         wb = write.get(k, 0.0) * 1024 / w_fac
         alg = B_ALG.get(KERNEL_FAMILY[k], 0) if KERNEL_FAMILY[k] else 0
-        lines.append("%-18s %6s %10.1f %10.1f %10.1f %8.2f %8.0f %8s" % (
-            k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / n, (fb + wb) / 1e3 / avg_us, alg or "-"))
+        q = sq.get(k, {})
+        waves = q.get("SQ_WAVES", 0.0)
+        valu = q.get("SQ_INSTS_VALU", 0.0)
+        busy = 100.0 * valu * 4 / (avg_us * 1e-6 * N_SIMD * CLOCK_GHZ * 1e9) if avg_us else 0.0
+        lines.append("%-18s %6s %10.1f %10.1f %10.1f %8.2f %8.0f %8s %9.0f %9.0f %6.1f" % (
+            k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / n, (fb + wb) / 1e3 / avg_us, alg or "-",
+            waves, valu / waves if waves else 0.0, busy))
         traffic[k] = dict(src_digest=digest, bytes_per_launch=fb + wb, fetch_bytes=fb, write_bytes=wb,
                           avg_us=avg_us)
+        if q:
+            traffic[k].update(valu_insts=valu, valu_busy=busy / 100.0)
     txt = os.path.join(out_dir, "%s_kernels.txt" % workload)
     open(txt, "w").write("\n".join(lines) + "\n")
     tj = os.path.join(out_dir, "traffic.json")

@@ -25,6 +25,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "tpc_internal.h"
 #include "tpc_track.h"
 
 namespace {
@@ -163,28 +164,25 @@ struct Request {
   int32_t batch_requests = 0;
   size_t footprint = 0;
   bool solo = false;  // runs in a batch of its own (after its batch failed)
-  // results: the request's slice of its batch's packed results.  Indices in
-  // them are batch-wide; when the batch held other requests they are made
-  // request-local on the first poll (on the caller's thread, under rmu).
+  // results: the request's slice of its batch's packed results, made
+  // request-local on the device before they were copied back
   std::shared_ptr<BatchOut> out;
   int64_t n_tracks = 0, n_track_hits = 0;
-  int64_t cb = 0, ub = 0, t0 = 0, h0 = 0;  // cluster, unit, track and hit bases in the batch
   const int32_t *b_ct = nullptr, *b_unit = nullptr, *b_nhits = nullptr, *b_nfit = nullptr,
                 *b_first = nullptr, *b_hits = nullptr;
   const float *b_params = nullptr, *b_cov = nullptr, *b_xref = nullptr, *b_chi2 = nullptr;
-  std::mutex rmu;
-  bool local = false;  // the request-local index arrays below are filled
-  std::vector<int32_t> cluster_track, unit, first_hit, hits;
 };
 
-struct OutLayout {  // device outputs of a batch, offsets inside its arena block
+struct OutLayout {  // device buffers of a batch, offsets inside its arena block
   size_t off_in_offsets, off_y, off_z, off_row, off_ws, ws_bytes, off_ct, off_params, off_cov,
       off_xref, off_chi2, off_unit, off_nhits, off_nfit, off_first, off_hits, off_counts, off_status,
-      total;
+      off_cbase, off_ubase, off_req, total;
   int64_t cap_tracks, cap_hits;
 };
 
-bool batch_layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t &p, OutLayout *L) {
+// a batch of R requests with n clusters in n_units units in all
+bool batch_layout(int64_t n, int32_t n_units, int32_t R, int32_t n_rows, const tpc_params_t &p,
+                  OutLayout *L) {
   const size_t ws = tpc_workspace_size(n, n_units, n_rows, &p);
   if (ws == 0) return false;
   const int64_t nmin = p.n_min > 0 ? p.n_min : 1;
@@ -215,6 +213,9 @@ bool batch_layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t
   L->off_hits = take(4 * size_t(L->cap_hits));
   L->off_counts = take(4 * 8);
   L->off_status = take(8);
+  L->off_cbase = take(8 * (size_t(R) + 1));
+  L->off_ubase = take(8 * (size_t(R) + 1));
+  L->off_req = take(16 * (size_t(R) + 1));
   L->total = o;
   return true;
 }
@@ -229,7 +230,7 @@ struct Batch {
   OutLayout L{};
   int slot = -1;
   int phase = 0;              // 0: kernels queued, 1: result copies queued
-  void *h_offsets = nullptr;  // pinned [n_units + 1]
+  void *h_offsets = nullptr;  // pinned: unit offsets [n_units + 1], cluster and unit bases [R + 1] each
   std::shared_ptr<BatchOut> out;
   size_t out_bytes = 0;
 };
@@ -308,7 +309,7 @@ bool tpc_server::form_and_launch() {
     if (cfg.max_batch_requests > 0 && int32_t(i) >= cfg.max_batch_requests) break;
     if (i > 0 && cfg.max_batch_clusters > 0 && n + r->n > cfg.max_batch_clusters) break;
     OutLayout L2{};
-    if (!batch_layout(n + r->n, units + r->n_units, cfg.n_rows, cfg.params, &L2)) break;
+    if (!batch_layout(n + r->n, units + r->n_units, int32_t(i + 1), cfg.n_rows, cfg.params, &L2)) break;
     if (L2.total > arena.largest_free()) break;
     n += r->n;
     units += r->n_units;
@@ -352,17 +353,28 @@ void tpc_server::launch(Batch *b) {
   Slot &s = slots[b->slot];
   char *base = d_arena + b->arena_off;
   const OutLayout &L = b->L;
-  // concatenated unit offsets
-  b->h_offsets = pinned.get(8 * (size_t(b->n_units) + 1));
+  // concatenated unit offsets, then the requests' cluster and unit bases
+  const size_t R = b->reqs.size(), nu1 = size_t(b->n_units) + 1;
+  b->h_offsets = pinned.get(8 * (nu1 + 2 * (R + 1)));
   int64_t *ho = static_cast<int64_t *>(b->h_offsets);
   int64_t u = 0;
   ho[0] = 0;
-  for (size_t i = 0; i < b->reqs.size(); ++i) {
+  for (size_t i = 0; i < R; ++i) {
     const Request *r = b->reqs[i];
     for (int32_t k = 1; k <= r->n_units; ++k) ho[++u] = b->cluster_base[i] + r->offsets[k];
   }
-  (void)hipMemcpyAsync(base + L.off_in_offsets, ho, 8 * (size_t(b->n_units) + 1), hipMemcpyHostToDevice,
-                       s.stream);
+  int64_t *hcb = ho + nu1, *hub = hcb + (R + 1);
+  for (size_t i = 0; i < R; ++i) {
+    hcb[i] = b->cluster_base[i];
+    hub[i] = b->unit_base[i];
+  }
+  hcb[R] = b->n;
+  hub[R] = b->n_units;
+  (void)hipMemcpyAsync(base + L.off_in_offsets, ho, 8 * nu1, hipMemcpyHostToDevice, s.stream);
+  if (R > 1) {
+    (void)hipMemcpyAsync(base + L.off_cbase, hcb, 8 * (R + 1), hipMemcpyHostToDevice, s.stream);
+    (void)hipMemcpyAsync(base + L.off_ubase, hub, 8 * (R + 1), hipMemcpyHostToDevice, s.stream);
+  }
   for (size_t i = 0; i < b->reqs.size(); ++i) {
     const Request *r = b->reqs[i];
     if (r->n == 0) continue;
@@ -399,16 +411,22 @@ void tpc_server::launch(Batch *b) {
   o.hits = reinterpret_cast<int32_t *>(base + L.off_hits);
   o.counts = reinterpret_cast<int64_t *>(base + L.off_counts);
   o.status = reinterpret_cast<int32_t *>(base + L.off_status);
-  const int rc = tpc_track_sectors(&c, &g, &f, &cfg.params, &o, base + L.off_ws, L.ws_bytes, s.stream);
+  int rc = tpc_track_sectors(&c, &g, &f, &cfg.params, &o, base + L.off_ws, L.ws_bytes, s.stream);
+  if (rc == TPC_OK && R > 1)  // indices of each request counted from its own first track, hit, cluster
+    rc = tpc_internal::rebase_requests(reinterpret_cast<const int64_t *>(base + L.off_cbase),
+                                       reinterpret_cast<const int64_t *>(base + L.off_ubase), int32_t(R), &o,
+                                       b->n, reinterpret_cast<int64_t *>(base + L.off_req), s.stream);
   b->out = std::make_shared<BatchOut>();
   b->out->pool = &pinned;
-  b->out->h_head = pinned.get(64);
+  // head: counts[4], status, pad[3], then per request its first track and hit
+  b->out->h_head = pinned.get(64 + 16 * (R + 1));
   int64_t *hh = static_cast<int64_t *>(b->out->h_head);
   hh[0] = hh[1] = hh[2] = hh[3] = 0;
   hh[4] = rc;  // launch status if the call failed on the host
   if (rc == TPC_OK) {
     (void)hipMemcpyAsync(hh, base + L.off_counts, 32, hipMemcpyDeviceToHost, s.stream);
     (void)hipMemcpyAsync(hh + 4, base + L.off_status, 4, hipMemcpyDeviceToHost, s.stream);
+    if (R > 1) (void)hipMemcpyAsync(hh + 8, base + L.off_req, 16 * (R + 1), hipMemcpyDeviceToHost, s.stream);
   }
   (void)hipEventRecord(s.ev_kernel, s.stream);
   b->phase = 0;
@@ -459,7 +477,8 @@ bool tpc_server::progress_slot(Slot &s) {
   }
   if (hipEventQuery(s.ev_copy) != hipSuccess) return false;
   // each request's slice of the packed results (tracks are in unit order)
-  const int64_t T = static_cast<const int64_t *>(b->out->h_head)[0];
+  const int64_t *hh = static_cast<const int64_t *>(b->out->h_head);
+  const int64_t T = hh[0], H = hh[1];
   const char *ho = static_cast<const char *>(b->out->h_out);
   const size_t N = size_t(b->n);
   const int32_t *ct = reinterpret_cast<const int32_t *>(ho);
@@ -472,25 +491,23 @@ bool tpc_server::progress_slot(Slot &s) {
   const int32_t *nf = nh + T;
   const int32_t *fh = nf + T;
   const int32_t *hits = fh + T;
-  for (size_t i = 0; i < b->reqs.size(); ++i) {
+  const size_t R = b->reqs.size();
+  for (size_t i = 0; i < R; ++i) {
     Request *r = b->reqs[i];
-    r->cb = b->cluster_base[i];
-    r->ub = b->unit_base[i];
-    r->t0 = std::lower_bound(un, un + T, int32_t(r->ub)) - un;
-    const int64_t t1 = std::lower_bound(un, un + T, int32_t(r->ub + r->n_units)) - un;
-    r->n_tracks = t1 - r->t0;
-    r->h0 = r->n_tracks ? fh[r->t0] : 0;
-    r->n_track_hits = r->n_tracks ? fh[t1 - 1] + nh[t1 - 1] - r->h0 : 0;
-    r->b_ct = ct + r->cb;
-    r->b_params = par + 5 * r->t0;
-    r->b_cov = cov + 15 * r->t0;
-    r->b_xref = xr + r->t0;
-    r->b_chi2 = c2 + r->t0;
-    r->b_unit = un + r->t0;
-    r->b_nhits = nh + r->t0;
-    r->b_nfit = nf + r->t0;
-    r->b_first = fh + r->t0;
-    r->b_hits = hits + r->h0;
+    const int64_t t0 = R > 1 ? hh[8 + 2 * i] : 0, t1 = R > 1 ? hh[8 + 2 * i + 2] : T;
+    const int64_t h0 = R > 1 ? hh[8 + 2 * i + 1] : 0, h1 = R > 1 ? hh[8 + 2 * i + 3] : H;
+    r->n_tracks = t1 - t0;
+    r->n_track_hits = h1 - h0;
+    r->b_ct = ct + b->cluster_base[i];
+    r->b_params = par + 5 * t0;
+    r->b_cov = cov + 15 * t0;
+    r->b_xref = xr + t0;
+    r->b_chi2 = c2 + t0;
+    r->b_unit = un + t0;
+    r->b_nhits = nh + t0;
+    r->b_nfit = nf + t0;
+    r->b_first = fh + t0;
+    r->b_hits = hits + h0;
     r->out = b->out;
     r->status = TPC_OK;
   }
@@ -552,7 +569,7 @@ void tpc_server::loop() {
 extern "C" size_t tpc_server_footprint(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p) {
   if (!p) return 0;
   OutLayout L{};
-  if (!batch_layout(n, n_units, n_rows, *p, &L)) return 0;
+  if (!batch_layout(n, n_units, 1, n_rows, *p, &L)) return 0;
   return L.total;
 }
 
@@ -595,7 +612,7 @@ extern "C" int tpc_server_submit(tpc_server_t *s, const tpc_request_t *r, uint64
     return TPC_E_INVALID;
   }
   OutLayout L{};
-  if (!batch_layout(r->n, r->n_units, s->cfg.n_rows, s->cfg.params, &L) || L.total > s->arena.size()) {
+  if (!batch_layout(r->n, r->n_units, 1, s->cfg.n_rows, s->cfg.params, &L) || L.total > s->arena.size()) {
     std::lock_guard<std::mutex> g(s->mu);
     ++s->st.rejected_nomem;
     return TPC_E_NOMEM;
@@ -675,35 +692,10 @@ extern "C" int tpc_server_poll(tpc_server_t *s, uint64_t ticket, tpc_result_t *r
   res->chi2 = r->b_chi2;
   res->n_hits = r->b_nhits;
   res->n_fit = r->b_nfit;
-  if (r->batch_requests == 1) {  // alone in its batch: the indices are already its own
-    res->cluster_track = r->b_ct;
-    res->unit = r->b_unit;
-    res->first_hit = r->b_first;
-    res->hits = r->b_hits;
-    return TPC_OK;
-  }
-  std::lock_guard<std::mutex> g(r->rmu);
-  if (!r->local) {  // make the batch-wide indices request-local, once
-    const int64_t n = r->n, T = r->n_tracks, H = r->n_track_hits;
-    r->cluster_track.resize(size_t(n));
-    for (int64_t k = 0; k < n; ++k) {
-      const int32_t v = r->b_ct[k];
-      r->cluster_track[size_t(k)] = v >= 0 ? int32_t(v - r->t0) : -1;
-    }
-    r->unit.resize(size_t(T));
-    r->first_hit.resize(size_t(T));
-    for (int64_t k = 0; k < T; ++k) {
-      r->unit[size_t(k)] = int32_t(r->b_unit[k] - r->ub);
-      r->first_hit[size_t(k)] = int32_t(r->b_first[k] - r->h0);
-    }
-    r->hits.resize(size_t(H));
-    for (int64_t k = 0; k < H; ++k) r->hits[size_t(k)] = int32_t(r->b_hits[k] - r->cb);
-    r->local = true;
-  }
-  res->cluster_track = r->cluster_track.data();
-  res->unit = r->unit.data();
-  res->first_hit = r->first_hit.data();
-  res->hits = r->hits.data();
+  res->cluster_track = r->b_ct;
+  res->unit = r->b_unit;
+  res->first_hit = r->b_first;
+  res->hits = r->b_hits;
   return TPC_OK;
 }
 

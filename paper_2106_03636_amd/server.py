@@ -169,8 +169,9 @@ class Server:
             self._keep[t] = keep  # borrowed arrays stay alive until released
         return st, t
 
-    def poll(self, ticket, wait_us=-1):
-        """None while running (wait_us >= 0), else a dict of numpy results."""
+    def poll(self, ticket, wait_us=-1, arrays=True):
+        """None while running (wait_us >= 0), else a dict: status, counts and
+        times, plus copies of the result arrays unless arrays is False."""
         st, r = tpc_server_poll(self._h, ticket, wait_us)
         if st == TPC_E_BUSY:
             return None
@@ -180,7 +181,7 @@ class Server:
         out = dict(status=r.status, n=n, n_tracks=T, n_track_hits=H,
                    t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done,
                    batch_id=r.batch_id, batch_requests=r.batch_requests)
-        if r.status == TPC_OK:
+        if r.status == TPC_OK and arrays:
             out.update(cluster_track=_np(r.cluster_track, n, np.int32),
                        params=_np(r.params, 5 * T, np.float32, (T, 5)),
                        cov=_np(r.cov, 15 * T, np.float32, (T, 15)),

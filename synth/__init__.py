@@ -378,6 +378,93 @@ def event_uneven_chunks(seed: int, n_units: int = 512, n_lo: float = 1e3, n_hi: 
                  tracks, bz, "uneven_chunks")
 
 
+# --- serving: time frames composed from libraries of collisions ----------------
+
+@dataclass
+class CollisionLibrary:
+    """Smeared clusters of collisions generated at t0 = 0, grouped by
+    (collision, sector) and in random order inside each group."""
+    y: np.ndarray
+    z: np.ndarray
+    row: np.ndarray
+    label: np.ndarray
+    offsets: np.ndarray  # [n_collisions * N_SECTORS + 1]
+    n_collisions: int
+
+
+def collision_library(rng, tracks_per_collision, bz: float = 0.5) -> CollisionLibrary:
+    """Min-bias primaries (the soft Pb-Pb spectrum) of each collision."""
+    counts = np.asarray(tracks_per_collision, np.int64)
+    parts = [primaries_pbpb(rng, int(k)) for k in counts]
+    tr = Tracks.concat(parts)
+    coll = np.repeat(np.arange(len(counts)), counts)
+    xs = helix_crossings(tr, bz)
+    n = len(xs["y"])
+    key = (coll[xs["track"]].astype(np.uint64) * np.uint64(N_SECTORS) + xs["sector"].astype(np.uint64))
+    key = (key << np.uint64(32)) | rng.integers(0, 1 << 32, n, dtype=np.uint64)
+    order = np.argsort(key)
+    grp = (key[order] >> np.uint64(32)).astype(np.int64)
+    off = np.zeros(len(counts) * N_SECTORS + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(grp, minlength=len(counts) * N_SECTORS))
+    y = (xs["y"] + rng.normal(0, SIGMA_Y, n))[order].astype(np.float32)
+    z = (xs["z"] + rng.normal(0, SIGMA_Z, n))[order].astype(np.float32)
+    return CollisionLibrary(y, z, xs["row"][order].astype(np.uint16), xs["track"][order].astype(np.int32), off,
+                            len(counts))
+
+
+def compose_timeframe(rng, lib: CollisionLibrary, collisions, slice_us: float, bz: float = 0.5,
+                      name: str = "tf") -> Event:
+    """A continuous-readout frame of the given library collisions at times
+    uniform over the slice (z' = z - side * v_drift * t0), 36 sector units,
+    plus 5% uniform noise per unit.  Labels are library track ids."""
+    collisions = np.asarray(collisions, np.int64)
+    t0 = rng.uniform(0.0, slice_us, len(collisions))
+    ys, zs, rows, labs, offs = [], [], [], [], [0]
+    for u in range(N_SECTORS):
+        side = 1.0 if u < 18 else -1.0
+        a = lib.offsets[collisions * N_SECTORS + u]
+        b = lib.offsets[collisions * N_SECTORS + u + 1]
+        lens = b - a
+        idx = np.concatenate([np.arange(x, y) for x, y in zip(a, b)]) if len(a) else np.zeros(0, np.int64)
+        shift = np.repeat((-side * V_DRIFT * t0).astype(np.float32), lens)
+        nn = int(round(NOISE_FRACTION * len(idx)))
+        r = rng.integers(0, N_ROWS, nn)
+        zlo, zhi = _side_span(u, slice_us)
+        ys += [lib.y[idx], (rng.uniform(-1.0, 1.0, nn) * ROW_X[r] * TAN_HALF).astype(np.float32)]
+        zs += [lib.z[idx] + shift, rng.uniform(zlo, zhi, nn).astype(np.float32)]
+        rows += [lib.row[idx], r.astype(np.uint16)]
+        labs += [lib.label[idx], np.full(nn, -1, np.int32)]
+        offs.append(offs[-1] + len(idx) + nn)
+    empty = Tracks(*[np.zeros(0) for _ in range(8)])
+    return Event(np.concatenate(ys), np.concatenate(zs).astype(np.float32), np.concatenate(rows),
+                 np.asarray(offs, np.int64), np.arange(N_SECTORS, dtype=np.int16), np.concatenate(labs),
+                 empty, bz, name)
+
+
+def serving_pool(seed: int = 5001, n_frames: int = 32, pbpb_fraction: float = 0.8, pbpb_collisions=(10, 50),
+                 pp_collisions: int = 500, pp_tracks_mean: float = 10.0, pp_rate_khz: float = 1000.0,
+                 lib_pbpb: int = 64, lib_pp: int = 2000, bz: float = 0.5):
+    """Frames a request stream draws from: a pbpb_fraction share of Pb-Pb
+    slices of U{pbpb_collisions} min-bias collisions (slice = n / 50 kHz), the
+    rest pp frames of pp_collisions collisions of Poisson(pp_tracks_mean)
+    tracks at pp_rate_khz.  Collisions come from libraries of lib_pbpb Pb-Pb
+    and lib_pp pp collisions, each drawn at its own time, so frames share
+    collisions but no two frames are alike.  Returns a list of Events."""
+    rng = np.random.default_rng(seed)
+    libA = collision_library(rng, pbpb_multiplicity(rng, lib_pbpb), bz)
+    libP = collision_library(rng, rng.poisson(pp_tracks_mean, lib_pp), bz)
+    frames = []
+    for i in range(n_frames):
+        if rng.random() < pbpb_fraction:
+            k = int(rng.integers(pbpb_collisions[0], pbpb_collisions[1] + 1))
+            coll = rng.choice(lib_pbpb, size=k, replace=k > lib_pbpb)
+            frames.append(compose_timeframe(rng, libA, coll, k / 50e3 * 1e6, bz, "pbpb_slice_%d" % k))
+        else:
+            coll = rng.choice(lib_pp, size=pp_collisions, replace=pp_collisions > lib_pp)
+            frames.append(compose_timeframe(rng, libP, coll, pp_collisions / pp_rate_khz * 1e3, bz, "pp_frame"))
+    return frames
+
+
 WORKLOADS = {
     "pp_sector": lambda seed=1001: event_pp_sector(seed),
     "pbpb_central": lambda seed=2001: event_pbpb_central(seed),
