@@ -189,6 +189,177 @@ def summarize_profiles(prof_dir, workload):
     print("\n".join(lines))
 
 
+def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_flight, seed=5001):
+    """Time frames arriving over time (Poisson) at the native server.
+
+    A pool of frames is generated (80% Pb-Pb slices of 10-50 collisions, 20%
+    pp frames) and staged on the device and in pinned host memory; requests
+    draw frames from it uniformly (seeded), so the server does the full work
+    every time.  First the server's capacity is measured in a closed loop,
+    then open loops run at fractions of it.  Latency = arrival to the results
+    being in host memory, on the client's clock.  The plain form (one tracking
+    call per sector unit, then the results copied back) is timed per frame
+    and put through the same arrival sequence (first come, first served)."""
+    import queue
+    import threading
+    import numpy as np
+    import torch
+    import synth
+    import paper_2106_03636_amd as T
+    from paper_2106_03636_amd.runtime import Batch, Tracker
+    from paper_2106_03636_amd.server import Server, TPC_REQ_BORROW_HOST, TPC_REQ_DEVICE
+
+    t = time.time()
+    frames = synth.serving_pool(seed, n_frames=n_frames)
+    sizes = np.array([f.n for f in frames], np.float64)
+    log("bench: serving pool of %d frames, %.1f M clusters mean (%.1f-%.1f M), %.1f s" % (
+        len(frames), sizes.mean() / 1e6, sizes.min() / 1e6, sizes.max() / 1e6, time.time() - t))
+    dpool = [(torch.as_tensor(f.y).to(dev), torch.as_tensor(f.z).to(dev),
+              torch.as_tensor(f.row.view(np.int16)).to(dev)) for f in frames]
+    hpool = [tuple(torch.as_tensor(a).pin_memory().numpy() for a in (f.y, f.z, f.row.view(np.int16)))
+             for f in frames]
+    torch.cuda.synchronize(dev)
+    rng = np.random.default_rng(seed + 1)
+    srv = Server(frames[0].row_x, frames[0].bz, budget_bytes=int(budget_gb * (1 << 30)),
+                 max_in_flight=max_in_flight, queue_depth=64)
+
+    def submit(i, host):
+        f = frames[i]
+        if host:
+            y, z, r = hpool[i]
+            return srv.submit(y, z, r.view(np.uint16), f.unit_offsets, flags=TPC_REQ_BORROW_HOST)
+        return srv.submit(*dpool[i], f.unit_offsets, flags=TPC_REQ_DEVICE)
+
+    def run(ids, gaps, host):
+        """gaps: inter-arrival times (s), or None for a closed loop."""
+        done = [None] * len(ids)
+        q = queue.Queue()
+
+        def collect():
+            for _ in range(len(ids)):
+                k, tk, ta = q.get()
+                r = srv.poll(tk, arrays=False)
+                done[k] = (time.perf_counter() - ta, r)
+                srv.release(tk)
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        ta = t0
+        busy = 0
+        for k, i in enumerate(ids):
+            if gaps is not None:
+                ta += gaps[k]
+                while True:
+                    now = time.perf_counter()
+                    if now >= ta:
+                        break
+                    if ta - now > 2e-3:
+                        time.sleep(ta - now - 1e-3)
+            else:
+                ta = time.perf_counter()
+            while True:
+                st, tk = submit(int(i), host)
+                if st == 0:
+                    break
+                if st != T.TPC_E_BUSY:
+                    raise RuntimeError("submit: %s" % T.tpc_status_string(st))
+                busy += 1
+                time.sleep(2e-4)
+            q.put((k, tk, ta))
+        th.join()
+        wall = time.perf_counter() - t0
+        lat = np.array([d[0] for d in done]) * 1e3
+        bad = [d[1]["status"] for d in done if d[1]["status"] != 0]
+        if bad:
+            raise RuntimeError("served requests failed: %s" % bad[:4])
+        ncl = float(sizes[ids].sum())
+        batches = np.array([d[1]["batch_requests"] for d in done], np.float64)
+        return dict(requests=len(ids), clusters=ncl, wall_s=wall, throughput=ncl / wall,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    mean_batch_requests=float(batches.mean()), busy_retries=busy)
+
+    def arrivals(n, load, cap):
+        ids = rng.integers(0, len(frames), n)
+        rate = load * cap / sizes.mean()  # frames per second
+        return ids, rng.exponential(1.0 / rate, n)
+
+    # warm up, then the closed-loop capacity
+    run(rng.integers(0, len(frames), 8), None, False)
+    capr = run(rng.integers(0, len(frames), max(32, n_sweep // 2)), None, False)
+    cap = capr["throughput"]
+    log("bench: served capacity %.3g clusters/s (mean %.2f requests per batch)"
+        % (cap, capr["mean_batch_requests"]))
+    out = dict(pool=dict(frames=len(frames), mean_clusters=float(sizes.mean()), min_clusters=float(sizes.min()),
+                         max_clusters=float(sizes.max()), pbpb_share=float(np.mean(
+                             [f.name.startswith("pbpb") for f in frames])), seed=seed),
+               budget_gb=budget_gb, max_in_flight=max_in_flight,
+               capacity=dict(clusters_per_s=cap, frames_per_s=cap / sizes.mean(),
+                             mean_batch_requests=capr["mean_batch_requests"]))
+    res = []
+    main_ids = main_gaps = None
+    for j, load in enumerate(loads):
+        n = n_main if j == 0 else n_sweep
+        ids, gaps = arrivals(n, load, cap)
+        if j == 0:
+            main_ids, main_gaps = ids, gaps
+        r = run(ids, gaps, False)
+        r.update(load=load, offered=load * cap)
+        log("bench: served load %.1f: %.3g clusters/s, p50 %.1f ms, p99 %.1f ms, %.2f requests per batch"
+            % (load, r["throughput"], r["p50_ms"], r["p99_ms"], r["mean_batch_requests"]))
+        res.append(r)
+    out["device_inputs"] = res
+    ids, gaps = arrivals(n_sweep, loads[0], cap)
+    r = run(ids, gaps, True)
+    r.update(load=loads[0], offered=loads[0] * cap)
+    log("bench: served from host memory, load %.1f: p50 %.1f ms, p99 %.1f ms" % (loads[0], r["p50_ms"], r["p99_ms"]))
+    out["host_inputs"] = [r]
+    srv.close()
+
+    # the plain form: one call per sector unit, results copied back
+    per_unit = max(int(np.diff(f.unit_offsets).max()) for f in frames)
+    tr = Tracker(per_unit, 1, len(frames[0].row_x), device=dev)
+    units = [[Batch.from_device(dpool[i][0][a:b], dpool[i][1][a:b], dpool[i][2][a:b], [0, b - a], f.row_x, f.bz)
+              for a, b in zip(f.unit_offsets[:-1], f.unit_offsets[1:])] for i, f in enumerate(frames)]
+    svc = np.zeros(len(frames))
+    for rep in range(2):
+        for i in range(len(frames)):
+            torch.cuda.synchronize(dev)
+            t1 = time.perf_counter()
+            for b in units[i]:
+                tr.launch(b)
+                r = tr.result()
+                r["cluster_track"].cpu(), r["hits"].cpu(), r["params"].cpu()
+            svc[i] = time.perf_counter() - t1
+    plain_cap = float(sizes.sum() / svc.sum())
+
+    def fifo(ids, gaps):
+        t_arr = np.cumsum(gaps)
+        end = 0.0
+        lat = np.empty(len(ids))
+        for k, i in enumerate(ids):
+            start = max(t_arr[k], end)
+            end = start + svc[i]
+            lat[k] = end - t_arr[k]
+        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    throughput=float(sizes[ids].sum() / (end - 0.0)))
+    plain = dict(capacity_clusters_per_s=plain_cap, calls_per_frame=len(frames[0].unit_offsets) - 1)
+    plain["at_served_main_load"] = fifo(main_ids, main_gaps)
+    plain["at_served_main_load"]["stable"] = bool(loads[0] * cap < plain_cap)
+    # both forms at a load the plain form sustains
+    srv = Server(frames[0].row_x, frames[0].bz, budget_bytes=int(budget_gb * (1 << 30)),
+                 max_in_flight=max_in_flight, queue_depth=64)
+    ids, gaps = arrivals(max(32, n_sweep // 2), 0.7, plain_cap)
+    low = run(ids, gaps, False)
+    srv.close()
+    plain["at_0.7_of_plain_capacity"] = dict(offered=0.7 * plain_cap, plain=fifo(ids, gaps),
+                                             served=dict(p50_ms=low["p50_ms"], p99_ms=low["p99_ms"],
+                                                         throughput=low["throughput"]))
+    log("bench: plain per-sector capacity %.3g clusters/s; at 0.7 of it: plain p99 %.1f ms, served p99 %.1f ms"
+        % (plain_cap, plain["at_0.7_of_plain_capacity"]["plain"]["p99_ms"], low["p99_ms"]))
+    out["plain_per_sector"] = plain
+    return out
+
+
 def cpu_baseline(ev, n_units_sample, values):
     """The CPU oracle, as it stands, on the first n_units_sample units."""
     import oracle
@@ -212,6 +383,11 @@ def main():
     ap.add_argument("--workload", default="pbpb_timeframe_50")
     ap.add_argument("--cpu-units", type=int, default=-1,
                     help="units in the CPU-oracle sample (-1: all, 0: skip)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-frames", type=int, default=32, help="frames in the serving pool")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests at the main load")
+    ap.add_argument("--serve-sweep", type=int, default=200, help="requests at each other load")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="the server's device memory")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 runs of this script and exit")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
@@ -334,6 +510,12 @@ def main():
         out["plain_per_sector"] = dict(value=batch.n / dtp, unit="clusters/s", ms_per_step=dtp * 1e3,
                                        calls_per_step=len(subs))
         del trp
+
+    if not args.no_serve:
+        del tr
+        torch.cuda.empty_cache()
+        out["serving"] = serving_bench(dev, args.serve_frames, args.serve_requests, args.serve_sweep,
+                                       (0.7, 0.3, 0.5, 0.9), args.serve_budget_gb, 2)
 
     if args.cpu_units != 0:
         from paper_2106_03636_amd.params import DEFAULT_PARAMS

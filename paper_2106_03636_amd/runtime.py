@@ -48,6 +48,21 @@ class Batch:
     def from_event(ev, device="cuda"):
         return Batch(ev.y, ev.z, ev.row, ev.unit_offsets, ev.row_x, ev.bz, device)
 
+    @staticmethod
+    def from_device(y, z, row, unit_offsets, row_x, bz):
+        """A batch over device tensors that are already resident (no copies of
+        y, z, row: float32, float32, int16 holding the uint16 rows)."""
+        b = Batch.__new__(Batch)
+        dev = y.device
+        b.y, b.z, b.row = y, z, row
+        b.unit_offsets = torch.as_tensor(np.ascontiguousarray(unit_offsets, np.int64)).to(dev)
+        b.row_x = torch.as_tensor(np.ascontiguousarray(row_x, np.float32)).to(dev)
+        b.n = int(y.numel())
+        b.n_units = int(len(unit_offsets) - 1)
+        b.n_rows = int(len(row_x))
+        b.bz = float(bz)
+        return b
+
     def clusters_struct(self):
         c = tpc_clusters_t()
         c.n = self.n
