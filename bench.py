@@ -360,6 +360,75 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
     return out
 
 
+def batched_bench(dev, reps):
+    """512 sector chunks of uneven occupancy (1e3-1e5 clusters, pp and Pb-Pb
+    generators): one call over all of them, eager with the default grid shape
+    and replayed from a HIP graph with the autotuned shape, against the plain
+    form of one call per chunk.  Every form gives the same tracks."""
+    import numpy as np
+    import torch
+    from paper_2106_03636_amd.autotune import tune
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS
+    from paper_2106_03636_amd.runtime import Batch, GraphRunner, Tracker
+
+    ev = make_workload("uneven_chunks_512")
+    batch = Batch.from_event(ev, dev)
+    sizes = np.diff(ev.unit_offsets)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize(dev)
+        return e0.elapsed_time(e1) / k
+
+    tr = Tracker(batch.n, batch.n_units, batch.n_rows, device=dev)
+    eager_ms = timed(lambda: tr.launch(batch), reps)
+    ref = tr.result()
+    n_tracks = ref["n_tracks"]
+    del tr
+    best, table = tune(batch, reps=3, log=None)
+    shape = {k: best[k] for k in ("bin_y_q", "bin_occ", "bin_zmin_q")}
+    trt = Tracker(batch.n, batch.n_units, batch.n_rows, best, device=dev)
+    g = GraphRunner(trt, batch)
+    graph_ms = timed(g.replay, reps)
+    res = g.result()
+    if res["n_tracks"] != n_tracks:
+        raise RuntimeError("tuned graph form found %d tracks, eager %d" % (res["n_tracks"], n_tracks))
+    del g, trt
+    subs = [Batch.from_device(batch.y[a:b], batch.z[a:b], batch.row[a:b], [0, b - a], ev.row_x, ev.bz)
+            for a, b in zip(ev.unit_offsets[:-1], ev.unit_offsets[1:])]
+    trp = Tracker(int(sizes.max()), 1, batch.n_rows, device=dev)
+
+    def plain():
+        for sb in subs:
+            trp.launch(sb)
+    plain_ms = timed(plain, max(1, reps // 4))
+    plain_tracks = 0
+    for sb in subs:  # same tracks as the single call (units are independent)
+        trp.launch(sb)
+        plain_tracks += trp.result()["n_tracks"]
+    if plain_tracks != n_tracks:
+        raise RuntimeError("per-chunk calls found %d tracks, one call %d" % (plain_tracks, n_tracks))
+    del trp
+    n = float(batch.n)
+    out = dict(workload="uneven_chunks_512", clusters=int(batch.n), units=int(batch.n_units),
+               unit_clusters=dict(min=int(sizes.min()), median=int(np.median(sizes)), max=int(sizes.max())),
+               tracks=int(n_tracks),
+               graph_tuned=dict(value=n / graph_ms * 1e3, ms=graph_ms, grid_shape=shape),
+               eager_default=dict(value=n / eager_ms * 1e3, ms=eager_ms,
+                                  grid_shape={k: DEFAULT_PARAMS[k] for k in shape}),
+               plain_per_chunk=dict(value=n / plain_ms * 1e3, ms=plain_ms, calls=int(batch.n_units)),
+               autotune=[dict(r) for r in table], unit="clusters/s")
+    log("bench: 512 chunks: graph+tuned %.3g, eager default %.3g, plain per chunk %.3g clusters/s"
+        % (out["graph_tuned"]["value"], out["eager_default"]["value"], out["plain_per_chunk"]["value"]))
+    return out
+
+
 def cpu_baseline(ev, n_units_sample, values):
     """The CPU oracle, as it stands, on the first n_units_sample units."""
     import oracle
@@ -383,7 +452,11 @@ def main():
     ap.add_argument("--workload", default="pbpb_timeframe_50")
     ap.add_argument("--cpu-units", type=int, default=-1,
                     help="units in the CPU-oracle sample (-1: all, 0: skip)")
+    ap.add_argument("--no-tune", action="store_true", help="default grid shape instead of the autotuned one")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune the grid shape for this workload and store it in the autotune cache first")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-chunk batched measurement")
     ap.add_argument("--serve-frames", type=int, default=32, help="frames in the serving pool")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests at the main load")
     ap.add_argument("--serve-sweep", type=int, default=200, help="requests at each other load")
@@ -410,7 +483,25 @@ def main():
     ev = make_workload(args.workload)
     dev = torch.device("cuda:0")
     batch = Batch.from_event(ev, dev)
-    tr = Tracker(batch.n, batch.n_units, batch.n_rows, device=dev)
+    # grid shape (speed only; the tuner checks that every shape gives the same
+    # tracks): the autotuner's cached choice for this batch class
+    from paper_2106_03636_amd import autotune
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS
+    params = dict(DEFAULT_PARAMS)
+    shape_source = "default"
+    if not args.no_tune:
+        if args.retune:
+            t = time.time()
+            autotune.tuned_params(batch, force=True, log=None)
+            log("bench: tuned the grid shape in %.1f s" % (time.time() - t))
+            torch.cuda.empty_cache()
+        key = autotune.cache_key(batch)
+        if key in autotune.load_cache():
+            params = autotune.tuned_params(batch)
+            shape_source = "autotune cache " + key
+    shape = {k: params[k] for k in autotune.SPACE}
+    log("bench: grid shape %s (%s)" % (shape, shape_source))
+    tr = Tracker(batch.n, batch.n_units, batch.n_rows, params, device=dev)
     log("bench: workspace %.2f GB" % (tr.ws_bytes / 1e9))
     stream = torch.cuda.current_stream(dev)
 
@@ -481,7 +572,8 @@ def main():
         ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f32+i64", data="synthetic",
         config=dict(workload=args.workload, clusters=batch.n, units=batch.n_units, rows=batch.n_rows,
-                    bz_tesla=batch.bz, collisions=50 if args.workload.startswith("pbpb_timeframe") else None),
+                    bz_tesla=batch.bz, collisions=50 if args.workload.startswith("pbpb_timeframe") else None,
+                    grid_shape=dict(shape, source=shape_source)),
         p50_ms=float(np.percentile(step_ms, 50)), p99_ms=float(np.percentile(step_ms, 99)),
         roofline=dict(bound="hbm", kernel=dom_name, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
@@ -496,7 +588,7 @@ def main():
     # the plain form: one call per sector unit, same stream, same work
     if not args.no_plain:
         subs = [Batch.from_event(ev.subset_units([u]), dev) for u in range(ev.n_units)]
-        trp = Tracker(max(s.n for s in subs), 1, batch.n_rows, device=dev)
+        trp = Tracker(max(s.n for s in subs), 1, batch.n_rows, params, device=dev)
         for s in subs[:2]:
             trp.launch(s)
         torch.cuda.synchronize(dev)
@@ -511,9 +603,12 @@ def main():
                                        calls_per_step=len(subs))
         del trp
 
-    if not args.no_serve:
-        del tr
+    del tr
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_bench(dev, max(4, args.steps))
         torch.cuda.empty_cache()
+    if not args.no_serve:
         out["serving"] = serving_bench(dev, args.serve_frames, args.serve_requests, args.serve_sweep,
                                        (0.7, 0.3, 0.5, 0.9), args.serve_budget_gb, 2)
 

@@ -22,8 +22,7 @@ import torch
 from .params import DEFAULT_PARAMS
 from .runtime import Batch, Tracker
 
-CACHE_PATH = os.environ.get("TPC_AUTOTUNE_CACHE",
-                            os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json"))
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 SPACE = dict(bin_y_q=(384, 768, 1536), bin_occ=(1, 2, 4), bin_zmin_q=(128, 512))
 
@@ -95,7 +94,8 @@ def tune(batch: Batch, base=None, space=None, reps=3, verify=True, log=None):
     return best[0], table
 
 
-def load_cache(path=CACHE_PATH):
+def load_cache(path=None):
+    path = path or os.environ.get("TPC_AUTOTUNE_CACHE", CACHE_PATH)
     if os.path.exists(path):
         try:
             return json.load(open(path))
@@ -104,14 +104,17 @@ def load_cache(path=CACHE_PATH):
     return {}
 
 
-def tuned_params(batch: Batch, base=None, path=CACHE_PATH, tune_if_missing=False, log=None):
-    """Cached grid shape for this batch class, merged into `base`."""
+def tuned_params(batch: Batch, base=None, path=None, tune_if_missing=False, force=False, log=None):
+    """Cached grid shape for this batch class, merged into `base`; tuned (and
+    cached) when missing and tune_if_missing, or always when force.  The
+    cache file is TPC_AUTOTUNE_CACHE if set, else the one next to this file."""
+    path = path or os.environ.get("TPC_AUTOTUNE_CACHE", CACHE_PATH)
     base = dict(DEFAULT_PARAMS if base is None else base)
     cache = load_cache(path)
     key = cache_key(batch)
-    if key in cache:
+    if key in cache and not force:
         return dict(base, **{k: cache[key][k] for k in SPACE})
-    if not tune_if_missing:
+    if not (tune_if_missing or force):
         return base
     best, table = tune(batch, base, log=log)
     cache[key] = dict({k: best[k] for k in SPACE}, ms=min(r["ms"] for r in table), tuned_at=time.time())

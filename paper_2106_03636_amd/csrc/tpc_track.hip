@@ -529,8 +529,7 @@ __device__ __forceinline__ int bin_of(const int32_t *rec, int Y, int Z) {
 // order and one wave ranks them chunk by chunk with ballots), and the cell
 // table.  Fast path: bins and per-hit ranks in LDS, data moved by all threads
 // afterwards; rows too large for LDS take the same steps with global cursors.
-constexpr int BIN_LDS = 4096;   // bin counters in LDS
-constexpr int HIT_LDS = 8192;   // per-hit slots in LDS
+constexpr int BIN_POOL = 12288;  // LDS ints shared by the bin counters and the per-hit slots
 
 __device__ __forceinline__ void scan_bins(int *hist, int nbins, int32_t *cell_out, int start, int *tmp) {
   const int per = (nbins + TPB - 1) / TPB;
@@ -548,8 +547,7 @@ __device__ __forceinline__ void scan_bins(int *hist, int nbins, int32_t *cell_ou
 }
 
 __global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
-  __shared__ int hist_lds[BIN_LDS];
-  __shared__ int slot[HIT_LDS];
+  __shared__ int pool[BIN_POOL];
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
@@ -560,7 +558,8 @@ __global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
   int nbits = 1;
   while ((1 << nbits) < nbins) ++nbits;
   const int lane = __lane_id();
-  if (nbins <= BIN_LDS && count <= HIT_LDS) {
+  if (nbins + count <= BIN_POOL) {
+    int *hist_lds = pool, *slot = pool + nbins;
     for (int b = threadIdx.x; b < nbins; b += TPB) hist_lds[b] = 0;
     __syncthreads();
     for (int p = threadIdx.x; p < count; p += TPB) {
@@ -671,9 +670,11 @@ __device__ __forceinline__ Win window_cells(const int32_t *rec, int64_t ylo, int
 }
 
 // A z-slab of a neighbour row staged in LDS: hits at positions [q0, q0 + nq)
-// and the cell table entries [c0, c0 + nc].
-constexpr int STAGE_HITS = 1024;
-constexpr int STAGE_CELLS = 512;
+// (int2, first) and the cell table entries [c0, c0 + nc] (after them), in one
+// pool of STAGE_INTS ints per row.
+constexpr int STAGE_INTS = 2560;
+constexpr int STAGE_KH = 5;   // hit loads per thread (nq <= 1280)
+constexpr int STAGE_KC = 10;  // cell loads per thread (nc < 2560)
 
 struct Slab {
   int q0, nq, c0, nc;
@@ -682,7 +683,7 @@ struct Slab {
 
 template <bool LDS>
 __device__ __forceinline__ int cell_at(const Workspace &w, const Slab &sl, const int *lc, int c) {
-  return LDS ? lc[c - sl.c0] : w.cell[c];
+  return LDS ? lc[2 * sl.nq + c - sl.c0] : w.cell[c];
 }
 template <bool LDS>
 __device__ __forceinline__ int2 hit_at(const Workspace &w, const Slab &sl, const int2 *lh, int q) {
@@ -818,7 +819,7 @@ __device__ __forceinline__ Slab make_slab(const Workspace &w, const int32_t *rec
   sl.nc = (iz1 - iz0 + 1) * ny;  // entries c0 .. c0 + nc (inclusive end)
   sl.q0 = w.cell[sl.c0];
   sl.nq = w.cell[sl.c0 + sl.nc] - sl.q0;
-  sl.lds = sl.nq <= STAGE_HITS && sl.nc + 1 <= STAGE_CELLS;
+  sl.lds = 2 * sl.nq + sl.nc + 1 <= STAGE_INTS;
   return sl;
 }
 
@@ -878,8 +879,7 @@ __device__ __forceinline__ void chunk_links(const Args &A, const Chunk &c, const
 // loops wait on LDS, and twice the waves hide that better than the few
 // spilled registers cost.
 __global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(8, 8))) k_neighbours(Args A) {
-  __shared__ int2 lh[2][STAGE_HITS];
-  __shared__ int lc[2][STAGE_CELLS];
+  __shared__ __align__(16) int pool[2][STAGE_INTS];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int64_t n_chunks = w.ctr[C_NCHUNK];
@@ -898,37 +898,40 @@ __global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(8, 8))
     if (threadIdx.x == 0) w.wide[atomicAdd(reinterpret_cast<unsigned long long *>(&w.ctr[C_NWIDE]), 1ull)] = b;
     return;
   }
-  {  // stage both slabs: every load issued before the first LDS store
-    constexpr int KH = STAGE_HITS / NCH, KC = STAGE_CELLS / NCH;
-    int2 vd[KH], vu[KH];
-    int cd[KC], cu[KC];
+  {  // stage both slabs: hits, then cells, each with all loads issued before the stores
+    int2 *lhd = reinterpret_cast<int2 *>(pool[0]), *lhu = reinterpret_cast<int2 *>(pool[1]);
+    int2 vd[STAGE_KH], vu[STAGE_KH];
 #pragma unroll
-    for (int k = 0; k < KH; ++k) {
+    for (int k = 0; k < STAGE_KH; ++k) {
       const int i = int(threadIdx.x) + k * NCH;
       if (i < c.sd.nq) vd[k] = w.syz[c.sd.q0 + i];
       if (i < c.su.nq) vu[k] = w.syz[c.su.q0 + i];
     }
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
+    for (int k = 0; k < STAGE_KH; ++k) {
       const int i = int(threadIdx.x) + k * NCH;
-      if (i <= c.sd.nc && c.sd.nq + c.sd.nc > 0) cd[k] = w.cell[c.sd.c0 + i];
-      if (i <= c.su.nc && c.su.nq + c.su.nc > 0) cu[k] = w.cell[c.su.c0 + i];
+      if (i < c.sd.nq) lhd[i] = vd[k];
+      if (i < c.su.nq) lhu[i] = vu[k];
+    }
+    int cd[STAGE_KC], cu[STAGE_KC];
+    const bool cdo = c.sd.nq + c.sd.nc > 0, cuo = c.su.nq + c.su.nc > 0;
+#pragma unroll
+    for (int k = 0; k < STAGE_KC; ++k) {
+      const int i = int(threadIdx.x) + k * NCH;
+      if (cdo && i <= c.sd.nc) cd[k] = w.cell[c.sd.c0 + i];
+      if (cuo && i <= c.su.nc) cu[k] = w.cell[c.su.c0 + i];
     }
 #pragma unroll
-    for (int k = 0; k < KH; ++k) {
+    for (int k = 0; k < STAGE_KC; ++k) {
       const int i = int(threadIdx.x) + k * NCH;
-      if (i < c.sd.nq) lh[0][i] = vd[k];
-      if (i < c.su.nq) lh[1][i] = vu[k];
-    }
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int i = int(threadIdx.x) + k * NCH;
-      if (i <= c.sd.nc && c.sd.nq + c.sd.nc > 0) lc[0][i] = cd[k];
-      if (i <= c.su.nc && c.su.nq + c.su.nc > 0) lc[1][i] = cu[k];
+      if (cdo && i <= c.sd.nc) pool[0][2 * c.sd.nq + i] = cd[k];
+      if (cuo && i <= c.su.nc) pool[1][2 * c.su.nq + i] = cu[k];
     }
   }
   __syncthreads();
-  if (act) chunk_links<true>(A, c, lc[0], lc[1], lh[0], lh[1]);
+  if (act)
+    chunk_links<true>(A, c, pool[0], pool[1], reinterpret_cast<const int2 *>(pool[0]),
+                      reinterpret_cast<const int2 *>(pool[1]));
 }
 
 // The listed chunks, reading the neighbour rows from the workspace.
