@@ -189,7 +189,7 @@ def summarize_profiles(prof_dir, workload):
     print("\n".join(lines))
 
 
-def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_flight, seed=5001):
+def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_flight, params, seed=5001):
     """Time frames arriving over time (Poisson) at the native server.
 
     A pool of frames is generated (80% Pb-Pb slices of 10-50 collisions, 20%
@@ -221,7 +221,7 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
     torch.cuda.synchronize(dev)
     rng = np.random.default_rng(seed + 1)
     srv = Server(frames[0].row_x, frames[0].bz, budget_bytes=int(budget_gb * (1 << 30)),
-                 max_in_flight=max_in_flight, queue_depth=64)
+                 max_in_flight=max_in_flight, queue_depth=64, params=params)
 
     def submit(i, host):
         f = frames[i]
@@ -293,6 +293,7 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
                          max_clusters=float(sizes.max()), pbpb_share=float(np.mean(
                              [f.name.startswith("pbpb") for f in frames])), seed=seed),
                budget_gb=budget_gb, max_in_flight=max_in_flight,
+               grid_shape={k: params[k] for k in ("bin_y_q", "bin_occ", "bin_zmin_q")},
                capacity=dict(clusters_per_s=cap, frames_per_s=cap / sizes.mean(),
                              mean_batch_requests=capr["mean_batch_requests"]))
     res = []
@@ -317,7 +318,7 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
 
     # the plain form: one call per sector unit, results copied back
     per_unit = max(int(np.diff(f.unit_offsets).max()) for f in frames)
-    tr = Tracker(per_unit, 1, len(frames[0].row_x), device=dev)
+    tr = Tracker(per_unit, 1, len(frames[0].row_x), params, device=dev)
     units = [[Batch.from_device(dpool[i][0][a:b], dpool[i][1][a:b], dpool[i][2][a:b], [0, b - a], f.row_x, f.bz)
               for a, b in zip(f.unit_offsets[:-1], f.unit_offsets[1:])] for i, f in enumerate(frames)]
     svc = np.zeros(len(frames))
@@ -347,7 +348,7 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
     plain["at_served_main_load"]["stable"] = bool(loads[0] * cap < plain_cap)
     # both forms at a load the plain form sustains
     srv = Server(frames[0].row_x, frames[0].bz, budget_bytes=int(budget_gb * (1 << 30)),
-                 max_in_flight=max_in_flight, queue_depth=64)
+                 max_in_flight=max_in_flight, queue_depth=64, params=params)
     ids, gaps = arrivals(max(32, n_sweep // 2), 0.7, plain_cap)
     low = run(ids, gaps, False)
     srv.close()
@@ -429,8 +430,10 @@ def batched_bench(dev, reps):
     return out
 
 
-def cpu_baseline(ev, n_units_sample, values):
-    """The CPU oracle, as it stands, on the first n_units_sample units."""
+def cpu_baseline(ev, n_units_sample, values, single_core_units=2):
+    """The CPU oracle, as it stands, on the first n_units_sample units with all
+    its threads, and on single_core_units units with one thread (the paper
+    compares against one CPU core, section 3.2)."""
     import oracle
     sub = ev.subset_units(list(range(n_units_sample)))
     oracle.build()
@@ -438,10 +441,20 @@ def cpu_baseline(ev, n_units_sample, values):
     t = time.time()
     r = oracle.run_event(sub, values)
     dt = time.time() - t
-    return dict(value=sub.n / dt, unit="clusters/s", cores=threads, kind="oracle",
-                sample="%d of %d sector units of the same workload (%d clusters), one call, %.1f s"
-                       % (n_units_sample, ev.n_units, sub.n, dt),
-                seconds=dt, n_tracks=int(r["n_tracks"]))
+    out = dict(value=sub.n / dt, unit="clusters/s", cores=threads, kind="oracle",
+               sample="%d of %d sector units of the same workload (%d clusters), one call, %.1f s"
+                      % (n_units_sample, ev.n_units, sub.n, dt),
+               seconds=dt, n_tracks=int(r["n_tracks"]))
+    if single_core_units > 0:
+        one = ev.subset_units(list(range(single_core_units)))
+        oracle.set_threads(1)
+        t = time.time()
+        oracle.run_event(one, values)
+        d1 = time.time() - t
+        oracle.set_threads(threads)
+        out["single_core"] = dict(value=one.n / d1, unit="clusters/s", cores=1,
+                                  sample="%d sector units (%d clusters), %.1f s" % (single_core_units, one.n, d1))
+    return out
 
 
 def main():
@@ -610,7 +623,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = serving_bench(dev, args.serve_frames, args.serve_requests, args.serve_sweep,
-                                       (0.7, 0.3, 0.5, 0.9), args.serve_budget_gb, 2)
+                                       (0.7, 0.3, 0.5, 0.9), args.serve_budget_gb, 2, params)
 
     if args.cpu_units != 0:
         from paper_2106_03636_amd.params import DEFAULT_PARAMS

@@ -95,6 +95,7 @@ def _load():
         lib.orc_kf_update.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, vp]
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -220,6 +221,11 @@ def kf_update(p, cov15, my, mz, sy, sz):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of later calls (timing only: results do not depend on it)."""
+    _load().orc_set_threads(int(n))
 
 
 def unpack_cov(c15):
