@@ -41,6 +41,7 @@ enum { C_K = 0, C_CELLS = 1, C_TRACKS = 2, C_HITS = 3, C_TILES = 4, C_NCHUNK = 5
 struct Workspace {
   int64_t *ctr;
   int32_t *seg, *seg_cnt, *seg_zmin, *seg_zmax, *seg_nbins;
+  float2 *seg_inv;  // per (unit,row): 1/by, 1/bz
   int32_t *unit_tiles, *tile_hist;
   int32_t *rs_idx;
   int2 *rs_yz;
@@ -107,6 +108,7 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.seg_zmin = (int32_t *)take(4 * S);
   L.seg_zmax = (int32_t *)take(4 * S);
   L.seg_nbins = (int32_t *)take(4 * S);
+  L.seg_inv = (float2 *)take(8 * S);
   L.unit_tiles = (int32_t *)take(4 * (size_t(n_units) + 1));
   L.tile_hist = (int32_t *)take(4 * size_t(n_rows) * size_t(L.T_max));
   L.rs_idx = (int32_t *)take(4 * N);
@@ -401,6 +403,7 @@ __global__ void __launch_bounds__(256) k_seg_plan(Args A) {
   rec[10] = 0;
   rec[11] = 0;
   w.seg_nbins[s] = int32_t(ny * nz);
+  w.seg_inv[s] = make_float2(1.f / float(by), 1.f / float(bz));
 }
 
 // step 2c: first cell of every (unit,row), and the end sentinel
@@ -649,8 +652,8 @@ struct Win {
   bool empty;
 };
 
-__device__ __forceinline__ Win window_cells(const int32_t *rec, int64_t ylo, int64_t yhi, int64_t zlo,
-                                            int64_t zhi) {
+__device__ __forceinline__ Win window_cells(const int32_t *rec, float2 inv, int64_t ylo, int64_t yhi,
+                                            int64_t zlo, int64_t zhi) {
   Win c;
   const int count = rec[S_COUNT];
   const int64_t zmin = rec[S_ZMIN], zmax = rec[S_ZMAX];
@@ -659,11 +662,10 @@ __device__ __forceinline__ Win window_cells(const int32_t *rec, int64_t ylo, int
   const int64_t H = rec[S_H], span = zmax - zmin;
   const int by = rec[S_BY], bz = rec[S_BZ];
   auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
-  const float iby = 1.f / float(by), ibz = 1.f / float(bz);
-  c.iy0 = div_small(int(cl(ylo + H, 0, 2 * H)), by, iby);
-  c.iy1 = div_small(int(cl(yhi + H, 0, 2 * H)), by, iby);
-  c.iz0 = div_small(int(cl(zlo - zmin, 0, span)), bz, ibz);
-  c.iz1 = div_small(int(cl(zhi - zmin, 0, span)), bz, ibz);
+  c.iy0 = div_small(int(cl(ylo + H, 0, 2 * H)), by, inv.x);
+  c.iy1 = div_small(int(cl(yhi + H, 0, 2 * H)), by, inv.x);
+  c.iz0 = div_small(int(cl(zlo - zmin, 0, span)), bz, inv.y);
+  c.iz1 = div_small(int(cl(zhi - zmin, 0, span)), bz, inv.y);
   c.ny = rec[S_NY];
   c.cbase = rec[S_CBASE];
   return c;
@@ -706,15 +708,19 @@ struct Cand {
   Win c;
 };
 
-__device__ __forceinline__ Cand cand_window(const int32_t *rec, int64_t Ym, int64_t Zm, int64_t Xi,
+// The window is ceil(Y_m X_j / X_i) - W <= Y_n <= floor(Y_m X_j / X_i) + W
+// (W is an integer, so it moves out of the floor and the ceiling).
+__device__ __forceinline__ Cand cand_window(const int32_t *rec, float2 inv, int64_t Ym, int64_t Zm, int64_t Xi,
                                             double inv_xi, int64_t Xj, int64_t WY, int64_t WZ) {
   Cand k;
-  const int64_t lo = -floor_div_exact(-(Ym * Xj - WY * Xi), Xi, inv_xi);  // ceil
-  const int64_t hi = floor_div_exact(Ym * Xj + WY * Xi, Xi, inv_xi);
+  const int64_t a = Ym * Xj;
+  const int64_t q = floor_div_exact(a, Xi, inv_xi);
+  const int64_t lo = q + (q * Xi != a ? 1 : 0) - WY;
+  const int64_t hi = q + WY;
   // |Y| <= 2^21 for every cluster: clamping keeps the compares exact in int32
   k.ylo = int(lo < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (lo > (int64_t(1) << 30) ? (int64_t(1) << 30) : lo));
   k.yhi = int(hi < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (hi > (int64_t(1) << 30) ? (int64_t(1) << 30) : hi));
-  k.c = window_cells(rec, lo, hi, Zm - WZ, Zm + WZ);
+  k.c = window_cells(rec, inv, lo, hi, Zm - WZ, Zm + WZ);
   return k;
 }
 
@@ -723,6 +729,7 @@ constexpr int MAXU = 4;  // row-above candidates kept in registers
 // Best (d, u) pair of hit m; see the step description above.
 template <bool LDS>
 __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *recd, const int32_t *recu,
+                                          float2 invd, float2 invu,
                                           const Slab &sd, const Slab &su, const int *lcd, const int *lcu,
                                           const int2 *lhd, const int2 *lhu, int64_t Xi, double inv_xi,
                                           int64_t Xd, int64_t Xu, int64_t smax, int &best_d, int &best_u) {
@@ -731,8 +738,8 @@ __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *r
   const int dxd = int(Xi - Xd), dxu = int(Xu - Xi);
   const int2 hm = w.syz[m];
   const int Ym = hm.x, Zm = hm.y;
-  const Cand kd = cand_window(recd, Ym, Zm, Xi, inv_xi, Xd, WY, WZ);
-  const Cand ku = cand_window(recu, Ym, Zm, Xi, inv_xi, Xu, WY, WZ);
+  const Cand kd = cand_window(recd, invd, Ym, Zm, Xi, inv_xi, Xd, WY, WZ);
+  const Cand ku = cand_window(recu, invu, Ym, Zm, Xi, inv_xi, Xu, WY, WZ);
   best_d = -1;
   best_u = -1;
   if (kd.c.empty || ku.c.empty) return;
@@ -868,17 +875,16 @@ __device__ __forceinline__ void chunk_links(const Args &A, const Chunk &c, const
   const int64_t Xu = __float2ll_rn(A.row_x[r + 1] * 256.0f);
   const int64_t smax = A.p.smax_k * (Xu - Xd) * (Xu - Xd);
   int bd, bu;
-  best_pair<LDS>(A, c.m, c.rec - SEGW, c.rec + SEGW, c.sd, c.su, lcd, lcu, lhd, lhu, Xi, 1.0 / double(Xi), Xd,
+  best_pair<LDS>(A, c.m, c.rec - SEGW, c.rec + SEGW, w.seg_inv[c.s - 1], w.seg_inv[c.s + 1], c.sd, c.su, lcd, lcu, lhd, lhu, Xi, 1.0 / double(Xi), Xd,
                  Xu, smax, bd, bu);
   w.dn[c.m] = bd;
   w.up[c.m] = bu;
 }
 
 // Chunks whose slabs fit in LDS; the others are listed for k_neighbours_wide.
-// 8 waves per SIMD (the LDS of 8 blocks is exactly one CU's): the candidate
-// loops wait on LDS, and twice the waves hide that better than the few
-// spilled registers cost.
-__global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(8, 8))) k_neighbours(Args A) {
+// 6 waves per SIMD (80 registers, a few spilled): measured faster than the
+// 4 that 98 registers would allow and than 7 or 8 with more spills.
+__global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(6, 8))) k_neighbours(Args A) {
   __shared__ __align__(16) int pool[2][STAGE_INTS];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
@@ -1173,7 +1179,8 @@ __device__ __forceinline__ int round_offset(float v, int ref) {
 // Least (w_y dY^2 + w_z dZ^2, id) inside the pickup window of the rounded
 // prediction.  The state is relative to the integer reference (Yr, Zr).
 // stop = 1 when the prediction has left the sector.
-__device__ int pick(const Args &A, const int32_t *rec, float yp, float zp, int Yr, int Zr, bool &stop) {
+__device__ int pick(const Args &A, const int32_t *rec, float2 inv, float yp, float zp, int Yr, int Zr,
+                    bool &stop) {
   const Workspace &w = A.w;
   const float vy = yp * 256.f, vz = zp * 256.f;
   if (!(fabsf(vy) < 1.0e9f)) {
@@ -1189,7 +1196,7 @@ __device__ int pick(const Args &A, const int32_t *rec, float yp, float zp, int Y
   if (!(fabsf(vz) < 1.0e9f)) return -1;  // beyond every cluster: a miss
   const int Zp = round_offset(vz, Zr);
   const int WY = A.p.ext_win_y_q, WZ = A.p.ext_win_z_q;
-  const Win c = window_cells(rec, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);
+  const Win c = window_cells(rec, inv, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);
   if (c.empty) return -1;
   // windows < 2^13 and weights <= 15 keep the score below 2^31
   int best_s = INT32_MAX;
@@ -1307,9 +1314,9 @@ __global__ void __launch_bounds__(TPB) k_compact_seeds(Args A) {
 // lane idles on rows outside its walk), so their hit-table accesses and
 // (unit,row) records coalesce; each lane's own sequence of operations is that
 // of its walk alone.
-// 6 waves per SIMD: the walk is bound by dependent gathers, and the extra
-// waves hide more of their latency than the few spilled registers cost
-__global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))) k_fit(Args A) {
+// 5 waves per SIMD (96 registers): the walk waits on dependent gathers, and
+// measured faster than 4 (no spills, fewer waves) or 6-8 (more spills)
+__global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))) k_fit(Args A) {
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int64_t n_seeds = w.ctr[C_SEEDS];
@@ -1325,6 +1332,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))
   int nfit = 0, rlo = -1, rhi = -1;
   int h0 = 0, u = 0, L = 0, r1 = 0, Yr = 0, Zr = 0;
   const int32_t *segu = w.seg;
+  const float2 *invs = w.seg_inv;
   KState s;
   bool ok = false;
   if (valid) {
@@ -1333,6 +1341,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))
     L = w.trk_len[t];
     r1 = w.trk_r1[t];
     segu = w.seg + int64_t(u) * nr * SEGW;
+    invs = w.seg_inv + int64_t(u) * nr;
     // seed, in coordinates relative to the first chain hit: small numbers
     // keep FP32 precise even at |z'| of metres (continuous readout)
     const int2 ya = w.syz[h0], ym = w.syz[w.trk_hm[t]], yb = w.syz[w.trk_hb[t]];
@@ -1384,7 +1393,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))
       h = hc;
     } else {
       bool stop = false;
-      h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
+      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
       if (stop) {
         act = false;
         continue;
@@ -1423,7 +1432,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(6, 8))
     int h = r >= r1 ? col[r * 64] : -1;  // pass-1 hit of this row, if any
     if (h < 0) {
       bool stop = false;
-      h = pick(A, segu + r * SEGW, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
+      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
       if (stop) {
         act = false;
         continue;
