@@ -257,6 +257,8 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+constexpr int RB = 4;  // rows of the hit table read per round trip in the row loops
+
 // Hit table of the seeds: [seed / 64][row][seed % 64], so the 64 lanes of a
 // wave (64 consecutive seeds) at one row touch one contiguous 256-byte run.
 // Returns the column of seed i; its row r is at col[r * 64].
@@ -1180,7 +1182,7 @@ __device__ __forceinline__ int round_offset(float v, int ref) {
 // prediction.  The state is relative to the integer reference (Yr, Zr).
 // stop = 1 when the prediction has left the sector.
 __device__ int pick(const Args &A, const int32_t *rec, float2 inv, float yp, float zp, int Yr, int Zr,
-                    bool &stop) {
+                    bool &stop, int2 &best_yz) {
   const Workspace &w = A.w;
   const float vy = yp * 256.f, vz = zp * 256.f;
   if (!(fabsf(vy) < 1.0e9f)) {
@@ -1212,6 +1214,7 @@ __device__ int pick(const Args &A, const int32_t *rec, float2 inv, float yp, flo
       if (sc < best_s || (sc == best_s && w.perm[q] < w.perm[best])) {
         best_s = sc;
         best = q;
+        best_yz = h;
       }
     }
   }
@@ -1229,9 +1232,7 @@ __device__ __forceinline__ void cov_reset(KState &s, const float *cov0) {
 }
 
 // measurement of hit h relative to the reference (exact: integer difference)
-__device__ __forceinline__ void upd_hit(const Args &A, KState &s, int h, int Yr, int Zr, float sy2,
-                                        float sz2) {
-  const int2 yz = A.w.syz[h];
+__device__ __forceinline__ void upd_hit(KState &s, int2 yz, int Yr, int Zr, float sy2, float sz2) {
   kf_update(s, float(yz.x - Yr) * (1.f / 256.f), float(yz.y - Zr) * (1.f / 256.f), sy2, sz2);
 }
 
@@ -1371,29 +1372,39 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     cov_reset(s, P.cov0);
   }
   // pass 1: the chain rows, then extension rows, in one walk up the rows;
-  // one propagate/update site serves both kinds of row
-  int r_out = r1, misses = 0, hc = h0;
+  // one propagate/update site serves both kinds of row.  The next chain hit
+  // and its coordinates are loaded a row ahead, under this row's arithmetic.
+  int r_out = r1, misses = 0;
   bool act = ok;
+  int nxt = -1;
+  int2 nyz = make_int2(0, 0);
   if (ok) {
     col[r1 * 64] = h0;
-    upd_hit(A, s, h0, Yr, Zr, sy2, sz2);
+    upd_hit(s, w.syz[h0], Yr, Zr, sy2, sz2);
+    if (L > 1) nxt = w.upc[h0];
   }
+  if (nxt >= 0) nyz = w.syz[nxt];
   for (int r = wave_min(ok ? r1 : nr) + 1; r < nr; ++r) {
     if (!__any(act)) break;
     if (!act || r <= r1) continue;
+    int h = -1;
+    int2 yz = make_int2(0, 0);
+    const bool chain = r < r1 + L;
+    int fut = -1;
+    if (chain) {
+      h = nxt;
+      yz = nyz;
+      if (r + 1 < r1 + L) fut = w.upc[h];  // chain hit of the next row
+    }
     Step st;
     const float xr = A.row_x[r];
     if (!step_prepare(s, xr, k, smx, st)) {
       act = false;
       continue;
     }
-    int h;
-    if (r < r1 + L) {
-      hc = w.upc[hc];
-      h = hc;
-    } else {
+    if (!chain) {
       bool stop = false;
-      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
+      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
       if (stop) {
         act = false;
         continue;
@@ -1402,37 +1413,50 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     col[r * 64] = h;
     if (h >= 0) {
       step_apply(s, st, xr, k);
-      upd_hit(A, s, h, Yr, Zr, sy2, sz2);
+      upd_hit(s, yz, Yr, Zr, sy2, sz2);
       r_out = r;
       misses = 0;
     } else if (++misses > P.max_miss) {
       act = false;
     }
+    if (chain) {
+      nxt = fut;
+      if (fut >= 0) nyz = w.syz[fut];
+    }
   }
-  // pass 2: from the outermost hit down to row 0, covariance reset
+  // pass 2: from the outermost hit down to row 0, covariance reset.  The
+  // pass-1 entry of the next row and its coordinates are loaded a row ahead
+  // (the entry of row r is written only while row r is processed).
   act = ok;
+  int ph = -1;
+  int2 pyz = make_int2(0, 0);
   if (ok) {
     cov_reset(s, P.cov0);
     s.chi2 = 0.f;
-    upd_hit(A, s, col[r_out * 64], Yr, Zr, sy2, sz2);
+    upd_hit(s, w.syz[col[r_out * 64]], Yr, Zr, sy2, sz2);
     nfit = 1;
     rhi = r_out;
     rlo = r_out;
     misses = 0;
+    if (r_out - 1 >= r1) ph = col[(r_out - 1) * 64];
   }
+  if (ph >= 0) pyz = w.syz[ph];
   for (int r = wave_max(ok ? r_out - 1 : -1); r >= 0; --r) {
     if (!__any(act)) break;
     if (!act || r >= r_out) continue;
+    int h = ph;  // pass-1 hit of this row, if any
+    int2 yz = pyz;
+    const int nh = r - 1 >= r1 ? col[(r - 1) * 64] : -1;
     Step st;
     const float xr = A.row_x[r];
     if (!step_prepare(s, xr, k, smx, st)) {
       act = false;
       continue;
     }
-    int h = r >= r1 ? col[r * 64] : -1;  // pass-1 hit of this row, if any
+    bool upd = true;
     if (h < 0) {
       bool stop = false;
-      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop);
+      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
       if (stop) {
         act = false;
         continue;
@@ -1441,14 +1465,19 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
       if (h < 0) {
         rlo = r;
         if (r < r1 && ++misses > P.max_miss) act = false;
-        continue;
+        upd = false;
+      } else {
+        misses = 0;
       }
-      misses = 0;
     }
-    step_apply(s, st, xr, k);
-    upd_hit(A, s, h, Yr, Zr, sy2, sz2);
-    ++nfit;
-    rlo = r;
+    if (upd) {
+      step_apply(s, st, xr, k);
+      upd_hit(s, yz, Yr, Zr, sy2, sz2);
+      ++nfit;
+      rlo = r;
+    }
+    ph = nh;
+    if (nh >= 0) pyz = w.syz[nh];
   }
   uint32_t key = 0;
   if (nfit > 0) {
@@ -1479,11 +1508,13 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
   // ownership: every hit goes to the tracklet with the largest key
   const bool has = nfit > 0;
   const int rb = wave_max(has ? rhi : -1);
-  for (int r = wave_min(has ? rlo : nr); r <= rb; ++r) {
-    if (has && r >= rlo && r <= rhi) {
-      const int h = col[r * 64];
-      if (h >= 0) atomicMax(&w.owner[h], key);
-    }
+  for (int r0 = wave_min(has ? rlo : nr); r0 <= rb; r0 += RB) {
+    int h[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) h[k] = (has && r0 + k >= rlo && r0 + k <= rhi) ? col[(r0 + k) * 64] : -1;
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (h[k] >= 0) atomicMax(&w.owner[h[k]], key);
   }
 }
 
@@ -1512,11 +1543,15 @@ __global__ void __launch_bounds__(TPB) k_select(Args A) {
   const int32_t *col = seed_column(w, i, nr);
   int owned = 0;
   const int rb = wave_max(has ? rhi : -1);
-  for (int r = wave_min(has ? rlo : nr); r <= rb; ++r) {
-    if (r >= rlo && r <= rhi) {
-      const int h = col[r * 64];
-      if (h >= 0 && w.owner[h] == key) ++owned;
-    }
+  for (int r0 = wave_min(has ? rlo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
+    int h[RB];
+    uint32_t o[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) h[k] = (r0 + k >= rlo && r0 + k <= rhi) ? col[(r0 + k) * 64] : -1;
+#pragma unroll
+    for (int k = 0; k < RB; ++k) o[k] = h[k] >= 0 ? w.owner[h[k]] : 0u;
+#pragma unroll
+    for (int k = 0; k < RB; ++k) owned += (h[k] >= 0 && o[k] == key) ? 1 : 0;
   }
   const int keep = has && owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
   if (valid) {
@@ -1570,13 +1605,21 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   const int nr = A.n_rows;
   const int32_t *col = seed_column(w, i, nr);
   const int rb = wave_max(keep ? rhi : -1);
-  for (int r = wave_min(keep ? rlo : nr); r <= rb; ++r) {
-    if (r >= rlo && r <= rhi) {
-      const int h = col[r * 64];
-      if (h >= 0 && w.owner[h] == key) {
-        const int id = w.perm[h];
-        O.hits[off++] = id;
-        O.cluster_track[id] = tr;
+  for (int r0 = wave_min(keep ? rlo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
+    int h[RB], id[RB];
+    uint32_t o[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) h[k] = (r0 + k >= rlo && r0 + k <= rhi) ? col[(r0 + k) * 64] : -1;
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      o[k] = h[k] >= 0 ? w.owner[h[k]] : 0u;
+      id[k] = h[k] >= 0 ? w.perm[h[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      if (h[k] >= 0 && o[k] == key) {
+        O.hits[off++] = id[k];
+        O.cluster_track[id[k]] = tr;
       }
     }
   }
