@@ -728,8 +728,16 @@ __device__ __forceinline__ Cand cand_window(const int32_t *rec, float2 inv, int6
 
 constexpr int MAXU = 4;  // row-above candidates kept in registers
 
-// Best (d, u) pair of hit m; see the step description above.
-template <bool LDS>
+// Scores of rows whose S_max is below 2^48 are evaluated in FP64 exactly:
+// a residual of 2^24 or more (with a nonzero weight) puts the score at 2^48
+// or above, past S_max, and below that every product and sum is an integer
+// under 2^53.  Other rows take the int64 path.
+constexpr double SMAX_F64 = 281474976710656.0;  // 2^48
+constexpr double RES_F64 = 16777216.0;          // 2^24
+
+// Best (d, u) pair of hit m; see the step description above.  F64: scores in
+// FP64 (S_max < 2^48), else in int64.
+template <bool LDS, bool F64>
 __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *recd, const int32_t *recu,
                                           float2 invd, float2 invu,
                                           const Slab &sd, const Slab &su, const int *lcd, const int *lcu,
@@ -769,20 +777,34 @@ __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *r
   }
   if (nu == 0) return;
   int64_t best_s = INT64_MAX;
+  double best_f = 1e300;
+  const double dxu_f = double(dxu), dxd_f = double(dxd), wy_f = double(wy), wz_f = double(wz);
+  const double smax_f = double(smax);
   auto consider = [&](int d, int2 hd, int uu, int2 hu) {
-    const int64_t ry = int64_t(hd.x - Ym) * dxu + int64_t(hu.x - Ym) * dxd;
-    const int64_t rz = int64_t(hd.y - Zm) * dxu + int64_t(hu.y - Zm) * dxd;
-    // a residual of 2^28 or more puts the score above 2^56 > smax
-    if ((wy && llabs(ry) >= (int64_t(1) << 28)) || (wz && llabs(rz) >= (int64_t(1) << 28))) return;
-    const int64_t sc = wy * ry * ry + wz * rz * rz;
-    if (sc > smax || sc > best_s) return;
-    bool take = sc < best_s;
+    bool take;
+    if (F64) {
+      const double ry = fma(double(hu.x - Ym), dxd_f, double(hd.x - Ym) * dxu_f);
+      const double rz = fma(double(hu.y - Zm), dxd_f, double(hd.y - Zm) * dxu_f);
+      if ((wy && fabs(ry) >= RES_F64) || (wz && fabs(rz) >= RES_F64)) return;
+      const double sc = fma(wy_f * ry, ry, wz_f * (rz * rz));
+      if (sc > smax_f || sc > best_f) return;
+      take = sc < best_f;
+      if (take) best_f = sc;
+    } else {
+      const int64_t ry = int64_t(hd.x - Ym) * dxu + int64_t(hu.x - Ym) * dxd;
+      const int64_t rz = int64_t(hd.y - Zm) * dxu + int64_t(hu.y - Zm) * dxd;
+      // a residual of 2^28 or more puts the score above 2^56 > smax
+      if ((wy && llabs(ry) >= (int64_t(1) << 28)) || (wz && llabs(rz) >= (int64_t(1) << 28))) return;
+      const int64_t sc = wy * ry * ry + wz * rz * rz;
+      if (sc > smax || sc > best_s) return;
+      take = sc < best_s;
+      if (take) best_s = sc;
+    }
     if (!take) {  // equal score: smaller ids win
       const int idd = w.perm[d], idb = w.perm[best_d];
       take = idd < idb || (idd == idb && w.perm[uu] < w.perm[best_u]);
     }
     if (take) {
-      best_s = sc;
       best_d = d;
       best_u = uu;
     }
@@ -867,7 +889,7 @@ __device__ __forceinline__ Chunk chunk_setup(const Args &A, int b) {
   return c;
 }
 
-template <bool LDS>
+template <bool LDS, bool F64>
 __device__ __forceinline__ void chunk_links(const Args &A, const Chunk &c, const int *lcd, const int *lcu,
                                             const int2 *lhd, const int2 *lhu) {
   const Workspace &w = A.w;
@@ -877,13 +899,14 @@ __device__ __forceinline__ void chunk_links(const Args &A, const Chunk &c, const
   const int64_t Xu = __float2ll_rn(A.row_x[r + 1] * 256.0f);
   const int64_t smax = A.p.smax_k * (Xu - Xd) * (Xu - Xd);
   int bd, bu;
-  best_pair<LDS>(A, c.m, c.rec - SEGW, c.rec + SEGW, w.seg_inv[c.s - 1], w.seg_inv[c.s + 1], c.sd, c.su, lcd, lcu, lhd, lhu, Xi, 1.0 / double(Xi), Xd,
+  best_pair<LDS, F64>(A, c.m, c.rec - SEGW, c.rec + SEGW, w.seg_inv[c.s - 1], w.seg_inv[c.s + 1], c.sd, c.su, lcd, lcu, lhd, lhu, Xi, 1.0 / double(Xi), Xd,
                  Xu, smax, bd, bu);
   w.dn[c.m] = bd;
   w.up[c.m] = bu;
 }
 
-// Chunks whose slabs fit in LDS; the others are listed for k_neighbours_wide.
+// Chunks whose slabs fit in LDS (and whose rows allow FP64 scores); the others
+// are listed for k_neighbours_wide.
 // 6 waves per SIMD (80 registers, a few spilled): measured faster than the
 // 4 that 98 registers would allow and than 7 or 8 with more spills.
 __global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(6, 8))) k_neighbours(Args A) {
@@ -902,7 +925,9 @@ __global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(6, 8))
     }
     return;
   }
-  if (!(c.sd.lds && c.su.lds)) {
+  const int64_t Xd = __float2ll_rn(A.row_x[c.r - 1] * 256.0f), Xu = __float2ll_rn(A.row_x[c.r + 1] * 256.0f);
+  const bool f64 = double(A.p.smax_k * (Xu - Xd) * (Xu - Xd)) < SMAX_F64;
+  if (!(c.sd.lds && c.su.lds && f64)) {
     if (threadIdx.x == 0) w.wide[atomicAdd(reinterpret_cast<unsigned long long *>(&w.ctr[C_NWIDE]), 1ull)] = b;
     return;
   }
@@ -938,18 +963,18 @@ __global__ void __launch_bounds__(NCH) __attribute__((amdgpu_waves_per_eu(6, 8))
   }
   __syncthreads();
   if (act)
-    chunk_links<true>(A, c, pool[0], pool[1], reinterpret_cast<const int2 *>(pool[0]),
+    chunk_links<true, true>(A, c, pool[0], pool[1], reinterpret_cast<const int2 *>(pool[0]),
                       reinterpret_cast<const int2 *>(pool[1]));
 }
 
-// The listed chunks, reading the neighbour rows from the workspace.
+// The listed chunks, reading the neighbour rows from the workspace, int64 scores.
 __global__ void __launch_bounds__(NCH) k_neighbours_wide(Args A) {
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int64_t n_wide = w.ctr[C_NWIDE];
   for (int64_t j = blockIdx.x; j < n_wide; j += gridDim.x) {
     const Chunk c = chunk_setup(A, w.wide[j]);
-    if (int(threadIdx.x) < c.n_here) chunk_links<false>(A, c, nullptr, nullptr, nullptr, nullptr);
+    if (int(threadIdx.x) < c.n_here) chunk_links<false, false>(A, c, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
