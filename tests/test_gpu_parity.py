@@ -159,6 +159,20 @@ def test_parity_other_bin_sizes(T, bins):
     _compare(T, ev, oracle.run_event(ev, q, fragile_eps=0.05), params=q)
 
 
+def test_parity_int64_scores(T):
+    """S_max at or above 2^48 sends every row to the int64 scoring path (the
+    FP64 one is exact only below it): links must still match bit for bit."""
+    import oracle
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    ev = cached_event("pp_sector")
+    x = np.round(ev.row_x.astype(np.float64) * 256)
+    span = int((x[2:] - x[:-2]).min())
+    q = dict(P, smax_k=int(2 ** 48 // span ** 2) + 1)
+    assert q["smax_k"] < 2 ** 30
+    _say("case int64 scores", q["smax_k"])
+    _compare(T, ev, oracle.run_event(ev, q, fragile_eps=0.05), params=q)
+
+
 def test_empty_batch(T):
     import synth
     ev = _Ev(np.zeros(0), np.zeros(0), np.zeros(0), [0, 0], synth.ROW_X_F32, 0.5, "empty")
