@@ -654,6 +654,30 @@ struct Win {
   bool empty;
 };
 
+// The fields of a (unit,row) record that the window search reads.
+struct Rec {
+  int count, zmin, zmax, H, by, ny, bz, cbase;
+};
+
+// loaded with three 16-byte loads (records are 48 bytes, 16-byte aligned)
+__device__ __forceinline__ Rec rec_fields_v(const int32_t *rec) {
+  const int4 a = reinterpret_cast<const int4 *>(rec)[0], b = reinterpret_cast<const int4 *>(rec)[1],
+             c = reinterpret_cast<const int4 *>(rec)[2];
+  static_assert(S_COUNT == 1 && S_ZMIN == 2 && S_ZMAX == 3 && S_H == 4 && S_BY == 5 && S_NY == 6 && S_BZ == 7 &&
+                    S_CBASE == 9 && SEGW == 12,
+                "record layout");
+  Rec f;
+  f.count = a.y;
+  f.zmin = a.z;
+  f.zmax = a.w;
+  f.H = b.x;
+  f.by = b.y;
+  f.ny = b.z;
+  f.bz = b.w;
+  f.cbase = c.y;
+  return f;
+}
+
 __device__ __forceinline__ Win window_cells(const int32_t *rec, float2 inv, int64_t ylo, int64_t yhi,
                                             int64_t zlo, int64_t zhi) {
   Win c;
@@ -670,6 +694,26 @@ __device__ __forceinline__ Win window_cells(const int32_t *rec, float2 inv, int6
   c.iz1 = div_small(int(cl(zhi - zmin, 0, span)), bz, inv.y);
   c.ny = rec[S_NY];
   c.cbase = rec[S_CBASE];
+  return c;
+}
+
+// The same window from a record already in registers.
+__device__ __forceinline__ Win window_cells(const Rec &r, float2 inv, int64_t ylo, int64_t yhi, int64_t zlo,
+                                            int64_t zhi) {
+  Win c;
+  const int count = r.count;
+  const int64_t zmin = r.zmin, zmax = r.zmax;
+  c.empty = count == 0 || zhi < zmin || zlo > zmax || yhi < ylo;
+  if (c.empty) return c;
+  const int64_t H = r.H, span = zmax - zmin;
+  const int by = r.by, bz = r.bz;
+  auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  c.iy0 = div_small(int(cl(ylo + H, 0, 2 * H)), by, inv.x);
+  c.iy1 = div_small(int(cl(yhi + H, 0, 2 * H)), by, inv.x);
+  c.iz0 = div_small(int(cl(zlo - zmin, 0, span)), bz, inv.y);
+  c.iz1 = div_small(int(cl(zhi - zmin, 0, span)), bz, inv.y);
+  c.ny = r.ny;
+  c.cbase = r.cbase;
   return c;
 }
 
@@ -1215,15 +1259,15 @@ __device__ int pick(const Args &A, const int32_t *rec, float2 inv, float yp, flo
     return -1;
   }
   const int Yp = round_offset(vy, Yr);
-  const int H = rec[S_H];
-  if (abs(Yp) > H + A.p.ext_edge_q) {
+  const Rec rf = rec_fields_v(rec);
+  if (abs(Yp) > rf.H + A.p.ext_edge_q) {
     stop = true;
     return -1;
   }
   if (!(fabsf(vz) < 1.0e9f)) return -1;  // beyond every cluster: a miss
   const int Zp = round_offset(vz, Zr);
   const int WY = A.p.ext_win_y_q, WZ = A.p.ext_win_z_q;
-  const Win c = window_cells(rec, inv, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);
+  const Win c = window_cells(rf, inv, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);
   if (c.empty) return -1;
   // windows < 2^13 and weights <= 15 keep the score below 2^31
   int best_s = INT32_MAX;
