@@ -1441,37 +1441,30 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     cov_reset(s, P.cov0);
   }
   // pass 1: the chain rows, then extension rows, in one walk up the rows;
-  // one propagate/update site serves both kinds of row.  The next chain hit
-  // and its coordinates are loaded a row ahead, under this row's arithmetic.
-  int r_out = r1, misses = 0;
+  // one propagate/update site serves both kinds of row.
+  int r_out = r1, misses = 0, hc = h0;
   bool act = ok;
-  int nxt = -1;
-  int2 nyz = make_int2(0, 0);
   if (ok) {
     col[r1 * 64] = h0;
     upd_hit(s, w.syz[h0], Yr, Zr, sy2, sz2);
-    if (L > 1) nxt = w.upc[h0];
   }
-  if (nxt >= 0) nyz = w.syz[nxt];
   for (int r = wave_min(ok ? r1 : nr) + 1; r < nr; ++r) {
     if (!__any(act)) break;
     if (!act || r <= r1) continue;
     int h = -1;
     int2 yz = make_int2(0, 0);
     const bool chain = r < r1 + L;
-    int fut = -1;
-    if (chain) {
-      h = nxt;
-      yz = nyz;
-      if (r + 1 < r1 + L) fut = w.upc[h];  // chain hit of the next row
-    }
     Step st;
     const float xr = A.row_x[r];
     if (!step_prepare(s, xr, k, smx, st)) {
       act = false;
       continue;
     }
-    if (!chain) {
+    if (chain) {
+      hc = w.upc[hc];
+      h = hc;
+      yz = w.syz[h];
+    } else {
       bool stop = false;
       h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
       if (stop) {
@@ -1488,17 +1481,9 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     } else if (++misses > P.max_miss) {
       act = false;
     }
-    if (chain) {
-      nxt = fut;
-      if (fut >= 0) nyz = w.syz[fut];
-    }
   }
-  // pass 2: from the outermost hit down to row 0, covariance reset.  The
-  // pass-1 entry of the next row and its coordinates are loaded a row ahead
-  // (the entry of row r is written only while row r is processed).
+  // pass 2: from the outermost hit down to row 0, covariance reset
   act = ok;
-  int ph = -1;
-  int2 pyz = make_int2(0, 0);
   if (ok) {
     cov_reset(s, P.cov0);
     s.chi2 = 0.f;
@@ -1507,15 +1492,12 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     rhi = r_out;
     rlo = r_out;
     misses = 0;
-    if (r_out - 1 >= r1) ph = col[(r_out - 1) * 64];
   }
-  if (ph >= 0) pyz = w.syz[ph];
   for (int r = wave_max(ok ? r_out - 1 : -1); r >= 0; --r) {
     if (!__any(act)) break;
     if (!act || r >= r_out) continue;
-    int h = ph;  // pass-1 hit of this row, if any
-    int2 yz = pyz;
-    const int nh = r - 1 >= r1 ? col[(r - 1) * 64] : -1;
+    int h = r >= r1 ? col[r * 64] : -1;  // pass-1 hit of this row, if any
+    int2 yz = make_int2(0, 0);
     Step st;
     const float xr = A.row_x[r];
     if (!step_prepare(s, xr, k, smx, st)) {
@@ -1523,7 +1505,9 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
       continue;
     }
     bool upd = true;
-    if (h < 0) {
+    if (h >= 0) {
+      yz = w.syz[h];
+    } else {
       bool stop = false;
       h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
       if (stop) {
@@ -1545,8 +1529,6 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
       ++nfit;
       rlo = r;
     }
-    ph = nh;
-    if (nh >= 0) pyz = w.syz[nh];
   }
   uint32_t key = 0;
   if (nfit > 0) {
