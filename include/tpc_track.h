@@ -79,7 +79,7 @@ typedef struct tpc_clusters {
 typedef struct tpc_geometry {
   int32_t n_rows;              /* 3 <= n_rows <= 255 */
   int32_t reserved;
-  const float *row_x;          /* [n_rows] row positions x_i (cm), increasing, 0 < x < 8192 */
+  const float *row_x;          /* [n_rows] row positions x_i (cm), increasing, 1 <= x < 8192 */
 } tpc_geometry_t;
 
 /* Solenoid field along z. */

@@ -784,8 +784,9 @@ int orc_run(int64_t n, int64_t n_units, const int64_t *unit_offsets, const float
   for (int64_t u = 0; u < n_units; ++u)
     if (unit_offsets[u + 1] < unit_offsets[u] || unit_offsets[u + 1] - unit_offsets[u] >= (1 << 24))
       return ORC_INVALID;
+  /* pad rows between 1 cm and 8192 cm from the axis, increasing */
   for (int64_t r = 0; r < n_rows; ++r)
-    if (!(row_x[r] > 0.0f) || !(row_x[r] < 8192.0f) || (r > 0 && !(row_x[r] > row_x[r - 1])))
+    if (!(row_x[r] >= 1.0f) || !(row_x[r] < 8192.0f) || (r > 0 && !(row_x[r] > row_x[r - 1])))
       return ORC_INVALID;
   /* rows two apart at most 32 cm apart: keeps the neighbour cut below 2^56 */
   for (int64_t r = 1; r + 1 < n_rows; ++r)

@@ -289,10 +289,10 @@ __global__ void __launch_bounds__(1024) k_units(Args A) {
   bool bad = false;
   for (int r = threadIdx.x; r < A.n_rows; r += blockDim.x) {
     const float x = A.row_x[r];
-    if (!(x > 0.f && x < 8192.f)) bad = true;
+    if (!(x >= 1.f && x < 8192.f)) bad = true;  // 1 cm .. 8192 cm: X is at least 256 quanta
     if (r > 0 && !(x > A.row_x[r - 1])) bad = true;
     // rows two apart at most 32 cm apart: keeps the neighbour cut below 2^56
-    if (r > 0 && r + 1 < A.n_rows && x > 0.f && x < 8192.f &&
+    if (r > 0 && r + 1 < A.n_rows && x >= 1.f && x < 8192.f &&
         __float2ll_rn(A.row_x[r + 1] * 256.f) - __float2ll_rn(A.row_x[r - 1] * 256.f) >= 8192)
       bad = true;
   }
@@ -678,40 +678,38 @@ __device__ __forceinline__ Rec rec_fields_v(const int32_t *rec) {
   return f;
 }
 
-__device__ __forceinline__ Win window_cells(const int32_t *rec, float2 inv, int64_t ylo, int64_t yhi,
-                                            int64_t zlo, int64_t zhi) {
+// Window bounds are within +-2^30 and coordinates within +-2^21 (every
+// cluster is checked), so the sums below stay exact in int32.
+__device__ __forceinline__ Win window_cells(const int32_t *rec, float2 inv, int ylo, int yhi, int zlo, int zhi) {
   Win c;
   const int count = rec[S_COUNT];
-  const int64_t zmin = rec[S_ZMIN], zmax = rec[S_ZMAX];
+  const int zmin = rec[S_ZMIN], zmax = rec[S_ZMAX];
   c.empty = count == 0 || zhi < zmin || zlo > zmax || yhi < ylo;
   if (c.empty) return c;
-  const int64_t H = rec[S_H], span = zmax - zmin;
+  const int H = rec[S_H], span = zmax - zmin;
   const int by = rec[S_BY], bz = rec[S_BZ];
-  auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
-  c.iy0 = div_small(int(cl(ylo + H, 0, 2 * H)), by, inv.x);
-  c.iy1 = div_small(int(cl(yhi + H, 0, 2 * H)), by, inv.x);
-  c.iz0 = div_small(int(cl(zlo - zmin, 0, span)), bz, inv.y);
-  c.iz1 = div_small(int(cl(zhi - zmin, 0, span)), bz, inv.y);
+  c.iy0 = div_small(clampi(ylo + H, 0, 2 * H), by, inv.x);
+  c.iy1 = div_small(clampi(yhi + H, 0, 2 * H), by, inv.x);
+  c.iz0 = div_small(clampi(zlo - zmin, 0, span), bz, inv.y);
+  c.iz1 = div_small(clampi(zhi - zmin, 0, span), bz, inv.y);
   c.ny = rec[S_NY];
   c.cbase = rec[S_CBASE];
   return c;
 }
 
 // The same window from a record already in registers.
-__device__ __forceinline__ Win window_cells(const Rec &r, float2 inv, int64_t ylo, int64_t yhi, int64_t zlo,
-                                            int64_t zhi) {
+__device__ __forceinline__ Win window_cells(const Rec &r, float2 inv, int ylo, int yhi, int zlo, int zhi) {
   Win c;
   const int count = r.count;
-  const int64_t zmin = r.zmin, zmax = r.zmax;
+  const int zmin = r.zmin, zmax = r.zmax;
   c.empty = count == 0 || zhi < zmin || zlo > zmax || yhi < ylo;
   if (c.empty) return c;
-  const int64_t H = r.H, span = zmax - zmin;
+  const int H = r.H, span = zmax - zmin;
   const int by = r.by, bz = r.bz;
-  auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
-  c.iy0 = div_small(int(cl(ylo + H, 0, 2 * H)), by, inv.x);
-  c.iy1 = div_small(int(cl(yhi + H, 0, 2 * H)), by, inv.x);
-  c.iz0 = div_small(int(cl(zlo - zmin, 0, span)), bz, inv.y);
-  c.iz1 = div_small(int(cl(zhi - zmin, 0, span)), bz, inv.y);
+  c.iy0 = div_small(clampi(ylo + H, 0, 2 * H), by, inv.x);
+  c.iy1 = div_small(clampi(yhi + H, 0, 2 * H), by, inv.x);
+  c.iz0 = div_small(clampi(zlo - zmin, 0, span), bz, inv.y);
+  c.iz1 = div_small(clampi(zhi - zmin, 0, span), bz, inv.y);
   c.ny = r.ny;
   c.cbase = r.cbase;
   return c;
@@ -738,16 +736,6 @@ __device__ __forceinline__ int2 hit_at(const Workspace &w, const Slab &sl, const
   return LDS ? lh[q - sl.q0] : w.syz[q];
 }
 
-// floor(a / b) for 0 < b and |a| < 2^50, exactly: a times the rounded
-// reciprocal of b is within one of the quotient, then corrected with integer
-// products.
-__device__ __forceinline__ int64_t floor_div_exact(int64_t a, int64_t b, double inv_b) {
-  int64_t q = int64_t(floor(double(a) * inv_b));
-  if (q * b > a) --q;
-  else if ((q + 1) * b <= a) ++q;
-  return q;
-}
-
 // Candidate rows: the exact y interval of the window in row j and its cells.
 struct Cand {
   int ylo, yhi;  // Y_n in [ylo, yhi]  <=>  |Y_n X_i - Y_m X_j| <= W X_i
@@ -756,17 +744,21 @@ struct Cand {
 
 // The window is ceil(Y_m X_j / X_i) - W <= Y_n <= floor(Y_m X_j / X_i) + W
 // (W is an integer, so it moves out of the floor and the ceiling).
-__device__ __forceinline__ Cand cand_window(const int32_t *rec, float2 inv, int64_t Ym, int64_t Zm, int64_t Xi,
-                                            double inv_xi, int64_t Xj, int64_t WY, int64_t WZ) {
+// In FP64, exactly: |Y_m| <= 2^21 and X < 2^22, so every product and sum is
+// an integer below 2^53; the quotient from the reciprocal is within one of
+// the floor and corrected by exact products.
+__device__ __forceinline__ Cand cand_window(const int32_t *rec, float2 inv, int Ym, int Zm, double xi,
+                                            double inv_xi, double xj, int WY, int WZ) {
   Cand k;
-  const int64_t a = Ym * Xj;
-  const int64_t q = floor_div_exact(a, Xi, inv_xi);
-  const int64_t lo = q + (q * Xi != a ? 1 : 0) - WY;
-  const int64_t hi = q + WY;
+  const double a = double(Ym) * xj;
+  double q = floor(a * inv_xi);
+  if (q * xi > a) q -= 1.0;
+  else if ((q + 1.0) * xi <= a) q += 1.0;
+  const double lo = q + (q * xi != a ? 1.0 : 0.0) - double(WY), hi = q + double(WY);
   // |Y| <= 2^21 for every cluster: clamping keeps the compares exact in int32
-  k.ylo = int(lo < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (lo > (int64_t(1) << 30) ? (int64_t(1) << 30) : lo));
-  k.yhi = int(hi < -(int64_t(1) << 30) ? -(int64_t(1) << 30) : (hi > (int64_t(1) << 30) ? (int64_t(1) << 30) : hi));
-  k.c = window_cells(rec, inv, lo, hi, Zm - WZ, Zm + WZ);
+  k.ylo = int(fmin(fmax(lo, -1073741824.0), 1073741824.0));
+  k.yhi = int(fmin(fmax(hi, -1073741824.0), 1073741824.0));
+  k.c = window_cells(rec, inv, k.ylo, k.yhi, Zm - WZ, Zm + WZ);
   return k;
 }
 
@@ -792,8 +784,8 @@ __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *r
   const int dxd = int(Xi - Xd), dxu = int(Xu - Xi);
   const int2 hm = w.syz[m];
   const int Ym = hm.x, Zm = hm.y;
-  const Cand kd = cand_window(recd, invd, Ym, Zm, Xi, inv_xi, Xd, WY, WZ);
-  const Cand ku = cand_window(recu, invu, Ym, Zm, Xi, inv_xi, Xu, WY, WZ);
+  const Cand kd = cand_window(recd, invd, Ym, Zm, double(Xi), inv_xi, double(Xd), int(WY), int(WZ));
+  const Cand ku = cand_window(recu, invu, Ym, Zm, double(Xi), inv_xi, double(Xu), int(WY), int(WZ));
   best_d = -1;
   best_u = -1;
   if (kd.c.empty || ku.c.empty) return;

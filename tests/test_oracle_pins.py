@@ -630,6 +630,10 @@ def test_invalid_inputs_rejected():
         oracle.run(y, z, row, [0, 2], rx, 0.5, P)  # offsets do not cover n
     with pytest.raises(ValueError):
         oracle.run(y, z, row, [0, 2, 1, 3], rx, 0.5, P)  # decreasing offsets
+    near = rx.copy()
+    near[:3] = np.array([0.001, 0.5, 0.9], np.float32)  # rows closer than 1 cm to the axis
+    with pytest.raises(ValueError):
+        oracle.run(y, z, row, [0, 3], near, 0.5, P)
 
 
 def test_empty_and_sparse_units():
