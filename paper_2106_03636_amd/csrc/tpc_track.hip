@@ -535,6 +535,7 @@ __device__ __forceinline__ int bin_of(const int32_t *rec, int Y, int Z) {
 // table.  Fast path: bins and per-hit ranks in LDS, data moved by all threads
 // afterwards; rows too large for LDS take the same steps with global cursors.
 constexpr int BIN_POOL = 12288;  // LDS ints shared by the bin counters and the per-hit slots
+constexpr int KREG = 24;         // hits per thread kept in registers by the bin sort (rows <= 6144)
 
 __device__ __forceinline__ void scan_bins(int *hist, int nbins, int32_t *cell_out, int start, int *tmp) {
   const int per = (nbins + TPB - 1) / TPB;
@@ -566,8 +567,28 @@ __global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
   if (nbins + count <= BIN_POOL) {
     int *hist_lds = pool, *slot = pool + nbins;
     for (int b = threadIdx.x; b < nbins; b += TPB) hist_lds[b] = 0;
+    // the thread's first KREG hits stay in registers from here to the scatter
+    int2 ryz[KREG];
+    int rid[KREG];
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) {
+      const int p = int(threadIdx.x) + k * TPB;
+      if (p < count) {
+        ryz[k] = w.rs_yz[start + p];
+        rid[k] = w.rs_idx[start + p];
+      }
+    }
     __syncthreads();
-    for (int p = threadIdx.x; p < count; p += TPB) {
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) {
+      const int p = int(threadIdx.x) + k * TPB;
+      if (p < count) {
+        const int bn = bin_of(rec, ryz[k].x, ryz[k].y);
+        slot[p] = bn;
+        atomicAdd(&hist_lds[bn], 1);
+      }
+    }
+    for (int p = int(threadIdx.x) + KREG * TPB; p < count; p += TPB) {
       const int2 yz = w.rs_yz[start + p];
       const int bn = bin_of(rec, yz.x, yz.y);
       slot[p] = bn;
@@ -576,11 +597,13 @@ __global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
     __syncthreads();
     scan_bins(hist_lds, nbins, w.cell + cbase, start, tmp);
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if (threadIdx.x < 64) {  // stable ranks, one wave, chunk by chunk; the next chunk's bins load early
+      int nb = lane < count ? slot[lane] : 0;
       for (int c = 0; c < count; c += 64) {
         const int p = c + lane;
         const bool act = p < count;
-        const int bn = act ? slot[p] : 0;
+        const int bn = nb;
+        nb = p + 64 < count ? slot[p + 64] : 0;
         const uint64_t peers = peer_mask(uint32_t(bn), nbits, act);
         const int lp = act ? hist_lds[bn] + __popcll(peers & lanemask_lt()) : 0;
         __builtin_amdgcn_wave_barrier();
@@ -590,7 +613,16 @@ __global__ void __launch_bounds__(TPB) k_bin_sort(Args A) {
       }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < count; p += TPB) {
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) {
+      const int p = int(threadIdx.x) + k * TPB;
+      if (p < count) {
+        const int lp = slot[p];
+        w.perm[start + lp] = rid[k];
+        w.syz[start + lp] = ryz[k];
+      }
+    }
+    for (int p = int(threadIdx.x) + KREG * TPB; p < count; p += TPB) {
       const int lp = slot[p];
       w.perm[start + lp] = w.rs_idx[start + p];
       w.syz[start + lp] = w.rs_yz[start + p];
