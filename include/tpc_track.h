@@ -182,7 +182,8 @@ const char *tpc_status_string(int status);
  *                      in tracklet order; the first (number of seeds) valid.
  *   TPC_VIEW_TRK_HITS  int32 [ceil(capacity/64)][n_rows][64] hit of each row
  *                      (-1 none) of seed i at [i/64][row][i%64], rows RLO..RHI
- *                      of its tracklet valid. */
+ *                      of its tracklet valid; bit 30 is set on the hits the
+ *                      tracklet owns (the position is the low 30 bits). */
 enum {
   TPC_VIEW_PERM = 1, TPC_VIEW_CELL, TPC_VIEW_SEG, TPC_VIEW_UP, TPC_VIEW_DN, TPC_VIEW_UPC,
   TPC_VIEW_DNC, TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN,

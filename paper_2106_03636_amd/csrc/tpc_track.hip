@@ -213,11 +213,6 @@ __device__ __forceinline__ uint64_t peer_mask(uint32_t key, int nbits, bool acti
 
 __device__ __forceinline__ int quant(float v) { return __float2int_rn(v * 256.0f); }
 
-__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
-  int64_t q = a / b;
-  if ((a % b != 0) && (a < 0)) --q;
-  return q;
-}
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -258,6 +253,7 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 constexpr int RB = 4;  // rows of the hit table read per round trip in the row loops
+constexpr int OWNED = 1 << 30;  // hit table entries (< 2^30) of hits their tracklet owns, once selected
 
 // Hit table of the seeds: [seed / 64][row][seed % 64], so the 64 lanes of a
 // wave (64 consecutive seeds) at one row touch one contiguous 256-byte run.
@@ -1230,12 +1226,6 @@ __device__ __forceinline__ void step_apply(KState &s, const Step &t, float x2, f
   c[12] = P42 + f * P44;
 }
 
-__device__ __forceinline__ bool propagate(KState &s, float x2, float k, float sinmax) {
-  Step t;
-  if (!step_prepare(s, x2, k, sinmax, t)) return false;
-  step_apply(s, t, x2, k);
-  return true;
-}
 
 __device__ __forceinline__ void kf_update(KState &s, float my, float mz, float sy2, float sz2) {
   float *c = s.c;
@@ -1615,7 +1605,7 @@ __global__ void __launch_bounds__(TPB) k_select(Args A) {
   const uint32_t key = has ? w.trk_key[t] : 0u;
   const int rlo = has ? w.trk_rlo[t] : 0, rhi = has ? w.trk_rhi[t] : -1;
   const int nr = A.n_rows;
-  const int32_t *col = seed_column(w, i, nr);
+  int32_t *col = seed_column(w, i, nr);
   int owned = 0;
   const int rb = wave_max(has ? rhi : -1);
   for (int r0 = wave_min(has ? rlo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
@@ -1626,7 +1616,11 @@ __global__ void __launch_bounds__(TPB) k_select(Args A) {
 #pragma unroll
     for (int k = 0; k < RB; ++k) o[k] = h[k] >= 0 ? w.owner[h[k]] : 0u;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) owned += (h[k] >= 0 && o[k] == key) ? 1 : 0;
+    for (int k = 0; k < RB; ++k)
+      if (h[k] >= 0 && o[k] == key) {  // mark the hit for the emitter
+        ++owned;
+        col[(r0 + k) * 64] = h[k] | OWNED;
+      }
   }
   const int keep = has && owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
   if (valid) {
@@ -1660,7 +1654,6 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   const int tr = w.blk_keep[b] + ek;
   int off = w.blk_own[b] + eo;
   const tpc_tracks_t &O = A.out;
-  uint32_t key = 0u;
   int rlo = 0, rhi = -1;
   if (keep) {
 #pragma unroll
@@ -1673,7 +1666,6 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
     O.n_hits[tr] = owned;
     O.n_fit[tr] = w.trk_nfit[t];
     O.first_hit[tr] = off;
-    key = w.trk_key[t];
     rlo = w.trk_rlo[t];
     rhi = w.trk_rhi[t];
   }
@@ -1682,17 +1674,13 @@ __global__ void __launch_bounds__(TPB) k_emit(Args A) {
   const int rb = wave_max(keep ? rhi : -1);
   for (int r0 = wave_min(keep ? rlo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
     int h[RB], id[RB];
-    uint32_t o[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) h[k] = (r0 + k >= rlo && r0 + k <= rhi) ? col[(r0 + k) * 64] : -1;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      o[k] = h[k] >= 0 ? w.owner[h[k]] : 0u;
-      id[k] = h[k] >= 0 ? w.perm[h[k]] : 0;
-    }
+    for (int k = 0; k < RB; ++k) id[k] = (h[k] >= 0 && (h[k] & OWNED)) ? w.perm[h[k] & (OWNED - 1)] : -1;
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-      if (h[k] >= 0 && o[k] == key) {
+      if (id[k] >= 0) {
         O.hits[off++] = id[k];
         O.cluster_track[id[k]] = tr;
       }

@@ -68,6 +68,7 @@ def gpu_state(tracker, result):
     g["seeds_expected"] = seeds
     raw = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(-1, n_rows, 64)
     per_seed = raw.transpose(0, 2, 1).reshape(-1, n_rows)[:len(seeds)]  # [seed][row]
+    per_seed = np.where(per_seed >= 0, per_seed & ((1 << 30) - 1), per_seed)  # drop the owned mark
     hitrows = np.full((n_rows, K), -1, np.int32)
     hitrows[:, seeds] = per_seed.T
     g["trk_hitrows"] = hitrows  # [row][tracklet]
