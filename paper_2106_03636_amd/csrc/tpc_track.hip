@@ -462,10 +462,16 @@ __global__ void __launch_bounds__(64) k_tile_offsets(Args A) {
 
 // step 2e: stable scatter of every tile's hits to row order.  Each wave owns a
 // contiguous quarter of the tile, holds its rows in registers, and ranks equal
-// rows with ballots, so hits of one row keep the order of their ids.
+// rows with ballots, so hits of one row keep the order of their ids.  The
+// tile is first put in row order in LDS, so that each row's run of hits is
+// written to HBM as one contiguous piece.
 __global__ void __launch_bounds__(TPB) k_tile_scatter(Args A) {
   constexpr int CH = TILE / 4 / 64;  // 64-hit chunks per wave
   __shared__ int wcnt[4][256];
+  __shared__ int tbase[256], tloc[256];  // per row: first output position, first staged slot
+  __shared__ int2 s_yz[TILE];
+  __shared__ int s_id[TILE];
+  __shared__ uint8_t s_row[TILE];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int b = blockIdx.x;
@@ -488,13 +494,31 @@ __global__ void __launch_bounds__(TPB) k_tile_scatter(Args A) {
   for (int c = 0; c < CH; ++c)
     if (rr[c] >= 0) atomicAdd(&wcnt[wid][rr[c]], 1);
   __syncthreads();
+  if (threadIdx.x < 64) {  // staged slots: rows in order (exclusive scan of the tile's row counts)
+    int run = 0;
+    for (int r0 = 0; r0 < 256; r0 += 64) {
+      const int r = r0 + lane;
+      const int v = r < A.n_rows ? wcnt[0][r] + wcnt[1][r] + wcnt[2][r] + wcnt[3][r] : 0;
+      int x = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      tloc[r] = run + x - v;
+      run += __shfl(x, 63);
+    }
+  }
+  __syncthreads();
   for (int r = threadIdx.x; r < A.n_rows; r += TPB) {
     int base = w.tile_hist[int64_t(r) * w.T_max + b];
+    tbase[r] = base;
+    int loc = tloc[r];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 4; ++k) {  // per wave: first staged slot of its hits of the row
       const int t = wcnt[k][r];
-      wcnt[k][r] = base;
-      base += t;
+      wcnt[k][r] = loc;
+      loc += t;
     }
   }
   __syncthreads();
@@ -513,9 +537,18 @@ __global__ void __launch_bounds__(TPB) k_tile_scatter(Args A) {
   for (int c = 0; c < CH; ++c) {
     if (rr[c] >= 0) {
       const int64_t i = sub_beg + c * 64 + lane;
-      w.rs_idx[pos[c]] = int32_t(i);
-      w.rs_yz[pos[c]] = make_int2(quant(A.y[i]), quant(A.z[i]));
+      s_id[pos[c]] = int32_t(i);
+      s_yz[pos[c]] = make_int2(quant(A.y[i]), quant(A.z[i]));
+      s_row[pos[c]] = uint8_t(rr[c]);
     }
+  }
+  __syncthreads();
+  const int n_tile = int(end - beg);
+  for (int j = threadIdx.x; j < n_tile; j += TPB) {  // each row's run to consecutive positions
+    const int r = s_row[j];
+    const int gp = tbase[r] + (j - tloc[r]);
+    w.rs_idx[gp] = s_id[j];
+    w.rs_yz[gp] = s_yz[j];
   }
 }
 
