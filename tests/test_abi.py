@@ -30,9 +30,12 @@ def test_struct_layouts_match_header(tmp_path):
     """ctypes mirrors of the structs have the sizes and field offsets the C
     compiler gives the header's structs."""
     import subprocess
+    from paper_2106_03636_amd import server as S
     structs = {"tpc_clusters_t": T.tpc_clusters_t, "tpc_geometry_t": T.tpc_geometry_t,
                "tpc_field_t": T.tpc_field_t, "tpc_params_t": T.tpc_params_t,
-               "tpc_tracks_t": T.tpc_tracks_t, "tpc_view_t": T.tpc_view_t}
+               "tpc_tracks_t": T.tpc_tracks_t, "tpc_view_t": T.tpc_view_t,
+               "tpc_server_config_t": S.tpc_server_config_t, "tpc_request_t": S.tpc_request_t,
+               "tpc_result_t": S.tpc_result_t, "tpc_server_stats_t": S.tpc_server_stats_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tpc_track.h"', 'int main(void){']
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
@@ -48,6 +51,23 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(got["%s.%s" % (name, f)]) == getattr(cls, f).offset, (name, f)
+
+
+def test_server_host_checks():
+    """Serving calls that fail before any device work: bad configuration,
+    footprint of impossible shapes."""
+    from paper_2106_03636_amd import server as S
+    p = T.make_params()
+    assert S.tpc_server_footprint(1000, 1, 152, p) > S.tpc_server_footprint(10, 1, 152, p) > 0
+    assert S.tpc_server_footprint(-1, 1, 152, p) == 0
+    cfg = S.tpc_server_config_t()
+    cfg.budget_bytes = 0  # no arena
+    cfg.max_in_flight = 1
+    cfg.queue_depth = 1
+    cfg.n_rows = 152
+    cfg.params = p
+    st, h = S.tpc_server_create(cfg)
+    assert st == T.TPC_E_INVALID and not h.value
 
 
 def test_workspace_size_monotone_and_rejects_bad_shapes():
