@@ -1115,12 +1115,22 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(int32_t *blk, int64_t nb, 
   for (int which = 0; which < (blk2 ? 2 : 1); ++which) {
     int32_t *b = which ? blk2 : blk;
     int carry = 0;
-    for (int64_t base = 0; base < nb; base += 1024) {
-      const int64_t i = base + threadIdx.x;
-      const int v = i < nb ? b[i] : 0;
+    constexpr int PER = 8;  // consecutive entries per thread, one block scan per 8192
+    for (int64_t base = 0; base < nb; base += 1024 * PER) {
+      const int64_t i0 = base + int64_t(threadIdx.x) * PER;
+      int v[PER], sum = 0;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        v[e] = i0 + e < nb ? b[i0 + e] : 0;
+        sum += v[e];
+      }
       int tot;
-      const int ex = block_exclusive_scan<1024>(v, tmp, &tot);
-      if (i < nb) b[i] = carry + ex;
+      int ex = carry + block_exclusive_scan<1024>(sum, tmp, &tot);
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        if (i0 + e < nb) b[i0 + e] = ex;
+        ex += v[e];
+      }
       carry += tot;
     }
     if (threadIdx.x == 0) {
@@ -1139,25 +1149,36 @@ __global__ void __launch_bounds__(TPB) k_compact_starts(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t base = int64_t(blockIdx.x) * ELEMS;
-  int carry = w.blk[blockIdx.x];
-#pragma unroll 1
-  for (int e = 0; e < ELEMS / TPB; ++e) {
-    const int64_t p = base + e * TPB + threadIdx.x;
-    const int f = p < A.n ? w.flag[p] : 0;
-    int tot;
-    const int ex = block_exclusive_scan<TPB>(f, tmp, &tot);
-    if (f) {
-      const int t = carry + ex;
-      int lo = 0, hi = A.n_units - 1;  // unit: largest u with off[u] <= p
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (A.off[mid] <= p) lo = mid; else hi = mid - 1;
-      }
-      w.trk_start[t] = int32_t(p);
-      w.trk_unit[t] = lo;
+  // each thread takes ELEMS / TPB consecutive flags (one 8-byte load), so one
+  // block scan numbers the block's starts in position order
+  constexpr int PER = ELEMS / TPB;
+  static_assert(PER == 8, "one 64-bit load of flags per thread");
+  const int64_t p0 = int64_t(blockIdx.x) * ELEMS + int64_t(threadIdx.x) * PER;
+  uint64_t f8 = 0;
+  if (p0 + PER <= A.n) {
+    f8 = *reinterpret_cast<const uint64_t *>(w.flag + p0);  // flags are 256-byte aligned
+  } else {
+    for (int e = 0; e < PER; ++e)
+      if (p0 + e < A.n) f8 |= uint64_t(w.flag[p0 + e]) << (8 * e);
+  }
+  const int cnt = __popcll(f8 & 0x0101010101010101ull);
+  int tot;
+  int t = w.blk[blockIdx.x] + block_exclusive_scan<TPB>(cnt, tmp, &tot);
+  if (cnt) {
+    int lo = 0, hi = A.n_units - 1;  // unit of the first flag: largest u with off[u] <= p0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (A.off[mid] <= p0) lo = mid; else hi = mid - 1;
     }
-    carry += tot;
+    for (int e = 0; e < PER; ++e) {
+      if ((f8 >> (8 * e)) & 1) {
+        const int64_t p = p0 + e;
+        while (A.off[lo + 1] <= p) ++lo;
+        w.trk_start[t] = int32_t(p);
+        w.trk_unit[t] = lo;
+        ++t;
+      }
+    }
   }
 }
 
