@@ -486,8 +486,9 @@ def main():
         summarize_profiles(args.summarize_profiles, args.workload)
         return
     if args.gpus != 1:
-        print("bench.py measures one MI355X; --gpus %d is not supported (units are independent, "
-              "see the sharding note in DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one MI355X; --gpus %d is not supported (sector units are independent, "
+              "so several GPUs would each take whole time frames or a share of a frame's units)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
