@@ -78,20 +78,21 @@ def src_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
+def measured_counters(kernel, workload):
+    """Counter figures of a kernel (HBM bytes per launch, VALU busy) from the
+    committed rocprofv3 runs, if they were taken on the current kernel source;
+    else {}."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
-        return None
+        return {}
     try:
         d = json.load(open(p))
     except ValueError:
-        return None
+        return {}
     e = d.get(workload, {}).get(kernel)
     if not e or e.get("src_digest") != src_digest():
-        return None
-    return e.get("bytes_per_launch")
+        return {}
+    return e
 
 
 def _short(name):
@@ -521,13 +522,22 @@ def main():
     log("bench: workspace %.2f GB" % (tr.ws_bytes / 1e9))
     stream = torch.cuda.current_stream(dev)
 
-    if args.calib_copy:  # a copy kernel of known size for the FETCH_SIZE / WRITE_SIZE scale
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            torch.neg(a, out=b)
-        torch.cuda.synchronize(dev)
-        del a, b
+    # a plain device copy (1 GiB read, 1 GiB written): the HBM rate a streaming
+    # kernel reaches here, and the known size that scales the byte counters
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3 if args.calib_copy else 5
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize(dev)
+    copy_gbs = 2.0 * a.numel() * 4 / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
 
     # warmup
     for _ in range(args.warmup):
@@ -603,7 +613,8 @@ def main():
     achieved = algo_bytes / (mean_k[dom] * 1e-3) / 1e9
     ms_per_step = wall / args.steps * 1e3
     value = batch.n * args.steps / wall
-    traffic = measured_traffic(dom_name, args.workload)
+    counters = measured_counters(dom_name, args.workload)
+    traffic = counters.get("bytes_per_launch")
     log("bench: per-kernel ms " + json.dumps(per_kernel))
 
     out = dict(
@@ -615,11 +626,13 @@ def main():
                     grid_shape=dict(shape, source=shape_source)),
         p50_ms=float(np.percentile(step_ms, 50)), p99_ms=float(np.percentile(step_ms, 99)),
         roofline=dict(bound="hbm", kernel=dom_name, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                      frac=achieved / HBM_PEAK_GBS, traffic=traffic, valu_busy=counters.get("valu_busy"),
                       algorithmic_bytes_per_launch=algo_bytes, mean_ms=float(mean_k[dom])),
         pipeline_roofline=dict(bytes_per_cluster=B_ALG_TOTAL,
                                achieved=B_ALG_TOTAL * value / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-                               frac=B_ALG_TOTAL * value / 1e9 / HBM_PEAK_GBS),
+                               frac=B_ALG_TOTAL * value / 1e9 / HBM_PEAK_GBS,
+                               measured_copy_gbs=copy_gbs,
+                               frac_of_copy=B_ALG_TOTAL * value / 1e9 / copy_gbs),
         kernel_ms=per_kernel, profiled_step_ms=profiled_step_ms,
         tracks=res["n_tracks"], tracklets=res["n_tracklets"],
     )
