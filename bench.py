@@ -432,6 +432,51 @@ def batched_bench(dev, reps):
     return out
 
 
+def central_bench(dev, reps, params):
+    """One central Pb-Pb collision (36 sector units, ~2.6 M clusters): the
+    whole event as one graph-replayed call against one call per sector."""
+    import numpy as np
+    import torch
+    from paper_2106_03636_amd.runtime import Batch, GraphRunner, Tracker
+
+    ev = make_workload("pbpb_central")
+    batch = Batch.from_event(ev, dev)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize(dev)
+        return e0.elapsed_time(e1) / k
+
+    tr = Tracker(batch.n, batch.n_units, batch.n_rows, params, device=dev)
+    g = GraphRunner(tr, batch)
+    one_ms = timed(g.replay, reps)
+    n_tracks = g.result()["n_tracks"]
+    del g, tr
+    sizes = np.diff(ev.unit_offsets)
+    subs = [Batch.from_device(batch.y[a:b], batch.z[a:b], batch.row[a:b], [0, b - a], ev.row_x, ev.bz)
+            for a, b in zip(ev.unit_offsets[:-1], ev.unit_offsets[1:])]
+    trp = Tracker(int(sizes.max()), 1, batch.n_rows, params, device=dev)
+
+    def plain():
+        for sb in subs:
+            trp.launch(sb)
+    plain_ms = timed(plain, reps)
+    n = float(batch.n)
+    out = dict(workload="pbpb_central", clusters=int(batch.n), units=int(batch.n_units), tracks=int(n_tracks),
+               one_call_graph=dict(value=n / one_ms * 1e3, ms=one_ms),
+               plain_per_sector=dict(value=n / plain_ms * 1e3, ms=plain_ms, calls=int(batch.n_units)),
+               unit="clusters/s")
+    log("bench: central Pb-Pb: one call %.3g, one call per sector %.3g clusters/s"
+        % (out["one_call_graph"]["value"], out["plain_per_sector"]["value"]))
+    return out
+
+
 def cpu_baseline(ev, n_units_sample, values, single_core_units=2):
     """The CPU oracle, as it stands, on the first n_units_sample units with all
     its threads, and on single_core_units units with one thread (the paper
@@ -658,6 +703,7 @@ def main():
     del tr
     torch.cuda.empty_cache()
     if not args.no_batched:
+        out["central"] = central_bench(dev, max(4, args.steps), params)
         out["batched"] = batched_bench(dev, max(4, args.steps))
         torch.cuda.empty_cache()
     if not args.no_serve:

@@ -1394,14 +1394,14 @@ __global__ void __launch_bounds__(TPB) k_chains(Args A) {
       if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
     }
     const int r1 = lo;
-    int L = 0, hb = h0;
+    // one walk; hm trails at half speed, so it ends on the chain's hit L/2
+    int L = 0, hb = h0, hm = h0;
     for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
       hb = h;
       ++L;
+      if ((L & 1) == 0) hm = w.upc[hm];
     }
     if (L >= A.p.l_min) {
-      int hm = h0;
-      for (int j = 0; j < L / 2; ++j) hm = w.upc[hm];
       w.trk_hm[t] = hm;
       w.trk_hb[t] = hb;
     }

@@ -261,20 +261,21 @@ def _unit_tracks(ev, g, units):
     return res_ct, res_par
 
 
-def _full_size_case(T, name, sample_units):
+def _full_size_case(T, name, sample_units, params=None):
     """Full-size batch on the GPU (as timed by the benchmark); the oracle runs
     on a sample of units, which are independent.  Checks (1) GPU(full batch)
     restricted to the sample == GPU(sample batch), bit for bit, and (2)
     GPU(sample batch) against the oracle at the parity bars."""
     import oracle
     import parity
-    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS
+    P = dict(DEFAULT_PARAMS if params is None else params)
     ev = cached_event(name)
-    _say("case full-size", name, ev.n, "clusters")
-    trf, resf = _run(T, ev)
+    _say("case full-size", name, ev.n, "clusters", {k: P[k] for k in ("bin_y_q", "bin_occ", "bin_zmin_q")})
+    trf, resf = _run(T, ev, P)
     gf = parity.gpu_state(trf, resf)
     sub = ev.subset_units(sample_units)
-    trs, ress = _run(T, sub)
+    trs, ress = _run(T, sub, P)
     gs = parity.gpu_state(trs, ress)
     ct_f, par_f = _unit_tracks(ev, gf, sample_units)
     ct_s, par_s = _unit_tracks(sub, gs, range(len(sample_units)))
@@ -292,6 +293,19 @@ def _full_size_case(T, name, sample_units):
 
 def test_parity_timeframe_full_size(T):
     _full_size_case(T, "pbpb_timeframe_50", [0, 13, 27])
+
+
+def test_parity_timeframe_full_size_tuned_shape(T):
+    """The grid shape the benchmark runs with (the autotune cache's entry for
+    this batch), at the benchmark's full size."""
+    from paper_2106_03636_amd import autotune
+    from paper_2106_03636_amd.runtime import Batch
+    ev = cached_event("pbpb_timeframe_50")
+    key = autotune.cache_key(Batch.from_event(ev))
+    cache = autotune.load_cache()
+    if key not in cache:
+        pytest.skip("no tuned shape cached for %s" % key)
+    _full_size_case(T, "pbpb_timeframe_50", [5, 22], params=autotune.tuned_params(Batch.from_event(ev)))
 
 
 def test_parity_uneven_chunks_full_size(T):
