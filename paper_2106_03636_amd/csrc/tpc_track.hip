@@ -1316,9 +1316,10 @@ __device__ __forceinline__ int round_offset(float v, int ref) {
 }
 
 // Least (w_y dY^2 + w_z dZ^2, id) inside the pickup window of the rounded
-// prediction.  The state is relative to the integer reference (Yr, Zr).
+// prediction, from the row's record rf (already loaded) and its bin-size
+// reciprocals inv.  The state is relative to the integer reference (Yr, Zr).
 // stop = 1 when the prediction has left the sector.
-__device__ int pick(const Args &A, const int32_t *rec, float2 inv, float yp, float zp, int Yr, int Zr,
+__device__ int pick(const Args &A, const Rec &rf, float2 inv, float yp, float zp, int Yr, int Zr,
                     bool &stop, int2 &best_yz) {
   const Workspace &w = A.w;
   const float vy = yp * 256.f, vz = zp * 256.f;
@@ -1327,7 +1328,6 @@ __device__ int pick(const Args &A, const int32_t *rec, float2 inv, float yp, flo
     return -1;
   }
   const int Yp = round_offset(vy, Yr);
-  const Rec rf = rec_fields_v(rec);
   if (abs(Yp) > rf.H + A.p.ext_edge_q) {
     stop = true;
     return -1;
@@ -1340,18 +1340,37 @@ __device__ int pick(const Args &A, const int32_t *rec, float2 inv, float yp, flo
   // windows < 2^13 and weights <= 15 keep the score below 2^31
   int best_s = INT32_MAX;
   int best = -1;
-  for (int iz = c.iz0; iz <= c.iz1; ++iz) {
-    const int cb = c.cbase + iz * c.ny;
-    const int q0 = w.cell[cb + c.iy0], q1 = w.cell[cb + c.iy1 + 1];
-    for (int q = q0; q < q1; ++q) {
-      const int2 h = w.syz[q];
-      const int dY = h.x - Yp, dZ = h.y - Zp;
-      if (abs(dY) > WY || abs(dZ) > WZ) continue;
-      const int sc = A.p.w_y * dY * dY + A.p.w_z * dZ * dZ;
-      if (sc < best_s || (sc == best_s && w.perm[q] < w.perm[best])) {
-        best_s = sc;
-        best = q;
-        best_yz = h;
+  // The cell bounds of up to ZB z bins are loaded together, and the hits of
+  // each bin HB at a time, so that one pickup waits for few round trips.
+  constexpr int ZB = 4, HB = 4;
+  for (int izb = c.iz0; izb <= c.iz1; izb += ZB) {
+    int qa[ZB], qb[ZB];
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const bool v = izb + k <= c.iz1;
+      const int cb = c.cbase + (izb + k) * c.ny;
+      qa[k] = v ? w.cell[cb + c.iy0] : 0;
+      qb[k] = v ? w.cell[cb + c.iy1 + 1] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      for (int q = qa[k]; q < qb[k]; q += HB) {
+        int2 hh[HB];
+#pragma unroll
+        for (int j = 0; j < HB; ++j) hh[j] = q + j < qb[k] ? w.syz[q + j] : make_int2(0, 0);
+#pragma unroll
+        for (int j = 0; j < HB; ++j) {
+          if (q + j >= qb[k]) break;
+          const int2 h = hh[j];
+          const int dY = h.x - Yp, dZ = h.y - Zp;
+          if (abs(dY) > WY || abs(dZ) > WZ) continue;
+          const int sc = A.p.w_y * dY * dY + A.p.w_z * dZ * dZ;
+          if (sc < best_s || (sc == best_s && w.perm[q + j] < w.perm[best])) {
+            best_s = sc;
+            best = q + j;
+            best_yz = h;
+          }
+        }
       }
     }
   }
@@ -1452,9 +1471,11 @@ __global__ void __launch_bounds__(TPB) k_compact_seeds(Args A) {
 // lane idles on rows outside its walk), so their hit-table accesses and
 // (unit,row) records coalesce; each lane's own sequence of operations is that
 // of its walk alone.
-// 5 waves per SIMD (96 registers): the walk waits on dependent gathers, and
-// measured faster than 4 (no spills, fewer waves) or 6-8 (more spills)
-__global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))) k_fit(Args A) {
+// 4 waves per SIMD (up to 128 registers): the walk waits on dependent
+// gathers, so each pickup loads its cell bounds and hits in batches (and the
+// row's record before the transport), which needs the registers; measured
+// faster than 5 waves with the batches spilled or without them
+__global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(4, 8))) k_fit(Args A) {
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int64_t n_seeds = w.ctr[C_SEEDS];
@@ -1522,6 +1543,13 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     int h = -1;
     int2 yz = make_int2(0, 0);
     const bool chain = r < r1 + L;
+    // the row's record for a pickup, loaded before the transport it waits on
+    Rec rf{};
+    float2 inv = make_float2(0.f, 0.f);
+    if (!chain) {
+      rf = rec_fields_v(segu + r * SEGW);
+      inv = invs[r];
+    }
     Step st;
     const float xr = A.row_x[r];
     if (!step_prepare(s, xr, k, smx, st)) {
@@ -1534,7 +1562,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
       yz = w.syz[h];
     } else {
       bool stop = false;
-      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
+      h = pick(A, rf, inv, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
       if (stop) {
         act = false;
         continue;
@@ -1566,6 +1594,8 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     if (!act || r >= r_out) continue;
     int h = r >= r1 ? col[r * 64] : -1;  // pass-1 hit of this row, if any
     int2 yz = make_int2(0, 0);
+    const Rec rf = rec_fields_v(segu + r * SEGW);
+    const float2 inv = invs[r];
     Step st;
     const float xr = A.row_x[r];
     if (!step_prepare(s, xr, k, smx, st)) {
@@ -1577,7 +1607,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
       yz = w.syz[h];
     } else {
       bool stop = false;
-      h = pick(A, segu + r * SEGW, invs[r], s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
+      h = pick(A, rf, inv, s.p[0] + st.dy, s.p[1] + s.p[3] * st.sT, Yr, Zr, stop, yz);
       if (stop) {
         act = false;
         continue;
