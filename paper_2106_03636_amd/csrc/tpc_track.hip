@@ -240,19 +240,22 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t n_work) {
   return (b & 7) * (n8 >> 3) + (b >> 3);
 }
 
+// Minimum and maximum over the 64 lanes (all lanes active).  The result is
+// moved to a scalar register, so loops bounded by it are uniform: their
+// counter, exit test and row-indexed loads stay scalar.
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
-constexpr int RB = 4;  // rows of the hit table read per round trip in the row loops
+constexpr int RB = 8;  // rows of the hit table read per round trip in the row loops
 constexpr int OWNED = 1 << 30;  // hit table entries (< 2^30) of hits their tracklet owns, once selected
 
 // Hit table of the seeds: [seed / 64][row][seed % 64], so the 64 lanes of a
