@@ -230,6 +230,7 @@ struct Batch {
   OutLayout L{};
   int slot = -1;
   int phase = 0;              // 0: kernels queued, 1: result copies queued
+  int32_t host_status = TPC_OK;  // set when the batch could not be launched (pinned memory)
   void *h_offsets = nullptr;  // pinned: unit offsets [n_units + 1], cluster and unit bases [R + 1] each
   std::shared_ptr<BatchOut> out;
   size_t out_bytes = 0;
@@ -356,6 +357,16 @@ void tpc_server::launch(Batch *b) {
   // concatenated unit offsets, then the requests' cluster and unit bases
   const size_t R = b->reqs.size(), nu1 = size_t(b->n_units) + 1;
   b->h_offsets = pinned.get(8 * (nu1 + 2 * (R + 1)));
+  b->out = std::make_shared<BatchOut>();
+  b->out->pool = &pinned;
+  // head: counts[4], status, pad[3], then per request its first track and hit
+  b->out->h_head = pinned.get(64 + 16 * (R + 1));
+  b->phase = 0;
+  if (!b->h_offsets || !b->out->h_head) {  // no pinned memory: the batch fails as a whole
+    b->host_status = TPC_E_NOMEM;
+    (void)hipEventRecord(s.ev_kernel, s.stream);
+    return;
+  }
   int64_t *ho = static_cast<int64_t *>(b->h_offsets);
   int64_t u = 0;
   ho[0] = 0;
@@ -416,10 +427,6 @@ void tpc_server::launch(Batch *b) {
     rc = tpc_internal::rebase_requests(reinterpret_cast<const int64_t *>(base + L.off_cbase),
                                        reinterpret_cast<const int64_t *>(base + L.off_ubase), int32_t(R), &o,
                                        b->n, reinterpret_cast<int64_t *>(base + L.off_req), s.stream);
-  b->out = std::make_shared<BatchOut>();
-  b->out->pool = &pinned;
-  // head: counts[4], status, pad[3], then per request its first track and hit
-  b->out->h_head = pinned.get(64 + 16 * (R + 1));
   int64_t *hh = static_cast<int64_t *>(b->out->h_head);
   hh[0] = hh[1] = hh[2] = hh[3] = 0;
   hh[4] = rc;  // launch status if the call failed on the host
@@ -429,7 +436,6 @@ void tpc_server::launch(Batch *b) {
     if (R > 1) (void)hipMemcpyAsync(hh + 8, base + L.off_req, 16 * (R + 1), hipMemcpyDeviceToHost, s.stream);
   }
   (void)hipEventRecord(s.ev_kernel, s.stream);
-  b->phase = 0;
 }
 
 // Advance the batch of a slot; true when something changed.
@@ -438,6 +444,11 @@ bool tpc_server::progress_slot(Slot &s) {
   if (!b) return false;
   if (b->phase == 0) {
     if (hipEventQuery(s.ev_kernel) != hipSuccess) return false;
+    if (b->host_status != TPC_OK) {
+      for (Request *r : b->reqs) r->status = b->host_status;
+      finish(b);
+      return true;
+    }
     const int64_t *hh = static_cast<const int64_t *>(b->out->h_head);
     const int32_t status = int32_t(reinterpret_cast<const int32_t *>(hh + 4)[0]);
     if (status != TPC_OK) {
@@ -454,6 +465,11 @@ bool tpc_server::progress_slot(Slot &s) {
     const size_t N = size_t(b->n);
     b->out_bytes = 4 * N + 4 * size_t(T) * (5 + 15 + 1 + 1 + 4) + 4 * size_t(H) + 64;
     b->out->h_out = pinned.get(b->out_bytes);
+    if (!b->out->h_out) {
+      for (Request *r : b->reqs) r->status = TPC_E_NOMEM;
+      finish(b);
+      return true;
+    }
     char *ho = static_cast<char *>(b->out->h_out);
     char *base = d_arena + b->arena_off;
     size_t o = 0;
@@ -594,8 +610,16 @@ extern "C" int tpc_server_create(const tpc_server_config_t *cfg, tpc_server_t **
   for (Slot &sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev_kernel, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&sl.ev_copy, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&sl.ev_copy, hipEventDisableTiming) != hipSuccess) {
+      for (Slot &q : s->slots) {  // undo what was made
+        if (q.ev_copy) (void)hipEventDestroy(q.ev_copy);
+        if (q.ev_kernel) (void)hipEventDestroy(q.ev_kernel);
+        if (q.stream) (void)hipStreamDestroy(q.stream);
+      }
+      (void)hipFree(s->d_row_x);
+      (void)hipFree(s->d_arena);
       return TPC_E_HIP;
+    }
   }
   s->st.arena_bytes = cfg->budget_bytes;
   tpc_server *raw = s.release();
