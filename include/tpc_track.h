@@ -297,7 +297,9 @@ int tpc_server_submit(tpc_server_t *server, const tpc_request_t *request, uint64
 /* Results of a ticket.  wait_us = 0: do not wait (TPC_E_BUSY if not done yet);
  * < 0: wait until done; > 0: wait up to that many microseconds.  Returns
  * TPC_OK when *result is filled (see result->status), TPC_E_BUSY if not done,
- * TPC_E_INVALID for an unknown ticket. */
+ * TPC_E_INVALID for an unknown ticket.  result->status is the tracking
+ * status, or TPC_E_NOMEM when the server could not get pinned host memory
+ * for the request's batch. */
 int tpc_server_poll(tpc_server_t *server, uint64_t ticket, tpc_result_t *result, int64_t wait_us);
 
 /* Free a completed request's results. */
