@@ -240,6 +240,46 @@ def test_rerun_is_bit_identical(T):
             assert a == c, k
 
 
+def test_profiled_launch_matches_plain(T):
+    """The launch that records an event pair around every kernel (used for the
+    per-kernel times) computes the same results as the plain launch."""
+    import ctypes
+    import torch
+    from paper_2106_03636_amd.runtime import Batch, Tracker
+    ev = cached_event("pbpb_central")
+    b = Batch.from_event(ev)
+    tr = Tracker(b.n, b.n_units, b.n_rows)
+    tr.launch(b)
+    ref = {k: (v.clone() if isinstance(v, torch.Tensor) else v) for k, v in tr.result().items()}
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    events = []
+    for _ in range(T.tpc_kernel_count() + 1):
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        events.append(e.value)
+    try:
+        tr.launch_profiled(b, events)
+        out = tr.result()
+        for k, v in ref.items():
+            if isinstance(v, torch.Tensor):
+                assert torch.equal(v, out[k]), k
+            else:
+                assert v == out[k], k
+        total = 0.0
+        for a, c in zip(events, events[1:]):
+            ms = ctypes.c_float()
+            assert hip.hipEventElapsedTime(ctypes.byref(ms), a, c) == 0
+            assert ms.value >= 0.0
+            total += ms.value
+        assert total > 0.0
+    finally:
+        for e in events:
+            hip.hipEventDestroy(e)
+
+
 def _unit_tracks(ev, g, units):
     """Per cluster of the given units: (local id of the track's start hit) or -1;
     and per track of those units: its params keyed by the start's local id."""
