@@ -1,0 +1,77 @@
+"""The pins catch plausible mistakes in the oracle (CPU).
+
+Each case copies the oracle's C source, plants one mistake of the kind a
+reader could make (a dropped term, a wrong factor, a swapped weight, a
+one-sided cleaning rule, a shifted key), builds the copy, points the oracle
+loader at it, and checks that at least one of the pins meant for that part
+fails.  The committed oracle is never modified.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+from conftest import cached_event, cached_oracle
+
+JAC_CASES = [([3.0, -20.0, 0.3, 0.7, -2.5], 40.0), ([10.0, 100.0, 0.05, 1.0, 8.0], -25.0)]
+
+MUTATIONS = [
+    ("jacobian_dy_dqpt",
+     "    F[0 * 5 + 4] = b;", "    F[0 * 5 + 4] = 0.5 * b;",
+     [lambda: [pins.test_jacobian_matches_finite_differences(p, dx) for p, dx in JAC_CASES]]),
+    ("propagation_dy",
+     "  const double dy = dx * N / D;", "  const double dy = dx * N / (D * 1.0001);",
+     [pins.test_propagation_matches_closed_form_crossings]),
+    ("kalman_cov_term",
+     "      nc[i * 5 + j] = cov[i * 5 + j] - (K[i][0] * cov[0 * 5 + j] + K[i][1] * cov[1 * 5 + j]);",
+     "      nc[i * 5 + j] = cov[i * 5 + j] - (K[i][0] * cov[0 * 5 + j]);",
+     [pins.test_kalman_equals_batch_least_squares, pins.test_fit_pulls_are_standard_normal]),
+    ("seed_half_angle",
+     "  const double sa = C * d13 * 0.5;", "  const double sa = C * d13 * 0.45;",
+     [pins.test_seed_exact_on_helix]),
+    ("score_weights_swapped",
+     "(__int128)P->w_y * Ry * Ry + (__int128)P->w_z * Rz * Rz",
+     "(__int128)P->w_z * Ry * Ry + (__int128)P->w_y * Rz * Rz",
+     [pins.test_golden_neighbour_rule, pins.test_neighbour_score_weights_decide]),
+    ("cleaning_one_sided",
+     "    upc[m] = (up[m] >= 0 && dn[up[m]] == m) ? up[m] : -1;",
+     "    upc[m] = up[m];",
+     [pins.test_cleaning_and_chain_invariants]),
+    ("owner_key_nfit_field",
+     "res->trk_key[t] = ((uint32_t)o.nfit << 24) | (0xFFFFFFu - local);",
+     "res->trk_key[t] = ((uint32_t)o.nfit << 20) | (0xFFFFFFu - local);",
+     [pins.test_owner_is_max_key_over_incidences, pins.test_selection_invariants]),
+]
+
+
+def _build_mutant(tmp_path, find, replace):
+    src = open(oracle._SRC).read()
+    assert src.count(find) == 1, "mutation site not unique: %r" % find
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(find, replace))
+    lib = tmp_path / "mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c11", "-D_POSIX_C_SOURCE=200809L", "-shared",
+                           "-fPIC", "-o", str(lib), str(path), "-lm"])
+    return str(lib)
+
+
+@pytest.mark.parametrize("name,find,replace,checks", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, name, find, replace, checks):
+    lib = _build_mutant(tmp_path, find, replace)
+    saved = (oracle._LIB, oracle._lib)
+    cached_oracle.cache_clear()
+    cached_event.cache_clear()
+    oracle._LIB, oracle._lib = lib, None
+    caught = []
+    try:
+        for check in checks:
+            try:
+                check()
+            except AssertionError as e:
+                caught.append(str(e)[:120])
+    finally:
+        oracle._LIB, oracle._lib = saved
+        cached_oracle.cache_clear()
+    assert caught, "no pin caught the planted mistake %s" % name

@@ -76,6 +76,22 @@ def test_golden_neighbour_rule():
     assert res["trk_len"].tolist() == [len(e["chain_from_start"])]
 
 
+def test_neighbour_score_weights_decide():
+    """Hand-derived: hit m (id 2, row 1, at the origin) has two pairs below it
+    with the same hit above (id 3, at the origin): id 0 off by 40 quanta in y,
+    id 1 off by 40 quanta in z.  With rows 256 quanta apart the residuals are
+    R = 256 (V_d + V_u), so the pairs score w_y (256*40)^2 and w_z (256*40)^2;
+    with w_y = 9 > w_z = 4 the z-displaced hit wins.  Both pass the windows
+    (|Y| <= 384, |Z| <= 640) and the cut smax_k (512)^2."""
+    assert P["w_y"] > P["w_z"]
+    row_x = [100.0, 101.0, 102.0]
+    Y = np.array([40, 0, 0, 0], np.float64)
+    Z = np.array([0, 40, 0, 0], np.float64)
+    res = oracle.run(Y / 256.0, Z / 256.0, [0, 0, 1, 2], [0, 4], row_x, 0.5, P)
+    assert _links_by_id(res, "dn").tolist()[2] == 1
+    assert _links_by_id(res, "up").tolist()[2] == 3
+
+
 # ----------------------------------------------------------------------------
 # O1/O2 hit grid
 
