@@ -39,6 +39,14 @@ MUTATIONS = [
      "    upc[m] = (up[m] >= 0 && dn[up[m]] == m) ? up[m] : -1;",
      "    upc[m] = up[m];",
      [pins.test_cleaning_and_chain_invariants]),
+    ("constructor_no_pass2_reset",
+     "    s = last;\n    cov_init(s.cov, P);\n    s.chi2 = 0;\n    int nfit = 0;",
+     "    s = last;\n    s.chi2 = 0;\n    int nfit = 0;",
+     [pins.test_constructor_fit_agrees_with_two_pass_fit]),
+    ("pickup_weights_swapped",
+     "const int64_t s = (int64_t)P->w_y * dY * dY + (int64_t)P->w_z * dZ * dZ;",
+     "const int64_t s = (int64_t)P->w_z * dY * dY + (int64_t)P->w_y * dZ * dZ;",
+     [pins.test_pickup_score_weights_decide]),
     ("owner_key_nfit_field",
      "res->trk_key[t] = ((uint32_t)o.nfit << 24) | (0xFFFFFFu - local);",
      "res->trk_key[t] = ((uint32_t)o.nfit << 20) | (0xFFFFFFu - local);",

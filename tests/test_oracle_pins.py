@@ -465,6 +465,78 @@ def _smeared_fits(n_tracks, seed, pt_range=(1.0, 10.0)):
     return np.array(pulls), fits
 
 
+def test_constructor_fit_agrees_with_two_pass_fit():
+    """The tracklet constructor (chain, extension pickups, two passes) on a
+    lone smeared primary that it follows through every row, against the
+    two-pass fit of the same hit list, which the other fit pins tie to the
+    truth.  Both reset the covariance for pass 2 and see the same hits; they
+    differ only in the pass-1 seed (the chain cannot hold the first and last
+    row, so the constructor seeds from rows 1 and n-2), which reaches the
+    result only through the finite pass-2 prior: within 0.1 sigma, diagonal
+    covariance within 1e-2, chi2 within 1e-3."""
+    rng = np.random.default_rng(31)
+    tr = synth.primaries_pp_sector(rng, 40, 0, pt_range=(1.0, 10.0))
+    xs = synth.helix_crossings(tr, 0.5)
+    k = -synth.KAPPA * 0.5
+    diag = [0, 2, 5, 9, 14]
+    n_checked = 0
+    for t in range(len(tr)):
+        st, rows = _local_states(tr, xs, t, 0)
+        if len(st) < 40:
+            continue
+        y = (np.array([q[1][0] for q in st]) + rng.normal(0, synth.SIGMA_Y, len(st))).astype(np.float32)
+        z = (np.array([q[1][1] for q in st]) + rng.normal(0, synth.SIGMA_Z, len(st))).astype(np.float32)
+        res = oracle.run(y, z, rows.astype(np.uint16), [0, len(y)], synth.ROW_X_F32, 0.5, P)
+        full = np.nonzero(res["trk_nfit"] == len(y))[0]
+        if len(full) == 0:
+            continue
+        tl = full[0]
+        ids = res["perm"][res["trk_hits"][tl, :len(y)]]
+        ids = ids[np.argsort(rows[ids])]
+        assert np.array_equal(np.sort(ids), np.arange(len(y)))  # every hit of the track, once
+        Y = np.rint(y[ids].astype(np.float64) * 256) / 256
+        Z = np.rint(z[ids].astype(np.float64) * 256) / 256
+        X = synth.ROW_X_F32[rows[ids]].astype(np.float64)
+        f = oracle.fit_two_pass(X, Y, Z, k, P)
+        assert f is not None
+        sig = np.sqrt(f["cov"][diag])
+        assert np.all(np.abs(res["trk_params"][tl] - f["p"]) <= 0.1 * sig), (res["trk_params"][tl], f["p"])
+        assert np.all(np.abs(res["trk_cov"][tl][diag] / f["cov"][diag] - 1) <= 1e-2)
+        assert abs(res["trk_chi2"][tl] / f["chi2"] - 1) <= 1e-3
+        n_checked += 1
+    assert n_checked >= 20
+
+
+def test_pickup_score_weights_decide():
+    """Hand-derived pickup: a straight track (Bz = 0) along y = z = 0 on rows
+    0..19 with no hit in row 10, and two decoys in row 10, one 240 quanta off
+    in y and one 240 quanta off in z.  Neither decoy links to its row
+    neighbours (its best straight-line residual 240 (X_11 - X_9) scores
+    w (240 (X_11 - X_9))^2 above the cut smax_k (X_11 - X_9)^2 for both
+    weights), so the chain stops at row 9 and the extension picks in row 10.  Both decoys are inside the pickup window (256 and 384 quanta);
+    they score w_y 240^2 and w_z 240^2, and with w_y = 9 > w_z = 4 the
+    z-displaced decoy is picked."""
+    assert P["w_y"] > P["w_z"] and P["ext_win_y_q"] > 240 and P["ext_win_z_q"] > 240
+    n_rows = 20
+    row_x = synth.ROW_X_F32[:n_rows]
+    X = np.rint(row_x.astype(np.float64) * 256)
+    assert P["w_z"] * (240 * (X[11] - X[9])) ** 2 > P["smax_k"] * (X[11] - X[9]) ** 2
+    rows = [r for r in range(n_rows) if r != 10] + [10, 10]
+    Y = np.zeros(len(rows))
+    Z = np.zeros(len(rows))
+    y_decoy, z_decoy = len(rows) - 2, len(rows) - 1
+    Y[y_decoy] = 240
+    Z[z_decoy] = 240
+    res = oracle.run(Y / 256.0, Z / 256.0, rows, [0, len(rows)], row_x, 0.0, P)
+    # rows 0 and n-1 take no links (no row beyond them), so the chain runs
+    # from the row-1 hit (id 1) to row 9
+    first = res["perm"][res["trk_start"]]
+    tl = int(np.nonzero(first == 1)[0][0])
+    assert res["trk_len"][tl] == 9
+    hit_ids = set(res["perm"][res["trk_hits"][tl, :res["trk_nfit"][tl]]].tolist())
+    assert z_decoy in hit_ids and y_decoy not in hit_ids
+
+
 def test_fit_pulls_are_standard_normal():
     pulls, _ = _smeared_fits(12000, 21)
     assert len(pulls) > 10000
