@@ -47,6 +47,13 @@ MUTATIONS = [
      "const int64_t s = (int64_t)P->w_y * dY * dY + (int64_t)P->w_z * dZ * dZ;",
      "const int64_t s = (int64_t)P->w_z * dY * dY + (int64_t)P->w_y * dZ * dZ;",
      [pins.test_pickup_score_weights_decide]),
+    ("walk_stops_one_miss_early",
+     "        } else if (++misses > P->max_miss) {",
+     "        } else if (++misses >= P->max_miss) {",
+     [pins.test_walk_crosses_max_miss_empty_rows_but_not_more]),
+    ("keep_threshold_strict",
+     "owned >= P->n_min &&", "owned > P->n_min &&",
+     [pins.test_keep_threshold_boundary, pins.test_selection_invariants]),
     ("owner_key_nfit_field",
      "res->trk_key[t] = ((uint32_t)o.nfit << 24) | (0xFFFFFFu - local);",
      "res->trk_key[t] = ((uint32_t)o.nfit << 20) | (0xFFFFFFu - local);",

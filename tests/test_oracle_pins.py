@@ -537,6 +537,44 @@ def test_pickup_score_weights_decide():
     assert z_decoy in hit_ids and y_decoy not in hit_ids
 
 
+def _straight_track(rows, n_rows):
+    """Hits of a straight track along y = z = 0 (Bz = 0) on the given rows."""
+    rows = list(rows)
+    return (np.zeros(len(rows)), np.zeros(len(rows)), rows, [0, len(rows)],
+            synth.ROW_X_F32[:n_rows])
+
+
+def test_walk_crosses_max_miss_empty_rows_but_not_more():
+    """Hand-derived: a straight track on rows 0..14 and, after a gap, on the
+    rows above it.  Its chain (rows 1..13; rows 0 and 14 take no links) is
+    extended upward; a walk stops after more than max_miss consecutive rows
+    without a hit.  A gap of exactly max_miss rows is crossed, so the
+    tracklet holds the hits on both sides; a gap one row longer is not."""
+    m = P["max_miss"]
+    for gap, crosses in ((m, True), (m + 1, False)):
+        top = 15 + gap + 10
+        rows = list(range(15)) + list(range(15 + gap, top))
+        y, z, r, off, row_x = _straight_track(rows, top)
+        res = oracle.run(y, z, r, off, row_x, 0.0, P)
+        first = res["perm"][res["trk_start"]]
+        tl = int(np.nonzero(first == 1)[0][0])  # the chain from the row-1 hit
+        assert res["trk_len"][tl] == 13
+        assert res["trk_nfit"][tl] == (25 if crosses else 15), (gap, res["trk_nfit"][tl])
+
+
+def test_keep_threshold_boundary():
+    """Hand-derived: a lone straight track owns all its hits.  With n_min = 10
+    a track of 10 hits is kept and one of 9 hits is not (owned fraction 1 >=
+    f_min in both)."""
+    assert P["n_min"] == 10 and P["f_min_q8"] <= 256
+    for n_hits, kept in ((10, 1), (9, 0)):
+        y, z, r, off, row_x = _straight_track(range(n_hits), n_hits + 2)
+        res = oracle.run(y, z, r, off, row_x, 0.0, P)
+        assert res["n_tracks"] == kept, (n_hits, res["n_tracks"])
+        if kept:
+            assert res["track_n_hits"][0] == n_hits
+
+
 def test_fit_pulls_are_standard_normal():
     pulls, _ = _smeared_fits(12000, 21)
     assert len(pulls) > 10000
