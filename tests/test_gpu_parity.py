@@ -87,6 +87,38 @@ def test_golden_neighbour_rule_gpu(T):
     _compare(T, ev, o)
 
 
+def _hand_derived_cases():
+    """The hand-derived toy events of the oracle pins: the score weights decide
+    a neighbour pair and a pickup, a walk crosses max_miss empty rows but not
+    one more, a track of n_min hits is kept and one of n_min - 1 is not."""
+    import synth
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    rx = synth.ROW_X_F32
+    cases = [_Ev(np.array([40, 0, 0, 0]) / 256.0, np.array([0, 40, 0, 0]) / 256.0, [0, 0, 1, 2], [0, 4],
+                 [100.0, 101.0, 102.0], 0.5, "neighbour_weights")]
+    rows = [r for r in range(20) if r != 10] + [10, 10]
+    y, z = np.zeros(len(rows)), np.zeros(len(rows))
+    y[-2], z[-1] = 240 / 256.0, 240 / 256.0
+    cases.append(_Ev(y, z, rows, [0, len(rows)], rx[:20], 0.0, "pickup_weights"))
+    m = P["max_miss"]
+    for gap in (m, m + 1):
+        rows = list(range(15)) + list(range(15 + gap, 25 + gap))
+        cases.append(_Ev(np.zeros(len(rows)), np.zeros(len(rows)), rows, [0, len(rows)], rx[:25 + gap], 0.0,
+                         "gap_%d" % gap))
+    for n_hits in (P["n_min"], P["n_min"] - 1):
+        cases.append(_Ev(np.zeros(n_hits), np.zeros(n_hits), list(range(n_hits)), [0, n_hits], rx[:n_hits + 2],
+                         0.0, "keep_%d" % n_hits))
+    return cases
+
+
+def test_parity_hand_derived_cases(T):
+    import oracle
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    for ev in _hand_derived_cases():
+        _say("case", ev.name, ev.n, "clusters")
+        _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
+
+
 def test_parity_pp_sector(T):
     _say("case pp_sector")
     _compare(T, cached_event("pp_sector"), cached_oracle("pp_sector"))
