@@ -89,8 +89,9 @@ def test_golden_neighbour_rule_gpu(T):
 
 def _hand_derived_cases():
     """The hand-derived toy events of the oracle pins: the score weights decide
-    a neighbour pair and a pickup, a walk crosses max_miss empty rows but not
-    one more, a track of n_min hits is kept and one of n_min - 1 is not."""
+    a neighbour pair and a pickup, a pickup tie goes to the smaller id, a walk
+    crosses max_miss empty rows but not one more, a track of n_min hits is
+    kept and one of n_min - 1 is not."""
     import synth
     from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
     rx = synth.ROW_X_F32
@@ -100,6 +101,9 @@ def _hand_derived_cases():
     y, z = np.zeros(len(rows)), np.zeros(len(rows))
     y[-2], z[-1] = 240 / 256.0, 240 / 256.0
     cases.append(_Ev(y, z, rows, [0, len(rows)], rx[:20], 0.0, "pickup_weights"))
+    y = np.zeros(len(rows))
+    y[-2], y[-1] = -200 / 256.0, 200 / 256.0
+    cases.append(_Ev(y, np.zeros(len(rows)), rows, [0, len(rows)], rx[:20], 0.0, "pickup_tie"))
     m = P["max_miss"]
     for gap in (m, m + 1):
         rows = list(range(15)) + list(range(15 + gap, 25 + gap))

@@ -54,6 +54,13 @@ MUTATIONS = [
     ("keep_threshold_strict",
      "owned >= P->n_min &&", "owned > P->n_min &&",
      [pins.test_keep_threshold_boundary, pins.test_selection_invariants]),
+    ("pickup_tie_reversed",
+     "if (s < best_s || (s == best_s && id < best_id)) {", "if (s < best_s || (s == best_s && id > best_id)) {",
+     [pins.test_pickup_tie_goes_to_the_smaller_id]),
+    ("chi2_z_term_dropped",
+     "  *chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);",
+     "  *chi2 += r0 * (I00 * r0 + I01 * r1);",
+     [pins.test_fit_chi2_per_degree_of_freedom_is_one]),
     ("owner_key_nfit_field",
      "res->trk_key[t] = ((uint32_t)o.nfit << 24) | (0xFFFFFFu - local);",
      "res->trk_key[t] = ((uint32_t)o.nfit << 20) | (0xFFFFFFu - local);",

@@ -544,6 +544,28 @@ def _straight_track(rows, n_rows):
             synth.ROW_X_F32[:n_rows])
 
 
+def test_pickup_tie_goes_to_the_smaller_id():
+    """Hand-derived: as in the weights case, but the two decoys in row 10 sit
+    200 quanta to either side in y, so they score the same; the one with the
+    smaller cluster id is picked, whichever side it is on.  (Neither links to
+    its row neighbours: w_y (200 (X_11 - X_9))^2 exceeds the cut.)"""
+    n_rows = 20
+    row_x = synth.ROW_X_F32[:n_rows]
+    X = np.rint(row_x.astype(np.float64) * 256)
+    assert P["w_y"] * (200 * (X[11] - X[9])) ** 2 > P["smax_k"] * (X[11] - X[9]) ** 2
+    assert P["ext_win_y_q"] > 200
+    rows = [r for r in range(n_rows) if r != 10] + [10, 10]
+    a_id, b_id = len(rows) - 2, len(rows) - 1
+    for ya, yb in ((200, -200), (-200, 200)):
+        Y = np.zeros(len(rows))
+        Y[a_id], Y[b_id] = ya, yb
+        res = oracle.run(Y / 256.0, np.zeros(len(rows)), rows, [0, len(rows)], row_x, 0.0, P)
+        first = res["perm"][res["trk_start"]]
+        tl = int(np.nonzero(first == 1)[0][0])
+        hit_ids = set(res["perm"][res["trk_hits"][tl, :res["trk_nfit"][tl]]].tolist())
+        assert a_id in hit_ids and b_id not in hit_ids, (ya, yb)
+
+
 def test_walk_crosses_max_miss_empty_rows_but_not_more():
     """Hand-derived: a straight track on rows 0..14 and, after a gap, on the
     rows above it.  Its chain (rows 1..13; rows 0 and 14 take no links) is
@@ -603,6 +625,16 @@ def _model_yz(p, x_ref, xs_rows, bz=0.5):
         if r not in out or s < out[r][2]:
             out[int(r)] = (yy, zz, s)
     return np.array([[out[r][0], out[r][1]] for r in xs_rows])
+
+
+def test_fit_chi2_per_degree_of_freedom_is_one():
+    """With the generator's Gaussian errors equal to the fit's, the filter's
+    chi2 over 2n measurements follows chi2 with 2n - 5 degrees of freedom:
+    its mean per degree of freedom is 1 (statistical error ~0.002 here)."""
+    _, fits = _smeared_fits(3000, 23)
+    assert len(fits) > 2000
+    r = np.array([f["chi2"] / (2 * len(x) - 5) for x, y, z, f, st in fits])
+    assert abs(r.mean() - 1.0) < 0.02, r.mean()
 
 
 def test_kalman_equals_batch_least_squares():
