@@ -432,14 +432,15 @@ def batched_bench(dev, reps):
     return out
 
 
-def central_bench(dev, reps, params):
-    """One central Pb-Pb collision (36 sector units, ~2.6 M clusters): the
-    whole event as one graph-replayed call against one call per sector."""
+def event_bench(dev, reps, params, name):
+    """One event (a central Pb-Pb collision: 36 sector units, ~2.6 M clusters;
+    or one pp sector): the whole event as one graph-replayed call against one
+    eager call per sector unit."""
     import numpy as np
     import torch
     from paper_2106_03636_amd.runtime import Batch, GraphRunner, Tracker
 
-    ev = make_workload("pbpb_central")
+    ev = make_workload(name)
     batch = Batch.from_event(ev, dev)
 
     def timed(fn, k):
@@ -468,12 +469,12 @@ def central_bench(dev, reps, params):
             trp.launch(sb)
     plain_ms = timed(plain, reps)
     n = float(batch.n)
-    out = dict(workload="pbpb_central", clusters=int(batch.n), units=int(batch.n_units), tracks=int(n_tracks),
+    out = dict(workload=name, clusters=int(batch.n), units=int(batch.n_units), tracks=int(n_tracks),
                one_call_graph=dict(value=n / one_ms * 1e3, ms=one_ms),
                plain_per_sector=dict(value=n / plain_ms * 1e3, ms=plain_ms, calls=int(batch.n_units)),
                unit="clusters/s")
-    log("bench: central Pb-Pb: one call %.3g, one call per sector %.3g clusters/s"
-        % (out["one_call_graph"]["value"], out["plain_per_sector"]["value"]))
+    log("bench: %s: one call %.3g, one call per sector %.3g clusters/s"
+        % (name, out["one_call_graph"]["value"], out["plain_per_sector"]["value"]))
     return out
 
 
@@ -703,7 +704,8 @@ def main():
     del tr
     torch.cuda.empty_cache()
     if not args.no_batched:
-        out["central"] = central_bench(dev, max(4, args.steps), params)
+        out["central"] = event_bench(dev, max(4, args.steps), params, "pbpb_central")
+        out["pp_sector"] = event_bench(dev, max(4, args.steps), params, "pp_sector")
         out["batched"] = batched_bench(dev, max(4, args.steps))
         torch.cuda.empty_cache()
     if not args.no_serve:
