@@ -144,6 +144,27 @@ def test_parity_tiny_crowded(T, seed):
     _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
 
 
+@pytest.mark.parametrize("per_row,z_max", [(8000, 250.0), (20000, 80.0)])
+def test_parity_crowded_rows(T, per_row, z_max):
+    """Three adjacent rows far denser than any time frame: 8000 hits per row
+    over 250 cm (more than a thread block keeps in registers while binning)
+    and 20000 over 80 cm (more than the binning's LDS pool, so the bins go
+    through the workspace; and neighbour slabs of ~1500 hits, too large for
+    LDS, so those chunks take the wide path)."""
+    import oracle
+    import synth
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
+    rng = np.random.default_rng(per_row)
+    rows = np.repeat(np.arange(10, 13), per_row)
+    half = synth.ROW_X_F32[rows].astype(np.float64) * np.tan(np.radians(10.0)) * 0.95
+    y = rng.uniform(-1, 1, len(rows)) * half
+    z = rng.uniform(0.0, z_max, len(rows))
+    order = rng.permutation(len(rows))
+    ev = _Ev(y[order], z[order], rows[order], [0, len(rows)], synth.ROW_X_F32, 0.5, "crowded%d" % per_row)
+    _say("case crowded rows", per_row)
+    _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
+
+
 def test_parity_ragged_units(T):
     """Units of very different sizes: empty, single cluster, one row only,
     several tiles with a ragged tail, and a full sector."""
