@@ -1194,7 +1194,8 @@ __global__ void __launch_bounds__(TPB) k_compact_starts(Args A) {
 
 struct KState {
   float p[5];
-  float c[15];  // lower triangle, row-major
+  float *c;  // covariance, lower triangle, row-major: element k at c[k * 64]
+             // (the lane's column of a [15][64] block of LDS)
   float x, chi2;
 };
 
@@ -1258,9 +1259,9 @@ __device__ __forceinline__ void step_apply(KState &s, const Step &t, float x2, f
   s.x = x2;
   // cov <- F cov F^T, F = I + {(0,2)=a, (0,4)=b, (1,2)=cc, (1,3)=d, (1,4)=e, (2,4)=f}
   float *c = s.c;
-  const float P00 = c[0], P10 = c[1], P11 = c[2], P20 = c[3], P21 = c[4], P22 = c[5], P30 = c[6],
-              P31 = c[7], P32 = c[8], P33 = c[9], P40 = c[10], P41 = c[11], P42 = c[12],
-              P43 = c[13], P44 = c[14];
+  const float P00 = c[0], P10 = c[64], P11 = c[128], P20 = c[192], P21 = c[256], P22 = c[320], P30 = c[384],
+              P31 = c[448], P32 = c[512], P33 = c[576], P40 = c[640], P41 = c[704], P42 = c[768],
+              P43 = c[832], P44 = c[896];
   // T = F P, rows 0..2
   const float T00 = P00 + a * P20 + b * P40, T02 = P20 + a * P22 + b * P42,
               T04 = P40 + a * P42 + b * P44;
@@ -1270,29 +1271,29 @@ __device__ __forceinline__ void step_apply(KState &s, const Step &t, float x2, f
   const float T20 = P20 + f * P40, T21 = P21 + f * P41, T22 = P22 + f * P42, T23 = P32 + f * P43,
               T24 = P42 + f * P44;
   c[0] = T00 + a * T02 + b * T04;
-  c[1] = T10 + a * T12 + b * T14;
-  c[2] = T11 + cc * T12 + d * T13 + e * T14;
-  c[3] = T20 + a * T22 + b * T24;
-  c[4] = T21 + cc * T22 + d * T23 + e * T24;
-  c[5] = T22 + f * T24;
-  c[6] = P30 + a * P32 + b * P43;
-  c[7] = P31 + cc * P32 + d * P33 + e * P43;
-  c[8] = P32 + f * P43;
-  c[10] = P40 + a * P42 + b * P44;
-  c[11] = P41 + cc * P42 + d * P43 + e * P44;
-  c[12] = P42 + f * P44;
+  c[64] = T10 + a * T12 + b * T14;
+  c[128] = T11 + cc * T12 + d * T13 + e * T14;
+  c[192] = T20 + a * T22 + b * T24;
+  c[256] = T21 + cc * T22 + d * T23 + e * T24;
+  c[320] = T22 + f * T24;
+  c[384] = P30 + a * P32 + b * P43;
+  c[448] = P31 + cc * P32 + d * P33 + e * P43;
+  c[512] = P32 + f * P43;
+  c[640] = P40 + a * P42 + b * P44;
+  c[704] = P41 + cc * P42 + d * P43 + e * P44;
+  c[768] = P42 + f * P44;
 }
 
 
 __device__ __forceinline__ void kf_update(KState &s, float my, float mz, float sy2, float sz2) {
   float *c = s.c;
   const float r0 = my - s.p[0], r1 = mz - s.p[1];
-  const float S00 = c[0] + sy2, S01 = c[1], S11 = c[2] + sz2;
+  const float S00 = c[0] + sy2, S01 = c[64], S11 = c[128] + sz2;
   const float idet = 1.f / (S00 * S11 - S01 * S01);
   const float I00 = S11 * idet, I01 = -S01 * idet, I11 = S00 * idet;
   // columns 0 and 1 of P (P_i0, P_i1)
-  const float q0[5] = {c[0], c[1], c[3], c[6], c[10]};
-  const float q1[5] = {c[1], c[2], c[4], c[7], c[11]};
+  const float q0[5] = {c[0], c[64], c[192], c[384], c[640]};
+  const float q1[5] = {c[64], c[128], c[256], c[448], c[704]};
   float K0[5], K1[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -1304,7 +1305,7 @@ __device__ __forceinline__ void kf_update(KState &s, float my, float mz, float s
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j, ++k) c[k] -= K0[i] * q0[j] + K1[i] * q1[j];
+    for (int j = 0; j <= i; ++j, ++k) c[k * 64] -= K0[i] * q0[j] + K1[i] * q1[j];
   s.chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
 }
 
@@ -1382,12 +1383,12 @@ __device__ int pick(const Args &A, const Rec &rf, float2 inv, float yp, float zp
 
 __device__ __forceinline__ void cov_reset(KState &s, const float *cov0) {
 #pragma unroll
-  for (int i = 0; i < 15; ++i) s.c[i] = 0.f;
+  for (int i = 0; i < 15; ++i) s.c[i * 64] = 0.f;
   s.c[0] = cov0[0];
-  s.c[2] = cov0[1];
-  s.c[5] = cov0[2];
-  s.c[9] = cov0[3];
-  s.c[14] = cov0[4];
+  s.c[2 * 64] = cov0[1];
+  s.c[5 * 64] = cov0[2];
+  s.c[9 * 64] = cov0[3];
+  s.c[14 * 64] = cov0[4];
 }
 
 // measurement of hit h relative to the reference (exact: integer difference)
@@ -1474,11 +1475,13 @@ __global__ void __launch_bounds__(TPB) k_compact_seeds(Args A) {
 // lane idles on rows outside its walk), so their hit-table accesses and
 // (unit,row) records coalesce; each lane's own sequence of operations is that
 // of its walk alone.
-// 4 waves per SIMD (up to 128 registers): the walk waits on dependent
-// gathers, so each pickup loads its cell bounds and hits in batches (and the
-// row's record before the transport), which needs the registers; measured
-// faster than 5 waves with the batches spilled or without them
-__global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(4, 8))) k_fit(Args A) {
+// 5 waves per SIMD (96 registers): the walk waits on dependent gathers, so
+// each pickup loads its cell bounds and hits in batches (and the row's record
+// before the transport), and each lane keeps its covariance in LDS rather
+// than in 15 registers, which frees the registers for the batches at 5
+// waves; measured faster than 4 waves with the covariance in registers and
+// than 6 waves (spills)
+__global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))) k_fit(Args A) {
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int64_t n_seeds = w.ctr[C_SEEDS];
@@ -1495,7 +1498,9 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(4, 8))
   int h0 = 0, u = 0, L = 0, r1 = 0, Yr = 0, Zr = 0;
   const int32_t *segu = w.seg;
   const float2 *invs = w.seg_inv;
+  __shared__ float cov_lds[CTB * 15];  // per wave [15][64]: lanes side by side, no bank conflicts
   KState s;
+  s.c = cov_lds + (threadIdx.x >> 6) * (15 * 64) + (threadIdx.x & 63);
   bool ok = false;
   if (valid) {
     h0 = w.trk_start[t];
@@ -1641,7 +1646,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
     for (int j = 0; j < 5; ++j) s.p[j] = 0.f;
 #pragma unroll
-    for (int j = 0; j < 15; ++j) s.c[j] = 0.f;
+    for (int j = 0; j < 15; ++j) s.c[j * 64] = 0.f;
     s.x = 0.f;
     s.chi2 = 0.f;
   }
@@ -1653,7 +1658,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
     for (int j = 0; j < 5; ++j) w.trk_par[t * 5 + j] = s.p[j];
 #pragma unroll
-    for (int j = 0; j < 15; ++j) w.trk_cov[t * 15 + j] = s.c[j];
+    for (int j = 0; j < 15; ++j) w.trk_cov[t * 15 + j] = s.c[j * 64];
     w.trk_x[t] = s.x;
     w.trk_chi2[t] = s.chi2;
   }
