@@ -255,7 +255,7 @@ __device__ __forceinline__ int wave_max(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
-constexpr int RB = 16;  // rows of the hit table read per round trip in the row loops
+constexpr int RB = 32;  // rows of the hit table read per round trip in the row loops
 constexpr int OWNED = 1 << 30;  // hit table entries (< 2^30) of hits their tracklet owns, once selected
 
 // Hit table of the seeds: [seed / 64][row][seed % 64], so the 64 lanes of a
