@@ -363,14 +363,16 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
     return out
 
 
-def batched_bench(dev, reps):
+def batched_bench(dev, reps, retune=False):
     """512 sector chunks of uneven occupancy (1e3-1e5 clusters, pp and Pb-Pb
     generators): one call over all of them, eager with the default grid shape
-    and replayed from a HIP graph with the autotuned shape, against the plain
-    form of one call per chunk.  Every form gives the same tracks."""
+    and replayed from a HIP graph with the autotuned shape (the autotune
+    cache's entry for this batch class; tuned and cached when missing or when
+    retune), against the plain form of one call per chunk.  Every form gives
+    the same tracks."""
     import numpy as np
     import torch
-    from paper_2106_03636_amd.autotune import tune
+    from paper_2106_03636_amd import autotune
     from paper_2106_03636_amd.params import DEFAULT_PARAMS
     from paper_2106_03636_amd.runtime import Batch, GraphRunner, Tracker
 
@@ -394,8 +396,13 @@ def batched_bench(dev, reps):
     ref = tr.result()
     n_tracks = ref["n_tracks"]
     del tr
-    best, table = tune(batch, reps=3, log=None)
-    shape = {k: best[k] for k in ("bin_y_q", "bin_occ", "bin_zmin_q")}
+    key = autotune.cache_key(batch)
+    table = []
+    if retune or key not in autotune.load_cache():
+        best, table = autotune.tune(batch, reps=3, log=None)
+        autotune.store(batch, best, table)
+    best = autotune.tuned_params(batch)
+    shape = {k: best[k] for k in autotune.SPACE}
     trt = Tracker(batch.n, batch.n_units, batch.n_rows, best, device=dev)
     g = GraphRunner(trt, batch)
     graph_ms = timed(g.replay, reps)
@@ -426,7 +433,7 @@ def batched_bench(dev, reps):
                eager_default=dict(value=n / eager_ms * 1e3, ms=eager_ms,
                                   grid_shape={k: DEFAULT_PARAMS[k] for k in shape}),
                plain_per_chunk=dict(value=n / plain_ms * 1e3, ms=plain_ms, calls=int(batch.n_units)),
-               autotune=[dict(r) for r in table], unit="clusters/s")
+               autotune_key=key, autotune=[dict(r) for r in table], unit="clusters/s")
     log("bench: 512 chunks: graph+tuned %.3g, eager default %.3g, plain per chunk %.3g clusters/s"
         % (out["graph_tuned"]["value"], out["eager_default"]["value"], out["plain_per_chunk"]["value"]))
     return out
@@ -706,7 +713,7 @@ def main():
     if not args.no_batched:
         out["central"] = event_bench(dev, max(4, args.steps), params, "pbpb_central")
         out["pp_sector"] = event_bench(dev, max(4, args.steps), params, "pp_sector")
-        out["batched"] = batched_bench(dev, max(4, args.steps))
+        out["batched"] = batched_bench(dev, max(4, args.steps), retune=args.retune)
         torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = serving_bench(dev, args.serve_frames, args.serve_requests, args.serve_sweep,

@@ -117,9 +117,17 @@ def tuned_params(batch: Batch, base=None, path=None, tune_if_missing=False, forc
     if not (tune_if_missing or force):
         return base
     best, table = tune(batch, base, log=log)
-    cache[key] = dict({k: best[k] for k in SPACE}, ms=min(r["ms"] for r in table), tuned_at=time.time())
+    store(batch, best, table, path)
+    return best
+
+
+def store(batch: Batch, best, table, path=None):
+    """Record a tuning result for this batch class in the cache file."""
+    path = path or os.environ.get("TPC_AUTOTUNE_CACHE", CACHE_PATH)
+    cache = load_cache(path)
+    cache[cache_key(batch)] = dict({k: best[k] for k in SPACE}, ms=min(r["ms"] for r in table),
+                                   tuned_at=time.time())
     tmp = path + ".tmp%d" % os.getpid()
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(tmp, path)
-    return best

@@ -10,23 +10,23 @@ Bars (the FP32 GPU fit against the FP64 oracle fit):
     limit);
   * fitted parameters of identical hit sets: |dp_k| <= 1e-4 max(|p_k|, f_k)
     with floors f = (1 cm, 1 cm, 1e-2, 1e-2, 0.1 /GeV) for at least 99.9% of
-    the fitted tracklets; |dp_k| <= max(that, 0.1 sigma_k) for at least
-    99.99% and max(that, 0.5 sigma_k) for every one (sigma from the oracle's
-    covariance); chi2 within 1e-3 relative (floor 1) for 99.9% and 2e-2 for
-    all; covariance diagonal within 1e-2 for 99.99% and 5e-2 for all, and
-    within 1e-3 for 99.5% on samples of at least 1e4 fitted tracklets (a
-    fraction that means something only on a large sample).
-    The clauses beyond the 99.9% one bound the few ill-conditioned fits
-    (short, low-pT, steep tracklets; chi2 per degree of freedom well above 1)
-    where FP32 cannot follow FP64 closer.  They are set from the oracle's own
-    steps evaluated in FP32 with the covariance kept as a symmetric lower
-    triangle, the way the kernel keeps it, against the FP64 oracle on all 36
-    sectors of the 50-collision time frame: 99.998% within max(1e-4, 0.1
-    sigma), at most 0.33 sigma; covariance diagonal 99.64% within 1e-3,
-    99.998% within 1e-2, at most 3.4e-2; chi2 at most 5.8e-3 (1.9e-2 with
-    the full 5x5 products).  The same exact-arithmetic steps in another
-    rounding order give tails of that size, so a tail of that size is
-    rounding, not a different computation;
+    the fitted tracklets (the benchmark spec's 1e-4 relative, read as a bar on
+    the bulk); every tracklet within max(that, 0.21 sigma_k) and at most
+    0.003% beyond max(that, 0.1 sigma_k) (sigma from the oracle's
+    covariance); chi2 within 1e-3 relative (floor 1) for 99.98% and within
+    2e-2 for all; covariance diagonal within 4.7e-2 for all, within 1e-2 for
+    99.998% and, on samples of at least 1e4 fitted tracklets, within 1e-3 for
+    99.6%.
+    The clauses beyond the 1e-4 one bound the few ill-conditioned fits (short,
+    low-pT, steep tracklets; chi2 per degree of freedom far above 1) where
+    FP32 cannot follow FP64 closer.  Each is no looser than the tail that
+    FP32 rounding alone produces: tests/test_fp32_bars.py builds two copies of
+    the oracle whose fit runs operation by operation in FP32 (full 5x5
+    covariance products, and the symmetric lower triangle the kernel keeps),
+    runs them on all 36 sectors of the 50-collision time frame, and checks
+    every clause against the worse of the two tails (maxima to within 5%,
+    fractions of outliers to within 10-50%, since the two builds' tails differ
+    by up to 9x between rounding orders);
   * owner keys, keep flags and the cluster-to-track map: bit-exact for every
     cluster and tracklet not touched by a differing tracklet.
 """
@@ -37,16 +37,17 @@ import numpy as np
 PARAM_FLOORS = np.array([1.0, 1.0, 1e-2, 1e-2, 0.1])
 PARAM_RTOL = 1e-4
 PARAM_SIGMA = 0.1
-PARAM_SIGMA_ALL = 0.5
-MIN_SIGMA_FRACTION = 0.9999
+PARAM_SIGMA_ALL = 0.21
+MIN_SIGMA_FRACTION = 0.99997
 COV_RTOL = 1e-3
 COV_RTOL_MID = 1e-2
-COV_RTOL_ALL = 5e-2
-MIN_COV_FRACTION = 0.995
-MIN_COV_MID_FRACTION = 0.9999
+COV_RTOL_ALL = 4.7e-2
+MIN_COV_FRACTION = 0.996
+MIN_COV_MID_FRACTION = 0.99998
 COV_FRACTION_MIN_SAMPLE = 10000
 CHI2_RTOL = 1e-3
 CHI2_RTOL_ALL = 2e-2
+MIN_CHI2_FRACTION = 0.9998
 MIN_MATCHED_FRACTION = 0.999
 MIN_WITHIN_FRACTION = 0.999
 
@@ -84,10 +85,7 @@ def gpu_state(tracker, result):
     g["seeds_expected"] = seeds
     raw = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(-1, n_rows, 64)
     per_seed = raw.transpose(0, 2, 1).reshape(-1, n_rows)[:len(seeds)]  # [seed][row]
-    per_seed = np.where(per_seed >= 0, per_seed & ((1 << 30) - 1), per_seed)  # drop the owned mark
-    hitrows = np.full((n_rows, K), -1, np.int32)
-    hitrows[:, seeds] = per_seed.T
-    g["trk_hitrows"] = hitrows  # [row][tracklet]
+    g["seed_hits"] = np.where(per_seed >= 0, per_seed & ((1 << 30) - 1), per_seed)  # drop the owned mark
     for k in ("n_tracks", "n_track_hits", "n_tracklets", "n_cells"):
         g[k] = result[k]
     for k in ("cluster_track", "params", "cov", "x_ref", "chi2", "unit", "n_hits", "n_fit",
@@ -96,26 +94,47 @@ def gpu_state(tracker, result):
     return g
 
 
-def gpu_hit_sets(g):
-    """Per tracklet: sorted array of hit positions from the by-row store."""
-    K = g["n_tracklets"]
-    H = g["trk_hitrows"]
-    out = []
-    for t in range(K):
-        lo, hi = g["trk_rlo"][t], g["trk_rhi"][t]
-        if g["trk_nfit"][t] <= 0 or lo < 0:
-            out.append(np.zeros(0, np.int64))
-            continue
-        h = H[lo:hi + 1, t]
-        out.append(np.sort(h[h >= 0]).astype(np.int64))
-    return out
+def gpu_hit_pairs(g):
+    """(tracklet, hit position) pairs of every fitted tracklet, sorted by
+    tracklet then position, from the by-row hit table of the seeds (rows
+    rlo..rhi of each seed are valid)."""
+    seeds = g["seeds_expected"]
+    H = g["seed_hits"]
+    if len(seeds) == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    lo, hi, nfit = g["trk_rlo"][seeds], g["trk_rhi"][seeds], g["trk_nfit"][seeds]
+    rows = np.arange(H.shape[1])[None, :]
+    m = (rows >= lo[:, None]) & (rows <= hi[:, None]) & (H >= 0) & (nfit[:, None] > 0) & (lo[:, None] >= 0)
+    j, _ = np.nonzero(m)
+    return _sorted_pairs(seeds[j].astype(np.int64), H[m].astype(np.int64))
 
 
-def oracle_hit_sets(o):
-    out = []
-    for t in range(o["n_tracklets"]):
-        out.append(np.sort(o["trk_hits"][t, :o["trk_nfit"][t]]).astype(np.int64))
-    return out
+def oracle_hit_pairs(o):
+    """The same pairs from the oracle's per-tracklet hit lists."""
+    H = o["trk_hits"]
+    nfit = o["trk_nfit"]
+    m = np.arange(H.shape[1])[None, :] < nfit[:, None]
+    t, _ = np.nonzero(m)
+    return _sorted_pairs(t.astype(np.int64), H[m].astype(np.int64))
+
+
+def _sorted_pairs(t, h):
+    key = (t << 32) | h
+    key.sort()
+    return key >> 32, key & 0xFFFFFFFF
+
+
+def hit_set_diff(gp, op, K):
+    """Tracklets whose hit sets differ, from sorted (tracklet, hit) pairs."""
+    cg, co = np.bincount(gp[0], minlength=K), np.bincount(op[0], minlength=K)
+    same_n = cg == co
+    sg, so = same_n[gp[0]], same_n[op[0]]
+    # tracklets with equal counts line up element by element in both sorted lists
+    neq = gp[1][sg] != op[1][so]
+    bad = np.zeros(K, bool)
+    bad[~same_n] = True
+    bad[gp[0][sg][neq]] = True
+    return bad
 
 
 class ParityReport(dict):
@@ -149,7 +168,7 @@ def compare_fit(rep, g_par, g_cov, g_chi2, g_xref, o_par, o_cov, o_chi2, o_xref,
         rep.fail("%d tracklets beyond max(1e-4 relative, 0.1 sigma)" % int((~mid).sum()))
     loose = np.all(dp <= np.maximum(tol, PARAM_SIGMA_ALL * sig), axis=1)
     if not loose.all():
-        rep.fail("%d tracklets beyond max(1e-4 relative, 0.5 sigma)" % int((~loose).sum()))
+        rep.fail("%d tracklets beyond max(1e-4 relative, %g sigma)" % (int((~loose).sum()), PARAM_SIGMA_ALL))
     gc, oc = np.asarray(g_cov, np.float64)[:, diag], np.asarray(o_cov, np.float64)[:, diag]
     crel = (np.abs(gc - oc) / np.maximum(np.abs(oc), 1e-12)).max(axis=1)
     rep["cov_max_rel"] = float(crel.max())
@@ -160,12 +179,13 @@ def compare_fit(rep, g_par, g_cov, g_chi2, g_xref, o_par, o_cov, o_chi2, o_xref,
     if rep["cov_within_1e-2"] < MIN_COV_MID_FRACTION:
         rep.fail("only %.5f of covariances within 1e-2" % rep["cov_within_1e-2"])
     if crel.max() > COV_RTOL_ALL * rtol_scale:
-        rep.fail("covariance beyond 5e-2: max %.3g" % crel.max())
+        rep.fail("covariance beyond %g: max %.3g" % (COV_RTOL_ALL, crel.max()))
     gx, ox = np.asarray(g_chi2, np.float64), np.asarray(o_chi2, np.float64)
     xrel = np.abs(gx - ox) / np.maximum(np.abs(ox), 1.0)
     rep["chi2_max_rel"] = float(xrel.max())
-    if (xrel <= CHI2_RTOL * rtol_scale).mean() < MIN_WITHIN_FRACTION or xrel.max() > CHI2_RTOL_ALL * rtol_scale:
-        rep.fail("chi2: %.5f within 1e-3, max %.3g" % ((xrel <= CHI2_RTOL).mean(), xrel.max()))
+    rep["chi2_within_1e-3"] = float((xrel <= CHI2_RTOL * rtol_scale).mean())
+    if rep["chi2_within_1e-3"] < MIN_CHI2_FRACTION or xrel.max() > CHI2_RTOL_ALL * rtol_scale:
+        rep.fail("chi2: %.5f within 1e-3, max %.3g" % (rep["chi2_within_1e-3"], xrel.max()))
     if not np.allclose(g_xref, o_xref, rtol=0, atol=1e-4):
         rep.fail("x_ref differs")
 
@@ -195,13 +215,14 @@ def compare(g, o, check_outputs=True, rtol_scale=1.0):
             rep.fail("%s differs" % k)
     if "seed_list" in g and not np.array_equal(g["seed_list"], g["seeds_expected"]):
         rep.fail("seed list is not the tracklets with a chain of >= l_min hits")
-    gs, os_ = gpu_hit_sets(g), oracle_hit_sets(o)
-    same = np.array([len(a) == len(b) and np.array_equal(a, b) for a, b in zip(gs, os_)], bool)
+    gp, op = gpu_hit_pairs(g), oracle_hit_pairs(o)
+    same = ~hit_set_diff(gp, op, K)
     same &= g["trk_nfit"] == o["trk_nfit"]
     diff = np.nonzero(~same)[0]
     rep["n_hitset_diff"] = int(len(diff))
     rep["n_fragile"] = int(o["trk_fragile"].sum())
     seeded = int((o["trk_nfit"] > 0).sum())
+    rep["n_fitted"] = seeded
     rep["matched_fraction"] = 1.0 - len(diff) / max(1, seeded)
     if rep["matched_fraction"] < MIN_MATCHED_FRACTION:
         rep.fail("only %.5f of tracklet hit sets match" % rep["matched_fraction"])
@@ -214,16 +235,15 @@ def compare(g, o, check_outputs=True, rtol_scale=1.0):
         compare_fit(rep, g["trk_params"][m], g["trk_cov"][m], g["trk_chi2"][m], g["trk_xref"][m],
                     o["trk_params"][m], o["trk_cov"][m], o["trk_chi2"][m], o["trk_xref"][m], rtol_scale)
     # --- ownership and selection away from differing tracklets
-    touched = np.zeros(len(g["perm"]), bool)
-    for t in diff:
-        touched[gs[t]] = True
-        touched[os_[t]] = True
+    n_pos = len(g["perm"])
+    is_diff = ~same
+    touched = np.zeros(n_pos, bool)
+    touched[gp[1][is_diff[gp[0]]]] = True
+    touched[op[1][is_diff[op[0]]]] = True
     # tracklets sharing a touched hit may change their owned count
-    affected = np.zeros(K, bool)
-    affected[diff] = True
-    for t in range(K):
-        if not affected[t] and (np.any(touched[gs[t]]) or np.any(touched[os_[t]])):
-            affected[t] = True
+    affected = is_diff.copy()
+    affected[gp[0][touched[gp[1]]]] = True
+    affected[op[0][touched[op[1]]]] = True
     rep["n_affected"] = int(affected.sum())
     ok_t = ~affected
     if not np.array_equal(g["trk_key"][ok_t], o["trk_key"][ok_t]):
@@ -234,9 +254,13 @@ def compare(g, o, check_outputs=True, rtol_scale=1.0):
     if not np.array_equal(g["trk_keep"][ok_t], o["trk_keep"][ok_t]) or \
             not np.array_equal(g["trk_owned"][ok_t], o["trk_owned"][ok_t]):
         rep.fail("selection differs on unaffected tracklets")
+    g_kept = np.nonzero(g["trk_keep"])[0]
+    if check_outputs and (len(g_kept) != g["n_tracks"] or
+                          (len(g["out_cluster_track"]) and g["out_cluster_track"].max() >= g["n_tracks"])):
+        rep.fail("kept tracklets (%d) and track outputs (%d tracks) disagree" % (len(g_kept), g["n_tracks"]))
+        check_outputs = False
     if check_outputs:
         # cluster -> tracklet (through the track list) must agree away from affected tracklets
-        g_kept = np.nonzero(g["trk_keep"])[0]
         o_kept = o["track_tracklet"]
         def _through(ct, kept):
             r = np.full(len(ct), -1, np.int64)
@@ -246,11 +270,10 @@ def compare(g, o, check_outputs=True, rtol_scale=1.0):
         gct = _through(g["out_cluster_track"], g_kept)
         oct_ = _through(o["cluster_track"], o_kept)
         perm = g["perm"]
-        aff_cluster = np.zeros(len(perm), bool)
         aff_pos = np.zeros(len(perm), bool)
-        for t in np.nonzero(affected)[0]:
-            aff_pos[gs[t]] = True
-            aff_pos[os_[t]] = True
+        aff_pos[gp[1][affected[gp[0]]]] = True
+        aff_pos[op[1][affected[op[0]]]] = True
+        aff_cluster = np.zeros(len(perm), bool)
         aff_cluster[perm[aff_pos]] = True
         bad = (gct != oct_) & ~aff_cluster
         rep["cluster_track_mismatch"] = int(bad.sum())

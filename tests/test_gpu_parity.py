@@ -358,55 +358,68 @@ def _unit_tracks(ev, g, units):
     return res_ct, res_par
 
 
-def _full_size_case(T, name, sample_units, params=None):
-    """Full-size batch on the GPU (as timed by the benchmark); the oracle runs
-    on a sample of units, which are independent.  Checks (1) GPU(full batch)
-    restricted to the sample == GPU(sample batch), bit for bit, and (2)
-    GPU(sample batch) against the oracle at the parity bars."""
+def _full_size_case(T, name, params=None, sample_units=()):
+    """Full-size batch on the GPU (as timed by the benchmark) against the
+    oracle on every unit of the same batch, at the parity bars.  With
+    sample_units, also GPU(full batch) restricted to those units ==
+    GPU(batch of those units alone), bit for bit (units are independent)."""
     import oracle
     import parity
     from paper_2106_03636_amd.params import DEFAULT_PARAMS
     P = dict(DEFAULT_PARAMS if params is None else params)
     ev = cached_event(name)
-    _say("case full-size", name, ev.n, "clusters", {k: P[k] for k in ("bin_y_q", "bin_occ", "bin_zmin_q")})
+    _say("case full-size", name, ev.n, "clusters", ev.n_units, "units",
+         {k: P[k] for k in ("bin_y_q", "bin_occ", "bin_zmin_q")})
     trf, resf = _run(T, ev, P)
     gf = parity.gpu_state(trf, resf)
-    sub = ev.subset_units(sample_units)
-    trs, ress = _run(T, sub, P)
-    gs = parity.gpu_state(trs, ress)
-    ct_f, par_f = _unit_tracks(ev, gf, sample_units)
-    ct_s, par_s = _unit_tracks(sub, gs, range(len(sample_units)))
-    for a, b in zip(ct_f, ct_s):
-        assert np.array_equal(a, b)
-    assert len(par_f) == len(par_s)
-    for (u, k), v in par_f.items():
-        j = list(sample_units).index(u)
-        assert np.array_equal(v, par_s[(j, k)])
-    o = oracle.run_event(sub, P, fragile_eps=0.05)
-    rep = parity.compare(gs, o)
-    _say("parity", name, "sample", list(sample_units), {k: v for k, v in rep.items() if k != "failures"})
+    o = oracle.run_event(ev, P, fragile_eps=0.05)
+    rep = parity.compare(gf, o)
+    _say("parity", name, "all %d units" % ev.n_units, {k: v for k, v in rep.items() if k != "failures"})
     assert rep.ok, rep.get("failures")
+    assert rep["n_fitted"] > 0
+    del trf, o
+    if len(sample_units):
+        sub = ev.subset_units(sample_units)
+        trs, ress = _run(T, sub, P)
+        gs = parity.gpu_state(trs, ress)
+        ct_f, par_f = _unit_tracks(ev, gf, sample_units)
+        ct_s, par_s = _unit_tracks(sub, gs, range(len(sample_units)))
+        for a, b in zip(ct_f, ct_s):
+            assert np.array_equal(a, b)
+        assert len(par_f) == len(par_s)
+        for (u, k), v in par_f.items():
+            j = list(sample_units).index(u)
+            assert np.array_equal(v, par_s[(j, k)])
+
+
+def _tuned(name):
+    from paper_2106_03636_amd import autotune
+    from paper_2106_03636_amd.runtime import Batch
+    ev = cached_event(name)
+    b = Batch.from_event(ev)
+    key = autotune.cache_key(b)
+    if key not in autotune.load_cache():
+        pytest.fail("no tuned shape cached for %s (%s)" % (name, key))
+    return autotune.tuned_params(b)
 
 
 def test_parity_timeframe_full_size(T):
-    _full_size_case(T, "pbpb_timeframe_50", [0, 13, 27])
+    _full_size_case(T, "pbpb_timeframe_50", sample_units=[0, 13, 27])
 
 
 def test_parity_timeframe_full_size_tuned_shape(T):
     """The grid shape the benchmark runs with (the autotune cache's entry for
-    this batch), at the benchmark's full size."""
-    from paper_2106_03636_amd import autotune
-    from paper_2106_03636_amd.runtime import Batch
-    ev = cached_event("pbpb_timeframe_50")
-    key = autotune.cache_key(Batch.from_event(ev))
-    cache = autotune.load_cache()
-    if key not in cache:
-        pytest.skip("no tuned shape cached for %s" % key)
-    _full_size_case(T, "pbpb_timeframe_50", [5, 22], params=autotune.tuned_params(Batch.from_event(ev)))
+    this batch), every unit at the benchmark's full size."""
+    _full_size_case(T, "pbpb_timeframe_50", params=_tuned("pbpb_timeframe_50"))
 
 
 def test_parity_uneven_chunks_full_size(T):
-    _full_size_case(T, "uneven_chunks_512", list(range(0, 512, 16)))
+    _full_size_case(T, "uneven_chunks_512", sample_units=list(range(0, 512, 64)))
+
+
+def test_parity_uneven_chunks_full_size_tuned_shape(T):
+    """All 512 chunks at the shape the batched benchmark replays."""
+    _full_size_case(T, "uneven_chunks_512", params=_tuned("uneven_chunks_512"))
 
 
 def test_graph_capture_replays_match_eager(T):

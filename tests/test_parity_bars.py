@@ -47,20 +47,20 @@ def test_one_large_shift_fails(fit):
     par = fit["trk_params"].copy()
     sig = np.sqrt(fit["trk_cov"][:, DIAG])
     t = int(np.argmax(np.abs(par[:, 0])))
-    par[t, 0] += 0.6 * sig[t, 0]  # y off by 0.6 sigma on one tracklet
+    par[t, 0] += 0.3 * sig[t, 0]  # y off by 0.3 sigma on one tracklet
     rep = _check(fit, par=par)
-    assert not rep.ok and any("0.5 sigma" in f for f in rep["failures"])
+    assert not rep.ok and any("0.21 sigma" in f for f in rep["failures"])
 
 
 def test_moderate_shift_on_a_few_fails(fit):
     par = fit["trk_params"].copy()
     sig = np.sqrt(fit["trk_cov"][:, DIAG])
     idx = np.arange(0, len(par), len(par) // 3)[:3]
-    par[idx, 2] += 0.2 * sig[idx, 2]  # sin(phi) off by 0.2 sigma on 3 tracklets
+    par[idx, 2] += 0.15 * sig[idx, 2]  # sin(phi) off by 0.15 sigma on 3 tracklets
     par[idx, 2] += 2e-4 * np.maximum(np.abs(par[idx, 2]), 1e-2)  # and beyond 1e-4 relative
     rep = _check(fit, par=par)
     assert not rep.ok and any("0.1 sigma" in f for f in rep["failures"])
-    assert not any("0.5 sigma" in f for f in rep["failures"])
+    assert not any("0.21 sigma" in f for f in rep["failures"])
 
 
 def test_swapped_tracklets_fail(fit):
@@ -74,9 +74,9 @@ def test_covariance_and_chi2_clauses(fit):
     cov = fit["trk_cov"].astype(np.float32).copy()
     cov[7, 14] *= 1.06  # q/pT variance off by 6% on one tracklet
     rep = _check(fit, cov=cov)
-    assert not rep.ok and any("5e-2" in f for f in rep["failures"])
+    assert not rep.ok and any("covariance beyond" in f for f in rep["failures"])
     cov = fit["trk_cov"].astype(np.float32).copy()
-    cov[7, 5] *= 1.02  # sin(phi) variance off by 2% on one tracklet: within 5e-2, beyond 1e-2
+    cov[7, 5] *= 1.02  # sin(phi) variance off by 2% on one tracklet: within 4.7e-2, beyond 1e-2
     rep = _check(fit, cov=cov)
     assert not rep.ok and any("within 1e-2" in f for f in rep["failures"])
     chi2 = fit["trk_chi2"].astype(np.float32).copy()
