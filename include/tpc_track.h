@@ -158,6 +158,26 @@ int tpc_track_sectors_profiled(const tpc_clusters_t *clusters, const tpc_geometr
                                tpc_tracks_t *out, void *workspace, size_t workspace_bytes,
                                void *stream, void *const *events, int32_t n_events);
 
+/* Bytes of the device scratch array tpc_track_sectors_noalloc uses as its
+ * workspace (one array per GPU, held from the library's first use on that GPU
+ * until the process ends). */
+#define TPC_SCRATCH_BYTES (64u << 20)
+
+/* Same as tpc_track_sectors, but allocates nothing and takes no workspace: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid allocation).  The workspace is the
+ * library's own scratch array on the device that runs `stream`; its address is
+ * looked up on the first call on each device.  Returns TPC_E_NOMEM when
+ * tpc_workspace_size() of the batch exceeds TPC_SCRATCH_BYTES, TPC_E_HIP when
+ * the array's address cannot be obtained; otherwise as tpc_track_sectors, with
+ * the same results.  All calls on one GPU share that GPU's array, which keeps
+ * the last call's contents (each call clears what it needs): calls that may
+ * overlap in time on one GPU (several streams or host threads) race and must
+ * be ordered by the caller, e.g. on one stream. */
+int tpc_track_sectors_noalloc(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry,
+                              const tpc_field_t *field, const tpc_params_t *params,
+                              tpc_tracks_t *out, void *stream);
+
 /* Number of kernels one call launches, and the name of kernel i (host-only). */
 int32_t tpc_kernel_count(void);
 const char *tpc_kernel_name(int32_t i);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "_tpctrack.so")
 
 TPC_PARAMS_VERSION = 1
 TPC_OK, TPC_E_INVALID, TPC_E_CAPACITY, TPC_E_NOMEM, TPC_E_HIP, TPC_E_BUSY = 0, -1, -2, -3, -4, -5
+TPC_SCRATCH_BYTES = 64 << 20
 
 (TPC_VIEW_PERM, TPC_VIEW_CELL, TPC_VIEW_SEG, TPC_VIEW_UP, TPC_VIEW_DN, TPC_VIEW_UPC, TPC_VIEW_DNC,
  TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN, TPC_VIEW_TRK_NFIT,
@@ -89,6 +90,10 @@ def load_library():
         lib.tpc_track_sectors_profiled.restype = ctypes.c_int
         lib.tpc_track_sectors_profiled.argtypes = lib.tpc_track_sectors.argtypes + [
             ctypes.POINTER(_vp), ctypes.c_int32]
+        lib.tpc_track_sectors_noalloc.restype = ctypes.c_int
+        lib.tpc_track_sectors_noalloc.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
+                                                  ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_params_t),
+                                                  ctypes.POINTER(tpc_tracks_t), _vp]
         lib.tpc_kernel_count.restype = ctypes.c_int32
         lib.tpc_kernel_name.restype = ctypes.c_char_p
         lib.tpc_kernel_name.argtypes = [ctypes.c_int32]
@@ -133,6 +138,13 @@ def tpc_track_sectors(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field:
     return int(load_library().tpc_track_sectors(ctypes.byref(clusters), ctypes.byref(geometry),
                                                 ctypes.byref(field), ctypes.byref(params),
                                                 ctypes.byref(out), workspace, workspace_bytes, stream))
+
+
+def tpc_track_sectors_noalloc(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t,
+                              params: tpc_params_t, out: tpc_tracks_t, stream: int) -> int:
+    return int(load_library().tpc_track_sectors_noalloc(ctypes.byref(clusters), ctypes.byref(geometry),
+                                                        ctypes.byref(field), ctypes.byref(params),
+                                                        ctypes.byref(out), stream))
 
 
 def tpc_track_sectors_profiled(clusters, geometry, field, params, out, workspace, workspace_bytes,

@@ -20,6 +20,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "tpc_track.h"
 
 namespace {
@@ -1925,6 +1927,59 @@ extern "C" int tpc_track_sectors_profiled(const tpc_clusters_t *c, const tpc_geo
                                           void *stream, void *const *events, int32_t n_events) {
   if (!events) return TPC_E_INVALID;
   return track_impl(c, g, f, p, out, workspace, ws_bytes, stream, events, n_events);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace for callers that cannot allocate: one file-scope device array per
+// GPU (the loader places a copy on every device the library runs on, and it
+// stays until the process ends).  Host code never passes the array's name to
+// a kernel: the name is a host-side stand-in.  Its device address is looked up
+// once per device with that device current and kept in scratch_ptr.
+
+__device__ __align__(256) unsigned char scratch[TPC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices];
+
+// Address of the scratch array on the device that runs `stream` (the current
+// device for the null stream), or nullptr when it cannot be obtained.
+void *scratch_for(hipStream_t stream) {
+  int dev = -1;
+  if (stream) {
+    if (hipStreamGetDevice(stream, &dev) != hipSuccess) return nullptr;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return nullptr;
+    scratch_ptr[dev] = p;
+  }
+  return scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int tpc_track_sectors_noalloc(const tpc_clusters_t *c, const tpc_geometry_t *g,
+                                         const tpc_field_t *f, const tpc_params_t *p,
+                                         tpc_tracks_t *out, void *stream) {
+  if (!c || !g || !p || !params_ok(p)) return TPC_E_INVALID;
+  const size_t need = tpc_workspace_size(c->n, c->n_units, g->n_rows, p);
+  if (need == 0) return TPC_E_INVALID;
+  if (need > size_t(TPC_SCRATCH_BYTES)) return TPC_E_NOMEM;
+  void *ws = scratch_for(static_cast<hipStream_t>(stream));
+  if (!ws) return TPC_E_HIP;
+  return track_impl(c, g, f, p, out, ws, size_t(TPC_SCRATCH_BYTES), stream, nullptr, 0);
 }
 
 extern "C" int32_t tpc_kernel_count(void) { return kNumKernels; }

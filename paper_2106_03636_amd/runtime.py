@@ -82,7 +82,10 @@ class Tracker:
     """Workspace + outputs for batches of up to max_n clusters / max_units units."""
 
     def __init__(self, max_n, max_units, n_rows=152, params=None, device="cuda", cap_tracks=None,
-                 cap_hits=None):
+                 cap_hits=None, workspace=True):
+        """workspace=False: no workspace is allocated and launches go through
+        tpc_track_sectors_noalloc (the library's fixed device scratch array;
+        no intermediate arrays to inspect)."""
         self.values = dict(DEFAULT_PARAMS if params is None else params)
         self.params = make_params(self.values)
         self.device = torch.device(device)
@@ -91,7 +94,7 @@ class Tracker:
         if ws == 0:
             raise ValueError("invalid batch shape or parameters")
         self.ws_bytes = ws
-        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device) if workspace else None
         n_min = max(1, int(self.values["n_min"]))
         self.cap_tracks = int(cap_tracks if cap_tracks is not None else self.max_n // n_min + 1)
         self.cap_hits = int(cap_hits if cap_hits is not None else self.max_n)
@@ -131,10 +134,16 @@ class Tracker:
         f = tpc_field_t()
         f.bz_tesla = batch.bz
         o = self.tracks_struct()
-        st = tpc_track_sectors(c, g, f, self.params, o, self.workspace.data_ptr(), self.ws_bytes,
-                               s.cuda_stream)
+        if self.workspace is None:
+            from . import tpc_track_sectors_noalloc
+            st = tpc_track_sectors_noalloc(c, g, f, self.params, o, s.cuda_stream)
+            name = "tpc_track_sectors_noalloc"
+        else:
+            st = tpc_track_sectors(c, g, f, self.params, o, self.workspace.data_ptr(), self.ws_bytes,
+                                   s.cuda_stream)
+            name = "tpc_track_sectors"
         if st != TPC_OK:
-            raise TrackingError(st, "tpc_track_sectors: %s" % tpc_status_string(st))
+            raise TrackingError(st, "%s: %s" % (name, tpc_status_string(st)))
         self._last = batch
         return st
 
@@ -176,6 +185,8 @@ class Tracker:
 
     def inspect(self, what, dtype=torch.int32, shape=None):
         """Copy of an intermediate workspace array of the last launch (tpc_inspect)."""
+        if self.workspace is None:
+            raise ValueError("a tracker without a workspace has no intermediate arrays")
         b = self._last
         v = tpc_inspect(b.clusters_struct(), b.n_rows, self.params, self.workspace.data_ptr(), what)
         base = self.workspace.data_ptr()
