@@ -16,7 +16,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(HERE, "tpc_oracle.c")
-_LIB = os.path.join(HERE, "_oracle.so")
+# TPC_ORACLE_LIB: another build of the same source (the sanitizer test uses it)
+_LIB = os.environ.get("TPC_ORACLE_LIB") or os.path.join(HERE, "_oracle.so")
 
 
 def build(force: bool = False) -> str:

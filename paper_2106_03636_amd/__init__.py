@@ -179,4 +179,10 @@ def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, wor
 
 # --- torch convenience ---------------------------------------------------------------
 
-from .runtime import Tracker, track  # noqa: E402,F401
+def __getattr__(name):
+    # the torch-side helpers load on first use, so that importing the package
+    # (e.g. for its parameter values) does not import torch
+    if name in ("Tracker", "track"):
+        from . import runtime
+        return getattr(runtime, name)
+    raise AttributeError(name)

@@ -1329,7 +1329,10 @@ __device__ int pick(const Args &A, const Rec &rf, float2 inv, float yp, float zp
                     bool &stop, int2 &best_yz) {
   const Workspace &w = A.w;
   const float vy = yp * 256.f, vz = zp * 256.f;
-  if (!(fabsf(vy) < 1.0e9f)) {
+  // a prediction that is not finite (or beyond 4e15 quanta) ends the walk;
+  // one beyond every cluster (|v| >= 1e9 quanta) is outside the sector in y
+  // (a stop) and outside every window in z (a miss)
+  if (!(fabsf(vy) < 1.0e9f) || !(fabsf(vz) < 4.0e15f)) {
     stop = true;
     return -1;
   }
@@ -1338,7 +1341,7 @@ __device__ int pick(const Args &A, const Rec &rf, float2 inv, float yp, float zp
     stop = true;
     return -1;
   }
-  if (!(fabsf(vz) < 1.0e9f)) return -1;  // beyond every cluster: a miss
+  if (!(fabsf(vz) < 1.0e9f)) return -1;
   const int Zp = round_offset(vz, Zr);
   const int WY = A.p.ext_win_y_q, WZ = A.p.ext_win_z_q;
   const Win c = window_cells(rf, inv, Yp - WY, Yp + WY, Zp - WZ, Zp + WZ);

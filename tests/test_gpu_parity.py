@@ -90,8 +90,11 @@ def test_golden_neighbour_rule_gpu(T):
 def _hand_derived_cases():
     """The hand-derived toy events of the oracle pins: the score weights decide
     a neighbour pair and a pickup, a pickup tie goes to the smaller id, a walk
-    crosses max_miss empty rows but not one more, a track of n_min hits is
-    kept and one of n_min - 1 is not."""
+    crosses max_miss empty rows but not one more (upward, and downward below
+    the chain), a track of n_min hits is kept and one of n_min - 1 is not, a
+    walk stops where its prediction leaves the sector, and a pickup 0.01
+    quanta from a rounding boundary (flagged fragile by the oracle; the GPU
+    must still take the same decision)."""
     import synth
     from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
     rx = synth.ROW_X_F32
@@ -112,6 +115,16 @@ def _hand_derived_cases():
     for n_hits in (P["n_min"], P["n_min"] - 1):
         cases.append(_Ev(np.zeros(n_hits), np.zeros(n_hits), list(range(n_hits)), [0, n_hits], rx[:n_hits + 2],
                          0.0, "keep_%d" % n_hits))
+    import test_oracle_pins as pins
+    for gap in (m, m + 1):
+        (y, z, r, off, row_x), _ = pins.pass2_gap_event(gap)
+        cases.append(_Ev(y, z, r, off, row_x, 0.0, "pass2_gap_%d" % gap))
+    for far in (True, False):
+        (y, z, r, off, row_x), _ = pins.edge_stop_event(with_far_hit=far)
+        cases.append(_Ev(y, z, r, off, row_x, 0.0, "edge_stop_%s" % far))
+    for x10, yd in ((128.47, 9 - P["ext_win_y_q"]), (127.6, 9 - P["ext_win_y_q"]), (128.47, 9)):
+        y, z, r, off, row_x = pins.fragile_event(x10, yd)
+        cases.append(_Ev(y, z, r, off, row_x, 0.0, "fragile_%g_%d" % (x10, yd)))
     return cases
 
 
@@ -120,7 +133,8 @@ def test_parity_hand_derived_cases(T):
     from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
     for ev in _hand_derived_cases():
         _say("case", ev.name, ev.n, "clusters")
-        _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
+        _, rep = _compare(T, ev, oracle.run_event(ev, P, fragile_eps=0.05))
+        assert rep["n_hitset_diff"] == 0, ev.name
 
 
 def test_parity_pp_sector(T):

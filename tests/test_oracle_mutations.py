@@ -61,6 +61,22 @@ MUTATIONS = [
      "  *chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);",
      "  *chi2 += r0 * (I00 * r0 + I01 * r1);",
      [pins.test_fit_chi2_per_degree_of_freedom_is_one]),
+    ("pass2_stops_one_miss_early",
+     "      } else if (r < r1 && ++misses > P->max_miss) {",
+     "      } else if (r < r1 && ++misses >= P->max_miss) {",
+     [pins.test_pass2_crosses_max_miss_empty_rows_below_the_chain_but_not_more]),
+    ("no_sector_edge_stop",
+     "  if (llabs(Yp) > g->H + P->ext_edge_q) {",
+     "  if (0 && llabs(Yp) > g->H + P->ext_edge_q) {",
+     [pins.test_walk_stops_where_the_prediction_leaves_the_sector]),
+    ("fragile_ignores_a_changed_pick",
+     "          if (r2.found != r.found || r2.stop != r.stop) *fragile = 1;",
+     "          if (r2.stop != r.stop) *fragile = 1;",
+     [pins.test_fragile_flag_marks_only_decisions_a_rounding_boundary_can_flip]),
+    ("fragile_margin_inverted",
+     "    const int ny = fabs(fy - 0.5) < eps, nz = fabs(fz - 0.5) < eps;",
+     "    const int ny = fabs(fy - 0.5) > eps, nz = fabs(fz - 0.5) > eps;",
+     [pins.test_fragile_flag_marks_only_decisions_a_rounding_boundary_can_flip]),
     ("owner_key_nfit_field",
      "res->trk_key[t] = ((uint32_t)o.nfit << 24) | (0xFFFFFFu - local);",
      "res->trk_key[t] = ((uint32_t)o.nfit << 20) | (0xFFFFFFu - local);",

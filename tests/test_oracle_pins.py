@@ -584,6 +584,108 @@ def test_walk_crosses_max_miss_empty_rows_but_not_more():
         assert res["trk_nfit"][tl] == (25 if crosses else 15), (gap, res["trk_nfit"][tl])
 
 
+def pass2_gap_event(gap):
+    """A straight track (y = z = 0, Bz = 0) on rows 0..4 and, after `gap`
+    empty rows, on 13 rows above them; the last row (one above) is empty."""
+    a = 5 + gap
+    top = a + 13
+    rows = list(range(5)) + list(range(a, top))
+    return _straight_track(rows, top + 1), a
+
+
+def test_pass2_crosses_max_miss_empty_rows_below_the_chain_but_not_more():
+    """Hand-derived: the hit at the gap's upper edge has no row below to pair
+    with, so the chain starts one row above it (rows a+1..a+11; the top hit
+    has no row above).  Pass 1 extends it to the top hit; pass 2 walks down,
+    reuses those hits, picks the hit at row a below the chain, then counts
+    misses in the gap: a gap of exactly max_miss rows is crossed and the
+    five hits under it are picked (18 hits); a gap one row longer stops the
+    walk (13 hits)."""
+    m = P["max_miss"]
+    for gap, crosses in ((m, True), (m + 1, False)):
+        (y, z, r, off, row_x), a = pass2_gap_event(gap)
+        res = oracle.run(y, z, r, off, row_x, 0.0, P)
+        first = res["perm"][res["trk_start"]]
+        tl = int(np.nonzero(first == 6)[0][0])  # the chain from the hit of row a + 1 (id 6)
+        assert res["trk_len"][tl] == 11
+        assert res["trk_nfit"][tl] == (18 if crosses else 13), (gap, res["trk_nfit"][tl])
+
+
+TAN_HALF_Q16 = P["tan_half_q16"]
+
+
+def edge_stop_event(with_far_hit=True):
+    """A straight track (Bz = 0) that leaves the sector through its +y edge.
+    Rows 0..11 at x = 100 + 3r cm, hits on rows 0..9 at Y_r = Y_9 - 192 (9 - r)
+    quanta (64 quanta per cm of x), row 10 empty, and on row 11 a hit exactly
+    where the line crosses it.  Returns the event and the quantities the pin
+    derives by hand."""
+    x = 100.0 + 3.0 * np.arange(12)
+    X = (x * 256).astype(np.int64)
+    H = (X * TAN_HALF_Q16) >> 16  # row half widths (R-2)
+    Y9 = int(H[9]) + 300  # beyond the edge, inside the margin
+    rows = list(range(10)) + ([11] if with_far_hit else [])
+    Y = [Y9 - 192 * (9 - r) for r in range(10)] + ([Y9 + 2 * 192] if with_far_hit else [])
+    ev = (np.asarray(Y, np.float64) / 256.0, np.zeros(len(rows)), rows, [0, len(rows)], x.astype(np.float32))
+    return ev, dict(H=H, Y9=Y9, Yp10=Y9 + 192, Yp11=Y9 + 2 * 192)
+
+
+def test_walk_stops_where_the_prediction_leaves_the_sector():
+    """Hand-derived: the chain is rows 1..8 (rows 0 and 11 are edge rows; row 9
+    has no row-10 partner).  Pass 1 picks the row-9 hit (|Y_9| = H_9 + 300
+    <= H_9 + margin), misses row 10 (|Y_p| - H_10 <= margin: no stop), and at
+    row 11 the prediction is more than the margin (384 quanta) beyond the
+    edge, so the walk stops and the hit lying exactly on the prediction there
+    is not picked: 10 hits (row 0 comes from pass 2).  Without that hit the
+    tracklet is the same."""
+    edge = P["ext_edge_q"]
+    (y, z, r, off, row_x), h = edge_stop_event()
+    H = h["H"]
+    assert h["Y9"] - H[9] <= edge and h["Yp10"] - H[10] <= edge and h["Yp11"] - H[11] > edge
+    res = oracle.run(y, z, r, off, row_x, 0.0, P)
+    first = res["perm"][res["trk_start"]]
+    tl = int(np.nonzero(first == 1)[0][0])
+    assert res["trk_len"][tl] == 8
+    hit_ids = set(res["perm"][res["trk_hits"][tl, :res["trk_nfit"][tl]]].tolist())
+    assert hit_ids == set(range(10)), sorted(hit_ids)
+    (y2, z2, r2, off2, _), _ = edge_stop_event(with_far_hit=False)
+    res2 = oracle.run(y2, z2, r2, off2, row_x, 0.0, P)
+    assert res2["trk_nfit"].max() == 10
+
+
+def fragile_event(x10, y_decoy):
+    """A straight track (Bz = 0) with Y = r quanta on rows r = 0..9 at
+    x = 100 + 3r cm, so the line through them predicts Y = (x - 100)/3 exactly;
+    row 10 at x10 holds one decoy hit at y_decoy quanta; row 11 (x10 + 3) is
+    empty."""
+    x = np.array([100.0 + 3.0 * r for r in range(10)] + [x10, x10 + 3.0], np.float32)
+    Y = np.array(list(range(10)) + [y_decoy], np.float64)
+    rows = list(range(11))
+    return Y / 256.0, np.zeros(11), rows, [0, 11], x
+
+
+def test_fragile_flag_marks_only_decisions_a_rounding_boundary_can_flip():
+    """Hand-derived: the prediction in row 10 is vy = (x10 - 100)/3 quanta.
+    With x10 = 128.47 cm it is 9.49, 0.01 quanta from the boundary 9.5: it
+    rounds to 9 and the decoy at 9 - 256 sits exactly on the window's edge
+    (picked), while a rounding to 10 would leave it 257 away (not picked), so
+    the decision is fragile.  With x10 = 127.6 (vy = 9.2, far from any
+    boundary), or with the decoy at 9 (picked under either rounding), nothing
+    is flagged.  The decoy is picked in all three."""
+    W = P["ext_win_y_q"]
+    assert W == 256
+    for x10, yd, fragile in ((128.47, 9 - W, 1), (127.6, 9 - W, 0), (128.47, 9, 0)):
+        vy = (float(np.float32(x10)) - 100.0) / 3.0
+        assert (abs(vy - 9.5) < 0.05) == (x10 == 128.47)
+        y, z, r, off, row_x = fragile_event(x10, yd)
+        res = oracle.run(y, z, r, off, row_x, 0.0, P, fragile_eps=0.05)
+        first = res["perm"][res["trk_start"]]
+        tl = int(np.nonzero(first == 1)[0][0])
+        hit_ids = set(res["perm"][res["trk_hits"][tl, :res["trk_nfit"][tl]]].tolist())
+        assert 10 in hit_ids, (x10, yd, sorted(hit_ids))
+        assert res["trk_fragile"][tl] == fragile, (x10, yd)
+
+
 def test_keep_threshold_boundary():
     """Hand-derived: a lone straight track owns all its hits.  With n_min = 10
     a track of 10 hits is kept and one of 9 hits is not (owned fraction 1 >=
