@@ -39,7 +39,9 @@
  *     (invalid clusters, capacities exceeded) are written to *out->status on
  *     the device; read it after the stream completes.  When it is not TPC_OK,
  *     no track output is valid; out->counts still reports required sizes for
- *     TPC_E_CAPACITY.
+ *     TPC_E_CAPACITY: counts[0] and [1] against cap_tracks and cap_hits,
+ *     counts[4] (seeds) against the seed capacity n / tracklet_cap_div + 64
+ *     (retry with a div of at most n / (counts[4] - 64), or l_min).
  */
 #ifndef TPC_TRACK_H
 #define TPC_TRACK_H
@@ -107,7 +109,11 @@ typedef struct tpc_params {
   int32_t max_miss;            /* ... or after more than max_miss consecutive misses */
   int32_t n_min;               /* selector: at least n_min owned hits */
   int32_t f_min_q8;            /* selector: owned * 256 >= f_min_q8 * hits */
-  int32_t tracklet_cap_div;    /* internal tracklet capacity = n / div + 64 (>= 2) */
+  int32_t tracklet_cap_div;    /* seed capacity = n / div + 64 (>= 2): tracklets with a chain
+                                  of >= l_min hits that the constructor fits; the workspace
+                                  holds a 152-row hit table per seed.  Seeds never exceed
+                                  n / l_min, so div = l_min can never overflow; 16 holds the
+                                  synthetic Pb-Pb time frames (about n / 27 seeds) */
   float sinphi_max;            /* walks stop when |sin(phi)| reaches this (0 < . < 1) */
   float sigma_y, sigma_z;      /* cluster resolution (cm), Kalman measurement errors */
   float cov0[5];               /* diagonal of the initial covariance */
@@ -129,7 +135,7 @@ typedef struct tpc_tracks {
   int32_t *n_fit;              /* [cap_tracks] hits used by the fit (ndf = 2 n_fit - 5) */
   int32_t *first_hit;          /* [cap_tracks] offset into hits */
   int32_t *hits;               /* [cap_hits] cluster ids */
-  int64_t *counts;             /* [4] n_tracks, n_track_hits, n_tracklets, n_grid_cells */
+  int64_t *counts;             /* [5] n_tracks, n_track_hits, n_tracklets, n_grid_cells, n_seeds */
   int32_t *status;             /* [1] TPC_OK or a negative status (see above) */
 } tpc_tracks_t;
 
@@ -194,22 +200,27 @@ const char *tpc_status_string(int status);
  *   TPC_VIEW_UP/DN     int32 [n]  neighbour links (sorted positions, -1 none)
  *   TPC_VIEW_UPC/DNC   int32 [n]  links after cleaning
  *   TPC_VIEW_OWNER     uint32 [n] owner key per sorted position
- *   TPC_VIEW_TRK_*     per tracklet (capacity entries, the first counts[2] valid):
- *     START int32, UNIT int32, LEN int32, NFIT int32, RLO int32, RHI int32,
- *     KEY uint32, OWNED int32, KEEP int32, PARAMS float[5], COV float[15],
- *     XREF float, CHI2 float.
- *   TPC_VIEW_SEED_LIST int32 [capacity] the seeds (tracklets with LEN >= l_min)
- *                      in tracklet order; the first (number of seeds) valid.
- *   TPC_VIEW_TRK_HITS  int32 [ceil(capacity/64)][n_rows][64] hit of each row
+ *   TPC_VIEW_TRK_START, _UNIT, _LEN  int32 per tracklet (capacity n/2 + 64, the
+ *                      first counts[2] valid): start hit (sorted position), unit,
+ *                      chain length.
+ *   TPC_VIEW_TRK_*     the other tracklet fields, per SEED (seed capacity entries,
+ *                      the first counts[4] valid; seed i is tracklet SEED_LIST[i];
+ *                      tracklets that are not seeds have no fit, no hits, no key):
+ *     NFIT int32, RLO int32, RHI int32, KEY uint32, OWNED int32, KEEP int32,
+ *     PARAMS float[5], COV float[15], XREF float, CHI2 float, P1N int32.
+ *   TPC_VIEW_SEED_LIST int32 [seed capacity] the seeds (tracklets with LEN >= l_min)
+ *                      in tracklet order.
+ *   TPC_VIEW_TRK_HITS  int32 [ceil(seed capacity/64)][n_rows][64] hit of each row
  *                      (-1 none) of seed i at [i/64][row][i%64], rows RLO..RHI
- *                      of its tracklet valid; bit 30 is set on the hits the
- *                      tracklet owns (the position is the low 30 bits). */
+ *                      of the seed valid; bit 30 is set on the hits the
+ *                      tracklet owns (the position is the low 30 bits).
+ *   P1N is the number of hits (Kalman updates) of the constructor's first pass. */
 enum {
   TPC_VIEW_PERM = 1, TPC_VIEW_CELL, TPC_VIEW_SEG, TPC_VIEW_UP, TPC_VIEW_DN, TPC_VIEW_UPC,
   TPC_VIEW_DNC, TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN,
   TPC_VIEW_TRK_NFIT, TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI, TPC_VIEW_TRK_KEY,
   TPC_VIEW_TRK_OWNED, TPC_VIEW_TRK_KEEP, TPC_VIEW_TRK_PARAMS, TPC_VIEW_TRK_COV,
-  TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2, TPC_VIEW_TRK_HITS, TPC_VIEW_SEED_LIST
+  TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2, TPC_VIEW_TRK_HITS, TPC_VIEW_SEED_LIST, TPC_VIEW_TRK_P1N
 };
 
 typedef struct tpc_view {

@@ -23,7 +23,7 @@ TPC_SCRATCH_BYTES = 64 << 20
  TPC_VIEW_OWNER, TPC_VIEW_TRK_START, TPC_VIEW_TRK_UNIT, TPC_VIEW_TRK_LEN, TPC_VIEW_TRK_NFIT,
  TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI, TPC_VIEW_TRK_KEY, TPC_VIEW_TRK_OWNED, TPC_VIEW_TRK_KEEP,
  TPC_VIEW_TRK_PARAMS, TPC_VIEW_TRK_COV, TPC_VIEW_TRK_XREF, TPC_VIEW_TRK_CHI2,
- TPC_VIEW_TRK_HITS, TPC_VIEW_SEED_LIST) = range(1, 24)
+ TPC_VIEW_TRK_HITS, TPC_VIEW_SEED_LIST, TPC_VIEW_TRK_P1N) = range(1, 25)
 
 _vp = ctypes.c_void_p
 
@@ -117,7 +117,7 @@ def make_params(values: dict | None = None, **overrides) -> tpc_params_t:
                  "w_y", "w_z", "smax_k", "l_min", "ext_win_y_q", "ext_win_z_q", "ext_edge_q",
                  "max_miss", "n_min", "f_min_q8"):
         setattr(p, name, int(v[name]))
-    p.tracklet_cap_div = int(v.get("tracklet_cap_div", 4))
+    p.tracklet_cap_div = int(v.get("tracklet_cap_div", 16))
     p.sinphi_max = float(v["sinphi_max"])
     p.sigma_y = float(v["sigma_y"])
     p.sigma_z = float(v["sigma_z"])

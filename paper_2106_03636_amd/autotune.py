@@ -43,7 +43,7 @@ def _partition_key(tr: Tracker, res):
     ct = res["cluster_track"].cpu().numpy()
     if res["n_tracks"] == 0:
         return ct
-    keep = tr.inspect(T.TPC_VIEW_TRK_KEEP).cpu().numpy()[:res["n_tracklets"]]
+    keep = tr.tracklet_field(T.TPC_VIEW_TRK_KEEP)
     start = tr.inspect(T.TPC_VIEW_TRK_START).cpu().numpy()[:res["n_tracklets"]]
     perm = tr.inspect(T.TPC_VIEW_PERM).cpu().numpy()
     first = perm[start[np.nonzero(keep)[0]]]

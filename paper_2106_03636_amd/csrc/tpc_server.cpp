@@ -211,7 +211,7 @@ bool batch_layout(int64_t n, int32_t n_units, int32_t R, int32_t n_rows, const t
   L->off_nfit = take(4 * T);
   L->off_first = take(4 * T);
   L->off_hits = take(4 * size_t(L->cap_hits));
-  L->off_counts = take(4 * 8);
+  L->off_counts = take(5 * 8);
   L->off_status = take(8);
   L->off_cbase = take(8 * (size_t(R) + 1));
   L->off_ubase = take(8 * (size_t(R) + 1));

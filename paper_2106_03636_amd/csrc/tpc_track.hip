@@ -38,7 +38,7 @@ constexpr float KAPPA = 0.00299792458f;
 enum { S_START = 0, S_COUNT, S_ZMIN, S_ZMAX, S_H, S_BY, S_NY, S_BZ, S_NZ, S_CBASE, S_CHUNK };
 // internal counters
 enum { C_K = 0, C_CELLS = 1, C_TRACKS = 2, C_HITS = 3, C_TILES = 4, C_NCHUNK = 5, C_SEEDS = 6, C_NWIDE = 7,
-       C_N = 8 };
+       C_TICKET = 8, C_N = 9 };
 
 struct Workspace {
   int64_t *ctr;
@@ -54,13 +54,18 @@ struct Workspace {
   uint32_t *owner;
   int32_t *cell, *cursor;
   int32_t *chunk_seg, *wide;  // neighbour-finder chunk -> (unit,row); chunks too wide for LDS
-  int32_t *blk, *blk_keep, *blk_own;
-  int32_t *trk_start, *trk_unit, *trk_len, *trk_nfit, *trk_rlo, *trk_rhi, *trk_owned, *trk_keep;
-  int32_t *trk_r1, *trk_hm, *trk_hb, *seed_list;
-  uint32_t *trk_key;
-  float *trk_par, *trk_cov, *trk_x, *trk_chi2;
-  int32_t *trk_hits;
-  int64_t N, S, T_max, C_max, K_cap, NB, KB, KW, CH_max;
+  int32_t *blk, *blk_keep;
+  uint64_t *lookback;  // per seed block: decoupled look-back word of the selector
+  // per tracklet (chain start), capacity T_cap = n/2 + 64: a start hit has an
+  // upward partner that starts nothing, so there are at most n/2
+  int32_t *trk_start, *trk_unit, *trk_len;
+  int32_t *tmp_r1, *tmp_hm, *tmp_hb;  // per tracklet, k_chains -> k_compact_seeds (aliases the hit table)
+  // per seed (tracklet with a chain of >= l_min hits), capacity S_cap
+  int32_t *seed_list, *sd_r1, *sd_hm, *sd_hb, *sd_nfit, *sd_rlo, *sd_rhi, *sd_owned, *sd_keep, *sd_p1n;
+  uint32_t *sd_key;
+  float *sd_par, *sd_cov, *sd_x, *sd_chi2;
+  int32_t *trk_hits;  // seed hit table [S_cap / 64][n_rows][64]
+  int64_t N, S, T_max, C_max, T_cap, S_cap, NB, KB, SB, KW, CH_max;
   size_t total;
 };
 
@@ -92,10 +97,12 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.S = int64_t(n_units) * n_rows;
   L.T_max = n / TILE + n_units + 1;
   L.C_max = n / p->bin_occ + 65 * L.S + 1;
-  L.K_cap = n / p->tracklet_cap_div + 64;
+  L.T_cap = n / 2 + 64;
+  L.S_cap = n / p->tracklet_cap_div + 64;
   L.NB = (n + ELEMS - 1) / ELEMS + 1;
-  L.KB = (L.K_cap + TPB - 1) / TPB;
-  L.KW = (L.K_cap + 63) / 64;
+  L.KB = (L.T_cap + TPB - 1) / TPB;
+  L.SB = (L.S_cap + TPB - 1) / TPB;
+  L.KW = (L.S_cap + 63) / 64;
   L.CH_max = n / NCH + L.S;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -103,7 +110,7 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
     o = align256(o + bytes);
     return base ? base + at : nullptr;
   };
-  const size_t N = size_t(n), S = size_t(L.S), K = size_t(L.K_cap);
+  const size_t N = size_t(n), S = size_t(L.S), T = size_t(L.T_cap), K = size_t(L.S_cap);
   L.ctr = (int64_t *)take(sizeof(int64_t) * C_N);
   L.seg = (int32_t *)take(4 * S * SEGW);
   L.seg_cnt = (int32_t *)take(4 * S);
@@ -113,8 +120,6 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.seg_inv = (float2 *)take(8 * S);
   L.unit_tiles = (int32_t *)take(4 * (size_t(n_units) + 1));
   L.tile_hist = (int32_t *)take(4 * size_t(n_rows) * size_t(L.T_max));
-  L.rs_idx = (int32_t *)take(4 * N);
-  L.rs_yz = (int2 *)take(8 * N);
   L.perm = (int32_t *)take(4 * N);
   L.syz = (int2 *)take(8 * N);
   L.up = (int32_t *)take(4 * N);
@@ -124,30 +129,46 @@ bool layout(int64_t n, int32_t n_units, int32_t n_rows, const tpc_params_t *p, c
   L.flag = (uint8_t *)take(N + 16);
   L.owner = (uint32_t *)take(4 * N);
   L.cell = (int32_t *)take(4 * (size_t(L.C_max) + 1));
-  L.cursor = (int32_t *)take(4 * size_t(L.C_max));
   L.chunk_seg = (int32_t *)take(4 * size_t(L.CH_max));
   L.wide = (int32_t *)take(4 * size_t(L.CH_max));
   L.blk = (int32_t *)take(4 * size_t(L.NB));
   L.blk_keep = (int32_t *)take(4 * size_t(L.KB));
-  L.blk_own = (int32_t *)take(4 * size_t(L.KB));
-  L.trk_start = (int32_t *)take(4 * K);
-  L.trk_unit = (int32_t *)take(4 * K);
-  L.trk_len = (int32_t *)take(4 * K);
-  L.trk_nfit = (int32_t *)take(4 * K);
-  L.trk_rlo = (int32_t *)take(4 * K);
-  L.trk_rhi = (int32_t *)take(4 * K);
-  L.trk_owned = (int32_t *)take(4 * K);
-  L.trk_keep = (int32_t *)take(4 * K);
-  L.trk_key = (uint32_t *)take(4 * K);
-  L.trk_r1 = (int32_t *)take(4 * K);
-  L.trk_hm = (int32_t *)take(4 * K);
-  L.trk_hb = (int32_t *)take(4 * K);
+  L.lookback = (uint64_t *)take(8 * size_t(L.SB));
+  L.trk_start = (int32_t *)take(4 * T);
+  L.trk_unit = (int32_t *)take(4 * T);
+  L.trk_len = (int32_t *)take(4 * T);
   L.seed_list = (int32_t *)take(4 * K);
-  L.trk_par = (float *)take(4 * 5 * K);
-  L.trk_cov = (float *)take(4 * 15 * K);
-  L.trk_x = (float *)take(4 * K);
-  L.trk_chi2 = (float *)take(4 * K);
-  L.trk_hits = (int32_t *)take(4 * size_t(n_rows) * 64 * size_t(L.KW));
+  L.sd_r1 = (int32_t *)take(4 * K);
+  L.sd_hm = (int32_t *)take(4 * K);
+  L.sd_hb = (int32_t *)take(4 * K);
+  L.sd_nfit = (int32_t *)take(4 * K);
+  L.sd_rlo = (int32_t *)take(4 * K);
+  L.sd_rhi = (int32_t *)take(4 * K);
+  L.sd_owned = (int32_t *)take(4 * K);
+  L.sd_keep = (int32_t *)take(4 * K);
+  L.sd_p1n = (int32_t *)take(4 * K);
+  L.sd_key = (uint32_t *)take(4 * K);
+  L.sd_par = (float *)take(4 * 5 * K);
+  L.sd_cov = (float *)take(4 * 15 * K);
+  L.sd_x = (float *)take(4 * K);
+  L.sd_chi2 = (float *)take(4 * K);
+  // The seed hit table is written only by the tracklet constructor.  Before
+  // it, the same memory holds arrays that are dead by then: the row-sorted
+  // hits and the bin cursors of the grid build, and the per-tracklet seed
+  // fields k_chains hands to k_compact_seeds.
+  const size_t table = 4 * size_t(n_rows) * 64 * size_t(L.KW);
+  const size_t grid_tmp = align256(4 * N) + align256(8 * N) + align256(4 * size_t(L.C_max));
+  const size_t chain_tmp = 3 * align256(4 * T);
+  const size_t region = table > grid_tmp ? (table > chain_tmp ? table : chain_tmp)
+                                         : (grid_tmp > chain_tmp ? grid_tmp : chain_tmp);
+  char *r = (char *)take(region);
+  L.trk_hits = (int32_t *)r;
+  L.rs_idx = (int32_t *)r;
+  L.rs_yz = (int2 *)(r ? r + align256(4 * N) : nullptr);
+  L.cursor = (int32_t *)(r ? r + align256(4 * N) + align256(8 * N) : nullptr);
+  L.tmp_r1 = (int32_t *)r;
+  L.tmp_hm = (int32_t *)(r ? r + align256(4 * T) : nullptr);
+  L.tmp_hb = (int32_t *)(r ? r + 2 * align256(4 * T) : nullptr);
   L.total = o;
   *w = L;
   return true;
@@ -280,7 +301,9 @@ __global__ void k_init(Args A) {
     A.out.cluster_track[i] = -1;
   }
   if (i < C_N) w.ctr[i] = 0;
-  if (i < 4) A.out.counts[i] = 0;
+  if (i < w.SB) w.lookback[i] = 0;
+  if (i < w.KB) w.blk_keep[i] = 0;
+  if (i < 5) A.out.counts[i] = 0;
   if (i == 0) *A.out.status = TPC_OK;
 }
 
@@ -828,7 +851,8 @@ __device__ __forceinline__ Cand cand_window(const int32_t *rec, float2 inv, int 
   return k;
 }
 
-constexpr int MAXU = 4;  // row-above candidates kept in registers
+constexpr int MAXU = 8;  // row-above candidates kept in registers
+constexpr int MAXD = 8;  // row-below candidates kept in registers
 
 // Scores of rows whose S_max is below 2^48 are evaluated in FP64 exactly:
 // a residual of 2^24 or more (with a nonzero weight) puts the score at 2^48
@@ -837,8 +861,32 @@ constexpr int MAXU = 4;  // row-above candidates kept in registers
 constexpr double SMAX_F64 = 281474976710656.0;  // 2^48
 constexpr double RES_F64 = 16777216.0;          // 2^24
 
+// Positions of the candidates of one neighbour row that pass the exact
+// window, in grid order; at most N are kept (more set `overflow`).
+template <bool LDS, int N>
+__device__ __forceinline__ int collect(const Workspace &w, const Cand &k, const Slab &sl, const int *lc,
+                                       const int2 *lh, int zlo, int zhi, int (&q)[N], bool &overflow) {
+  int n = 0;
+  for (int iz = k.c.iz0; iz <= k.c.iz1; ++iz) {
+    const int cb = k.c.cbase + iz * k.c.ny;
+    const int v0 = cell_at<LDS>(w, sl, lc, cb + k.c.iy0), v1 = cell_at<LDS>(w, sl, lc, cb + k.c.iy1 + 1);
+    for (int p = v0; p < v1; ++p) {
+      const int2 hp = hit_at<LDS>(w, sl, lh, p);
+      if (hp.x < k.ylo || hp.x > k.yhi || hp.y < zlo || hp.y > zhi) continue;
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (j == n) q[j] = p;
+      if (n < N) ++n;
+      else overflow = true;
+    }
+  }
+  return n;
+}
+
 // Best (d, u) pair of hit m; see the step description above.  F64: scores in
-// FP64 (S_max < 2^48), else in int64.
+// FP64 (S_max < 2^48), else in int64.  Both windows' candidates are gathered
+// first (a few per side), then every pair is scored; a hit with more
+// candidates than the registers hold scans the windows again pair by pair.
 template <bool LDS, bool F64>
 __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *recd, const int32_t *recu,
                                           float2 invd, float2 invu,
@@ -856,28 +904,12 @@ __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *r
   best_u = -1;
   if (kd.c.empty || ku.c.empty) return;
   const int zlo = Zm - int(WZ), zhi = Zm + int(WZ);
-  // row-above candidates passing the window, kept in registers when few
-  int uq[MAXU];
-  int2 uh[MAXU];
-  int nu = 0;
+  int uq[MAXU], dq[MAXD];
   bool overflow = false;
-  for (int izu = ku.c.iz0; izu <= ku.c.iz1; ++izu) {
-    const int cu = ku.c.cbase + izu * ku.c.ny;
-    const int v0 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy0), v1 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy1 + 1);
-    for (int q = v0; q < v1; ++q) {
-      const int2 h = hit_at<LDS>(w, su, lhu, q);
-      if (h.x < ku.ylo || h.x > ku.yhi || h.y < zlo || h.y > zhi) continue;
-#pragma unroll
-      for (int k = 0; k < MAXU; ++k)
-        if (k == nu) {
-          uq[k] = q;
-          uh[k] = h;
-        }
-      if (nu < MAXU) ++nu;
-      else overflow = true;
-    }
-  }
+  const int nu = collect<LDS, MAXU>(w, ku, su, lcu, lhu, zlo, zhi, uq, overflow);
   if (nu == 0) return;
+  const int nd = collect<LDS, MAXD>(w, kd, sd, lcd, lhd, zlo, zhi, dq, overflow);
+  if (nd == 0) return;
   int64_t best_s = INT64_MAX;
   double best_f = 1e300;
   const double dxu_f = double(dxu), dxd_f = double(dxd), wy_f = double(wy), wz_f = double(wz);
@@ -911,25 +943,32 @@ __device__ __forceinline__ void best_pair(const Args &A, int m, const int32_t *r
       best_u = uu;
     }
   };
+  if (!overflow) {
+#pragma unroll
+    for (int a = 0; a < MAXD; ++a) {
+      if (a < nd) {
+        const int2 hd = hit_at<LDS>(w, sd, lhd, dq[a]);
+#pragma unroll
+        for (int b = 0; b < MAXU; ++b)
+          if (b < nu) consider(dq[a], hd, uq[b], hit_at<LDS>(w, su, lhu, uq[b]));
+      }
+    }
+    return;
+  }
+  // more candidates than the registers hold: every pair from the windows
   for (int izd = kd.c.iz0; izd <= kd.c.iz1; ++izd) {
     const int cd = kd.c.cbase + izd * kd.c.ny;
     const int q0 = cell_at<LDS>(w, sd, lcd, cd + kd.c.iy0), q1 = cell_at<LDS>(w, sd, lcd, cd + kd.c.iy1 + 1);
     for (int d = q0; d < q1; ++d) {
       const int2 hd = hit_at<LDS>(w, sd, lhd, d);
       if (hd.x < kd.ylo || hd.x > kd.yhi || hd.y < zlo || hd.y > zhi) continue;
-      if (!overflow) {
-#pragma unroll
-        for (int k = 0; k < MAXU; ++k)
-          if (k < nu) consider(d, hd, uq[k], uh[k]);
-      } else {  // many candidates above: scan them again
-        for (int izu = ku.c.iz0; izu <= ku.c.iz1; ++izu) {
-          const int cu = ku.c.cbase + izu * ku.c.ny;
-          const int v0 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy0), v1 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy1 + 1);
-          for (int q = v0; q < v1; ++q) {
-            const int2 h = hit_at<LDS>(w, su, lhu, q);
-            if (h.x < ku.ylo || h.x > ku.yhi || h.y < zlo || h.y > zhi) continue;
-            consider(d, hd, q, h);
-          }
+      for (int izu = ku.c.iz0; izu <= ku.c.iz1; ++izu) {
+        const int cu = ku.c.cbase + izu * ku.c.ny;
+        const int v0 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy0), v1 = cell_at<LDS>(w, su, lcu, cu + ku.c.iy1 + 1);
+        for (int q = v0; q < v1; ++q) {
+          const int2 h = hit_at<LDS>(w, su, lhu, q);
+          if (h.x < ku.ylo || h.x > ku.yhi || h.y < zlo || h.y > zhi) continue;
+          consider(d, hd, q, h);
         }
       }
     }
@@ -1349,36 +1388,44 @@ __device__ int pick(const Args &A, const Rec &rf, float2 inv, float yp, float zp
   // windows < 2^13 and weights <= 15 keep the score below 2^31
   int best_s = INT32_MAX;
   int best = -1;
-  // The cell bounds of up to ZB z bins are loaded together, and the hits of
-  // each bin HB at a time, so that one pickup waits for few round trips.
+  // The cell bounds of up to ZB z bins are loaded together; their hits are
+  // taken as one list, HB at a time, so that a lane's batches follow its
+  // number of hits rather than its number of bins, and one pickup waits for
+  // few round trips.
   constexpr int ZB = 4, HB = 4;
   for (int izb = c.iz0; izb <= c.iz1; izb += ZB) {
-    int qa[ZB], qb[ZB];
+    int qa[ZB], e[ZB];  // first hit of each bin; end of each bin in the joint list
+    int tot = 0;
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
       const bool v = izb + k <= c.iz1;
       const int cb = c.cbase + (izb + k) * c.ny;
       qa[k] = v ? w.cell[cb + c.iy0] : 0;
-      qb[k] = v ? w.cell[cb + c.iy1 + 1] : 0;
+      const int qb = v ? w.cell[cb + c.iy1 + 1] : 0;
+      tot += qb - qa[k];
+      e[k] = tot;
     }
+    for (int j0 = 0; j0 < tot; j0 += HB) {
+      int qq[HB];
+      int2 hh[HB];
 #pragma unroll
-    for (int k = 0; k < ZB; ++k) {
-      for (int q = qa[k]; q < qb[k]; q += HB) {
-        int2 hh[HB];
+      for (int j = 0; j < HB; ++j) {
+        const int t = j0 + j;
+        qq[j] = t < e[0] ? qa[0] + t : t < e[1] ? qa[1] + (t - e[0]) : t < e[2] ? qa[2] + (t - e[1])
+                                                                               : qa[3] + (t - e[2]);
+        hh[j] = t < tot ? w.syz[qq[j]] : make_int2(0, 0);
+      }
 #pragma unroll
-        for (int j = 0; j < HB; ++j) hh[j] = q + j < qb[k] ? w.syz[q + j] : make_int2(0, 0);
-#pragma unroll
-        for (int j = 0; j < HB; ++j) {
-          if (q + j >= qb[k]) break;
-          const int2 h = hh[j];
-          const int dY = h.x - Yp, dZ = h.y - Zp;
-          if (abs(dY) > WY || abs(dZ) > WZ) continue;
-          const int sc = A.p.w_y * dY * dY + A.p.w_z * dZ * dZ;
-          if (sc < best_s || (sc == best_s && w.perm[q + j] < w.perm[best])) {
-            best_s = sc;
-            best = q + j;
-            best_yz = h;
-          }
+      for (int j = 0; j < HB; ++j) {
+        if (j0 + j >= tot) break;
+        const int2 h = hh[j];
+        const int dY = h.x - Yp, dZ = h.y - Zp;
+        if (abs(dY) > WY || abs(dZ) > WZ) continue;
+        const int sc = A.p.w_y * dY * dY + A.p.w_z * dZ * dZ;
+        if (sc < best_s || (sc == best_s && w.perm[qq[j]] < w.perm[best])) {
+          best_s = sc;
+          best = qq[j];
+          best_yz = h;
         }
       }
     }
@@ -1403,69 +1450,72 @@ __device__ __forceinline__ void upd_hit(KState &s, int2 yz, int Yr, int Zr, floa
 
 // step 5a: chains.  Per tracklet: the row of its start hit and the length of
 // the chain along the cleaned upward links (a cellular automaton over pad
-// rows); chains of >= l_min hits become seeds, and their middle and last hits
-// are kept for the seed fit.  Other tracklets are finalised here (no fit, no
-// hits).
+// rows); chains of >= l_min hits become seeds, and their start row, middle
+// and last hits are kept for the seed fit.
+constexpr int CHAIN_BLOCKS = 2048;  // grid of the per-tracklet kernels (blocks loop over 256-tracklet chunks)
+
 __global__ void __launch_bounds__(TPB) k_chains(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  int seed = 0;
-  if (t < w.ctr[C_K]) {
-    const int nr = A.n_rows;
-    const int h0 = w.trk_start[t], u = w.trk_unit[t];
-    const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
-    int lo = 0, hi = nr - 1;  // row of the start hit: last row whose start <= h0
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
+  const int64_t n_trk = w.ctr[C_K];
+  const int64_t n_chunks = (n_trk + TPB - 1) / TPB;
+  for (int64_t b = blockIdx.x; b < n_chunks; b += gridDim.x) {
+    const int64_t t = b * TPB + threadIdx.x;
+    int seed = 0;
+    if (t < n_trk) {
+      const int nr = A.n_rows;
+      const int h0 = w.trk_start[t], u = w.trk_unit[t];
+      const int32_t *segu = w.seg + int64_t(u) * nr * SEGW;
+      int lo = 0, hi = nr - 1;  // row of the start hit: last row whose start <= h0
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segu[mid * SEGW + S_START] <= h0) lo = mid; else hi = mid - 1;
+      }
+      const int r1 = lo;
+      // one walk; hm trails at half speed, so it ends on the chain's hit L/2
+      int L = 0, hb = h0, hm = h0;
+      for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
+        hb = h;
+        ++L;
+        if ((L & 1) == 0) hm = w.upc[hm];
+      }
+      w.trk_len[t] = L;
+      seed = L >= A.p.l_min;
+      if (seed) {  // handed to k_compact_seeds, which files them by seed
+        w.tmp_r1[t] = r1;
+        w.tmp_hm[t] = hm;
+        w.tmp_hb[t] = hb;
+      }
     }
-    const int r1 = lo;
-    // one walk; hm trails at half speed, so it ends on the chain's hit L/2
-    int L = 0, hb = h0, hm = h0;
-    for (int h = h0; h >= 0 && r1 + L < nr; h = w.upc[h]) {
-      hb = h;
-      ++L;
-      if ((L & 1) == 0) hm = w.upc[hm];
-    }
-    if (L >= A.p.l_min) {
-      w.trk_hm[t] = hm;
-      w.trk_hb[t] = hb;
-    }
-    w.trk_len[t] = L;
-    w.trk_r1[t] = r1;
-    seed = L >= A.p.l_min;
-    if (!seed) {
-      w.trk_nfit[t] = 0;
-      w.trk_rlo[t] = -1;
-      w.trk_rhi[t] = -1;
-      w.trk_key[t] = 0u;
-#pragma unroll
-      for (int i = 0; i < 5; ++i) w.trk_par[t * 5 + i] = 0.f;
-#pragma unroll
-      for (int i = 0; i < 15; ++i) w.trk_cov[t * 15 + i] = 0.f;
-      w.trk_x[t] = 0.f;
-      w.trk_chi2[t] = 0.f;
-      w.trk_owned[t] = 0;
-      w.trk_keep[t] = 0;
-    }
+    int tot;
+    block_exclusive_scan<TPB>(seed, tmp, &tot);
+    if (threadIdx.x == 0) w.blk_keep[b] = tot;  // chunks past the tracklets keep k_init's 0
   }
-  int tot;
-  block_exclusive_scan<TPB>(seed, tmp, &tot);
-  if (threadIdx.x == 0) w.blk_keep[blockIdx.x] = tot;
 }
 
-// step 5b: list of seeds in tracklet order
+// step 5b: list of seeds in tracklet order, with their seed-fit inputs
 __global__ void __launch_bounds__(TPB) k_compact_seeds(Args A) {
   __shared__ int tmp[4];
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
-  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  const int seed = (t < w.ctr[C_K] && w.trk_len[t] >= A.p.l_min) ? 1 : 0;
-  int tot;
-  const int ex = block_exclusive_scan<TPB>(seed, tmp, &tot);
-  if (seed) w.seed_list[w.blk_keep[blockIdx.x] + ex] = int32_t(t);
+  const int64_t n_trk = w.ctr[C_K];
+  const int64_t n_chunks = (n_trk + TPB - 1) / TPB;
+  for (int64_t b = blockIdx.x; b < n_chunks; b += gridDim.x) {
+    const int64_t t = b * TPB + threadIdx.x;
+    const int seed = (t < n_trk && w.trk_len[t] >= A.p.l_min) ? 1 : 0;
+    int tot;
+    const int ex = block_exclusive_scan<TPB>(seed, tmp, &tot);
+    if (seed) {
+      const int64_t i = w.blk_keep[b] + ex;
+      if (i < w.S_cap) {  // beyond: the scan has already reported TPC_E_CAPACITY
+        w.seed_list[i] = int32_t(t);
+        w.sd_r1[i] = w.tmp_r1[t];
+        w.sd_hm[i] = w.tmp_hm[t];
+        w.sd_hb[i] = w.tmp_hb[t];
+      }
+    }
+  }
 }
 
 // step 5c: Kalman fit of every seed, one seed per lane.
@@ -1511,12 +1561,12 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     h0 = w.trk_start[t];
     u = w.trk_unit[t];
     L = w.trk_len[t];
-    r1 = w.trk_r1[t];
+    r1 = w.sd_r1[i];
     segu = w.seg + int64_t(u) * nr * SEGW;
     invs = w.seg_inv + int64_t(u) * nr;
     // seed, in coordinates relative to the first chain hit: small numbers
     // keep FP32 precise even at |z'| of metres (continuous readout)
-    const int2 ya = w.syz[h0], ym = w.syz[w.trk_hm[t]], yb = w.syz[w.trk_hb[t]];
+    const int2 ya = w.syz[h0], ym = w.syz[w.sd_hm[i]], yb = w.syz[w.sd_hb[i]];
     Yr = ya.x;
     Zr = ya.y;
     const float x0 = A.row_x[r1], x1 = A.row_x[r1 + L / 2], x2 = A.row_x[r1 + L - 1];
@@ -1544,7 +1594,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
   }
   // pass 1: the chain rows, then extension rows, in one walk up the rows;
   // one propagate/update site serves both kinds of row.
-  int r_out = r1, misses = 0, hc = h0;
+  int r_out = r1, misses = 0, hc = h0, p1n = ok ? 1 : 0;
   bool act = ok;
   if (ok) {
     col[r1 * 64] = h0;
@@ -1586,6 +1636,7 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
       step_apply(s, st, xr, k);
       upd_hit(s, yz, Yr, Zr, sy2, sz2);
       r_out = r;
+      ++p1n;
       misses = 0;
     } else if (++misses > P.max_miss) {
       act = false;
@@ -1656,16 +1707,17 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
     s.chi2 = 0.f;
   }
   if (valid) {
-    w.trk_nfit[t] = nfit;
-    w.trk_rlo[t] = rlo;
-    w.trk_rhi[t] = rhi;
-    w.trk_key[t] = key;
+    w.sd_nfit[i] = nfit;
+    w.sd_p1n[i] = p1n;
+    w.sd_rlo[i] = rlo;
+    w.sd_rhi[i] = rhi;
+    w.sd_key[i] = key;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) w.trk_par[t * 5 + j] = s.p[j];
+    for (int j = 0; j < 5; ++j) w.sd_par[i * 5 + j] = s.p[j];
 #pragma unroll
-    for (int j = 0; j < 15; ++j) w.trk_cov[t * 15 + j] = s.c[j * 64];
-    w.trk_x[t] = s.x;
-    w.trk_chi2[t] = s.chi2;
+    for (int j = 0; j < 15; ++j) w.sd_cov[i * 15 + j] = s.c[j * 64];
+    w.sd_x[i] = s.x;
+    w.sd_chi2[i] = s.chi2;
   }
   // ownership: every hit goes to the tracklet with the largest key
   const bool has = nfit > 0;
@@ -1681,107 +1733,178 @@ __global__ void __launch_bounds__(CTB) __attribute__((amdgpu_waves_per_eu(5, 8))
 }
 
 // ---------------------------------------------------------------------------
-// step 6: selector.  Keep a tracklet that owns >= n_min of its hits and at
-// least f_min of them; tracks keep the tracklet order; no refit.
+// step 6: selector and output.  Keep a tracklet that owns >= n_min of its
+// hits and at least f_min of them; tracks keep the tracklet order; no refit.
+//
+// One pass over the seed list (tracklets that are not seeds own nothing and
+// are never kept; k_chains set their owned = keep = 0).  Seeds are in
+// tracklet order, so an exclusive scan over seed order numbers the tracks in
+// tracklet order.  The scan is a single-pass decoupled look-back: a block
+// takes the next 256 seeds by ticket (so every seed block it waits on has
+// already started), counts and marks its tracklets' owned hits, publishes its
+// (tracks, hits) aggregate, adds up its predecessors' aggregates until it
+// meets an inclusive prefix, publishes its own inclusive prefix, and writes
+// its tracks.  The grid is a fixed number of blocks that loop over tickets,
+// so the launch does not depend on the tracklet capacity.
 
-// Runs over the seed list (tracklets that are not seeds own nothing and are
-// never kept; k_chains set their owned = keep = 0).  Seeds are in tracklet
-// order, so scans over seed order number the tracks in tracklet order.
-__global__ void __launch_bounds__(TPB) k_select(Args A) {
-  __shared__ int tmp[4];
-  const Workspace &w = A.w;
-  if (*A.out.status != TPC_OK) return;
-  const int64_t n_seeds = w.ctr[C_SEEDS];
-  const int64_t b = xcd_chunk(blockIdx.x, (n_seeds + TPB - 1) / TPB);
-  if (b >= w.KB) return;
-  const int64_t i = b * TPB + threadIdx.x;
-  const bool valid = i < n_seeds;
-  const int64_t t = valid ? w.seed_list[i] : 0;
-  const int nfit = valid ? w.trk_nfit[t] : 0;
-  const bool has = nfit > 0;
-  const uint32_t key = has ? w.trk_key[t] : 0u;
-  const int rlo = has ? w.trk_rlo[t] : 0, rhi = has ? w.trk_rhi[t] : -1;
-  const int nr = A.n_rows;
-  int32_t *col = seed_column(w, i, nr);
-  int owned = 0;
-  const int rb = wave_max(has ? rhi : -1);
-  for (int r0 = wave_min(has ? rlo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
-    int h[RB];
-    uint32_t o[RB];
-#pragma unroll
-    for (int k = 0; k < RB; ++k) h[k] = (r0 + k >= rlo && r0 + k <= rhi) ? col[(r0 + k) * 64] : -1;
-#pragma unroll
-    for (int k = 0; k < RB; ++k) o[k] = h[k] >= 0 ? w.owner[h[k]] : 0u;
-#pragma unroll
-    for (int k = 0; k < RB; ++k)
-      if (h[k] >= 0 && o[k] == key) {  // mark the hit for the emitter
-        ++owned;
-        col[(r0 + k) * 64] = h[k] | OWNED;
-      }
-  }
-  const int keep = has && owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
-  if (valid) {
-    w.trk_owned[t] = owned;
-    w.trk_keep[t] = keep;
-  }
-  int tk, to;
-  block_exclusive_scan<TPB>(keep, tmp, &tk);
-  block_exclusive_scan<TPB>(keep ? owned : 0, tmp, &to);
-  if (threadIdx.x == 0) {
-    w.blk_keep[b] = tk;
-    w.blk_own[b] = to;
-  }
+// look-back word: flag (bits 62-63: 1 aggregate, 2 inclusive prefix),
+// tracks (bits 31-61), hits (bits 0-30).  The counts travel in the same
+// 64-bit word as their flag, so relaxed device-scope atomics suffice: no
+// other memory is published with it (release/acquire would write back and
+// invalidate the caches at every step).
+constexpr uint64_t LB_AGG = uint64_t(1) << 62, LB_INC = uint64_t(2) << 62;
+__device__ __forceinline__ uint64_t lb_word(uint64_t flag, int tracks, int hits) {
+  return flag | (uint64_t(uint32_t(tracks)) << 31) | uint64_t(uint32_t(hits));
 }
+constexpr int SELECT_BLOCKS = 2048;
+constexpr int LB_SPIN_MAX = 1 << 26;
 
-__global__ void __launch_bounds__(TPB) k_emit(Args A) {
+__global__ void __launch_bounds__(TPB) k_select_emit(Args A) {
   __shared__ int tmp[4];
+  __shared__ int64_t s_vb;
+  __shared__ int s_bt, s_bh;  // tracks and hits of the blocks before this one
   const Workspace &w = A.w;
   if (*A.out.status != TPC_OK) return;
   const int64_t n_seeds = w.ctr[C_SEEDS];
-  const int64_t b = xcd_chunk(blockIdx.x, (n_seeds + TPB - 1) / TPB);
-  if (b >= w.KB) return;
-  const int64_t i = b * TPB + threadIdx.x;
-  const bool valid = i < n_seeds;
-  const int64_t t = valid ? w.seed_list[i] : 0;
-  const int keep = valid ? w.trk_keep[t] : 0;
-  const int owned = keep ? w.trk_owned[t] : 0;
-  int tk, to;
-  const int ek = block_exclusive_scan<TPB>(keep, tmp, &tk);
-  const int eo = block_exclusive_scan<TPB>(owned, tmp, &to);
-  const int tr = w.blk_keep[b] + ek;
-  int off = w.blk_own[b] + eo;
-  const tpc_tracks_t &O = A.out;
-  int rlo = 0, rhi = -1;
-  if (keep) {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) O.params[int64_t(tr) * 5 + j] = w.trk_par[t * 5 + j];
-#pragma unroll
-    for (int j = 0; j < 15; ++j) O.cov[int64_t(tr) * 15 + j] = w.trk_cov[t * 15 + j];
-    O.x_ref[tr] = w.trk_x[t];
-    O.chi2[tr] = w.trk_chi2[t];
-    O.unit[tr] = w.trk_unit[t];
-    O.n_hits[tr] = owned;
-    O.n_fit[tr] = w.trk_nfit[t];
-    O.first_hit[tr] = off;
-    rlo = w.trk_rlo[t];
-    rhi = w.trk_rhi[t];
-  }
+  const int64_t nvb = (n_seeds + TPB - 1) / TPB;
   const int nr = A.n_rows;
-  const int32_t *col = seed_column(w, i, nr);
-  const int rb = wave_max(keep ? rhi : -1);
-  for (int r0 = wave_min(keep ? rlo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
-    int h[RB], id[RB];
+  const tpc_tracks_t &O = A.out;
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_vb = int64_t(atomicAdd(reinterpret_cast<unsigned long long *>(&w.ctr[C_TICKET]), 1ull));
+    __syncthreads();
+    const int64_t vb = s_vb;
+    if (vb >= nvb) return;
+    const int64_t i = vb * TPB + threadIdx.x;
+    const bool valid = i < n_seeds;
+    const int64_t t = valid ? w.seed_list[i] : 0;
+    const int nfit = valid ? w.sd_nfit[i] : 0;
+    const bool has = nfit > 0;
+    const uint32_t key = has ? w.sd_key[i] : 0u;
+    const int rlo = has ? w.sd_rlo[i] : 0, rhi = has ? w.sd_rhi[i] : -1;
+    int32_t *col = seed_column(w, i, nr);
+    // owned hits: those whose owner key is this tracklet's, marked for the output
+    int owned = 0;
+    {
+      const int rb = wave_max(has ? rhi : -1);
+      for (int r0 = wave_min(has ? rlo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
+        int h[RB];
+        uint32_t o[RB];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) h[k] = (r0 + k >= rlo && r0 + k <= rhi) ? col[(r0 + k) * 64] : -1;
+        for (int k = 0; k < RB; ++k) h[k] = (r0 + k >= rlo && r0 + k <= rhi) ? col[(r0 + k) * 64] : -1;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) id[k] = (h[k] >= 0 && (h[k] & OWNED)) ? w.perm[h[k] & (OWNED - 1)] : -1;
+        for (int k = 0; k < RB; ++k) o[k] = h[k] >= 0 ? w.owner[h[k]] : 0u;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      if (id[k] >= 0) {
-        O.hits[off++] = id[k];
-        O.cluster_track[id[k]] = tr;
+        for (int k = 0; k < RB; ++k)
+          if (h[k] >= 0 && o[k] == key) {
+            ++owned;
+            col[(r0 + k) * 64] = h[k] | OWNED;
+          }
       }
     }
+    const int keep = has && owned >= A.p.n_min && int64_t(owned) * 256 >= int64_t(A.p.f_min_q8) * nfit;
+    if (valid) {
+      w.sd_owned[i] = owned;
+      w.sd_keep[i] = keep;
+    }
+    int tk, to;
+    const int ek = block_exclusive_scan<TPB>(keep, tmp, &tk);
+    const int eo = block_exclusive_scan<TPB>(keep ? owned : 0, tmp, &to);
+    if (threadIdx.x < 64) {  // wave 0: publish, then look back 64 predecessors at a time
+      uint64_t *lb = w.lookback;
+      const int lane = threadIdx.x;
+      int bt = 0, bh = 0;
+      if (vb == 0) {
+        if (lane == 0)
+          __hip_atomic_store(&lb[0], lb_word(LB_INC, tk, to), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (lane == 0)
+          __hip_atomic_store(&lb[vb], lb_word(LB_AGG, tk, to), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t top = vb - 1;  // lane k reads block top - k
+        int spins = 0;
+        for (;;) {
+          const int64_t j = top - lane;
+          // before block 0 counts as an inclusive prefix of nothing
+          const uint64_t v =
+              j >= 0 ? __hip_atomic_load(&lb[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LB_INC;
+          const uint64_t inc = __ballot((v >> 62) == 2), empty = __ballot((v >> 62) == 0);
+          const int first = inc ? __ffsll(static_cast<unsigned long long>(inc)) - 1 : 64;  // nearest prefix
+          const uint64_t before = first < 64 ? ((uint64_t(1) << first) << 1) - 1 : ~uint64_t(0);
+          if (empty & before) {  // a block between us and that prefix has not published yet
+            // the blocks looked at hold earlier tickets, so they are running or done
+            if (++spins > LB_SPIN_MAX) {
+              if (lane == 0) set_status(A.out.status, TPC_E_HIP);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          int vt = lane <= first ? int((v >> 31) & 0x7FFFFFFF) : 0;
+          int vh = lane <= first ? int(v & 0x7FFFFFFF) : 0;
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            vt += __shfl_xor(vt, o, 64);
+            vh += __shfl_xor(vh, o, 64);
+          }
+          bt += vt;
+          bh += vh;
+          if (first < 64) break;
+          top -= 64;
+        }
+        if (lane == 0)
+          __hip_atomic_store(&lb[vb], lb_word(LB_INC, bt + tk, bh + to), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (lane == 0) {
+        s_bt = bt;
+        s_bh = bh;
+        if (vb == nvb - 1) {  // the last block knows the totals
+          const int64_t nt = int64_t(bt) + tk, nh = int64_t(bh) + to;
+          w.ctr[C_TRACKS] = nt;
+          w.ctr[C_HITS] = nh;
+          O.counts[0] = nt;
+          O.counts[1] = nh;
+          if (nt > O.cap_tracks || nh > O.cap_hits) set_status(A.out.status, TPC_E_CAPACITY);
+        }
+      }
+    }
+    __syncthreads();
+    const int tr = s_bt + ek;
+    int64_t off = int64_t(s_bh) + eo;
+    const bool fits = keep && tr < O.cap_tracks && off + owned <= O.cap_hits;
+    int elo = 0, ehi = -1;
+    if (fits) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) O.params[int64_t(tr) * 5 + j] = w.sd_par[i * 5 + j];
+#pragma unroll
+      for (int j = 0; j < 15; ++j) O.cov[int64_t(tr) * 15 + j] = w.sd_cov[i * 15 + j];
+      O.x_ref[tr] = w.sd_x[i];
+      O.chi2[tr] = w.sd_chi2[i];
+      O.unit[tr] = w.trk_unit[t];
+      O.n_hits[tr] = owned;
+      O.n_fit[tr] = nfit;
+      O.first_hit[tr] = int32_t(off);
+      elo = rlo;
+      ehi = rhi;
+    }
+    {
+      const int rb = wave_max(fits ? ehi : -1);
+      for (int r0 = wave_min(fits ? elo : nr); r0 <= rb; r0 += RB) {  // RB rows per round trip
+        int h[RB], id[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) h[k] = (r0 + k >= elo && r0 + k <= ehi) ? col[(r0 + k) * 64] : -1;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) id[k] = (h[k] >= 0 && (h[k] & OWNED)) ? w.perm[h[k] & (OWNED - 1)] : -1;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+          if (id[k] >= 0) {
+            O.hits[off++] = id[k];
+            O.cluster_track[id[k]] = tr;
+          }
+        }
+      }
+    }
+    __syncthreads();  // s_vb, s_bt, s_bh are rewritten by the next ticket
   }
 }
 
@@ -1819,7 +1942,7 @@ const char *const kKernelNames[] = {
     "k_init",        "k_units",      "k_tile_hist",  "k_seg_plan",      "k_cell_base",
     "k_tile_offsets", "k_tile_scatter", "k_bin_sort",  "k_neighbours",    "k_neighbours_wide", "k_clean",
     "k_scan_blocks", "k_compact_starts", "k_chains", "k_scan_blocks", "k_compact_seeds",
-    "k_fit",         "k_select",     "k_scan_blocks", "k_emit"};
+    "k_fit",         "k_select_emit"};
 constexpr int kNumKernels = int(sizeof(kKernelNames) / sizeof(kKernelNames[0]));
 
 int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field_t *f,
@@ -1862,7 +1985,9 @@ int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field
     if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[ki]), st);
     ++ki;
   };
-  const int64_t init_n = w.S > c->n ? w.S : (c->n > C_N ? c->n : int64_t(C_N));
+  int64_t init_n = w.S > c->n ? w.S : (c->n > C_N ? c->n : int64_t(C_N));
+  if (init_n < w.SB) init_n = w.SB;
+  if (init_n < w.KB) init_n = w.KB;
   mark();
   hipLaunchKernelGGL(k_init, dim3(blocks_for(init_n, TPB)), dim3(TPB), 0, st, A);
   mark();
@@ -1888,28 +2013,24 @@ int track_impl(const tpc_clusters_t *c, const tpc_geometry_t *g, const tpc_field
     hipLaunchKernelGGL(k_clean, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
     mark();
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, w.blk, w.NB, w.ctr + C_K,
-                       out->counts + 2, w.K_cap, out->status, (int32_t *)nullptr, (int64_t *)nullptr,
+                       out->counts + 2, w.T_cap, out->status, (int32_t *)nullptr, (int64_t *)nullptr,
                        (int64_t *)nullptr, int64_t(0));
     mark();
     hipLaunchKernelGGL(k_compact_starts, dim3(unsigned(w.NB)), dim3(TPB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_chains, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+    hipLaunchKernelGGL(k_chains, dim3(unsigned(w.KB < CHAIN_BLOCKS ? w.KB : CHAIN_BLOCKS)), dim3(TPB), 0, st, A);
     mark();
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, w.blk_keep, w.KB, w.ctr + C_SEEDS,
-                       (int64_t *)nullptr, w.K_cap, out->status, (int32_t *)nullptr, (int64_t *)nullptr,
+                       out->counts + 4, w.S_cap, out->status, (int32_t *)nullptr, (int64_t *)nullptr,
                        (int64_t *)nullptr, int64_t(0));
     mark();
-    hipLaunchKernelGGL(k_compact_seeds, dim3(unsigned(w.KB)), dim3(TPB), 0, st, A);
+    hipLaunchKernelGGL(k_compact_seeds, dim3(unsigned(w.KB < CHAIN_BLOCKS ? w.KB : CHAIN_BLOCKS)), dim3(TPB), 0,
+                       st, A);
     mark();
-    hipLaunchKernelGGL(k_fit, dim3(round8(blocks_for(w.K_cap, CTB))), dim3(CTB), 0, st, A);
+    hipLaunchKernelGGL(k_fit, dim3(round8(blocks_for(w.S_cap, CTB))), dim3(CTB), 0, st, A);
     mark();
-    hipLaunchKernelGGL(k_select, dim3(round8(w.KB)), dim3(TPB), 0, st, A);
-    mark();
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, w.blk_keep, w.KB, w.ctr + C_TRACKS,
-                       out->counts + 0, out->cap_tracks, out->status, w.blk_own, w.ctr + C_HITS,
-                       out->counts + 1, out->cap_hits);
-    mark();
-    hipLaunchKernelGGL(k_emit, dim3(round8(w.KB)), dim3(TPB), 0, st, A);
+    hipLaunchKernelGGL(k_select_emit, dim3(unsigned(w.SB < SELECT_BLOCKS ? w.SB : SELECT_BLOCKS)), dim3(TPB), 0,
+                       st, A);
   }
   while (ki <= kNumKernels) mark();  // empty batch: the remaining events mark the same point
   if (hipGetLastError() != hipSuccess) return TPC_E_HIP;
@@ -1996,7 +2117,7 @@ extern "C" int tpc_inspect(const tpc_clusters_t *c, int32_t n_rows, const tpc_pa
   if (!c || !p || !v || !workspace || !params_ok(p)) return TPC_E_INVALID;
   Workspace w;
   if (!layout(c->n, c->n_units, n_rows, p, (char *)workspace, &w)) return TPC_E_INVALID;
-  const int64_t N = c->n, K = w.K_cap;
+  const int64_t N = c->n, T = w.T_cap, K = w.S_cap;
   void *ptr = nullptr;
   int64_t cnt = 0;
   int eb = 4;
@@ -2009,21 +2130,22 @@ extern "C" int tpc_inspect(const tpc_clusters_t *c, int32_t n_rows, const tpc_pa
     case TPC_VIEW_UPC: ptr = w.upc; cnt = N; break;
     case TPC_VIEW_DNC: ptr = w.dnc; cnt = N; break;
     case TPC_VIEW_OWNER: ptr = w.owner; cnt = N; break;
-    case TPC_VIEW_TRK_START: ptr = w.trk_start; cnt = K; break;
-    case TPC_VIEW_TRK_UNIT: ptr = w.trk_unit; cnt = K; break;
-    case TPC_VIEW_TRK_LEN: ptr = w.trk_len; cnt = K; break;
-    case TPC_VIEW_TRK_NFIT: ptr = w.trk_nfit; cnt = K; break;
-    case TPC_VIEW_TRK_RLO: ptr = w.trk_rlo; cnt = K; break;
-    case TPC_VIEW_TRK_RHI: ptr = w.trk_rhi; cnt = K; break;
-    case TPC_VIEW_TRK_KEY: ptr = w.trk_key; cnt = K; break;
-    case TPC_VIEW_TRK_OWNED: ptr = w.trk_owned; cnt = K; break;
-    case TPC_VIEW_TRK_KEEP: ptr = w.trk_keep; cnt = K; break;
-    case TPC_VIEW_TRK_PARAMS: ptr = w.trk_par; cnt = K * 5; break;
-    case TPC_VIEW_TRK_COV: ptr = w.trk_cov; cnt = K * 15; break;
-    case TPC_VIEW_TRK_XREF: ptr = w.trk_x; cnt = K; break;
-    case TPC_VIEW_TRK_CHI2: ptr = w.trk_chi2; cnt = K; break;
+    case TPC_VIEW_TRK_START: ptr = w.trk_start; cnt = T; break;
+    case TPC_VIEW_TRK_UNIT: ptr = w.trk_unit; cnt = T; break;
+    case TPC_VIEW_TRK_LEN: ptr = w.trk_len; cnt = T; break;
+    case TPC_VIEW_TRK_NFIT: ptr = w.sd_nfit; cnt = K; break;
+    case TPC_VIEW_TRK_RLO: ptr = w.sd_rlo; cnt = K; break;
+    case TPC_VIEW_TRK_RHI: ptr = w.sd_rhi; cnt = K; break;
+    case TPC_VIEW_TRK_KEY: ptr = w.sd_key; cnt = K; break;
+    case TPC_VIEW_TRK_OWNED: ptr = w.sd_owned; cnt = K; break;
+    case TPC_VIEW_TRK_KEEP: ptr = w.sd_keep; cnt = K; break;
+    case TPC_VIEW_TRK_PARAMS: ptr = w.sd_par; cnt = K * 5; break;
+    case TPC_VIEW_TRK_COV: ptr = w.sd_cov; cnt = K * 15; break;
+    case TPC_VIEW_TRK_XREF: ptr = w.sd_x; cnt = K; break;
+    case TPC_VIEW_TRK_CHI2: ptr = w.sd_chi2; cnt = K; break;
     case TPC_VIEW_TRK_HITS: ptr = w.trk_hits; cnt = w.KW * 64 * n_rows; break;
     case TPC_VIEW_SEED_LIST: ptr = w.seed_list; cnt = K; break;
+    case TPC_VIEW_TRK_P1N: ptr = w.sd_p1n; cnt = K; break;
     default: return TPC_E_INVALID;
   }
   v->ptr = ptr;

@@ -110,7 +110,7 @@ class Tracker:
         self.o_n_fit = torch.empty(ct, dtype=i32, device=d)
         self.o_first_hit = torch.empty(ct, dtype=i32, device=d)
         self.o_hits = torch.empty(max(1, self.cap_hits), dtype=i32, device=d)
-        self.o_counts = torch.zeros(4, dtype=torch.int64, device=d)
+        self.o_counts = torch.zeros(5, dtype=torch.int64, device=d)
         self.o_status = torch.zeros(1, dtype=i32, device=d)
         self._last = None
 
@@ -178,10 +178,25 @@ class Tracker:
         T, H = int(counts[0]), int(counts[1])
         n = self._last.n
         return dict(n_tracks=T, n_track_hits=H, n_tracklets=int(counts[2]), n_cells=int(counts[3]),
+                    n_seeds=int(counts[4]),
                     cluster_track=self.o_cluster_track[:n], params=self.o_params[:T], cov=self.o_cov[:T],
                     x_ref=self.o_x_ref[:T], chi2=self.o_chi2[:T], unit=self.o_unit[:T],
                     n_hits=self.o_n_hits[:T], n_fit=self.o_n_fit[:T], first_hit=self.o_first_hit[:T],
                     hits=self.o_hits[:H])
+
+    def tracklet_field(self, what, dtype=torch.int32, width=1):
+        """A per-seed view (NFIT, RLO, ..., PARAMS) of the last launch spread over
+        all its tracklets (host numpy; tracklets that are not seeds get 0, and -1
+        for RLO / RHI)."""
+        from . import TPC_VIEW_SEED_LIST, TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI
+        counts = self.o_counts.cpu().numpy()
+        K, S = int(counts[2]), int(counts[4])
+        seeds = self.inspect(TPC_VIEW_SEED_LIST).cpu().numpy()[:S]
+        v = self.inspect(what, dtype).cpu().numpy().reshape(-1, width)[:S]
+        fill = -1 if what in (TPC_VIEW_TRK_RLO, TPC_VIEW_TRK_RHI) else 0
+        out = np.full((K, width), fill, v.dtype)
+        out[seeds] = v
+        return out if width > 1 else out[:, 0]
 
     def inspect(self, what, dtype=torch.int32, shape=None):
         """Copy of an intermediate workspace array of the last launch (tpc_inspect)."""

@@ -70,18 +70,22 @@ def gpu_state(tracker, result):
         g[name] = tracker.inspect(what).cpu().numpy()
     g["owner"] = tracker.inspect(T.TPC_VIEW_OWNER).cpu().numpy().view(np.uint32)
     for name, what in (("trk_start", T.TPC_VIEW_TRK_START), ("trk_unit", T.TPC_VIEW_TRK_UNIT),
-                       ("trk_len", T.TPC_VIEW_TRK_LEN), ("trk_nfit", T.TPC_VIEW_TRK_NFIT),
-                       ("trk_rlo", T.TPC_VIEW_TRK_RLO), ("trk_rhi", T.TPC_VIEW_TRK_RHI),
-                       ("trk_owned", T.TPC_VIEW_TRK_OWNED), ("trk_keep", T.TPC_VIEW_TRK_KEEP)):
+                       ("trk_len", T.TPC_VIEW_TRK_LEN)):
         g[name] = tracker.inspect(what).cpu().numpy()[:K]
-    g["trk_key"] = tracker.inspect(T.TPC_VIEW_TRK_KEY).cpu().numpy().view(np.uint32)[:K]
-    g["trk_params"] = tracker.inspect(T.TPC_VIEW_TRK_PARAMS, torch.float32).cpu().numpy().reshape(-1, 5)[:K]
-    g["trk_cov"] = tracker.inspect(T.TPC_VIEW_TRK_COV, torch.float32).cpu().numpy().reshape(-1, 15)[:K]
-    g["trk_xref"] = tracker.inspect(T.TPC_VIEW_TRK_XREF, torch.float32).cpu().numpy()[:K]
-    g["trk_chi2"] = tracker.inspect(T.TPC_VIEW_TRK_CHI2, torch.float32).cpu().numpy()[:K]
+    # the fit's fields are stored per seed; spread them over the tracklets
+    for name, what in (("trk_nfit", T.TPC_VIEW_TRK_NFIT), ("trk_rlo", T.TPC_VIEW_TRK_RLO),
+                       ("trk_rhi", T.TPC_VIEW_TRK_RHI), ("trk_owned", T.TPC_VIEW_TRK_OWNED),
+                       ("trk_keep", T.TPC_VIEW_TRK_KEEP), ("trk_p1n", T.TPC_VIEW_TRK_P1N)):
+        g[name] = tracker.tracklet_field(what)
+    g["trk_key"] = tracker.tracklet_field(T.TPC_VIEW_TRK_KEY).view(np.uint32)
+    g["trk_params"] = tracker.tracklet_field(T.TPC_VIEW_TRK_PARAMS, torch.float32, 5)
+    g["trk_cov"] = tracker.tracklet_field(T.TPC_VIEW_TRK_COV, torch.float32, 15)
+    g["trk_xref"] = tracker.tracklet_field(T.TPC_VIEW_TRK_XREF, torch.float32)
+    g["trk_chi2"] = tracker.tracklet_field(T.TPC_VIEW_TRK_CHI2, torch.float32)
     # seeds: tracklets with a chain of >= l_min hits, in tracklet order
     seeds = np.nonzero(g["trk_len"] >= int(tracker.params.l_min))[0]
-    g["seed_list"] = tracker.inspect(T.TPC_VIEW_SEED_LIST).cpu().numpy()[:len(seeds)]
+    g["n_seeds"] = result["n_seeds"]
+    g["seed_list"] = tracker.inspect(T.TPC_VIEW_SEED_LIST).cpu().numpy()[:result["n_seeds"]]
     g["seeds_expected"] = seeds
     raw = tracker.inspect(T.TPC_VIEW_TRK_HITS).cpu().numpy().reshape(-1, n_rows, 64)
     per_seed = raw.transpose(0, 2, 1).reshape(-1, n_rows)[:len(seeds)]  # [seed][row]
@@ -218,6 +222,9 @@ def compare(g, o, check_outputs=True, rtol_scale=1.0):
     gp, op = gpu_hit_pairs(g), oracle_hit_pairs(o)
     same = ~hit_set_diff(gp, op, K)
     same &= g["trk_nfit"] == o["trk_nfit"]
+    if "trk_p1n" in g:  # the first pass took the same number of hits
+        fitted = o["trk_nfit"] > 0
+        same &= ~fitted | (g["trk_p1n"] == o["trk_p1n"])
     diff = np.nonzero(~same)[0]
     rep["n_hitset_diff"] = int(len(diff))
     rep["n_fragile"] = int(o["trk_fragile"].sum())

@@ -291,6 +291,31 @@ def test_capacity_exceeded_then_retry(T):
     assert tr2.result()["n_tracks"] == o["n_tracks"]
 
 
+def test_seed_capacity_exceeded_then_retry(T):
+    """A seed capacity below the batch's seeds (n / 64 + 64 for a central Pb-Pb
+    collision with about n / 29 seeds) fails with TPC_E_CAPACITY and reports
+    the seeds needed in counts[4]; a retry with the divisor derived from it
+    gives the oracle's tracks."""
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS
+    from paper_2106_03636_amd.runtime import Batch, Tracker, TrackingError
+    ev = cached_event("pbpb_central")
+    o = cached_oracle("pbpb_central")
+    b = Batch.from_event(ev)
+    seeds = int((o["trk_len"] >= DEFAULT_PARAMS["l_min"]).sum())
+    tr = Tracker(b.n, b.n_units, params=dict(DEFAULT_PARAMS, tracklet_cap_div=64))
+    tr.launch(b)
+    with pytest.raises(TrackingError) as e:
+        tr.result()
+    assert e.value.status == T.TPC_E_CAPACITY
+    counts = tr.o_counts.cpu().numpy()
+    assert counts[4] == seeds and counts[2] == o["n_tracklets"]
+    div = max(2, int(b.n // int(counts[4])))
+    tr2 = Tracker(b.n, b.n_units, params=dict(DEFAULT_PARAMS, tracklet_cap_div=div))
+    tr2.launch(b)
+    r = tr2.result()
+    assert r["n_tracks"] == o["n_tracks"] and r["n_seeds"] == seeds
+
+
 def test_rerun_is_bit_identical(T):
     """Order-independent merges: two runs give identical bits (race check)."""
     import torch

@@ -21,7 +21,7 @@ def state_from_oracle(o, n_rows):
         if f is not None:
             seg[:, j] = o[f]
     g["seg"] = seg
-    for k in ("trk_start", "trk_unit", "trk_len", "trk_nfit", "trk_owned", "trk_keep", "trk_key"):
+    for k in ("trk_start", "trk_unit", "trk_len", "trk_nfit", "trk_p1n", "trk_owned", "trk_keep", "trk_key"):
         g[k] = o[k].copy()
     g["trk_params"] = o["trk_params"].astype(np.float32)
     g["trk_cov"] = o["trk_cov"].astype(np.float32)
@@ -91,6 +91,16 @@ def test_planted_hit_set_difference_is_reported(case):
     # a different hit in the same row, same count
     g = state_from_oracle(o, nr)
     g["seed_hits"][j, row] += 1
+    rep = parity.compare(g, o)
+    assert not rep.ok and rep["n_hitset_diff"] == 1
+
+
+def test_planted_first_pass_count_difference_is_reported(case):
+    import parity
+    o, nr = case
+    g = state_from_oracle(o, nr)
+    t = int(_unflagged_fitted(o)[0])
+    g["trk_p1n"][t] += 1  # same final hits, a different first pass
     rep = parity.compare(g, o)
     assert not rep.ok and rep["n_hitset_diff"] == 1
 
