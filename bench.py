@@ -37,6 +37,15 @@ B_ALG_TOTAL = sum(B_ALG.values())
 # VALU issue: 256 CUs x 4 SIMDs; a wave64 VALU instruction holds a 16-lane SIMD 4 cycles
 N_SIMD = 1024
 CLOCK_GHZ = 2.4
+# FP32 vector peak of MI355X (256 CUs x 128 FP32 lanes x 2 (FMA) x 2.4 GHz)
+FP32_PEAK_TFLOPS = 157.3
+# FP32 operations the method defines per Kalman hit update of the tracklet
+# constructor (counted on the update's formulas, each FMA as 2, each
+# division or square root as 1): parameter transport to the row 24 (with 3
+# square roots and 1 division), Jacobian and parameter step 35 (3
+# divisions), covariance transport F C F^T on the 15 stored entries 102,
+# measurement update with gain, state, covariance and chi2 119 (1 division)
+FIT_OPS_PER_UPDATE = 24 + 3 + 1 + 35 + 3 + 102 + 119 + 1
 SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
                "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY")
 KERNEL_FAMILY = {
@@ -44,8 +53,7 @@ KERNEL_FAMILY = {
     "k_cell_base": "grid", "k_tile_offsets": "grid", "k_tile_scatter": "grid", "k_bin_sort": "grid",
     "k_neighbours": "neighbours", "k_neighbours_wide": "neighbours", "k_clean": "cleaner", "k_scan_blocks": "cleaner",
     "k_compact_starts": "cleaner", "k_chains": "constructor", "k_compact_seeds": "constructor",
-    "k_fit": "constructor", "k_select": "selector",
-    "k_emit": "selector",
+    "k_fit": "constructor", "k_select_emit": "selector",
 }
 
 
@@ -668,6 +676,37 @@ def main():
     value = batch.n * args.steps / wall
     counters = measured_counters(dom_name, args.workload)
     traffic = counters.get("bytes_per_launch")
+    hbm = dict(achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+               algorithmic_bytes_per_launch=algo_bytes, traffic=traffic)
+    if dom_name == "k_fit":
+        # the constructor is bound by FP32 instruction issue, not by HBM: price it
+        # at the FP32 operations its Kalman updates define (both passes)
+        K = res["n_seeds"]
+        nfit = tr.inspect(T.TPC_VIEW_TRK_NFIT).cpu().numpy()[:K].astype(np.int64)
+        p1n = tr.inspect(T.TPC_VIEW_TRK_P1N).cpu().numpy()[:K].astype(np.int64)
+        fitted = nfit > 0
+        updates = int(nfit[fitted].sum() + p1n[fitted].sum())
+        flops = updates * FIT_OPS_PER_UPDATE
+        tfs = flops / (mean_k[dom] * 1e-3) / 1e12
+        roofline = dict(bound="alu", kernel=dom_name, achieved=tfs, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=tfs / FP32_PEAK_TFLOPS, traffic=traffic, valu_busy=counters.get("valu_busy"),
+                        hit_updates_per_launch=updates, ops_per_update=FIT_OPS_PER_UPDATE,
+                        algorithmic_flops_per_launch=flops, mean_ms=float(mean_k[dom]), hbm=hbm)
+    else:
+        roofline = dict(bound="hbm", kernel=dom_name, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=achieved / HBM_PEAK_GBS, traffic=traffic, valu_busy=counters.get("valu_busy"),
+                        algorithmic_bytes_per_launch=algo_bytes, mean_ms=float(mean_k[dom]))
+    # physics performance of the GPU result against MC truth, and the
+    # workspace the call needs as the input grows
+    from paper_2106_03636_amd import mctruth
+    physics = mctruth.report(ev.label, ev.unit_offsets, ev.tracks.pt, res["first_hit"].cpu().numpy(),
+                             res["n_hits"].cpu().numpy(), res["hits"].cpu().numpy(), pt_min=0.2)
+    memory = dict(workspace_bytes=int(tr.ws_bytes), workspace_bytes_per_cluster=tr.ws_bytes / batch.n,
+                  vs_n=[dict(clusters=int(nn), units=36,
+                             workspace_bytes=int(T.tpc_workspace_size(int(nn), 36, batch.n_rows, tr.params)))
+                        for nn in (1e4, 1e5, 1e6, 5e6, 2e7, 5e7, 1e8)])
+    for e in memory["vs_n"]:
+        e["bytes_per_cluster"] = e["workspace_bytes"] / e["clusters"]
     log("bench: per-kernel ms " + json.dumps(per_kernel))
 
     out = dict(
@@ -678,16 +717,14 @@ def main():
                     bz_tesla=batch.bz, collisions=50 if args.workload.startswith("pbpb_timeframe") else None,
                     grid_shape=dict(shape, source=shape_source)),
         p50_ms=float(np.percentile(step_ms, 50)), p99_ms=float(np.percentile(step_ms, 99)),
-        roofline=dict(bound="hbm", kernel=dom_name, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=traffic, valu_busy=counters.get("valu_busy"),
-                      algorithmic_bytes_per_launch=algo_bytes, mean_ms=float(mean_k[dom])),
+        roofline=roofline,
         pipeline_roofline=dict(bytes_per_cluster=B_ALG_TOTAL,
                                achieved=B_ALG_TOTAL * value / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                                frac=B_ALG_TOTAL * value / 1e9 / HBM_PEAK_GBS,
                                measured_copy_gbs=copy_gbs,
                                frac_of_copy=B_ALG_TOTAL * value / 1e9 / copy_gbs),
         kernel_ms=per_kernel, profiled_step_ms=profiled_step_ms,
-        tracks=res["n_tracks"], tracklets=res["n_tracklets"],
+        tracks=res["n_tracks"], tracklets=res["n_tracklets"], physics=physics, memory=memory,
     )
 
     # the plain form: one call per sector unit, same stream, same work
