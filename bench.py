@@ -199,7 +199,8 @@ def summarize_profiles(prof_dir, workload):
     print("\n".join(lines))
 
 
-def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_flight, params, seed=5001):
+def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_flight, params, seed=5001,
+                  n_capacity=256, batch_clusters=0):
     """Time frames arriving over time (Poisson) at the native server.
 
     A pool of frames is generated (80% Pb-Pb slices of 10-50 collisions, 20%
@@ -231,7 +232,8 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
     torch.cuda.synchronize(dev)
     rng = np.random.default_rng(seed + 1)
     srv = Server(frames[0].row_x, frames[0].bz, budget_bytes=int(budget_gb * (1 << 30)),
-                 max_in_flight=max_in_flight, queue_depth=64, params=params)
+                 max_in_flight=max_in_flight, queue_depth=64, params=params,
+                 max_batch_clusters=int(batch_clusters))
 
     def submit(i, host):
         f = frames[i]
@@ -245,13 +247,19 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
         done = [None] * len(ids)
         q = queue.Queue()
 
+        cpu = {}
+
         def collect():
+            c0 = time.thread_time()
             for _ in range(len(ids)):
                 k, tk, ta = q.get()
                 r = srv.poll(tk, arrays=False)
                 done[k] = (time.perf_counter() - ta, r)
                 srv.release(tk)
+            cpu["collect"] = time.thread_time() - c0
         th = threading.Thread(target=collect)
+        s0 = srv.stats()["host_cpu_s"]
+        c_sub = time.thread_time()
         th.start()
         t0 = time.perf_counter()
         ta = t0
@@ -276,17 +284,23 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
                 busy += 1
                 time.sleep(2e-4)
             q.put((k, tk, ta))
+        c_sub = time.thread_time() - c_sub
         th.join()
         wall = time.perf_counter() - t0
+        server_cpu = srv.stats()["host_cpu_s"] - s0
         lat = np.array([d[0] for d in done]) * 1e3
         bad = [d[1]["status"] for d in done if d[1]["status"] != 0]
         if bad:
             raise RuntimeError("served requests failed: %s" % bad[:4])
         ncl = float(sizes[ids].sum())
         batches = np.array([d[1]["batch_requests"] for d in done], np.float64)
+        # host cores: the server's own thread, and the client's submit and
+        # collect threads (paper §3.1.1 counts the cores that drive a GPU)
         return dict(requests=len(ids), clusters=ncl, wall_s=wall, throughput=ncl / wall,
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                    mean_batch_requests=float(batches.mean()), busy_retries=busy)
+                    mean_batch_requests=float(batches.mean()), busy_retries=busy,
+                    host_cores=dict(server_thread=server_cpu / wall,
+                                    client_threads=(c_sub + cpu.get("collect", 0.0)) / wall))
 
     def arrivals(n, load, cap):
         ids = rng.integers(0, len(frames), n)
@@ -295,17 +309,17 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
 
     # warm up, then the closed-loop capacity
     run(rng.integers(0, len(frames), 8), None, False)
-    capr = run(rng.integers(0, len(frames), max(32, n_sweep // 2)), None, False)
+    capr = run(rng.integers(0, len(frames), n_capacity), None, False)
     cap = capr["throughput"]
-    log("bench: served capacity %.3g clusters/s (mean %.2f requests per batch)"
-        % (cap, capr["mean_batch_requests"]))
+    log("bench: served capacity %.3g clusters/s (mean %.2f requests per batch, server thread %.2f cores)"
+        % (cap, capr["mean_batch_requests"], capr["host_cores"]["server_thread"]))
     out = dict(pool=dict(frames=len(frames), mean_clusters=float(sizes.mean()), min_clusters=float(sizes.min()),
                          max_clusters=float(sizes.max()), pbpb_share=float(np.mean(
                              [f.name.startswith("pbpb") for f in frames])), seed=seed),
-               budget_gb=budget_gb, max_in_flight=max_in_flight,
+               budget_gb=budget_gb, max_in_flight=max_in_flight, max_batch_clusters=int(batch_clusters),
                grid_shape={k: params[k] for k in ("bin_y_q", "bin_occ", "bin_zmin_q")},
                capacity=dict(clusters_per_s=cap, frames_per_s=cap / sizes.mean(),
-                             mean_batch_requests=capr["mean_batch_requests"]))
+                             mean_batch_requests=capr["mean_batch_requests"], host_cores=capr["host_cores"]))
     res = []
     main_ids = main_gaps = None
     for j, load in enumerate(loads):
@@ -358,7 +372,8 @@ def serving_bench(dev, n_frames, n_main, n_sweep, loads, budget_gb, max_in_fligh
     plain["at_served_main_load"]["stable"] = bool(loads[0] * cap < plain_cap)
     # both forms at a load the plain form sustains
     srv = Server(frames[0].row_x, frames[0].bz, budget_bytes=int(budget_gb * (1 << 30)),
-                 max_in_flight=max_in_flight, queue_depth=64, params=params)
+                 max_in_flight=max_in_flight, queue_depth=64, params=params,
+                 max_batch_clusters=int(batch_clusters))
     ids, gaps = arrivals(max(32, n_sweep // 2), 0.7, plain_cap)
     low = run(ids, gaps, False)
     srv.close()
@@ -533,11 +548,15 @@ def main():
                     help="tune the grid shape for this workload and store it in the autotune cache first")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-chunk batched measurement")
-    ap.add_argument("--serve-frames", type=int, default=32, help="frames in the serving pool")
+    ap.add_argument("--serve-frames", type=int, default=64, help="frames in the serving pool")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests at the main load")
     ap.add_argument("--serve-sweep", type=int, default=200, help="requests at each other load")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="the server's device memory")
     ap.add_argument("--serve-inflight", type=int, default=3, help="batches the server keeps on the GPU")
+    ap.add_argument("--serve-capacity-requests", type=int, default=256,
+                    help="requests of the closed loop that measures the served capacity")
+    ap.add_argument("--serve-batch-clusters", type=float, default=5e7,
+                    help="clusters packed into one batch at most (0: as many as the arena holds)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 runs of this script and exit")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
@@ -754,7 +773,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = serving_bench(dev, args.serve_frames, args.serve_requests, args.serve_sweep,
-                                       (0.7, 0.3, 0.5, 0.9), args.serve_budget_gb, args.serve_inflight, params)
+                                       (0.7, 0.3, 0.5, 0.9), args.serve_budget_gb, args.serve_inflight, params,
+                                       n_capacity=args.serve_capacity_requests,
+                                       batch_clusters=args.serve_batch_clusters)
 
     if args.cpu_units != 0:
         from paper_2106_03636_amd.params import DEFAULT_PARAMS

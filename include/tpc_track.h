@@ -308,6 +308,8 @@ typedef struct tpc_server_stats {
   int64_t submitted, completed, rejected_busy, rejected_nomem, rejected_invalid, batches;
   int32_t pending, in_flight;
   size_t arena_bytes, arena_used, arena_peak;
+  double host_cpu_s;             /* CPU seconds the server's host thread has used (the paper
+                                    measures the host cores a GPU needs, §3.1.1) */
 } tpc_server_stats_t;
 
 /* Create a server: allocates the arena (budget_bytes of device memory), the

@@ -13,7 +13,8 @@ import os
 from .params import DEFAULT_PARAMS
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_tpctrack.so")
+# TPC_TRACK_LIB: another build of the library to load instead of the in-tree one
+LIB_PATH = os.environ.get("TPC_TRACK_LIB") or os.path.join(HERE, "_tpctrack.so")
 
 TPC_PARAMS_VERSION = 1
 TPC_OK, TPC_E_INVALID, TPC_E_CAPACITY, TPC_E_NOMEM, TPC_E_HIP, TPC_E_BUSY = 0, -1, -2, -3, -4, -5

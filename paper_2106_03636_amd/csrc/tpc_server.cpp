@@ -10,6 +10,8 @@
 // create; pinned host staging is pooled and reused.
 
 #include <hip/hip_runtime.h>
+#include <pthread.h>
+#include <time.h>
 
 #include <algorithm>
 #include <atomic>
@@ -742,6 +744,11 @@ extern "C" int tpc_server_stats(tpc_server_t *s, tpc_server_stats_t *out) {
   out->in_flight = fl;
   out->arena_used = s->arena.used();
   out->arena_peak = s->arena.peak();
+  out->host_cpu_s = 0.0;
+  clockid_t cid;
+  struct timespec ts;
+  if (pthread_getcpuclockid(s->th.native_handle(), &cid) == 0 && clock_gettime(cid, &ts) == 0)
+    out->host_cpu_s = double(ts.tv_sec) + 1e-9 * double(ts.tv_nsec);
   return TPC_OK;
 }
 

@@ -45,7 +45,7 @@ class tpc_server_stats_t(ctypes.Structure):
                 ("rejected_invalid", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("pending", ctypes.c_int32), ("in_flight", ctypes.c_int32),
                 ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
-                ("arena_peak", ctypes.c_size_t)]
+                ("arena_peak", ctypes.c_size_t), ("host_cpu_s", ctypes.c_double)]
 
 
 _bound = False

@@ -214,3 +214,62 @@ def test_malformed_requests_fail_alone(frames):
         assert srv.stats()["rejected_invalid"] == 1
     finally:
         srv.close()
+
+
+def _tracks_as_sets(first, n_hits, hits):
+    """Each track's clusters, keyed by its smallest cluster id (tracks share no cluster)."""
+    out = {}
+    for t in range(len(first)):
+        h = np.sort(np.asarray(hits[first[t]:first[t] + n_hits[t]], np.int64))
+        out[int(h[0])] = (t, h)
+    return out
+
+
+def test_served_mix_matches_the_oracle(frames):
+    """Requests that share batches are checked against the CPU oracle
+    directly, on their outputs: the same tracks (cluster sets) and the same
+    cluster-to-track map for at least 99.9% of the tracks and clusters, and
+    the parity bars on the fitted parameters of every track whose cluster set
+    is the oracle's."""
+    import oracle
+    import parity
+    from paper_2106_03636_amd.params import DEFAULT_PARAMS
+    evs, alone = frames
+    srv = _server(evs, budget_bytes=4 << 30, max_in_flight=1, queue_depth=16)
+    try:
+        # a large frame holds the only slot, so the next ones queue and share a batch
+        order = [3, 0, 4, 1]
+        tickets = []
+        for i in order:
+            e = evs[i]
+            st, t = srv.submit(e.y, e.z, e.row, e.unit_offsets)
+            assert st == 0
+            tickets.append((i, t))
+        shared = 0
+        for i, t in tickets:
+            res = srv.poll(t)
+            shared += res["batch_requests"] > 1
+            e = evs[i]
+            o = oracle.run_event(e, DEFAULT_PARAMS)
+            g = _tracks_as_sets(res["first_hit"], res["n_hits"], res["hits"])
+            c = _tracks_as_sets(o["track_first_hit"], o["track_n_hits"], o["track_hits"])
+            same = [k for k in g if k in c and np.array_equal(g[k][1], c[k][1])]
+            print("served frame %d (batch of %d): %d tracks, %d oracle, %d identical" % (
+                i, res["batch_requests"], len(g), len(c), len(same)), flush=True)
+            assert len(same) >= parity.MIN_MATCHED_FRACTION * max(len(g), len(c))
+            gt = np.array([g[k][0] for k in same], np.int64)
+            ot = o["track_tracklet"][np.array([c[k][0] for k in same], np.int64)]
+            rep = parity.ParityReport()
+            parity.compare_fit(rep, res["params"][gt], res["cov"][gt], res["chi2"][gt], res["x_ref"][gt],
+                               o["trk_params"][ot], o["trk_cov"][ot], o["trk_chi2"][ot], o["trk_xref"][ot])
+            assert rep.ok, rep.get("failures")
+            # cluster -> track, through the track keys
+            def key_of(ct, sets):
+                inv = {t: k for k, (t, _) in sets.items()}
+                return np.array([inv.get(int(x), -1) if x >= 0 else -1 for x in ct], np.int64)
+            kg, kc = key_of(res["cluster_track"], g), key_of(o["cluster_track"], c)
+            assert (kg == kc).mean() >= parity.MIN_MATCHED_FRACTION
+            srv.release(t)
+        assert shared >= 2
+    finally:
+        srv.close()
