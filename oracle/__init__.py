@@ -95,6 +95,12 @@ def _load():
                                          ctypes.POINTER(Params), vp, vp, vp, vp]
         lib.orc_kf_update.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, vp]
+        lib.orc_zdca.restype = ctypes.c_double
+        lib.orc_zdca.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp, vp]
+        lib.orc_collisions.restype = ctypes.c_int64
+        lib.orc_collisions.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_double] + [vp] * 10
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -218,6 +224,40 @@ def kf_update(p, cov15, my, mz, sy, sz):
     chi2 = np.zeros(1)
     lib.orc_kf_update(p.ctypes.data, c.ctypes.data, my, mz, sy, sz, chi2.ctypes.data)
     return p, c, float(chi2[0])
+
+
+def zdca(p, x, k):
+    """z' at the transverse point of closest approach to the beam axis and the
+    arc length to it, for the state p at plane x (curvature k p[4])."""
+    lib = _load()
+    p = np.ascontiguousarray(p, np.float64)
+    sT, turn = np.zeros(1), np.zeros(1)
+    z = lib.orc_zdca(p.ctypes.data, float(x), float(k), sT.ctypes.data, turn.ctypes.data)
+    return float(z), float(sT[0])
+
+
+def collisions(params, x_ref, unit, unit_side, k, v_drift, width=1.0, zmax=4096.0, c_max=None, n_min=10,
+               reach=2, eps=0.0):
+    """Collision candidates of tracks (see orc_collisions in tpc_oracle.c).
+    c_max defaults to no cut (every track forms candidates)."""
+    lib = _load()
+    params = np.ascontiguousarray(params, np.float64).reshape(-1, 5)
+    n = len(params)
+    x_ref = np.ascontiguousarray(x_ref, np.float64)
+    unit = np.ascontiguousarray(unit, np.int32)
+    unit_side = np.ascontiguousarray(unit_side, np.int32)
+    zd, t0 = np.zeros(n), np.zeros(n)
+    col, frag = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    cap = 2 * int(np.ceil(2 * zmax / width)) + 1
+    cs, cb, cc, cf = (np.zeros(cap, np.int32) for _ in range(4))
+    cz, ct = np.zeros(cap), np.zeros(cap)
+    nc = lib.orc_collisions(n, params.ctypes.data, x_ref.ctypes.data, unit.ctypes.data, unit_side.ctypes.data,
+                            float(k), float(v_drift), float(width), float(zmax),
+                            float("inf") if c_max is None else float(c_max), int(n_min), int(reach), float(eps),
+                            zd.ctypes.data, t0.ctypes.data, col.ctypes.data, frag.ctypes.data, cs.ctypes.data,
+                            cb.ctypes.data, cc.ctypes.data, cf.ctypes.data, cz.ctypes.data, ct.ctypes.data)
+    return dict(zdca=zd, t0=t0, collision=col, fragile=frag, n_collisions=int(nc), side=cs[:nc], bin=cb[:nc],
+                count=cc[:nc], n_form=cf[:nc], c_zdca=cz[:nc], c_t0=ct[:nc])
 
 
 def num_threads() -> int:

@@ -1059,6 +1059,135 @@ int orc_run(int64_t n, int64_t n_units, const int64_t *unit_offsets, const float
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Collision assignment in continuous readout (a step after track finding).    */
+/* The paper states that in continuous readout the collisions overlap in the   */
+/* drift volume and that tracks are assigned to collisions only after tracking */
+/* (§2, §2.3); it does not say how.  Reading used here: the measured z' of a   */
+/* cluster is z - side v_d t0, so every track of one collision on one side of  */
+/* the TPC carries the same z' at the vertex, z_vertex - side v_d t0.  A       */
+/* track's z' at its transverse point of closest approach to the beam axis     */
+/* estimates it.  That estimate is unambiguous only for a track whose circle   */
+/* does not fit inside the TPC (|C| < c_max = 2 / outer radius): a looper may  */
+/* be seen on a later leg or turn, where z' is off by the z advance per turn.  */
+/* Per side, the z' of those "forming" tracks are histogrammed in bins of      */
+/* width w over [-zmax, zmax); a candidate collision is a bin holding at least */
+/* n_min of them that is the largest within `reach` bins on either side (ties  */
+/* go to the lower bin).  Every track in the range (loopers too) joins the     */
+/* candidate whose bin is nearest to its own within `reach` bins (ties to the  */
+/* lower bin), else none.  A candidate's z' is the mean over the forming       */
+/* tracks it holds, its t0 = -side z' / v_d with the vertex taken at z = 0     */
+/* (the spread of vertex z is the resolution of t0 here).                      */
+
+/* z' at the transverse point of closest approach to the beam axis (x = y = 0
+ * of the sector frame) of the helix with state p at plane x, curvature k p[4].
+ * The closest point of a circle to the origin lies on the line from the
+ * circle's centre to the origin; the arc length to it follows from the signed
+ * angle it turns about the centre.  *sT: transverse arc length from the
+ * reference point (negative toward the beam); *turn: that angle (radians). */
+double orc_zdca(const double p[5], double x, double k, double *sT_out, double *turn_out) {
+  const double y = p[0], z = p[1], sphi = p[2], tgl = p[3];
+  const double C = k * p[4];
+  const double cphi = sqrt(1.0 - sphi * sphi);
+  double sT = 0.0, turn = 0.0;
+  if (C == 0.0) {  /* straight line: foot of the perpendicular from the origin */
+    sT = -(x * cphi + y * sphi);
+  } else {
+    const double xc = x - sphi / C, yc = y + cphi / C; /* centre of the circle */
+    const double dc = sqrt(xc * xc + yc * yc);
+    if (dc > 0.0) {
+      const double R = 1.0 / fabs(C);
+      const double px = xc * (1.0 - R / dc), py = yc * (1.0 - R / dc);
+      const double ax = x - xc, ay = y - yc, bx = px - xc, by = py - yc;
+      turn = atan2(ax * by - ay * bx, ax * bx + ay * by);
+      sT = turn / C;
+    }
+  }
+  if (sT_out) *sT_out = sT;
+  if (turn_out) *turn_out = turn;
+  return z + tgl * sT;
+}
+
+/* Histogram bin of a z' value (range [-zmax, zmax) in bins of width w), or -1. */
+static int64_t col_bin(double z, double w, double zmax) {
+  if (!(z >= -zmax && z < zmax)) return -1;
+  return (int64_t)floor((z + zmax) / w);
+}
+
+/* Collision candidates of n_tracks tracks (state at x_ref in the frame of
+ * their unit, unit_side[unit] = +1 or -1).  Outputs per track: zdca, t0 (us,
+ * the track's own estimate), collision (-1 none; candidates are numbered side
+ * A first, then by increasing bin) and fragile (1 when another rounding of its
+ * z' could move it to the next bin: within eps of a bin edge or of the range
+ * ends, or a closest point half a turn away); per candidate (capacity: all
+ * bins of both sides): side, bin, tracks assigned, forming tracks assigned,
+ * mean z' and t0.  Returns the number of candidates. */
+int64_t orc_collisions(int64_t n_tracks, const double *params, const double *x_ref, const int32_t *unit,
+                       const int32_t *unit_side, double k, double v_drift, double w, double zmax,
+                       double c_max, int32_t n_min, int32_t reach, double eps, double *zdca, double *t0,
+                       int32_t *collision, int32_t *fragile, int32_t *c_side, int32_t *c_bin,
+                       int32_t *c_count, int32_t *c_form, double *c_zdca, double *c_t0) {
+  const int64_t nb = (int64_t)ceil(2.0 * zmax / w);
+  int32_t *hist = (int32_t *)xcalloc((size_t)(2 * nb), sizeof(int32_t)); /* [side A, side C][bin] */
+  int64_t *cand = (int64_t *)xcalloc((size_t)(2 * nb), sizeof(int64_t)); /* candidate of a bin, -1 */
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    const int32_t side = unit_side[unit[t]];
+    double turn = 0.0;
+    zdca[t] = orc_zdca(&params[t * 5], x_ref[t], k, NULL, &turn);
+    t0[t] = -(double)side * zdca[t] / v_drift;
+    const double f = (zdca[t] + zmax) / w;
+    fragile[t] = fabs(f - nearbyint(f)) * w < eps || fabs(fabs(turn) - 3.14159265358979323846) < eps;
+    const int64_t b = col_bin(zdca[t], w, zmax);
+    if (b >= 0 && fabs(k * params[t * 5 + 4]) < c_max) hist[(side > 0 ? 0 : nb) + b] += 1;
+  }
+  int64_t nc = 0;
+  for (int s = 0; s < 2; ++s) {
+    const int32_t *h = hist + s * nb;
+    for (int64_t b = 0; b < nb; ++b) {
+      cand[s * nb + b] = -1;
+      if (h[b] < n_min) continue;
+      int peak = 1;
+      for (int64_t d = 1; d <= reach && peak; ++d) {
+        if (b - d >= 0 && h[b - d] >= h[b]) peak = 0; /* a lower bin as large wins */
+        if (b + d < nb && h[b + d] > h[b]) peak = 0;
+      }
+      if (!peak) continue;
+      cand[s * nb + b] = nc;
+      c_side[nc] = s == 0 ? 1 : -1;
+      c_bin[nc] = (int32_t)b;
+      c_count[nc] = 0;
+      c_form[nc] = 0;
+      c_zdca[nc] = 0.0;
+      ++nc;
+    }
+  }
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    collision[t] = -1;
+    const int32_t side = unit_side[unit[t]];
+    const int64_t b = col_bin(zdca[t], w, zmax);
+    if (b < 0) continue;
+    const int64_t *cs = cand + (side > 0 ? 0 : nb);
+    for (int64_t d = 0; d <= reach; ++d) { /* nearest candidate bin, the lower one first */
+      if (b - d >= 0 && cs[b - d] >= 0) { collision[t] = (int32_t)cs[b - d]; break; }
+      if (b + d < nb && cs[b + d] >= 0) { collision[t] = (int32_t)cs[b + d]; break; }
+    }
+    const int32_t c = collision[t];
+    if (c < 0) continue;
+    c_count[c] += 1;
+    if (fabs(k * params[t * 5 + 4]) < c_max) {
+      c_form[c] += 1;
+      c_zdca[c] += zdca[t];
+    }
+  }
+  for (int64_t c = 0; c < nc; ++c) { /* a candidate holds the >= n_min forming tracks of its own bin */
+    c_zdca[c] /= c_form[c];
+    c_t0[c] = -(double)c_side[c] * c_zdca[c] / v_drift;
+  }
+  free(hist);
+  free(cand);
+  return nc;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -39,6 +39,7 @@ SIGMA_Y, SIGMA_Z = 0.1, 0.15  # cm
 VERTEX_SIGMA = (0.01, 0.01, 5.0)
 NOISE_FRACTION = 0.05
 ETA_MAX = 0.9
+R_EXIT = ROW_X1 / math.cos(math.radians(HALF_OPEN_DEG))  # outer wall: the corner of the outermost row
 
 
 def sector_alpha(sector: int) -> float:
@@ -61,13 +62,12 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
+        build()  # compiles when missing or older than its source
         lib = ctypes.CDLL(_LIB_PATH)
         d = ctypes.POINTER(ctypes.c_double)
         lib.synth_crossings.restype = ctypes.c_int64
         lib.synth_crossings.argtypes = [ctypes.c_int64, d, d, d, d, d, d, ctypes.c_int, d,
-                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -107,8 +107,10 @@ class Tracks:
                         ("vx", "vy", "vz", "pt", "phi0", "tgl", "q", "t0")])
 
 
-def helix_crossings(tr: Tracks, bz: float, max_turns: float = 2.0, z_max: float = Z_MAX):
+def helix_crossings(tr: Tracks, bz: float, max_turns: float = 2.0, z_max: float = Z_MAX, r_exit: float = 0.0):
     """All (sector, row) crossings of the helices, noise-free, FP64, true z.
+    With r_exit > 0 a helix ends where it first leaves the cylinder of that
+    radius (R_EXIT: the outer wall); by default it is followed for max_turns.
 
     Returns a dict of arrays ordered by (track, sector, row, arc length).
     """
@@ -118,13 +120,13 @@ def helix_crossings(tr: Tracks, bz: float, max_turns: float = 2.0, z_max: float 
             (tr.vx, tr.vy, tr.vz, tr.curvature(bz), tr.phi0, tr.tgl)]
     counts = np.zeros(n, dtype=np.int64)
     lib.synth_crossings(n, *[_dptr(a) for a in args], N_ROWS, _dptr(ROW_X), TAN_HALF, z_max,
-                        max_turns, _ptr(counts), None, None, None, None, None, None, None, None)
+                        max_turns, float(r_exit), _ptr(counts), None, None, None, None, None, None, None, None)
     tot = int(counts.sum())
     out = dict(sector=np.empty(tot, np.int32), row=np.empty(tot, np.int32),
                track=np.empty(tot, np.int32), y=np.empty(tot), z=np.empty(tot),
                s=np.empty(tot), sinphi=np.empty(tot), cosphi=np.empty(tot))
     lib.synth_crossings(n, *[_dptr(a) for a in args], N_ROWS, _dptr(ROW_X), TAN_HALF, z_max,
-                        max_turns, _ptr(counts), _ptr(out["sector"]), _ptr(out["row"]),
+                        max_turns, float(r_exit), _ptr(counts), _ptr(out["sector"]), _ptr(out["row"]),
                         _ptr(out["track"]), _ptr(out["y"]), _ptr(out["z"]), _ptr(out["s"]),
                         _ptr(out["sinphi"]), _ptr(out["cosphi"]))
     return out
@@ -168,8 +170,12 @@ def _pt_pbpb(rng, n):
     return np.maximum(pt, 1e-3)
 
 
-def primaries_pbpb(rng, n, t0=0.0, phi_range=None):
-    vx, vy, vz = _vertex(rng, n)
+def primaries_pbpb(rng, n, t0=0.0, phi_range=None, vertex=None):
+    """Soft Pb-Pb spectrum; a vertex per particle, or the given common one."""
+    if vertex is None:
+        vx, vy, vz = _vertex(rng, n)
+    else:
+        vx, vy, vz = (np.full(n, float(c)) for c in vertex)
     if phi_range is None:
         phi0 = rng.uniform(-math.pi, math.pi, n)
     else:
@@ -301,17 +307,28 @@ def pbpb_multiplicity(rng, n):
 
 
 def event_pbpb_timeframe(seed: int, n_collisions: int = 50, slice_us: float = None,
-                         bz: float = 0.5) -> Event:
+                         bz: float = 0.5, physical: bool = False) -> Event:
     """Continuous-readout slice: n_collisions min-bias Pb-Pb collisions at times
-    uniform over the slice (default n / 50 kHz); z' = z - side * v_drift * t0."""
+    uniform over the slice (default n / 50 kHz); z' = z - side * v_drift * t0.
+
+    By default every particle draws its own vertex and its helix is followed
+    for two full turns (also after it has left through the outer wall): extra
+    passes that load the tracker like loopers and secondaries do.  physical=True
+    gives each collision one vertex and ends a helix at the outer wall
+    (R_EXIT), as in a detector: the frame on which tracks are assigned to
+    collisions."""
     rng = np.random.default_rng(seed)
     if slice_us is None:
         slice_us = n_collisions / 50e3 * 1e6
     mult = pbpb_multiplicity(rng, n_collisions)
     t0s = rng.uniform(0.0, slice_us, n_collisions)
-    parts = [primaries_pbpb(rng, int(m), t0=t) for m, t in zip(mult, t0s)]
+    if physical:
+        verts = np.stack(_vertex(rng, n_collisions), axis=1)
+        parts = [primaries_pbpb(rng, int(m), t0=t, vertex=v) for m, t, v in zip(mult, t0s, verts)]
+    else:
+        parts = [primaries_pbpb(rng, int(m), t0=t) for m, t in zip(mult, t0s)]
     tr = Tracks.concat(parts)
-    xs = helix_crossings(tr, bz)
+    xs = helix_crossings(tr, bz, r_exit=R_EXIT if physical else 0.0)
     t0 = tr.t0
 
     def shift(trk, side):

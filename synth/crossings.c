@@ -15,7 +15,10 @@
  * phi = phi0 + C s, centre c = v + (1/C) (-sin phi0, cos phi0).
  * A crossing with row line (s, i) satisfies sin(phi - alpha) = C (x_i - c.e);
  * its local y is c.e_perp - cos(phi - alpha)/C.  The helix is followed for at
- * most max_turns full turns and while |z| <= z_max.
+ * most max_turns full turns and while |z| <= z_max; with r_exit > 0 also only
+ * up to the arc length where it first leaves the cylinder r = r_exit around
+ * the beam axis (a particle that leaves the TPC through its outer wall does not
+ * come back; loopers that stay inside keep their turns).
  *
  * Output: one record per crossing, ordered by (track, sector, row, arc length),
  * so the result does not depend on the number of threads.
@@ -34,11 +37,38 @@ typedef struct {
   double cosphi_local;
 } xing_t;
 
+/* Arc length at which the helix first reaches distance r_exit from the beam
+ * axis (the vertex lies inside), or infinity when it never does or r_exit <= 0. */
+static double exit_arc(double vx, double vy, double curv, double phi0, double r_exit) {
+  if (r_exit <= 0.0) return INFINITY;
+  if (curv == 0.0) { /* |v + s u| = r_exit, u = (cos phi0, sin phi0), the positive root */
+    const double vu = vx * cos(phi0) + vy * sin(phi0);
+    return -vu + sqrt(vu * vu - (vx * vx + vy * vy) + r_exit * r_exit);
+  }
+  const double R = 1.0 / curv; /* signed */
+  const double cx = vx - R * sin(phi0), cy = vy + R * cos(phi0);
+  const double dc = sqrt(cx * cx + cy * cy);
+  if (dc + fabs(R) <= r_exit) return INFINITY;
+  /* |P|^2 = dc^2 + R^2 + 2 R dc sin(phi - psi), psi the direction of the centre */
+  const double kap = (r_exit * r_exit - dc * dc - R * R) / (2.0 * R * dc);
+  if (fabs(kap) > 1.0) return INFINITY;
+  const double psi = atan2(cy, cx), a0 = asin(kap);
+  double best = INFINITY;
+  for (int k = 0; k < 2; ++k) {
+    const double phi_star = psi + (k == 0 ? a0 : M_PI - a0);
+    double dphi = fmod((phi_star - phi0) * (curv > 0 ? 1.0 : -1.0), TWO_PI);
+    if (dphi < 0) dphi += TWO_PI;
+    if (dphi / fabs(curv) < best) best = dphi / fabs(curv);
+  }
+  return best;
+}
+
 /* Enumerate crossings of one helix; store up to cap of them in out, return the count. */
 static int64_t one_track(double vx, double vy, double vz, double curv, double phi0,
                          double tgl, int n_rows, const double *row_x, double tan_half,
-                         double z_max, double max_turns, xing_t *out, int64_t cap) {
+                         double z_max, double max_turns, double r_exit, xing_t *out, int64_t cap) {
   int64_t n = 0;
+  const double s_exit = exit_arc(vx, vy, curv, phi0, r_exit);
   for (int sec = 0; sec < 36; ++sec) {
     const double a = ((sec % 18) * 20.0 + 10.0) * (M_PI / 180.0);
     const double ca = cos(a), sa = sin(a);
@@ -104,7 +134,7 @@ static int64_t one_track(double vx, double vy, double vz, double curv, double ph
         }
       for (int p = 0; p < nc; ++p) {
         const double z = vz + tgl * cand_s[p];
-        if (fabs(z) > z_max) continue;
+        if (fabs(z) > z_max || cand_s[p] > s_exit) continue;
         if ((side > 0 && !(z > 0.0)) || (side < 0 && !(z < 0.0))) continue;
         if (n < cap) {
           out[n].sector = sec;
@@ -131,7 +161,7 @@ static int64_t one_track(double vx, double vy, double vz, double curv, double ph
 int64_t synth_crossings(int64_t n_trk, const double *vx, const double *vy, const double *vz,
                         const double *curv, const double *phi0, const double *tgl,
                         int n_rows, const double *row_x, double tan_half, double z_max,
-                        double max_turns, int64_t *counts, int32_t *out_sector,
+                        double max_turns, double r_exit, int64_t *counts, int32_t *out_sector,
                         int32_t *out_row, int32_t *out_track, double *out_y, double *out_z,
                         double *out_s, double *out_sinphi, double *out_cosphi) {
   const int fill = out_sector != NULL;
@@ -152,7 +182,7 @@ int64_t synth_crossings(int64_t n_trk, const double *vx, const double *vy, const
       cap = counts[t];
     }
     int64_t n = one_track(vx[t], vy[t], vz[t], curv[t], phi0[t], tgl[t], n_rows, row_x,
-                          tan_half, z_max, max_turns, b, cap);
+                          tan_half, z_max, max_turns, r_exit, b, cap);
     if (!fill) {
       counts[t] = n;
     } else {

@@ -12,6 +12,7 @@ import subprocess
 import pytest
 
 import oracle
+import test_collisions_oracle as col
 import test_oracle_pins as pins
 from conftest import cached_event, cached_oracle
 
@@ -81,6 +82,28 @@ MUTATIONS = [
      "res->trk_key[t] = ((uint32_t)o.nfit << 24) | (0xFFFFFFu - local);",
      "res->trk_key[t] = ((uint32_t)o.nfit << 20) | (0xFFFFFFu - local);",
      [pins.test_owner_is_max_key_over_incidences, pins.test_selection_invariants]),
+    ("zdca_arc_sign",
+     "  return z + tgl * sT;", "  return z - tgl * sT;",
+     [col.test_zdca_is_the_vertex_z_of_generated_helices]),
+    ("collision_t0_ignores_side",
+     "    c_t0[c] = -(double)c_side[c] * c_zdca[c] / v_drift;", "    c_t0[c] = -c_zdca[c] / v_drift;",
+     [col.test_histogram_peaks_and_assignment_hand_worked]),
+    ("peak_tie_to_both",
+     "if (b - d >= 0 && h[b - d] >= h[b]) peak = 0;", "if (b - d >= 0 && h[b - d] > h[b]) peak = 0;",
+     [col.test_histogram_peaks_and_assignment_hand_worked]),
+    ("loopers_form_candidates",
+     "if (b >= 0 && fabs(k * params[t * 5 + 4]) < c_max) hist", "if (b >= 0) hist",
+     [col.test_histogram_peaks_and_assignment_hand_worked]),
+    ("loopers_in_the_mean",
+     "    if (fabs(k * params[t * 5 + 4]) < c_max) {\n      c_form[c] += 1;",
+     "    if (1) {\n      c_form[c] += 1;",
+     [col.test_histogram_peaks_and_assignment_hand_worked]),
+    ("nearest_tie_to_the_upper_bin",
+     "      if (b - d >= 0 && cs[b - d] >= 0) { collision[t] = (int32_t)cs[b - d]; break; }\n"
+     "      if (b + d < nb && cs[b + d] >= 0) { collision[t] = (int32_t)cs[b + d]; break; }",
+     "      if (b + d < nb && cs[b + d] >= 0) { collision[t] = (int32_t)cs[b + d]; break; }\n"
+     "      if (b - d >= 0 && cs[b - d] >= 0) { collision[t] = (int32_t)cs[b - d]; break; }",
+     [col.test_histogram_peaks_and_assignment_hand_worked]),
 ]
 
 
