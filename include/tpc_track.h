@@ -191,6 +191,77 @@ const char *tpc_kernel_name(int32_t i);
 /* Human-readable text of a status code (static storage). */
 const char *tpc_status_string(int status);
 
+/* ------------------------------------------------------------------------- */
+/* Collision assignment.  In continuous readout the collisions of a time     */
+/* frame overlap in the drift volume, and tracks are assigned to them only   */
+/* after tracking (paper §2, §2.3); the paper does not describe how.  What   */
+/* this call computes:                                                       */
+/*   - per track, z'_dca: z' at the transverse point of closest approach of  */
+/*     its helix to the beam axis (FP64, from the FP32 state at x_ref, with  */
+/*     curvature C = -0.00299792458f * bz * q/pT as the tracker's fit uses). */
+/*     A track from a collision at time t0 and vertex z_v has                */
+/*     z'_dca = z_v - side v_drift t0 (side +1 for A, -1 for C);             */
+/*   - per side, a histogram of z'_dca over [-z_range, z_range) in bins of   */
+/*     bin_width, of the "forming" tracks only: |C| < c_max.  A track whose  */
+/*     circle fits inside the TPC (a looper) may be seen on a later leg or   */
+/*     turn, where z'_dca is off by the z advance of a turn; c_max = 2 /     */
+/*     (outer radius) keeps those out;                                       */
+/*   - candidates: bins holding at least n_min forming tracks that are the  */
+/*     largest within `reach` bins either side (a lower bin as large wins),  */
+/*     numbered side A first, then by increasing bin;                        */
+/*   - every track in the range (loopers too) joins the candidate whose bin  */
+/*     is nearest to its own within `reach` bins (the lower one on a tie),   */
+/*     else none (-1);                                                       */
+/*   - per candidate: the tracks and forming tracks it holds, z = the mean   */
+/*     z'_dca of its forming tracks (summed in fixed point, 2^-16 cm per     */
+/*     track, so the result does not depend on the order of the sums), and   */
+/*     t0 = -side z / v_drift (us), the vertex taken at z = 0.               */
+/* ------------------------------------------------------------------------- */
+
+typedef struct tpc_collision_params {
+  float v_drift;               /* drift velocity (cm/us), > 0 */
+  float bin_width;             /* histogram bin width (cm), > 0 */
+  float z_range;               /* histogram range [-z_range, z_range), <= 2^20 cm;
+                                  ceil(2 z_range / bin_width) <= 65536 bins per side */
+  float c_max;                 /* forming tracks: |curvature| < c_max (1/cm), >= 0 */
+  int32_t n_min;               /* forming tracks a candidate's bin holds at least, >= 1 */
+  int32_t reach;               /* bins, 0 <= reach <= 64 */
+} tpc_collision_params_t;
+
+/* Outputs (device pointers, allocated by the caller). */
+typedef struct tpc_collisions {
+  int64_t cap;                 /* capacity of the per-candidate arrays */
+  double *zdca;                /* [cap_tracks of the input] z'_dca per track */
+  int32_t *collision;          /* [cap_tracks] candidate of each track, -1 none */
+  int32_t *side;               /* [cap] +1 (A) or -1 (C) */
+  int32_t *bin;                /* [cap] histogram bin on its side */
+  int32_t *count;              /* [cap] tracks assigned */
+  int32_t *n_form;             /* [cap] forming tracks assigned (>= n_min) */
+  double *z;                   /* [cap] mean z'_dca of the forming tracks (cm) */
+  double *t0;                  /* [cap] (us) */
+  int64_t *n_collisions;       /* [1] number of candidates (also when it exceeds cap) */
+  int32_t *status;             /* [1] TPC_OK, the tracker's own status when that is not TPC_OK,
+                                  TPC_E_INVALID (a track's unit has no side +-1), or
+                                  TPC_E_CAPACITY (n_collisions > cap); outputs are valid
+                                  only with TPC_OK */
+} tpc_collisions_t;
+
+/* Bytes of device workspace tpc_assign_collisions needs (host-only, pure;
+ * 0 on bad parameters). */
+size_t tpc_collisions_workspace_size(const tpc_collision_params_t *params);
+
+/* Assign the tracks of a tpc_track_sectors output to collisions.  `tracks` is
+ * that call's output struct (params, x_ref, unit, counts, status are read on
+ * the device, cap_tracks on the host); unit_side is a device array of n_units
+ * entries, +1 or -1, the side of each unit's sector.  Enqueued on `stream`
+ * after the tracking call (same stream, or ordered by the caller); the
+ * workspace (aligned to 256 bytes) holds no state across calls.  Returns
+ * TPC_OK when the work was enqueued, TPC_E_INVALID / TPC_E_NOMEM on bad
+ * arguments or a small workspace, TPC_E_HIP on a launch failure. */
+int tpc_assign_collisions(const tpc_tracks_t *tracks, const int32_t *unit_side, int32_t n_units,
+                          const tpc_field_t *field, const tpc_collision_params_t *params,
+                          tpc_collisions_t *out, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Intermediate arrays kept in the workspace after a call, for inspection and
  * tests.  Valid until the workspace is reused.  `what` selects the array:
  *   TPC_VIEW_PERM      int32 [n]  sorted position -> cluster id

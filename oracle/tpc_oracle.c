@@ -1108,10 +1108,12 @@ double orc_zdca(const double p[5], double x, double k, double *sT_out, double *t
   return z + tgl * sT;
 }
 
-/* Histogram bin of a z' value (range [-zmax, zmax) in bins of width w), or -1. */
-static int64_t col_bin(double z, double w, double zmax) {
+/* Histogram bin of a z' value (range [-zmax, zmax) in nb bins of width w), or
+ * -1; a value just below zmax whose quotient rounds up to nb is in the last bin. */
+static int64_t col_bin(double z, double w, double zmax, int64_t nb) {
   if (!(z >= -zmax && z < zmax)) return -1;
-  return (int64_t)floor((z + zmax) / w);
+  const int64_t b = (int64_t)floor((z + zmax) / w);
+  return b < nb ? b : nb - 1;
 }
 
 /* Collision candidates of n_tracks tracks (state at x_ref in the frame of
@@ -1137,7 +1139,7 @@ int64_t orc_collisions(int64_t n_tracks, const double *params, const double *x_r
     t0[t] = -(double)side * zdca[t] / v_drift;
     const double f = (zdca[t] + zmax) / w;
     fragile[t] = fabs(f - nearbyint(f)) * w < eps || fabs(fabs(turn) - 3.14159265358979323846) < eps;
-    const int64_t b = col_bin(zdca[t], w, zmax);
+    const int64_t b = col_bin(zdca[t], w, zmax, nb);
     if (b >= 0 && fabs(k * params[t * 5 + 4]) < c_max) hist[(side > 0 ? 0 : nb) + b] += 1;
   }
   int64_t nc = 0;
@@ -1164,7 +1166,7 @@ int64_t orc_collisions(int64_t n_tracks, const double *params, const double *x_r
   for (int64_t t = 0; t < n_tracks; ++t) {
     collision[t] = -1;
     const int32_t side = unit_side[unit[t]];
-    const int64_t b = col_bin(zdca[t], w, zmax);
+    const int64_t b = col_bin(zdca[t], w, zmax, nb);
     if (b < 0) continue;
     const int64_t *cs = cand + (side > 0 ? 0 : nb);
     for (int64_t d = 0; d <= reach; ++d) { /* nearest candidate bin, the lower one first */

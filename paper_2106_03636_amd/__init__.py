@@ -64,6 +64,17 @@ class tpc_tracks_t(ctypes.Structure):
                 ("first_hit", _vp), ("hits", _vp), ("counts", _vp), ("status", _vp)]
 
 
+class tpc_collision_params_t(ctypes.Structure):
+    _fields_ = [("v_drift", ctypes.c_float), ("bin_width", ctypes.c_float), ("z_range", ctypes.c_float),
+                ("c_max", ctypes.c_float), ("n_min", ctypes.c_int32), ("reach", ctypes.c_int32)]
+
+
+class tpc_collisions_t(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64), ("zdca", _vp), ("collision", _vp), ("side", _vp), ("bin", _vp),
+                ("count", _vp), ("n_form", _vp), ("z", _vp), ("t0", _vp), ("n_collisions", _vp),
+                ("status", _vp)]
+
+
 class tpc_view_t(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("count", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -100,6 +111,12 @@ def load_library():
         lib.tpc_kernel_name.argtypes = [ctypes.c_int32]
         lib.tpc_status_string.restype = ctypes.c_char_p
         lib.tpc_status_string.argtypes = [ctypes.c_int]
+        lib.tpc_collisions_workspace_size.restype = ctypes.c_size_t
+        lib.tpc_collisions_workspace_size.argtypes = [ctypes.POINTER(tpc_collision_params_t)]
+        lib.tpc_assign_collisions.restype = ctypes.c_int
+        lib.tpc_assign_collisions.argtypes = [ctypes.POINTER(tpc_tracks_t), _vp, ctypes.c_int32,
+                                              ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_collision_params_t),
+                                              ctypes.POINTER(tpc_collisions_t), _vp, ctypes.c_size_t, _vp]
         lib.tpc_inspect.restype = ctypes.c_int
         lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
                                     ctypes.POINTER(tpc_params_t), _vp, ctypes.c_int,
@@ -168,6 +185,32 @@ def tpc_status_string(status: int) -> str:
     return load_library().tpc_status_string(status).decode()
 
 
+def tpc_collisions_workspace_size(params: tpc_collision_params_t) -> int:
+    return int(load_library().tpc_collisions_workspace_size(ctypes.byref(params)))
+
+
+def tpc_assign_collisions(tracks: tpc_tracks_t, unit_side: int, n_units: int, field: tpc_field_t,
+                          params: tpc_collision_params_t, out: tpc_collisions_t, workspace: int,
+                          workspace_bytes: int, stream: int) -> int:
+    return int(load_library().tpc_assign_collisions(ctypes.byref(tracks), unit_side, n_units, ctypes.byref(field),
+                                                    ctypes.byref(params), ctypes.byref(out), workspace,
+                                                    workspace_bytes, stream))
+
+
+def make_collision_params(v_drift=2.58, bin_width=1.0, z_range=4096.0, c_max=None, n_min=10, reach=2,
+                          outer_radius=None) -> tpc_collision_params_t:
+    """Defaults: 1 cm bins over +-4096 cm, 10 forming tracks per candidate,
+    reach 2 bins; c_max = 2 / outer_radius when that is given, else c_max
+    (None: every track forms candidates)."""
+    cp = tpc_collision_params_t()
+    cp.v_drift, cp.bin_width, cp.z_range = v_drift, bin_width, z_range
+    if c_max is None:
+        c_max = 2.0 / outer_radius if outer_radius else float("inf")
+    cp.c_max = c_max
+    cp.n_min, cp.reach = int(n_min), int(reach)
+    return cp
+
+
 def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, workspace: int,
                 what: int) -> tpc_view_t:
     v = tpc_view_t()
@@ -183,7 +226,7 @@ def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, wor
 def __getattr__(name):
     # the torch-side helpers load on first use, so that importing the package
     # (e.g. for its parameter values) does not import torch
-    if name in ("Tracker", "track"):
+    if name in ("Tracker", "track", "CollisionAssigner"):
         from . import runtime
         return getattr(runtime, name)
     raise AttributeError(name)

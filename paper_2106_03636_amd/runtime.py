@@ -244,3 +244,72 @@ class GraphRunner:
 
     def result(self):
         return self.tracker.result()
+
+
+class CollisionAssigner:
+    """Workspace and outputs of tpc_assign_collisions for the tracks of a
+    Tracker (same device, same stream order)."""
+
+    def __init__(self, tracker: Tracker, params=None, cap=4096):
+        from . import make_collision_params, tpc_collisions_workspace_size
+        self.params = params if params is not None else make_collision_params()
+        self.tracker = tracker
+        self.device = tracker.device
+        ws = tpc_collisions_workspace_size(self.params)
+        if ws == 0:
+            raise ValueError("invalid collision parameters")
+        self.ws_bytes = ws
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.cap = int(cap)
+        d, ct, c = self.device, max(1, tracker.cap_tracks), max(1, self.cap)
+        self.o_zdca = torch.empty(ct, dtype=torch.float64, device=d)
+        self.o_collision = torch.empty(ct, dtype=torch.int32, device=d)
+        self.o_side = torch.empty(c, dtype=torch.int32, device=d)
+        self.o_bin = torch.empty(c, dtype=torch.int32, device=d)
+        self.o_count = torch.empty(c, dtype=torch.int32, device=d)
+        self.o_n_form = torch.empty(c, dtype=torch.int32, device=d)
+        self.o_z = torch.empty(c, dtype=torch.float64, device=d)
+        self.o_t0 = torch.empty(c, dtype=torch.float64, device=d)
+        self.o_n = torch.zeros(1, dtype=torch.int64, device=d)
+        self.o_status = torch.zeros(1, dtype=torch.int32, device=d)
+        self._side = None
+
+    def out_struct(self):
+        from . import tpc_collisions_t
+        o = tpc_collisions_t()
+        o.cap = self.cap
+        o.zdca, o.collision = _ptr(self.o_zdca), _ptr(self.o_collision)
+        o.side, o.bin, o.count, o.n_form = _ptr(self.o_side), _ptr(self.o_bin), _ptr(self.o_count), _ptr(self.o_n_form)
+        o.z, o.t0 = _ptr(self.o_z), _ptr(self.o_t0)
+        o.n_collisions, o.status = _ptr(self.o_n), _ptr(self.o_status)
+        return o
+
+    def launch(self, unit_side, bz, stream=None):
+        """Enqueue the assignment of the tracker's last tracks; unit_side: +1 / -1
+        per unit (host sequence or device int32 tensor)."""
+        from . import tpc_assign_collisions
+        if not torch.is_tensor(unit_side):
+            unit_side = torch.as_tensor(np.ascontiguousarray(unit_side, np.int32)).to(self.device)
+        self._side = unit_side
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        f = tpc_field_t()
+        f.bz_tesla = float(bz)
+        st = tpc_assign_collisions(self.tracker.tracks_struct(), _ptr(unit_side), int(unit_side.numel()), f,
+                                   self.params, self.out_struct(), self.workspace.data_ptr(), self.ws_bytes,
+                                   s.cuda_stream)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_assign_collisions: %s" % tpc_status_string(st))
+        return st
+
+    def result(self, sync=True):
+        if sync:
+            torch.cuda.synchronize(self.device)
+        st = int(self.o_status.item())
+        n = int(self.o_n.item())
+        if st != TPC_OK:
+            raise TrackingError(st, "collision assignment failed on the device: %s (candidates %d)"
+                                % (tpc_status_string(st), n))
+        T = int(self.tracker.o_counts[0].item())
+        return dict(n_collisions=n, zdca=self.o_zdca[:T], collision=self.o_collision[:T], side=self.o_side[:n],
+                    bin=self.o_bin[:n], count=self.o_count[:n], n_form=self.o_n_form[:n], z=self.o_z[:n],
+                    t0=self.o_t0[:n])

@@ -34,6 +34,7 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"tpc_clusters_t": T.tpc_clusters_t, "tpc_geometry_t": T.tpc_geometry_t,
                "tpc_field_t": T.tpc_field_t, "tpc_params_t": T.tpc_params_t,
                "tpc_tracks_t": T.tpc_tracks_t, "tpc_view_t": T.tpc_view_t,
+               "tpc_collision_params_t": T.tpc_collision_params_t, "tpc_collisions_t": T.tpc_collisions_t,
                "tpc_server_config_t": S.tpc_server_config_t, "tpc_request_t": S.tpc_request_t,
                "tpc_result_t": S.tpc_result_t, "tpc_server_stats_t": S.tpc_server_stats_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tpc_track.h"', 'int main(void){']
@@ -104,6 +105,32 @@ def test_invalid_arguments_rejected_on_host():
     assert T.tpc_track_sectors(c, g, f, bad, o, 0x7000, 1 << 30, 0) == T.TPC_E_INVALID
     g.n_rows = 300
     assert T.tpc_track_sectors(c, g, f, p, o, 0x7000, 1 << 30, 0) == T.TPC_E_INVALID
+
+
+def test_collision_call_host_checks():
+    """Workspace sizes and the arguments tpc_assign_collisions rejects before
+    any device work."""
+    cp = T.make_collision_params()
+    ws = T.tpc_collisions_workspace_size(cp)
+    assert ws >= 2 * 8192 * 16  # two int32 and one int64 per bin, 8192 bins per side
+    assert T.tpc_collisions_workspace_size(T.make_collision_params(bin_width=2.0)) < ws
+    for bad in (dict(bin_width=0.0), dict(z_range=-1.0), dict(bin_width=0.01, z_range=4096.0),
+                dict(z_range=2.0e6, bin_width=100.0)):
+        assert T.tpc_collisions_workspace_size(T.make_collision_params(**bad)) == 0, bad
+    trk, out, f = T.tpc_tracks_t(), T.tpc_collisions_t(), T.tpc_field_t()
+    f.bz_tesla = 0.5
+    assert T.tpc_assign_collisions(trk, 0x1000, 36, f, cp, out, 0x8000, ws, 0) == T.TPC_E_INVALID
+    trk.params = trk.x_ref = trk.unit = trk.counts = trk.status = 0x2000
+    trk.cap_tracks = 100
+    out.cap = 16
+    out.zdca = out.collision = out.side = out.bin = out.count = out.n_form = out.z = out.t0 = 0x3000
+    out.n_collisions = out.status = 0x4000
+    assert T.tpc_assign_collisions(trk, 0x1000, 36, f, cp, out, 0x8001, ws, 0) == T.TPC_E_INVALID  # misaligned
+    assert T.tpc_assign_collisions(trk, 0x1000, 36, f, cp, out, 0x8000, ws - 1, 0) == T.TPC_E_NOMEM
+    assert T.tpc_assign_collisions(trk, 0x1000, 0, f, cp, out, 0x8000, ws, 0) == T.TPC_E_INVALID
+    for bad in (dict(v_drift=0.0), dict(n_min=0), dict(reach=65), dict(reach=-1)):
+        assert T.tpc_assign_collisions(trk, 0x1000, 36, f, T.make_collision_params(**bad), out, 0x8000,
+                                       1 << 20, 0) == T.TPC_E_INVALID, bad
 
 
 def test_status_strings():

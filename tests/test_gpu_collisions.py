@@ -1,0 +1,209 @@
+"""Collision assignment on the GPU (tpc_assign_collisions through the C ABI)
+against the oracle (orc_collisions) and against the hand-worked histogram.
+
+The oracle is handed the GPU's own FP32 track states (as FP64) and the same
+FP32-rounded parameters, so that both sides assign the same tracks.  Bars:
+  - z'_dca per track within 1e-9 cm: both compute it in FP64 from the same
+    state, by two different closed forms (the oracle through the circle's
+    centre, the kernel through atan2(-aC, 1 + bC)); their rounding differs by
+    about 1e-12 cm at |z'| <= 4096 cm;
+  - bins, candidates, per-track candidates and per-candidate counts exactly,
+    once no track lies within 1e-9 cm of a bin edge (the oracle's fragile
+    flag; checked, and none does on these frames);
+  - per-candidate mean z' within 2^-17 cm + 1e-9 cm: the kernel sums z' in
+    fixed point of 2^-16 cm (each term rounded by at most 2^-17), the oracle
+    in FP64; t0 within that over v_drift."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KAPPA_F32 = np.float32(0.00299792458)
+BAR_Z = 2.0 ** -17 + 1e-9
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    import paper_2106_03636_amd as T
+    T.load_library()
+    return T
+
+
+def _k(bz):
+    """The curvature constant of the tracker's fit, -KAPPA * bz in FP32."""
+    return float(np.float32(-KAPPA_F32 * np.float32(bz)))
+
+
+def _oracle(cp, params, x_ref, unit, unit_side, bz, eps=1e-9):
+    import oracle
+    f32 = lambda v: float(np.float32(v))
+    return oracle.collisions(np.asarray(params, np.float64), np.asarray(x_ref, np.float64), unit, unit_side,
+                             _k(bz), f32(cp.v_drift), f32(cp.bin_width), f32(cp.z_range), f32(cp.c_max),
+                             cp.n_min, cp.reach, eps)
+
+
+def _compare(g, o, edges_exact=False):
+    """edges_exact: the case puts tracks exactly on bin edges, where both
+    sides compute z' without rounding (straight tracks, tan(lambda) = 0)."""
+    if not edges_exact:
+        assert o["fragile"].sum() == 0, "a track within 1e-9 cm of a bin edge: the bins may differ legitimately"
+    assert np.abs(g["zdca"] - o["zdca"]).max(initial=0.0) <= 1e-9
+    assert g["n_collisions"] == o["n_collisions"]
+    for a, b in (("side", "side"), ("bin", "bin"), ("count", "count"), ("n_form", "n_form"),
+                 ("collision", "collision")):
+        assert np.array_equal(g[a], o[b]), a
+    assert np.abs(g["z"] - o["c_zdca"]).max(initial=0.0) <= BAR_Z
+    assert np.abs(g["t0"] - o["c_t0"]).max(initial=0.0) <= BAR_Z / float(np.float32(synth.V_DRIFT))
+
+
+def _host(res):
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+
+
+def _track_and_assign(T, ev, cp, cap=4096):
+    from paper_2106_03636_amd.runtime import Batch, CollisionAssigner, Tracker
+    b = Batch.from_event(ev)
+    tr = Tracker(max(1, b.n), b.n_units, b.n_rows)
+    tr.launch(b)
+    ca = CollisionAssigner(tr, cp, cap=cap)
+    side = np.where(np.asarray(ev.unit_sector) < 18, 1, -1).astype(np.int32)
+    ca.launch(side, ev.bz)
+    res = tr.result()
+    return tr, res, ca, side
+
+
+@pytest.mark.parametrize("name", ["physical_timeframe_50", "pbpb_timeframe_50"])
+def test_collisions_match_the_oracle_full_size(T, name):
+    """The 50-collision frames: the physical one (one vertex per collision,
+    helices end at the outer wall) and the throughput workload, at full size
+    in the launch configuration the benchmark times."""
+    if name == "physical_timeframe_50":
+        ev = synth.event_pbpb_timeframe(3001, physical=True)
+    else:
+        ev = synth.WORKLOADS[name]()
+    cp = T.make_collision_params(v_drift=synth.V_DRIFT, outer_radius=synth.R_EXIT)
+    _say("case collisions", name, ev.n, "clusters")
+    tr, res, ca, side = _track_and_assign(T, ev, cp)
+    g = _host(ca.result())
+    _say("tracks", res["n_tracks"], "candidates", g["n_collisions"])
+    o = _oracle(cp, res["params"].cpu().numpy(), res["x_ref"].cpu().numpy(), res["unit"].cpu().numpy(), side,
+                ev.bz)
+    _compare(g, o)
+    assert g["n_collisions"] >= 60 and (g["collision"] >= 0).mean() > 0.5
+
+
+class _Tracks:
+    """Track arrays filled by hand, in the layout a tracking call writes."""
+
+    def __init__(self, params, x_ref, unit, status=0, device="cuda"):
+        import torch
+        from paper_2106_03636_amd import tpc_tracks_t
+        from paper_2106_03636_amd.runtime import _ptr
+        self.device = torch.device(device)
+        n = len(x_ref)
+        self.cap_tracks = max(1, n)
+        self.o_params = torch.as_tensor(np.asarray(params, np.float32).reshape(-1, 5)).to(self.device)
+        if n == 0:
+            self.o_params = torch.zeros((1, 5), dtype=torch.float32, device=self.device)
+        self.o_x_ref = torch.as_tensor(np.asarray(x_ref, np.float32).reshape(-1)).to(self.device)
+        self.o_unit = torch.as_tensor(np.asarray(unit, np.int32).reshape(-1)).to(self.device)
+        self.o_counts = torch.tensor([n, 0, 0, 0, 0], dtype=torch.int64, device=self.device)
+        self.o_status = torch.tensor([status], dtype=torch.int32, device=self.device)
+        self._ptr = _ptr
+        self._t = tpc_tracks_t
+
+    def tracks_struct(self):
+        o = self._t()
+        o.cap_tracks = self.cap_tracks
+        o.params, o.counts, o.status = self._ptr(self.o_params), self._ptr(self.o_counts), self._ptr(self.o_status)
+        # no tracks: any valid device address will do, nothing is read
+        o.x_ref = self._ptr(self.o_x_ref) if self.o_x_ref.numel() else self._ptr(self.o_params)
+        o.unit = self._ptr(self.o_unit) if self.o_unit.numel() else self._ptr(self.o_counts)
+        return o
+
+
+def _hand_case(T, bz=0.5):
+    import test_collisions_oracle as H
+    zs, units = H.HAND_Z, H.HAND_U
+    n = len(zs)
+    params = np.zeros((n, 5), np.float32)
+    params[:, 1] = zs
+    # loopers: curvature -KAPPA bz q/pT = -1.5 / cm, beyond c_max = 0.5
+    params[list(H.HAND_LOOP), 4] = 1.5 / (float(KAPPA_F32) * bz)
+    cp = T.make_collision_params(v_drift=synth.V_DRIFT, bin_width=1.0, z_range=16.0, c_max=0.5, n_min=2, reach=2)
+    return params, np.ones(n, np.float32), np.asarray(units, np.int32), cp
+
+
+def test_hand_worked_histogram_on_the_gpu(T):
+    """The hand-worked case of the oracle's pins, through the C ABI: the same
+    candidates, assignments, counts and means, derived by hand."""
+    from paper_2106_03636_amd.runtime import CollisionAssigner
+    params, x_ref, unit, cp = _hand_case(T)
+    trk = _Tracks(params, x_ref, unit)
+    ca = CollisionAssigner(trk, cp, cap=16)
+    ca.launch([1, -1], 0.5)
+    g = _host(ca.result())
+    assert g["n_collisions"] == 4
+    assert g["side"].tolist() == [1, 1, 1, -1] and g["bin"].tolist() == [16, 21, 25, 16]
+    assert g["collision"].tolist() == [0, 0, 0, 0, 0, 1, 1, 2, 2, 2, 2, 0, -1, -1, -1, 1, 1, -1, -1, 3, 3]
+    assert g["count"].tolist() == [6, 4, 4, 2] and g["n_form"].tolist() == [5, 4, 4, 2]
+    z32 = params[:, 1].astype(np.float64)
+    want = [z32[[0, 1, 2, 3, 4]].mean(), z32[[5, 6, 15, 16]].mean(), z32[[7, 8, 9, 10]].mean(), z32[[19, 20]].mean()]
+    assert np.abs(g["z"] - want).max() <= BAR_Z
+    vd = float(np.float32(synth.V_DRIFT))
+    assert np.abs(g["t0"] - np.array(want) * np.array([-1, -1, -1, 1]) / vd).max() <= BAR_Z / vd
+    o = _oracle(cp, params, x_ref, unit, [1, -1], 0.5)
+    _compare(g, o, edges_exact=True)
+
+
+def test_edge_cases(T):
+    """No tracks; a failed tracking call (its status passes through); more
+    candidates than the capacity (reported, with the count); a unit without
+    a side; two calls in a row on one workspace, the second smaller."""
+    from paper_2106_03636_amd.runtime import CollisionAssigner, TrackingError
+    params, x_ref, unit, cp = _hand_case(T)
+    empty = _Tracks(np.zeros((0, 5)), [], [])
+    ca = CollisionAssigner(empty, cp, cap=16)
+    ca.launch([1, -1], 0.5)
+    g = _host(ca.result())
+    assert g["n_collisions"] == 0 and len(g["collision"]) == 0
+    failed = _Tracks(params, x_ref, unit, status=T.TPC_E_CAPACITY)
+    ca = CollisionAssigner(failed, cp, cap=16)
+    ca.launch([1, -1], 0.5)
+    with pytest.raises(TrackingError) as e:
+        ca.result()
+    assert e.value.status == T.TPC_E_CAPACITY
+    trk = _Tracks(params, x_ref, unit)
+    ca = CollisionAssigner(trk, cp, cap=3)
+    ca.launch([1, -1], 0.5)
+    with pytest.raises(TrackingError) as e:
+        ca.result()
+    assert e.value.status == T.TPC_E_CAPACITY and int(ca.o_n.item()) == 4
+    ca = CollisionAssigner(trk, cp, cap=16)
+    ca.launch([1, 0], 0.5)
+    with pytest.raises(TrackingError) as e:
+        ca.result()
+    assert e.value.status == T.TPC_E_INVALID
+    # the same workspace twice: the hand case, then its A side only
+    ca.launch([1, -1], 0.5)
+    first = _host(ca.result())
+    small = _Tracks(params[:19], x_ref[:19], unit[:19])
+    ca.tracker = small
+    ca.launch([1, -1], 0.5)
+    second = _host(ca.result())
+    assert first["n_collisions"] == 4 and second["n_collisions"] == 3
+    assert np.array_equal(second["collision"], first["collision"][:19])
+    assert np.array_equal(second["count"], first["count"][:3]) and np.array_equal(second["z"], first["z"][:3])
