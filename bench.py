@@ -11,7 +11,11 @@ Prints ONE JSON line (rank 0).  Besides the contract fields it carries:
   roofline      the dominant kernel: algorithmic bytes per launch / its mean
                 duration from HIP events recorded on the library's stream;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
-  plain_per_sector  the same work as one call per sector (the plain form).
+  plain_per_sector  the same work as one call per sector (the plain form);
+  collisions    the assignment of the frame's tracks to collisions, after
+                tracking and outside the timed step: the call's device time
+                (HIP graph replays) and its physics on the 50-collision frame
+                of the physical generator against MC truth.
 """
 from __future__ import annotations
 
@@ -46,6 +50,12 @@ FP32_PEAK_TFLOPS = 157.3
 # divisions), covariance transport F C F^T on the 15 stored entries 102,
 # measurement update with gain, state, covariance and chi2 119 (1 division)
 FIT_OPS_PER_UPDATE = 24 + 3 + 1 + 35 + 3 + 102 + 119 + 1
+# collision assignment, algorithmic bytes per track: z' kernel reads the state
+# (20), x_ref (4) and unit (4) and writes z' (8); the assignment kernel reads
+# z' (8), unit (4) and q/pT (4) and writes the candidate (4)
+COL_BYTES_PER_TRACK = 20 + 4 + 4 + 8 + 8 + 4 + 4 + 4
+COL_KERNEL_BYTES = {"k_col_clear": None, "k_col_zdca": 36, "k_col_flags": None, "k_col_number": None,
+                    "k_col_assign": 20, "k_col_finish": None}
 SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
                "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY")
 KERNEL_FAMILY = {
@@ -77,6 +87,13 @@ def make_workload(name, seed=None):
     ev = synth.WORKLOADS[name]() if seed is None else synth.WORKLOADS[name](seed)
     log("bench: generated %s: %d clusters in %d units (%.1f s)" % (name, ev.n, ev.n_units, time.time() - t))
     return ev
+
+
+def col_digest():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2106_03636_amd", "csrc", "tpc_collisions.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def src_digest():
@@ -190,6 +207,24 @@ def summarize_profiles(prof_dir, workload):
                           avg_us=avg_us)
         if q:
             traffic[k].update(valu_insts=valu, valu_busy=busy / 100.0)
+    col = run.get("collisions")
+    if col:
+        nt = col["tracks"]
+        lines += ["", "collision assignment (tpc_assign_collisions) over the %d tracks of the frame; one of the "
+                  "calls runs on the physical frame's tracks instead" % nt,
+                  "%-18s %6s %10s %10s %10s %8s %8s %8s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB",
+                                                             "B/track", "GB/s", "alg_B/t")]
+        for k, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["totaldurationns"])):
+            if k not in COL_KERNEL_BYTES:
+                continue
+            avg_us = float(r["averagens"]) / 1e3
+            fb = fetch.get(k, 0.0) * 1024 / f_fac
+            wb = write.get(k, 0.0) * 1024 / w_fac
+            lines.append("%-18s %6s %10.1f %10.2f %10.2f %8.1f %8.0f %8s" % (
+                k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / nt, (fb + wb) / 1e3 / avg_us,
+                COL_KERNEL_BYTES[k] or "-"))
+            traffic[k] = dict(src_digest=col_digest(), bytes_per_launch=fb + wb, fetch_bytes=fb, write_bytes=wb,
+                              avg_us=avg_us)
     txt = os.path.join(out_dir, "%s_kernels.txt" % workload)
     open(txt, "w").write("\n".join(lines) + "\n")
     tj = os.path.join(out_dir, "traffic.json")
@@ -508,6 +543,71 @@ def event_bench(dev, reps, params, name):
     return out
 
 
+def collision_bench(dev, tr, ev, reps, workload):
+    """Collision assignment (tpc_assign_collisions) after tracking: the time
+    of one call over the tracks of `ev` (the tracker's last result), and its
+    physics on the physical 50-collision frame (one vertex per collision,
+    helices end at the outer wall) against MC truth."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2106_03636_amd as T
+    from paper_2106_03636_amd import mctruth
+    from paper_2106_03636_amd.runtime import Batch, CollisionAssigner
+    cp = T.make_collision_params(v_drift=synth.V_DRIFT, outer_radius=synth.R_EXIT)
+    side = torch.as_tensor(np.where(np.asarray(ev.unit_sector) < 18, 1, -1).astype(np.int32)).to(dev)
+    ca = CollisionAssigner(tr, cp)
+    for _ in range(3):
+        ca.launch(side, ev.bz)
+    g = {k: v.clone() if torch.is_tensor(v) else v for k, v in ca.result().items()}
+    n_tracks = int(tr.o_counts[0].item())
+    # the call captured in a HIP graph and replayed back to back, so that the
+    # host's launch overhead does not show in the device time
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ca.launch(side, ev.bz)
+    torch.cuda.synchronize(dev)
+    graph.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    gr = ca.result()
+    if int(gr["n_collisions"]) != int(g["n_collisions"]) or not torch.equal(gr["collision"], g["collision"]):
+        raise RuntimeError("graph replay and eager call of the collision assignment disagree")
+    del graph
+    achieved = n_tracks * COL_BYTES_PER_TRACK / (ms * 1e-3) / 1e9
+    out = dict(workload=workload, tracks=n_tracks, candidates=int(g["n_collisions"]), ms_per_call=ms,
+               tracks_per_s=n_tracks / (ms * 1e-3), launches=5,
+               roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=achieved / HBM_PEAK_GBS, algorithmic_bytes_per_track=COL_BYTES_PER_TRACK,
+                             traffic=None))
+    t = time.time()
+    evp = synth.event_pbpb_timeframe(3001, physical=True)
+    log("bench: generated the physical frame: %d clusters (%.1f s)" % (evp.n, time.time() - t))
+    bp = Batch.from_event(evp, dev)
+    tr.launch(bp)
+    ca.launch(side, evp.bz)
+    res = tr.result()
+    gp = ca.result()
+    p = res["params"].cpu().numpy()
+    kcurv = float(np.float32(-np.float32(synth.KAPPA) * np.float32(evp.bz)))
+    trk_side = side.cpu().numpy()[res["unit"].cpu().numpy()]
+    out["physics"] = dict(workload="pbpb_timeframe_50 physical (seed 3001)", clusters=int(evp.n),
+                          tracks=int(res["n_tracks"]),
+                          **mctruth.collision_report(evp.label, evp.tracks.t0, evp.tracks.vz,
+                                                     res["n_hits"].cpu().numpy(), res["hits"].cpu().numpy(),
+                                                     trk_side, np.abs(kcurv * p[:, 4]) < cp.c_max,
+                                                     gp["collision"].cpu().numpy(), gp["side"].cpu().numpy(),
+                                                     gp["t0"].cpu().numpy(), synth.V_DRIFT))
+    log("bench: collisions " + json.dumps(out))
+    return out
+
+
 def cpu_baseline(ev, n_units_sample, values, single_core_units=2):
     """The CPU oracle, as it stands, on the first n_units_sample units with all
     its threads, and on single_core_units units with one thread (the paper
@@ -560,6 +660,7 @@ def main():
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 runs of this script and exit")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
+    ap.add_argument("--no-collisions", action="store_true", help="skip the collision-assignment measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -727,6 +828,7 @@ def main():
     for e in memory["vs_n"]:
         e["bytes_per_cluster"] = e["workspace_bytes"] / e["clusters"]
     log("bench: per-kernel ms " + json.dumps(per_kernel))
+    collisions = None if args.no_collisions else collision_bench(dev, tr, ev, max(50, args.steps), args.workload)
 
     out = dict(
         metric=METRIC, value=value, unit="clusters/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -745,6 +847,8 @@ def main():
         kernel_ms=per_kernel, profiled_step_ms=profiled_step_ms,
         tracks=res["n_tracks"], tracklets=res["n_tracklets"], physics=physics, memory=memory,
     )
+    if collisions is not None:
+        out["collisions"] = collisions
 
     # the plain form: one call per sector unit, same stream, same work
     if not args.no_plain:

@@ -67,3 +67,77 @@ def report(label, unit_offsets, pt, track_first_hit, track_n_hits, track_hits, m
                              efficiency=float(found[sel].mean())))
     out["vs_pt"] = bins
     return out
+
+
+def majority_particle(label, track_n_hits, track_hits):
+    """Per track, the particle that generated most of its clusters (ties: the
+    lower index; -1 when only noise)."""
+    label = np.asarray(label, np.int64)
+    nh = np.asarray(track_n_hits, np.int64)
+    nt = len(nh)
+    out = np.full(nt, -1, np.int64)
+    if nt == 0:
+        return out
+    tid = np.repeat(np.arange(nt, dtype=np.int64), nh)
+    lab = label[np.asarray(track_hits, np.int64)[:int(nh.sum())]]
+    span = int(lab.max()) + 2
+    u, cnt = np.unique(tid * span + (lab + 1), return_counts=True)
+    ut, ul = u // span, u % span - 1
+    order = np.lexsort((-cnt, ut))
+    first = np.ones(len(order), bool)
+    first[1:] = ut[order][1:] != ut[order][:-1]
+    out[ut[order][first]] = ul[order][first]
+    return out
+
+
+def collision_report(label, particle_t0, particle_vz, track_n_hits, track_hits, track_side, track_forming,
+                     collision, c_side, c_t0, v_drift, min_tracks=100):
+    """Collision assignment against MC truth.  A track's true collision is the
+    t0 of its majority particle.  A candidate's collision is the majority over
+    its tracks; forming tracks (the ones that define candidates) are
+    *assigned* when they join a candidate and *pure* when that candidate's
+    collision is theirs.  A (collision, side) with at least min_tracks forming
+    tracks, and no other collision within 3 cm of its z' on that side, is
+    *found* when some candidate on that side has it as its collision."""
+    truth = majority_particle(label, track_n_hits, track_hits)
+    ok = truth >= 0
+    t0t = np.where(ok, np.asarray(particle_t0)[np.maximum(truth, 0)], np.nan)
+    col = np.asarray(collision)
+    form = np.asarray(track_forming, bool)
+    side = np.asarray(track_side)
+    nc = len(c_side)
+    cmaj = np.full(nc, np.nan)
+    sel = (col >= 0) & ok
+    if sel.any():  # per candidate, the most frequent true t0 (ties: the earlier one)
+        t0u, t0i = np.unique(t0t[sel], return_inverse=True)
+        u, cnt = np.unique(col[sel].astype(np.int64) * len(t0u) + t0i, return_counts=True)
+        uc = u // len(t0u)
+        order = np.lexsort((-cnt, uc))
+        first = np.ones(len(order), bool)
+        first[1:] = uc[order][1:] != uc[order][:-1]
+        cmaj[uc[order][first]] = t0u[u[order][first] % len(t0u)]
+    assigned = (col >= 0) & ok & form
+    pure = assigned & (cmaj[np.maximum(col, 0)] == t0t)
+    resid = np.abs(np.asarray(c_t0) - cmaj)[~np.isnan(cmaj)]
+    pt0, pvz = np.asarray(particle_t0), np.asarray(particle_vz)
+    found = findable = 0
+    for s in (1, -1):
+        zs = {}
+        for t0 in np.unique(pt0):
+            zs[t0] = np.median(pvz[pt0 == t0]) - s * v_drift * t0
+        zall = np.array(list(zs.values()))
+        have = set(cmaj[(np.asarray(c_side) == s) & ~np.isnan(cmaj)].tolist())
+        for t0, z in zs.items():
+            if ((t0t == t0) & (side == s) & form).sum() < min_tracks or (np.abs(zall - z) < 3.0).sum() > 1:
+                continue
+            findable += 1
+            found += t0 in have
+    return dict(candidates=int(nc), candidates_a=int((np.asarray(c_side) == 1).sum()),
+                candidates_c=int((np.asarray(c_side) == -1).sum()),
+                collisions_found=int(found), collisions_findable=int(findable),
+                forming_assigned=float(assigned.sum() / max(1, (ok & form).sum())),
+                forming_purity=float(pure.sum() / max(1, assigned.sum())),
+                all_assigned=float(((col >= 0) & ok).sum() / max(1, ok.sum())),
+                t0_resid_us_p50=float(np.percentile(resid, 50)) if len(resid) else None,
+                t0_resid_us_p90=float(np.percentile(resid, 90)) if len(resid) else None,
+                min_tracks=min_tracks)

@@ -169,6 +169,45 @@ def test_hand_worked_histogram_on_the_gpu(T):
     _compare(g, o, edges_exact=True)
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_histograms_match_the_oracle(T, seed):
+    """Straight-on tracks (z'_dca = their z) drawn in tight groups around the
+    places where the peak finder's bookkeeping changes: the join of the two
+    sides (bins 8191 / 8192 of the concatenated histogram), the edge of its
+    first LDS chunk (15872), the ends of the range; plus a uniform background
+    and loopers; random group sizes around n_min and random reach."""
+    from paper_2106_03636_amd.runtime import CollisionAssigner
+    rng = np.random.default_rng(seed)
+    reach = int(rng.integers(1, 5))
+    cp = T.make_collision_params(v_drift=synth.V_DRIFT, c_max=0.5, n_min=int(rng.integers(3, 12)), reach=reach)
+    zs, units = [], []
+    centres = [(1, 4095.5), (-1, -4095.5), (-1, 15872 - 8192 - 4096 + 0.5), (1, -4095.5), (-1, 4095.0)]
+    centres += [(int(rng.choice([1, -1])), float(rng.uniform(-4090, 4090))) for _ in range(30)]
+    for side, c in centres:
+        for _ in range(8):
+            m = int(rng.integers(0, 25))
+            zs += list(c + rng.integers(-6, 7) + rng.normal(0, 0.3, m))
+            units += [0 if side > 0 else 1] * m
+    nbg = 3000
+    zs += list(rng.uniform(-4200, 4200, nbg))
+    units += list(rng.integers(0, 2, nbg))
+    zs = np.asarray(zs, np.float32)
+    n = len(zs)
+    params = np.zeros((n, 5), np.float32)
+    params[:, 1] = zs
+    loop = rng.random(n) < 0.2
+    params[loop, 4] = 1.5 / (float(KAPPA_F32) * 0.5)  # curvature 1.5 / cm: no forming track
+    x_ref = np.ones(n, np.float32)
+    trk = _Tracks(params, x_ref, np.asarray(units, np.int32))
+    ca = CollisionAssigner(trk, cp, cap=4096)
+    ca.launch([1, -1], 0.5)
+    g = _host(ca.result())
+    o = _oracle(cp, params, x_ref, np.asarray(units, np.int32), [1, -1], 0.5)
+    _say("random case", seed, "tracks", n, "candidates", g["n_collisions"], "reach", reach, "n_min", cp.n_min)
+    _compare(g, o, edges_exact=True)
+    assert g["n_collisions"] > 20
+
+
 def test_edge_cases(T):
     """No tracks; a failed tracking call (its status passes through); more
     candidates than the capacity (reported, with the count); a unit without
