@@ -582,7 +582,7 @@ def collision_bench(dev, tr, ev, reps, workload):
     del graph
     achieved = n_tracks * COL_BYTES_PER_TRACK / (ms * 1e-3) / 1e9
     out = dict(workload=workload, tracks=n_tracks, candidates=int(g["n_collisions"]), ms_per_call=ms,
-               tracks_per_s=n_tracks / (ms * 1e-3), launches=5,
+               tracks_per_s=n_tracks / (ms * 1e-3), launches=6,
                roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=achieved / HBM_PEAK_GBS, algorithmic_bytes_per_track=COL_BYTES_PER_TRACK,
                              traffic=None))
