@@ -101,6 +101,9 @@ def _load():
         lib.orc_collisions.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_double] + [vp] * 10
+        lib.orc_clusterize.restype = ctypes.c_int64
+        lib.orc_clusterize.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double] + [vp] * 12
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -258,6 +261,27 @@ def collisions(params, x_ref, unit, unit_side, k, v_drift, width=1.0, zmax=4096.
                             cb.ctypes.data, cc.ctypes.data, cf.ctypes.data, cz.ctypes.data, ct.ctypes.data)
     return dict(zdca=zd, t0=t0, collision=col, fragile=frag, n_collisions=int(nc), side=cs[:nc], bin=cb[:nc],
                 count=cc[:nc], n_form=cf[:nc], c_zdca=cz[:nc], c_t0=ct[:nc])
+
+
+def clusterize(half, pad_offsets, time, q, n_units, q_min, pw, tb, zoff):
+    """Clusters of zero-suppressed digits (see orc_clusterize in tpc_oracle.c).
+    half: half the pad count per row; pad_offsets: CSR over (unit, row, pad)."""
+    lib = _load()
+    half = np.ascontiguousarray(half, np.int32)
+    off = np.ascontiguousarray(pad_offsets, np.int64)
+    time = np.ascontiguousarray(time, np.uint16)
+    q = np.ascontiguousarray(q, np.uint16)
+    cap = max(1, len(time))
+    ints = {k: np.zeros(cap, np.int32) for k in ("unit", "row", "pad", "time", "qmax", "q", "sp", "st")}
+    flts = {k: np.zeros(cap, np.float32) for k in ("padf", "timef", "y", "z")}
+    n = lib.orc_clusterize(int(n_units), len(half), half.ctypes.data, off.ctypes.data, time.ctypes.data,
+                           q.ctypes.data, int(q_min), float(pw), float(tb), float(zoff),
+                           *[ints[k].ctypes.data for k in ("unit", "row", "pad", "time", "qmax", "q", "sp", "st")],
+                           *[flts[k].ctypes.data for k in ("padf", "timef", "y", "z")])
+    out = {k: v[:n] for k, v in ints.items()}
+    out.update({k: v[:n] for k, v in flts.items()})
+    out["n"] = int(n)
+    return out
 
 
 def num_threads() -> int:

@@ -1190,6 +1190,96 @@ int64_t orc_collisions(int64_t n_tracks, const double *params, const double *x_r
   return nc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Clusterizer: raw ADC digits to clusters (the producer of the tracker's      */
+/* input).  The paper states that a clusterizing algorithm turns the raw ADC   */
+/* values into hits (§2.1) and that it runs much faster on GPUs than on CPUs   */
+/* (§3.2); it does not describe it.  Reading used here: digits are grouped by  */
+/* (unit, row, pad), times increasing inside a pad.  A digit of charge v at    */
+/* (pad p, time t) is a peak when v >= q_min and every digit among its eight   */
+/* neighbours (pads p-1..p+1 of the same row, times t-1..t+1) is smaller, or   */
+/* equal and later in (pad, time) order -- so a plateau of equal charges has   */
+/* one peak, its first digit.  The cluster of a peak sums the digits of the    */
+/* 3x3 window around it: Q = sum v, Sp = sum v (p' - p), St = sum v (t' - t);  */
+/* its centre is (p + Sp/Q, t + St/Q) in FP64; y = (pad + 0.5 - half) pw and   */
+/* z' = (time + 0.5) tb - zoff, rounded once to FP32.  Clusters come in the    */
+/* order of their peaks.                                                       */
+
+/* digits of pad j with time in [t0, t1]: the index range [*a, *b) */
+static void pad_range(const int64_t *pad_offsets, const uint16_t *time, int64_t j, int32_t t0, int32_t t1,
+                      int64_t *a, int64_t *b) {
+  int64_t lo = pad_offsets[j], hi = pad_offsets[j + 1];
+  while (lo < hi && time[lo] < t0) ++lo;
+  int64_t e = lo;
+  while (e < hi && time[e] <= t1) ++e;
+  *a = lo;
+  *b = e;
+}
+
+/* Clusters of all digits.  half[n_rows]: half the pad count of each row
+ * (rows have 2 half[r] pads; pads_total = sum of them); pad_offsets has
+ * n_units * pads_total + 1 entries.  Outputs (capacity: the number of
+ * digits): unit, row, peak pad and time, qmax, Q, Sp, St, and the float
+ * centre (pad, time) and position (y, z').  Returns the cluster count. */
+int64_t orc_clusterize(int32_t n_units, int32_t n_rows, const int32_t *half, const int64_t *pad_offsets,
+                       const uint16_t *time, const uint16_t *q, int32_t q_min, double pw, double tb, double zoff,
+                       int32_t *c_unit, int32_t *c_row, int32_t *c_pad, int32_t *c_time, int32_t *c_qmax,
+                       int32_t *c_q, int32_t *c_sp, int32_t *c_st, float *c_padf, float *c_timef, float *c_y,
+                       float *c_z) {
+  int64_t pads_total = 0;
+  for (int r = 0; r < n_rows; ++r) pads_total += 2 * (int64_t)half[r];
+  int64_t nc = 0;
+  for (int32_t u = 0; u < n_units; ++u) {
+    int64_t base = (int64_t)u * pads_total;
+    for (int32_t r = 0; r < n_rows; ++r) {
+      const int32_t np = 2 * half[r];
+      for (int32_t p = 0; p < np; ++p) {
+        const int64_t j = base + p;
+        for (int64_t d = pad_offsets[j]; d < pad_offsets[j + 1]; ++d) {
+          const int32_t t = time[d], v = q[d];
+          if (v < q_min) continue;
+          int peak = 1;
+          int32_t Q = 0, Sp = 0, St = 0;
+          for (int dp = -1; dp <= 1 && peak; ++dp) {
+            if (p + dp < 0 || p + dp >= np) continue; /* neighbours stay in the row */
+            int64_t a, b;
+            pad_range(pad_offsets, time, j + dp, t - 1, t + 1, &a, &b);
+            for (int64_t e = a; e < b; ++e) {
+              const int32_t dt = (int32_t)time[e] - t, w = q[e];
+              const int later = dp > 0 || (dp == 0 && dt > 0);
+              if (!(dp == 0 && dt == 0) && !(w < v || (w == v && later))) {
+                peak = 0;
+                break;
+              }
+              Q += w;
+              Sp += w * dp;
+              St += w * dt;
+            }
+          }
+          if (!peak) continue;
+          const double padf = (double)p + (double)Sp / (double)Q;
+          const double timef = (double)t + (double)St / (double)Q;
+          c_unit[nc] = u;
+          c_row[nc] = r;
+          c_pad[nc] = p;
+          c_time[nc] = t;
+          c_qmax[nc] = v;
+          c_q[nc] = Q;
+          c_sp[nc] = Sp;
+          c_st[nc] = St;
+          c_padf[nc] = (float)padf;
+          c_timef[nc] = (float)timef;
+          c_y[nc] = (float)((padf + 0.5 - (double)half[r]) * pw);
+          c_z[nc] = (float)((timef + 0.5) * tb - zoff);
+          ++nc;
+        }
+      }
+      base += np;
+    }
+  }
+  return nc;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

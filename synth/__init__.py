@@ -47,11 +47,12 @@ def sector_alpha(sector: int) -> float:
 
 
 def build(force: bool = False) -> str:
-    """Compile the crossing routine (gcc, OpenMP) next to this file."""
-    src = os.path.join(HERE, "crossings.c")
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+    """Compile the crossing and digit routines (gcc, OpenMP) next to this file."""
+    srcs = [os.path.join(HERE, "crossings.c"), os.path.join(HERE, "digits.c")]
+    newest = max(os.path.getmtime(f) for f in srcs)
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp] + srcs + ["-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -71,6 +72,10 @@ def _load():
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        vp = ctypes.c_void_p
+        lib.synth_digits.restype = ctypes.c_int64
+        lib.synth_digits.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32] + [ctypes.c_double] * 6 + [
+            ctypes.c_int32, ctypes.c_uint64] + [vp] * 9
         _lib = lib
     return _lib
 
@@ -480,6 +485,73 @@ def serving_pool(seed: int = 5001, n_frames: int = 32, pbpb_fraction: float = 0.
             coll = rng.choice(lib_pp, size=pp_collisions, replace=pp_collisions > lib_pp)
             frames.append(compose_timeframe(rng, libP, coll, pp_collisions / pp_rate_khz * 1e3, bz, "pp_frame"))
     return frames
+
+
+# --- raw ADC digits (clusterizer input) ---------------------------------------
+
+PAD_W = 0.6                     # pad width, cm
+TIME_BIN = 0.2 * V_DRIFT        # one 200 ns time bin, cm of drift
+Z_OFF = 4096.0                  # time bin t is centred at z' = (t + 0.5) TIME_BIN - Z_OFF
+SIG_PAD, SIG_TIME = 0.7, 0.7    # response widths, in pads and time bins
+NOISE_ADC, THR_ADC = 1.0, 3     # noise (ADC rms) and zero-suppression threshold
+PAD_HALF = np.ceil(ROW_X * TAN_HALF / PAD_W).astype(np.int32)  # row r has 2 * PAD_HALF[r] pads
+PADS_TOTAL = int(2 * PAD_HALF.sum())
+PAD_ROW_BASE = np.concatenate([[0], np.cumsum(2 * PAD_HALF)]).astype(np.int64)  # first pad of each row
+
+
+@dataclass
+class Digits:
+    """Zero-suppressed ADC digits grouped by (unit, row, pad), times increasing
+    inside a pad: digit k of pad (u, r, p) is at pad_offsets[u * PADS_TOTAL +
+    PAD_ROW_BASE[r] + p] + k.  `clusters` is the event whose clusters made
+    them (its labels are the truth)."""
+    time: np.ndarray
+    q: np.ndarray
+    pad_offsets: np.ndarray
+    n_units: int
+    clusters: Event
+    name: str = ""
+
+    @property
+    def n(self):
+        return int(self.pad_offsets[-1])
+
+
+def event_digits(ev: Event, seed: int, charge_mean: float = 60.0, charge_min: float = 40.0,
+                 noise: float = NOISE_ADC) -> Digits:
+    """Digits of every cluster of `ev` (signal and noise clusters alike): a
+    charge of charge_min + Exp(charge_mean) ADC spread over +-2 pads and time
+    bins by Gaussian responses (SIG_PAD, SIG_TIME), overlaps summed, noise of
+    NOISE_ADC rms, rounded, kept from THR_ADC, clipped to 1023."""
+    lib = _load()
+    rng = np.random.default_rng(seed)
+    n_units, n_rows = ev.n_units, N_ROWS
+    unit = np.repeat(np.arange(n_units, dtype=np.int64), np.diff(ev.unit_offsets))
+    key = unit * n_rows + ev.row.astype(np.int64)
+    order = np.argsort(key, kind="stable").astype(np.int64)
+    ur = np.zeros(n_units * n_rows + 1, np.int64)
+    ur[1:] = np.cumsum(np.bincount(key, minlength=n_units * n_rows))
+    q = charge_min + rng.exponential(charge_mean, ev.n)
+    max_pads = int(2 * PAD_HALF.max())
+    counts = np.zeros(n_units * n_rows * max_pads, np.int64)
+    y = np.ascontiguousarray(ev.y, np.float32)
+    z = np.ascontiguousarray(ev.z, np.float32)
+    args = (n_units, n_rows, _ptr(PAD_HALF), max_pads, PAD_W, TIME_BIN, Z_OFF, SIG_PAD, SIG_TIME, float(noise),
+            THR_ADC, int(seed) & ((1 << 64) - 1), _ptr(ur), _ptr(order), _ptr(y), _ptr(z), _ptr(q), _ptr(counts))
+    lib.synth_digits(*args, None, None, None)
+    # compact CSR over (unit, row, pad) from the padded [unit * row][max_pads] counts
+    cm = counts.reshape(n_units, n_rows, max_pads)
+    valid = np.arange(max_pads)[None, :] < (2 * PAD_HALF)[:, None]
+    per_pad = cm[:, valid]  # [n_units, PADS_TOTAL] in (row, pad) order
+    off = np.zeros(n_units * PADS_TOTAL + 1, np.int64)
+    off[1:] = np.cumsum(per_pad.reshape(-1))
+    starts = np.zeros_like(cm)
+    starts[:, valid] = off[:-1].reshape(n_units, PADS_TOTAL)
+    starts = np.ascontiguousarray(starts.reshape(-1))
+    time = np.empty(int(off[-1]), np.uint16)
+    qq = np.empty(int(off[-1]), np.uint16)
+    lib.synth_digits(*args, _ptr(starts), _ptr(time), _ptr(qq))
+    return Digits(time, qq, off, n_units, ev, ev.name + "_digits")
 
 
 WORKLOADS = {

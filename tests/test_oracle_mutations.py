@@ -12,6 +12,7 @@ import subprocess
 import pytest
 
 import oracle
+import test_clusterizer_oracle as clu
 import test_collisions_oracle as col
 import test_oracle_pins as pins
 from conftest import cached_event, cached_oracle
@@ -104,6 +105,20 @@ MUTATIONS = [
      "      if (b + d < nb && cs[b + d] >= 0) { collision[t] = (int32_t)cs[b + d]; break; }\n"
      "      if (b - d >= 0 && cs[b - d] >= 0) { collision[t] = (int32_t)cs[b - d]; break; }",
      [col.test_histogram_peaks_and_assignment_hand_worked]),
+    ("clusterizer_tie_to_the_later_digit",
+     "const int later = dp > 0 || (dp == 0 && dt > 0);", "const int later = dp < 0 || (dp == 0 && dt < 0);",
+     [clu.test_plateau_and_diagonal_ties_give_one_peak]),
+    ("clusterizer_neighbours_across_rows",
+     "if (p + dp < 0 || p + dp >= np) continue; /* neighbours stay in the row */",
+     "if (j + dp < (int64_t)u * pads_total || j + dp >= (int64_t)(u + 1) * pads_total) continue;",
+     [clu.test_neighbours_stay_in_their_row_pad_and_time_window]),
+    ("clusterizer_5x5_time_window",
+     "pad_range(pad_offsets, time, j + dp, t - 1, t + 1, &a, &b);",
+     "pad_range(pad_offsets, time, j + dp, t - 2, t + 2, &a, &b);",
+     [clu.test_neighbours_stay_in_their_row_pad_and_time_window, lambda: clu.test_matches_a_dense_map_implementation(1)]),
+    ("clusterizer_pad_moment_sign",
+     "Sp += w * dp;", "Sp -= w * dp;",
+     [clu.test_plateau_and_diagonal_ties_give_one_peak]),
 ]
 
 
