@@ -192,6 +192,81 @@ const char *tpc_kernel_name(int32_t i);
 const char *tpc_status_string(int status);
 
 /* ------------------------------------------------------------------------- */
+/* Clusterizer.  The producer of the clusters above: the paper states that a */
+/* clusterizing algorithm turns the TPC's raw ADC values into hits (§2.1)    */
+/* and that it runs much faster on GPUs than on CPUs (§3.2); it does not     */
+/* describe it.  What this call computes:                                    */
+/*   - input: zero-suppressed digits (time bin, ADC charge) grouped by       */
+/*     (unit, row, pad), times strictly increasing inside a pad;             */
+/*   - a digit of charge v at (pad p, time t) is a peak when v >= q_min and  */
+/*     every digit among its eight neighbours (pads p-1..p+1 of the same     */
+/*     row, times t-1..t+1) is smaller, or equal and later in (pad, time)    */
+/*     order (so a plateau of equal charges yields one peak, its first       */
+/*     digit);                                                               */
+/*   - the cluster of a peak sums the digits of the 3x3 window around it:    */
+/*     qtot = sum v, and the first moments in pad and time; its centre is    */
+/*     pad = p + sum v (p' - p) / qtot, time = t + sum v (t' - t) / qtot     */
+/*     (FP64), its position y = (pad + 0.5 - half[row]) pad_width and       */
+/*     z' = (time + 0.5) time_bin - z_offset (FP64, rounded once to FP32);   */
+/*   - clusters come in the order of their peaks: (unit, row, pad, time).    */
+/* y, z, row and unit_offsets of the output form the tpc_clusters_t that     */
+/* tpc_track_sectors takes.                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Pads: row r has 2 half[r] pads, pad p centred at y = (p + 0.5 - half[r]) *
+ * pad_width; time bin t centred at z' = (t + 0.5) * time_bin - z_offset. */
+typedef struct tpc_pad_geometry {
+  int32_t n_rows;              /* 1..255 */
+  int32_t pads_total;          /* sum over rows of 2 half[r] (pads per unit) */
+  const int32_t *half;         /* [n_rows] device, >= 1 */
+  float pad_width;             /* cm, > 0 */
+  float time_bin;              /* cm of drift per time bin, > 0 */
+  float z_offset;              /* cm */
+  int32_t reserved;
+} tpc_pad_geometry_t;
+
+/* Digits (device pointers).  Digit k of pad (u, r, p) is at
+ * pad_offsets[u * pads_total + (pads of rows < r) + p] + k. */
+typedef struct tpc_digits {
+  int64_t n;                   /* number of digits, 0 <= n < 2^31 */
+  int32_t n_units;             /* >= 1 */
+  int32_t reserved;
+  const int64_t *pad_offsets;  /* [n_units * pads_total + 1], non-decreasing, [0] = 0, last = n */
+  const uint16_t *time;        /* [n] time bin, strictly increasing inside a pad */
+  const uint16_t *q;           /* [n] ADC charge */
+} tpc_digits_t;
+
+typedef struct tpc_clusterizer_params {
+  int32_t q_min;               /* smallest peak charge, >= 1 */
+  int32_t reserved;
+} tpc_clusterizer_params_t;
+
+/* Outputs (device pointers, allocated by the caller). */
+typedef struct tpc_cluster_out {
+  int64_t cap;                 /* capacity of the per-cluster arrays */
+  float *y, *z;                /* [cap] position (cm) */
+  uint16_t *row;               /* [cap] */
+  int32_t *qtot;               /* [cap] charge of the 3x3 window */
+  uint16_t *qmax;              /* [cap] peak charge */
+  float *pad, *time;           /* [cap] centre in pads and time bins */
+  int64_t *unit_offsets;       /* [n_units + 1] first cluster of each unit */
+  int64_t *count;              /* [1] clusters found (also when it exceeds cap) */
+  int32_t *status;             /* [1] TPC_OK, TPC_E_INVALID (malformed offsets or times),
+                                  TPC_E_CAPACITY (count > cap); outputs valid only with TPC_OK */
+} tpc_cluster_out_t;
+
+/* Bytes of device workspace tpc_clusterize needs (host-only; 0 on bad shapes). */
+size_t tpc_clusterize_workspace_size(int32_t n_units, const tpc_pad_geometry_t *geometry);
+
+/* Clusters of all digits, enqueued on `stream`; the workspace (aligned to 256
+ * bytes) holds no state across calls.  Returns TPC_OK when the work was
+ * enqueued, TPC_E_INVALID / TPC_E_NOMEM on bad arguments or a small
+ * workspace, TPC_E_HIP on a launch failure. */
+int tpc_clusterize(const tpc_digits_t *digits, const tpc_pad_geometry_t *geometry,
+                   const tpc_clusterizer_params_t *params, tpc_cluster_out_t *out, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Collision assignment.  In continuous readout the collisions of a time     */
 /* frame overlap in the drift volume, and tracks are assigned to them only   */
 /* after tracking (paper §2, §2.3); the paper does not describe how.  What   */

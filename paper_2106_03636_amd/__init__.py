@@ -75,6 +75,26 @@ class tpc_collisions_t(ctypes.Structure):
                 ("status", _vp)]
 
 
+class tpc_pad_geometry_t(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("pads_total", ctypes.c_int32), ("half", _vp),
+                ("pad_width", ctypes.c_float), ("time_bin", ctypes.c_float), ("z_offset", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
+class tpc_digits_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_units", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pad_offsets", _vp), ("time", _vp), ("q", _vp)]
+
+
+class tpc_clusterizer_params_t(ctypes.Structure):
+    _fields_ = [("q_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class tpc_cluster_out_t(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64), ("y", _vp), ("z", _vp), ("row", _vp), ("qtot", _vp), ("qmax", _vp),
+                ("pad", _vp), ("time", _vp), ("unit_offsets", _vp), ("count", _vp), ("status", _vp)]
+
+
 class tpc_view_t(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("count", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -117,6 +137,12 @@ def load_library():
         lib.tpc_assign_collisions.argtypes = [ctypes.POINTER(tpc_tracks_t), _vp, ctypes.c_int32,
                                               ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_collision_params_t),
                                               ctypes.POINTER(tpc_collisions_t), _vp, ctypes.c_size_t, _vp]
+        lib.tpc_clusterize_workspace_size.restype = ctypes.c_size_t
+        lib.tpc_clusterize_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(tpc_pad_geometry_t)]
+        lib.tpc_clusterize.restype = ctypes.c_int
+        lib.tpc_clusterize.argtypes = [ctypes.POINTER(tpc_digits_t), ctypes.POINTER(tpc_pad_geometry_t),
+                                       ctypes.POINTER(tpc_clusterizer_params_t), ctypes.POINTER(tpc_cluster_out_t),
+                                       _vp, ctypes.c_size_t, _vp]
         lib.tpc_inspect.restype = ctypes.c_int
         lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
                                     ctypes.POINTER(tpc_params_t), _vp, ctypes.c_int,
@@ -197,6 +223,16 @@ def tpc_assign_collisions(tracks: tpc_tracks_t, unit_side: int, n_units: int, fi
                                                     workspace_bytes, stream))
 
 
+def tpc_clusterize_workspace_size(n_units: int, geometry: tpc_pad_geometry_t) -> int:
+    return int(load_library().tpc_clusterize_workspace_size(n_units, ctypes.byref(geometry)))
+
+
+def tpc_clusterize(digits: tpc_digits_t, geometry: tpc_pad_geometry_t, params: tpc_clusterizer_params_t,
+                   out: tpc_cluster_out_t, workspace: int, workspace_bytes: int, stream: int) -> int:
+    return int(load_library().tpc_clusterize(ctypes.byref(digits), ctypes.byref(geometry), ctypes.byref(params),
+                                             ctypes.byref(out), workspace, workspace_bytes, stream))
+
+
 def make_collision_params(v_drift=2.58, bin_width=1.0, z_range=4096.0, c_max=None, n_min=10, reach=2,
                           outer_radius=None) -> tpc_collision_params_t:
     """Defaults: 1 cm bins over +-4096 cm, 10 forming tracks per candidate,
@@ -226,7 +262,7 @@ def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, wor
 def __getattr__(name):
     # the torch-side helpers load on first use, so that importing the package
     # (e.g. for its parameter values) does not import torch
-    if name in ("Tracker", "track", "CollisionAssigner"):
+    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer"):
         from . import runtime
         return getattr(runtime, name)
     raise AttributeError(name)

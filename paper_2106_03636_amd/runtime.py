@@ -313,3 +313,99 @@ class CollisionAssigner:
         return dict(n_collisions=n, zdca=self.o_zdca[:T], collision=self.o_collision[:T], side=self.o_side[:n],
                     bin=self.o_bin[:n], count=self.o_count[:n], n_form=self.o_n_form[:n], z=self.o_z[:n],
                     t0=self.o_t0[:n])
+
+
+class Clusterizer:
+    """Workspace and outputs of tpc_clusterize for digit batches of up to
+    max_units units and cap clusters.  half: half the pad count of each row;
+    pad_width, time_bin, z_offset as in tpc_pad_geometry_t."""
+
+    def __init__(self, half, pad_width, time_bin, z_offset, max_units, cap, q_min=10, device="cuda"):
+        from . import tpc_clusterize_workspace_size, tpc_clusterizer_params_t, tpc_pad_geometry_t
+        self.device = torch.device(device)
+        half = np.ascontiguousarray(half, np.int32)
+        self.half = torch.as_tensor(half).to(self.device)
+        self.geometry = tpc_pad_geometry_t()
+        self.geometry.n_rows = len(half)
+        self.geometry.pads_total = int(2 * half.sum())
+        self.geometry.half = _ptr(self.half)
+        self.geometry.pad_width, self.geometry.time_bin, self.geometry.z_offset = pad_width, time_bin, z_offset
+        self.params = tpc_clusterizer_params_t()
+        self.params.q_min = int(q_min)
+        self.max_units, self.cap = int(max_units), int(cap)
+        ws = tpc_clusterize_workspace_size(self.max_units, self.geometry)
+        if ws == 0:
+            raise ValueError("invalid pad geometry")
+        self.ws_bytes = ws
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        d, c = self.device, max(1, self.cap)
+        self.o_y = torch.empty(c, dtype=torch.float32, device=d)
+        self.o_z = torch.empty(c, dtype=torch.float32, device=d)
+        self.o_row = torch.empty(c, dtype=torch.int16, device=d)  # uint16 rows
+        self.o_qtot = torch.empty(c, dtype=torch.int32, device=d)
+        self.o_qmax = torch.empty(c, dtype=torch.int16, device=d)  # uint16 charges
+        self.o_pad = torch.empty(c, dtype=torch.float32, device=d)
+        self.o_time = torch.empty(c, dtype=torch.float32, device=d)
+        self.o_unit_offsets = torch.zeros(self.max_units + 1, dtype=torch.int64, device=d)
+        self.o_count = torch.zeros(1, dtype=torch.int64, device=d)
+        self.o_status = torch.zeros(1, dtype=torch.int32, device=d)
+        self._n_units = 0
+
+    @staticmethod
+    def upload(digits, device="cuda"):
+        """Host digits (time, q: uint16; pad_offsets: int64) to device tensors."""
+        dev = torch.device(device)
+        t = torch.as_tensor(np.ascontiguousarray(digits.time, np.uint16).view(np.int16)).to(dev)
+        q = torch.as_tensor(np.ascontiguousarray(digits.q, np.uint16).view(np.int16)).to(dev)
+        off = torch.as_tensor(np.ascontiguousarray(digits.pad_offsets, np.int64)).to(dev)
+        return t, q, off
+
+    def launch(self, time, q, pad_offsets, n_units, stream=None):
+        """Enqueue the clusterization of device digits (time, q as int16 views
+        of uint16, pad_offsets int64) of n_units units."""
+        from . import tpc_cluster_out_t, tpc_clusterize, tpc_digits_t
+        if n_units > self.max_units:
+            raise ValueError("more units than this clusterizer was sized for")
+        if pad_offsets.numel() != n_units * self.geometry.pads_total + 1:
+            raise ValueError("pad_offsets must have n_units * pads_total + 1 entries")
+        dg = tpc_digits_t()
+        dg.n = int(time.numel())
+        dg.n_units = int(n_units)
+        dg.pad_offsets = _ptr(pad_offsets)
+        dg.time, dg.q = _ptr(time), _ptr(q)
+        o = tpc_cluster_out_t()
+        o.cap = self.cap
+        o.y, o.z, o.row = _ptr(self.o_y), _ptr(self.o_z), _ptr(self.o_row)
+        o.qtot, o.qmax, o.pad, o.time = _ptr(self.o_qtot), _ptr(self.o_qmax), _ptr(self.o_pad), _ptr(self.o_time)
+        o.unit_offsets, o.count, o.status = _ptr(self.o_unit_offsets), _ptr(self.o_count), _ptr(self.o_status)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = tpc_clusterize(dg, self.geometry, self.params, o, self.workspace.data_ptr(), self.ws_bytes, s.cuda_stream)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_clusterize: %s" % tpc_status_string(st))
+        self._n_units = int(n_units)
+        return st
+
+    def result(self, sync=True):
+        if sync:
+            torch.cuda.synchronize(self.device)
+        st = int(self.o_status.item())
+        n = int(self.o_count.item())
+        if st != TPC_OK:
+            raise TrackingError(st, "clusterization failed on the device: %s (clusters %d)" % (tpc_status_string(st), n))
+        return dict(n=n, y=self.o_y[:n], z=self.o_z[:n], row=self.o_row[:n], qtot=self.o_qtot[:n],
+                    qmax=self.o_qmax[:n], pad=self.o_pad[:n], time=self.o_time[:n],
+                    unit_offsets=self.o_unit_offsets[:self._n_units + 1])
+
+    def batch(self, row_x, bz):
+        """The last result as a tracking Batch over the same device arrays
+        (synchronizes once, for the cluster count)."""
+        r = self.result()
+        b = Batch.__new__(Batch)
+        b.y, b.z, b.row = r["y"], r["z"], r["row"]
+        b.unit_offsets = r["unit_offsets"]
+        b.row_x = torch.as_tensor(np.ascontiguousarray(row_x, np.float32)).to(self.device)
+        b.n = r["n"]
+        b.n_units = self._n_units
+        b.n_rows = int(len(row_x))
+        b.bz = float(bz)
+        return b

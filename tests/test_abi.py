@@ -35,6 +35,8 @@ def test_struct_layouts_match_header(tmp_path):
                "tpc_field_t": T.tpc_field_t, "tpc_params_t": T.tpc_params_t,
                "tpc_tracks_t": T.tpc_tracks_t, "tpc_view_t": T.tpc_view_t,
                "tpc_collision_params_t": T.tpc_collision_params_t, "tpc_collisions_t": T.tpc_collisions_t,
+               "tpc_pad_geometry_t": T.tpc_pad_geometry_t, "tpc_digits_t": T.tpc_digits_t,
+               "tpc_clusterizer_params_t": T.tpc_clusterizer_params_t, "tpc_cluster_out_t": T.tpc_cluster_out_t,
                "tpc_server_config_t": S.tpc_server_config_t, "tpc_request_t": S.tpc_request_t,
                "tpc_result_t": S.tpc_result_t, "tpc_server_stats_t": S.tpc_server_stats_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tpc_track.h"', 'int main(void){']
@@ -131,6 +133,31 @@ def test_collision_call_host_checks():
     for bad in (dict(v_drift=0.0), dict(n_min=0), dict(reach=65), dict(reach=-1)):
         assert T.tpc_assign_collisions(trk, 0x1000, 36, f, T.make_collision_params(**bad), out, 0x8000,
                                        1 << 20, 0) == T.TPC_E_INVALID, bad
+
+
+def test_clusterizer_host_checks():
+    """Workspace sizes and the arguments tpc_clusterize rejects before any
+    device work."""
+    g = T.tpc_pad_geometry_t()
+    g.n_rows, g.pads_total, g.half = 152, 14982, 0x1000
+    g.pad_width, g.time_bin, g.z_offset = 0.6, 0.516, 4096.0
+    ws = T.tpc_clusterize_workspace_size(36, g)
+    assert ws >= 36 * 14982 * 4 and T.tpc_clusterize_workspace_size(1, g) < ws
+    assert T.tpc_clusterize_workspace_size(0, g) == 0
+    p = T.tpc_clusterizer_params_t()
+    p.q_min = 10
+    d, o = T.tpc_digits_t(), T.tpc_cluster_out_t()
+    assert T.tpc_clusterize(d, g, p, o, 0x8000, ws, 0) == T.TPC_E_INVALID
+    d.n, d.n_units, d.pad_offsets, d.time, d.q = 100, 36, 0x2000, 0x3000, 0x3000
+    o.cap, o.unit_offsets, o.count, o.status = 10, 0x4000, 0x4000, 0x4000
+    o.y = o.z = o.row = o.qtot = o.qmax = o.pad = o.time = 0x5000
+    assert T.tpc_clusterize(d, g, p, o, 0x8001, ws, 0) == T.TPC_E_INVALID  # misaligned
+    assert T.tpc_clusterize(d, g, p, o, 0x8000, ws - 1, 0) == T.TPC_E_NOMEM
+    p.q_min = 0
+    assert T.tpc_clusterize(d, g, p, o, 0x8000, ws, 0) == T.TPC_E_INVALID
+    p.q_min = 10
+    g.pad_width = 0.0
+    assert T.tpc_clusterize(d, g, p, o, 0x8000, ws, 0) == T.TPC_E_INVALID
 
 
 def test_status_strings():
