@@ -15,7 +15,10 @@ Prints ONE JSON line (rank 0).  Besides the contract fields it carries:
   collisions    the assignment of the frame's tracks to collisions, after
                 tracking and outside the timed step: the call's device time
                 (HIP graph replays) and its physics on the 50-collision frame
-                of the physical generator against MC truth.
+                of the physical generator against MC truth;
+  clusterizer   raw ADC digits of the frame's clusters to clusters, outside
+                the timed step: the call's device time, its HBM roofline and
+                the oracle on a sample of units.
 """
 from __future__ import annotations
 
@@ -54,6 +57,10 @@ FIT_OPS_PER_UPDATE = 24 + 3 + 1 + 35 + 3 + 102 + 119 + 1
 # (20), x_ref (4) and unit (4) and writes z' (8); the assignment kernel reads
 # z' (8), unit (4) and q/pT (4) and writes the candidate (4)
 COL_BYTES_PER_TRACK = 20 + 4 + 4 + 8 + 8 + 4 + 4 + 4
+# clusterizer, algorithmic bytes: each digit (time 2, charge 2) read once,
+# each pad's offset (8) read once, each cluster (y, z, pad, time 4 each, row
+# 2, qtot 4, qmax 2) written once
+CLU_BYTES_PER_DIGIT, CLU_BYTES_PER_PAD, CLU_BYTES_PER_CLUSTER = 4, 8, 24
 COL_KERNEL_BYTES = {"k_col_clear": None, "k_col_zdca": 36, "k_col_flags": None, "k_col_number": None,
                     "k_col_assign": 20, "k_col_finish": None}
 SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
@@ -89,9 +96,9 @@ def make_workload(name, seed=None):
     return ev
 
 
-def col_digest():
+def col_digest(name="tpc_collisions.hip"):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2106_03636_amd", "csrc", "tpc_collisions.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2106_03636_amd", "csrc", name), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -225,6 +232,26 @@ def summarize_profiles(prof_dir, workload):
                 COL_KERNEL_BYTES[k] or "-"))
             traffic[k] = dict(src_digest=col_digest(), bytes_per_launch=fb + wb, fetch_bytes=fb, write_bytes=wb,
                               avg_us=avg_us)
+    clu = run.get("clusterizer")
+    if clu:
+        nd = clu["digits"]
+        lines += ["", "clusterizer (tpc_clusterize) over the %d raw ADC digits of the frame's clusters (%d clusters)"
+                  % (nd, clu["clusters"]),
+                  "%-18s %6s %10s %10s %10s %8s %8s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB",
+                                                       "B/digit", "GB/s")]
+        for k, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["totaldurationns"])):
+            if not k.startswith("k_clu_"):
+                continue
+            avg_us = float(r["averagens"]) / 1e3
+            fb = fetch.get(k, 0.0) * 1024 / f_fac
+            wb = write.get(k, 0.0) * 1024 / w_fac
+            lines.append("%-18s %6s %10.1f %10.2f %10.2f %8.2f %8.0f" % (
+                k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / nd, (fb + wb) / 1e3 / avg_us))
+            traffic[k] = dict(src_digest=col_digest("tpc_clusterize.hip"), bytes_per_launch=fb + wb,
+                              fetch_bytes=fb, write_bytes=wb, avg_us=avg_us)
+        lines.append("algorithmic: %d B per digit, %d per pad, %d per cluster; %.3g GB per call"
+                     % (CLU_BYTES_PER_DIGIT, CLU_BYTES_PER_PAD, CLU_BYTES_PER_CLUSTER,
+                        clu["roofline"]["algorithmic_bytes_per_launch"] / 1e9))
     txt = os.path.join(out_dir, "%s_kernels.txt" % workload)
     open(txt, "w").write("\n".join(lines) + "\n")
     tj = os.path.join(out_dir, "traffic.json")
@@ -608,6 +635,64 @@ def collision_bench(dev, tr, ev, reps, workload):
     return out
 
 
+def clusterizer_bench(dev, ev, reps, workload, cpu_units=2):
+    """Clusterizer (tpc_clusterize) on the raw ADC digits of `ev` (generated
+    from its clusters): the call's device time from HIP graph replays, the
+    HBM roofline at the algorithmic bytes, and the oracle on cpu_units units
+    of the same digits (one core)."""
+    import numpy as np
+    import torch
+    import synth
+    import oracle
+    from paper_2106_03636_amd.runtime import Clusterizer
+    t = time.time()
+    d = synth.event_digits(ev, 7)
+    log("bench: generated %d digits of %s (%.1f s)" % (d.n, workload, time.time() - t))
+    pw, tb, zoff = (float(np.float32(v)) for v in (synth.PAD_W, synth.TIME_BIN, synth.Z_OFF))
+    tt, qq, off = Clusterizer.upload(d, dev)
+    c = Clusterizer(synth.PAD_HALF, pw, tb, zoff, d.n_units, d.n, device=dev)
+    for _ in range(2):
+        c.launch(tt, qq, off, d.n_units)
+    n_clusters = c.result()["n"]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        c.launch(tt, qq, off, d.n_units)
+    torch.cuda.synchronize(dev)
+    graph.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    if c.result()["n"] != n_clusters:
+        raise RuntimeError("graph replay and eager call of the clusterizer disagree")
+    del graph
+    n_pads = d.n_units * synth.PADS_TOTAL
+    alg = CLU_BYTES_PER_DIGIT * d.n + CLU_BYTES_PER_PAD * n_pads + CLU_BYTES_PER_CLUSTER * n_clusters
+    achieved = alg / (ms * 1e-3) / 1e9
+    # the oracle on a sample of units, one thread
+    nu = min(cpu_units, d.n_units)
+    pads = nu * synth.PADS_TOTAL
+    sub_off = d.pad_offsets[:pads + 1]
+    n_sub = int(sub_off[-1])
+    t = time.time()
+    oracle.clusterize(synth.PAD_HALF, sub_off, d.time[:n_sub], d.q[:n_sub], nu, 10, pw, tb, zoff)
+    cpu_s = time.time() - t
+    out = dict(workload=workload, digits=int(d.n), clusters=int(n_clusters), pads=int(n_pads),
+               ms_per_call=ms, digits_per_s=d.n / (ms * 1e-3), launches=4,
+               roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=achieved / HBM_PEAK_GBS, algorithmic_bytes_per_launch=int(alg), traffic=None),
+               cpu_oracle=dict(value=n_sub / cpu_s, unit="digits/s", cores=1,
+                               sample="%d of %d units (%d digits), %.1f s" % (nu, d.n_units, n_sub, cpu_s)))
+    log("bench: clusterizer " + json.dumps(out))
+    del tt, qq, off, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(ev, n_units_sample, values, single_core_units=2):
     """The CPU oracle, as it stands, on the first n_units_sample units with all
     its threads, and on single_core_units units with one thread (the paper
@@ -661,6 +746,7 @@ def main():
                     help="write profiles/ summaries from rocprofv3 runs of this script and exit")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
     ap.add_argument("--no-collisions", action="store_true", help="skip the collision-assignment measurement")
+    ap.add_argument("--no-clusterizer", action="store_true", help="skip the clusterizer measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -870,6 +956,8 @@ def main():
 
     del tr
     torch.cuda.empty_cache()
+    if not args.no_clusterizer:
+        out["clusterizer"] = clusterizer_bench(dev, ev, max(20, args.steps), args.workload)
     if not args.no_batched:
         out["central"] = event_bench(dev, max(4, args.steps), params, "pbpb_central")
         out["pp_sector"] = event_bench(dev, max(4, args.steps), params, "pp_sector")

@@ -7,14 +7,16 @@
 //   k_clu_init   status and count;
 //   k_clu_count  one wave per pad: the peaks among the pad's digits (their
 //                neighbours in the pads either side found by binary search
-//                over those pads' time-ordered digits), counted per pad and
-//                per block of four pads; input checks;
+//                over those pads' time-ordered digits, staged in LDS with
+//                the block's own pads), counted per pad and per block of
+//                four pads; input checks;
 //   k_clu_scan   one block: exclusive scan of the per-block counts, total,
 //                capacity check;
 //   k_clu_emit   one wave per pad again: each peak recomputed and written at
 //                its block's base plus the counts of the pads and lanes
 //                before it, so clusters come in (unit, row, pad, time) order.
-// The digits are read twice (2 x 4 bytes each); everything else is small.
+// The digits are read twice (2 x 4 bytes each, once per pass into LDS, with
+// the pads either side of a block's four pads); everything else is small.
 // Peaks and charge sums are integer; the centre and position are FP64
 // expressions rounded once to FP32, so the result is exact.
 
@@ -70,75 +72,56 @@ __device__ __forceinline__ int row_of(const int32_t *rbase, int n_rows, int32_t 
   return lo;
 }
 
-struct PadCtx {
-  int64_t j, a, b;         // pad index, its digits [a, b)
-  int64_t am, bm, ap, bp;  // digits of the pads below and above (empty at a row's edge)
-  int u, r, p;
+// A pad's time-ordered digits: times and charges, n of them (LDS or global).
+struct List {
+  const uint16_t *t, *q;
+  int32_t n;
 };
-
-__device__ __forceinline__ PadCtx pad_ctx(const CluArgs &A, const int32_t *rbase, int64_t j) {
-  PadCtx c;
-  c.j = j;
-  c.u = int(j / A.pads_total);
-  const int32_t jr = int32_t(j - int64_t(c.u) * A.pads_total);
-  c.r = row_of(rbase, A.n_rows, jr);
-  c.p = jr - rbase[c.r];
-  const int np = 2 * A.half[c.r];
-  c.a = A.off[j];
-  c.b = A.off[j + 1];
-  c.am = c.bm = c.ap = c.bp = 0;
-  if (c.p > 0) {
-    c.am = A.off[j - 1];
-    c.bm = c.a;
-  }
-  if (c.p < np - 1) {
-    c.ap = c.b;
-    c.bp = A.off[j + 2];
-  }
-  return c;
-}
 
 struct Peak {
   bool is;
   int32_t t, v, Q, Sp, St;
 };
 
-// The peak test and 3x3 sums of digit d of pad c: neighbours in the same pad
-// are the adjacent digits (times increase inside a pad); in the pads either
-// side, the digits with time t-1..t+1.  A neighbour earlier in (pad, time)
-// order must be smaller, a later one at most equal.
-__device__ __forceinline__ Peak peak_at(const CluArgs &A, const PadCtx &c, int64_t d) {
+// The peak test and 3x3 sums of digit i of `own`: neighbours in the same pad
+// are the adjacent digits (times increase inside a pad); in the pads below
+// and above (`lo`, `hi`: empty at a row's edge), the digits with time
+// t-1..t+1, found by binary search.  A neighbour earlier in (pad, time) order
+// must be smaller, a later one at most equal.
+__device__ __forceinline__ Peak peak_at(int32_t q_min, const List &own, const List &lo, const List &hi, int32_t i) {
   Peak k;
-  k.t = A.time[d];
-  k.v = A.q[d];
+  k.t = own.t[i];
+  k.v = own.q[i];
   k.Q = k.v;
   k.Sp = 0;
   k.St = 0;
-  k.is = k.v >= A.q_min;
+  k.is = k.v >= q_min;
   if (!k.is) return k;
-  // same pad: dp = 0, later digits win ties against the earlier ones
-  if (d > c.a && int32_t(A.time[d - 1]) == k.t - 1) {
-    const int32_t w = A.q[d - 1];
+  if (i > 0 && int32_t(own.t[i - 1]) == k.t - 1) {  // earlier in the same pad
+    const int32_t w = own.q[i - 1];
     if (!(w < k.v)) k.is = false;
     k.Q += w;
     k.St -= w;
   }
-  if (d + 1 < c.b && int32_t(A.time[d + 1]) == k.t + 1) {
-    const int32_t w = A.q[d + 1];
+  if (i + 1 < own.n && int32_t(own.t[i + 1]) == k.t + 1) {  // later in the same pad
+    const int32_t w = own.q[i + 1];
     if (!(w <= k.v)) k.is = false;
     k.Q += w;
     k.St += w;
   }
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
+    const List &L = side ? hi : lo;
     const int dp = side ? 1 : -1;
-    const int64_t lo = side ? c.ap : c.am, hi = side ? c.bp : c.bm;
-    if (lo >= hi) continue;
-    int64_t e = lower_time(A.time, lo, hi, k.t - 1);
-    for (int m = 0; m < 3 && e < hi; ++m, ++e) {
-      const int32_t te = A.time[e];
+    int32_t a = 0, b = L.n;  // first digit with time >= t - 1
+    while (a < b) {
+      const int32_t mid = (a + b) >> 1;
+      if (int32_t(L.t[mid]) < k.t - 1) a = mid + 1; else b = mid;
+    }
+    for (int m = 0; m < 3 && a < L.n; ++m, ++a) {
+      const int32_t te = L.t[a];
       if (te > k.t + 1) break;
-      const int32_t w = A.q[e];
+      const int32_t w = L.q[a];
       // the pad above is later in (pad, time) order, the pad below earlier
       if (side ? !(w <= k.v) : !(w < k.v)) k.is = false;
       k.Q += w;
@@ -157,7 +140,6 @@ __device__ __forceinline__ void load_rbase(const CluArgs &A, int32_t *rbase) {
       s += 2 * A.half[r];
     }
   }
-  __syncthreads();
 }
 
 __global__ void k_clu_init(CluArgs A) {
@@ -165,41 +147,124 @@ __global__ void k_clu_init(CluArgs A) {
   *A.count = 0;
 }
 
-// pad ranges that lie inside the digit arrays and do not decrease
-__device__ __forceinline__ bool ranges_ok(const CluArgs &A, const PadCtx &c) {
-  return c.a >= 0 && c.a <= c.b && c.b <= A.n && c.am >= 0 && c.am <= c.bm && c.bm <= A.n && c.ap >= 0 &&
-         c.ap <= c.bp && c.bp <= A.n;
+// A block takes PADS_PER_BLOCK consecutive pads, one per wave.  The digits
+// of those pads and of the pads just before and after (a contiguous range of
+// the digit arrays) are staged in LDS when they fit, so every neighbour
+// search runs in LDS; a block whose range does not fit reads the digit
+// arrays directly.  Slot s holds pad j0 - 1 + s.
+constexpr int SLOTS = PADS_PER_BLOCK + 2;
+constexpr int STAGE_DIGITS = 6144;  // 24 KB of (time, charge)
+
+struct Stage {
+  int64_t a[SLOTS + 1];  // slot s: digits [a[s], a[s+1]) of the arrays
+  int32_t rbase[MAX_ROWS];
+  uint16_t t[STAGE_DIGITS], q[STAGE_DIGITS];
+  int32_t cnt[PADS_PER_BLOCK];
+  int ok, fits;
+};
+
+// Offsets of the staged pads, checked; the digits staged if they fit.
+__device__ __forceinline__ void stage_block(const CluArgs &A, Stage &S, int64_t j0) {
+  load_rbase(A, S.rbase);
+  if (threadIdx.x <= SLOTS) {
+    const int64_t j = j0 - 1 + threadIdx.x;  // the offset at the start of pad j
+    S.a[threadIdx.x] = j < 0 ? -1 : (j > A.n_pads ? -2 : A.off[j]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // pads before the first and after the last are empty
+    if (S.a[0] == -1) S.a[0] = S.a[1];
+    for (int s = 1; s <= SLOTS; ++s)
+      if (S.a[s] == -2) S.a[s] = S.a[s - 1];
+    bool ok = true;
+    for (int s = 0; s <= SLOTS; ++s) ok = ok && S.a[s] >= 0 && S.a[s] <= A.n && (s == 0 || S.a[s - 1] <= S.a[s]);
+    if (j0 == 0) ok = ok && S.a[1] == 0;
+    if (j0 + PADS_PER_BLOCK >= A.n_pads) ok = ok && A.off[A.n_pads] == A.n;
+    if (!ok) fail(A.status, TPC_E_INVALID);
+    S.ok = ok;
+    S.fits = ok && S.a[SLOTS] - S.a[0] <= STAGE_DIGITS;
+  }
+  __syncthreads();
+  if (S.fits) {
+    const int32_t m = int32_t(S.a[SLOTS] - S.a[0]);
+    for (int32_t e = threadIdx.x; e < m; e += TPB) {
+      S.t[e] = A.time[S.a[0] + e];
+      S.q[e] = A.q[S.a[0] + e];
+    }
+  }
+  __syncthreads();
+}
+
+struct PadView {
+  List own, lo, hi;
+  int u, r, p;
+  bool valid;
+};
+
+// pad j0 + w of the block, its lists in LDS (LDS) or in the arrays
+template <bool LDS>
+__device__ __forceinline__ PadView pad_view(const CluArgs &A, const Stage &S, int64_t j0, int w) {
+  PadView v;
+  const int64_t j = j0 + w;
+  v.valid = j < A.n_pads;
+  v.u = int(j / A.pads_total);
+  const int32_t jr = int32_t(j - int64_t(v.u) * A.pads_total);
+  v.r = row_of(S.rbase, A.n_rows, jr);
+  v.p = jr - S.rbase[v.r];
+  const int np = 2 * A.half[v.r];
+  auto list = [&](int s) {
+    List L;
+    L.n = int32_t(S.a[s + 1] - S.a[s]);
+    if (LDS) {
+      L.t = S.t + (S.a[s] - S.a[0]);
+      L.q = S.q + (S.a[s] - S.a[0]);
+    } else {
+      L.t = A.time + S.a[s];
+      L.q = A.q + S.a[s];
+    }
+    return L;
+  };
+  v.own = list(w + 1);
+  v.lo = list(w);
+  v.hi = list(w + 2);
+  if (v.p == 0) v.lo.n = 0;  // neighbours stay in the row
+  if (v.p == np - 1) v.hi.n = 0;
+  return v;
+}
+
+template <bool LDS>
+__device__ __forceinline__ int32_t count_pad(const CluArgs &A, const Stage &S, int64_t j0, int w) {
+  const PadView v = pad_view<LDS>(A, S, j0, w);
+  int32_t cnt = 0;
+  if (!v.valid) return 0;
+  const int lane = __lane_id();
+  for (int32_t i0 = 0; i0 < v.own.n; i0 += 64) {
+    const int32_t i = i0 + lane;
+    bool pk = false;
+    if (i < v.own.n) {
+      if (i > 0 && v.own.t[i] <= v.own.t[i - 1]) fail(A.status, TPC_E_INVALID);  // times must increase
+      pk = peak_at(A.q_min, v.own, v.lo, v.hi, i).is;
+    }
+    cnt += __popcll(__ballot(pk));
+  }
+  return cnt;
 }
 
 __global__ void __launch_bounds__(TPB) k_clu_count(CluArgs A) {
-  __shared__ int32_t rbase[MAX_ROWS];
-  __shared__ int32_t wcnt[PADS_PER_BLOCK];
-  load_rbase(A, rbase);
+  __shared__ Stage S;
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
-  const int64_t j = int64_t(blockIdx.x) * PADS_PER_BLOCK + wave;
+  const int64_t j0 = int64_t(blockIdx.x) * PADS_PER_BLOCK;
+  stage_block(A, S, j0);
   int32_t cnt = 0;
-  if (j < A.n_pads) {
-    PadCtx c = pad_ctx(A, rbase, j);
-    if (!ranges_ok(A, c) || (j == 0 && c.a != 0) || (j == A.n_pads - 1 && c.b != A.n)) {
-      if (lane == 0) fail(A.status, TPC_E_INVALID);
-      c.b = c.a;  // read none of its digits
-    }
-    for (int64_t d0 = c.a; d0 < c.b; d0 += 64) {
-      const int64_t d = d0 + lane;
-      bool pk = false;
-      if (d < c.b) {
-        if (d > c.a && A.time[d] <= A.time[d - 1]) fail(A.status, TPC_E_INVALID);  // times must increase
-        pk = peak_at(A, c, d).is;
-      }
-      cnt += __popcll(__ballot(pk));
-    }
-    if (lane == 0) A.pad_cnt[j] = cnt;
+  if (S.ok) cnt = S.fits ? count_pad<true>(A, S, j0, wave) : count_pad<false>(A, S, j0, wave);
+  if (lane == 0) {
+    S.cnt[wave] = cnt;
+    if (j0 + wave < A.n_pads) A.pad_cnt[j0 + wave] = cnt;
   }
-  if (lane == 0) wcnt[wave] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
     int32_t s = 0;
-    for (int w = 0; w < PADS_PER_BLOCK; ++w) s += wcnt[w];
+    for (int w = 0; w < PADS_PER_BLOCK; ++w) s += S.cnt[w];
     A.blk[blockIdx.x] = s;
   }
 }
@@ -250,40 +315,49 @@ __global__ void __launch_bounds__(1024) k_clu_scan(CluArgs A, int64_t nblk) {
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_clu_emit(CluArgs A) {
-  __shared__ int32_t rbase[MAX_ROWS];
-  load_rbase(A, rbase);
-  if (*A.status != TPC_OK) return;
-  const int lane = __lane_id(), wave = threadIdx.x >> 6;
-  const int64_t j = int64_t(blockIdx.x) * PADS_PER_BLOCK + wave;
-  if (j >= A.n_pads) return;
+template <bool LDS>
+__device__ __forceinline__ void emit_pad(const CluArgs &A, const Stage &S, int64_t j0, int w) {
+  const PadView v = pad_view<LDS>(A, S, j0, w);
+  if (!v.valid) return;
+  const int lane = __lane_id();
+  const int64_t j = j0 + w;
   int64_t o = A.blk[blockIdx.x];
-  for (int64_t k = int64_t(blockIdx.x) * PADS_PER_BLOCK; k < j; ++k) o += A.pad_cnt[k];
-  const PadCtx c = pad_ctx(A, rbase, j);
-  if (c.p == 0 && c.r == 0 && lane == 0) A.unit_offsets[c.u] = o;  // first pad of the unit
-  const double half = double(A.half[c.r]);
-  for (int64_t d0 = c.a; d0 < c.b; d0 += 64) {
-    const int64_t d = d0 + lane;
+  for (int64_t k = j0; k < j; ++k) o += A.pad_cnt[k];
+  if (v.p == 0 && v.r == 0 && lane == 0) A.unit_offsets[v.u] = o;  // first pad of the unit
+  const double half = double(A.half[v.r]);
+  for (int32_t i0 = 0; i0 < v.own.n; i0 += 64) {
+    const int32_t i = i0 + lane;
     Peak k;
     k.is = false;
-    if (d < c.b) k = peak_at(A, c, d);
+    if (i < v.own.n) k = peak_at(A.q_min, v.own, v.lo, v.hi, i);
     const uint64_t m = __ballot(k.is);
     if (k.is) {
       // the oracle's order of operations, each rounded (no fused multiply-add)
 #pragma clang fp contract(off)
-      const int64_t i = o + __popcll(m & ((1ull << lane) - 1ull));
-      const double padf = double(c.p) + double(k.Sp) / double(k.Q);
+      const int64_t c = o + __popcll(m & ((1ull << lane) - 1ull));
+      const double padf = double(v.p) + double(k.Sp) / double(k.Q);
       const double timef = double(k.t) + double(k.St) / double(k.Q);
-      A.y[i] = float((padf + 0.5 - half) * A.pw);
-      A.z[i] = float((timef + 0.5) * A.tb - A.zoff);
-      A.padf[i] = float(padf);
-      A.timef[i] = float(timef);
-      A.row[i] = uint16_t(c.r);
-      A.qmax[i] = uint16_t(k.v);
-      A.qtot[i] = k.Q;
+      A.y[c] = float((padf + 0.5 - half) * A.pw);
+      A.z[c] = float((timef + 0.5) * A.tb - A.zoff);
+      A.padf[c] = float(padf);
+      A.timef[c] = float(timef);
+      A.row[c] = uint16_t(v.r);
+      A.qmax[c] = uint16_t(k.v);
+      A.qtot[c] = k.Q;
     }
     o += __popcll(m);
   }
+}
+
+__global__ void __launch_bounds__(TPB) k_clu_emit(CluArgs A) {
+  __shared__ Stage S;
+  if (*A.status != TPC_OK) return;
+  const int wave = threadIdx.x >> 6;
+  const int64_t j0 = int64_t(blockIdx.x) * PADS_PER_BLOCK;
+  stage_block(A, S, j0);
+  if (!S.ok) return;
+  if (S.fits) emit_pad<true>(A, S, j0, wave);
+  else emit_pad<false>(A, S, j0, wave);
 }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
