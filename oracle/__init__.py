@@ -104,6 +104,8 @@ def _load():
         lib.orc_clusterize.restype = ctypes.c_int64
         lib.orc_clusterize.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double] + [vp] * 12
+        lib.orc_compress.restype = None
+        lib.orc_compress.argtypes = [ctypes.c_int64] + [vp] * 7 + [ctypes.c_double] * 5 + [vp] * 4
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -282,6 +284,30 @@ def clusterize(half, pad_offsets, time, q, n_units, q_min, pw, tb, zoff):
     out.update({k: v[:n] for k, v in flts.items()})
     out["n"] = int(n)
     return out
+
+
+def compress(y, z, row, cluster_track, params, x_ref, row_x, k, step=1.0 / 64, pt_remove=0.1, sinphi_max=0.999,
+             eps=1e-6):
+    """Hit removal and residual codes of clusters (see orc_compress in tpc_oracle.c)."""
+    lib = _load()
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    row = np.ascontiguousarray(row, np.uint16)
+    ct = np.ascontiguousarray(cluster_track, np.int32)
+    params = np.ascontiguousarray(params, np.float32).reshape(-1)
+    x_ref = np.ascontiguousarray(x_ref, np.float32)
+    row_x = np.ascontiguousarray(row_x, np.float32)
+    n = len(y)
+    cls = np.zeros(n, np.uint8)
+    cy, cz = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    frag = np.zeros(n, np.uint8)
+    if len(params) == 0:
+        params = np.zeros(5, np.float32)
+        x_ref = np.zeros(1, np.float32)
+    lib.orc_compress(n, y.ctypes.data, z.ctypes.data, row.ctypes.data, ct.ctypes.data, params.ctypes.data,
+                     x_ref.ctypes.data, row_x.ctypes.data, float(k), float(step), float(pt_remove),
+                     float(sinphi_max), float(eps), cls.ctypes.data, cy.ctypes.data, cz.ctypes.data, frag.ctypes.data)
+    return dict(cls=cls, code_y=cy, code_z=cz, fragile=frag)
 
 
 def num_threads() -> int:

@@ -1280,6 +1280,56 @@ int64_t orc_clusterize(int32_t n_units, int32_t n_rows, const int32_t *half, con
   return nc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Hit removal and track-model compression (the consumer of the tracks).  The  */
+/* paper states that hits of tracks not used for physics are removed and the  */
+/* remaining hits go through entropy-reduction steps such as the track model  */
+/* compression (§2.1); it does not give them.  Reading used here: a cluster   */
+/* attached to a track with pT below pt_remove (|q/pT| pt_remove > 1: loopers */
+/* that curl inside the chamber) is removed; a cluster attached to another    */
+/* track is stored as its residual to the track model -- the track's state at */
+/* x_ref carried along the helix to the cluster's row -- in steps of `step`   */
+/* cm, rounded half to even; a cluster attached to no track, or whose track   */
+/* cannot reach its row within |sin(phi)| < sinphi_max, is stored by its      */
+/* position in the same steps.  The entropy coder that would follow is out of */
+/* scope; the codes' histograms give its size.                                */
+
+/* Codes of n clusters.  cls: 0 no track (position codes), 1 residual codes,
+ * 2 removed, 3 attached without a model (position codes).  fragile: the
+ * unrounded code of y or z lies within eps of a rounding boundary, so another
+ * rounding of the prediction could change it. */
+void orc_compress(int64_t n, const float *y, const float *z, const uint16_t *row, const int32_t *cluster_track,
+                  const float *params, const float *x_ref, const float *row_x, double k, double step,
+                  double pt_remove, double sinphi_max, double eps, uint8_t *cls, int32_t *code_y, int32_t *code_z,
+                  uint8_t *fragile) {
+  for (int64_t c = 0; c < n; ++c) {
+    const int32_t t = cluster_track[c];
+    double vy = (double)y[c] / step, vz = (double)z[c] / step;
+    cls[c] = 0;
+    if (t >= 0) {
+      double p[5], out[5];
+      for (int i = 0; i < 5; ++i) p[i] = (double)params[(int64_t)t * 5 + i];
+      if (fabs(p[4]) * pt_remove > 1.0) {
+        cls[c] = 2;
+        code_y[c] = code_z[c] = 0;
+        fragile[c] = 0;
+        continue;
+      }
+      if (orc_propagate(p, (double)x_ref[t], (double)row_x[row[c]], k, sinphi_max, out, NULL) == 0) {
+        cls[c] = 1;
+        vy = ((double)y[c] - out[0]) / step;
+        vz = ((double)z[c] - out[1]) / step;
+      } else {
+        cls[c] = 3;
+      }
+    }
+    code_y[c] = (int32_t)nearbyint(vy);
+    code_z[c] = (int32_t)nearbyint(vz);
+    const double fy = vy - floor(vy), fz = vz - floor(vz);
+    fragile[c] = fabs(fy - 0.5) < eps || fabs(fz - 0.5) < eps;
+  }
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -14,6 +14,7 @@ import pytest
 import oracle
 import test_clusterizer_oracle as clu
 import test_collisions_oracle as col
+import test_compression_oracle as cmp
 import test_oracle_pins as pins
 from conftest import cached_event, cached_oracle
 
@@ -119,6 +120,19 @@ MUTATIONS = [
     ("clusterizer_pad_moment_sign",
      "Sp += w * dp;", "Sp -= w * dp;",
      [clu.test_plateau_and_diagonal_ties_give_one_peak]),
+    ("compression_residual_sign",
+     "        vy = ((double)y[c] - out[0]) / step;", "        vy = (out[0] - (double)y[c]) / step;",
+     [cmp.test_displacements_come_back_as_codes]),
+    ("compression_removal_at_the_cut",
+     "if (fabs(p[4]) * pt_remove > 1.0) {", "if (fabs(p[4]) * pt_remove >= 1.0) {",
+     [cmp.test_removal_cut_and_unattached_rounding]),
+    ("compression_model_at_the_row_below",
+     "(double)row_x[row[c]], k, sinphi_max, out, NULL)",
+     "(double)row_x[row[c] > 0 ? row[c] - 1 : 0], k, sinphi_max, out, NULL)",
+     [cmp.test_clusters_on_the_helix_have_code_zero]),
+    ("compression_z_against_y",
+     "        vz = ((double)z[c] - out[1]) / step;", "        vz = ((double)z[c] - out[0]) / step;",
+     [cmp.test_clusters_on_the_helix_have_code_zero]),
 ]
 
 
