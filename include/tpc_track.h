@@ -267,6 +267,51 @@ int tpc_clusterize(const tpc_digits_t *digits, const tpc_pad_geometry_t *geometr
                    size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------- */
+/* Hit removal and track-model compression.  The consumer of the tracks: the */
+/* paper states that hits of tracks not used for physics are removed and the */
+/* remaining hits go through entropy-reduction steps such as the track model */
+/* compression (§2.1); it does not give them.  What this call computes, per  */
+/* cluster of a tracking call's input:                                       */
+/*   - class 2 (removed): attached to a track with |q/pT| pt_remove > 1;     */
+/*   - class 1 (residual): attached to another track whose helix, carried    */
+/*     in FP64 from the track's state at x_ref to the cluster's row, stays   */
+/*     within |sin(phi)| < sinphi_max: codes (y - y_track) / step and        */
+/*     (z - z_track) / step, rounded half to even;                           */
+/*   - class 0 (no track) and 3 (attached, helix does not reach the row):    */
+/*     codes y / step and z / step, rounded half to even.                    */
+/* Class-1 codes are also histogrammed, so the bits an entropy coder would   */
+/* need follow from the histograms (the coder itself is not part of this     */
+/* library).  Helix: C = -0.00299792458f * bz * q/pT as the tracker's fit    */
+/* uses; sin(phi) grows by C dx, y by dx (sin1 + sin2) / (cos1 + cos2), z by */
+/* tan(lambda) times the transverse arc length 2 asin(C L / 2) / C over the  */
+/* chord L.                                                                  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct tpc_compress_params {
+  float step;                  /* code unit (cm), > 0 */
+  float pt_remove;             /* GeV, >= 0 (0 removes nothing) */
+  float sinphi_max;            /* the helix model's limit, 0 < . < 1 */
+  int32_t hist_half;           /* histograms cover codes [-hist_half, hist_half), 1..2048 */
+} tpc_compress_params_t;
+
+/* Outputs (device pointers, allocated by the caller). */
+typedef struct tpc_compressed {
+  uint8_t *cls;                /* [n] class of each cluster (0..3, above) */
+  int32_t *code_y, *code_z;    /* [n] codes (0 for removed clusters) */
+  int64_t *hist;               /* [4 hist_half]: class-1 y codes, then z codes; bin = code + hist_half */
+  int64_t *counts;             /* [6]: clusters of classes 0..3, class-1 y and z codes outside the histograms */
+  int32_t *status;             /* [1] TPC_OK, or the tracking call's own status when that is not TPC_OK */
+} tpc_compressed_t;
+
+/* Codes of the clusters of a tpc_track_sectors call (the same clusters and
+ * geometry, and that call's output), enqueued on `stream` after it.  No
+ * workspace.  Returns TPC_OK when the work was enqueued, TPC_E_INVALID on bad
+ * arguments, TPC_E_HIP on a launch failure. */
+int tpc_compress(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry, const tpc_field_t *field,
+                 const tpc_tracks_t *tracks, const tpc_compress_params_t *params, tpc_compressed_t *out,
+                 void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Collision assignment.  In continuous readout the collisions of a time     */
 /* frame overlap in the drift volume, and tracks are assigned to them only   */
 /* after tracking (paper §2, §2.3); the paper does not describe how.  What   */

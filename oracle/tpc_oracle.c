@@ -1295,9 +1295,9 @@ int64_t orc_clusterize(int32_t n_units, int32_t n_rows, const int32_t *half, con
 /* scope; the codes' histograms give its size.                                */
 
 /* Codes of n clusters.  cls: 0 no track (position codes), 1 residual codes,
- * 2 removed, 3 attached without a model (position codes).  fragile: the
- * unrounded code of y or z lies within eps of a rounding boundary, so another
- * rounding of the prediction could change it. */
+ * 2 removed, 3 attached without a model (position codes).  fragile: a
+ * residual code whose unrounded value lies within eps of a rounding boundary,
+ * so another rounding of the prediction could change it. */
 void orc_compress(int64_t n, const float *y, const float *z, const uint16_t *row, const int32_t *cluster_track,
                   const float *params, const float *x_ref, const float *row_x, double k, double step,
                   double pt_remove, double sinphi_max, double eps, uint8_t *cls, int32_t *code_y, int32_t *code_z,
@@ -1325,8 +1325,12 @@ void orc_compress(int64_t n, const float *y, const float *z, const uint16_t *row
     }
     code_y[c] = (int32_t)nearbyint(vy);
     code_z[c] = (int32_t)nearbyint(vz);
+    /* a position code is one correctly rounded quotient of the inputs, the
+     * same everywhere, and so is a residual at the state's own plane (the
+     * helix carries nothing there); other residual codes depend on the
+     * helix's rounding */
     const double fy = vy - floor(vy), fz = vz - floor(vz);
-    fragile[c] = fabs(fy - 0.5) < eps || fabs(fz - 0.5) < eps;
+    fragile[c] = cls[c] == 1 && row_x[row[c]] != x_ref[t] && (fabs(fy - 0.5) < eps || fabs(fz - 0.5) < eps);
   }
 }
 

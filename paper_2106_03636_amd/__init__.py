@@ -95,6 +95,15 @@ class tpc_cluster_out_t(ctypes.Structure):
                 ("pad", _vp), ("time", _vp), ("unit_offsets", _vp), ("count", _vp), ("status", _vp)]
 
 
+class tpc_compress_params_t(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_float), ("pt_remove", ctypes.c_float), ("sinphi_max", ctypes.c_float),
+                ("hist_half", ctypes.c_int32)]
+
+
+class tpc_compressed_t(ctypes.Structure):
+    _fields_ = [("cls", _vp), ("code_y", _vp), ("code_z", _vp), ("hist", _vp), ("counts", _vp), ("status", _vp)]
+
+
 class tpc_view_t(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("count", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -143,6 +152,10 @@ def load_library():
         lib.tpc_clusterize.argtypes = [ctypes.POINTER(tpc_digits_t), ctypes.POINTER(tpc_pad_geometry_t),
                                        ctypes.POINTER(tpc_clusterizer_params_t), ctypes.POINTER(tpc_cluster_out_t),
                                        _vp, ctypes.c_size_t, _vp]
+        lib.tpc_compress.restype = ctypes.c_int
+        lib.tpc_compress.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
+                                     ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_tracks_t),
+                                     ctypes.POINTER(tpc_compress_params_t), ctypes.POINTER(tpc_compressed_t), _vp]
         lib.tpc_inspect.restype = ctypes.c_int
         lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
                                     ctypes.POINTER(tpc_params_t), _vp, ctypes.c_int,
@@ -233,6 +246,18 @@ def tpc_clusterize(digits: tpc_digits_t, geometry: tpc_pad_geometry_t, params: t
                                              ctypes.byref(out), workspace, workspace_bytes, stream))
 
 
+def tpc_compress(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t, tracks: tpc_tracks_t,
+                 params: tpc_compress_params_t, out: tpc_compressed_t, stream: int) -> int:
+    return int(load_library().tpc_compress(ctypes.byref(clusters), ctypes.byref(geometry), ctypes.byref(field),
+                                           ctypes.byref(tracks), ctypes.byref(params), ctypes.byref(out), stream))
+
+
+def make_compress_params(step=1.0 / 64, pt_remove=0.1, sinphi_max=0.999, hist_half=1024) -> tpc_compress_params_t:
+    cp = tpc_compress_params_t()
+    cp.step, cp.pt_remove, cp.sinphi_max, cp.hist_half = step, pt_remove, sinphi_max, int(hist_half)
+    return cp
+
+
 def make_collision_params(v_drift=2.58, bin_width=1.0, z_range=4096.0, c_max=None, n_min=10, reach=2,
                           outer_radius=None) -> tpc_collision_params_t:
     """Defaults: 1 cm bins over +-4096 cm, 10 forming tracks per candidate,
@@ -262,7 +287,7 @@ def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, wor
 def __getattr__(name):
     # the torch-side helpers load on first use, so that importing the package
     # (e.g. for its parameter values) does not import torch
-    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer"):
+    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer", "Compressor"):
         from . import runtime
         return getattr(runtime, name)
     raise AttributeError(name)

@@ -10,6 +10,7 @@ SRC_REQUESTS = os.path.join(HERE, "csrc", "tpc_requests.hip")
 SRC_SERVER = os.path.join(HERE, "csrc", "tpc_server.cpp")
 SRC_COLLISIONS = os.path.join(HERE, "csrc", "tpc_collisions.hip")
 SRC_CLUSTERIZE = os.path.join(HERE, "csrc", "tpc_clusterize.hip")
+SRC_COMPRESS = os.path.join(HERE, "csrc", "tpc_compress.hip")
 LIB = os.path.join(HERE, "_tpctrack.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -28,7 +29,7 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC, SRC_REQUESTS, SRC_COLLISIONS, SRC_CLUSTERIZE, SRC_SERVER, "-lpthread"]
+    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC, SRC_REQUESTS, SRC_COLLISIONS, SRC_CLUSTERIZE, SRC_COMPRESS, SRC_SERVER, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -409,3 +409,47 @@ class Clusterizer:
         b.n_rows = int(len(row_x))
         b.bz = float(bz)
         return b
+
+
+class Compressor:
+    """Outputs of tpc_compress for the clusters of a Tracker's last batch."""
+
+    def __init__(self, tracker: Tracker, params=None):
+        from . import make_compress_params
+        self.params = params if params is not None else make_compress_params()
+        self.tracker = tracker
+        self.device = tracker.device
+        d, n = self.device, max(1, tracker.max_n)
+        self.o_cls = torch.empty(n, dtype=torch.uint8, device=d)
+        self.o_code_y = torch.empty(n, dtype=torch.int32, device=d)
+        self.o_code_z = torch.empty(n, dtype=torch.int32, device=d)
+        self.o_hist = torch.zeros(4 * self.params.hist_half, dtype=torch.int64, device=d)
+        self.o_counts = torch.zeros(6, dtype=torch.int64, device=d)
+        self.o_status = torch.zeros(1, dtype=torch.int32, device=d)
+
+    def launch(self, batch: Batch, stream=None):
+        """Enqueue the codes of `batch`, the batch of the tracker's last call."""
+        from . import tpc_compress, tpc_compressed_t
+        o = tpc_compressed_t()
+        o.cls, o.code_y, o.code_z = _ptr(self.o_cls), _ptr(self.o_code_y), _ptr(self.o_code_z)
+        o.hist, o.counts, o.status = _ptr(self.o_hist), _ptr(self.o_counts), _ptr(self.o_status)
+        f = tpc_field_t()
+        f.bz_tesla = batch.bz
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = tpc_compress(batch.clusters_struct(), batch.geometry_struct(), f, self.tracker.tracks_struct(),
+                          self.params, o, s.cuda_stream)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_compress: %s" % tpc_status_string(st))
+        self._n = batch.n
+        return st
+
+    def result(self, sync=True):
+        if sync:
+            torch.cuda.synchronize(self.device)
+        st = int(self.o_status.item())
+        if st != TPC_OK:
+            raise TrackingError(st, "compression failed on the device: %s" % tpc_status_string(st))
+        n, h = self._n, self.params.hist_half
+        hist = self.o_hist.cpu().numpy()
+        return dict(cls=self.o_cls[:n], code_y=self.o_code_y[:n], code_z=self.o_code_z[:n],
+                    hist_y=hist[:2 * h], hist_z=hist[2 * h:], counts=self.o_counts.cpu().numpy())

@@ -79,17 +79,21 @@ def test_removal_cut_and_unattached_rounding():
 
 def test_unreachable_row_and_fragile_flag():
     """A track that turns back before the cluster's row is coded by position
-    (class 3); a code within eps of a half step is flagged."""
-    y = np.array([0.3, 5 * STEP + 0.5 * STEP], np.float32)
-    z = np.array([0.0, 0.0], np.float32)
-    row = np.array([150, 0], np.uint16)
-    ct = np.array([0, -1], np.int32)
-    params = np.array([[0.0, 0.0, 0.9, 0.0, -5.0]], np.float32)  # C = +0.0075/cm: sin(phi) passes 0.999 on the way
-    x_ref = np.array([synth.ROW_X_F32[0]], np.float32)
+    (class 3).  A residual code within eps of a half step on a row the helix
+    is carried to is flagged; one on the state's own plane (nothing carried)
+    and a position code (one correctly rounded quotient) never are."""
+    y = np.array([0.3, 5.5 * STEP, 1.0 + 2.5 * STEP, 1.0 + 2.5 * STEP], np.float32)
+    z = np.array([0.0, 0.0, 2.0, 2.0], np.float32)
+    row = np.array([150, 0, 10, 20], np.uint16)
+    ct = np.array([0, -1, 1, 1], np.int32)
+    params = np.array([[0.0, 0.0, 0.9, 0.0, -5.0],  # C = +0.0075/cm: sin(phi) passes 0.999 on the way
+                       [1.0, 2.0, 0.0, 0.0, 0.0]], np.float32)  # straight, along x
+    x_ref = np.array([synth.ROW_X_F32[0], synth.ROW_X_F32[10]], np.float32)
     r = oracle.compress(y, z, row, ct, params, x_ref, synth.ROW_X_F32, K, STEP, eps=1e-3)
-    assert r["cls"].tolist() == [3, 0]
+    assert r["cls"].tolist() == [3, 0, 1, 1]
     assert r["code_y"][0] == round(0.3 / STEP)
-    assert r["fragile"].tolist() == [0, 1]
+    assert r["code_y"][2:].tolist() == [2, 2]  # 2.5 steps from the line, half to even
+    assert r["fragile"].tolist() == [0, 0, 0, 1]
 
 
 def _entropy(codes):
