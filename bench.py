@@ -16,6 +16,9 @@ Prints ONE JSON line (rank 0).  Besides the contract fields it carries:
                 tracking and outside the timed step: the call's device time
                 (HIP graph replays) and its physics on the 50-collision frame
                 of the physical generator against MC truth;
+  compression   hit removal and track-model compression of the frame's
+                clusters after tracking: device time, HBM roofline, entropy
+                of the codes against plain positions;
   clusterizer   raw ADC digits of the frame's clusters to clusters, outside
                 the timed step: the call's device time, its HBM roofline and
                 the oracle on a sample of units.
@@ -61,6 +64,10 @@ COL_BYTES_PER_TRACK = 20 + 4 + 4 + 8 + 8 + 4 + 4 + 4
 # each pad's offset (8) read once, each cluster (y, z, pad, time 4 each, row
 # 2, qtot 4, qmax 2) written once
 CLU_BYTES_PER_DIGIT, CLU_BYTES_PER_PAD, CLU_BYTES_PER_CLUSTER = 4, 8, 24
+# hit removal and compression, algorithmic bytes: per cluster its position and
+# row (10) and track index (4) read, class and codes (9) written; per track
+# its state at x_ref (24) read once
+CMP_BYTES_PER_CLUSTER, CMP_BYTES_PER_TRACK = 23, 24
 COL_KERNEL_BYTES = {"k_col_clear": None, "k_col_zdca": 36, "k_col_flags": None, "k_col_number": None,
                     "k_col_assign": 20, "k_col_finish": None}
 SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
@@ -232,6 +239,22 @@ def summarize_profiles(prof_dir, workload):
                 COL_KERNEL_BYTES[k] or "-"))
             traffic[k] = dict(src_digest=col_digest(), bytes_per_launch=fb + wb, fetch_bytes=fb, write_bytes=wb,
                               avg_us=avg_us)
+    cmpr = run.get("compression")
+    if cmpr:
+        lines += ["", "hit removal and compression (tpc_compress) over the %d clusters of the frame" % cmpr["clusters"],
+                  "%-18s %6s %10s %10s %10s %8s %8s %8s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB",
+                                                             "B/clus", "GB/s", "alg_B/c")]
+        for k, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["totaldurationns"])):
+            if not k.startswith("k_cmp_"):
+                continue
+            avg_us = float(r["averagens"]) / 1e3
+            fb = fetch.get(k, 0.0) * 1024 / f_fac
+            wb = write.get(k, 0.0) * 1024 / w_fac
+            lines.append("%-18s %6s %10.1f %10.2f %10.2f %8.2f %8.0f %8s" % (
+                k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / cmpr["clusters"], (fb + wb) / 1e3 / avg_us,
+                CMP_BYTES_PER_CLUSTER if k == "k_cmp_codes" else "-"))
+            traffic[k] = dict(src_digest=col_digest("tpc_compress.hip"), bytes_per_launch=fb + wb,
+                              fetch_bytes=fb, write_bytes=wb, avg_us=avg_us)
     clu = run.get("clusterizer")
     if clu:
         nd = clu["digits"]
@@ -635,6 +658,74 @@ def collision_bench(dev, tr, ev, reps, workload):
     return out
 
 
+def _entropy_bits(counts):
+    import numpy as np
+    c = np.asarray(counts, np.float64)
+    c = c[c > 0]
+    p = c / c.sum()
+    return float(-(p * np.log2(p)).sum()) if len(p) else 0.0
+
+
+def compression_bench(dev, tr, batch, reps, workload):
+    """Hit removal and track-model compression (tpc_compress) of the tracker's
+    last batch: the call's device time from HIP graph replays, the HBM
+    roofline, and the entropy of the codes against that of plain positions."""
+    import numpy as np
+    import torch
+    from paper_2106_03636_amd import make_compress_params
+    from paper_2106_03636_amd.runtime import Compressor
+    cp = make_compress_params()
+    c = Compressor(tr, cp)
+    for _ in range(2):
+        c.launch(batch)
+    r = c.result()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        c.launch(batch)
+    torch.cuda.synchronize(dev)
+    graph.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    r2 = c.result()
+    if not np.array_equal(r2["counts"], r["counts"]):
+        raise RuntimeError("graph replay and eager call of the compression disagree")
+    del graph
+    n_tracks = int(tr.o_counts[0].item())
+    alg = CMP_BYTES_PER_CLUSTER * batch.n + CMP_BYTES_PER_TRACK * n_tracks
+    achieved = alg / (ms * 1e-3) / 1e9
+    # entropy of the codes (what an entropy coder would need) against plain positions
+    cls = r["cls"].cpu().numpy()
+    cy, cz = r["code_y"].cpu().numpy(), r["code_z"].cpu().numpy()
+    keep = cls != 2
+    step = float(np.float32(cp.step))
+    py = np.rint(batch.y.cpu().numpy().astype(np.float64) / step).astype(np.int64)
+    pz = np.rint(batch.z.cpu().numpy().astype(np.float64) / step).astype(np.int64)
+    h_pos = sum(_entropy_bits(np.unique(v[keep], return_counts=True)[1]) for v in (py, pz))
+    res = cls == 1
+    other = keep & ~res
+    h_res = _entropy_bits(r["hist_y"]) + _entropy_bits(r["hist_z"])
+    h_oth = sum(_entropy_bits(np.unique(v[other], return_counts=True)[1]) for v in (cy, cz)) if other.any() else 0.0
+    bits_model = (res.sum() * h_res + other.sum() * h_oth) / max(1, batch.n)
+    bits_plain = h_pos * keep.sum() / max(1, batch.n)
+    out = dict(workload=workload, clusters=int(batch.n), tracks=n_tracks, ms_per_call=ms,
+               clusters_per_s=batch.n / (ms * 1e-3), launches=2,
+               classes=dict(no_track=int(r["counts"][0]), residual=int(r["counts"][1]), removed=int(r["counts"][2]),
+                            no_model=int(r["counts"][3])),
+               removed_fraction=float(r["counts"][2]) / max(1, batch.n),
+               entropy_bits_per_cluster=dict(positions_of_kept=bits_plain, track_model=bits_model,
+                                             residual_y_z=h_res, raw_float_y_z=64.0),
+               roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=achieved / HBM_PEAK_GBS, algorithmic_bytes_per_launch=int(alg), traffic=None))
+    log("bench: compression " + json.dumps(out))
+    return out
+
+
 def clusterizer_bench(dev, ev, reps, workload, cpu_units=2):
     """Clusterizer (tpc_clusterize) on the raw ADC digits of `ev` (generated
     from its clusters): the call's device time from HIP graph replays, the
@@ -747,6 +838,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-sector comparison")
     ap.add_argument("--no-collisions", action="store_true", help="skip the collision-assignment measurement")
     ap.add_argument("--no-clusterizer", action="store_true", help="skip the clusterizer measurement")
+    ap.add_argument("--no-compression", action="store_true", help="skip the compression measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -914,6 +1006,8 @@ def main():
     for e in memory["vs_n"]:
         e["bytes_per_cluster"] = e["workspace_bytes"] / e["clusters"]
     log("bench: per-kernel ms " + json.dumps(per_kernel))
+    compression = None if args.no_compression else compression_bench(dev, tr, batch, max(20, args.steps),
+                                                                     args.workload)
     collisions = None if args.no_collisions else collision_bench(dev, tr, ev, max(50, args.steps), args.workload)
 
     out = dict(
@@ -935,6 +1029,8 @@ def main():
     )
     if collisions is not None:
         out["collisions"] = collisions
+    if compression is not None:
+        out["compression"] = compression
 
     # the plain form: one call per sector unit, same stream, same work
     if not args.no_plain:
