@@ -106,6 +106,8 @@ def _load():
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double] + [vp] * 12
         lib.orc_compress.restype = None
         lib.orc_compress.argtypes = [ctypes.c_int64] + [vp] * 7 + [ctypes.c_double] * 5 + [vp] * 4
+        lib.orc_refit_tracks.restype = None
+        lib.orc_refit_tracks.argtypes = [ctypes.c_int64] + [vp] * 7 + [ctypes.c_double, ctypes.POINTER(Params)] + [vp] * 9
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -328,3 +330,33 @@ def unpack_cov(c15):
             M[i, j] = M[j, i] = c15[k]
             k += 1
     return M
+
+
+def refit_tracks(first_hit, n_hits, hits, y, z, row, row_x, k, values: dict):
+    """Two-pass refit of selected tracks over their hit lists (see
+    orc_refit_tracks in tpc_oracle.c).  row_x as the tracker sees it (pass the
+    FP32 values to compare with FP32 code)."""
+    lib = _load()
+    first = np.ascontiguousarray(first_hit, np.int32)
+    nh = np.ascontiguousarray(n_hits, np.int32)
+    hits = np.ascontiguousarray(hits, np.int32)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    row = np.ascontiguousarray(row, np.uint16)
+    row_x = np.ascontiguousarray(row_x, np.float64)
+    T = len(nh)
+    assert len(first) == T
+    if T:
+        assert first.min() >= 0 and (first.astype(np.int64) + nh).max() <= len(hits)
+    if len(hits):
+        assert hits.min() >= 0 and hits.max() < len(y) and row[hits].max() < len(row_x)
+    P = make_params(values)
+    out = dict(p=np.zeros((T, 5)), cov=np.zeros((T, 15)), x_ref=np.zeros(T), chi2=np.zeros(T),
+               p_out=np.zeros((T, 5)), cov_out=np.zeros((T, 15)), x_out=np.zeros(T),
+               ok=np.zeros(T, np.int8), fragile=np.zeros(T, np.int8))
+    lib.orc_refit_tracks(T, first.ctypes.data, nh.ctypes.data, hits.ctypes.data, y.ctypes.data, z.ctypes.data,
+                         row.ctypes.data, row_x.ctypes.data, float(k), ctypes.byref(P),
+                         *[out[key].ctypes.data for key in ("p", "cov", "x_ref", "chi2", "p_out", "cov_out",
+                                                            "x_out", "ok", "fragile")])
+    return out
+

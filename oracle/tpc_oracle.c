@@ -672,12 +672,19 @@ done:
 /* ------------------------------------------------------------------------- */
 /* helpers exported for the pins                                               */
 
+/* The fit's arithmetic type (a build of this file that evaluates the fit in
+ * single precision turns it into float; the batch refit below the driver
+ * keeps its double interface either way). */
+typedef double fit_real;
+
 /* Two-pass fit of a fixed list of hits (no pickups): pass 1 from hit 0 to hit
  * n-1 starting from the three-point seed, pass 2 back from hit n-1 to hit 0
- * with the covariance reset.  Output at hit 0.  Returns 0 or -1. */
-int orc_fit_two_pass(int n, const double *x, const double *y, const double *z, double k,
-                     const orc_params_t *P, double p_out[5], double cov_out[15], double *chi2,
-                     double p1_out[5]) {
+ * with the covariance reset.  Output at hit 0; p1_out / cov1_out (each
+ * optional) receive pass 1's state at hit n-1; *fragile_out (optional) is set
+ * when a transport came within 1e-5 of the sin(phi) limit.  Returns 0 or -1. */
+static int fit_two_pass(int n, const fit_real *x, const fit_real *y, const fit_real *z, fit_real k,
+                        const orc_params_t *P, fit_real p_out[5], fit_real cov_out[15], fit_real *chi2,
+                        fit_real p1_out[5], fit_real cov1_out[15], int *fragile_out) {
   if (n < 3) return -1;
   double sx[3] = {x[0], x[n / 2], x[n - 1]}, sy[3] = {y[0], y[n / 2], y[n - 1]},
          sz[3] = {z[0], z[n / 2], z[n - 1]};
@@ -688,21 +695,35 @@ int orc_fit_two_pass(int n, const double *x, const double *y, const double *z, d
   s.x = x[0];
   s.chi2 = 0;
   for (int j = 0; j < n; ++j) {
-    if (j > 0 && step_to(&s, x[j], k, P, &fr) != 0) return -1;
+    if (j > 0 && step_to(&s, x[j], k, P, &fr) != 0) {
+      if (fragile_out) *fragile_out = fr;
+      return -1;
+    }
     kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
   }
   if (p1_out) memcpy(p1_out, s.p, sizeof(s.p));
+  if (cov1_out) pack_cov(s.cov, cov1_out);
   cov_init(s.cov, P);
   s.chi2 = 0;
   kf_update(s.p, s.cov, y[n - 1], z[n - 1], P->sigma_y, P->sigma_z, &s.chi2);
   for (int j = n - 2; j >= 0; --j) {
-    if (step_to(&s, x[j], k, P, &fr) != 0) return -1;
+    if (step_to(&s, x[j], k, P, &fr) != 0) {
+      if (fragile_out) *fragile_out = fr;
+      return -1;
+    }
     kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
   }
   memcpy(p_out, s.p, sizeof(s.p));
   if (cov_out) pack_cov(s.cov, cov_out);
   if (chi2) *chi2 = s.chi2;
+  if (fragile_out) *fragile_out = fr;
   return 0;
+}
+
+int orc_fit_two_pass(int n, const double *x, const double *y, const double *z, double k,
+                     const orc_params_t *P, double p_out[5], double cov_out[15], double *chi2,
+                     double p1_out[5]) {
+  return fit_two_pass(n, x, y, z, k, P, p_out, cov_out, chi2, p1_out, NULL, NULL);
 }
 
 int orc_kf_update(double p[5], double cov15[15], double my, double mz, double sy, double sz,
@@ -1331,6 +1352,52 @@ void orc_compress(int64_t n, const float *y, const float *z, const uint16_t *row
      * helix's rounding */
     const double fy = vy - floor(vy), fz = vz - floor(vz);
     fragile[c] = cls[c] == 1 && row_x[row[c]] != x_ref[t] && (fabs(fy - 0.5) < eps || fabs(fz - 0.5) < eps);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Refit of the selected tracks (the step after the selector, which may have
+ * taken hits away from a tracklet): track t's hits are the cluster ids
+ * hits[first[t] .. first[t] + nh[t]), in increasing row order.  Each hit is
+ * measured at x = row_x[row] with y and z in quanta of 1/256 cm, rounded half
+ * to even, as the tracker measures them; the fit is the two-pass fit of the
+ * helpers above (fit_two_pass).  Per track: ok = 1 when the fit succeeded
+ * (else every output is zero), the pass-2 state at the first hit (p_in,
+ * cov_in, x_in, chi2), the pass-1 state at the last hit (p_out, cov_out,
+ * x_out), and fragile = 1 when a transport came within 1e-5 of the sin(phi)
+ * limit. */
+void orc_refit_tracks(int64_t n_tracks, const int32_t *first, const int32_t *nh, const int32_t *hits,
+                      const float *y, const float *z, const uint16_t *row, const double *row_x, double k,
+                      const orc_params_t *P, double *p_in, double *cov_in, double *x_in, double *chi2,
+                      double *p_out, double *cov_out, double *x_out, int8_t *ok, int8_t *fragile) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    const int n = nh[t];
+    fit_real *X = (fit_real *)malloc(sizeof(fit_real) * 3 * (size_t)(n > 0 ? n : 1));
+    fit_real *Y = X + n, *Z = X + 2 * n;
+    for (int j = 0; j < n; ++j) {
+      const int32_t h = hits[first[t] + j];
+      X[j] = row_x[row[h]];
+      Y[j] = nearbyint(256.0 * (double)y[h]) / 256.0;
+      Z[j] = nearbyint(256.0 * (double)z[h]) / 256.0;
+    }
+    fit_real pi[5], ci[15], ch = 0, po[5], co[15];
+    int fr = 0;
+    const int st = fit_two_pass(n, X, Y, Z, (fit_real)k, P, pi, ci, &ch, po, co, &fr);
+    ok[t] = st == 0;
+    fragile[t] = (int8_t)fr;
+    for (int q = 0; q < 5; ++q) {
+      p_in[t * 5 + q] = st == 0 ? (double)pi[q] : 0.0;
+      p_out[t * 5 + q] = st == 0 ? (double)po[q] : 0.0;
+    }
+    for (int q = 0; q < 15; ++q) {
+      cov_in[t * 15 + q] = st == 0 ? (double)ci[q] : 0.0;
+      cov_out[t * 15 + q] = st == 0 ? (double)co[q] : 0.0;
+    }
+    chi2[t] = st == 0 ? (double)ch : 0.0;
+    x_in[t] = st == 0 ? (double)X[0] : 0.0;
+    x_out[t] = st == 0 ? (double)X[n - 1] : 0.0;
+    free(X);
   }
 }
 
