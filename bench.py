@@ -103,18 +103,18 @@ def make_workload(name, seed=None):
     return ev
 
 
-def col_digest(name="tpc_collisions.hip"):
+def col_digest(*names):
+    """Digest of kernel sources (default: the collision kernels)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2106_03636_amd", "csrc", name), "rb") as f:
-        h.update(f.read())
+    for name in names or ("tpc_collisions.hip",):
+        with open(os.path.join(ROOT, "paper_2106_03636_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def src_digest():
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2106_03636_amd", "csrc", "tpc_track.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+    """Digest of the tracker's kernel sources (its file and the filter header)."""
+    return col_digest("tpc_track.hip", "tpc_kalman.h")
 
 
 def measured_counters(kernel, workload):
@@ -255,6 +255,30 @@ def summarize_profiles(prof_dir, workload):
                 CMP_BYTES_PER_CLUSTER if k == "k_cmp_codes" else "-"))
             traffic[k] = dict(src_digest=col_digest("tpc_compress.hip"), bytes_per_launch=fb + wb,
                               fetch_bytes=fb, write_bytes=wb, avg_us=avg_us)
+    rft = run.get("refit")
+    if rft:
+        nt, nh = rft["tracks"], rft["track_hits"]
+        lines += ["", "track refit (tpc_refit_tracks) of the %d tracks (%d hits) of the frame" % (nt, nh),
+                  "%-18s %6s %10s %10s %10s %8s %8s %9s %9s %6s" % ("kernel", "calls", "avg_us", "fetch_MB",
+                                                                    "write_MB", "B/hit", "GB/s", "waves",
+                                                                    "valu/wave", "VALU%")]
+        for k, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["totaldurationns"])):
+            if not k.startswith("k_rf_"):
+                continue
+            avg_us = float(r["averagens"]) / 1e3
+            fb = fetch.get(k, 0.0) * 1024 / f_fac
+            wb = write.get(k, 0.0) * 1024 / w_fac
+            q = sq.get(k, {})
+            waves = q.get("SQ_WAVES", 0.0)
+            valu = q.get("SQ_INSTS_VALU", 0.0)
+            busy = 100.0 * valu * 4 / (avg_us * 1e-6 * N_SIMD * CLOCK_GHZ * 1e9) if avg_us else 0.0
+            lines.append("%-18s %6s %10.1f %10.2f %10.2f %8.2f %8.0f %9.0f %9.0f %6.1f" % (
+                k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / max(1, nh), (fb + wb) / 1e3 / avg_us,
+                waves, valu / waves if waves else 0.0, busy))
+            traffic[k] = dict(src_digest=col_digest("tpc_refit.hip", "tpc_kalman.h"), bytes_per_launch=fb + wb,
+                              fetch_bytes=fb, write_bytes=wb, avg_us=avg_us)
+            if q:
+                traffic[k].update(valu_insts=valu, valu_busy=busy / 100.0)
     clu = run.get("clusterizer")
     if clu:
         nd = clu["digits"]
@@ -726,6 +750,54 @@ def compression_bench(dev, tr, batch, reps, workload):
     return out
 
 
+def refit_bench(dev, tr, batch, reps, workload):
+    """Track refit (tpc_refit_tracks) of the tracker's last batch: the call's
+    device time from HIP graph replays, and its FP32 issue rate against the
+    vector peak at the method's operation count per Kalman hit update."""
+    import numpy as np
+    import torch
+    from paper_2106_03636_amd.runtime import Refitter
+    rf = Refitter(tr)
+    n_tracks = int(tr.o_counts[0].item())
+    n_hits = int(tr.o_counts[1].item())
+    for _ in range(2):
+        rf.launch(batch)
+    r = {k: v.cpu().numpy() for k, v in rf.result(n_tracks).items()}
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rf.launch(batch)
+    torch.cuda.synchronize(dev)
+    graph.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    r2 = {k: v.cpu().numpy() for k, v in rf.result(n_tracks).items()}
+    if not all(np.array_equal(r[k], r2[k]) for k in r):
+        raise RuntimeError("graph replay and eager call of the refit disagree")
+    del graph
+    ok = r["ok"].astype(bool)
+    nh = tr.o_n_hits[:n_tracks].cpu().numpy()
+    updates = int(2 * nh[ok].sum())  # every hit is updated once per pass
+    flops = updates * FIT_OPS_PER_UPDATE
+    tfs = flops / (ms * 1e-3) / 1e12
+    chi2_ndf = r["chi2"][ok] / np.maximum(1, 2 * nh[ok] - 5)
+    out = dict(workload=workload, tracks=n_tracks, track_hits=n_hits, ms_per_call=ms,
+               tracks_per_s=n_tracks / (ms * 1e-3), hits_per_s=n_hits / (ms * 1e-3), launches=5,
+               refitted_fraction=float(ok.mean()) if n_tracks else 0.0,
+               chi2_per_ndf_median=float(np.median(chi2_ndf)) if ok.any() else None,
+               roofline=dict(bound="alu", kernel="k_rf_fit (whole call timed)", achieved=tfs,
+                             peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tfs / FP32_PEAK_TFLOPS,
+                             hit_updates_per_launch=updates, ops_per_update=FIT_OPS_PER_UPDATE,
+                             algorithmic_flops_per_launch=flops, traffic=None))
+    log("bench: refit " + json.dumps(out))
+    return out
+
+
 def clusterizer_bench(dev, ev, reps, workload, cpu_units=2):
     """Clusterizer (tpc_clusterize) on the raw ADC digits of `ev` (generated
     from its clusters): the call's device time from HIP graph replays, the
@@ -839,6 +911,7 @@ def main():
     ap.add_argument("--no-collisions", action="store_true", help="skip the collision-assignment measurement")
     ap.add_argument("--no-clusterizer", action="store_true", help="skip the clusterizer measurement")
     ap.add_argument("--no-compression", action="store_true", help="skip the compression measurement")
+    ap.add_argument("--no-refit", action="store_true", help="skip the track refit measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -1009,6 +1082,7 @@ def main():
     compression = None if args.no_compression else compression_bench(dev, tr, batch, max(20, args.steps),
                                                                      args.workload)
     collisions = None if args.no_collisions else collision_bench(dev, tr, ev, max(50, args.steps), args.workload)
+    refit = None if args.no_refit else refit_bench(dev, tr, batch, max(20, args.steps), args.workload)
 
     out = dict(
         metric=METRIC, value=value, unit="clusters/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -1031,6 +1105,8 @@ def main():
         out["collisions"] = collisions
     if compression is not None:
         out["compression"] = compression
+    if refit is not None:
+        out["refit"] = refit
 
     # the plain form: one call per sector unit, same stream, same work
     if not args.no_plain:

@@ -382,6 +382,69 @@ int tpc_assign_collisions(const tpc_tracks_t *tracks, const int32_t *unit_side, 
                           const tpc_field_t *field, const tpc_collision_params_t *params,
                           tpc_collisions_t *out, void *workspace, size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------- */
+/* Track refit.  Synchronous processing needs full tracking (paper §2.1), at */
+/* a track resolution that matches offline reconstruction (§2.3).  A track's */
+/* parameters from tpc_track_sectors come from its tracklet's fit, over a    */
+/* hit set the selector may since have shrunk (hits owned by other           */
+/* tracklets leave the track).  This call fits every output track again     */
+/* over exactly the hits it kept, in the order of its hit list (increasing   */
+/* row):                                                                     */
+/*   - measurements: y and z of each hit's cluster in quanta of 1/256 cm     */
+/*     (rounded half to even), at x = row_x[row], errors sigma_y, sigma_z    */
+/*     of the tracking parameters;                                           */
+/*   - seed: the circle through the first, middle (index n/2) and last hit  */
+/*     gives C and sin(phi) at the first hit, tan(lambda) follows from the   */
+/*     z difference over the arc to the last hit;                            */
+/*   - pass 1: covariance diag(cov0), update at the first hit, then          */
+/*     transport and update at each later hit; its state at the last hit is  */
+/*     the outer state;                                                      */
+/*   - pass 2: covariance reset to diag(cov0), chi2 reset, update at the     */
+/*     last hit, then transport and update back to the first hit; its state */
+/*     there and its chi2 are the result;                                    */
+/*   - FP32 throughout, the tracker's transport, Jacobian and update, with   */
+/*     C = -0.00299792458f * bz * q/pT.                                      */
+/* A track with fewer than 3 hits, whose seed fails (coincident points, no   */
+/* circle through them, |sin(phi)| >= sinphi_max) or whose helix cannot      */
+/* reach a hit's x within |sin(phi)| < sinphi_max in either pass is not      */
+/* refitted: ok = 0 and all of its outputs are zero.                         */
+/* ------------------------------------------------------------------------- */
+
+/* Outputs (device pointers, allocated by the caller; the per-track arrays
+ * hold at least the tracking output's cap_tracks entries, entry t refers to
+ * track t). */
+typedef struct tpc_refit {
+  float *params;               /* [cap_tracks][5] y, z, sin(phi), tan(lambda), q/pT at x_ref */
+  float *cov;                  /* [cap_tracks][15] lower triangle, row-major */
+  float *x_ref;                /* [cap_tracks] x of the first (innermost) hit */
+  float *chi2;                 /* [cap_tracks] chi2 of pass 2 (ndf = 2 n_hits - 5) */
+  float *params_out;           /* [cap_tracks][5] outer state: pass 1 at x_out */
+  float *cov_out;              /* [cap_tracks][15] */
+  float *x_out;                /* [cap_tracks] x of the last (outermost) hit */
+  uint8_t *ok;                 /* [cap_tracks] 1 refitted, 0 not (above) */
+  int32_t *status;             /* [1] TPC_OK, the tracker's own status when that is not TPC_OK, or
+                                  TPC_E_INVALID (a track hit names no cluster of the batch or a
+                                  cluster outside |y|, |z| <= 8192, row < n_rows); outputs are
+                                  valid only with TPC_OK */
+} tpc_refit_t;
+
+/* Bytes of device workspace tpc_refit_tracks needs for an output of these
+ * capacities (host-only, pure; 0 on bad arguments). */
+size_t tpc_refit_workspace_size(int64_t cap_tracks, int64_t cap_hits);
+
+/* Refit the tracks of a tpc_track_sectors call: the same clusters, geometry,
+ * field and tracking parameters (sigma_y, sigma_z, cov0, sinphi_max are
+ * used), and that call's output (n_hits, first_hit, hits, counts and status
+ * read on the device, the capacities on the host).  Enqueued on `stream`
+ * after the tracking call; the workspace (aligned to 256 bytes) holds no
+ * state across calls.  Returns TPC_OK when the work was enqueued,
+ * TPC_E_INVALID on bad arguments (a null or misaligned workspace among them),
+ * TPC_E_NOMEM when the workspace is smaller than tpc_refit_workspace_size(),
+ * TPC_E_HIP on a launch failure. */
+int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry, const tpc_field_t *field,
+                     const tpc_params_t *params, const tpc_tracks_t *tracks, tpc_refit_t *out, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
 /* Intermediate arrays kept in the workspace after a call, for inspection and
  * tests.  Valid until the workspace is reused.  `what` selects the array:
  *   TPC_VIEW_PERM      int32 [n]  sorted position -> cluster id

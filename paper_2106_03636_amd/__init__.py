@@ -104,6 +104,11 @@ class tpc_compressed_t(ctypes.Structure):
     _fields_ = [("cls", _vp), ("code_y", _vp), ("code_z", _vp), ("hist", _vp), ("counts", _vp), ("status", _vp)]
 
 
+class tpc_refit_t(ctypes.Structure):
+    _fields_ = [("params", _vp), ("cov", _vp), ("x_ref", _vp), ("chi2", _vp), ("params_out", _vp),
+                ("cov_out", _vp), ("x_out", _vp), ("ok", _vp), ("status", _vp)]
+
+
 class tpc_view_t(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("count", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -156,6 +161,13 @@ def load_library():
         lib.tpc_compress.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
                                      ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_tracks_t),
                                      ctypes.POINTER(tpc_compress_params_t), ctypes.POINTER(tpc_compressed_t), _vp]
+        lib.tpc_refit_workspace_size.restype = ctypes.c_size_t
+        lib.tpc_refit_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64]
+        lib.tpc_refit_tracks.restype = ctypes.c_int
+        lib.tpc_refit_tracks.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
+                                         ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_params_t),
+                                         ctypes.POINTER(tpc_tracks_t), ctypes.POINTER(tpc_refit_t), _vp,
+                                         ctypes.c_size_t, _vp]
         lib.tpc_inspect.restype = ctypes.c_int
         lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
                                     ctypes.POINTER(tpc_params_t), _vp, ctypes.c_int,
@@ -252,6 +264,17 @@ def tpc_compress(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_
                                            ctypes.byref(tracks), ctypes.byref(params), ctypes.byref(out), stream))
 
 
+def tpc_refit_workspace_size(cap_tracks: int, cap_hits: int) -> int:
+    return int(load_library().tpc_refit_workspace_size(cap_tracks, cap_hits))
+
+
+def tpc_refit_tracks(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t, params: tpc_params_t,
+                     tracks: tpc_tracks_t, out: tpc_refit_t, workspace: int, workspace_bytes: int, stream: int) -> int:
+    return int(load_library().tpc_refit_tracks(ctypes.byref(clusters), ctypes.byref(geometry), ctypes.byref(field),
+                                               ctypes.byref(params), ctypes.byref(tracks), ctypes.byref(out),
+                                               workspace, workspace_bytes, stream))
+
+
 def make_compress_params(step=1.0 / 64, pt_remove=0.1, sinphi_max=0.999, hist_half=1024) -> tpc_compress_params_t:
     cp = tpc_compress_params_t()
     cp.step, cp.pt_remove, cp.sinphi_max, cp.hist_half = step, pt_remove, sinphi_max, int(hist_half)
@@ -287,7 +310,7 @@ def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, wor
 def __getattr__(name):
     # the torch-side helpers load on first use, so that importing the package
     # (e.g. for its parameter values) does not import torch
-    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer", "Compressor"):
+    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer", "Compressor", "Refitter"):
         from . import runtime
         return getattr(runtime, name)
     raise AttributeError(name)

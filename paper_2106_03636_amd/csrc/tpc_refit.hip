@@ -1,0 +1,315 @@
+// Track refit: every output track of a tracking call fitted again over
+// exactly the hits it kept (the paper's synchronous processing needs full
+// tracking, §2.1, at a resolution that matches offline reconstruction, §2.3).
+// The operation is stated with tpc_refit_tracks in include/tpc_track.h.
+//
+// Five launches on the caller's stream:
+//   k_rf_init    clear the length histogram, take over the tracking status;
+//   k_rf_hist    histogram of the tracks' hit counts (LDS per block);
+//   k_rf_scan    one block: bucket offsets, longest tracks first;
+//   k_rf_gather  per track hit: its row and its y, z in quanta, packed into
+//                one 64-bit record, in the order of the track's hit list, and
+//                the track's slot in the length order;
+//   k_rf_fit     one lane per track, in length order (so the lanes of a wave
+//                run loops of about the same length): seed, pass 1 forward,
+//                pass 2 backward; the covariance lives in LDS.
+// The gather turns three dependent random loads per hit (id, then y, z, row)
+// into one coalesced pass, after which each lane of the fit reads a
+// contiguous run of records.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "tpc_kalman.h"
+#include "tpc_track.h"
+
+namespace {
+
+using namespace tpc_kf;
+
+constexpr int TPB = 256;
+constexpr int FTB = 128;  // threads per block of the fit
+constexpr int NB = 256;   // length buckets (hit counts >= 255 share the last)
+constexpr int GATHER_BLOCKS = 4096;
+constexpr int FIT_BLOCKS = 4096;
+constexpr float KAPPA = 0.00299792458f;
+constexpr int QBIAS = 1 << 23;  // record fields hold Y + 2^23 and Z + 2^23 (24 bits each)
+
+struct RfArgs {
+  const float *y, *z;
+  const uint16_t *row;
+  int64_t n_clusters;
+  const float *row_x;
+  int32_t n_rows;
+  const int32_t *trk_status, *n_hits, *first_hit, *hits;
+  const int64_t *trk_counts;
+  int64_t cap_tracks, cap_hits;
+  float k, smx, sy2, sz2;
+  float cov0[5];
+  // outputs
+  float *par, *cov, *xref, *chi2, *par_out, *cov_out, *xout;
+  uint8_t *ok;
+  int32_t *status;
+  // workspace
+  int32_t *bucket;   // [NB] histogram, then running offsets
+  int32_t *order;    // [cap_tracks] slot -> track
+  uint64_t *rec;     // [cap_hits] packed (row, Y, Z)
+  int32_t *bad;      // [1] a hit record out of range
+};
+
+__device__ __forceinline__ int bucket_of(int n) {  // longest first
+  return NB - 1 - (n < 0 ? 0 : n < NB - 1 ? n : NB - 1);
+}
+// tracks and track hits of the tracking call, within the output capacities
+__device__ __forceinline__ int64_t n_tracks(const RfArgs &A) {
+  const int64_t T = A.trk_counts[0];
+  return T < A.cap_tracks ? T : A.cap_tracks;
+}
+__device__ __forceinline__ int64_t n_track_hits(const RfArgs &A) {
+  const int64_t H = A.trk_counts[1];
+  return H < A.cap_hits ? H : A.cap_hits;
+}
+
+__global__ void __launch_bounds__(TPB) k_rf_init(RfArgs A) {
+  const int i = threadIdx.x;
+  if (i == 0) {
+    *A.status = *A.trk_status;
+    *A.bad = 0;
+  }
+  if (i < NB) A.bucket[i] = 0;
+}
+
+__global__ void __launch_bounds__(TPB) k_rf_hist(RfArgs A) {
+  __shared__ int32_t h[NB];
+  if (*A.status != TPC_OK) return;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t T = n_tracks(A);
+  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB)
+    atomicAdd(&h[bucket_of(A.n_hits[t])], 1);
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&A.bucket[threadIdx.x], h[threadIdx.x]);
+}
+
+// exclusive scan of the NB bucket counts (one block of NB threads)
+__global__ void __launch_bounds__(NB) k_rf_scan(RfArgs A) {
+  __shared__ int32_t s[NB];
+  if (*A.status != TPC_OK) return;
+  const int i = threadIdx.x;
+  const int v = A.bucket[i];
+  s[i] = v;
+  __syncthreads();
+  for (int d = 1; d < NB; d <<= 1) {
+    const int a = i >= d ? s[i - d] : 0;
+    __syncthreads();
+    s[i] += a;
+    __syncthreads();
+  }
+  A.bucket[i] = s[i] - v;
+}
+
+__global__ void __launch_bounds__(TPB) k_rf_gather(RfArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t T = n_tracks(A), H = n_track_hits(A);
+  const int64_t stride = int64_t(gridDim.x) * TPB;
+  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += stride)
+    A.order[atomicAdd(&A.bucket[bucket_of(A.n_hits[t])], 1)] = int32_t(t);
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < H; i += stride) {
+    const int32_t h = A.hits[i];
+    uint64_t r = 0;
+    const bool in = h >= 0 && h < A.n_clusters && A.row[h] < A.n_rows && fabsf(A.y[h]) <= 8192.f &&
+                    fabsf(A.z[h]) <= 8192.f;  // |Y|, |Z| <= 2^21 quanta fit the 24-bit fields
+    if (in) {
+      const int Y = __float2int_rn(A.y[h] * 256.0f), Z = __float2int_rn(A.z[h] * 256.0f);
+      r = (uint64_t(A.row[h]) << 48) | (uint64_t(uint32_t(Y + QBIAS)) << 24) | uint64_t(uint32_t(Z + QBIAS));
+    } else {
+      atomicOr(A.bad, 1);
+    }
+    A.rec[i] = r;
+  }
+}
+
+struct Hit {
+  int row, Y, Z;
+};
+__device__ __forceinline__ Hit unpack(uint64_t r) {
+  Hit h;
+  h.row = int(r >> 48);
+  h.Y = int((r >> 24) & 0xFFFFFFu) - QBIAS;
+  h.Z = int(r & 0xFFFFFFu) - QBIAS;
+  return h;
+}
+
+// The state in absolute coordinates (the filter runs relative to the first
+// hit's quanta Yr, Zr), its covariance and x; zeros for a track not fitted.
+__device__ __forceinline__ void store(const KState &s, bool ok, int Yr, int Zr, float *p, float *c, float *x) {
+  p[0] = ok ? s.p[0] + float(Yr) * (1.f / 256.f) : 0.f;
+  p[1] = ok ? s.p[1] + float(Zr) * (1.f / 256.f) : 0.f;
+#pragma unroll
+  for (int q = 2; q < 5; ++q) p[q] = ok ? s.p[q] : 0.f;
+#pragma unroll
+  for (int q = 0; q < 15; ++q) c[q] = ok ? s.c[q * 64] : 0.f;
+  *x = ok ? s.x : 0.f;
+}
+
+__global__ void __launch_bounds__(FTB) k_rf_fit(RfArgs A) {
+  __shared__ float cov_lds[FTB * 15];  // per wave [15][64]: lanes side by side
+  if (*A.status != TPC_OK) return;
+  if (*A.bad) {  // every block sees the same flag; one writes the status
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.status = TPC_E_INVALID;
+    return;
+  }
+  const int64_t T = n_tracks(A);
+  KState s;
+  s.c = cov_lds + (threadIdx.x >> 6) * (15 * 64) + (threadIdx.x & 63);
+  const float k = A.k, smx = A.smx, sy2 = A.sy2, sz2 = A.sz2;
+  for (int64_t i0 = int64_t(blockIdx.x) * FTB; i0 < T; i0 += int64_t(gridDim.x) * FTB) {
+    const int64_t i = i0 + threadIdx.x;
+    if ((i & ~int64_t(63)) >= T) break;  // whole wave past the tracks (wave-uniform)
+    const bool valid = i < T;
+    const int32_t t = valid ? A.order[i] : 0;
+    const int n = valid ? A.n_hits[t] : 0;
+    const uint64_t *R = A.rec + (valid ? A.first_hit[t] : 0);
+    bool ok = valid && n >= 3;
+    int Yr = 0, Zr = 0;
+    if (ok) {
+      const Hit a = unpack(R[0]), m = unpack(R[n / 2]), b = unpack(R[n - 1]);
+      Yr = a.Y;
+      Zr = a.Z;
+      ok = seed3(s, A.row_x[a.row], A.row_x[m.row], A.row_x[b.row], float(m.Y - Yr) * (1.f / 256.f),
+                 float(b.Y - Yr) * (1.f / 256.f), float(b.Z - Zr) * (1.f / 256.f), k, smx, A.cov0);
+    }
+    if (ok) kf_update(s, 0.f, 0.f, sy2, sz2);  // the first hit is the reference
+    // pass 1: hits 1 .. n-1, the next record loaded ahead of the step
+    int nmax = ok ? n : 0;
+    for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, __shfl_xor(nmax, d));
+    uint64_t nxt = ok ? R[1] : 0;
+    for (int j = 1; j < nmax; ++j) {
+      const uint64_t cur = nxt;
+      if (ok && j + 1 < n) nxt = R[j + 1];
+      if (!ok || j >= n) continue;
+      const Hit h = unpack(cur);
+      const float xr = A.row_x[h.row];
+      Step st;
+      if (!step_prepare(s, xr, k, smx, st)) {
+        ok = false;
+        continue;
+      }
+      step_apply(s, st, xr, k);
+      upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
+    }
+    // outer state: the end of pass 1
+    if (valid) store(s, ok, Yr, Zr, A.par_out + int64_t(t) * 5, A.cov_out + int64_t(t) * 15, A.xout + t);
+    // pass 2: hits n-2 .. 0, the covariance reset
+    if (ok) {
+      cov_reset(s, A.cov0);
+      s.chi2 = 0.f;
+      const Hit h = unpack(R[n - 1]);
+      upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
+    }
+    nxt = ok ? R[n - 2] : 0;
+    for (int j = nmax - 2; j >= 0; --j) {
+      const bool mine = ok && j <= n - 2;
+      const uint64_t cur = nxt;
+      if (mine && j >= 1) nxt = R[j - 1];
+      if (!mine) continue;
+      const Hit h = unpack(cur);
+      const float xr = A.row_x[h.row];
+      Step st;
+      if (!step_prepare(s, xr, k, smx, st)) {
+        ok = false;
+        continue;
+      }
+      step_apply(s, st, xr, k);
+      upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
+    }
+    if (valid && !ok) store(s, false, 0, 0, A.par_out + int64_t(t) * 5, A.cov_out + int64_t(t) * 15, A.xout + t);
+    if (valid) {
+      A.ok[t] = ok ? 1 : 0;
+      store(s, ok, Yr, Zr, A.par + int64_t(t) * 5, A.cov + int64_t(t) * 15, A.xref + t);
+      A.chi2[t] = ok ? s.chi2 : 0.f;
+    }
+  }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" size_t tpc_refit_workspace_size(int64_t cap_tracks, int64_t cap_hits) {
+  if (cap_tracks < 0 || cap_hits < 0 || cap_tracks > (int64_t(1) << 31) || cap_hits > (int64_t(1) << 31)) return 0;
+  return align256(NB * 4 + 256) + align256(size_t(cap_tracks) * 4) + align256(size_t(cap_hits) * 8);
+}
+
+extern "C" int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry,
+                                const tpc_field_t *field, const tpc_params_t *params, const tpc_tracks_t *tracks,
+                                tpc_refit_t *out, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!clusters || !geometry || !field || !params || !tracks || !out) return TPC_E_INVALID;
+  if (clusters->n < 0 || clusters->n >= (int64_t(1) << 30) ||
+      (clusters->n > 0 && (!clusters->y || !clusters->z || !clusters->row)))
+    return TPC_E_INVALID;
+  if (geometry->n_rows < 3 || geometry->n_rows > 255 || !geometry->row_x) return TPC_E_INVALID;
+  if (!tracks->n_hits || !tracks->first_hit || !tracks->hits || !tracks->counts || !tracks->status ||
+      tracks->cap_tracks < 0 || tracks->cap_hits < 0)
+    return TPC_E_INVALID;
+  if (!isfinite(field->bz_tesla) || !(params->sinphi_max > 0.f) || !(params->sinphi_max < 1.f) ||
+      !(params->sigma_y > 0.f) || !(params->sigma_z > 0.f))
+    return TPC_E_INVALID;
+  for (int q = 0; q < 5; ++q)
+    if (!(params->cov0[q] > 0.f) || !isfinite(params->cov0[q])) return TPC_E_INVALID;
+  if (!out->params || !out->cov || !out->x_ref || !out->chi2 || !out->params_out || !out->cov_out ||
+      !out->x_out || !out->ok || !out->status)
+    return TPC_E_INVALID;
+  const size_t need = tpc_refit_workspace_size(tracks->cap_tracks, tracks->cap_hits);
+  if (need == 0) return TPC_E_INVALID;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return TPC_E_INVALID;
+  if (workspace_bytes < need) return TPC_E_NOMEM;
+  RfArgs A;
+  A.y = clusters->y;
+  A.z = clusters->z;
+  A.row = clusters->row;
+  A.n_clusters = clusters->n;
+  A.row_x = geometry->row_x;
+  A.n_rows = geometry->n_rows;
+  A.trk_status = tracks->status;
+  A.n_hits = tracks->n_hits;
+  A.first_hit = tracks->first_hit;
+  A.hits = tracks->hits;
+  A.trk_counts = tracks->counts;
+  A.cap_tracks = tracks->cap_tracks;
+  A.cap_hits = tracks->cap_hits;
+  A.k = -KAPPA * field->bz_tesla;  // the tracker's curvature constant
+  A.smx = params->sinphi_max;
+  A.sy2 = params->sigma_y * params->sigma_y;
+  A.sz2 = params->sigma_z * params->sigma_z;
+  for (int q = 0; q < 5; ++q) A.cov0[q] = params->cov0[q];
+  A.par = out->params;
+  A.cov = out->cov;
+  A.xref = out->x_ref;
+  A.chi2 = out->chi2;
+  A.par_out = out->params_out;
+  A.cov_out = out->cov_out;
+  A.xout = out->x_out;
+  A.ok = out->ok;
+  A.status = out->status;
+  char *w = static_cast<char *>(workspace);
+  A.bucket = reinterpret_cast<int32_t *>(w);
+  A.bad = A.bucket + NB;
+  w += align256(NB * 4 + 256);
+  A.order = reinterpret_cast<int32_t *>(w);
+  w += align256(size_t(tracks->cap_tracks) * 4);
+  A.rec = reinterpret_cast<uint64_t *>(w);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t tb = (tracks->cap_tracks + TPB - 1) / TPB;
+  const int64_t hb = (tracks->cap_hits + TPB - 1) / TPB;
+  const int64_t gb = hb > tb ? hb : tb;
+  const int64_t fb = (tracks->cap_tracks + FTB - 1) / FTB;
+  auto clamp = [](int64_t b, int64_t hi) { return unsigned(b < 1 ? 1 : (b > hi ? hi : b)); };
+  hipLaunchKernelGGL(k_rf_init, dim3(1), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_hist, dim3(clamp(tb, 1024)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_scan, dim3(1), dim3(NB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_gather, dim3(clamp(gb, GATHER_BLOCKS)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_fit, dim3(clamp(fb, FIT_BLOCKS)), dim3(FTB), 0, st, A);
+  return hipGetLastError() == hipSuccess ? TPC_OK : TPC_E_HIP;
+}

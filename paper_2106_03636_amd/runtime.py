@@ -453,3 +453,56 @@ class Compressor:
         hist = self.o_hist.cpu().numpy()
         return dict(cls=self.o_cls[:n], code_y=self.o_code_y[:n], code_z=self.o_code_z[:n],
                     hist_y=hist[:2 * h], hist_z=hist[2 * h:], counts=self.o_counts.cpu().numpy())
+
+
+class Refitter:
+    """Outputs of tpc_refit_tracks for the tracks of a Tracker's last batch."""
+
+    def __init__(self, tracker: Tracker):
+        from . import tpc_refit_workspace_size
+        self.tracker = tracker
+        self.device = d = tracker.device
+        T, H = max(1, tracker.cap_tracks), max(1, tracker.cap_hits)
+        self.o_params = torch.empty((T, 5), dtype=torch.float32, device=d)
+        self.o_cov = torch.empty((T, 15), dtype=torch.float32, device=d)
+        self.o_xref = torch.empty(T, dtype=torch.float32, device=d)
+        self.o_chi2 = torch.empty(T, dtype=torch.float32, device=d)
+        self.o_params_out = torch.empty((T, 5), dtype=torch.float32, device=d)
+        self.o_cov_out = torch.empty((T, 15), dtype=torch.float32, device=d)
+        self.o_xout = torch.empty(T, dtype=torch.float32, device=d)
+        self.o_ok = torch.empty(T, dtype=torch.uint8, device=d)
+        self.o_status = torch.zeros(1, dtype=torch.int32, device=d)
+        self.ws_bytes = tpc_refit_workspace_size(T, H)
+        if self.ws_bytes == 0:
+            raise ValueError("tpc_refit_workspace_size rejected capacities %d tracks, %d hits" % (T, H))
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d)
+
+    def launch(self, batch: Batch, stream=None):
+        """Enqueue the refit of the tracks of `batch`, the batch of the tracker's last call."""
+        from . import tpc_refit_t, tpc_refit_tracks
+        o = tpc_refit_t()
+        o.params, o.cov, o.x_ref, o.chi2 = _ptr(self.o_params), _ptr(self.o_cov), _ptr(self.o_xref), _ptr(self.o_chi2)
+        o.params_out, o.cov_out, o.x_out = _ptr(self.o_params_out), _ptr(self.o_cov_out), _ptr(self.o_xout)
+        o.ok, o.status = _ptr(self.o_ok), _ptr(self.o_status)
+        f = tpc_field_t()
+        f.bz_tesla = batch.bz
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = tpc_refit_tracks(batch.clusters_struct(), batch.geometry_struct(), f, self.tracker.params,
+                              self.tracker.tracks_struct(), o, self.workspace.data_ptr(), self.ws_bytes,
+                              s.cuda_stream)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_refit_tracks: %s" % tpc_status_string(st))
+        return st
+
+    def result(self, n_tracks: int, sync=True):
+        """Device tensors of the first n_tracks tracks (the tracker's result count)."""
+        if sync:
+            torch.cuda.synchronize(self.device)
+        st = int(self.o_status.item())
+        if st != TPC_OK:
+            raise TrackingError(st, "refit failed on the device: %s" % tpc_status_string(st))
+        T = n_tracks
+        return dict(params=self.o_params[:T], cov=self.o_cov[:T], x_ref=self.o_xref[:T], chi2=self.o_chi2[:T],
+                    params_out=self.o_params_out[:T], cov_out=self.o_cov_out[:T], x_out=self.o_xout[:T],
+                    ok=self.o_ok[:T])
+

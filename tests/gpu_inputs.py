@@ -1,0 +1,82 @@
+"""Inputs for the GPU stages downstream of the tracker that do not come from
+the GPU: track lists taken from the generator's truth or from the oracle's
+own tracker, uploaded into a tpc_tracks_t, so that the GPU stage and the
+oracle stage see identical inputs.  Used by the GPU tests only."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def truth_tracks(ev, min_hits=10):
+    """Hit lists of the generated particles: per (unit, particle) the clusters
+    in increasing row order, for the particles that cross every row of the
+    unit at most once (no second leg of a looper in the unit) and leave at
+    least min_hits clusters there.  Returns (first_hit, n_hits, hits, unit)."""
+    n_units = len(ev.unit_offsets) - 1
+    unit = np.repeat(np.arange(n_units, dtype=np.int64), np.diff(ev.unit_offsets))
+    ids = np.nonzero(ev.label >= 0)[0]
+    key = (unit[ids] << 40) | (ev.label[ids].astype(np.int64) << 8) | ev.row[ids].astype(np.int64)
+    o = np.argsort(key, kind="stable")
+    ids, key = ids[o], key[o]
+    grp = key >> 8
+    start = np.r_[0, np.nonzero(grp[1:] != grp[:-1])[0] + 1]
+    end = np.r_[start[1:], len(grp)]
+    dup = np.zeros(len(grp), bool)
+    dup[1:] = key[1:] == key[:-1]  # same (unit, particle, row)
+    has_dup = np.add.reduceat(dup.astype(np.int64), start) > 0 if len(start) else np.zeros(0, bool)
+    keep = (~has_dup) & (end - start >= min_hits)
+    s, e = start[keep], end[keep]
+    n_hits = (e - s).astype(np.int32)
+    first = np.r_[0, np.cumsum(n_hits)[:-1]].astype(np.int32) if len(n_hits) else np.zeros(0, np.int32)
+    hits = np.concatenate([ids[a:b] for a, b in zip(s, e)]).astype(np.int32) if len(s) else np.zeros(0, np.int32)
+    return first, n_hits, hits, (grp[s] >> 32).astype(np.int32)
+
+
+class DeviceTracks:
+    """A tpc_tracks_t over device copies of host arrays (a tracker's output
+    as far as the downstream stages read it).  Fields not given are zero-
+    filled arrays of the right size.  Stands in for a Tracker where the
+    runtime's stage classes take one (cap_tracks, cap_hits, device, params,
+    tracks_struct())."""
+
+    def __init__(self, n_clusters, first_hit=None, n_hits=None, hits=None, params=None, x_ref=None, unit=None,
+                 cluster_track=None, status=0, device="cuda"):
+        import torch
+
+        from paper_2106_03636_amd import make_params, tpc_tracks_t
+
+        def dev(a, dtype, n, width=1):
+            if a is None:
+                a = np.zeros((n, width) if width > 1 else n, dtype)
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype).reshape(-1)).to(device)
+            return t if t.numel() else torch.zeros(1, dtype=t.dtype, device=device)
+
+        T = len(n_hits) if n_hits is not None else (len(x_ref) if x_ref is not None else 0)
+        H = len(hits) if hits is not None else 0
+        self.T, self.H = T, H
+        self.cap_tracks, self.cap_hits, self.device = T, H, device
+        self.params = make_params()  # tracking parameters (the refit reads sigma, cov0, sinphi_max)
+        self.first_hit = dev(first_hit, np.int32, T)
+        self.n_hits = dev(n_hits, np.int32, T)
+        self.hits = dev(hits, np.int32, H)
+        self.track_params = dev(params, np.float32, T, 5)
+        self.cov = dev(None, np.float32, T, 15)
+        self.x_ref = dev(x_ref, np.float32, T)
+        self.chi2 = dev(None, np.float32, T)
+        self.unit = dev(unit, np.int32, T)
+        self.n_fit = dev(n_hits, np.int32, T)
+        self.cluster_track = dev(cluster_track if cluster_track is not None else np.full(n_clusters, -1),
+                                 np.int32, n_clusters)
+        self.counts = dev(np.array([T, H, 0, 0, 0]), np.int64, 5)
+        self.status = dev(np.array([status]), np.int32, 1)
+        s = tpc_tracks_t()
+        s.cap_tracks, s.cap_hits = T, H
+        for f in ("cluster_track", "cov", "x_ref", "chi2", "unit", "n_hits", "n_fit", "first_hit", "hits",
+                  "counts", "status"):
+            setattr(s, f, getattr(self, f).data_ptr())
+        s.params = self.track_params.data_ptr()
+        self.struct = s
+
+    def tracks_struct(self):
+        return self.struct
+

@@ -37,6 +37,8 @@ def test_struct_layouts_match_header(tmp_path):
                "tpc_collision_params_t": T.tpc_collision_params_t, "tpc_collisions_t": T.tpc_collisions_t,
                "tpc_pad_geometry_t": T.tpc_pad_geometry_t, "tpc_digits_t": T.tpc_digits_t,
                "tpc_clusterizer_params_t": T.tpc_clusterizer_params_t, "tpc_cluster_out_t": T.tpc_cluster_out_t,
+               "tpc_compress_params_t": T.tpc_compress_params_t, "tpc_compressed_t": T.tpc_compressed_t,
+               "tpc_refit_t": T.tpc_refit_t,
                "tpc_server_config_t": S.tpc_server_config_t, "tpc_request_t": S.tpc_request_t,
                "tpc_result_t": S.tpc_result_t, "tpc_server_stats_t": S.tpc_server_stats_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tpc_track.h"', 'int main(void){']
@@ -158,6 +160,33 @@ def test_clusterizer_host_checks():
     p.q_min = 10
     g.pad_width = 0.0
     assert T.tpc_clusterize(d, g, p, o, 0x8000, ws, 0) == T.TPC_E_INVALID
+
+
+def test_refit_host_checks():
+    """Workspace sizes and the arguments tpc_refit_tracks rejects before any
+    device work."""
+    ws = T.tpc_refit_workspace_size(1000, 50000)
+    assert ws >= 1000 * 4 + 50000 * 8
+    assert T.tpc_refit_workspace_size(1000, 40000) < ws and T.tpc_refit_workspace_size(0, 0) > 0
+    assert T.tpc_refit_workspace_size(-1, 10) == 0 and T.tpc_refit_workspace_size(10, 1 << 40) == 0
+    c, g, f, trk, out = T.tpc_clusters_t(), T.tpc_geometry_t(), T.tpc_field_t(), T.tpc_tracks_t(), T.tpc_refit_t()
+    p = T.make_params()
+    f.bz_tesla = 0.5
+    c.n, c.n_units, c.y, c.z, c.row = 100, 1, 0x1000, 0x1000, 0x1000
+    g.n_rows, g.row_x = 152, 0x1000
+    assert T.tpc_refit_tracks(c, g, f, p, trk, out, 0x8000, ws, 0) == T.TPC_E_INVALID
+    trk.cap_tracks, trk.cap_hits = 1000, 50000
+    trk.n_hits = trk.first_hit = trk.hits = trk.counts = trk.status = 0x2000
+    assert T.tpc_refit_tracks(c, g, f, p, trk, out, 0x8000, ws, 0) == T.TPC_E_INVALID  # no outputs
+    out.params = out.cov = out.x_ref = out.chi2 = out.params_out = out.cov_out = out.x_out = 0x3000
+    out.ok = out.status = 0x4000
+    assert T.tpc_refit_tracks(c, g, f, p, trk, out, 0x8001, ws, 0) == T.TPC_E_INVALID  # misaligned
+    assert T.tpc_refit_tracks(c, g, f, p, trk, out, 0, ws, 0) == T.TPC_E_INVALID
+    assert T.tpc_refit_tracks(c, g, f, p, trk, out, 0x8000, ws - 1, 0) == T.TPC_E_NOMEM
+    for bad in (dict(sinphi_max=1.0), dict(sigma_y=0.0), dict(cov0=[1.0, 1.0, 0.0, 1.0, 1.0])):
+        assert T.tpc_refit_tracks(c, g, f, T.make_params(**bad), trk, out, 0x8000, ws, 0) == T.TPC_E_INVALID, bad
+    g.n_rows = 2
+    assert T.tpc_refit_tracks(c, g, f, p, trk, out, 0x8000, ws, 0) == T.TPC_E_INVALID
 
 
 def test_status_strings():

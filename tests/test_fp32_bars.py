@@ -75,14 +75,24 @@ def _fp32_source(symmetric):
     return out
 
 
-def _build(tmp_path, symmetric):
-    name = "fp32_sym" if symmetric else "fp32_full"
+def _build(tmp_path, symmetric, fma=False):
+    """fma: let the compiler contract a * b + c into fused multiply-adds (the
+    GPU compiler does), another rounding order of the same operations."""
+    name = ("fp32_sym" if symmetric else "fp32_full") + ("_fma" if fma else "")
     c = tmp_path / (name + ".c")
     c.write_text(_fp32_source(symmetric))
     lib = tmp_path / (name + ".so")
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c11", "-D_POSIX_C_SOURCE=200809L", "-shared", "-fPIC",
-                           "-ffp-contract=off", "-w", "-o", str(lib), str(c), "-lm"])
+    contract = ["-ffp-contract=fast", "-mfma"] if fma else ["-ffp-contract=off"]
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c11", "-D_POSIX_C_SOURCE=200809L", "-shared", "-fPIC"]
+                          + contract + ["-w", "-o", str(lib), str(c), "-lm"])
     return str(lib)
+
+
+def _cpu_has_fma():
+    try:
+        return " fma " in " %s " % " ".join(l for l in open("/proc/cpuinfo") if l.startswith("flags"))
+    except OSError:
+        return False
 
 
 def _run_with(lib, ev):
@@ -168,3 +178,62 @@ def test_relative_clause_is_the_north_star_figure(tails):
     its state relative to exact integer references."""
     assert parity.PARAM_RTOL == 1e-4 and parity.MIN_WITHIN_FRACTION == 0.999
     assert _worst(tails, "within_1e4", min) < 0.95
+
+
+# ----------------------------------------------------------------------------
+# the refit's covariance clauses (parity.REFIT_*)
+
+def _refit_with(lib, ev, o):
+    import synth
+    saved = (oracle._LIB, oracle._lib)
+    if lib:
+        oracle._LIB, oracle._lib = lib, None
+    try:
+        k = float(np.float32(-np.float32(synth.KAPPA) * np.float32(ev.bz)))
+        return oracle.refit_tracks(o["track_first_hit"], o["track_n_hits"], o["track_hits"], ev.y, ev.z, ev.row,
+                                   ev.row_x.astype(np.float64), k, P)
+    finally:
+        oracle._LIB, oracle._lib = saved
+
+
+@pytest.fixture(scope="module")
+def refit_tails(tmp_path_factory):
+    """Covariance deviations of FP32 builds of the oracle's refit from its
+    FP64 refit, over the tracks of the 50-collision frame (the oracle
+    tracker's): per build, inner (pass 2) and outer (pass 1) states."""
+    tmp = tmp_path_factory.mktemp("fp32_refit")
+    ev = cached_event("pbpb_timeframe_50")
+    o = cached_oracle("pbpb_timeframe_50")
+    r64 = _refit_with(None, ev, o)
+    cov0 = np.array([float(np.float32(v)) for v in P["cov0"]])
+    out = {}
+    for sym in (False, True):
+        for fma in ((False, True) if _cpu_has_fma() else (False,)):
+            r32 = _refit_with(_build(tmp, sym, fma), ev, o)
+            both = r64["ok"].astype(bool) & r32["ok"].astype(bool)
+            for end, key in (("inner", "cov"), ("outer", "cov_out")):
+                oc = r64[key][both][:, DIAG]
+                gc = r32[key][both][:, DIAG].astype(np.float32).astype(np.float64)
+                crel_el = np.abs(gc - oc) / np.abs(oc)
+                crel = crel_el.max(axis=1)
+                big = crel_el > parity.COV_RTOL_MID
+                cond = parity.FP32_EPS * cov0[None, :] / np.abs(oc)
+                out[(sym, fma, end)] = dict(
+                    n=int(both.sum()), within_1e3=float((crel <= parity.COV_RTOL).mean()),
+                    within_1e2=float((crel <= parity.COV_RTOL_MID).mean()),
+                    cond_ratio=float((crel_el[big] / cond[big]).max(initial=0.0)))
+    print("FP32 refit covariance tails:", out)
+    return out
+
+
+def test_refit_covariance_clauses_admit_fp32_and_are_no_looser(refit_tails):
+    """Each refit clause admits the worst FP32 build and is at most the
+    tracklet clauses' margins (1.1x, 1.5x, 1.05x) beyond it."""
+    assert all(t["n"] > 300000 for t in refit_tails.values())
+    short = 1.0 - min(t["within_1e3"] for t in refit_tails.values())
+    assert short <= 1.0 - parity.REFIT_MIN_COV_FRACTION <= 1.1 * short
+    short_mid = 1.0 - min(t["within_1e2"] for t in refit_tails.values())
+    assert short_mid <= 1.0 - parity.REFIT_MIN_COV_MID_FRACTION <= 1.5 * short_mid
+    ratio = max(t["cond_ratio"] for t in refit_tails.values())
+    assert ratio <= parity.REFIT_COV_COND_K <= 1.05 * ratio
+
