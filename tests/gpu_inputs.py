@@ -54,7 +54,7 @@ class DeviceTracks:
         T = len(n_hits) if n_hits is not None else (len(x_ref) if x_ref is not None else 0)
         H = len(hits) if hits is not None else 0
         self.T, self.H = T, H
-        self.cap_tracks, self.cap_hits, self.device = T, H, device
+        self.cap_tracks, self.cap_hits, self.device, self.max_n = T, H, device, n_clusters
         self.params = make_params()  # tracking parameters (the refit reads sigma, cov0, sinphi_max)
         self.first_hit = dev(first_hit, np.int32, T)
         self.n_hits = dev(n_hits, np.int32, T)
@@ -68,6 +68,7 @@ class DeviceTracks:
         self.cluster_track = dev(cluster_track if cluster_track is not None else np.full(n_clusters, -1),
                                  np.int32, n_clusters)
         self.counts = dev(np.array([T, H, 0, 0, 0]), np.int64, 5)
+        self.o_counts = self.counts  # the name a Tracker gives it
         self.status = dev(np.array([status]), np.int32, 1)
         s = tpc_tracks_t()
         s.cap_tracks, s.cap_hits = T, H
@@ -79,4 +80,13 @@ class DeviceTracks:
 
     def tracks_struct(self):
         return self.struct
+
+    @classmethod
+    def from_oracle(cls, o, device="cuda"):
+        """The output tracks of an oracle tracking run (oracle.run / run_event),
+        their FP64 states rounded to FP32 as a tracking call stores them."""
+        tl = o["track_tracklet"]
+        return cls(int(o["n"]), o["track_first_hit"], o["track_n_hits"], o["track_hits"],
+                   params=o["trk_params"][tl].astype(np.float32), x_ref=o["trk_xref"][tl].astype(np.float32),
+                   unit=o["trk_unit"][tl], cluster_track=o["cluster_track"], device=device)
 
