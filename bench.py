@@ -787,7 +787,7 @@ def refit_bench(dev, tr, batch, reps, workload):
     tfs = flops / (ms * 1e-3) / 1e12
     chi2_ndf = r["chi2"][ok] / np.maximum(1, 2 * nh[ok] - 5)
     out = dict(workload=workload, tracks=n_tracks, track_hits=n_hits, ms_per_call=ms,
-               tracks_per_s=n_tracks / (ms * 1e-3), hits_per_s=n_hits / (ms * 1e-3), launches=5,
+               tracks_per_s=n_tracks / (ms * 1e-3), hits_per_s=n_hits / (ms * 1e-3), launches=7,
                refitted_fraction=float(ok.mean()) if n_tracks else 0.0,
                chi2_per_ndf_median=float(np.median(chi2_ndf)) if ok.any() else None,
                roofline=dict(bound="alu", kernel="k_rf_fit (whole call timed)", achieved=tfs,

@@ -428,9 +428,10 @@ typedef struct tpc_refit {
                                   valid only with TPC_OK */
 } tpc_refit_t;
 
-/* Bytes of device workspace tpc_refit_tracks needs for an output of these
- * capacities (host-only, pure; 0 on bad arguments). */
-size_t tpc_refit_workspace_size(int64_t cap_tracks, int64_t cap_hits);
+/* Bytes of device workspace tpc_refit_tracks needs for a batch of n_clusters
+ * clusters and an output of these capacities (host-only, pure; 0 on bad
+ * arguments). */
+size_t tpc_refit_workspace_size(int64_t n_clusters, int64_t cap_tracks, int64_t cap_hits);
 
 /* Refit the tracks of a tpc_track_sectors call: the same clusters, geometry,
  * field and tracking parameters (sigma_y, sigma_z, cov0, sinphi_max are

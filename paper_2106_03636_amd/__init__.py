@@ -162,7 +162,7 @@ def load_library():
                                      ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_tracks_t),
                                      ctypes.POINTER(tpc_compress_params_t), ctypes.POINTER(tpc_compressed_t), _vp]
         lib.tpc_refit_workspace_size.restype = ctypes.c_size_t
-        lib.tpc_refit_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64]
+        lib.tpc_refit_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
         lib.tpc_refit_tracks.restype = ctypes.c_int
         lib.tpc_refit_tracks.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
                                          ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_params_t),
@@ -264,8 +264,8 @@ def tpc_compress(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_
                                            ctypes.byref(tracks), ctypes.byref(params), ctypes.byref(out), stream))
 
 
-def tpc_refit_workspace_size(cap_tracks: int, cap_hits: int) -> int:
-    return int(load_library().tpc_refit_workspace_size(cap_tracks, cap_hits))
+def tpc_refit_workspace_size(n_clusters: int, cap_tracks: int, cap_hits: int) -> int:
+    return int(load_library().tpc_refit_workspace_size(n_clusters, cap_tracks, cap_hits))
 
 
 def tpc_refit_tracks(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t, params: tpc_params_t,

@@ -4,8 +4,8 @@
 #include <math.h>
 
 // The FP32 Kalman filter shared by the tracklet constructor (tpc_track.hip)
-// and the track refit (tpc_refit.hip): one track per lane, the covariance in
-// LDS.  Internal header of the library.
+// and the track refit (tpc_refit.hip): one track per lane.  Internal header of
+// the library.
 //
 // State at plane x: (y, z, sin(phi), tan(lambda), q/pT); curvature C = k q/pT.
 // Exact helix transport: sin2 = sin1 + C dx, dy = dx (sin1+sin2)/(cos1+cos2),
@@ -14,12 +14,23 @@
 
 namespace tpc_kf {
 
+// Two forms of the state, which differ only in where the covariance (lower
+// triangle, row-major, 15 entries) lives: KState keeps it in LDS, entry k at
+// c[k * 64] (the lane's column of a [15][64] block, so the lanes of a wave
+// hit distinct banks); KStateR keeps it in registers.  The functions below
+// take either and reach entry k through cv(s, k).
 struct KState {
   float p[5];
-  float *c;  // covariance, lower triangle, row-major: element k at c[k * 64]
-             // (the lane's column of a [15][64] block of LDS)
+  float *c;
   float x, chi2;
 };
+struct KStateR {
+  float p[5];
+  float c[15];
+  float x, chi2;
+};
+__device__ __forceinline__ float &cv(KState &s, int k) { return s.c[k * 64]; }
+__device__ __forceinline__ float &cv(KStateR &s, int k) { return s.c[k]; }
 
 __device__ __forceinline__ float asin_over(float u) {  // asin(u)/u
   const float u2 = u * u;
@@ -38,7 +49,8 @@ struct Step {
   float dx, C, s1, s2, c1, c2, D, N, iD, dy, L, u, fu, sT, sg;
 };
 
-__device__ __forceinline__ bool step_prepare(const KState &s, float x2, float k, float sinmax, Step &t) {
+template <class S>
+__device__ __forceinline__ bool step_prepare(const S &s, float x2, float k, float sinmax, Step &t) {
   t.dx = x2 - s.x;
   t.C = k * s.p[4];
   t.s1 = s.p[2];
@@ -61,7 +73,8 @@ __device__ __forceinline__ bool step_prepare(const KState &s, float x2, float k,
 
 // Apply a prepared step: parameters, and the covariance through the analytic
 // Jacobian.
-__device__ __forceinline__ void step_apply(KState &s, const Step &t, float x2, float k) {
+template <class S>
+__device__ __forceinline__ void step_apply(S &s, const Step &t, float x2, float k) {
   const float dx = t.dx, s1 = t.s1, s2 = t.s2, c1 = t.c1, c2 = t.c2, D = t.D, N = t.N, iD = t.iD;
   const float dy = t.dy, L = t.L, u = t.u, fu = t.fu, sT = t.sT, sg = t.sg, C = t.C;
   const float tgl = s.p[3];
@@ -80,10 +93,9 @@ __device__ __forceinline__ void step_apply(KState &s, const Step &t, float x2, f
   s.p[2] = s2;
   s.x = x2;
   // cov <- F cov F^T, F = I + {(0,2)=a, (0,4)=b, (1,2)=cc, (1,3)=d, (1,4)=e, (2,4)=f}
-  float *c = s.c;
-  const float P00 = c[0], P10 = c[64], P11 = c[128], P20 = c[192], P21 = c[256], P22 = c[320], P30 = c[384],
-              P31 = c[448], P32 = c[512], P33 = c[576], P40 = c[640], P41 = c[704], P42 = c[768],
-              P43 = c[832], P44 = c[896];
+  const float P00 = cv(s, 0), P10 = cv(s, 1), P11 = cv(s, 2), P20 = cv(s, 3), P21 = cv(s, 4),
+              P22 = cv(s, 5), P30 = cv(s, 6), P31 = cv(s, 7), P32 = cv(s, 8), P33 = cv(s, 9),
+              P40 = cv(s, 10), P41 = cv(s, 11), P42 = cv(s, 12), P43 = cv(s, 13), P44 = cv(s, 14);
   // T = F P, rows 0..2
   const float T00 = P00 + a * P20 + b * P40, T02 = P20 + a * P22 + b * P42,
               T04 = P40 + a * P42 + b * P44;
@@ -92,30 +104,29 @@ __device__ __forceinline__ void step_apply(KState &s, const Step &t, float x2, f
               T14 = P41 + cc * P42 + d * P43 + e * P44;
   const float T20 = P20 + f * P40, T21 = P21 + f * P41, T22 = P22 + f * P42, T23 = P32 + f * P43,
               T24 = P42 + f * P44;
-  c[0] = T00 + a * T02 + b * T04;
-  c[64] = T10 + a * T12 + b * T14;
-  c[128] = T11 + cc * T12 + d * T13 + e * T14;
-  c[192] = T20 + a * T22 + b * T24;
-  c[256] = T21 + cc * T22 + d * T23 + e * T24;
-  c[320] = T22 + f * T24;
-  c[384] = P30 + a * P32 + b * P43;
-  c[448] = P31 + cc * P32 + d * P33 + e * P43;
-  c[512] = P32 + f * P43;
-  c[640] = P40 + a * P42 + b * P44;
-  c[704] = P41 + cc * P42 + d * P43 + e * P44;
-  c[768] = P42 + f * P44;
+  cv(s, 0) = T00 + a * T02 + b * T04;
+  cv(s, 1) = T10 + a * T12 + b * T14;
+  cv(s, 2) = T11 + cc * T12 + d * T13 + e * T14;
+  cv(s, 3) = T20 + a * T22 + b * T24;
+  cv(s, 4) = T21 + cc * T22 + d * T23 + e * T24;
+  cv(s, 5) = T22 + f * T24;
+  cv(s, 6) = P30 + a * P32 + b * P43;
+  cv(s, 7) = P31 + cc * P32 + d * P33 + e * P43;
+  cv(s, 8) = P32 + f * P43;
+  cv(s, 10) = P40 + a * P42 + b * P44;
+  cv(s, 11) = P41 + cc * P42 + d * P43 + e * P44;
+  cv(s, 12) = P42 + f * P44;
 }
 
-
-__device__ __forceinline__ void kf_update(KState &s, float my, float mz, float sy2, float sz2) {
-  float *c = s.c;
+template <class S>
+__device__ __forceinline__ void kf_update(S &s, float my, float mz, float sy2, float sz2) {
   const float r0 = my - s.p[0], r1 = mz - s.p[1];
-  const float S00 = c[0] + sy2, S01 = c[64], S11 = c[128] + sz2;
+  const float S00 = cv(s, 0) + sy2, S01 = cv(s, 1), S11 = cv(s, 2) + sz2;
   const float idet = 1.f / (S00 * S11 - S01 * S01);
   const float I00 = S11 * idet, I01 = -S01 * idet, I11 = S00 * idet;
   // columns 0 and 1 of P (P_i0, P_i1)
-  const float q0[5] = {c[0], c[64], c[192], c[384], c[640]};
-  const float q1[5] = {c[64], c[128], c[256], c[448], c[704]};
+  const float q0[5] = {cv(s, 0), cv(s, 1), cv(s, 3), cv(s, 6), cv(s, 10)};
+  const float q1[5] = {cv(s, 1), cv(s, 2), cv(s, 4), cv(s, 7), cv(s, 11)};
   float K0[5], K1[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -127,22 +138,24 @@ __device__ __forceinline__ void kf_update(KState &s, float my, float mz, float s
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j, ++k) c[k * 64] -= K0[i] * q0[j] + K1[i] * q1[j];
+    for (int j = 0; j <= i; ++j, ++k) cv(s, k) -= K0[i] * q0[j] + K1[i] * q1[j];
   s.chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
 }
 
-__device__ __forceinline__ void cov_reset(KState &s, const float *cov0) {
+template <class S>
+__device__ __forceinline__ void cov_reset(S &s, const float *cov0) {
 #pragma unroll
-  for (int i = 0; i < 15; ++i) s.c[i * 64] = 0.f;
-  s.c[0] = cov0[0];
-  s.c[2 * 64] = cov0[1];
-  s.c[5 * 64] = cov0[2];
-  s.c[9 * 64] = cov0[3];
-  s.c[14 * 64] = cov0[4];
+  for (int i = 0; i < 15; ++i) cv(s, i) = 0.f;
+  cv(s, 0) = cov0[0];
+  cv(s, 2) = cov0[1];
+  cv(s, 5) = cov0[2];
+  cv(s, 9) = cov0[3];
+  cv(s, 14) = cov0[4];
 }
 
 // measurement of hit h relative to the reference (exact: integer difference)
-__device__ __forceinline__ void upd_hit(KState &s, int2 yz, int Yr, int Zr, float sy2, float sz2) {
+template <class S>
+__device__ __forceinline__ void upd_hit(S &s, int2 yz, int Yr, int Zr, float sy2, float sz2) {
   kf_update(s, float(yz.x - Yr) * (1.f / 256.f), float(yz.y - Zr) * (1.f / 256.f), sy2, sz2);
 }
 
@@ -152,7 +165,8 @@ __device__ __forceinline__ void upd_hit(KState &s, int2 yz, int Yr, int Zr, floa
 // relative to the first point.  The state starts at x0 with the diagonal
 // covariance cov0.  False when the points are not distinct, the circle cannot
 // join them or |sin(phi)| reaches smx.
-__device__ __forceinline__ bool seed3(KState &s, float x0, float x1, float x2, float y1, float y2, float z2,
+template <class S>
+__device__ __forceinline__ bool seed3(S &s, float x0, float x1, float x2, float y1, float y2, float z2,
                                       float k, float smx, const float *cov0) {
   const float ax = x1 - x0, ay = y1, bx = x2 - x0, by = y2, cx = x2 - x1, cy = y2 - y1;
   const float d12 = sqrtf(ax * ax + ay * ay), d13 = sqrtf(bx * bx + by * by), d23 = sqrtf(cx * cx + cy * cy);

@@ -3,19 +3,23 @@
 // tracking, §2.1, at a resolution that matches offline reconstruction, §2.3).
 // The operation is stated with tpc_refit_tracks in include/tpc_track.h.
 //
-// Five launches on the caller's stream:
+// Seven launches on the caller's stream:
 //   k_rf_init    clear the length histogram, take over the tracking status;
+//   k_rf_pack    per cluster (coalesced): its row and its y, z in quanta,
+//                packed into one 64-bit record;
 //   k_rf_hist    histogram of the tracks' hit counts (LDS per block);
 //   k_rf_scan    one block: bucket offsets, longest tracks first;
-//   k_rf_gather  per track hit: its row and its y, z in quanta, packed into
-//                one 64-bit record, in the order of the track's hit list, and
-//                the track's slot in the length order;
+//   k_rf_order   each track's slot in the length order (one global atomic
+//                per block and bucket, the slots inside a block from LDS);
+//   k_rf_gather  per track hit: its cluster's record, in the order of the
+//                track's hit list (one random 8-byte read per hit);
 //   k_rf_fit     one lane per track, in length order (so the lanes of a wave
 //                run loops of about the same length): seed, pass 1 forward,
-//                pass 2 backward; the covariance lives in LDS.
-// The gather turns three dependent random loads per hit (id, then y, z, row)
-// into one coalesced pass, after which each lane of the fit reads a
-// contiguous run of records.
+//                pass 2 backward; state and covariance stay in registers.
+// Clusters are in no particular order, so a track's hits are scattered over
+// the cluster arrays: the pack turns three random reads per hit (y, z, row,
+// each a cache line for 2 or 4 bytes) into one, and after the gather each
+// lane of the fit reads a contiguous run of records.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -54,9 +58,12 @@ struct RfArgs {
   // workspace
   int32_t *bucket;   // [NB] histogram, then running offsets
   int32_t *order;    // [cap_tracks] slot -> track
-  uint64_t *rec;     // [cap_hits] packed (row, Y, Z)
-  int32_t *bad;      // [1] a hit record out of range
+  uint64_t *cl;      // [n_clusters] packed (row, Y, Z) per cluster, NO_REC when out of range
+  uint64_t *rec;     // [cap_hits] packed (row, Y, Z) per track hit
+  int32_t *bad;      // [1] a track hit names no cluster, or one out of range
 };
+
+constexpr uint64_t NO_REC = ~uint64_t(0);  // row field 0xFFFF: never a valid row
 
 __device__ __forceinline__ int bucket_of(int n) {  // longest first
   return NB - 1 - (n < 0 ? 0 : n < NB - 1 ? n : NB - 1);
@@ -109,22 +116,51 @@ __global__ void __launch_bounds__(NB) k_rf_scan(RfArgs A) {
   A.bucket[i] = s[i] - v;
 }
 
+__global__ void __launch_bounds__(TPB) k_rf_pack(RfArgs A) {
+  if (*A.status != TPC_OK) return;
+  for (int64_t c = int64_t(blockIdx.x) * TPB + threadIdx.x; c < A.n_clusters; c += int64_t(gridDim.x) * TPB) {
+    const int r = A.row[c];
+    const float y = A.y[c], z = A.z[c];
+    uint64_t v = NO_REC;
+    if (r < A.n_rows && fabsf(y) <= 8192.f && fabsf(z) <= 8192.f) {  // |Y|, |Z| <= 2^21 fit the 24-bit fields
+      const int Y = __float2int_rn(y * 256.0f), Z = __float2int_rn(z * 256.0f);
+      v = (uint64_t(r) << 48) | (uint64_t(uint32_t(Y + QBIAS)) << 24) | uint64_t(uint32_t(Z + QBIAS));
+    }
+    A.cl[c] = v;
+  }
+}
+
+// Slots of the length order: per block of TPB tracks, the tracks of each
+// bucket count themselves in LDS, one thread per bucket reserves the block's
+// range with one global atomic, and each track takes base + its LDS rank.
+__global__ void __launch_bounds__(TPB) k_rf_order(RfArgs A) {
+  static_assert(TPB == NB, "one thread per bucket");
+  __shared__ int32_t cnt[NB], base[NB];
+  if (*A.status != TPC_OK) return;
+  const int64_t T = n_tracks(A);
+  for (int64_t t0 = int64_t(blockIdx.x) * TPB; t0 < T; t0 += int64_t(gridDim.x) * TPB) {  // block-uniform
+    const int64_t t = t0 + threadIdx.x;
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int b = t < T ? bucket_of(A.n_hits[t]) : -1;
+    const int rank = b >= 0 ? atomicAdd(&cnt[b], 1) : 0;
+    __syncthreads();
+    if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&A.bucket[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (b >= 0) A.order[base[b] + rank] = int32_t(t);
+    __syncthreads();  // cnt and base are reused by the next chunk
+  }
+}
+
 __global__ void __launch_bounds__(TPB) k_rf_gather(RfArgs A) {
   if (*A.status != TPC_OK) return;
-  const int64_t T = n_tracks(A), H = n_track_hits(A);
-  const int64_t stride = int64_t(gridDim.x) * TPB;
-  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += stride)
-    A.order[atomicAdd(&A.bucket[bucket_of(A.n_hits[t])], 1)] = int32_t(t);
-  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < H; i += stride) {
+  const int64_t H = n_track_hits(A);
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < H; i += int64_t(gridDim.x) * TPB) {
     const int32_t h = A.hits[i];
-    uint64_t r = 0;
-    const bool in = h >= 0 && h < A.n_clusters && A.row[h] < A.n_rows && fabsf(A.y[h]) <= 8192.f &&
-                    fabsf(A.z[h]) <= 8192.f;  // |Y|, |Z| <= 2^21 quanta fit the 24-bit fields
-    if (in) {
-      const int Y = __float2int_rn(A.y[h] * 256.0f), Z = __float2int_rn(A.z[h] * 256.0f);
-      r = (uint64_t(A.row[h]) << 48) | (uint64_t(uint32_t(Y + QBIAS)) << 24) | uint64_t(uint32_t(Z + QBIAS));
-    } else {
+    uint64_t r = h >= 0 && h < A.n_clusters ? A.cl[h] : NO_REC;
+    if (r == NO_REC) {
       atomicOr(A.bad, 1);
+      r = 0;
     }
     A.rec[i] = r;
   }
@@ -143,26 +179,24 @@ __device__ __forceinline__ Hit unpack(uint64_t r) {
 
 // The state in absolute coordinates (the filter runs relative to the first
 // hit's quanta Yr, Zr), its covariance and x; zeros for a track not fitted.
-__device__ __forceinline__ void store(const KState &s, bool ok, int Yr, int Zr, float *p, float *c, float *x) {
+__device__ __forceinline__ void store(KStateR &s, bool ok, int Yr, int Zr, float *p, float *c, float *x) {
   p[0] = ok ? s.p[0] + float(Yr) * (1.f / 256.f) : 0.f;
   p[1] = ok ? s.p[1] + float(Zr) * (1.f / 256.f) : 0.f;
 #pragma unroll
   for (int q = 2; q < 5; ++q) p[q] = ok ? s.p[q] : 0.f;
 #pragma unroll
-  for (int q = 0; q < 15; ++q) c[q] = ok ? s.c[q * 64] : 0.f;
+  for (int q = 0; q < 15; ++q) c[q] = ok ? cv(s, q) : 0.f;
   *x = ok ? s.x : 0.f;
 }
 
 __global__ void __launch_bounds__(FTB) k_rf_fit(RfArgs A) {
-  __shared__ float cov_lds[FTB * 15];  // per wave [15][64]: lanes side by side
   if (*A.status != TPC_OK) return;
   if (*A.bad) {  // every block sees the same flag; one writes the status
     if (blockIdx.x == 0 && threadIdx.x == 0) *A.status = TPC_E_INVALID;
     return;
   }
   const int64_t T = n_tracks(A);
-  KState s;
-  s.c = cov_lds + (threadIdx.x >> 6) * (15 * 64) + (threadIdx.x & 63);
+  KStateR s;  // the covariance in registers: no LDS round trip in the update chain
   const float k = A.k, smx = A.smx, sy2 = A.sy2, sz2 = A.sz2;
   for (int64_t i0 = int64_t(blockIdx.x) * FTB; i0 < T; i0 += int64_t(gridDim.x) * FTB) {
     const int64_t i = i0 + threadIdx.x;
@@ -237,9 +271,12 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
-extern "C" size_t tpc_refit_workspace_size(int64_t cap_tracks, int64_t cap_hits) {
-  if (cap_tracks < 0 || cap_hits < 0 || cap_tracks > (int64_t(1) << 31) || cap_hits > (int64_t(1) << 31)) return 0;
-  return align256(NB * 4 + 256) + align256(size_t(cap_tracks) * 4) + align256(size_t(cap_hits) * 8);
+extern "C" size_t tpc_refit_workspace_size(int64_t n_clusters, int64_t cap_tracks, int64_t cap_hits) {
+  if (n_clusters < 0 || n_clusters >= (int64_t(1) << 30) || cap_tracks < 0 || cap_hits < 0 ||
+      cap_tracks > (int64_t(1) << 31) || cap_hits > (int64_t(1) << 31))
+    return 0;
+  return align256(NB * 4 + 256) + align256(size_t(cap_tracks) * 4) + align256(size_t(n_clusters) * 8) +
+         align256(size_t(cap_hits) * 8);
 }
 
 extern "C" int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry,
@@ -261,7 +298,7 @@ extern "C" int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   if (!out->params || !out->cov || !out->x_ref || !out->chi2 || !out->params_out || !out->cov_out ||
       !out->x_out || !out->ok || !out->status)
     return TPC_E_INVALID;
-  const size_t need = tpc_refit_workspace_size(tracks->cap_tracks, tracks->cap_hits);
+  const size_t need = tpc_refit_workspace_size(clusters->n, tracks->cap_tracks, tracks->cap_hits);
   if (need == 0) return TPC_E_INVALID;
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return TPC_E_INVALID;
   if (workspace_bytes < need) return TPC_E_NOMEM;
@@ -299,17 +336,21 @@ extern "C" int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   w += align256(NB * 4 + 256);
   A.order = reinterpret_cast<int32_t *>(w);
   w += align256(size_t(tracks->cap_tracks) * 4);
+  A.cl = reinterpret_cast<uint64_t *>(w);
+  w += align256(size_t(clusters->n) * 8);
   A.rec = reinterpret_cast<uint64_t *>(w);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t tb = (tracks->cap_tracks + TPB - 1) / TPB;
   const int64_t hb = (tracks->cap_hits + TPB - 1) / TPB;
-  const int64_t gb = hb > tb ? hb : tb;
+  const int64_t cb = (clusters->n + TPB - 1) / TPB;
   const int64_t fb = (tracks->cap_tracks + FTB - 1) / FTB;
   auto clamp = [](int64_t b, int64_t hi) { return unsigned(b < 1 ? 1 : (b > hi ? hi : b)); };
   hipLaunchKernelGGL(k_rf_init, dim3(1), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_pack, dim3(clamp(cb, GATHER_BLOCKS)), dim3(TPB), 0, st, A);
   hipLaunchKernelGGL(k_rf_hist, dim3(clamp(tb, 1024)), dim3(TPB), 0, st, A);
   hipLaunchKernelGGL(k_rf_scan, dim3(1), dim3(NB), 0, st, A);
-  hipLaunchKernelGGL(k_rf_gather, dim3(clamp(gb, GATHER_BLOCKS)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_order, dim3(clamp(tb, 1024)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_gather, dim3(clamp(hb, GATHER_BLOCKS)), dim3(TPB), 0, st, A);
   hipLaunchKernelGGL(k_rf_fit, dim3(clamp(fb, FIT_BLOCKS)), dim3(FTB), 0, st, A);
   return hipGetLastError() == hipSuccess ? TPC_OK : TPC_E_HIP;
 }

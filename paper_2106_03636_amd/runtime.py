@@ -472,9 +472,10 @@ class Refitter:
         self.o_xout = torch.empty(T, dtype=torch.float32, device=d)
         self.o_ok = torch.empty(T, dtype=torch.uint8, device=d)
         self.o_status = torch.zeros(1, dtype=torch.int32, device=d)
-        self.ws_bytes = tpc_refit_workspace_size(T, H)
+        N = max(1, tracker.max_n)
+        self.ws_bytes = tpc_refit_workspace_size(N, T, H)
         if self.ws_bytes == 0:
-            raise ValueError("tpc_refit_workspace_size rejected capacities %d tracks, %d hits" % (T, H))
+            raise ValueError("tpc_refit_workspace_size rejected %d clusters, capacities %d tracks, %d hits" % (N, T, H))
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d)
 
     def launch(self, batch: Batch, stream=None):

@@ -165,10 +165,12 @@ def test_clusterizer_host_checks():
 def test_refit_host_checks():
     """Workspace sizes and the arguments tpc_refit_tracks rejects before any
     device work."""
-    ws = T.tpc_refit_workspace_size(1000, 50000)
-    assert ws >= 1000 * 4 + 50000 * 8
-    assert T.tpc_refit_workspace_size(1000, 40000) < ws and T.tpc_refit_workspace_size(0, 0) > 0
-    assert T.tpc_refit_workspace_size(-1, 10) == 0 and T.tpc_refit_workspace_size(10, 1 << 40) == 0
+    ws = T.tpc_refit_workspace_size(100, 1000, 50000)
+    assert ws >= 100 * 8 + 1000 * 4 + 50000 * 8
+    assert T.tpc_refit_workspace_size(100, 1000, 40000) < ws and T.tpc_refit_workspace_size(0, 0, 0) > 0
+    assert T.tpc_refit_workspace_size(200, 1000, 50000) > ws
+    assert T.tpc_refit_workspace_size(10, -1, 10) == 0 and T.tpc_refit_workspace_size(10, 10, 1 << 40) == 0
+    assert T.tpc_refit_workspace_size(1 << 30, 10, 10) == 0
     c, g, f, trk, out = T.tpc_clusters_t(), T.tpc_geometry_t(), T.tpc_field_t(), T.tpc_tracks_t(), T.tpc_refit_t()
     p = T.make_params()
     f.bz_tesla = 0.5
