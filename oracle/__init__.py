@@ -108,6 +108,11 @@ def _load():
         lib.orc_compress.argtypes = [ctypes.c_int64] + [vp] * 7 + [ctypes.c_double] * 5 + [vp] * 4
         lib.orc_refit_tracks.restype = None
         lib.orc_refit_tracks.argtypes = [ctypes.c_int64] + [vp] * 7 + [ctypes.c_double, ctypes.POINTER(Params)] + [vp] * 9
+        lib.orc_rotate.restype = ctypes.c_int
+        lib.orc_rotate.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+        lib.orc_merge.restype = ctypes.c_int64
+        lib.orc_merge.argtypes = ([ctypes.c_int64] + [vp] * 10 + [ctypes.c_int32, vp, vp, ctypes.c_int32] +
+                                  [ctypes.c_double] * 3 + [ctypes.c_int32, ctypes.c_double, ctypes.c_double] + [vp] * 4)
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -359,4 +364,59 @@ def refit_tracks(first_hit, n_hits, hits, y, z, row, row_x, k, values: dict):
                          *[out[key].ctypes.data for key in ("p", "cov", "x_ref", "chi2", "p_out", "cov_out",
                                                             "x_out", "ok", "fragile")])
     return out
+
+
+def rotate(p, x, d, k, sinphi_max=0.95, jacobian=False):
+    """A state at plane x of one sector frame turned by angle d into another
+    (see orc_rotate): (state, x') or None; with jacobian, also the 5x5 Jacobian."""
+    lib = _load()
+    p = np.ascontiguousarray(p, np.float64)
+    out = np.zeros(5)
+    xo = np.zeros(1)
+    J = np.zeros(25)
+    st = lib.orc_rotate(p.ctypes.data, float(x), float(d), float(k), float(sinphi_max), out.ctypes.data,
+                        xo.ctypes.data, J.ctypes.data)
+    if st != 0:
+        return None
+    return (out, float(xo[0]), J.reshape(5, 5)) if jacobian else (out, float(xo[0]))
+
+
+def segment_rows(first_hit, n_hits, hits, row):
+    """First and last hit row of each track (hit lists in increasing row order)."""
+    first_hit = np.asarray(first_hit, np.int64)
+    n_hits = np.asarray(n_hits, np.int64)
+    row = np.asarray(row)
+    hits = np.asarray(hits, np.int64)
+    fr = np.zeros(len(n_hits), np.int32)
+    lr = np.zeros(len(n_hits), np.int32)
+    has = n_hits > 0
+    fr[has] = row[hits[first_hit[has]]]
+    lr[has] = row[hits[first_hit[has] + n_hits[has] - 1]]
+    return fr, lr
+
+
+def merge(unit, first_row, last_row, refit, unit_alpha, unit_side, n_rows, k, sinphi_max=0.95,
+          max_dalpha=0.3665, max_gap=32, chi2_max=30.0, eps=1e-9):
+    """Links between refitted segments (see orc_merge).  refit: a dict as
+    refit_tracks returns (ok, p, cov, x_ref, p_out, cov_out, x_out)."""
+    lib = _load()
+    T = len(unit)
+    unit = np.ascontiguousarray(unit, np.int32)
+    fr = np.ascontiguousarray(first_row, np.int32)
+    lr = np.ascontiguousarray(last_row, np.int32)
+    ok = np.ascontiguousarray(refit["ok"], np.int8)
+    arrs = [np.ascontiguousarray(refit[key], np.float64) for key in ("p", "cov", "x_ref", "p_out", "cov_out", "x_out")]
+    ua = np.ascontiguousarray(unit_alpha, np.float64)
+    us = np.ascontiguousarray(unit_side, np.int32)
+    if T:
+        assert unit.min() >= 0 and unit.max() < len(ua) and fr.min() >= 0 and lr.max() < n_rows
+    nxt = np.zeros(T, np.int32)
+    prv = np.zeros(T, np.int32)
+    lc = np.zeros(T)
+    frag = np.zeros(T, np.int8)
+    n_cand = lib.orc_merge(T, unit.ctypes.data, fr.ctypes.data, lr.ctypes.data, ok.ctypes.data,
+                           *[a.ctypes.data for a in arrs], len(ua), ua.ctypes.data, us.ctypes.data, int(n_rows),
+                           float(k), float(sinphi_max), float(max_dalpha), int(max_gap), float(chi2_max), float(eps),
+                           nxt.ctypes.data, prv.ctypes.data, lc.ctypes.data, frag.ctypes.data)
+    return dict(next=nxt, prev=prv, link_chi2=lc, fragile=frag, n_candidates=int(n_cand))
 

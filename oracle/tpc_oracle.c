@@ -28,6 +28,8 @@
 #include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
+
+#define M_PI_ORC 3.14159265358979323846
 #endif
 
 #define KAPPA 0.00299792458 /* GeV / (T cm): pT = KAPPA * B * R */
@@ -1399,6 +1401,213 @@ void orc_refit_tracks(int64_t n_tracks, const int32_t *first, const int32_t *nh,
     x_out[t] = st == 0 ? (double)X[n - 1] : 0.0;
     free(X);
   }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Merging of track segments across sector boundaries (Reading R-24: the      */
+/* paper asks for full tracking and does not describe the merger).            */
+/*                                                                             */
+/* A sector's local frame is the global one turned by the sector's angle a     */
+/* (x along the sector's centre line).  Turning a state from the frame at a1   */
+/* to the frame at a2 (d = a2 - a1): the point (x, y) becomes                  */
+/* (x cos d + y sin d, -x sin d + y cos d), the direction phi becomes phi - d; */
+/* z, tan(lambda) and q/pT do not change.  The new state lives at the plane    */
+/* x' of the turned point.  Its Jacobian against the old state: a shift dy of  */
+/* the track along the old y axis moves the point by (sin d, cos d) dy in the  */
+/* new frame, and taking it back to the plane x' along the track (a step of    */
+/* -sin d dy in x) gives dy' = (cos d - sin d tan phi') dy = cos phi / cos      */
+/* phi' dy, dz' = -sin d tan(lambda) / cos phi' dy and dsin(phi') = -C sin d   */
+/* dy; a turn of the direction gives dsin(phi') = cos phi' / cos phi           */
+/* dsin(phi); everything else is unchanged to first order.                     */
+
+/* Turn state p at plane x by d.  Returns 0, or -1 when the direction reaches
+ * |sin(phi')| >= sinphi_max or cos(phi') <= 0 (the state cannot describe a
+ * track moving inward in the new frame). */
+int orc_rotate(const double p[5], double x, double d, double k, double sinphi_max, double out[5], double *x_out,
+               double J[25]) {
+  const double cd = cos(d), sd = sin(d);
+  const double s = p[2];
+  if (!(fabs(s) < 1.0)) return -1;
+  const double c = sqrt(1.0 - s * s);
+  const double s2 = s * cd - c * sd, c2 = c * cd + s * sd;
+  if (!(c2 > 0.0) || !(fabs(s2) < sinphi_max)) return -1;
+  *x_out = x * cd + p[0] * sd;
+  out[0] = -x * sd + p[0] * cd;
+  out[1] = p[1];
+  out[2] = s2;
+  out[3] = p[3];
+  out[4] = p[4];
+  if (J) {
+    memset(J, 0, 25 * sizeof(double));
+    for (int i = 0; i < 5; ++i) J[i * 5 + i] = 1.0;
+    J[0 * 5 + 0] = c / c2;
+    J[1 * 5 + 0] = -sd * p[3] / c2;
+    J[2 * 5 + 0] = -k * p[4] * sd;
+    J[2 * 5 + 2] = c2 / c;
+  }
+  return 0;
+}
+
+/* S^-1 r . r for a symmetric positive definite 5x5 S (Cholesky); -1 when S
+ * is not positive definite. */
+static double chi2_of(const double S[25], const double r[5]) {
+  double L[25] = {0};
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = S[i * 5 + j];
+      for (int m = 0; m < j; ++m) v -= L[i * 5 + m] * L[j * 5 + m];
+      if (i == j) {
+        if (!(v > 0.0)) return -1.0;
+        L[i * 5 + i] = sqrt(v);
+      } else {
+        L[i * 5 + j] = v / L[j * 5 + j];
+      }
+    }
+  double w[5], q = 0.0;
+  for (int i = 0; i < 5; ++i) {  /* w = L^-1 r */
+    double v = r[i];
+    for (int m = 0; m < i; ++m) v -= L[i * 5 + m] * w[m];
+    w[i] = v / L[i * 5 + i];
+    q += w[i] * w[i];
+  }
+  return q;
+}
+
+static void unpack_cov15(const double c15[15], double c[25]) {
+  int m = 0;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j) c[i * 5 + j] = c[j * 5 + i] = c15[m++];
+}
+
+/* The match of segment a's outer end (state p_out at x_out in a's frame) to
+ * segment b's inner end (state p_in at x_in in b's frame): a's state turned
+ * into b's frame (when the units differ), carried along the helix to b's
+ * x_in with its covariance, and chi2 = r^T (C_a + C_b)^-1 r over the five
+ * parameters, r = p_b - p_a.  Returns chi2, or -1 when a's state cannot be
+ * turned or carried, or the summed covariance is not positive definite. */
+static double match_chi2(const double pa[5], const double ca15[15], double xa, double d, const double pb[5],
+                         const double cb15[15], double xb, double k, double sinphi_max) {
+  double p[5], C[25], x = xa, J[25], q[5], F[25];
+  unpack_cov15(ca15, C);
+  memcpy(p, pa, sizeof(p));
+  if (d != 0.0) {
+    if (orc_rotate(pa, xa, d, k, sinphi_max, p, &x, J) != 0) return -1.0;
+    transport_cov(J, C);
+  }
+  if (orc_propagate(p, x, xb, k, sinphi_max, q, F) != 0) return -1.0;
+  transport_cov(F, C);
+  double Cb[25], S[25], r[5];
+  unpack_cov15(cb15, Cb);
+  for (int i = 0; i < 25; ++i) S[i] = C[i] + Cb[i];
+  for (int i = 0; i < 5; ++i) r[i] = pb[i] - q[i];
+  return chi2_of(S, r);
+}
+
+/* Links between the refitted segments of a tracking call (Reading R-24).
+ * Segment b is a candidate continuation of segment a when both are refitted,
+ * their units lie on the same side with |a2 - a1| <= max_dalpha (the same
+ * unit included), b's first hit row follows a's last one by 1 .. max_gap rows,
+ * and match_chi2 <= chi2_max.  Each segment takes its best candidate in
+ * each direction (the least chi2, then the smaller index); a and b are linked
+ * when each is the other's best.  Output per segment: next (outer partner) and
+ * prev (inner partner), -1 for none, and the link's chi2 in link_chi2 (at the
+ * inner segment).  fragile = 1 on a segment whose link decision comes within
+ * eps (relative) of the cut or of a tie.  Returns the number of candidate
+ * pairs. */
+int64_t orc_merge(int64_t T, const int32_t *unit, const int32_t *first_row, const int32_t *last_row,
+                  const int8_t *ok, const double *p_in, const double *cov_in, const double *x_in,
+                  const double *p_out, const double *cov_out, const double *x_out, int32_t n_units,
+                  const double *unit_alpha, const int32_t *unit_side, int32_t n_rows, double k,
+                  double sinphi_max, double max_dalpha, int32_t max_gap, double chi2_max, double eps,
+                  int32_t *next, int32_t *prev, double *link_chi2, int8_t *fragile) {
+  /* segments by (unit, first row) */
+  const int64_t nb = (int64_t)n_units * n_rows;
+  int64_t *start = (int64_t *)calloc((size_t)nb + 1, sizeof(int64_t));
+  int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T > 0 ? T : 1));
+  for (int64_t t = 0; t < T; ++t)
+    if (ok[t]) ++start[(int64_t)unit[t] * n_rows + first_row[t] + 1];
+  for (int64_t b = 0; b < nb; ++b) start[b + 1] += start[b];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+  memcpy(fill, start, sizeof(int64_t) * (size_t)(nb + 1));
+  for (int64_t t = 0; t < T; ++t)
+    if (ok[t]) idx[fill[(int64_t)unit[t] * n_rows + first_row[t]]++] = t;
+  free(fill);
+  /* best candidate of each segment outward (ob) and inward (ib), with the
+   * runner-up chi2 for the fragile flag */
+  double *ob_c = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+  double *ib_c = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+  double *ob_2 = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+  double *ib_2 = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+  int64_t *ob = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T > 0 ? T : 1));
+  int64_t *ib = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T > 0 ? T : 1));
+  int8_t *near_cut = (int8_t *)calloc((size_t)(T > 0 ? T : 1), 1);
+  for (int64_t t = 0; t < T; ++t) {
+    ob[t] = ib[t] = -1;
+    ob_c[t] = ib_c[t] = ob_2[t] = ib_2[t] = INFINITY;
+  }
+  int64_t n_cand = 0;
+  for (int64_t a = 0; a < T; ++a) {
+    if (!ok[a]) continue;
+    for (int32_t w = 0; w < n_units; ++w) {
+      if (unit_side[w] != unit_side[unit[a]]) continue;
+      const double d = remainder(unit_alpha[w] - unit_alpha[unit[a]], 2.0 * M_PI_ORC);
+      if (!(fabs(d) <= max_dalpha)) continue;
+      for (int32_t r = last_row[a] + 1; r <= last_row[a] + max_gap && r < n_rows; ++r) {
+        const int64_t bin = (int64_t)w * n_rows + r;
+        for (int64_t q = start[bin]; q < start[bin + 1]; ++q) {
+          const int64_t b = idx[q];
+          const double c2 = match_chi2(p_out + a * 5, cov_out + a * 15, x_out[a], w == unit[a] ? 0.0 : d,
+                                       p_in + b * 5, cov_in + b * 15, x_in[b], k, sinphi_max);
+          if (c2 < 0.0) continue;
+          if (fabs(c2 - chi2_max) <= eps * chi2_max) near_cut[a] = near_cut[b] = 1;
+          if (c2 > chi2_max) continue;
+          ++n_cand;
+          if (c2 < ob_c[a] || (c2 == ob_c[a] && b < ob[a])) {
+            ob_2[a] = ob_c[a];
+            ob_c[a] = c2;
+            ob[a] = b;
+          } else if (c2 < ob_2[a]) {
+            ob_2[a] = c2;
+          }
+          if (c2 < ib_c[b] || (c2 == ib_c[b] && a < ib[b])) {
+            ib_2[b] = ib_c[b];
+            ib_c[b] = c2;
+            ib[b] = a;
+          } else if (c2 < ib_2[b]) {
+            ib_2[b] = c2;
+          }
+        }
+      }
+    }
+  }
+  for (int64_t t = 0; t < T; ++t) {
+    next[t] = prev[t] = -1;
+    link_chi2[t] = 0.0;
+  }
+  for (int64_t a = 0; a < T; ++a) {
+    const int64_t b = ob[a];
+    if (b >= 0 && ib[b] == a) {
+      next[a] = (int32_t)b;
+      prev[b] = (int32_t)a;
+      link_chi2[a] = ob_c[a];
+    }
+  }
+  for (int64_t t = 0; t < T; ++t) {
+    int fr = near_cut[t];
+    if (ob[t] >= 0 && ob_2[t] - ob_c[t] <= eps * ob_c[t]) fr = 1;
+    if (ib[t] >= 0 && ib_2[t] - ib_c[t] <= eps * ib_c[t]) fr = 1;
+    fragile[t] = (int8_t)fr;
+  }
+  free(start);
+  free(idx);
+  free(ob_c);
+  free(ib_c);
+  free(ob_2);
+  free(ib_2);
+  free(ob);
+  free(ib);
+  free(near_cut);
+  return n_cand;
 }
 
 int orc_num_threads(void) {

@@ -16,6 +16,7 @@ import test_clusterizer_oracle as clu
 import test_collisions_oracle as col
 import test_compression_oracle as cmp
 import test_oracle_pins as pins
+import test_merge_oracle as mrg
 import test_refit_oracle as rft
 from conftest import cached_event, cached_oracle
 
@@ -146,6 +147,28 @@ MUTATIONS = [
     ("refit_hit_list_reversed",
      "      const int32_t h = hits[first[t] + j];", "      const int32_t h = hits[first[t] + n - 1 - j];",
      [rft.test_refit_of_noise_free_helices_gives_the_helix_at_both_ends]),
+    ("merge_turn_sign",
+     "  const double s2 = s * cd - c * sd, c2 = c * cd + s * sd;",
+     "  const double s2 = s * cd + c * sd, c2 = c * cd - s * sd;",
+     [mrg.test_turn_and_transport_reproduce_the_helix_in_the_next_sector]),
+    ("merge_turn_jacobian_y",
+     "    J[0 * 5 + 0] = c / c2;", "    J[0 * 5 + 0] = c2 / c;",
+     [lambda: [mrg.test_turn_jacobian_matches_finite_differences(c) for c in
+               (([3.0, -20.0, 0.3, 0.7, -2.5], 120.0, 0.35), ([20.0, 5.0, 0.6, 0.2, 0.8], 90.0, 0.1))]]),
+    ("merge_not_mutual",
+     "    if (b >= 0 && ib[b] == a) {", "    if (b >= 0) {",
+     [mrg.test_hand_worked_links]),
+    ("merge_rows_may_touch",
+     "      for (int32_t r = last_row[a] + 1; r <= last_row[a] + max_gap && r < n_rows; ++r) {",
+     "      for (int32_t r = last_row[a]; r <= last_row[a] + max_gap && r < n_rows; ++r) {",
+     [mrg.test_hand_worked_rules]),
+    ("merge_tie_to_the_larger_index",
+     "          if (c2 < ib_c[b] || (c2 == ib_c[b] && a < ib[b])) {",
+     "          if (c2 < ib_c[b] || (c2 == ib_c[b] && a > ib[b])) {",
+     [mrg.test_hand_worked_links]),
+    ("merge_across_sides",
+     "      if (unit_side[w] != unit_side[unit[a]]) continue;\n", "",
+     [mrg.test_hand_worked_rules]),
 ]
 
 
