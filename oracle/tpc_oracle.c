@@ -1507,6 +1507,7 @@ static double match_chi2(const double pa[5], const double ca15[15], double xa, d
  * Segment b is a candidate continuation of segment a when both are refitted,
  * their units lie on the same side with |a2 - a1| <= max_dalpha (the same
  * unit included), b's first hit row follows a's last one by 1 .. max_gap rows,
+ * the z' of b's inner state lies within dz_max of the z' of a's outer state,
  * and match_chi2 <= chi2_max.  Each segment takes its best candidate in
  * each direction (the least chi2, then the smaller index); a and b are linked
  * when each is the other's best.  Output per segment: next (outer partner) and
@@ -1518,8 +1519,8 @@ int64_t orc_merge(int64_t T, const int32_t *unit, const int32_t *first_row, cons
                   const int8_t *ok, const double *p_in, const double *cov_in, const double *x_in,
                   const double *p_out, const double *cov_out, const double *x_out, int32_t n_units,
                   const double *unit_alpha, const int32_t *unit_side, int32_t n_rows, double k,
-                  double sinphi_max, double max_dalpha, int32_t max_gap, double chi2_max, double eps,
-                  int32_t *next, int32_t *prev, double *link_chi2, int8_t *fragile) {
+                  double sinphi_max, double max_dalpha, int32_t max_gap, double dz_max, double chi2_max,
+                  double eps, int32_t *next, int32_t *prev, double *link_chi2, int8_t *fragile) {
   /* segments by (unit, first row) */
   const int64_t nb = (int64_t)n_units * n_rows;
   int64_t *start = (int64_t *)calloc((size_t)nb + 1, sizeof(int64_t));
@@ -1556,6 +1557,7 @@ int64_t orc_merge(int64_t T, const int32_t *unit, const int32_t *first_row, cons
         const int64_t bin = (int64_t)w * n_rows + r;
         for (int64_t q = start[bin]; q < start[bin + 1]; ++q) {
           const int64_t b = idx[q];
+          if (!(fabs(p_in[b * 5 + 1] - p_out[a * 5 + 1]) <= dz_max)) continue;
           const double c2 = match_chi2(p_out + a * 5, cov_out + a * 15, x_out[a], w == unit[a] ? 0.0 : d,
                                        p_in + b * 5, cov_in + b * 15, x_in[b], k, sinphi_max);
           if (c2 < 0.0) continue;

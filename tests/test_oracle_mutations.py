@@ -166,6 +166,9 @@ MUTATIONS = [
      "          if (c2 < ib_c[b] || (c2 == ib_c[b] && a < ib[b])) {",
      "          if (c2 < ib_c[b] || (c2 == ib_c[b] && a > ib[b])) {",
      [mrg.test_hand_worked_links]),
+    ("merge_no_z_window",
+     "          if (!(fabs(p_in[b * 5 + 1] - p_out[a * 5 + 1]) <= dz_max)) continue;\n", "",
+     [mrg.test_hand_worked_rules]),
     ("merge_across_sides",
      "      if (unit_side[w] != unit_side[unit[a]]) continue;\n", "",
      [mrg.test_hand_worked_rules]),
