@@ -112,7 +112,7 @@ def _load():
         lib.orc_rotate.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp, vp]
         lib.orc_merge.restype = ctypes.c_int64
         lib.orc_merge.argtypes = ([ctypes.c_int64] + [vp] * 10 + [ctypes.c_int32, vp, vp, ctypes.c_int32] +
-                                  [ctypes.c_double] * 3 + [ctypes.c_int32] + [ctypes.c_double] * 3 + [vp] * 4)
+                                  [ctypes.c_double] * 3 + [ctypes.c_int32] + [ctypes.c_double] * 4 + [vp] * 4)
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -396,7 +396,7 @@ def segment_rows(first_hit, n_hits, hits, row):
 
 
 def merge(unit, first_row, last_row, refit, unit_alpha, unit_side, n_rows, k, sinphi_max=0.95,
-          max_dalpha=0.3665, max_gap=32, dz_max=64.0, chi2_max=30.0, eps=1e-9):
+          max_dalpha=0.3665, max_gap=32, dz_max=64.0, dy_max=2.0, chi2_max=30.0, eps=1e-9):
     """Links between refitted segments (see orc_merge).  refit: a dict as
     refit_tracks returns (ok, p, cov, x_ref, p_out, cov_out, x_out)."""
     lib = _load()
@@ -417,7 +417,7 @@ def merge(unit, first_row, last_row, refit, unit_alpha, unit_side, n_rows, k, si
     n_cand = lib.orc_merge(T, unit.ctypes.data, fr.ctypes.data, lr.ctypes.data, ok.ctypes.data,
                            *[a.ctypes.data for a in arrs], len(ua), ua.ctypes.data, us.ctypes.data, int(n_rows),
                            float(k), float(sinphi_max), float(max_dalpha), int(max_gap), float(dz_max),
-                           float(chi2_max), float(eps),
+                           float(dy_max), float(chi2_max), float(eps),
                            nxt.ctypes.data, prv.ctypes.data, lc.ctypes.data, frag.ctypes.data)
     return dict(next=nxt, prev=prv, link_chi2=lc, fragile=frag, n_candidates=int(n_cand))
 

@@ -1508,7 +1508,9 @@ static double match_chi2(const double pa[5], const double ca15[15], double xa, d
  * their units lie on the same side with |a2 - a1| <= max_dalpha (the same
  * unit included), b's first hit row follows a's last one by 1 .. max_gap rows,
  * the z' of b's inner state lies within dz_max of the z' of a's outer state,
- * and match_chi2 <= chi2_max.  Each segment takes its best candidate in
+ * the y of b's inner state within dy_max of the y of a's outer state turned
+ * into b's frame and carried along the helix to b's x_in, and
+ * match_chi2 <= chi2_max.  Each segment takes its best candidate in
  * each direction (the least chi2, then the smaller index); a and b are linked
  * when each is the other's best.  Output per segment: next (outer partner) and
  * prev (inner partner), -1 for none, and the link's chi2 in link_chi2 (at the
@@ -1519,8 +1521,9 @@ int64_t orc_merge(int64_t T, const int32_t *unit, const int32_t *first_row, cons
                   const int8_t *ok, const double *p_in, const double *cov_in, const double *x_in,
                   const double *p_out, const double *cov_out, const double *x_out, int32_t n_units,
                   const double *unit_alpha, const int32_t *unit_side, int32_t n_rows, double k,
-                  double sinphi_max, double max_dalpha, int32_t max_gap, double dz_max, double chi2_max,
-                  double eps, int32_t *next, int32_t *prev, double *link_chi2, int8_t *fragile) {
+                  double sinphi_max, double max_dalpha, int32_t max_gap, double dz_max, double dy_max,
+                  double chi2_max, double eps, int32_t *next, int32_t *prev, double *link_chi2,
+                  int8_t *fragile) {
   /* segments by (unit, first row) */
   const int64_t nb = (int64_t)n_units * n_rows;
   int64_t *start = (int64_t *)calloc((size_t)nb + 1, sizeof(int64_t));
@@ -1553,11 +1556,18 @@ int64_t orc_merge(int64_t T, const int32_t *unit, const int32_t *first_row, cons
       if (unit_side[w] != unit_side[unit[a]]) continue;
       const double d = remainder(unit_alpha[w] - unit_alpha[unit[a]], 2.0 * M_PI_ORC);
       if (!(fabs(d) <= max_dalpha)) continue;
+      /* a's outer state in w's frame (parameters only) */
+      double pw[5], xw = x_out[a];
+      memcpy(pw, p_out + a * 5, sizeof(pw));
+      if (w != unit[a] && orc_rotate(p_out + a * 5, x_out[a], d, k, sinphi_max, pw, &xw, NULL) != 0) continue;
       for (int32_t r = last_row[a] + 1; r <= last_row[a] + max_gap && r < n_rows; ++r) {
         const int64_t bin = (int64_t)w * n_rows + r;
         for (int64_t q = start[bin]; q < start[bin + 1]; ++q) {
           const int64_t b = idx[q];
           if (!(fabs(p_in[b * 5 + 1] - p_out[a * 5 + 1]) <= dz_max)) continue;
+          double yc[5];
+          if (orc_propagate(pw, xw, x_in[b], k, sinphi_max, yc, NULL) != 0) continue;
+          if (!(fabs(p_in[b * 5] - yc[0]) <= dy_max)) continue;
           const double c2 = match_chi2(p_out + a * 5, cov_out + a * 15, x_out[a], w == unit[a] ? 0.0 : d,
                                        p_in + b * 5, cov_in + b * 15, x_in[b], k, sinphi_max);
           if (c2 < 0.0) continue;

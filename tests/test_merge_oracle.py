@@ -12,7 +12,7 @@ match.  Pins, each against facts that do not come from the oracle:
     the transport back to the turned plane;
   * a hand-worked set of straight segments with unit covariances gives the
     chi2 values and links derived by hand: best matches both ways, ties to
-    the smaller index, the row, z, side and angle rules;
+    the smaller index, the row, z, y, side and angle rules;
   * MC truth on a central Pb-Pb collision: links join segments of one
     particle, and most particles that the tracker split are joined.
 """
@@ -141,7 +141,7 @@ def test_hand_worked_links():
 
 
 def test_hand_worked_rules():
-    """Row, gap, z, side and angle rules, on segments whose states agree."""
+    """Row, gap, z, y, side and angle rules, on segments whose states agree."""
     p = [_seg(0.0)] * 2
     # B must start after A ends, at most max_gap (32) rows after
     assert _hand([0, 0], [(0, 10), (10, 40)], p, p)["next"][0] == -1
@@ -153,6 +153,9 @@ def test_hand_worked_rules():
     assert _hand([0, 0], [(0, 10), (11, 40)], far, p, chi2_max=1e30)["next"][0] == 1
     far = [_seg(0.0), _seg(0.0, 64.5)]
     assert _hand([0, 0], [(0, 10), (11, 40)], far, p, chi2_max=1e30)["next"][0] == -1
+    # the inner y of B within dy_max (2 cm) of A's state carried to B's x
+    assert _hand([0, 0], [(0, 10), (11, 40)], [_seg(0.0), _seg(2.0)], p, chi2_max=1e30)["next"][0] == 1
+    assert _hand([0, 0], [(0, 10), (11, 40)], [_seg(0.0), _seg(-2.25)], p, chi2_max=1e30)["next"][0] == -1
     # unit 3 lies on the other side at unit 0's angle: identical states, no link
     assert _hand([0, 3], [(0, 10), (11, 40)], p, p)["next"][0] == -1
     # the straight line y = 0 of a unit at angle a2, seen from a unit at angle a1

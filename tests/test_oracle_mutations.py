@@ -169,6 +169,9 @@ MUTATIONS = [
     ("merge_no_z_window",
      "          if (!(fabs(p_in[b * 5 + 1] - p_out[a * 5 + 1]) <= dz_max)) continue;\n", "",
      [mrg.test_hand_worked_rules]),
+    ("merge_no_y_window",
+     "          if (!(fabs(p_in[b * 5] - yc[0]) <= dy_max)) continue;\n", "",
+     [mrg.test_hand_worked_rules]),
     ("merge_across_sides",
      "      if (unit_side[w] != unit_side[unit[a]]) continue;\n", "",
      [mrg.test_hand_worked_rules]),
