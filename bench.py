@@ -798,6 +798,57 @@ def refit_bench(dev, tr, batch, reps, workload):
     return out
 
 
+def merge_bench(dev, tr, batch, ev, reps, workload):
+    """Segment merging (tpc_merge_tracks) of the tracker's last batch after
+    its refit: the merge call's device time from HIP graph replays (the refit
+    runs once before), the pairs, candidates and links, and the links'
+    purity against MC truth."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2106_03636_amd import mctruth
+    from paper_2106_03636_amd.runtime import Merger, Refitter
+    rf = Refitter(tr)
+    rf.launch(batch)
+    # unit angles and sides on the device before the graph is captured
+    alpha = torch.as_tensor(np.array([synth.sector_alpha(int(s)) for s in ev.unit_sector], np.float32)).to(dev)
+    side = torch.as_tensor(np.where(np.asarray(ev.unit_sector) < 18, 1, -1).astype(np.int32)).to(dev)
+    mg = Merger(rf, len(alpha))
+    n_tracks = int(tr.o_counts[0].item())
+    for _ in range(2):
+        mg.launch(batch, alpha, side)
+    r = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in mg.result(n_tracks).items()}
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        mg.launch(batch, alpha, side)
+    torch.cuda.synchronize(dev)
+    graph.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    r2 = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in mg.result(n_tracks).items()}
+    if not np.array_equal(r["next"], r2["next"]):
+        raise RuntimeError("graph replay and eager call of the merger disagree")
+    del graph
+    res = tr.result(sync=False)
+    maj = mctruth.majority_particle(ev.label, res["n_hits"].cpu().numpy(), res["hits"].cpu().numpy())
+    a = np.nonzero(r["next"] >= 0)[0]
+    b = r["next"][a]
+    unit = res["unit"].cpu().numpy()
+    out = dict(workload=workload, tracks=n_tracks, ms_per_call=ms, tracks_per_s=n_tracks / (ms * 1e-3), launches=9,
+               pairs=r["n_pairs"], candidates=r["n_candidates"], links=r["n_links"],
+               links_across_sectors=int((unit[a] != unit[b]).sum()),
+               link_purity=float(((maj[a] == maj[b]) & (maj[a] >= 0)).mean()) if len(a) else None,
+               chains=int(((r["prev"] < 0) & (r["next"] >= 0)).sum()))
+    log("bench: merge " + json.dumps(out))
+    return out
+
+
 def clusterizer_bench(dev, ev, reps, workload, cpu_units=2):
     """Clusterizer (tpc_clusterize) on the raw ADC digits of `ev` (generated
     from its clusters): the call's device time from HIP graph replays, the
@@ -912,6 +963,7 @@ def main():
     ap.add_argument("--no-clusterizer", action="store_true", help="skip the clusterizer measurement")
     ap.add_argument("--no-compression", action="store_true", help="skip the compression measurement")
     ap.add_argument("--no-refit", action="store_true", help="skip the track refit measurement")
+    ap.add_argument("--no-merge", action="store_true", help="skip the segment merging measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -1083,6 +1135,7 @@ def main():
                                                                      args.workload)
     collisions = None if args.no_collisions else collision_bench(dev, tr, ev, max(50, args.steps), args.workload)
     refit = None if args.no_refit else refit_bench(dev, tr, batch, max(20, args.steps), args.workload)
+    merge = None if args.no_merge else merge_bench(dev, tr, batch, ev, max(20, args.steps), args.workload)
 
     out = dict(
         metric=METRIC, value=value, unit="clusters/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -1107,6 +1160,8 @@ def main():
         out["compression"] = compression
     if refit is not None:
         out["refit"] = refit
+    if merge is not None:
+        out["merge"] = merge
 
     # the plain form: one call per sector unit, same stream, same work
     if not args.no_plain:

@@ -446,6 +446,73 @@ int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geome
                      const tpc_params_t *params, const tpc_tracks_t *tracks, tpc_refit_t *out, void *workspace,
                      size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------- */
+/* Segment merging.  Full tracking (paper §2.1) joins the pieces of a track  */
+/* that the sector tracking finds separately: in neighbouring sectors, or    */
+/* split inside one; the paper does not describe how.  This call links the   */
+/* refitted tracks of a tpc_track_sectors call (its tpc_refit_tracks output)  */
+/* where one continues another.  Unit u's local frame is the global one      */
+/* turned by unit_alpha[u] (x along the sector's centre line).  Segment b is */
+/* a candidate continuation of segment a when                                */
+/*   - both are refitted (ok), their units lie on the same side             */
+/*     (unit_side) and |remainder(alpha_b - alpha_a, 2 pi)| <= max_dalpha    */
+/*     (the same unit included);                                             */
+/*   - b's first hit row follows a's last one by 1 .. max_gap rows;          */
+/*   - |z_b,in - z_a,out| <= dz_max (b's inner state, a's outer state);      */
+/*   - a's outer state, turned into b's frame (the point and the direction   */
+/*     turn; z, tan(lambda), q/pT stay; the state moves to the turned        */
+/*     point's x) and carried along the helix to b's x_ref, has              */
+/*     |y_b,in - y| <= dy_max;                                               */
+/*   - with both covariances carried along (the turn's and the transport's   */
+/*     Jacobians), chi2 = r^T (C_a + C_b)^-1 r <= chi2_max over the five     */
+/*     parameters, r = p_b,in - p_a carried (FP64).                          */
+/* Each segment takes its best candidate in each direction (least chi2,      */
+/* then the smaller track index); a and b are linked when each is the       */
+/* other's best.  Links never form a cycle (rows increase along them).      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct tpc_merge_params {
+  int64_t cap_pairs;           /* capacity of the list of pairs that pass the row, side, angle, z and y rules */
+  float max_dalpha;            /* radians, >= 0 */
+  int32_t max_gap;             /* rows, 1..255 */
+  float dz_max;                /* cm, >= 0 */
+  float dy_max;                /* cm, >= 0 */
+  float chi2_max;              /* > 0 */
+  float sinphi_max;            /* the helix model's limit, 0 < . < 1 */
+} tpc_merge_params_t;
+
+/* Outputs (device pointers, allocated by the caller; per-track arrays of at
+ * least the tracking output's cap_tracks entries). */
+typedef struct tpc_merged {
+  int32_t *next;               /* [cap_tracks] the segment continuing this one, -1 none */
+  int32_t *prev;               /* [cap_tracks] the segment this one continues, -1 none */
+  double *link_chi2;           /* [cap_tracks] chi2 of the link to next (0 without one) */
+  int64_t *counts;             /* [3] pairs past the rules, candidates (chi2 <= chi2_max), links */
+  int32_t *status;             /* [1] TPC_OK, the tracker's or the refit's own status when not TPC_OK,
+                                  TPC_E_INVALID (a track's unit has no side +-1, or a hit names no
+                                  cluster), TPC_E_CAPACITY (more pairs than cap_pairs; counts[0]
+                                  holds the number); outputs are valid only with TPC_OK */
+} tpc_merged_t;
+
+/* Bytes of device workspace tpc_merge_tracks needs (host-only, pure; 0 on bad
+ * arguments). */
+size_t tpc_merge_workspace_size(int32_t n_units, int32_t n_rows, int64_t cap_tracks,
+                                const tpc_merge_params_t *params);
+
+/* Links between the tracks of a tpc_track_sectors call, from that call's
+ * output (n_hits, first_hit, hits, unit, counts, status on the device) and
+ * the tpc_refit_tracks output for it (both states, covariances, ok, status),
+ * with the same clusters (their rows), geometry and field.  unit_alpha and
+ * unit_side are device arrays of n_units entries.  Enqueued on `stream`
+ * after those calls; the workspace (aligned to 256 bytes) holds no state
+ * across calls.  Returns TPC_OK when the work was enqueued, TPC_E_INVALID /
+ * TPC_E_NOMEM on bad arguments or a small workspace, TPC_E_HIP on a launch
+ * failure. */
+int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry, const tpc_field_t *field,
+                     const tpc_tracks_t *tracks, const tpc_refit_t *refit, const float *unit_alpha,
+                     const int32_t *unit_side, int32_t n_units, const tpc_merge_params_t *params,
+                     tpc_merged_t *out, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Intermediate arrays kept in the workspace after a call, for inspection and
  * tests.  Valid until the workspace is reused.  `what` selects the array:
  *   TPC_VIEW_PERM      int32 [n]  sorted position -> cluster id

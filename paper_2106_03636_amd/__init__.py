@@ -109,6 +109,16 @@ class tpc_refit_t(ctypes.Structure):
                 ("cov_out", _vp), ("x_out", _vp), ("ok", _vp), ("status", _vp)]
 
 
+class tpc_merge_params_t(ctypes.Structure):
+    _fields_ = [("cap_pairs", ctypes.c_int64), ("max_dalpha", ctypes.c_float), ("max_gap", ctypes.c_int32),
+                ("dz_max", ctypes.c_float), ("dy_max", ctypes.c_float), ("chi2_max", ctypes.c_float),
+                ("sinphi_max", ctypes.c_float)]
+
+
+class tpc_merged_t(ctypes.Structure):
+    _fields_ = [("next", _vp), ("prev", _vp), ("link_chi2", _vp), ("counts", _vp), ("status", _vp)]
+
+
 class tpc_view_t(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("count", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -167,6 +177,15 @@ def load_library():
         lib.tpc_refit_tracks.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
                                          ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_params_t),
                                          ctypes.POINTER(tpc_tracks_t), ctypes.POINTER(tpc_refit_t), _vp,
+                                         ctypes.c_size_t, _vp]
+        lib.tpc_merge_workspace_size.restype = ctypes.c_size_t
+        lib.tpc_merge_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                                 ctypes.POINTER(tpc_merge_params_t)]
+        lib.tpc_merge_tracks.restype = ctypes.c_int
+        lib.tpc_merge_tracks.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
+                                         ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_tracks_t),
+                                         ctypes.POINTER(tpc_refit_t), _vp, _vp, ctypes.c_int32,
+                                         ctypes.POINTER(tpc_merge_params_t), ctypes.POINTER(tpc_merged_t), _vp,
                                          ctypes.c_size_t, _vp]
         lib.tpc_inspect.restype = ctypes.c_int
         lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
@@ -275,6 +294,29 @@ def tpc_refit_tracks(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: 
                                                workspace, workspace_bytes, stream))
 
 
+def tpc_merge_workspace_size(n_units: int, n_rows: int, cap_tracks: int, params: tpc_merge_params_t) -> int:
+    return int(load_library().tpc_merge_workspace_size(n_units, n_rows, cap_tracks, ctypes.byref(params)))
+
+
+def tpc_merge_tracks(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t, tracks: tpc_tracks_t,
+                     refit: tpc_refit_t, unit_alpha: int, unit_side: int, n_units: int, params: tpc_merge_params_t,
+                     out: tpc_merged_t, workspace: int, workspace_bytes: int, stream: int) -> int:
+    return int(load_library().tpc_merge_tracks(ctypes.byref(clusters), ctypes.byref(geometry), ctypes.byref(field),
+                                               ctypes.byref(tracks), ctypes.byref(refit), unit_alpha, unit_side,
+                                               n_units, ctypes.byref(params), ctypes.byref(out), workspace,
+                                               workspace_bytes, stream))
+
+
+def make_merge_params(cap_pairs=1 << 22, max_dalpha=0.3665, max_gap=32, dz_max=64.0, dy_max=2.0, chi2_max=30.0,
+                      sinphi_max=0.95) -> tpc_merge_params_t:
+    """Defaults: neighbouring sectors 20 degrees apart (21 allowed), 32 rows,
+    64 cm in z', 2 cm in the carried y, chi2 30 over five parameters."""
+    mp = tpc_merge_params_t()
+    mp.cap_pairs, mp.max_dalpha, mp.max_gap = int(cap_pairs), max_dalpha, int(max_gap)
+    mp.dz_max, mp.dy_max, mp.chi2_max, mp.sinphi_max = dz_max, dy_max, chi2_max, sinphi_max
+    return mp
+
+
 def make_compress_params(step=1.0 / 64, pt_remove=0.1, sinphi_max=0.999, hist_half=1024) -> tpc_compress_params_t:
     cp = tpc_compress_params_t()
     cp.step, cp.pt_remove, cp.sinphi_max, cp.hist_half = step, pt_remove, sinphi_max, int(hist_half)
@@ -310,7 +352,7 @@ def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, wor
 def __getattr__(name):
     # the torch-side helpers load on first use, so that importing the package
     # (e.g. for its parameter values) does not import torch
-    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer", "Compressor", "Refitter"):
+    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer", "Compressor", "Refitter", "Merger"):
         from . import runtime
         return getattr(runtime, name)
     raise AttributeError(name)

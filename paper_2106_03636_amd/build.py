@@ -12,6 +12,7 @@ SRC_COLLISIONS = os.path.join(HERE, "csrc", "tpc_collisions.hip")
 SRC_CLUSTERIZE = os.path.join(HERE, "csrc", "tpc_clusterize.hip")
 SRC_COMPRESS = os.path.join(HERE, "csrc", "tpc_compress.hip")
 SRC_REFIT = os.path.join(HERE, "csrc", "tpc_refit.hip")
+SRC_MERGE = os.path.join(HERE, "csrc", "tpc_merge.hip")
 LIB = os.path.join(HERE, "_tpctrack.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -30,7 +31,7 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC, SRC_REQUESTS, SRC_COLLISIONS, SRC_CLUSTERIZE, SRC_COMPRESS, SRC_REFIT, SRC_SERVER, "-lpthread"]
+    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC, SRC_REQUESTS, SRC_COLLISIONS, SRC_CLUSTERIZE, SRC_COMPRESS, SRC_REFIT, SRC_MERGE, SRC_SERVER, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

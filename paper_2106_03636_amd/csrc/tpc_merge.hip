@@ -1,0 +1,658 @@
+// Merging of track segments across sector boundaries: the segments the
+// tracker found in neighbouring sectors (or split inside one) joined where
+// one continues the other.  The paper's synchronous processing needs full
+// tracking (§2.1) and does not describe this step; the operation is stated
+// with tpc_merge_tracks in include/tpc_track.h.
+//
+// Launches on the caller's stream:
+//   k_mg_init   status, counters, per-track outputs and best-match keys;
+//   k_mg_rows   per track: first and last hit row, per (unit, first row)
+//               counts of the refitted segments;
+//   k_mg_scan   one block: bin offsets;
+//   k_mg_fill   segments filed by (unit, first row), with their inner z', y
+//               and x next to them (so the scan below reads contiguous
+//               memory, not the refit's arrays at random);
+//   k_mg_sort   one wave per (unit, row >= 1) bin: its segments sorted by z'
+//               (bitonic in LDS up to SORT_MAX; larger bins by one lane);
+//   k_mg_pairs  one lane per segment a: for each unit on its side within
+//               max_dalpha, its outer state turned into that unit's frame
+//               (parameters, FP64); for each row 1 .. max_gap after its last
+//               one, two binary searches bound the z' window in that row's
+//               bin, whose segments get y carried along the helix
+//               (parameters only); pairs that pass go to a list;
+//   k_mg_chi2   one lane per pair: the turn with its Jacobian, the helix
+//               transport with its Jacobian, both covariances summed, chi2
+//               by Cholesky (FP64); candidates take the least chi2 per
+//               segment both ways (64-bit atomic minima on the chi2's bits:
+//               non-negative doubles order like their bit patterns);
+//   k_mg_pick   per candidate at its segment's least chi2: the least index;
+//   k_mg_link   per segment: linked when its best outward match takes it as
+//               its best inward match.
+// FP64 with contraction off, so the decisions follow the exact arithmetic to
+// about 1e-15 relative.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "tpc_track.h"
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int SCAN_T = 1024;
+constexpr int SORT_MAX = 1024;  // bins sorted in LDS up to this size
+constexpr int MAX_BLOCKS = 4096;
+constexpr double KAPPA = 0.00299792458;
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr unsigned long long NONE64 = ~0ull;
+
+struct MgArgs {
+  // clusters, geometry
+  const uint16_t *row;
+  int64_t n_clusters;
+  int32_t n_rows;
+  // tracks
+  const int32_t *trk_status, *n_hits, *first_hit, *hits, *unit;
+  const int64_t *trk_counts;
+  int64_t cap_tracks;
+  // refit
+  const float *p_in, *c_in, *x_in, *p_out, *c_out, *x_out;
+  const uint8_t *ok;
+  const int32_t *rf_status;
+  // units
+  const float *alpha;
+  const int32_t *side;
+  int32_t n_units;
+  // parameters
+  double k, smx, max_dalpha, dz_max, dy_max, chi2_max;
+  int32_t max_gap;
+  int64_t cap_pairs;
+  // outputs
+  int32_t *next, *prev;
+  double *link_chi2;
+  int64_t *counts;
+  int32_t *status;
+  // workspace
+  int32_t *bin;  // [nbins + 1] counts, then offsets
+  int32_t *cursor;
+  int32_t *idx;
+  float *zin, *yin, *xin;  // inner z', y and x of the filed segments, in filing order
+  int32_t *rows;  // first row | last row << 16
+  unsigned long long *ob_chi, *ib_chi;
+  int32_t *ob_idx, *ib_idx;
+  int2 *pairs;
+  double *pair_chi;
+  unsigned long long *ctr;  // pairs, candidates, links
+};
+
+__device__ __forceinline__ int64_t n_tracks(const MgArgs &A) {
+  const int64_t T = A.trk_counts[0];
+  return T < A.cap_tracks ? T : A.cap_tracks;
+}
+
+// ---- FP64 track model --------------------------------------------------------
+
+// asin(u)/u and (d/du asin(u)/u) / u, by their series below u = 1e-3
+__device__ double asin_over(double u) {
+#pragma clang fp contract(off)
+  return u < 1e-3 ? 1.0 + u * u / 6.0 : asin(u) / u;
+}
+__device__ double asin_over_d(double u) {
+#pragma clang fp contract(off)
+  return u < 1e-3 ? 1.0 / 3.0 + 0.3 * u * u : (u / sqrt(1.0 - u * u) - asin(u)) / (u * u * u);
+}
+
+// The state (y, z, sin(phi), tan(lambda), q/pT) at plane x turned by d into
+// another sector's frame: the point turns, so does the direction; the new
+// state lives at the turned point's x.  J (optional): the Jacobian of the
+// new state at the new plane against the old one (a shift of the track along
+// the old y, taken back to the new plane along the track; a turn of the
+// direction).  False when the direction reaches |sin| >= smx or cos <= 0.
+__device__ bool turn(const double p[5], double x, double d, double k, double smx, double q[5], double &xq,
+                     double *J) {
+#pragma clang fp contract(off)
+  const double cd = cos(d), sd = sin(d);
+  const double s = p[2];
+  if (!(fabs(s) < 1.0)) return false;
+  const double c = sqrt(1.0 - s * s);
+  const double s2 = s * cd - c * sd, c2 = c * cd + s * sd;
+  if (!(c2 > 0.0) || !(fabs(s2) < smx)) return false;
+  xq = x * cd + p[0] * sd;
+  q[0] = -x * sd + p[0] * cd;
+  q[1] = p[1];
+  q[2] = s2;
+  q[3] = p[3];
+  q[4] = p[4];
+  if (J) {
+    for (int i = 0; i < 25; ++i) J[i] = (i % 6 == 0) ? 1.0 : 0.0;
+    J[0] = c / c2;
+    J[5] = -sd * p[3] / c2;
+    J[10] = -k * p[4] * sd;
+    J[12] = c2 / c;
+  }
+  return true;
+}
+
+// Helix transport of the parameters from x1 to x2: sin(phi) grows by C dx,
+// y by dx (sin1 + sin2) / (cos1 + cos2), z by tan(lambda) times the arc
+// length sign(dx) L asin(u)/u (L the chord, u = |C| L / 2).  F (optional):
+// its Jacobian.  False when |sin(phi)| reaches smx at either end or u >= 1.
+__device__ bool carry(const double p[5], double x1, double x2, double k, double smx, double q[5], double *F) {
+#pragma clang fp contract(off)
+  const double dx = x2 - x1;
+  const double C = k * p[4];
+  const double s1 = p[2], s2 = s1 + C * dx;
+  if (!(fabs(s1) < smx) || !(fabs(s2) < smx)) return false;
+  const double c1 = sqrt(1.0 - s1 * s1), c2 = sqrt(1.0 - s2 * s2);
+  const double D = c1 + c2, N = s1 + s2;
+  const double dy = dx * N / D;
+  const double L = sqrt(dx * dx + dy * dy);
+  const double u = fabs(C) * L * 0.5;
+  if (!(u < 1.0)) return false;
+  const double sg = dx < 0 ? -1.0 : 1.0;
+  const double fu = asin_over(u);
+  const double sT = sg * L * fu;
+  q[0] = p[0] + dy;
+  q[1] = p[1] + p[3] * sT;
+  q[2] = s2;
+  q[3] = p[3];
+  q[4] = p[4];
+  if (F) {
+    for (int i = 0; i < 25; ++i) F[i] = (i % 6 == 0) ? 1.0 : 0.0;
+    const double a = dx * ((2.0 * D + N * (s1 / c1 + s2 / c2)) / (D * D));
+    const double b = dx * (k * dx * (D + N * s2 / c2) / (D * D));
+    const double g = asin_over_d(u);
+    const double dsdy = L > 0 ? sg * (dy / L) * (fu + u * u * g) : 0.0;
+    const double dsdC = sg * C * L * L * L * g * 0.25;
+    F[2] = a;
+    F[4] = b;
+    F[7] = p[3] * dsdy * a;
+    F[8] = sT;
+    F[9] = p[3] * (dsdy * b + dsdC * k);
+    F[14] = k * dx;
+  }
+  return true;
+}
+
+// C <- M C M^T (5x5, full products)
+__device__ void sandwich(const double M[25], double C[25]) {
+#pragma clang fp contract(off)
+  double T[25];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < 5; ++l) s += M[i * 5 + l] * C[l * 5 + j];
+      T[i * 5 + j] = s;
+    }
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < 5; ++l) s += T[i * 5 + l] * M[j * 5 + l];
+      C[i * 5 + j] = s;
+    }
+}
+
+__device__ void load_cov(const float *c15, double C[25]) {
+  int m = 0;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j) C[i * 5 + j] = C[j * 5 + i] = double(c15[m++]);
+}
+
+// r^T S^-1 r by Cholesky; -1 when S is not positive definite
+__device__ double chi2_solve(const double S[25], const double r[5]) {
+#pragma clang fp contract(off)
+  double L[25];
+  for (int i = 0; i < 25; ++i) L[i] = 0.0;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = S[i * 5 + j];
+      for (int m = 0; m < j; ++m) v -= L[i * 5 + m] * L[j * 5 + m];
+      if (i == j) {
+        if (!(v > 0.0)) return -1.0;
+        L[i * 5 + i] = sqrt(v);
+      } else {
+        L[i * 5 + j] = v / L[j * 5 + j];
+      }
+    }
+  double w[5], q = 0.0;
+  for (int i = 0; i < 5; ++i) {
+    double v = r[i];
+    for (int m = 0; m < i; ++m) v -= L[i * 5 + m] * w[m];
+    w[i] = v / L[i * 5 + i];
+    q += w[i] * w[i];
+  }
+  return q;
+}
+
+__device__ __forceinline__ double turn_angle(const MgArgs &A, int ua, int w) {
+  return remainder(double(A.alpha[w]) - double(A.alpha[ua]), TWO_PI);
+}
+
+// ---- kernels -------------------------------------------------------------------
+
+__global__ void __launch_bounds__(TPB) k_mg_init(MgArgs A) {
+  const int64_t T = n_tracks(A);
+  const int64_t nb = int64_t(A.n_units) * A.n_rows + 1;
+  const int64_t i0 = int64_t(blockIdx.x) * TPB + threadIdx.x, st = int64_t(gridDim.x) * TPB;
+  if (i0 == 0) {
+    *A.status = *A.trk_status != TPC_OK ? *A.trk_status : *A.rf_status;
+    A.ctr[0] = A.ctr[1] = A.ctr[2] = 0ull;
+  }
+  for (int64_t i = i0; i < nb; i += st) A.bin[i] = 0;
+  for (int64_t t = i0; t < T; t += st) {
+    A.next[t] = A.prev[t] = -1;
+    A.link_chi2[t] = 0.0;
+    A.ob_chi[t] = A.ib_chi[t] = NONE64;
+    A.ob_idx[t] = A.ib_idx[t] = INT32_MAX;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_mg_rows(MgArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t T = n_tracks(A);
+  bool bad = false;
+  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
+    const int n = A.n_hits[t], f = A.first_hit[t], u = A.unit[t];
+    int fr = 0, lr = 0;
+    if (n > 0) {
+      const int32_t h0 = A.hits[f], h1 = A.hits[f + n - 1];
+      if (h0 < 0 || h0 >= A.n_clusters || h1 < 0 || h1 >= A.n_clusters) {
+        bad = true;
+        continue;
+      }
+      fr = A.row[h0];
+      lr = A.row[h1];
+    }
+    if (u < 0 || u >= A.n_units || (A.side[u] != 1 && A.side[u] != -1) || fr >= A.n_rows || lr >= A.n_rows) {
+      bad = true;
+      continue;
+    }
+    A.rows[t] = fr | (lr << 16);
+    if (A.ok[t]) atomicAdd(&A.bin[u * A.n_rows + fr], 1);
+  }
+  if (bad) *A.status = TPC_E_INVALID;
+}
+
+// exclusive scan of the bin counts (one block), and the fill cursors
+__global__ void __launch_bounds__(SCAN_T) k_mg_scan(MgArgs A) {
+  __shared__ int32_t s[SCAN_T];
+  __shared__ int32_t carry_in;
+  if (*A.status != TPC_OK) return;
+  const int64_t nb = int64_t(A.n_units) * A.n_rows;
+  if (threadIdx.x == 0) carry_in = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 <= nb; b0 += SCAN_T) {
+    const int64_t b = b0 + threadIdx.x;
+    const int v = b < nb ? A.bin[b] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < SCAN_T; d <<= 1) {
+      const int a = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+      __syncthreads();
+      s[threadIdx.x] += a;
+      __syncthreads();
+    }
+    const int ex = carry_in + s[threadIdx.x] - v;
+    if (b <= nb) A.bin[b] = ex;
+    if (b < nb) A.cursor[b] = ex;
+    __syncthreads();
+    if (threadIdx.x == SCAN_T - 1) carry_in += s[SCAN_T - 1];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_mg_fill(MgArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t T = n_tracks(A);
+  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
+    if (!A.ok[t]) continue;
+    const int pos = atomicAdd(&A.cursor[A.unit[t] * A.n_rows + (A.rows[t] & 0xFFFF)], 1);
+    A.idx[pos] = int32_t(t);
+    A.zin[pos] = A.p_in[t * 5 + 1];
+    A.yin[pos] = A.p_in[t * 5];
+    A.xin[pos] = A.x_in[t];
+  }
+}
+
+// Slot of this lane in a list that the active lanes of its wave append to
+// together: one atomic per wave (a counter that every pair hit one by one
+// would serialize them), the lanes that append numbered in lane order.
+__device__ __forceinline__ unsigned long long append(unsigned long long &counter, bool take) {
+  const unsigned long long m = __ballot(take);
+  const int leader = __ffsll((long long)__ballot(1)) - 1;  // lowest active lane
+  unsigned long long base = 0;
+  if (__lane_id() == leader && m) base = atomicAdd(&counter, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader);
+  return base + __popcll(m & ((1ull << __lane_id()) - 1ull));
+}
+
+// z' as an unsigned key that orders like the float (negative values reversed)
+__device__ __forceinline__ uint32_t zkey(float z) {
+  const uint32_t u = __float_as_uint(z);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float zval(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__global__ void __launch_bounds__(64) k_mg_sort(MgArgs A) {
+  __shared__ unsigned long long key[SORT_MAX];
+  if (*A.status != TPC_OK) return;
+  const int64_t nb = int64_t(A.n_units) * A.n_rows;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {  // block-uniform
+    if (b % A.n_rows == 0) continue;  // a continuation never starts at row 0
+    const int32_t s0 = A.bin[b], n = A.bin[b + 1] - s0;
+    if (n <= 1) continue;
+    if (n > SORT_MAX) {  // rare: one lane, insertion sort in place
+      if (threadIdx.x == 0) {
+        for (int32_t i = 1; i < n; ++i) {
+          const float z = A.zin[s0 + i], y = A.yin[s0 + i], x = A.xin[s0 + i];
+          const int32_t id = A.idx[s0 + i];
+          int32_t j = i - 1;
+          for (; j >= 0 && A.zin[s0 + j] > z; --j) {
+            A.zin[s0 + j + 1] = A.zin[s0 + j];
+            A.yin[s0 + j + 1] = A.yin[s0 + j];
+            A.xin[s0 + j + 1] = A.xin[s0 + j];
+            A.idx[s0 + j + 1] = A.idx[s0 + j];
+          }
+          A.zin[s0 + j + 1] = z;
+          A.yin[s0 + j + 1] = y;
+          A.xin[s0 + j + 1] = x;
+          A.idx[s0 + j + 1] = id;
+        }
+      }
+      continue;
+    }
+    int np = 2;
+    while (np < n) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += 64)
+      key[i] = i < n ? (uint64_t(zkey(A.zin[s0 + i])) << 32) | uint32_t(A.idx[s0 + i]) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < np; i += 64) {
+          const int l = i ^ j;
+          if (l > i) {
+            const unsigned long long x = key[i], y = key[l];
+            if ((x > y) == ((i & k) == 0)) {
+              key[i] = y;
+              key[l] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = threadIdx.x; i < n; i += 64) {
+      const int32_t b2 = int32_t(uint32_t(key[i]));
+      A.zin[s0 + i] = zval(uint32_t(key[i] >> 32));
+      A.idx[s0 + i] = b2;
+      A.yin[s0 + i] = A.p_in[int64_t(b2) * 5];
+      A.xin[s0 + i] = A.x_in[b2];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t T = n_tracks(A);
+  for (int64_t a = int64_t(blockIdx.x) * TPB + threadIdx.x; a < T; a += int64_t(gridDim.x) * TPB) {
+    if (!A.ok[a]) continue;
+    const int ua = A.unit[a];
+    const int lr = A.rows[a] >> 16;
+    if (lr + 1 >= A.n_rows) continue;
+    const int r1 = min(lr + A.max_gap, A.n_rows - 1);
+    double pa[5];
+    for (int i = 0; i < 5; ++i) pa[i] = double(A.p_out[a * 5 + i]);
+    const double xa = double(A.x_out[a]);
+    const double za = pa[1];
+    for (int w = 0; w < A.n_units; ++w) {
+      if (A.side[w] != A.side[ua]) continue;
+      const double d = turn_angle(A, ua, w);
+      if (!(fabs(d) <= A.max_dalpha)) continue;
+      double q[5], xq = xa;
+      if (w == ua) {
+        for (int i = 0; i < 5; ++i) q[i] = pa[i];
+      } else if (!turn(pa, xa, d, A.k, A.smx, q, xq, nullptr)) {
+        continue;
+      }
+      for (int r = lr + 1; r <= r1; ++r) {
+        const int32_t s0 = A.bin[w * A.n_rows + r], s1 = A.bin[w * A.n_rows + r + 1];
+        if (s0 == s1) continue;
+        // the bin is sorted by z': its window [first with z' - z_a >= -dz_max,
+        // first with z' - z_a > dz_max) by two binary searches
+        int32_t lo = s0, hi = s1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (double(A.zin[mid]) - za < -A.dz_max) lo = mid + 1; else hi = mid;
+        }
+        int32_t l2 = lo, end = s1;
+        while (l2 < end) {
+          const int32_t mid = (l2 + end) >> 1;
+          if (double(A.zin[mid]) - za > A.dz_max) end = mid; else l2 = mid + 1;
+        }
+        for (int32_t s = lo; s < end; ++s) {
+          double c[5];
+          const bool pass = fabs(double(A.zin[s]) - za) <= A.dz_max &&
+                            carry(q, xq, double(A.xin[s]), A.k, A.smx, c, nullptr) &&
+                            fabs(double(A.yin[s]) - c[0]) <= A.dy_max;
+          const unsigned long long slot = append(A.ctr[0], pass);
+          if (pass && slot < (unsigned long long)A.cap_pairs) A.pairs[slot] = make_int2(int32_t(a), A.idx[s]);
+        }
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_mg_chi2(MgArgs A) {
+  if (*A.status != TPC_OK) return;
+  const unsigned long long np = A.ctr[0];
+  if (np > (unsigned long long)A.cap_pairs) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.status = TPC_E_CAPACITY;
+    return;
+  }
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < int64_t(np); i += int64_t(gridDim.x) * TPB) {
+    const int2 pr = A.pairs[i];
+    const int a = pr.x, b = pr.y;
+    const int ua = A.unit[a], ub = A.unit[b];
+    double pa[5], C[25], M[25], q[5], c[5];
+    for (int j = 0; j < 5; ++j) pa[j] = double(A.p_out[a * 5 + j]);
+    load_cov(A.c_out + int64_t(a) * 15, C);
+    double xq = double(A.x_out[a]);
+    double chi = -1.0;
+    bool ok = true;
+    if (ua != ub) {
+      ok = turn(pa, double(A.x_out[a]), turn_angle(A, ua, ub), A.k, A.smx, q, xq, M);
+      if (ok) sandwich(M, C);
+    } else {
+      for (int j = 0; j < 5; ++j) q[j] = pa[j];
+    }
+    if (ok) ok = carry(q, xq, double(A.x_in[b]), A.k, A.smx, c, M);
+    if (ok) {
+#pragma clang fp contract(off)
+      sandwich(M, C);
+      double Cb[25], r[5];
+      load_cov(A.c_in + int64_t(b) * 15, Cb);
+      for (int j = 0; j < 25; ++j) C[j] += Cb[j];
+      for (int j = 0; j < 5; ++j) r[j] = double(A.p_in[b * 5 + j]) - c[j];
+      chi = chi2_solve(C, r);
+    }
+    A.pair_chi[i] = chi;
+    const bool cand = chi >= 0.0 && chi <= A.chi2_max;
+    if (cand) {
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(chi);
+      atomicMin(&A.ob_chi[a], bits);
+      atomicMin(&A.ib_chi[b], bits);
+    }
+    append(A.ctr[1], cand);
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_mg_pick(MgArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t np = int64_t(A.ctr[0]);
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < np; i += int64_t(gridDim.x) * TPB) {
+    const double chi = A.pair_chi[i];
+    if (!(chi >= 0.0 && chi <= A.chi2_max)) continue;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(chi);
+    const int2 pr = A.pairs[i];
+    if (A.ob_chi[pr.x] == bits) atomicMin(&A.ob_idx[pr.x], pr.y);
+    if (A.ib_chi[pr.y] == bits) atomicMin(&A.ib_idx[pr.y], pr.x);
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_mg_link(MgArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t T = n_tracks(A);
+  for (int64_t a = int64_t(blockIdx.x) * TPB + threadIdx.x; a < T; a += int64_t(gridDim.x) * TPB) {
+    const int32_t b = A.ob_idx[a];
+    const bool link = b != INT32_MAX && A.ib_idx[b] == int32_t(a);
+    if (link) {
+      A.next[a] = b;
+      A.prev[b] = int32_t(a);
+      A.link_chi2[a] = __longlong_as_double((long long)A.ob_chi[a]);
+    }
+    append(A.ctr[2], link);
+  }
+}
+
+__global__ void k_mg_counts(MgArgs A) {
+  A.counts[0] = int64_t(A.ctr[0]);
+  A.counts[1] = int64_t(A.ctr[1]);
+  A.counts[2] = int64_t(A.ctr[2]);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t bin, cursor, idx, zin, yin, xin, rows, ob_chi, ib_chi, ob_idx, ib_idx, pairs, pair_chi, ctr, total;
+};
+
+Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.bin = take(size_t(nbins + 1) * 4);
+  L.cursor = take(size_t(nbins) * 4);
+  L.idx = take(size_t(cap_tracks) * 4);
+  L.zin = take(size_t(cap_tracks) * 4);
+  L.yin = take(size_t(cap_tracks) * 4);
+  L.xin = take(size_t(cap_tracks) * 4);
+  L.rows = take(size_t(cap_tracks) * 4);
+  L.ob_chi = take(size_t(cap_tracks) * 8);
+  L.ib_chi = take(size_t(cap_tracks) * 8);
+  L.ob_idx = take(size_t(cap_tracks) * 4);
+  L.ib_idx = take(size_t(cap_tracks) * 4);
+  L.pairs = take(size_t(cap_pairs) * 8);
+  L.pair_chi = take(size_t(cap_pairs) * 8);
+  L.ctr = take(4 * 8);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" size_t tpc_merge_workspace_size(int32_t n_units, int32_t n_rows, int64_t cap_tracks,
+                                           const tpc_merge_params_t *params) {
+  if (!params || n_units < 1 || n_rows < 3 || n_rows > 255 || cap_tracks < 0 || cap_tracks >= (int64_t(1) << 31) ||
+      params->cap_pairs < 0 || params->cap_pairs >= (int64_t(1) << 31) ||
+      int64_t(n_units) * n_rows >= (int64_t(1) << 30))
+    return 0;
+  return layout(int64_t(n_units) * n_rows, cap_tracks, params->cap_pairs).total;
+}
+
+extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry,
+                                const tpc_field_t *field, const tpc_tracks_t *tracks, const tpc_refit_t *refit,
+                                const float *unit_alpha, const int32_t *unit_side, int32_t n_units,
+                                const tpc_merge_params_t *params, tpc_merged_t *out, void *workspace,
+                                size_t workspace_bytes, void *stream) {
+  if (!clusters || !geometry || !field || !tracks || !refit || !params || !out || !unit_alpha || !unit_side)
+    return TPC_E_INVALID;
+  if (clusters->n < 0 || (clusters->n > 0 && !clusters->row) || !geometry->row_x) return TPC_E_INVALID;
+  if (!tracks->n_hits || !tracks->first_hit || !tracks->hits || !tracks->unit || !tracks->counts ||
+      !tracks->status || tracks->cap_tracks < 0)
+    return TPC_E_INVALID;
+  if (!refit->params || !refit->cov || !refit->x_ref || !refit->params_out || !refit->cov_out ||
+      !refit->x_out || !refit->ok || !refit->status)
+    return TPC_E_INVALID;
+  if (!out->next || !out->prev || !out->link_chi2 || !out->counts || !out->status) return TPC_E_INVALID;
+  if (!(params->max_dalpha >= 0.f) || params->max_gap < 1 || params->max_gap > 255 || !(params->dz_max >= 0.f) ||
+      !(params->dy_max >= 0.f) || !(params->chi2_max > 0.f) || !(params->sinphi_max > 0.f) ||
+      !(params->sinphi_max < 1.f) || !isfinite(field->bz_tesla))
+    return TPC_E_INVALID;
+  const size_t need = tpc_merge_workspace_size(n_units, geometry->n_rows, tracks->cap_tracks, params);
+  if (need == 0) return TPC_E_INVALID;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return TPC_E_INVALID;
+  if (workspace_bytes < need) return TPC_E_NOMEM;
+  MgArgs A;
+  A.row = clusters->row;
+  A.n_clusters = clusters->n;
+  A.n_rows = geometry->n_rows;
+  A.trk_status = tracks->status;
+  A.n_hits = tracks->n_hits;
+  A.first_hit = tracks->first_hit;
+  A.hits = tracks->hits;
+  A.unit = tracks->unit;
+  A.trk_counts = tracks->counts;
+  A.cap_tracks = tracks->cap_tracks;
+  A.p_in = refit->params;
+  A.c_in = refit->cov;
+  A.x_in = refit->x_ref;
+  A.p_out = refit->params_out;
+  A.c_out = refit->cov_out;
+  A.x_out = refit->x_out;
+  A.ok = refit->ok;
+  A.rf_status = refit->status;
+  A.alpha = unit_alpha;
+  A.side = unit_side;
+  A.n_units = n_units;
+  A.k = double(-float(KAPPA) * field->bz_tesla);  // the tracker's curvature constant, as its fit used it
+  A.smx = params->sinphi_max;
+  A.max_dalpha = params->max_dalpha;
+  A.dz_max = params->dz_max;
+  A.dy_max = params->dy_max;
+  A.chi2_max = params->chi2_max;
+  A.max_gap = params->max_gap;
+  A.cap_pairs = params->cap_pairs;
+  A.next = out->next;
+  A.prev = out->prev;
+  A.link_chi2 = out->link_chi2;
+  A.counts = out->counts;
+  A.status = out->status;
+  const int64_t nb = int64_t(n_units) * geometry->n_rows;
+  const Layout L = layout(nb, tracks->cap_tracks, params->cap_pairs);
+  char *w = static_cast<char *>(workspace);
+  A.bin = reinterpret_cast<int32_t *>(w + L.bin);
+  A.cursor = reinterpret_cast<int32_t *>(w + L.cursor);
+  A.idx = reinterpret_cast<int32_t *>(w + L.idx);
+  A.zin = reinterpret_cast<float *>(w + L.zin);
+  A.yin = reinterpret_cast<float *>(w + L.yin);
+  A.xin = reinterpret_cast<float *>(w + L.xin);
+  A.rows = reinterpret_cast<int32_t *>(w + L.rows);
+  A.ob_chi = reinterpret_cast<unsigned long long *>(w + L.ob_chi);
+  A.ib_chi = reinterpret_cast<unsigned long long *>(w + L.ib_chi);
+  A.ob_idx = reinterpret_cast<int32_t *>(w + L.ob_idx);
+  A.ib_idx = reinterpret_cast<int32_t *>(w + L.ib_idx);
+  A.pairs = reinterpret_cast<int2 *>(w + L.pairs);
+  A.pair_chi = reinterpret_cast<double *>(w + L.pair_chi);
+  A.ctr = reinterpret_cast<unsigned long long *>(w + L.ctr);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto blocks = [](int64_t n) { return unsigned(n < TPB ? 1 : ((n + TPB - 1) / TPB > MAX_BLOCKS ? MAX_BLOCKS : (n + TPB - 1) / TPB)); };
+  const int64_t T = tracks->cap_tracks;
+  hipLaunchKernelGGL(k_mg_init, dim3(blocks(T > nb + 1 ? T : nb + 1)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_mg_rows, dim3(blocks(T)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_mg_scan, dim3(1), dim3(SCAN_T), 0, st, A);
+  hipLaunchKernelGGL(k_mg_fill, dim3(blocks(T)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_mg_sort, dim3(unsigned(nb < MAX_BLOCKS ? nb : MAX_BLOCKS)), dim3(64), 0, st, A);
+  hipLaunchKernelGGL(k_mg_pairs, dim3(blocks(T)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_mg_chi2, dim3(blocks(params->cap_pairs)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_mg_pick, dim3(blocks(params->cap_pairs)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_mg_link, dim3(blocks(T)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_mg_counts, dim3(1), dim3(1), 0, st, A);
+  return hipGetLastError() == hipSuccess ? TPC_OK : TPC_E_HIP;
+}

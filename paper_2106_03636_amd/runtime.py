@@ -507,3 +507,72 @@ class Refitter:
                     params_out=self.o_params_out[:T], cov_out=self.o_cov_out[:T], x_out=self.o_xout[:T],
                     ok=self.o_ok[:T])
 
+    def struct(self):
+        """The tpc_refit_t of this refitter's outputs (the merger reads them)."""
+        from . import tpc_refit_t
+        o = tpc_refit_t()
+        o.params, o.cov, o.x_ref, o.chi2 = _ptr(self.o_params), _ptr(self.o_cov), _ptr(self.o_xref), _ptr(self.o_chi2)
+        o.params_out, o.cov_out, o.x_out = _ptr(self.o_params_out), _ptr(self.o_cov_out), _ptr(self.o_xout)
+        o.ok, o.status = _ptr(self.o_ok), _ptr(self.o_status)
+        return o
+
+
+class Merger:
+    """Outputs of tpc_merge_tracks for the tracks of a Tracker's last batch and
+    their refit (a Refitter launched on the same batch)."""
+
+    def __init__(self, refitter: Refitter, n_units: int, params=None):
+        from . import make_merge_params, tpc_merge_workspace_size
+        self.params = params if params is not None else make_merge_params()
+        self.refitter = refitter
+        self.tracker = refitter.tracker
+        self.device = d = self.tracker.device
+        T = max(1, self.tracker.cap_tracks)
+        self.n_units = int(n_units)
+        self.o_next = torch.empty(T, dtype=torch.int32, device=d)
+        self.o_prev = torch.empty(T, dtype=torch.int32, device=d)
+        self.o_chi2 = torch.empty(T, dtype=torch.float64, device=d)
+        self.o_counts = torch.zeros(3, dtype=torch.int64, device=d)
+        self.o_status = torch.zeros(1, dtype=torch.int32, device=d)
+        n_rows = self.tracker.n_rows if hasattr(self.tracker, "n_rows") else 152
+        self.ws_bytes = tpc_merge_workspace_size(self.n_units, n_rows, self.tracker.cap_tracks, self.params)
+        if self.ws_bytes == 0:
+            raise ValueError("tpc_merge_workspace_size rejected the arguments")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d)
+
+    def launch(self, batch: Batch, unit_alpha, unit_side, stream=None):
+        """Enqueue the links of the tracks of `batch`; unit_alpha (radians) and
+        unit_side (+1 / -1) per unit, host or device."""
+        from . import tpc_merge_tracks, tpc_merged_t
+        ua = torch.as_tensor(np.ascontiguousarray(unit_alpha, np.float32)).to(self.device) \
+            if not torch.is_tensor(unit_alpha) else unit_alpha
+        us = torch.as_tensor(np.ascontiguousarray(unit_side, np.int32)).to(self.device) \
+            if not torch.is_tensor(unit_side) else unit_side
+        if ua.numel() != self.n_units or us.numel() != self.n_units:
+            raise ValueError("unit_alpha and unit_side need %d entries" % self.n_units)
+        self._keep = (ua, us)
+        o = tpc_merged_t()
+        o.next, o.prev, o.link_chi2 = _ptr(self.o_next), _ptr(self.o_prev), _ptr(self.o_chi2)
+        o.counts, o.status = _ptr(self.o_counts), _ptr(self.o_status)
+        f = tpc_field_t()
+        f.bz_tesla = batch.bz
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = tpc_merge_tracks(batch.clusters_struct(), batch.geometry_struct(), f, self.tracker.tracks_struct(),
+                              self.refitter.struct(), _ptr(ua), _ptr(us), self.n_units, self.params, o,
+                              self.workspace.data_ptr(), self.ws_bytes, s.cuda_stream)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_merge_tracks: %s" % tpc_status_string(st))
+        return st
+
+    def result(self, n_tracks: int, sync=True):
+        if sync:
+            torch.cuda.synchronize(self.device)
+        st = int(self.o_status.item())
+        counts = self.o_counts.cpu().numpy()
+        if st != TPC_OK:
+            raise TrackingError(st, "merging failed on the device: %s (counts %s)"
+                                % (tpc_status_string(st), counts.tolist()))
+        T = n_tracks
+        return dict(next=self.o_next[:T], prev=self.o_prev[:T], link_chi2=self.o_chi2[:T],
+                    n_pairs=int(counts[0]), n_candidates=int(counts[1]), n_links=int(counts[2]))
+

@@ -90,3 +90,34 @@ class DeviceTracks:
                    params=o["trk_params"][tl].astype(np.float32), x_ref=o["trk_xref"][tl].astype(np.float32),
                    unit=o["trk_unit"][tl], cluster_track=o["cluster_track"], device=device)
 
+
+class DeviceRefit:
+    """A tpc_refit_t over device copies of a refit's host arrays (the dict
+    oracle.refit_tracks returns), rounded to FP32 as the refit call stores
+    them.  Stands in for a Refitter where the merger takes one (tracker,
+    struct())."""
+
+    def __init__(self, tracks: DeviceTracks, r, status=0):
+        import torch
+
+        from paper_2106_03636_amd import tpc_refit_t
+        d = tracks.device
+
+        def dev(a, dtype):
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype).reshape(-1)).to(d)
+            return t if t.numel() else torch.zeros(1, dtype=t.dtype, device=d)
+
+        self.tracker = tracks
+        self.arrays = dict(params=dev(r["p"], np.float32), cov=dev(r["cov"], np.float32),
+                           x_ref=dev(r["x_ref"], np.float32), chi2=dev(r["chi2"], np.float32),
+                           params_out=dev(r["p_out"], np.float32), cov_out=dev(r["cov_out"], np.float32),
+                           x_out=dev(r["x_out"], np.float32), ok=dev(r["ok"], np.uint8),
+                           status=dev(np.array([status]), np.int32))
+        s = tpc_refit_t()
+        for f, v in self.arrays.items():
+            setattr(s, f, v.data_ptr())
+        self._s = s
+
+    def struct(self):
+        return self._s
+

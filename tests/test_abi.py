@@ -38,7 +38,8 @@ def test_struct_layouts_match_header(tmp_path):
                "tpc_pad_geometry_t": T.tpc_pad_geometry_t, "tpc_digits_t": T.tpc_digits_t,
                "tpc_clusterizer_params_t": T.tpc_clusterizer_params_t, "tpc_cluster_out_t": T.tpc_cluster_out_t,
                "tpc_compress_params_t": T.tpc_compress_params_t, "tpc_compressed_t": T.tpc_compressed_t,
-               "tpc_refit_t": T.tpc_refit_t,
+               "tpc_refit_t": T.tpc_refit_t, "tpc_merge_params_t": T.tpc_merge_params_t,
+               "tpc_merged_t": T.tpc_merged_t,
                "tpc_server_config_t": S.tpc_server_config_t, "tpc_request_t": S.tpc_request_t,
                "tpc_result_t": S.tpc_result_t, "tpc_server_stats_t": S.tpc_server_stats_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tpc_track.h"', 'int main(void){']
@@ -189,6 +190,39 @@ def test_refit_host_checks():
         assert T.tpc_refit_tracks(c, g, f, T.make_params(**bad), trk, out, 0x8000, ws, 0) == T.TPC_E_INVALID, bad
     g.n_rows = 2
     assert T.tpc_refit_tracks(c, g, f, p, trk, out, 0x8000, ws, 0) == T.TPC_E_INVALID
+
+
+def test_merge_host_checks():
+    """Workspace sizes and the arguments tpc_merge_tracks rejects before any
+    device work."""
+    mp = T.make_merge_params(cap_pairs=1000)
+    ws = T.tpc_merge_workspace_size(36, 152, 5000, mp)
+    assert ws >= 36 * 152 * 8 + 5000 * 36 + 1000 * 16
+    assert T.tpc_merge_workspace_size(36, 152, 4000, mp) < ws
+    assert T.tpc_merge_workspace_size(36, 152, 5000, T.make_merge_params(cap_pairs=2000)) > ws
+    assert T.tpc_merge_workspace_size(0, 152, 5000, mp) == 0 and T.tpc_merge_workspace_size(36, 2, 5000, mp) == 0
+    assert T.tpc_merge_workspace_size(36, 152, -1, mp) == 0
+    c, g, f, trk, rf, out = (T.tpc_clusters_t(), T.tpc_geometry_t(), T.tpc_field_t(), T.tpc_tracks_t(),
+                             T.tpc_refit_t(), T.tpc_merged_t())
+    f.bz_tesla = 0.5
+    c.n, c.row = 100, 0x1000
+    g.n_rows, g.row_x = 152, 0x1000
+    trk.cap_tracks = 5000
+    trk.n_hits = trk.first_hit = trk.hits = trk.unit = trk.counts = trk.status = 0x2000
+    for name in ("params", "cov", "x_ref", "params_out", "cov_out", "x_out", "ok", "status"):
+        setattr(rf, name, 0x3000)
+    args = lambda ws_ptr, ws_bytes, params=mp, n_units=36: (c, g, f, trk, rf, 0x4000, 0x4000, n_units, params, out,  # noqa: E731
+                                                           ws_ptr, ws_bytes, 0)
+    assert T.tpc_merge_tracks(*args(0x8000, ws)) == T.TPC_E_INVALID  # no outputs
+    out.next = out.prev = out.link_chi2 = out.counts = out.status = 0x5000
+    assert T.tpc_merge_tracks(*args(0x8001, ws)) == T.TPC_E_INVALID  # misaligned
+    assert T.tpc_merge_tracks(*args(0, ws)) == T.TPC_E_INVALID
+    assert T.tpc_merge_tracks(*args(0x8000, ws - 1)) == T.TPC_E_NOMEM
+    assert T.tpc_merge_tracks(*args(0x8000, ws, n_units=0)) == T.TPC_E_INVALID
+    for bad in (dict(max_gap=0), dict(max_gap=256), dict(chi2_max=0.0), dict(sinphi_max=1.0), dict(dz_max=-1.0),
+                dict(dy_max=-1.0), dict(max_dalpha=-0.1)):
+        assert T.tpc_merge_tracks(*args(0x8000, 1 << 30, params=T.make_merge_params(cap_pairs=1000, **bad))) == \
+            T.TPC_E_INVALID, bad
 
 
 def test_status_strings():
