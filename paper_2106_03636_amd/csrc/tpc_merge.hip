@@ -6,20 +6,25 @@
 //
 // Launches on the caller's stream:
 //   k_mg_init   status, counters, per-track outputs and best-match keys;
-//   k_mg_rows   per track: first and last hit row, per (unit, first row)
-//               counts of the refitted segments;
+//   k_mg_rows   per track: first and last hit row; per (unit, z' cell)
+//               counts of the refitted segments that start after row 0
+//               (only those can continue another); cells are at least
+//               dz_max wide, so a z' window meets at most three;
 //   k_mg_scan   one block: bin offsets;
-//   k_mg_fill   segments filed by (unit, first row), with their inner z', y
-//               and x next to them (so the scan below reads contiguous
-//               memory, not the refit's arrays at random);
-//   k_mg_sort   one wave per (unit, row >= 1) bin: its segments sorted by z'
-//               (bitonic in LDS up to SORT_MAX; larger bins by one lane);
+//   k_mg_fill   those segments filed by (unit, z' cell);
+//   k_mg_sort   one wave per cell: its segments sorted by first row (bitonic
+//               in LDS up to SORT_MAX; larger cells by one lane), with their
+//               inner z', y, x and first row written next to them in that
+//               order (so the scan below reads contiguous memory);
 //   k_mg_pairs  one lane per segment a: for each unit on its side within
 //               max_dalpha, its outer state turned into that unit's frame
-//               (parameters, FP64); for each row 1 .. max_gap after its last
-//               one, two binary searches bound the z' window in that row's
-//               bin, whose segments get y carried along the helix
-//               (parameters only); pairs that pass go to a list;
+//               (parameters, FP64); in each cell its z' window meets, a
+//               binary search finds the first segment starting after a's
+//               last row, and the segments up to max_gap rows later are
+//               checked: z' window, then y carried along the helix
+//               (parameters only); pairs that pass are buffered per lane in
+//               LDS and go to a list with one atomic per lane at the end (an
+//               atomic per pair would make each wave wait on its return);
 //   k_mg_chi2   one lane per pair: the turn with its Jacobian, the helix
 //               transport with its Jacobian, both covariances summed, chi2
 //               by Cholesky (FP64); candidates take the least chi2 per
@@ -42,6 +47,7 @@ namespace {
 constexpr int TPB = 256;
 constexpr int SCAN_T = 1024;
 constexpr int SORT_MAX = 1024;  // bins sorted in LDS up to this size
+constexpr int PAIR_BUF = 16;   // pairs a lane of the scan buffers in LDS before it reserves list space
 constexpr int MAX_BLOCKS = 4096;
 constexpr double KAPPA = 0.00299792458;
 constexpr double TWO_PI = 6.283185307179586476925286766559;
@@ -67,6 +73,8 @@ struct MgArgs {
   // parameters
   double k, smx, max_dalpha, dz_max, dy_max, chi2_max;
   int32_t max_gap;
+  int32_t nzc;       // z' cells per unit
+  double zlo, cw;    // first cell's lower edge, cell width
   int64_t cap_pairs;
   // outputs
   int32_t *next, *prev;
@@ -78,6 +86,7 @@ struct MgArgs {
   int32_t *cursor;
   int32_t *idx;
   float *zin, *yin, *xin;  // inner z', y and x of the filed segments, in filing order
+  int32_t *frs;             // their first rows
   int32_t *rows;  // first row | last row << 16
   unsigned long long *ob_chi, *ib_chi;
   int32_t *ob_idx, *ib_idx;
@@ -175,6 +184,22 @@ __device__ bool carry(const double p[5], double x1, double x2, double k, double 
   return true;
 }
 
+// y of the parameters carried from x1 to x2 along the helix (the transport
+// above without the arc length); false where the transport fails.
+__device__ bool carry_y(const double p[5], double x1, double x2, double k, double smx, double &y) {
+#pragma clang fp contract(off)
+  const double dx = x2 - x1;
+  const double C = k * p[4];
+  const double s1 = p[2], s2 = s1 + C * dx;
+  if (!(fabs(s1) < smx) || !(fabs(s2) < smx)) return false;
+  const double c1 = sqrt(1.0 - s1 * s1), c2 = sqrt(1.0 - s2 * s2);
+  const double dy = dx * (s1 + s2) / (c1 + c2);
+  const double L = sqrt(dx * dx + dy * dy);
+  if (!(fabs(C) * L * 0.5 < 1.0)) return false;
+  y = p[0] + dy;
+  return true;
+}
+
 // C <- M C M^T (5x5, full products)
 __device__ void sandwich(const double M[25], double C[25]) {
 #pragma clang fp contract(off)
@@ -225,6 +250,11 @@ __device__ double chi2_solve(const double S[25], const double r[5]) {
   return q;
 }
 
+__device__ __forceinline__ int zcell(const MgArgs &A, double z) {
+  const double c = floor((z - A.zlo) / A.cw);
+  return c < 0.0 ? 0 : (c >= double(A.nzc) ? A.nzc - 1 : int(c));
+}
+
 __device__ __forceinline__ double turn_angle(const MgArgs &A, int ua, int w) {
   return remainder(double(A.alpha[w]) - double(A.alpha[ua]), TWO_PI);
 }
@@ -233,7 +263,7 @@ __device__ __forceinline__ double turn_angle(const MgArgs &A, int ua, int w) {
 
 __global__ void __launch_bounds__(TPB) k_mg_init(MgArgs A) {
   const int64_t T = n_tracks(A);
-  const int64_t nb = int64_t(A.n_units) * A.n_rows + 1;
+  const int64_t nb = int64_t(A.n_units) * A.nzc + 1;
   const int64_t i0 = int64_t(blockIdx.x) * TPB + threadIdx.x, st = int64_t(gridDim.x) * TPB;
   if (i0 == 0) {
     *A.status = *A.trk_status != TPC_OK ? *A.trk_status : *A.rf_status;
@@ -269,7 +299,7 @@ __global__ void __launch_bounds__(TPB) k_mg_rows(MgArgs A) {
       continue;
     }
     A.rows[t] = fr | (lr << 16);
-    if (A.ok[t]) atomicAdd(&A.bin[u * A.n_rows + fr], 1);
+    if (A.ok[t] && fr > 0) atomicAdd(&A.bin[u * A.nzc + zcell(A, double(A.p_in[t * 5 + 1]))], 1);
   }
   if (bad) *A.status = TPC_E_INVALID;
 }
@@ -279,7 +309,7 @@ __global__ void __launch_bounds__(SCAN_T) k_mg_scan(MgArgs A) {
   __shared__ int32_t s[SCAN_T];
   __shared__ int32_t carry_in;
   if (*A.status != TPC_OK) return;
-  const int64_t nb = int64_t(A.n_units) * A.n_rows;
+  const int64_t nb = int64_t(A.n_units) * A.nzc;
   if (threadIdx.x == 0) carry_in = 0;
   __syncthreads();
   for (int64_t b0 = 0; b0 <= nb; b0 += SCAN_T) {
@@ -306,68 +336,57 @@ __global__ void __launch_bounds__(TPB) k_mg_fill(MgArgs A) {
   if (*A.status != TPC_OK) return;
   const int64_t T = n_tracks(A);
   for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
-    if (!A.ok[t]) continue;
-    const int pos = atomicAdd(&A.cursor[A.unit[t] * A.n_rows + (A.rows[t] & 0xFFFF)], 1);
+    const int fr = A.rows[t] & 0xFFFF;
+    if (!A.ok[t] || fr == 0) continue;
+    const int pos = atomicAdd(&A.cursor[A.unit[t] * A.nzc + zcell(A, double(A.p_in[t * 5 + 1]))], 1);
     A.idx[pos] = int32_t(t);
-    A.zin[pos] = A.p_in[t * 5 + 1];
-    A.yin[pos] = A.p_in[t * 5];
-    A.xin[pos] = A.x_in[t];
+    A.frs[pos] = fr;
   }
 }
 
-// Slot of this lane in a list that the active lanes of its wave append to
-// together: one atomic per wave (a counter that every pair hit one by one
-// would serialize them), the lanes that append numbered in lane order.
-__device__ __forceinline__ unsigned long long append(unsigned long long &counter, bool take) {
+// Adds the number of active lanes with `take` to a counter: one atomic per
+// wave, whose result nobody waits for.
+__device__ __forceinline__ void count(unsigned long long &counter, bool take) {
   const unsigned long long m = __ballot(take);
   const int leader = __ffsll((long long)__ballot(1)) - 1;  // lowest active lane
-  unsigned long long base = 0;
-  if (__lane_id() == leader && m) base = atomicAdd(&counter, (unsigned long long)__popcll(m));
-  base = __shfl(base, leader);
-  return base + __popcll(m & ((1ull << __lane_id()) - 1ull));
+  if (__lane_id() == leader && m) atomicAdd(&counter, (unsigned long long)__popcll(m));
 }
 
-// z' as an unsigned key that orders like the float (negative values reversed)
-__device__ __forceinline__ uint32_t zkey(float z) {
-  const uint32_t u = __float_as_uint(z);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float zval(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+__device__ __forceinline__ void file_entry(const MgArgs &A, int32_t s, int32_t b, int32_t fr) {
+  A.idx[s] = b;
+  A.frs[s] = fr;
+  A.zin[s] = A.p_in[int64_t(b) * 5 + 1];
+  A.yin[s] = A.p_in[int64_t(b) * 5];
+  A.xin[s] = A.x_in[b];
 }
 
 __global__ void __launch_bounds__(64) k_mg_sort(MgArgs A) {
   __shared__ unsigned long long key[SORT_MAX];
   if (*A.status != TPC_OK) return;
-  const int64_t nb = int64_t(A.n_units) * A.n_rows;
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {  // block-uniform
-    if (b % A.n_rows == 0) continue;  // a continuation never starts at row 0
-    const int32_t s0 = A.bin[b], n = A.bin[b + 1] - s0;
-    if (n <= 1) continue;
-    if (n > SORT_MAX) {  // rare: one lane, insertion sort in place
+  const int64_t nb = int64_t(A.n_units) * A.nzc;
+  for (int64_t c = blockIdx.x; c < nb; c += gridDim.x) {  // block-uniform
+    const int32_t s0 = A.bin[c], n = A.bin[c + 1] - s0;
+    if (n == 0) continue;
+    if (n > SORT_MAX) {  // rare: one lane, insertion sort by (first row, index) in place
       if (threadIdx.x == 0) {
         for (int32_t i = 1; i < n; ++i) {
-          const float z = A.zin[s0 + i], y = A.yin[s0 + i], x = A.xin[s0 + i];
-          const int32_t id = A.idx[s0 + i];
+          const int32_t b = A.idx[s0 + i], fr = A.frs[s0 + i];
           int32_t j = i - 1;
-          for (; j >= 0 && A.zin[s0 + j] > z; --j) {
-            A.zin[s0 + j + 1] = A.zin[s0 + j];
-            A.yin[s0 + j + 1] = A.yin[s0 + j];
-            A.xin[s0 + j + 1] = A.xin[s0 + j];
+          for (; j >= 0 && (A.frs[s0 + j] > fr || (A.frs[s0 + j] == fr && A.idx[s0 + j] > b)); --j) {
             A.idx[s0 + j + 1] = A.idx[s0 + j];
+            A.frs[s0 + j + 1] = A.frs[s0 + j];
           }
-          A.zin[s0 + j + 1] = z;
-          A.yin[s0 + j + 1] = y;
-          A.xin[s0 + j + 1] = x;
-          A.idx[s0 + j + 1] = id;
+          A.idx[s0 + j + 1] = b;
+          A.frs[s0 + j + 1] = fr;
         }
+        for (int32_t i = 0; i < n; ++i) file_entry(A, s0 + i, A.idx[s0 + i], A.frs[s0 + i]);
       }
       continue;
     }
-    int np = 2;
+    int np = 1;
     while (np < n) np <<= 1;
     for (int i = threadIdx.x; i < np; i += 64)
-      key[i] = i < n ? (uint64_t(zkey(A.zin[s0 + i])) << 32) | uint32_t(A.idx[s0 + i]) : ~0ull;
+      key[i] = i < n ? (uint64_t(uint32_t(A.frs[s0 + i])) << 32) | uint32_t(A.idx[s0 + i]) : ~0ull;
     __syncthreads();
     for (int k = 2; k <= np; k <<= 1)
       for (int j = k >> 1; j > 0; j >>= 1) {
@@ -383,22 +402,30 @@ __global__ void __launch_bounds__(64) k_mg_sort(MgArgs A) {
         }
         __syncthreads();
       }
-    for (int i = threadIdx.x; i < n; i += 64) {
-      const int32_t b2 = int32_t(uint32_t(key[i]));
-      A.zin[s0 + i] = zval(uint32_t(key[i] >> 32));
-      A.idx[s0 + i] = b2;
-      A.yin[s0 + i] = A.p_in[int64_t(b2) * 5];
-      A.xin[s0 + i] = A.x_in[b2];
-    }
+    for (int i = threadIdx.x; i < n; i += 64)
+      file_entry(A, s0 + i, int32_t(uint32_t(key[i])), int32_t(key[i] >> 32));
     __syncthreads();
   }
 }
 
+// The lane's buffered pairs (a, buf[0 .. n)) written to the list at a
+// reserved range (one atomic per flush; past cap_pairs they are only counted).
+__device__ __forceinline__ void flush(const MgArgs &A, int32_t a, const int32_t *buf, int n) {
+  if (n == 0) return;
+  const unsigned long long base = atomicAdd(&A.ctr[0], (unsigned long long)n);
+  for (int i = 0; i < n; ++i)
+    if (base + i < (unsigned long long)A.cap_pairs) A.pairs[base + i] = make_int2(a, buf[i * TPB]);
+}
+
 __global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
+  // each lane's pair buffer: a column of a [PAIR_BUF][TPB] block (lanes side by side)
+  __shared__ int32_t pbuf[PAIR_BUF * TPB];
+  int32_t *buf = pbuf + threadIdx.x;
   if (*A.status != TPC_OK) return;
   const int64_t T = n_tracks(A);
   for (int64_t a = int64_t(blockIdx.x) * TPB + threadIdx.x; a < T; a += int64_t(gridDim.x) * TPB) {
     if (!A.ok[a]) continue;
+    int nbuf = 0;
     const int ua = A.unit[a];
     const int lr = A.rows[a] >> 16;
     if (lr + 1 >= A.n_rows) continue;
@@ -417,31 +444,32 @@ __global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
       } else if (!turn(pa, xa, d, A.k, A.smx, q, xq, nullptr)) {
         continue;
       }
-      for (int r = lr + 1; r <= r1; ++r) {
-        const int32_t s0 = A.bin[w * A.n_rows + r], s1 = A.bin[w * A.n_rows + r + 1];
+      const int c0 = zcell(A, za - A.dz_max), c1 = zcell(A, za + A.dz_max);
+      for (int cz = c0; cz <= c1; ++cz) {
+        const int32_t s0 = A.bin[w * A.nzc + cz], s1 = A.bin[w * A.nzc + cz + 1];
         if (s0 == s1) continue;
-        // the bin is sorted by z': its window [first with z' - z_a >= -dz_max,
-        // first with z' - z_a > dz_max) by two binary searches
+        // the cell is sorted by first row: the first segment starting after row lr
         int32_t lo = s0, hi = s1;
         while (lo < hi) {
           const int32_t mid = (lo + hi) >> 1;
-          if (double(A.zin[mid]) - za < -A.dz_max) lo = mid + 1; else hi = mid;
+          if (A.frs[mid] <= lr) lo = mid + 1; else hi = mid;
         }
-        int32_t l2 = lo, end = s1;
-        while (l2 < end) {
-          const int32_t mid = (l2 + end) >> 1;
-          if (double(A.zin[mid]) - za > A.dz_max) end = mid; else l2 = mid + 1;
-        }
-        for (int32_t s = lo; s < end; ++s) {
-          double c[5];
-          const bool pass = fabs(double(A.zin[s]) - za) <= A.dz_max &&
-                            carry(q, xq, double(A.xin[s]), A.k, A.smx, c, nullptr) &&
-                            fabs(double(A.yin[s]) - c[0]) <= A.dy_max;
-          const unsigned long long slot = append(A.ctr[0], pass);
-          if (pass && slot < (unsigned long long)A.cap_pairs) A.pairs[slot] = make_int2(int32_t(a), A.idx[s]);
+        for (int32_t s = lo; s < s1; ++s) {
+          const int fr = A.frs[s];
+          if (fr > r1) break;
+          double y;
+          if (!(fabs(double(A.zin[s]) - za) <= A.dz_max) || !carry_y(q, xq, double(A.xin[s]), A.k, A.smx, y) ||
+              !(fabs(double(A.yin[s]) - y) <= A.dy_max))
+            continue;
+          if (nbuf == PAIR_BUF) {
+            flush(A, int32_t(a), buf, nbuf);
+            nbuf = 0;
+          }
+          buf[nbuf++ * TPB] = A.idx[s];
         }
       }
     }
+    flush(A, int32_t(a), buf, nbuf);
   }
 }
 
@@ -485,7 +513,7 @@ __global__ void __launch_bounds__(TPB) k_mg_chi2(MgArgs A) {
       atomicMin(&A.ob_chi[a], bits);
       atomicMin(&A.ib_chi[b], bits);
     }
-    append(A.ctr[1], cand);
+    count(A.ctr[1], cand);
   }
 }
 
@@ -513,7 +541,7 @@ __global__ void __launch_bounds__(TPB) k_mg_link(MgArgs A) {
       A.prev[b] = int32_t(a);
       A.link_chi2[a] = __longlong_as_double((long long)A.ob_chi[a]);
     }
-    append(A.ctr[2], link);
+    count(A.ctr[2], link);
   }
 }
 
@@ -526,7 +554,7 @@ __global__ void k_mg_counts(MgArgs A) {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t bin, cursor, idx, zin, yin, xin, rows, ob_chi, ib_chi, ob_idx, ib_idx, pairs, pair_chi, ctr, total;
+  size_t bin, cursor, idx, zin, yin, xin, frs, rows, ob_chi, ib_chi, ob_idx, ib_idx, pairs, pair_chi, ctr, total;
 };
 
 Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
@@ -543,6 +571,7 @@ Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
   L.zin = take(size_t(cap_tracks) * 4);
   L.yin = take(size_t(cap_tracks) * 4);
   L.xin = take(size_t(cap_tracks) * 4);
+  L.frs = take(size_t(cap_tracks) * 4);
   L.rows = take(size_t(cap_tracks) * 4);
   L.ob_chi = take(size_t(cap_tracks) * 8);
   L.ib_chi = take(size_t(cap_tracks) * 8);
@@ -555,15 +584,35 @@ Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
   return L;
 }
 
+// z' cells of the candidate filing: at least dz_max wide where that keeps
+// the bins below 2^18 (a window then meets at most three cells), over
+// [-8256, 8256) cm (inputs lie within |z'| <= 8192; the rest is clamped).
+struct Cells {
+  int32_t nzc;
+  double zlo, cw;
+};
+Cells cells(const tpc_merge_params_t *p, int32_t n_units) {
+  constexpr double SPAN = 16512.0;
+  const int64_t most = (int64_t(1) << 18) / (n_units > 0 ? n_units : 1);
+  int64_t nz = p->dz_max > 0.f ? int64_t(SPAN / double(p->dz_max)) : most;
+  if (nz > most) nz = most;
+  if (nz > 65536) nz = 65536;
+  if (nz < 1) nz = 1;
+  Cells c;
+  c.nzc = int32_t(nz);
+  c.zlo = -SPAN / 2;
+  c.cw = SPAN / double(nz);
+  return c;
+}
+
 }  // namespace
 
 extern "C" size_t tpc_merge_workspace_size(int32_t n_units, int32_t n_rows, int64_t cap_tracks,
                                            const tpc_merge_params_t *params) {
   if (!params || n_units < 1 || n_rows < 3 || n_rows > 255 || cap_tracks < 0 || cap_tracks >= (int64_t(1) << 31) ||
-      params->cap_pairs < 0 || params->cap_pairs >= (int64_t(1) << 31) ||
-      int64_t(n_units) * n_rows >= (int64_t(1) << 30))
+      params->cap_pairs < 0 || params->cap_pairs >= (int64_t(1) << 31) || n_units > (1 << 18))
     return 0;
-  return layout(int64_t(n_units) * n_rows, cap_tracks, params->cap_pairs).total;
+  return layout(int64_t(n_units) * cells(params, n_units).nzc, cap_tracks, params->cap_pairs).total;
 }
 
 extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry,
@@ -624,7 +673,11 @@ extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   A.link_chi2 = out->link_chi2;
   A.counts = out->counts;
   A.status = out->status;
-  const int64_t nb = int64_t(n_units) * geometry->n_rows;
+  const Cells cz = cells(params, n_units);
+  A.nzc = cz.nzc;
+  A.zlo = cz.zlo;
+  A.cw = cz.cw;
+  const int64_t nb = int64_t(n_units) * cz.nzc;
   const Layout L = layout(nb, tracks->cap_tracks, params->cap_pairs);
   char *w = static_cast<char *>(workspace);
   A.bin = reinterpret_cast<int32_t *>(w + L.bin);
@@ -633,6 +686,7 @@ extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   A.zin = reinterpret_cast<float *>(w + L.zin);
   A.yin = reinterpret_cast<float *>(w + L.yin);
   A.xin = reinterpret_cast<float *>(w + L.xin);
+  A.frs = reinterpret_cast<int32_t *>(w + L.frs);
   A.rows = reinterpret_cast<int32_t *>(w + L.rows);
   A.ob_chi = reinterpret_cast<unsigned long long *>(w + L.ob_chi);
   A.ib_chi = reinterpret_cast<unsigned long long *>(w + L.ib_chi);
