@@ -113,6 +113,8 @@ def _load():
         lib.orc_merge.restype = ctypes.c_int64
         lib.orc_merge.argtypes = ([ctypes.c_int64] + [vp] * 10 + [ctypes.c_int32, vp, vp, ctypes.c_int32] +
                                   [ctypes.c_double] * 3 + [ctypes.c_int32] + [ctypes.c_double] * 4 + [vp] * 4)
+        lib.orc_refit_chains.restype = None
+        lib.orc_refit_chains.argtypes = [ctypes.c_int64] + [vp] * 9 + [ctypes.c_double, ctypes.POINTER(Params)] + [vp] * 5
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -420,4 +422,53 @@ def merge(unit, first_row, last_row, refit, unit_alpha, unit_side, n_rows, k, si
                            float(dy_max), float(chi2_max), float(eps),
                            nxt.ctypes.data, prv.ctypes.data, lc.ctypes.data, frag.ctypes.data)
     return dict(next=nxt, prev=prv, link_chi2=lc, fragile=frag, n_candidates=int(n_cand))
+
+
+def chains(next_, prev, first_hit, n_hits, hits, unit):
+    """The merged chains of linked segments (prev = -1, next >= 0 at the head):
+    per chain its head, its hit list (the segments' hit lists in chain order)
+    and each hit's unit.  Returns (heads, chain_first, chain_n, chain_hits,
+    hit_unit)."""
+    next_ = np.asarray(next_)
+    heads = np.nonzero((np.asarray(prev) < 0) & (next_ >= 0))[0]
+    cf, cn, ch, cu = [], [], [], []
+    pos = 0
+    for h in heads:
+        cf.append(pos)
+        t = int(h)
+        n = 0
+        while t >= 0:
+            f, m = int(first_hit[t]), int(n_hits[t])
+            ch.append(np.asarray(hits[f:f + m]))
+            cu.append(np.full(m, unit[t], np.int32))
+            n += m
+            t = int(next_[t])
+        cn.append(n)
+        pos += n
+    cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
+    return (heads.astype(np.int64), np.array(cf, np.int32), np.array(cn, np.int32), cat(ch, np.int32),
+            cat(cu, np.int32))
+
+
+def refit_chains(chain_first, chain_n, chain_hits, hit_unit, y, z, row, row_x, unit_alpha, k, values: dict):
+    """Two-pass fit of merged chains across frames (see orc_fit_chain)."""
+    lib = _load()
+    cf = np.ascontiguousarray(chain_first, np.int32)
+    cn = np.ascontiguousarray(chain_n, np.int32)
+    ch = np.ascontiguousarray(chain_hits, np.int32)
+    cu = np.ascontiguousarray(hit_unit, np.int32)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    row = np.ascontiguousarray(row, np.uint16)
+    row_x = np.ascontiguousarray(row_x, np.float64)
+    ua = np.ascontiguousarray(unit_alpha, np.float64)
+    C = len(cn)
+    if len(ch):
+        assert ch.min() >= 0 and ch.max() < len(y) and cu.min() >= 0 and cu.max() < len(ua)
+    P = make_params(values)
+    out = dict(p=np.zeros((C, 5)), cov=np.zeros((C, 15)), x_ref=np.zeros(C), chi2=np.zeros(C), ok=np.zeros(C, np.int8))
+    lib.orc_refit_chains(C, cf.ctypes.data, cn.ctypes.data, ch.ctypes.data, cu.ctypes.data, y.ctypes.data,
+                         z.ctypes.data, row.ctypes.data, row_x.ctypes.data, ua.ctypes.data, float(k), ctypes.byref(P),
+                         *[out[key].ctypes.data for key in ("p", "cov", "x_ref", "chi2", "ok")])
+    return out
 

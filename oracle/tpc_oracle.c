@@ -1622,6 +1622,107 @@ int64_t orc_merge(int64_t T, const int32_t *unit, const int32_t *first_row, cons
   return n_cand;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Fit of a merged chain of segments (Reading R-25): the hits of linked       */
+/* segments in chain order (segment by segment, rows increasing inside each), */
+/* hit j measured in its unit's frame (angle unit_alpha[u[j]]) at x[j] with   */
+/* y[j], z[j].  Seed: the three-point circle through the first, middle (n/2)  */
+/* and last hit, their positions turned into the first hit's frame.  Pass 1   */
+/* from hit 0: before a hit of another frame the state, and its covariance by */
+/* the turn's Jacobian, is turned into that frame, then carried to the hit    */
+/* and updated.  Pass 2 from hit n-1 back, the covariance reset, turning back */
+/* at each change of frame.  Output: the state at hit 0, in its frame.        */
+
+static int turn_state(kstate_t *s, double d_raw, double k, const orc_params_t *P) {
+  const double d = remainder(d_raw, 2.0 * M_PI_ORC);
+  double q[5], xq, J[25];
+  if (orc_rotate(s->p, s->x, d, k, P->sinphi_max, q, &xq, J) != 0) return -1;
+  memcpy(s->p, q, sizeof(q));
+  s->x = xq;
+  transport_cov(J, s->cov);
+  return 0;
+}
+
+/* Returns 0, or -1 when n < 3 or the seed, a turn or a transport fails. */
+int orc_fit_chain(int n, const double *x, const double *y, const double *z, const int32_t *u,
+                  const double *unit_alpha, double k, const orc_params_t *P, double p_out[5],
+                  double cov_out[15], double *chi2) {
+  if (n < 3) return -1;
+  const int js[3] = {0, n / 2, n - 1};
+  double sx[3], sy[3], sz[3];
+  for (int i = 0; i < 3; ++i) { /* the point of hit js[i] in hit 0's frame */
+    const int j = js[i];
+    const double d = remainder(unit_alpha[u[0]] - unit_alpha[u[j]], 2.0 * M_PI_ORC);
+    const double cd = cos(d), sd = sin(d);
+    sx[i] = x[j] * cd + y[j] * sd;
+    sy[i] = -x[j] * sd + y[j] * cd;
+    sz[i] = z[j];
+  }
+  kstate_t s;
+  int fr = 0, cu = u[0];
+  if (orc_seed(sx, sy, sz, k, P->sinphi_max, s.p) != 0) return -1;
+  cov_init(s.cov, P);
+  s.x = x[0];
+  s.chi2 = 0;
+  for (int j = 0; j < n; ++j) {
+    if (j > 0) {
+      if (u[j] != cu) {
+        if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;
+        cu = u[j];
+      }
+      if (step_to(&s, x[j], k, P, &fr) != 0) return -1;
+    }
+    kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
+  }
+  cov_init(s.cov, P);
+  s.chi2 = 0;
+  kf_update(s.p, s.cov, y[n - 1], z[n - 1], P->sigma_y, P->sigma_z, &s.chi2);
+  for (int j = n - 2; j >= 0; --j) {
+    if (u[j] != cu) {
+      if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;
+      cu = u[j];
+    }
+    if (step_to(&s, x[j], k, P, &fr) != 0) return -1;
+    kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
+  }
+  memcpy(p_out, s.p, sizeof(s.p));
+  pack_cov(s.cov, cov_out);
+  *chi2 = s.chi2;
+  return 0;
+}
+
+/* The chains of a batch: chain c's hits are the cluster ids
+ * hits[first[c] .. first[c] + nh[c]) with units hit_unit[...], measured as the
+ * tracker measures them (quanta of 1/256 cm at the rows' x).  ok[c] = 1 when
+ * the fit succeeded, else every output of the chain is zero. */
+void orc_refit_chains(int64_t n_chains, const int32_t *first, const int32_t *nh, const int32_t *hits,
+                      const int32_t *hit_unit, const float *y, const float *z, const uint16_t *row,
+                      const double *row_x, const double *unit_alpha, double k, const orc_params_t *P,
+                      double *p, double *cov, double *x_ref, double *chi2, int8_t *ok) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t c = 0; c < n_chains; ++c) {
+    const int n = nh[c];
+    double *X = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *Y = X + n, *Z = X + 2 * n;
+    for (int j = 0; j < n; ++j) {
+      const int32_t h = hits[first[c] + j];
+      X[j] = row_x[row[h]];
+      Y[j] = nearbyint(256.0 * (double)y[h]) / 256.0;
+      Z[j] = nearbyint(256.0 * (double)z[h]) / 256.0;
+    }
+    const int st = orc_fit_chain(n, X, Y, Z, hit_unit + first[c], unit_alpha, k, P, p + c * 5, cov + c * 15,
+                                 chi2 + c);
+    ok[c] = st == 0;
+    x_ref[c] = st == 0 ? X[0] : 0.0;
+    if (st != 0) {
+      memset(p + c * 5, 0, 5 * sizeof(double));
+      memset(cov + c * 15, 0, 15 * sizeof(double));
+      chi2[c] = 0.0;
+    }
+    free(X);
+  }
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -231,3 +231,104 @@ def test_links_on_a_central_collision_follow_the_particles():
             wanted += 1
             linked += m["next"][A] == B
     assert wanted > 5000 and linked / wanted > 0.9, (wanted, linked)
+
+
+# ----------------------------------------------------------------------------
+# fit of merged chains across frames
+
+def _crossing_chains(seed=23, n=400):
+    """Generator helices that cross from one sector into its neighbour on the
+    same side: their first-leg crossings in the first sector, then in the
+    second, as (rows_a, states_a, rows_b, states_b, sector_a, sector_b)."""
+    rng = np.random.default_rng(seed)
+    tr = synth.primaries_pp_sector(rng, n, 0, pt_range=(0.3, 2.0))
+    xs = synth.helix_crossings(tr, 0.5)
+    out = []
+    for t in range(len(tr)):
+        m = np.nonzero((xs["track"] == t) & (xs["cosphi"] > 0))[0]
+        if len(m) < 20:
+            continue
+        m = m[np.argsort(xs["s"][m])]
+        sec = xs["sector"][m]
+        if len(np.unique(sec)) != 2 or np.any(np.diff(xs["row"][m]) <= 0):
+            continue
+        cut = int(np.nonzero(sec != sec[0])[0][0])
+        if np.any(sec[cut:] != sec[cut]) or cut < 8 or len(m) - cut < 8:
+            continue
+        qpt = tr.q[t] / tr.pt[t]
+        st = [np.array([xs["y"][j], xs["z"][j], xs["sinphi"][j], tr.tgl[t], qpt]) for j in m]
+        out.append((xs["row"][m[:cut]], st[:cut], xs["row"][m[cut:]], st[cut:], int(sec[0]), int(sec[cut])))
+    return out
+
+
+def test_chain_fit_of_helices_across_two_sectors_gives_the_helix():
+    """Noise-free helices measured in two sector frames: the chain fit (turns
+    at the boundary in both passes) returns the helix's state at the first hit
+    within 0.1 sigma (quantization of the positions only) and a chi2 far below
+    one per hit."""
+    cases = _crossing_chains()
+    assert len(cases) > 20
+    for ra, sa, rb, sb, seca, secb in cases:
+        n = len(ra) + len(rb)
+        y = np.array([s[0] for s in sa + sb], np.float32)
+        z = np.array([s[1] for s in sa + sb], np.float32)
+        row = np.concatenate([ra, rb]).astype(np.uint16)
+        units = np.array([0] * len(ra) + [1] * len(rb), np.int32)
+        alpha = [synth.sector_alpha(seca), synth.sector_alpha(secb)]
+        r = oracle.refit_chains([0], [n], np.arange(n), units, y, z, row, synth.ROW_X, alpha, K_CURV, P)
+        assert r["ok"][0] and r["x_ref"][0] == synth.ROW_X[ra[0]]
+        sig = np.sqrt(r["cov"][0][[0, 2, 5, 9, 14]])
+        assert np.all(np.abs(r["p"][0] - sa[0]) <= 0.1 * sig), (r["p"][0], sa[0], sig)
+        assert r["chi2"][0] < 0.01 * n
+
+
+def test_chain_of_one_frame_is_the_track_refit():
+    """A chain whose hits all lie in one unit is fitted exactly as the track
+    refit fits the same hit list (no turn happens)."""
+    cases = _crossing_chains(seed=29)
+    for ra, sa, _, _, seca, _ in cases[:10]:
+        n = len(ra)
+        y = np.array([s[0] for s in sa], np.float32)
+        z = np.array([s[1] for s in sa], np.float32)
+        row = ra.astype(np.uint16)
+        r = oracle.refit_chains([0], [n], np.arange(n), np.zeros(n, np.int32), y, z, row, synth.ROW_X,
+                                [synth.sector_alpha(seca)], K_CURV, P)
+        q = oracle.refit_tracks([0], [n], np.arange(n), y, z, row, synth.ROW_X, K_CURV, P)
+        for key in ("p", "cov", "chi2", "x_ref", "ok"):
+            assert np.array_equal(r[key][0], q[key][0]), key
+
+
+def test_chains_follow_the_links():
+    """oracle.chains: heads are segments with no prev and a next; a chain's
+    hit list is its segments' hit lists in link order."""
+    nxt = np.array([2, -1, 3, -1, -1])
+    prv = np.array([-1, -1, 0, 2, -1])
+    first = np.array([0, 3, 5, 9, 12])
+    nh = np.array([3, 2, 4, 3, 2])
+    hits = np.arange(14) + 100
+    unit = np.array([0, 1, 1, 2, 0])
+    heads, cf, cn, ch, cu = oracle.chains(nxt, prv, first, nh, hits, unit)
+    assert heads.tolist() == [0] and cf.tolist() == [0] and cn.tolist() == [10]
+    assert ch.tolist() == [100, 101, 102, 105, 106, 107, 108, 109, 110, 111]
+    assert cu.tolist() == [0, 0, 0, 1, 1, 1, 1, 2, 2, 2]
+
+
+def test_chain_fit_on_a_central_collision():
+    """The linked chains of a central collision fitted across frames: almost
+    all succeed, chi2 per degree of freedom about 1, and q/pT is measured far
+    better than by the chain's first segment alone (a longer lever arm;
+    measured 0.16% against 1.84% median relative error)."""
+    ev, o, r, unit, fr, lr, alpha, side, m = merge_event("pbpb_central")
+    first, nh, hits = o["track_first_hit"], o["track_n_hits"], o["track_hits"]
+    heads, cf, cn, ch, cu = oracle.chains(m["next"], m["prev"], first, nh, hits, unit)
+    k = float(np.float32(-np.float32(synth.KAPPA) * np.float32(ev.bz)))
+    rc = oracle.refit_chains(cf, cn, ch, cu, ev.y, ev.z, ev.row, ev.row_x.astype(np.float64), alpha, k, P)
+    ok = rc["ok"].astype(bool)
+    assert len(heads) > 10000 and ok.mean() > 0.99
+    assert 0.9 < np.median(rc["chi2"][ok] / (2 * cn[ok] - 5)) < 1.1
+    maj = _maj(ev.label, first, nh, hits)[heads]
+    g = ok & (maj >= 0)
+    true_qpt = ev.tracks.q[maj[g]] / ev.tracks.pt[maj[g]]
+    chain_err = np.median(np.abs(rc["p"][g, 4] / true_qpt - 1))
+    head_err = np.median(np.abs(r["p"][heads[g], 4] / true_qpt - 1))
+    assert chain_err < head_err / 4, (chain_err, head_err)

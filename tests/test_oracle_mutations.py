@@ -172,6 +172,14 @@ MUTATIONS = [
     ("merge_no_y_window",
      "          if (!(fabs(p_in[b * 5] - yc[0]) <= dy_max)) continue;\n", "",
      [mrg.test_hand_worked_rules]),
+    ("chain_turn_backwards",
+     "        if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;",
+     "        if (turn_state(&s, unit_alpha[cu] - unit_alpha[u[j]], k, P) != 0) return -1;",
+     [mrg.test_chain_fit_of_helices_across_two_sectors_gives_the_helix]),
+    ("chain_pass2_without_turn",
+     "      if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;\n      cu = u[j];",
+     "      cu = u[j];",
+     [mrg.test_chain_fit_of_helices_across_two_sectors_gives_the_helix]),
     ("merge_across_sides",
      "      if (unit_side[w] != unit_side[unit[a]]) continue;\n", "",
      [mrg.test_hand_worked_rules]),
