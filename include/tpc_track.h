@@ -513,6 +513,49 @@ int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geometry_t *geome
                      const int32_t *unit_side, int32_t n_units, const tpc_merge_params_t *params,
                      tpc_merged_t *out, void *workspace, size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------- */
+/* Fit of merged chains.  A chain is a run of linked segments (a            */
+/* tpc_merge_tracks output): its head has no prev and a next.  Its hits are */
+/* its segments' hit lists in link order, each measured in its own unit's   */
+/* frame (quanta of 1/256 cm at the row's x).  The fit is the refit's       */
+/* two-pass FP32 filter across frames:                                      */
+/*   - seed: the circle through the first, middle (n/2) and last hit, their  */
+/*     positions turned into the first hit's frame;                          */
+/*   - pass 1 from the first hit: before a hit of another frame the state is */
+/*     turned into that frame (the merger's turn; the covariance by its     */
+/*     Jacobian), then carried to the hit and updated;                       */
+/*   - pass 2 from the last hit back, covariance reset to diag(cov0),       */
+/*     turning back at each change of frame;                                 */
+/*   - the result is the state at the chain's first hit, in its frame.     */
+/* A chain of fewer than 3 hits, or whose seed, a turn or a transport       */
+/* fails, is not fitted (ok = 0, outputs zero).                              */
+/* ------------------------------------------------------------------------- */
+
+/* Outputs, indexed by the chain's head track (device pointers; per-track
+ * arrays of at least the tracking output's cap_tracks entries). */
+typedef struct tpc_chain_fit {
+  float *params;               /* [cap_tracks][5] at x_ref, in the head segment's frame */
+  float *cov;                  /* [cap_tracks][15] lower triangle, row-major */
+  float *x_ref;                /* [cap_tracks] x of the chain's first hit */
+  float *chi2;                 /* [cap_tracks] chi2 of pass 2 (ndf = 2 n_hits - 5) */
+  int32_t *n_hits;             /* [cap_tracks] hits of the chain headed by this track, 0 if none */
+  uint8_t *ok;                 /* [cap_tracks] 1 fitted, 0 not (or not a head) */
+  int32_t *status;             /* [1] TPC_OK, the tracker's or the merger's own status when not TPC_OK,
+                                  or TPC_E_INVALID (a hit names no cluster of the batch or one out of
+                                  range, or the links do not form chains of at most 64 segments);
+                                  outputs are valid only with TPC_OK */
+} tpc_chain_fit_t;
+
+/* Fit the chains of a tpc_merge_tracks output: the tracking call's clusters,
+ * geometry, field, tracking parameters (sigma_y, sigma_z, cov0, sinphi_max)
+ * and output (n_hits, first_hit, hits, unit, counts, status), the merger's
+ * next / prev / status, and the unit angles it used.  No workspace.
+ * Enqueued on `stream` after those calls.  Returns TPC_OK when the work was
+ * enqueued, TPC_E_INVALID on bad arguments, TPC_E_HIP on a launch failure. */
+int tpc_fit_chains(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry, const tpc_field_t *field,
+                   const tpc_params_t *params, const tpc_tracks_t *tracks, const tpc_merged_t *merged,
+                   const float *unit_alpha, int32_t n_units, tpc_chain_fit_t *out, void *stream);
+
 /* Intermediate arrays kept in the workspace after a call, for inspection and
  * tests.  Valid until the workspace is reused.  `what` selects the array:
  *   TPC_VIEW_PERM      int32 [n]  sorted position -> cluster id

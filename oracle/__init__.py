@@ -114,7 +114,8 @@ def _load():
         lib.orc_merge.argtypes = ([ctypes.c_int64] + [vp] * 10 + [ctypes.c_int32, vp, vp, ctypes.c_int32] +
                                   [ctypes.c_double] * 3 + [ctypes.c_int32] + [ctypes.c_double] * 4 + [vp] * 4)
         lib.orc_refit_chains.restype = None
-        lib.orc_refit_chains.argtypes = [ctypes.c_int64] + [vp] * 9 + [ctypes.c_double, ctypes.POINTER(Params)] + [vp] * 5
+        lib.orc_refit_chains.argtypes = ([ctypes.c_int64] + [vp] * 9 + [ctypes.c_int32, ctypes.c_double,
+                                          ctypes.POINTER(Params)] + [vp] * 5)
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -468,7 +469,8 @@ def refit_chains(chain_first, chain_n, chain_hits, hit_unit, y, z, row, row_x, u
     P = make_params(values)
     out = dict(p=np.zeros((C, 5)), cov=np.zeros((C, 15)), x_ref=np.zeros(C), chi2=np.zeros(C), ok=np.zeros(C, np.int8))
     lib.orc_refit_chains(C, cf.ctypes.data, cn.ctypes.data, ch.ctypes.data, cu.ctypes.data, y.ctypes.data,
-                         z.ctypes.data, row.ctypes.data, row_x.ctypes.data, ua.ctypes.data, float(k), ctypes.byref(P),
+                         z.ctypes.data, row.ctypes.data, row_x.ctypes.data, ua.ctypes.data, len(ua), float(k),
+                         ctypes.byref(P),
                          *[out[key].ctypes.data for key in ("p", "cov", "x_ref", "chi2", "ok")])
     return out
 

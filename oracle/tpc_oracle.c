@@ -728,6 +728,105 @@ int orc_fit_two_pass(int n, const double *x, const double *y, const double *z, d
   return fit_two_pass(n, x, y, z, k, P, p_out, cov_out, chi2, p1_out, NULL, NULL);
 }
 
+/* The turn between sector frames (used by the merger below the driver and by
+ * the chain fit here; see the merger's section for the derivation). */
+/* Turn state p at plane x by d.  Returns 0, or -1 when the direction reaches
+ * |sin(phi')| >= sinphi_max or cos(phi') <= 0 (the state cannot describe a
+ * track moving inward in the new frame). */
+int orc_rotate(const double p[5], double x, double d, double k, double sinphi_max, double out[5], double *x_out,
+               double J[25]) {
+  const double cd = cos(d), sd = sin(d);
+  const double s = p[2];
+  if (!(fabs(s) < 1.0)) return -1;
+  const double c = sqrt(1.0 - s * s);
+  const double s2 = s * cd - c * sd, c2 = c * cd + s * sd;
+  if (!(c2 > 0.0) || !(fabs(s2) < sinphi_max)) return -1;
+  *x_out = x * cd + p[0] * sd;
+  out[0] = -x * sd + p[0] * cd;
+  out[1] = p[1];
+  out[2] = s2;
+  out[3] = p[3];
+  out[4] = p[4];
+  if (J) {
+    memset(J, 0, 25 * sizeof(double));
+    for (int i = 0; i < 5; ++i) J[i * 5 + i] = 1.0;
+    J[0 * 5 + 0] = c / c2;
+    J[1 * 5 + 0] = -sd * p[3] / c2;
+    J[2 * 5 + 0] = -k * p[4] * sd;
+    J[2 * 5 + 2] = c2 / c;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fit of a merged chain of segments (Reading R-25): the hits of linked       */
+/* segments in chain order (segment by segment, rows increasing inside each), */
+/* hit j measured in its unit's frame (angle unit_alpha[u[j]]) at x[j] with   */
+/* y[j], z[j].  Seed: the three-point circle through the first, middle (n/2)  */
+/* and last hit, their positions turned into the first hit's frame.  Pass 1   */
+/* from hit 0: before a hit of another frame the state, and its covariance by */
+/* the turn's Jacobian, is turned into that frame, then carried to the hit    */
+/* and updated.  Pass 2 from hit n-1 back, the covariance reset, turning back */
+/* at each change of frame.  Output: the state at hit 0, in its frame.        */
+
+static int turn_state(kstate_t *s, double d_raw, double k, const orc_params_t *P) {
+  const double d = remainder(d_raw, 2.0 * M_PI_ORC);
+  double q[5], xq, J[25];
+  if (orc_rotate(s->p, s->x, d, k, P->sinphi_max, q, &xq, J) != 0) return -1;
+  memcpy(s->p, q, sizeof(q));
+  s->x = xq;
+  transport_cov(J, s->cov);
+  return 0;
+}
+
+/* Returns 0, or -1 when n < 3 or the seed, a turn or a transport fails. */
+int orc_fit_chain(int n, const fit_real *x, const fit_real *y, const fit_real *z, const int32_t *u,
+                  const fit_real *unit_alpha, fit_real k, const orc_params_t *P, fit_real p_out[5],
+                  fit_real cov_out[15], fit_real *chi2) {
+  if (n < 3) return -1;
+  const int js[3] = {0, n / 2, n - 1};
+  double sx[3], sy[3], sz[3];
+  for (int i = 0; i < 3; ++i) { /* the point of hit js[i] in hit 0's frame */
+    const int j = js[i];
+    const double d = remainder(unit_alpha[u[0]] - unit_alpha[u[j]], 2.0 * M_PI_ORC);
+    const double cd = cos(d), sd = sin(d);
+    sx[i] = x[j] * cd + y[j] * sd;
+    sy[i] = -x[j] * sd + y[j] * cd;
+    sz[i] = z[j];
+  }
+  kstate_t s;
+  int fr = 0, cu = u[0];
+  if (orc_seed(sx, sy, sz, k, P->sinphi_max, s.p) != 0) return -1;
+  cov_init(s.cov, P);
+  s.x = x[0];
+  s.chi2 = 0;
+  for (int j = 0; j < n; ++j) {
+    if (j > 0) {
+      if (u[j] != cu) {
+        if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;
+        cu = u[j];
+      }
+      if (step_to(&s, x[j], k, P, &fr) != 0) return -1;
+    }
+    kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
+  }
+  cov_init(s.cov, P);
+  s.chi2 = 0;
+  kf_update(s.p, s.cov, y[n - 1], z[n - 1], P->sigma_y, P->sigma_z, &s.chi2);
+  for (int j = n - 2; j >= 0; --j) {
+    if (u[j] != cu) {
+      if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;
+      cu = u[j];
+    }
+    if (step_to(&s, x[j], k, P, &fr) != 0) return -1;
+    kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
+  }
+  memcpy(p_out, s.p, sizeof(s.p));
+  pack_cov(s.cov, cov_out);
+  *chi2 = s.chi2;
+  return 0;
+}
+
 int orc_kf_update(double p[5], double cov15[15], double my, double mz, double sy, double sz,
                   double *chi2) {
   double c[25];
@@ -1420,34 +1519,6 @@ void orc_refit_tracks(int64_t n_tracks, const int32_t *first, const int32_t *nh,
 /* dy; a turn of the direction gives dsin(phi') = cos phi' / cos phi           */
 /* dsin(phi); everything else is unchanged to first order.                     */
 
-/* Turn state p at plane x by d.  Returns 0, or -1 when the direction reaches
- * |sin(phi')| >= sinphi_max or cos(phi') <= 0 (the state cannot describe a
- * track moving inward in the new frame). */
-int orc_rotate(const double p[5], double x, double d, double k, double sinphi_max, double out[5], double *x_out,
-               double J[25]) {
-  const double cd = cos(d), sd = sin(d);
-  const double s = p[2];
-  if (!(fabs(s) < 1.0)) return -1;
-  const double c = sqrt(1.0 - s * s);
-  const double s2 = s * cd - c * sd, c2 = c * cd + s * sd;
-  if (!(c2 > 0.0) || !(fabs(s2) < sinphi_max)) return -1;
-  *x_out = x * cd + p[0] * sd;
-  out[0] = -x * sd + p[0] * cd;
-  out[1] = p[1];
-  out[2] = s2;
-  out[3] = p[3];
-  out[4] = p[4];
-  if (J) {
-    memset(J, 0, 25 * sizeof(double));
-    for (int i = 0; i < 5; ++i) J[i * 5 + i] = 1.0;
-    J[0 * 5 + 0] = c / c2;
-    J[1 * 5 + 0] = -sd * p[3] / c2;
-    J[2 * 5 + 0] = -k * p[4] * sd;
-    J[2 * 5 + 2] = c2 / c;
-  }
-  return 0;
-}
-
 /* S^-1 r . r for a symmetric positive definite 5x5 S (Cholesky); -1 when S
  * is not positive definite. */
 static double chi2_of(const double S[25], const double r[5]) {
@@ -1622,105 +1693,37 @@ int64_t orc_merge(int64_t T, const int32_t *unit, const int32_t *first_row, cons
   return n_cand;
 }
 
-/* ------------------------------------------------------------------------- */
-/* Fit of a merged chain of segments (Reading R-25): the hits of linked       */
-/* segments in chain order (segment by segment, rows increasing inside each), */
-/* hit j measured in its unit's frame (angle unit_alpha[u[j]]) at x[j] with   */
-/* y[j], z[j].  Seed: the three-point circle through the first, middle (n/2)  */
-/* and last hit, their positions turned into the first hit's frame.  Pass 1   */
-/* from hit 0: before a hit of another frame the state, and its covariance by */
-/* the turn's Jacobian, is turned into that frame, then carried to the hit    */
-/* and updated.  Pass 2 from hit n-1 back, the covariance reset, turning back */
-/* at each change of frame.  Output: the state at hit 0, in its frame.        */
-
-static int turn_state(kstate_t *s, double d_raw, double k, const orc_params_t *P) {
-  const double d = remainder(d_raw, 2.0 * M_PI_ORC);
-  double q[5], xq, J[25];
-  if (orc_rotate(s->p, s->x, d, k, P->sinphi_max, q, &xq, J) != 0) return -1;
-  memcpy(s->p, q, sizeof(q));
-  s->x = xq;
-  transport_cov(J, s->cov);
-  return 0;
-}
-
-/* Returns 0, or -1 when n < 3 or the seed, a turn or a transport fails. */
-int orc_fit_chain(int n, const double *x, const double *y, const double *z, const int32_t *u,
-                  const double *unit_alpha, double k, const orc_params_t *P, double p_out[5],
-                  double cov_out[15], double *chi2) {
-  if (n < 3) return -1;
-  const int js[3] = {0, n / 2, n - 1};
-  double sx[3], sy[3], sz[3];
-  for (int i = 0; i < 3; ++i) { /* the point of hit js[i] in hit 0's frame */
-    const int j = js[i];
-    const double d = remainder(unit_alpha[u[0]] - unit_alpha[u[j]], 2.0 * M_PI_ORC);
-    const double cd = cos(d), sd = sin(d);
-    sx[i] = x[j] * cd + y[j] * sd;
-    sy[i] = -x[j] * sd + y[j] * cd;
-    sz[i] = z[j];
-  }
-  kstate_t s;
-  int fr = 0, cu = u[0];
-  if (orc_seed(sx, sy, sz, k, P->sinphi_max, s.p) != 0) return -1;
-  cov_init(s.cov, P);
-  s.x = x[0];
-  s.chi2 = 0;
-  for (int j = 0; j < n; ++j) {
-    if (j > 0) {
-      if (u[j] != cu) {
-        if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;
-        cu = u[j];
-      }
-      if (step_to(&s, x[j], k, P, &fr) != 0) return -1;
-    }
-    kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
-  }
-  cov_init(s.cov, P);
-  s.chi2 = 0;
-  kf_update(s.p, s.cov, y[n - 1], z[n - 1], P->sigma_y, P->sigma_z, &s.chi2);
-  for (int j = n - 2; j >= 0; --j) {
-    if (u[j] != cu) {
-      if (turn_state(&s, unit_alpha[u[j]] - unit_alpha[cu], k, P) != 0) return -1;
-      cu = u[j];
-    }
-    if (step_to(&s, x[j], k, P, &fr) != 0) return -1;
-    kf_update(s.p, s.cov, y[j], z[j], P->sigma_y, P->sigma_z, &s.chi2);
-  }
-  memcpy(p_out, s.p, sizeof(s.p));
-  pack_cov(s.cov, cov_out);
-  *chi2 = s.chi2;
-  return 0;
-}
-
 /* The chains of a batch: chain c's hits are the cluster ids
  * hits[first[c] .. first[c] + nh[c]) with units hit_unit[...], measured as the
  * tracker measures them (quanta of 1/256 cm at the rows' x).  ok[c] = 1 when
  * the fit succeeded, else every output of the chain is zero. */
 void orc_refit_chains(int64_t n_chains, const int32_t *first, const int32_t *nh, const int32_t *hits,
                       const int32_t *hit_unit, const float *y, const float *z, const uint16_t *row,
-                      const double *row_x, const double *unit_alpha, double k, const orc_params_t *P,
-                      double *p, double *cov, double *x_ref, double *chi2, int8_t *ok) {
+                      const double *row_x, const double *unit_alpha, int32_t n_units, double k,
+                      const orc_params_t *P, double *p, double *cov, double *x_ref, double *chi2, int8_t *ok) {
+  fit_real *ua = (fit_real *)malloc(sizeof(fit_real) * (size_t)(n_units > 0 ? n_units : 1));
+  for (int32_t u = 0; u < n_units; ++u) ua[u] = unit_alpha[u];
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t c = 0; c < n_chains; ++c) {
     const int n = nh[c];
-    double *X = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-    double *Y = X + n, *Z = X + 2 * n;
+    fit_real *X = (fit_real *)malloc(sizeof(fit_real) * 3 * (size_t)(n > 0 ? n : 1));
+    fit_real *Y = X + n, *Z = X + 2 * n;
     for (int j = 0; j < n; ++j) {
       const int32_t h = hits[first[c] + j];
       X[j] = row_x[row[h]];
       Y[j] = nearbyint(256.0 * (double)y[h]) / 256.0;
       Z[j] = nearbyint(256.0 * (double)z[h]) / 256.0;
     }
-    const int st = orc_fit_chain(n, X, Y, Z, hit_unit + first[c], unit_alpha, k, P, p + c * 5, cov + c * 15,
-                                 chi2 + c);
+    fit_real pp[5], cc[15], ch = 0;
+    const int st = orc_fit_chain(n, X, Y, Z, hit_unit + first[c], ua, (fit_real)k, P, pp, cc, &ch);
     ok[c] = st == 0;
-    x_ref[c] = st == 0 ? X[0] : 0.0;
-    if (st != 0) {
-      memset(p + c * 5, 0, 5 * sizeof(double));
-      memset(cov + c * 15, 0, 15 * sizeof(double));
-      chi2[c] = 0.0;
-    }
+    for (int q = 0; q < 5; ++q) p[c * 5 + q] = st == 0 ? (double)pp[q] : 0.0;
+    for (int q = 0; q < 15; ++q) cov[c * 15 + q] = st == 0 ? (double)cc[q] : 0.0;
+    chi2[c] = st == 0 ? (double)ch : 0.0;
+    x_ref[c] = st == 0 ? (double)X[0] : 0.0;
     free(X);
   }
+  free(ua);
 }
 
 int orc_num_threads(void) {

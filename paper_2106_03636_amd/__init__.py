@@ -119,6 +119,11 @@ class tpc_merged_t(ctypes.Structure):
     _fields_ = [("next", _vp), ("prev", _vp), ("link_chi2", _vp), ("counts", _vp), ("status", _vp)]
 
 
+class tpc_chain_fit_t(ctypes.Structure):
+    _fields_ = [("params", _vp), ("cov", _vp), ("x_ref", _vp), ("chi2", _vp), ("n_hits", _vp), ("ok", _vp),
+                ("status", _vp)]
+
+
 class tpc_view_t(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("count", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -187,6 +192,11 @@ def load_library():
                                          ctypes.POINTER(tpc_refit_t), _vp, _vp, ctypes.c_int32,
                                          ctypes.POINTER(tpc_merge_params_t), ctypes.POINTER(tpc_merged_t), _vp,
                                          ctypes.c_size_t, _vp]
+        lib.tpc_fit_chains.restype = ctypes.c_int
+        lib.tpc_fit_chains.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
+                                       ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_params_t),
+                                       ctypes.POINTER(tpc_tracks_t), ctypes.POINTER(tpc_merged_t), _vp,
+                                       ctypes.c_int32, ctypes.POINTER(tpc_chain_fit_t), _vp]
         lib.tpc_inspect.restype = ctypes.c_int
         lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
                                     ctypes.POINTER(tpc_params_t), _vp, ctypes.c_int,
@@ -307,6 +317,14 @@ def tpc_merge_tracks(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: 
                                                workspace_bytes, stream))
 
 
+def tpc_fit_chains(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t, params: tpc_params_t,
+                   tracks: tpc_tracks_t, merged: tpc_merged_t, unit_alpha: int, n_units: int, out: tpc_chain_fit_t,
+                   stream: int) -> int:
+    return int(load_library().tpc_fit_chains(ctypes.byref(clusters), ctypes.byref(geometry), ctypes.byref(field),
+                                             ctypes.byref(params), ctypes.byref(tracks), ctypes.byref(merged),
+                                             unit_alpha, n_units, ctypes.byref(out), stream))
+
+
 def make_merge_params(cap_pairs=1 << 22, max_dalpha=0.3665, max_gap=32, dz_max=64.0, dy_max=2.0, chi2_max=30.0,
                       sinphi_max=0.95) -> tpc_merge_params_t:
     """Defaults: neighbouring sectors 20 degrees apart (21 allowed), 32 rows,
@@ -352,7 +370,8 @@ def tpc_inspect(clusters: tpc_clusters_t, n_rows: int, params: tpc_params_t, wor
 def __getattr__(name):
     # the torch-side helpers load on first use, so that importing the package
     # (e.g. for its parameter values) does not import torch
-    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer", "Compressor", "Refitter", "Merger"):
+    if name in ("Tracker", "track", "CollisionAssigner", "Clusterizer", "Compressor", "Refitter", "Merger",
+                "ChainFitter"):
         from . import runtime
         return getattr(runtime, name)
     raise AttributeError(name)

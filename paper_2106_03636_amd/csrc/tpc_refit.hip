@@ -354,3 +354,310 @@ extern "C" int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   hipLaunchKernelGGL(k_rf_fit, dim3(clamp(fb, FIT_BLOCKS)), dim3(FTB), 0, st, A);
   return hipGetLastError() == hipSuccess ? TPC_OK : TPC_E_HIP;
 }
+
+// ---------------------------------------------------------------------------
+// Fit of merged chains: the hits of linked segments (a tpc_merge_tracks
+// output) in chain order, across their sectors' frames.  One lane per chain
+// head walks the links; before a hit of another frame the state and its
+// covariance are turned into that frame (the turn's Jacobian), then carried
+// and updated as in the refit.  The state stays relative to the current
+// frame's reference quanta (z: the chain's first hit; y: the first hit seen
+// in the frame), re-based at each turn.  The operation is stated with
+// tpc_fit_chains in include/tpc_track.h.
+
+namespace {
+
+constexpr int MAX_CHAIN = 64;  // segments a chain may hold
+constexpr double CH_TWO_PI = 6.283185307179586476925286766559;
+
+struct ChArgs {
+  const float *y, *z;
+  const uint16_t *row;
+  int64_t n_clusters;
+  const float *row_x;
+  int32_t n_rows;
+  const int32_t *trk_status, *n_hits, *first_hit, *hits, *unit;
+  const int64_t *trk_counts;
+  int64_t cap_tracks;
+  const int32_t *next, *prev, *mg_status;
+  const float *alpha;
+  int32_t n_units;
+  float k, smx, sy2, sz2;
+  float cov0[5];
+  float *par, *cov, *xref, *chi2;
+  int32_t *n_chain;
+  uint8_t *ok;
+  int32_t *status;
+};
+
+struct CHit {
+  float x;
+  int Y, Z, u;
+  bool valid;
+};
+
+__device__ __forceinline__ CHit chain_hit(const ChArgs &A, int32_t seg, int j) {
+  CHit c;
+  const int32_t h = A.hits[A.first_hit[seg] + j];
+  c.valid = h >= 0 && h < A.n_clusters && A.row[h] < A.n_rows && fabsf(A.y[h]) <= 8192.f && fabsf(A.z[h]) <= 8192.f;
+  const int32_t hh = c.valid ? h : 0;
+  c.x = A.row_x[c.valid ? A.row[hh] : 0];
+  c.Y = __float2int_rn(A.y[hh] * 256.0f);
+  c.Z = __float2int_rn(A.z[hh] * 256.0f);
+  c.u = A.unit[seg];
+  return c;
+}
+
+// the chain's hit j: its segment found by walking the links from the head
+__device__ CHit chain_hit_at(const ChArgs &A, int32_t head, int j) {
+  int32_t s = head;
+  for (int g = 0; g < MAX_CHAIN && j >= A.n_hits[s]; ++g) {
+    j -= A.n_hits[s];
+    s = A.next[s];
+  }
+  return chain_hit(A, s, j);
+}
+
+__device__ __forceinline__ float frame_turn(const ChArgs &A, int from, int to) {
+  return float(remainder(double(A.alpha[to]) - double(A.alpha[from]), CH_TWO_PI));
+}
+
+// Turn the state by d into another frame: the point (x, ya) and the
+// direction turn, the state moves to the turned point's x; the covariance by
+// the turn's Jacobian (rows y, z, sin(phi) change: dy'/dy = cos phi / cos
+// phi', dz'/dy = -sin d tan(lambda) / cos phi', dsin'/dy = -C sin d,
+// dsin'/dsin = cos phi' / cos phi).  ya: absolute y in, turned y out.
+__device__ bool turn32(KStateR &s, float d, float &ya, float k, float smx) {
+  const float cd = cosf(d), sd = sinf(d);
+  const float sp = s.p[2];
+  if (!(fabsf(sp) < 1.f)) return false;
+  const float c = sqrtf(1.f - sp * sp);
+  const float s2 = sp * cd - c * sd, c2 = c * cd + sp * sd;
+  if (!(c2 > 0.f) || !(fabsf(s2) < smx)) return false;
+  const float x2 = s.x * cd + ya * sd;
+  const float y2 = -s.x * sd + ya * cd;
+  const float j00 = c / c2, j10 = -sd * s.p[3] / c2, j20 = -k * s.p[4] * sd, j22 = c2 / c;
+  float C[5][5];
+  int m = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++m) C[i][j] = C[j][i] = s.c[m];
+  // T = J C (rows 0..2 change), then C' = T J^T (columns 0..2 change)
+  float T[5][5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    T[0][j] = j00 * C[0][j];
+    T[1][j] = C[1][j] + j10 * C[0][j];
+    T[2][j] = j20 * C[0][j] + j22 * C[2][j];
+    T[3][j] = C[3][j];
+    T[4][j] = C[4][j];
+  }
+  m = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++m) {
+      const float v = j == 0 ? j00 * T[i][0]
+                    : j == 1 ? T[i][1] + j10 * T[i][0]
+                    : j == 2 ? j20 * T[i][0] + j22 * T[i][2]
+                             : T[i][j];
+      s.c[m] = v;
+    }
+  s.p[2] = s2;
+  s.x = x2;
+  ya = y2;
+  return true;
+}
+
+__global__ void __launch_bounds__(TPB) k_ch_init(ChArgs A) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    *A.status = *A.trk_status != TPC_OK ? *A.trk_status : *A.mg_status;
+}
+
+__global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t T0 = A.trk_counts[0];
+  const int64_t T = T0 < A.cap_tracks ? T0 : A.cap_tracks;
+  const float k = A.k, smx = A.smx, sy2 = A.sy2, sz2 = A.sz2;
+  bool bad = false;
+  for (int64_t t = int64_t(blockIdx.x) * FTB + threadIdx.x; t < T; t += int64_t(gridDim.x) * FTB) {
+    KStateR s;
+    bool ok = A.prev[t] < 0 && A.next[t] >= 0;
+    int n = 0, nseg = 0;
+    int32_t tail = int32_t(t);
+    if (ok) {
+      for (int32_t q = int32_t(t); q >= 0 && nseg <= MAX_CHAIN; q = A.next[q], ++nseg) {
+        if (q >= T) {
+          nseg = MAX_CHAIN + 1;
+          break;
+        }
+        n += A.n_hits[q];
+        tail = q;
+      }
+      if (nseg > MAX_CHAIN) {
+        bad = true;
+        ok = false;
+      }
+    }
+    ok = ok && n >= 3;
+    int Yr = 0, Zr = 0, cu = 0;
+    if (ok) {  // seed in the first hit's frame
+      const CHit h0 = chain_hit(A, int32_t(t), 0), hm = chain_hit_at(A, int32_t(t), n / 2),
+                 hl = chain_hit_at(A, int32_t(t), n - 1);
+      ok = h0.valid && hm.valid && hl.valid;
+      bad = bad || !ok;
+      cu = h0.u;
+      Yr = h0.Y;
+      Zr = h0.Z;
+      const float y0 = float(Yr) * (1.f / 256.f);
+      float xs[2], ys[2];
+      const CHit hs[2] = {hm, hl};
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float d = frame_turn(A, hs[i].u, cu);
+        const float cd = cosf(d), sd = sinf(d), yy = float(hs[i].Y) * (1.f / 256.f);
+        xs[i] = hs[i].u == cu ? hs[i].x : hs[i].x * cd + yy * sd;
+        ys[i] = hs[i].u == cu ? float(hs[i].Y - Yr) * (1.f / 256.f) : (-hs[i].x * sd + yy * cd) - y0;
+      }
+      if (ok)
+        ok = seed3(s, h0.x, xs[0], xs[1], ys[0], ys[1], float(hl.Z - Zr) * (1.f / 256.f), k, smx, A.cov0);
+    }
+    // pass 1: the segments in link order, every hit after the first
+    if (ok) {
+      kf_update(s, 0.f, 0.f, sy2, sz2);
+      int first = 1;
+      for (int32_t q = int32_t(t); ok && q >= 0; q = A.next[q]) {
+        const int nq = A.n_hits[q];
+        for (int j = first; ok && j < nq; ++j) {
+          const CHit h = chain_hit(A, q, j);
+          if (!h.valid) {
+            bad = true;
+            ok = false;
+            break;
+          }
+          if (h.u != cu) {  // into the next segment's frame, re-based on this hit
+            float ya = s.p[0] + float(Yr) * (1.f / 256.f);
+            if (!turn32(s, frame_turn(A, cu, h.u), ya, k, smx)) {
+              ok = false;
+              break;
+            }
+            cu = h.u;
+            Yr = h.Y;
+            s.p[0] = ya - float(Yr) * (1.f / 256.f);
+          }
+          Step st;
+          if (!step_prepare(s, h.x, k, smx, st)) {
+            ok = false;
+            break;
+          }
+          step_apply(s, st, h.x, k);
+          upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
+        }
+        first = 0;
+      }
+    }
+    // pass 2: from the last hit back, covariance reset, turning back at each change of frame
+    if (ok) {
+      cov_reset(s, A.cov0);
+      s.chi2 = 0.f;
+      const CHit hl = chain_hit(A, tail, A.n_hits[tail] - 1);
+      upd_hit(s, make_int2(hl.Y, hl.Z), Yr, Zr, sy2, sz2);
+      int skip = 1, g = 0;
+      for (int32_t q = tail; ok && q >= 0 && q < T && g <= MAX_CHAIN; q = A.prev[q], ++g) {
+        for (int j = A.n_hits[q] - 1 - skip; ok && j >= 0; --j) {
+          const CHit h = chain_hit(A, q, j);
+          if (h.u != cu) {
+            float ya = s.p[0] + float(Yr) * (1.f / 256.f);
+            if (!turn32(s, frame_turn(A, cu, h.u), ya, k, smx)) {
+              ok = false;
+              break;
+            }
+            cu = h.u;
+            Yr = h.Y;
+            s.p[0] = ya - float(Yr) * (1.f / 256.f);
+          }
+          Step st;
+          if (!step_prepare(s, h.x, k, smx, st)) {
+            ok = false;
+            break;
+          }
+          step_apply(s, st, h.x, k);
+          upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
+        }
+        skip = 0;
+        if (q == int32_t(t)) break;
+      }
+    }
+    A.ok[t] = ok ? 1 : 0;
+    A.n_chain[t] = (A.prev[t] < 0 && A.next[t] >= 0) ? n : 0;
+    A.par[t * 5 + 0] = ok ? s.p[0] + float(Yr) * (1.f / 256.f) : 0.f;
+    A.par[t * 5 + 1] = ok ? s.p[1] + float(Zr) * (1.f / 256.f) : 0.f;
+#pragma unroll
+    for (int q = 2; q < 5; ++q) A.par[t * 5 + q] = ok ? s.p[q] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 15; ++q) A.cov[t * 15 + q] = ok ? s.c[q] : 0.f;
+    A.xref[t] = ok ? s.x : 0.f;
+    A.chi2[t] = ok ? s.chi2 : 0.f;
+  }
+  if (bad) *A.status = TPC_E_INVALID;
+}
+
+}  // namespace
+
+extern "C" int tpc_fit_chains(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry, const tpc_field_t *field,
+                              const tpc_params_t *params, const tpc_tracks_t *tracks, const tpc_merged_t *merged,
+                              const float *unit_alpha, int32_t n_units, tpc_chain_fit_t *out, void *stream) {
+  if (!clusters || !geometry || !field || !params || !tracks || !merged || !unit_alpha || !out) return TPC_E_INVALID;
+  if (clusters->n < 0 || clusters->n >= (int64_t(1) << 30) ||
+      (clusters->n > 0 && (!clusters->y || !clusters->z || !clusters->row)))
+    return TPC_E_INVALID;
+  if (geometry->n_rows < 3 || geometry->n_rows > 255 || !geometry->row_x || n_units < 1) return TPC_E_INVALID;
+  if (!tracks->n_hits || !tracks->first_hit || !tracks->hits || !tracks->unit || !tracks->counts ||
+      !tracks->status || tracks->cap_tracks < 0)
+    return TPC_E_INVALID;
+  if (!merged->next || !merged->prev || !merged->status) return TPC_E_INVALID;
+  if (!isfinite(field->bz_tesla) || !(params->sinphi_max > 0.f) || !(params->sinphi_max < 1.f) ||
+      !(params->sigma_y > 0.f) || !(params->sigma_z > 0.f))
+    return TPC_E_INVALID;
+  for (int q = 0; q < 5; ++q)
+    if (!(params->cov0[q] > 0.f) || !isfinite(params->cov0[q])) return TPC_E_INVALID;
+  if (!out->params || !out->cov || !out->x_ref || !out->chi2 || !out->n_hits || !out->ok || !out->status)
+    return TPC_E_INVALID;
+  ChArgs A;
+  A.y = clusters->y;
+  A.z = clusters->z;
+  A.row = clusters->row;
+  A.n_clusters = clusters->n;
+  A.row_x = geometry->row_x;
+  A.n_rows = geometry->n_rows;
+  A.trk_status = tracks->status;
+  A.n_hits = tracks->n_hits;
+  A.first_hit = tracks->first_hit;
+  A.hits = tracks->hits;
+  A.unit = tracks->unit;
+  A.trk_counts = tracks->counts;
+  A.cap_tracks = tracks->cap_tracks;
+  A.next = merged->next;
+  A.prev = merged->prev;
+  A.mg_status = merged->status;
+  A.alpha = unit_alpha;
+  A.n_units = n_units;
+  A.k = -KAPPA * field->bz_tesla;
+  A.smx = params->sinphi_max;
+  A.sy2 = params->sigma_y * params->sigma_y;
+  A.sz2 = params->sigma_z * params->sigma_z;
+  for (int q = 0; q < 5; ++q) A.cov0[q] = params->cov0[q];
+  A.par = out->params;
+  A.cov = out->cov;
+  A.xref = out->x_ref;
+  A.chi2 = out->chi2;
+  A.n_chain = out->n_hits;
+  A.ok = out->ok;
+  A.status = out->status;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t fb = (tracks->cap_tracks + FTB - 1) / FTB;
+  hipLaunchKernelGGL(k_ch_init, dim3(1), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_ch_fit, dim3(unsigned(fb < 1 ? 1 : (fb > FIT_BLOCKS ? FIT_BLOCKS : fb))), dim3(FTB), 0, st, A);
+  return hipGetLastError() == hipSuccess ? TPC_OK : TPC_E_HIP;
+}

@@ -564,6 +564,14 @@ class Merger:
             raise TrackingError(st, "tpc_merge_tracks: %s" % tpc_status_string(st))
         return st
 
+    def struct(self):
+        """The tpc_merged_t of this merger's outputs (the chain fit reads them)."""
+        from . import tpc_merged_t
+        o = tpc_merged_t()
+        o.next, o.prev, o.link_chi2 = _ptr(self.o_next), _ptr(self.o_prev), _ptr(self.o_chi2)
+        o.counts, o.status = _ptr(self.o_counts), _ptr(self.o_status)
+        return o
+
     def result(self, n_tracks: int, sync=True):
         if sync:
             torch.cuda.synchronize(self.device)
@@ -575,4 +583,48 @@ class Merger:
         T = n_tracks
         return dict(next=self.o_next[:T], prev=self.o_prev[:T], link_chi2=self.o_chi2[:T],
                     n_pairs=int(counts[0]), n_candidates=int(counts[1]), n_links=int(counts[2]))
+
+
+class ChainFitter:
+    """Outputs of tpc_fit_chains: the fit of the merged chains of a Tracker's
+    last batch (a Merger launched on it), indexed by each chain's head track."""
+
+    def __init__(self, tracker):
+        self.tracker = tracker
+        self.device = d = tracker.device
+        T = max(1, tracker.cap_tracks)
+        self.o_params = torch.empty((T, 5), dtype=torch.float32, device=d)
+        self.o_cov = torch.empty((T, 15), dtype=torch.float32, device=d)
+        self.o_xref = torch.empty(T, dtype=torch.float32, device=d)
+        self.o_chi2 = torch.empty(T, dtype=torch.float32, device=d)
+        self.o_n = torch.empty(T, dtype=torch.int32, device=d)
+        self.o_ok = torch.empty(T, dtype=torch.uint8, device=d)
+        self.o_status = torch.zeros(1, dtype=torch.int32, device=d)
+
+    def launch(self, batch: Batch, merged, unit_alpha, stream=None):
+        """merged: a Merger (or anything with struct()) launched on `batch`;
+        unit_alpha: the same angles, a device tensor."""
+        from . import tpc_chain_fit_t, tpc_fit_chains
+        o = tpc_chain_fit_t()
+        o.params, o.cov, o.x_ref, o.chi2 = _ptr(self.o_params), _ptr(self.o_cov), _ptr(self.o_xref), _ptr(self.o_chi2)
+        o.n_hits, o.ok, o.status = _ptr(self.o_n), _ptr(self.o_ok), _ptr(self.o_status)
+        f = tpc_field_t()
+        f.bz_tesla = batch.bz
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = tpc_fit_chains(batch.clusters_struct(), batch.geometry_struct(), f, self.tracker.params,
+                            self.tracker.tracks_struct(), merged.struct(), _ptr(unit_alpha), int(unit_alpha.numel()),
+                            o, s.cuda_stream)
+        if st != TPC_OK:
+            raise TrackingError(st, "tpc_fit_chains: %s" % tpc_status_string(st))
+        return st
+
+    def result(self, n_tracks: int, sync=True):
+        if sync:
+            torch.cuda.synchronize(self.device)
+        st = int(self.o_status.item())
+        if st != TPC_OK:
+            raise TrackingError(st, "chain fit failed on the device: %s" % tpc_status_string(st))
+        T = n_tracks
+        return dict(params=self.o_params[:T], cov=self.o_cov[:T], x_ref=self.o_xref[:T], chi2=self.o_chi2[:T],
+                    n_hits=self.o_n[:T], ok=self.o_ok[:T])
 

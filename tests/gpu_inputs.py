@@ -121,3 +121,29 @@ class DeviceRefit:
     def struct(self):
         return self._s
 
+
+class DeviceMerged:
+    """A tpc_merged_t over device copies of links (next, prev) that do not
+    come from the GPU (the oracle merger's)."""
+
+    def __init__(self, next_, prev, status=0, device="cuda"):
+        import torch
+
+        from paper_2106_03636_amd import tpc_merged_t
+
+        def dev(a, dtype):
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype).reshape(-1)).to(device)
+            return t if t.numel() else torch.zeros(1, dtype=t.dtype, device=device)
+
+        self.next, self.prev = dev(next_, np.int32), dev(prev, np.int32)
+        self.chi2 = dev(np.zeros(len(next_)), np.float64)
+        self.counts = dev(np.zeros(3), np.int64)
+        self.status = dev(np.array([status]), np.int32)
+        s = tpc_merged_t()
+        s.next, s.prev, s.link_chi2 = self.next.data_ptr(), self.prev.data_ptr(), self.chi2.data_ptr()
+        s.counts, s.status = self.counts.data_ptr(), self.status.data_ptr()
+        self._s = s
+
+    def struct(self):
+        return self._s
+

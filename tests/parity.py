@@ -67,6 +67,13 @@ REFIT_MIN_COV_FRACTION = 0.992
 REFIT_MIN_COV_MID_FRACTION = 0.999955
 REFIT_COV_COND_K = 96.0
 FP32_EPS = 2.0 ** -24
+# The fit of merged chains (tests/test_gpu_merge.py): the refit's clauses with
+# wider bulk fractions.  A chain holds about twice a segment's hits, so its
+# q/pT variance falls further below its prior and its updates cancel more
+# bits; tests/test_fp32_bars.py derives the two fractions from the same four
+# FP32 builds, running the oracle's chain fit on the 50-collision frame.
+CHAIN_MIN_COV_FRACTION = 0.9812
+CHAIN_MIN_COV_MID_FRACTION = 0.9999
 
 SEG_FIELDS = ["seg_start", "seg_count", "seg_zmin", "seg_zmax", None, "seg_by", "seg_ny", "seg_bz",
               "seg_nz", "seg_cell_base"]
@@ -167,11 +174,13 @@ class ParityReport(dict):
         return not self.get("failures")
 
 
-def compare_fit(rep, g_par, g_cov, g_chi2, g_xref, o_par, o_cov, o_chi2, o_xref, rtol_scale=1.0, refit_cov0=None):
+def compare_fit(rep, g_par, g_cov, g_chi2, g_xref, o_par, o_cov, o_chi2, o_xref, rtol_scale=1.0, refit_cov0=None,
+                chain=False):
     """The fit clauses of the bars, over tracklets with identical hit sets:
     params [n,5], covariance lower triangles [n,15], chi2 and x_ref [n].
     refit_cov0: the prior covariance diagonal; given, the covariance clauses
-    are the refit's (REFIT_*)."""
+    are the refit's (REFIT_*), with the chain fit's bulk fractions (CHAIN_*)
+    when chain is set."""
     gp, op = np.asarray(g_par, np.float64), np.asarray(o_par, np.float64)
     diag = [0, 2, 5, 9, 14]
     sig = np.sqrt(np.abs(np.asarray(o_cov)[:, diag]))
@@ -199,6 +208,8 @@ def compare_fit(rep, g_par, g_cov, g_chi2, g_xref, o_par, o_cov, o_chi2, o_xref,
     bound = np.full_like(crel_el, COV_RTOL_ALL * rtol_scale)
     if refit_cov0 is not None:
         min_frac, min_mid = REFIT_MIN_COV_FRACTION, REFIT_MIN_COV_MID_FRACTION
+        if chain:
+            min_frac, min_mid = CHAIN_MIN_COV_FRACTION, CHAIN_MIN_COV_MID_FRACTION
         cond = FP32_EPS * np.asarray(refit_cov0, np.float64)[None, :] / np.maximum(np.abs(oc), 1e-30)
         bound = np.maximum(bound, REFIT_COV_COND_K * cond)
     rep["cov_max_rel"] = float(crel.max(initial=0.0))

@@ -39,7 +39,7 @@ def test_struct_layouts_match_header(tmp_path):
                "tpc_clusterizer_params_t": T.tpc_clusterizer_params_t, "tpc_cluster_out_t": T.tpc_cluster_out_t,
                "tpc_compress_params_t": T.tpc_compress_params_t, "tpc_compressed_t": T.tpc_compressed_t,
                "tpc_refit_t": T.tpc_refit_t, "tpc_merge_params_t": T.tpc_merge_params_t,
-               "tpc_merged_t": T.tpc_merged_t,
+               "tpc_merged_t": T.tpc_merged_t, "tpc_chain_fit_t": T.tpc_chain_fit_t,
                "tpc_server_config_t": S.tpc_server_config_t, "tpc_request_t": S.tpc_request_t,
                "tpc_result_t": S.tpc_result_t, "tpc_server_stats_t": S.tpc_server_stats_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tpc_track.h"', 'int main(void){']
@@ -223,6 +223,28 @@ def test_merge_host_checks():
                 dict(dy_max=-1.0), dict(max_dalpha=-0.1)):
         assert T.tpc_merge_tracks(*args(0x8000, 1 << 30, params=T.make_merge_params(cap_pairs=1000, **bad))) == \
             T.TPC_E_INVALID, bad
+
+
+def test_chain_fit_host_checks():
+    """The arguments tpc_fit_chains rejects before any device work."""
+    c, g, f, trk, mg, out = (T.tpc_clusters_t(), T.tpc_geometry_t(), T.tpc_field_t(), T.tpc_tracks_t(),
+                             T.tpc_merged_t(), T.tpc_chain_fit_t())
+    p = T.make_params()
+    f.bz_tesla = 0.5
+    c.n, c.y, c.z, c.row = 100, 0x1000, 0x1000, 0x1000
+    g.n_rows, g.row_x = 152, 0x1000
+    trk.cap_tracks = 50
+    trk.n_hits = trk.first_hit = trk.hits = trk.unit = trk.counts = trk.status = 0x2000
+    mg.next = mg.prev = mg.status = 0x3000
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0) == T.TPC_E_INVALID  # no outputs
+    out.params = out.cov = out.x_ref = out.chi2 = out.n_hits = out.ok = out.status = 0x5000
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 0, out, 0) == T.TPC_E_INVALID
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0, 36, out, 0) == T.TPC_E_INVALID
+    mg.prev = 0
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0) == T.TPC_E_INVALID
+    mg.prev = 0x3000
+    for bad in (dict(sinphi_max=1.0), dict(sigma_z=0.0), dict(cov0=[1.0, 0.0, 1.0, 1.0, 1.0])):
+        assert T.tpc_fit_chains(c, g, f, T.make_params(**bad), trk, mg, 0x4000, 36, out, 0) == T.TPC_E_INVALID, bad
 
 
 def test_status_strings():

@@ -237,3 +237,54 @@ def test_refit_covariance_clauses_admit_fp32_and_are_no_looser(refit_tails):
     ratio = max(t["cond_ratio"] for t in refit_tails.values())
     assert ratio <= parity.REFIT_COV_COND_K <= 1.05 * ratio
 
+
+# ----------------------------------------------------------------------------
+# the chain fit's bulk covariance fractions (parity.CHAIN_*)
+
+@pytest.fixture(scope="module")
+def chain_tails(tmp_path_factory):
+    """Covariance deviations of FP32 builds of the oracle's chain fit from its
+    FP64 fit, over the chains the oracle merger forms on the 50-collision
+    frame."""
+    import synth
+    from test_merge_oracle import merge_event
+    tmp = tmp_path_factory.mktemp("fp32_chain")
+    ev, o, r, unit, fr, lr, alpha, side, m = merge_event("pbpb_timeframe_50")
+    heads, cf, cn, ch, cu = oracle.chains(m["next"], m["prev"], o["track_first_hit"], o["track_n_hits"],
+                                          o["track_hits"], unit)
+    k = float(np.float32(-np.float32(synth.KAPPA) * np.float32(ev.bz)))
+
+    def run(lib):
+        saved = (oracle._LIB, oracle._lib)
+        if lib:
+            oracle._LIB, oracle._lib = lib, None
+        try:
+            return oracle.refit_chains(cf, cn, ch, cu, ev.y, ev.z, ev.row, ev.row_x.astype(np.float64), alpha, k, P)
+        finally:
+            oracle._LIB, oracle._lib = saved
+
+    c64 = run(None)
+    out = {}
+    for sym in (False, True):
+        for fma in ((False, True) if _cpu_has_fma() else (False,)):
+            c32 = run(_build(tmp, sym, fma))
+            both = c64["ok"].astype(bool) & c32["ok"].astype(bool)
+            oc = c64["cov"][both][:, DIAG]
+            gc = c32["cov"][both][:, DIAG].astype(np.float32).astype(np.float64)
+            crel = (np.abs(gc - oc) / np.abs(oc)).max(axis=1)
+            out[(sym, fma)] = dict(n=int(both.sum()), within_1e3=float((crel <= parity.COV_RTOL).mean()),
+                                   within_1e2=float((crel <= parity.COV_RTOL_MID).mean()),
+                                   cov_max=float(crel.max()))
+    print("FP32 chain covariance tails:", out)
+    return out
+
+
+def test_chain_covariance_fractions_admit_fp32_and_are_no_looser(chain_tails):
+    assert all(t["n"] > 100000 for t in chain_tails.values())
+    short = 1.0 - min(t["within_1e3"] for t in chain_tails.values())
+    assert short <= 1.0 - parity.CHAIN_MIN_COV_FRACTION <= 1.1 * short
+    short_mid = 1.0 - min(t["within_1e2"] for t in chain_tails.values())
+    assert short_mid <= 1.0 - parity.CHAIN_MIN_COV_MID_FRACTION <= 1.5 * short_mid
+    # the clause on every entry stays the refit's: the builds' worst lies under its floor
+    assert max(t["cov_max"] for t in chain_tails.values()) <= parity.COV_RTOL_ALL
+

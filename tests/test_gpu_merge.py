@@ -21,7 +21,7 @@ import pytest
 import oracle
 import synth
 from conftest import cached_event, cached_oracle
-from gpu_inputs import DeviceRefit, DeviceTracks
+from gpu_inputs import DeviceMerged, DeviceRefit, DeviceTracks
 from paper_2106_03636_amd.params import DEFAULT_PARAMS as P
 
 pytestmark = pytest.mark.gpu
@@ -216,3 +216,44 @@ def test_merge_edge_cases(T):
     ev0, dt0, r0 = _hand_tracks([], [], np.zeros((0, 5)), np.zeros((0, 5)))
     g = _gpu_merge(ev0, dt0, DeviceRefit(dt0, r0), alpha, side).result(0)
     assert g["n_links"] == 0 and len(g["next"]) == 0
+
+
+@pytest.mark.parametrize("name", ["pbpb_central", "pbpb_timeframe_50"])
+def test_chain_fit_matches_the_oracle(T, name):
+    """The chains of the oracle merger's links over the oracle tracker's
+    tracks, fitted across frames on the GPU (FP32) and by the oracle (FP64):
+    fitted flags identical, the states at the refit's bars with the chain
+    fit's bulk covariance fractions (parity.CHAIN_*, derived from FP32 builds
+    of the oracle's chain fit in tests/test_fp32_bars.py)."""
+    import torch
+    from parity import ParityReport, compare_fit
+    from paper_2106_03636_amd.runtime import Batch, ChainFitter
+    ev, ot = cached_event(name), cached_oracle(name)
+    first, nh, hits = ot["track_first_hit"], ot["track_n_hits"], ot["track_hits"]
+    r = _f32(oracle.refit_tracks(first, nh, hits, ev.y, ev.z, ev.row, ev.row_x.astype(np.float64), _k(ev.bz), P))
+    alpha, side = _units(ev)
+    unit = ot["trk_unit"][ot["track_tracklet"]]
+    fr, lr = oracle.segment_rows(first, nh, hits, ev.row)
+    m = oracle.merge(unit, fr, lr, r, alpha.astype(np.float64), side, len(ev.row_x), _k(ev.bz), **ORACLE_MERGE)
+    heads, cf, cn, ch, cu = oracle.chains(m["next"], m["prev"], first, nh, hits, unit)
+    _say("case chain fit", name, len(heads), "chains")
+    o = oracle.refit_chains(cf, cn, ch, cu, ev.y, ev.z, ev.row, ev.row_x.astype(np.float64), alpha.astype(np.float64),
+                            _k(ev.bz), P)
+    b = Batch.from_event(ev)
+    dt = DeviceTracks.from_oracle(ot)
+    cfit = ChainFitter(dt)
+    cfit.launch(b, DeviceMerged(m["next"], m["prev"]), torch.as_tensor(alpha).cuda())
+    g = {k: v.cpu().numpy() for k, v in cfit.result(len(nh)).items()}
+    assert np.array_equal(np.nonzero(g["n_hits"])[0], heads) and np.array_equal(g["n_hits"][heads], cn)
+    gok, ook = g["ok"][heads].astype(bool), o["ok"].astype(bool)
+    assert np.array_equal(gok, ook), int((gok != ook).sum())
+    assert ook.mean() > 0.99
+    both = gok & ook
+    cov0 = [float(np.float32(v)) for v in P["cov0"]]
+    rep = ParityReport()
+    compare_fit(rep, g["params"][heads][both], g["cov"][heads][both], g["chi2"][heads][both],
+                g["x_ref"][heads][both], o["p"][both], o["cov"][both], o["chi2"][both], o["x_ref"][both],
+                refit_cov0=cov0, chain=True)
+    _say({k: v for k, v in rep.items() if k != "failures"})
+    assert rep.ok, rep.get("failures")
+

@@ -136,13 +136,15 @@ MUTATIONS = [
      "        vz = ((double)z[c] - out[1]) / step;", "        vz = ((double)z[c] - out[0]) / step;",
      [cmp.test_clusters_on_the_helix_have_code_zero]),
     ("refit_not_in_quanta",
-     "      Y[j] = nearbyint(256.0 * (double)y[h]) / 256.0;", "      Y[j] = (double)y[h];",
+     "hits[first[t] + j];\n      X[j] = row_x[row[h]];\n      Y[j] = nearbyint(256.0 * (double)y[h]) / 256.0;",
+     "hits[first[t] + j];\n      X[j] = row_x[row[h]];\n      Y[j] = (double)y[h];",
      [rft.test_refit_takes_clusters_in_quanta]),
     ("refit_rounds_half_up",
-     "      Y[j] = nearbyint(256.0 * (double)y[h]) / 256.0;", "      Y[j] = floor(256.0 * (double)y[h] + 0.5) / 256.0;",
+     "hits[first[t] + j];\n      X[j] = row_x[row[h]];\n      Y[j] = nearbyint(256.0 * (double)y[h]) / 256.0;",
+     "hits[first[t] + j];\n      X[j] = row_x[row[h]];\n      Y[j] = floor(256.0 * (double)y[h] + 0.5) / 256.0;",
      [rft.test_refit_takes_clusters_in_quanta]),
     ("refit_x_of_the_row_below",
-     "      X[j] = row_x[row[h]];", "      X[j] = row_x[row[h] > 0 ? row[h] - 1 : 0];",
+     "hits[first[t] + j];\n      X[j] = row_x[row[h]];", "hits[first[t] + j];\n      X[j] = row_x[row[h] > 0 ? row[h] - 1 : 0];",
      [rft.test_refit_of_noise_free_helices_gives_the_helix_at_both_ends]),
     ("refit_hit_list_reversed",
      "      const int32_t h = hits[first[t] + j];", "      const int32_t h = hits[first[t] + n - 1 - j];",
