@@ -840,11 +840,43 @@ def merge_bench(dev, tr, batch, ev, reps, workload):
     a = np.nonzero(r["next"] >= 0)[0]
     b = r["next"][a]
     unit = res["unit"].cpu().numpy()
-    out = dict(workload=workload, tracks=n_tracks, ms_per_call=ms, tracks_per_s=n_tracks / (ms * 1e-3), launches=9,
+    out = dict(workload=workload, tracks=n_tracks, ms_per_call=ms, tracks_per_s=n_tracks / (ms * 1e-3), launches=10,
                pairs=r["n_pairs"], candidates=r["n_candidates"], links=r["n_links"],
                links_across_sectors=int((unit[a] != unit[b]).sum()),
                link_purity=float(((maj[a] == maj[b]) & (maj[a] >= 0)).mean()) if len(a) else None,
                chains=int(((r["prev"] < 0) & (r["next"] >= 0)).sum()))
+    # the fit of the merged chains across frames
+    from paper_2106_03636_amd.runtime import ChainFitter
+    cfit = ChainFitter(tr)
+    for _ in range(2):
+        cfit.launch(batch, mg, alpha)
+    c = {k: v.cpu().numpy() for k, v in cfit.result(n_tracks).items()}
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cfit.launch(batch, mg, alpha)
+    torch.cuda.synchronize(dev)
+    graph.replay()
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    cms = e0.elapsed_time(e1) / reps
+    del graph
+    heads = np.nonzero(c["n_hits"] > 0)[0]
+    ok = c["ok"][heads].astype(bool)
+    h = heads[ok]
+    chi2_ndf = c["chi2"][h] / np.maximum(1, 2 * c["n_hits"][h] - 5)
+    # q/pT against the generated particle: the chain fit and its head segment's own refit
+    p = maj[h]
+    g = p >= 0
+    true_qpt = ev.tracks.q[p[g]] / ev.tracks.pt[p[g]]
+    seg = rf.result(n_tracks, sync=False)["params"].cpu().numpy()
+    out["chain_fit"] = dict(ms_per_call=cms, chains=int(len(heads)), fitted_fraction=float(ok.mean()) if len(heads) else None,
+                            hits=int(c["n_hits"][heads].sum()), chi2_per_ndf_median=float(np.median(chi2_ndf)) if len(h) else None,
+                            qpt_rel_error_median=dict(chain=float(np.median(np.abs(c["params"][h][g, 4] / true_qpt - 1))),
+                                                      head_segment=float(np.median(np.abs(seg[h][g, 4] / true_qpt - 1)))))
     log("bench: merge " + json.dumps(out))
     return out
 
