@@ -279,6 +279,29 @@ def summarize_profiles(prof_dir, workload):
                               fetch_bytes=fb, write_bytes=wb, avg_us=avg_us)
             if q:
                 traffic[k].update(valu_insts=valu, valu_busy=busy / 100.0)
+    mrg = run.get("merge")
+    if mrg:
+        nt = mrg["tracks"]
+        lines += ["", "segment merging (tpc_merge_tracks) and chain fit (tpc_fit_chains) of the %d tracks of the frame: "
+                  "%d pairs, %d links, %d chains" % (nt, mrg["pairs"], mrg["links"], mrg["chains"]),
+                  "%-18s %6s %10s %10s %10s %8s %9s %9s %6s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB",
+                                                               "GB/s", "waves", "valu/wave", "VALU%")]
+        for k, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["totaldurationns"])):
+            if not (k.startswith("k_mg_") or k.startswith("k_ch_")):
+                continue
+            avg_us = float(r["averagens"]) / 1e3
+            fb = fetch.get(k, 0.0) * 1024 / f_fac
+            wb = write.get(k, 0.0) * 1024 / w_fac
+            q = sq.get(k, {})
+            waves = q.get("SQ_WAVES", 0.0)
+            valu = q.get("SQ_INSTS_VALU", 0.0)
+            busy = 100.0 * valu * 4 / (avg_us * 1e-6 * N_SIMD * CLOCK_GHZ * 1e9) if avg_us else 0.0
+            lines.append("%-18s %6s %10.1f %10.2f %10.2f %8.0f %9.0f %9.0f %6.1f" % (
+                k, r["calls"], avg_us, fb / 1e6, wb / 1e6, (fb + wb) / 1e3 / avg_us, waves,
+                valu / waves if waves else 0.0, busy))
+            src = ("tpc_merge.hip",) if k.startswith("k_mg_") else ("tpc_refit.hip", "tpc_kalman.h")
+            traffic[k] = dict(src_digest=col_digest(*src), bytes_per_launch=fb + wb, fetch_bytes=fb, write_bytes=wb,
+                              avg_us=avg_us)
     clu = run.get("clusterizer")
     if clu:
         nd = clu["digits"]
@@ -757,6 +780,8 @@ def refit_bench(dev, tr, batch, reps, workload):
     import numpy as np
     import torch
     from paper_2106_03636_amd.runtime import Refitter
+    if tr._last is not batch:
+        raise RuntimeError("the refit leg needs the tracker's last batch")
     rf = Refitter(tr)
     n_tracks = int(tr.o_counts[0].item())
     n_hits = int(tr.o_counts[1].item())
@@ -808,6 +833,8 @@ def merge_bench(dev, tr, batch, ev, reps, workload):
     import synth
     from paper_2106_03636_amd import mctruth
     from paper_2106_03636_amd.runtime import Merger, Refitter
+    if tr._last is not batch:
+        raise RuntimeError("the merge leg needs the tracker's last batch")
     rf = Refitter(tr)
     rf.launch(batch)
     # unit angles and sides on the device before the graph is captured
@@ -1165,9 +1192,11 @@ def main():
     log("bench: per-kernel ms " + json.dumps(per_kernel))
     compression = None if args.no_compression else compression_bench(dev, tr, batch, max(20, args.steps),
                                                                      args.workload)
-    collisions = None if args.no_collisions else collision_bench(dev, tr, ev, max(50, args.steps), args.workload)
+    # the refit and the merger read the tracker's last batch: they run before
+    # the collision leg, which tracks the physical frame with the same tracker
     refit = None if args.no_refit else refit_bench(dev, tr, batch, max(20, args.steps), args.workload)
     merge = None if args.no_merge else merge_bench(dev, tr, batch, ev, max(20, args.steps), args.workload)
+    collisions = None if args.no_collisions else collision_bench(dev, tr, ev, max(50, args.steps), args.workload)
 
     out = dict(
         metric=METRIC, value=value, unit="clusters/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
