@@ -549,12 +549,17 @@ typedef struct tpc_chain_fit {
 /* Fit the chains of a tpc_merge_tracks output: the tracking call's clusters,
  * geometry, field, tracking parameters (sigma_y, sigma_z, cov0, sinphi_max)
  * and output (n_hits, first_hit, hits, unit, counts, status), the merger's
- * next / prev / status, and the unit angles it used.  No workspace.
+ * next / prev / status, and the unit angles it used.  The workspace (aligned
+ * to 256 bytes, at least tpc_refit_workspace_size(clusters->n,
+ * tracks->cap_tracks, tracks->cap_hits) bytes) holds no state across calls.
  * Enqueued on `stream` after those calls.  Returns TPC_OK when the work was
- * enqueued, TPC_E_INVALID on bad arguments, TPC_E_HIP on a launch failure. */
+ * enqueued, TPC_E_INVALID on bad arguments (a null or misaligned workspace
+ * among them), TPC_E_NOMEM when the workspace is too small, TPC_E_HIP on a
+ * launch failure. */
 int tpc_fit_chains(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry, const tpc_field_t *field,
                    const tpc_params_t *params, const tpc_tracks_t *tracks, const tpc_merged_t *merged,
-                   const float *unit_alpha, int32_t n_units, tpc_chain_fit_t *out, void *stream);
+                   const float *unit_alpha, int32_t n_units, tpc_chain_fit_t *out, void *workspace,
+                   size_t workspace_bytes, void *stream);
 
 /* Intermediate arrays kept in the workspace after a call, for inspection and
  * tests.  Valid until the workspace is reused.  `what` selects the array:

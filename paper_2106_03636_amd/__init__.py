@@ -196,7 +196,7 @@ def load_library():
         lib.tpc_fit_chains.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.POINTER(tpc_geometry_t),
                                        ctypes.POINTER(tpc_field_t), ctypes.POINTER(tpc_params_t),
                                        ctypes.POINTER(tpc_tracks_t), ctypes.POINTER(tpc_merged_t), _vp,
-                                       ctypes.c_int32, ctypes.POINTER(tpc_chain_fit_t), _vp]
+                                       ctypes.c_int32, ctypes.POINTER(tpc_chain_fit_t), _vp, ctypes.c_size_t, _vp]
         lib.tpc_inspect.restype = ctypes.c_int
         lib.tpc_inspect.argtypes = [ctypes.POINTER(tpc_clusters_t), ctypes.c_int32,
                                     ctypes.POINTER(tpc_params_t), _vp, ctypes.c_int,
@@ -319,10 +319,11 @@ def tpc_merge_tracks(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: 
 
 def tpc_fit_chains(clusters: tpc_clusters_t, geometry: tpc_geometry_t, field: tpc_field_t, params: tpc_params_t,
                    tracks: tpc_tracks_t, merged: tpc_merged_t, unit_alpha: int, n_units: int, out: tpc_chain_fit_t,
-                   stream: int) -> int:
+                   workspace: int, workspace_bytes: int, stream: int) -> int:
     return int(load_library().tpc_fit_chains(ctypes.byref(clusters), ctypes.byref(geometry), ctypes.byref(field),
                                              ctypes.byref(params), ctypes.byref(tracks), ctypes.byref(merged),
-                                             unit_alpha, n_units, ctypes.byref(out), stream))
+                                             unit_alpha, n_units, ctypes.byref(out), workspace, workspace_bytes,
+                                             stream))
 
 
 def make_merge_params(cap_pairs=1 << 22, max_dalpha=0.3665, max_gap=32, dz_max=64.0, dy_max=2.0, chi2_max=30.0,

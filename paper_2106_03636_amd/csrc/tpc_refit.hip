@@ -357,12 +357,16 @@ extern "C" int tpc_refit_tracks(const tpc_clusters_t *clusters, const tpc_geomet
 
 // ---------------------------------------------------------------------------
 // Fit of merged chains: the hits of linked segments (a tpc_merge_tracks
-// output) in chain order, across their sectors' frames.  One lane per chain
-// head walks the links; before a hit of another frame the state and its
-// covariance are turned into that frame (the turn's Jacobian), then carried
-// and updated as in the refit.  The state stays relative to the current
-// frame's reference quanta (z: the chain's first hit; y: the first hit seen
-// in the frame), re-based at each turn.  The operation is stated with
+// output) in chain order, across their sectors' frames.  Launches: status;
+// the refit's k_rf_pack and k_rf_gather (every track hit as one packed
+// record, in hit-list order); k_ch_len (each head's chain length, a length
+// histogram); k_rf_scan; k_ch_order (heads in length order); k_ch_fit (one
+// lane per head in that order, so the lanes of a wave walk chains of about
+// one length): before a hit of another frame the state and its covariance
+// are turned into that frame (the turn's Jacobian), then carried and updated
+// as in the refit.  The state stays relative to the current frame's
+// reference quanta (z: the chain's first hit; y: the first hit seen in the
+// frame), re-based at each turn.  The operation is stated with
 // tpc_fit_chains in include/tpc_track.h.
 
 namespace {
@@ -388,22 +392,24 @@ struct ChArgs {
   int32_t *n_chain;
   uint8_t *ok;
   int32_t *status;
+  // workspace (the refit's layout)
+  const uint64_t *rec;  // [cap_hits] packed (row, Y, Z) per track hit
+  int32_t *order;       // [cap_tracks] slot -> chain head
+  int32_t *bucket;      // [NB] length histogram, then offsets
+  int32_t *bad;         // [0] a hit out of range, [1] number of heads
 };
 
 struct CHit {
   float x;
   int Y, Z, u;
-  bool valid;
 };
 
 __device__ __forceinline__ CHit chain_hit(const ChArgs &A, int32_t seg, int j) {
+  const Hit h = unpack(A.rec[A.first_hit[seg] + j]);
   CHit c;
-  const int32_t h = A.hits[A.first_hit[seg] + j];
-  c.valid = h >= 0 && h < A.n_clusters && A.row[h] < A.n_rows && fabsf(A.y[h]) <= 8192.f && fabsf(A.z[h]) <= 8192.f;
-  const int32_t hh = c.valid ? h : 0;
-  c.x = A.row_x[c.valid ? A.row[hh] : 0];
-  c.Y = __float2int_rn(A.y[hh] * 256.0f);
-  c.Z = __float2int_rn(A.z[hh] * 256.0f);
+  c.x = A.row_x[h.row];
+  c.Y = h.Y;
+  c.Z = h.Z;
   c.u = A.unit[seg];
   return c;
 }
@@ -471,42 +477,110 @@ __device__ bool turn32(KStateR &s, float d, float &ya, float k, float smx) {
 }
 
 __global__ void __launch_bounds__(TPB) k_ch_init(ChArgs A) {
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+  const int i = threadIdx.x;
+  if (i == 0) {
     *A.status = *A.trk_status != TPC_OK ? *A.trk_status : *A.mg_status;
+    A.bad[0] = A.bad[1] = 0;
+  }
+  if (i < NB) A.bucket[i] = 0;
+}
+
+__device__ __forceinline__ int64_t ch_tracks(const ChArgs &A) {
+  const int64_t T = A.trk_counts[0];
+  return T < A.cap_tracks ? T : A.cap_tracks;
+}
+
+// per track: the length of the chain it heads (0 for other tracks); heads
+// counted and histogrammed by length (longest first)
+__global__ void __launch_bounds__(TPB) k_ch_len(ChArgs A) {
+  __shared__ int32_t h[NB];
+  __shared__ int32_t heads;
+  if (*A.status != TPC_OK) return;
+  h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) heads = 0;
+  __syncthreads();
+  const int64_t T = ch_tracks(A);
+  bool bad = false;
+  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
+    int n = 0;
+    if (A.prev[t] < 0 && A.next[t] >= 0) {
+      int nseg = 0;
+      for (int32_t q = int32_t(t); q >= 0; q = A.next[q], ++nseg) {
+        if (q >= T || nseg >= MAX_CHAIN) {
+          bad = true;
+          n = 0;
+          break;
+        }
+        n += A.n_hits[q];
+      }
+      if (n > 0) {
+        atomicAdd(&h[bucket_of(n)], 1);
+        atomicAdd(&heads, 1);
+      }
+    }
+    A.n_chain[t] = n;
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&A.bucket[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 0 && heads) atomicAdd(&A.bad[1], heads);
+  if (bad) *A.status = TPC_E_INVALID;
+}
+
+// slots of the heads in length order (one global atomic per block and bucket)
+__global__ void __launch_bounds__(TPB) k_ch_order(ChArgs A) {
+  __shared__ int32_t cnt[NB], base[NB];
+  if (*A.status != TPC_OK) return;
+  const int64_t T = ch_tracks(A);
+  for (int64_t t0 = int64_t(blockIdx.x) * TPB; t0 < T; t0 += int64_t(gridDim.x) * TPB) {  // block-uniform
+    const int64_t t = t0 + threadIdx.x;
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int n = t < T ? A.n_chain[t] : 0;
+    const int b = n > 0 ? bucket_of(n) : -1;
+    const int rank = b >= 0 ? atomicAdd(&cnt[b], 1) : 0;
+    __syncthreads();
+    if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&A.bucket[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (b >= 0) A.order[base[b] + rank] = int32_t(t);
+    __syncthreads();
+  }
+}
+
+// outputs of the tracks that head no fitted chain
+__global__ void __launch_bounds__(TPB) k_ch_clear(ChArgs A) {
+  if (*A.status != TPC_OK) return;
+  const int64_t T = ch_tracks(A);
+  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
+    if (A.n_chain[t] > 0) continue;
+    A.ok[t] = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) A.par[t * 5 + q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 15; ++q) A.cov[t * 15 + q] = 0.f;
+    A.xref[t] = 0.f;
+    A.chi2[t] = 0.f;
+  }
 }
 
 __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
   if (*A.status != TPC_OK) return;
-  const int64_t T0 = A.trk_counts[0];
-  const int64_t T = T0 < A.cap_tracks ? T0 : A.cap_tracks;
+  if (A.bad[0]) {  // a track hit out of range (the gather's flag): every block sees it
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.status = TPC_E_INVALID;
+    return;
+  }
+  const int64_t H = A.bad[1];
   const float k = A.k, smx = A.smx, sy2 = A.sy2, sz2 = A.sz2;
-  bool bad = false;
-  for (int64_t t = int64_t(blockIdx.x) * FTB + threadIdx.x; t < T; t += int64_t(gridDim.x) * FTB) {
+  for (int64_t i = int64_t(blockIdx.x) * FTB + threadIdx.x; i < H; i += int64_t(gridDim.x) * FTB) {
     KStateR s;
-    bool ok = A.prev[t] < 0 && A.next[t] >= 0;
-    int n = 0, nseg = 0;
+    const int64_t t = A.order[i];
+    const int n = A.n_chain[t];
     int32_t tail = int32_t(t);
-    if (ok) {
-      for (int32_t q = int32_t(t); q >= 0 && nseg <= MAX_CHAIN; q = A.next[q], ++nseg) {
-        if (q >= T) {
-          nseg = MAX_CHAIN + 1;
-          break;
-        }
-        n += A.n_hits[q];
-        tail = q;
-      }
-      if (nseg > MAX_CHAIN) {
-        bad = true;
-        ok = false;
-      }
-    }
-    ok = ok && n >= 3;
+    for (int32_t q = A.next[t]; q >= 0; q = A.next[q]) tail = q;  // lengths checked by k_ch_len
+    bool ok = n >= 3;
     int Yr = 0, Zr = 0, cu = 0;
     if (ok) {  // seed in the first hit's frame
       const CHit h0 = chain_hit(A, int32_t(t), 0), hm = chain_hit_at(A, int32_t(t), n / 2),
                  hl = chain_hit_at(A, int32_t(t), n - 1);
-      ok = h0.valid && hm.valid && hl.valid;
-      bad = bad || !ok;
       cu = h0.u;
       Yr = h0.Y;
       Zr = h0.Z;
@@ -514,14 +588,13 @@ __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
       float xs[2], ys[2];
       const CHit hs[2] = {hm, hl};
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const float d = frame_turn(A, hs[i].u, cu);
-        const float cd = cosf(d), sd = sinf(d), yy = float(hs[i].Y) * (1.f / 256.f);
-        xs[i] = hs[i].u == cu ? hs[i].x : hs[i].x * cd + yy * sd;
-        ys[i] = hs[i].u == cu ? float(hs[i].Y - Yr) * (1.f / 256.f) : (-hs[i].x * sd + yy * cd) - y0;
+      for (int e = 0; e < 2; ++e) {
+        const float d = frame_turn(A, hs[e].u, cu);
+        const float cd = cosf(d), sd = sinf(d), yy = float(hs[e].Y) * (1.f / 256.f);
+        xs[e] = hs[e].u == cu ? hs[e].x : hs[e].x * cd + yy * sd;
+        ys[e] = hs[e].u == cu ? float(hs[e].Y - Yr) * (1.f / 256.f) : (-hs[e].x * sd + yy * cd) - y0;
       }
-      if (ok)
-        ok = seed3(s, h0.x, xs[0], xs[1], ys[0], ys[1], float(hl.Z - Zr) * (1.f / 256.f), k, smx, A.cov0);
+      ok = seed3(s, h0.x, xs[0], xs[1], ys[0], ys[1], float(hl.Z - Zr) * (1.f / 256.f), k, smx, A.cov0);
     }
     // pass 1: the segments in link order, every hit after the first
     if (ok) {
@@ -531,11 +604,6 @@ __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
         const int nq = A.n_hits[q];
         for (int j = first; ok && j < nq; ++j) {
           const CHit h = chain_hit(A, q, j);
-          if (!h.valid) {
-            bad = true;
-            ok = false;
-            break;
-          }
           if (h.u != cu) {  // into the next segment's frame, re-based on this hit
             float ya = s.p[0] + float(Yr) * (1.f / 256.f);
             if (!turn32(s, frame_turn(A, cu, h.u), ya, k, smx)) {
@@ -564,7 +632,7 @@ __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
       const CHit hl = chain_hit(A, tail, A.n_hits[tail] - 1);
       upd_hit(s, make_int2(hl.Y, hl.Z), Yr, Zr, sy2, sz2);
       int skip = 1, g = 0;
-      for (int32_t q = tail; ok && q >= 0 && q < T && g <= MAX_CHAIN; q = A.prev[q], ++g) {
+      for (int32_t q = tail; ok && q >= 0 && g <= MAX_CHAIN; q = A.prev[q], ++g) {
         for (int j = A.n_hits[q] - 1 - skip; ok && j >= 0; --j) {
           const CHit h = chain_hit(A, q, j);
           if (h.u != cu) {
@@ -590,7 +658,6 @@ __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
       }
     }
     A.ok[t] = ok ? 1 : 0;
-    A.n_chain[t] = (A.prev[t] < 0 && A.next[t] >= 0) ? n : 0;
     A.par[t * 5 + 0] = ok ? s.p[0] + float(Yr) * (1.f / 256.f) : 0.f;
     A.par[t * 5 + 1] = ok ? s.p[1] + float(Zr) * (1.f / 256.f) : 0.f;
 #pragma unroll
@@ -600,21 +667,21 @@ __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
     A.xref[t] = ok ? s.x : 0.f;
     A.chi2[t] = ok ? s.chi2 : 0.f;
   }
-  if (bad) *A.status = TPC_E_INVALID;
 }
 
 }  // namespace
 
 extern "C" int tpc_fit_chains(const tpc_clusters_t *clusters, const tpc_geometry_t *geometry, const tpc_field_t *field,
                               const tpc_params_t *params, const tpc_tracks_t *tracks, const tpc_merged_t *merged,
-                              const float *unit_alpha, int32_t n_units, tpc_chain_fit_t *out, void *stream) {
+                              const float *unit_alpha, int32_t n_units, tpc_chain_fit_t *out, void *workspace,
+                              size_t workspace_bytes, void *stream) {
   if (!clusters || !geometry || !field || !params || !tracks || !merged || !unit_alpha || !out) return TPC_E_INVALID;
   if (clusters->n < 0 || clusters->n >= (int64_t(1) << 30) ||
       (clusters->n > 0 && (!clusters->y || !clusters->z || !clusters->row)))
     return TPC_E_INVALID;
   if (geometry->n_rows < 3 || geometry->n_rows > 255 || !geometry->row_x || n_units < 1) return TPC_E_INVALID;
   if (!tracks->n_hits || !tracks->first_hit || !tracks->hits || !tracks->unit || !tracks->counts ||
-      !tracks->status || tracks->cap_tracks < 0)
+      !tracks->status || tracks->cap_tracks < 0 || tracks->cap_hits < 0)
     return TPC_E_INVALID;
   if (!merged->next || !merged->prev || !merged->status) return TPC_E_INVALID;
   if (!isfinite(field->bz_tesla) || !(params->sinphi_max > 0.f) || !(params->sinphi_max < 1.f) ||
@@ -624,6 +691,35 @@ extern "C" int tpc_fit_chains(const tpc_clusters_t *clusters, const tpc_geometry
     if (!(params->cov0[q] > 0.f) || !isfinite(params->cov0[q])) return TPC_E_INVALID;
   if (!out->params || !out->cov || !out->x_ref || !out->chi2 || !out->n_hits || !out->ok || !out->status)
     return TPC_E_INVALID;
+  const size_t need = tpc_refit_workspace_size(clusters->n, tracks->cap_tracks, tracks->cap_hits);
+  if (need == 0) return TPC_E_INVALID;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return TPC_E_INVALID;
+  if (workspace_bytes < need) return TPC_E_NOMEM;
+  // the refit's workspace layout; its pack and gather fill the hit records
+  char *w = static_cast<char *>(workspace);
+  RfArgs R{};
+  R.y = clusters->y;
+  R.z = clusters->z;
+  R.row = clusters->row;
+  R.n_clusters = clusters->n;
+  R.row_x = geometry->row_x;
+  R.n_rows = geometry->n_rows;
+  R.trk_status = tracks->status;
+  R.n_hits = tracks->n_hits;
+  R.first_hit = tracks->first_hit;
+  R.hits = tracks->hits;
+  R.trk_counts = tracks->counts;
+  R.cap_tracks = tracks->cap_tracks;
+  R.cap_hits = tracks->cap_hits;
+  R.status = out->status;
+  R.bucket = reinterpret_cast<int32_t *>(w);
+  R.bad = R.bucket + NB;
+  w += align256(NB * 4 + 256);
+  R.order = reinterpret_cast<int32_t *>(w);
+  w += align256(size_t(tracks->cap_tracks) * 4);
+  R.cl = reinterpret_cast<uint64_t *>(w);
+  w += align256(size_t(clusters->n) * 8);
+  R.rec = reinterpret_cast<uint64_t *>(w);
   ChArgs A;
   A.y = clusters->y;
   A.z = clusters->z;
@@ -655,9 +751,23 @@ extern "C" int tpc_fit_chains(const tpc_clusters_t *clusters, const tpc_geometry
   A.n_chain = out->n_hits;
   A.ok = out->ok;
   A.status = out->status;
+  A.rec = R.rec;
+  A.order = R.order;
+  A.bucket = R.bucket;
+  A.bad = R.bad;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  auto clamp = [](int64_t b, int64_t hi) { return unsigned(b < 1 ? 1 : (b > hi ? hi : b)); };
+  const int64_t tb = (tracks->cap_tracks + TPB - 1) / TPB;
+  const int64_t hb = (tracks->cap_hits + TPB - 1) / TPB;
+  const int64_t cb = (clusters->n + TPB - 1) / TPB;
   const int64_t fb = (tracks->cap_tracks + FTB - 1) / FTB;
   hipLaunchKernelGGL(k_ch_init, dim3(1), dim3(TPB), 0, st, A);
-  hipLaunchKernelGGL(k_ch_fit, dim3(unsigned(fb < 1 ? 1 : (fb > FIT_BLOCKS ? FIT_BLOCKS : fb))), dim3(FTB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_pack, dim3(clamp(cb, GATHER_BLOCKS)), dim3(TPB), 0, st, R);
+  hipLaunchKernelGGL(k_rf_gather, dim3(clamp(hb, GATHER_BLOCKS)), dim3(TPB), 0, st, R);
+  hipLaunchKernelGGL(k_ch_len, dim3(clamp(tb, 1024)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_rf_scan, dim3(1), dim3(NB), 0, st, R);
+  hipLaunchKernelGGL(k_ch_order, dim3(clamp(tb, 1024)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_ch_clear, dim3(clamp(tb, GATHER_BLOCKS)), dim3(TPB), 0, st, A);
+  hipLaunchKernelGGL(k_ch_fit, dim3(clamp(fb, FIT_BLOCKS)), dim3(FTB), 0, st, A);
   return hipGetLastError() == hipSuccess ? TPC_OK : TPC_E_HIP;
 }

@@ -590,9 +590,14 @@ class ChainFitter:
     last batch (a Merger launched on it), indexed by each chain's head track."""
 
     def __init__(self, tracker):
+        from . import tpc_refit_workspace_size
         self.tracker = tracker
         self.device = d = tracker.device
         T = max(1, tracker.cap_tracks)
+        self.ws_bytes = tpc_refit_workspace_size(max(1, tracker.max_n), T, max(1, tracker.cap_hits))
+        if self.ws_bytes == 0:
+            raise ValueError("tpc_refit_workspace_size rejected the tracker's capacities")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d)
         self.o_params = torch.empty((T, 5), dtype=torch.float32, device=d)
         self.o_cov = torch.empty((T, 15), dtype=torch.float32, device=d)
         self.o_xref = torch.empty(T, dtype=torch.float32, device=d)
@@ -613,7 +618,7 @@ class ChainFitter:
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         st = tpc_fit_chains(batch.clusters_struct(), batch.geometry_struct(), f, self.tracker.params,
                             self.tracker.tracks_struct(), merged.struct(), _ptr(unit_alpha), int(unit_alpha.numel()),
-                            o, s.cuda_stream)
+                            o, self.workspace.data_ptr(), self.ws_bytes, s.cuda_stream)
         if st != TPC_OK:
             raise TrackingError(st, "tpc_fit_chains: %s" % tpc_status_string(st))
         return st

@@ -236,15 +236,20 @@ def test_chain_fit_host_checks():
     trk.cap_tracks = 50
     trk.n_hits = trk.first_hit = trk.hits = trk.unit = trk.counts = trk.status = 0x2000
     mg.next = mg.prev = mg.status = 0x3000
-    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0) == T.TPC_E_INVALID  # no outputs
+    trk.cap_hits = 2000
+    ws = T.tpc_refit_workspace_size(100, 50, 2000)
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0x8000, ws, 0) == T.TPC_E_INVALID  # no outputs
     out.params = out.cov = out.x_ref = out.chi2 = out.n_hits = out.ok = out.status = 0x5000
-    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 0, out, 0) == T.TPC_E_INVALID
-    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0, 36, out, 0) == T.TPC_E_INVALID
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 0, out, 0x8000, ws, 0) == T.TPC_E_INVALID
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0, 36, out, 0x8000, ws, 0) == T.TPC_E_INVALID
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0x8001, ws, 0) == T.TPC_E_INVALID  # misaligned
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0x8000, ws - 1, 0) == T.TPC_E_NOMEM
     mg.prev = 0
-    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0) == T.TPC_E_INVALID
+    assert T.tpc_fit_chains(c, g, f, p, trk, mg, 0x4000, 36, out, 0x8000, ws, 0) == T.TPC_E_INVALID
     mg.prev = 0x3000
     for bad in (dict(sinphi_max=1.0), dict(sigma_z=0.0), dict(cov0=[1.0, 0.0, 1.0, 1.0, 1.0])):
-        assert T.tpc_fit_chains(c, g, f, T.make_params(**bad), trk, mg, 0x4000, 36, out, 0) == T.TPC_E_INVALID, bad
+        assert T.tpc_fit_chains(c, g, f, T.make_params(**bad), trk, mg, 0x4000, 36, out, 0x8000, ws, 0) == \
+            T.TPC_E_INVALID, bad
 
 
 def test_status_strings():
