@@ -424,8 +424,9 @@ typedef struct tpc_refit {
   uint8_t *ok;                 /* [cap_tracks] 1 refitted, 0 not (above) */
   int32_t *status;             /* [1] TPC_OK, the tracker's own status when that is not TPC_OK, or
                                   TPC_E_INVALID (a track hit names no cluster of the batch or a
-                                  cluster outside |y|, |z| <= 8192, row < n_rows); outputs are
-                                  valid only with TPC_OK */
+                                  cluster outside |y|, |z| <= 8192, row < n_rows, or a track's hits
+                                  first_hit .. first_hit + n_hits - 1 lie outside the first
+                                  counts[1] entries of hits); outputs are valid only with TPC_OK */
 } tpc_refit_t;
 
 /* Bytes of device workspace tpc_refit_tracks needs for a batch of n_clusters
@@ -489,8 +490,10 @@ typedef struct tpc_merged {
   double *link_chi2;           /* [cap_tracks] chi2 of the link to next (0 without one) */
   int64_t *counts;             /* [3] pairs past the rules, candidates (chi2 <= chi2_max), links */
   int32_t *status;             /* [1] TPC_OK, the tracker's or the refit's own status when not TPC_OK,
-                                  TPC_E_INVALID (a track's unit has no side +-1, or a hit names no
-                                  cluster), TPC_E_CAPACITY (more pairs than cap_pairs; counts[0]
+                                  TPC_E_INVALID (a track's unit is out of range or has no side +-1,
+                                  a hit names no cluster, or a track's hits first_hit ..
+                                  first_hit + n_hits - 1 lie outside the first counts[1] entries of
+                                  hits), TPC_E_CAPACITY (more pairs than cap_pairs; counts[0]
                                   holds the number); outputs are valid only with TPC_OK */
 } tpc_merged_t;
 
@@ -542,8 +545,11 @@ typedef struct tpc_chain_fit {
   uint8_t *ok;                 /* [cap_tracks] 1 fitted, 0 not (or not a head) */
   int32_t *status;             /* [1] TPC_OK, the tracker's or the merger's own status when not TPC_OK,
                                   or TPC_E_INVALID (a hit names no cluster of the batch or one out of
-                                  range, or the links do not form chains of at most 64 segments);
-                                  outputs are valid only with TPC_OK */
+                                  range; a track's hits lie outside the first counts[1] entries of
+                                  hits; the links do not form chains of at most 64 segments: next
+                                  and prev not mutual, a link to no track of the call, a closed
+                                  loop; a linked track's unit outside 0 .. n_units - 1); outputs
+                                  are valid only with TPC_OK */
 } tpc_chain_fit_t;
 
 /* Fit the chains of a tpc_merge_tracks output: the tracking call's clusters,

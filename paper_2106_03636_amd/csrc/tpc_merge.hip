@@ -61,7 +61,7 @@ struct MgArgs {
   // tracks
   const int32_t *trk_status, *n_hits, *first_hit, *hits, *unit;
   const int64_t *trk_counts;
-  int64_t cap_tracks;
+  int64_t cap_tracks, cap_hits;
   // refit
   const float *p_in, *c_in, *x_in, *p_out, *c_out, *x_out;
   const uint8_t *ok;
@@ -98,6 +98,10 @@ struct MgArgs {
 __device__ __forceinline__ int64_t n_tracks(const MgArgs &A) {
   const int64_t T = A.trk_counts[0];
   return T < A.cap_tracks ? T : A.cap_tracks;
+}
+__device__ __forceinline__ int64_t n_track_hits(const MgArgs &A) {
+  const int64_t H = A.trk_counts[1];
+  return H < A.cap_hits ? H : A.cap_hits;
 }
 
 // ---- FP64 track model --------------------------------------------------------
@@ -280,10 +284,14 @@ __global__ void __launch_bounds__(TPB) k_mg_init(MgArgs A) {
 
 __global__ void __launch_bounds__(TPB) k_mg_rows(MgArgs A) {
   if (*A.status != TPC_OK) return;
-  const int64_t T = n_tracks(A);
+  const int64_t T = n_tracks(A), H = n_track_hits(A);
   bool bad = false;
   for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
     const int n = A.n_hits[t], f = A.first_hit[t], u = A.unit[t];
+    if (n < 0 || f < 0 || int64_t(f) + n > H) {  // the track's hits lie outside the hit list
+      bad = true;
+      continue;
+    }
     int fr = 0, lr = 0;
     if (n > 0) {
       const int32_t h0 = A.hits[f], h1 = A.hits[f + n - 1];
@@ -624,7 +632,7 @@ extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geomet
     return TPC_E_INVALID;
   if (clusters->n < 0 || (clusters->n > 0 && !clusters->row) || !geometry->row_x) return TPC_E_INVALID;
   if (!tracks->n_hits || !tracks->first_hit || !tracks->hits || !tracks->unit || !tracks->counts ||
-      !tracks->status || tracks->cap_tracks < 0)
+      !tracks->status || tracks->cap_tracks < 0 || tracks->cap_hits < 0)
     return TPC_E_INVALID;
   if (!refit->params || !refit->cov || !refit->x_ref || !refit->params_out || !refit->cov_out ||
       !refit->x_out || !refit->ok || !refit->status)
@@ -649,6 +657,7 @@ extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   A.unit = tracks->unit;
   A.trk_counts = tracks->counts;
   A.cap_tracks = tracks->cap_tracks;
+  A.cap_hits = tracks->cap_hits;
   A.p_in = refit->params;
   A.c_in = refit->cov;
   A.x_in = refit->x_ref;

@@ -60,7 +60,7 @@ struct RfArgs {
   int32_t *order;    // [cap_tracks] slot -> track
   uint64_t *cl;      // [n_clusters] packed (row, Y, Z) per cluster, NO_REC when out of range
   uint64_t *rec;     // [cap_hits] packed (row, Y, Z) per track hit
-  int32_t *bad;      // [1] a track hit names no cluster, or one out of range
+  int32_t *bad;      // [1] a track hit names no cluster or one out of range, or a track's hits lie outside the list
 };
 
 constexpr uint64_t NO_REC = ~uint64_t(0);  // row field 0xFFFF: never a valid row
@@ -92,11 +92,17 @@ __global__ void __launch_bounds__(TPB) k_rf_hist(RfArgs A) {
   if (*A.status != TPC_OK) return;
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t T = n_tracks(A);
-  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB)
-    atomicAdd(&h[bucket_of(A.n_hits[t])], 1);
+  const int64_t T = n_tracks(A), H = n_track_hits(A);
+  bool bad = false;
+  for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
+    const int n = A.n_hits[t];
+    const int64_t f = A.first_hit[t];
+    if (n < 0 || f < 0 || f + n > H) bad = true;  // the track's hits lie outside the hit list
+    atomicAdd(&h[bucket_of(n)], 1);
+  }
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&A.bucket[threadIdx.x], h[threadIdx.x]);
+  if (bad) atomicOr(A.bad, 1);  // k_rf_fit reports it
 }
 
 // exclusive scan of the NB bucket counts (one block of NB threads)
@@ -382,7 +388,7 @@ struct ChArgs {
   int32_t n_rows;
   const int32_t *trk_status, *n_hits, *first_hit, *hits, *unit;
   const int64_t *trk_counts;
-  int64_t cap_tracks;
+  int64_t cap_tracks, cap_hits;
   const int32_t *next, *prev, *mg_status;
   const float *alpha;
   int32_t n_units;
@@ -396,7 +402,7 @@ struct ChArgs {
   const uint64_t *rec;  // [cap_hits] packed (row, Y, Z) per track hit
   int32_t *order;       // [cap_tracks] slot -> chain head
   int32_t *bucket;      // [NB] length histogram, then offsets
-  int32_t *bad;         // [0] a hit out of range, [1] number of heads
+  int32_t *bad;         // [0] a hit out of range (the gather's flag), [1] number of heads
 };
 
 struct CHit {
@@ -490,8 +496,11 @@ __device__ __forceinline__ int64_t ch_tracks(const ChArgs &A) {
   return T < A.cap_tracks ? T : A.cap_tracks;
 }
 
-// per track: the length of the chain it heads (0 for other tracks); heads
-// counted and histogrammed by length (longest first)
+// per track: the checks of the input (its hits inside the hit list; links
+// that are mutual, name tracks of the call and, followed back, reach a head
+// within MAX_CHAIN segments, so that no closed loop is left; a linked track's
+// unit in range), and the length of the chain it heads (0 for other tracks);
+// heads counted and histogrammed by length (longest first)
 __global__ void __launch_bounds__(TPB) k_ch_len(ChArgs A) {
   __shared__ int32_t h[NB];
   __shared__ int32_t heads;
@@ -500,10 +509,22 @@ __global__ void __launch_bounds__(TPB) k_ch_len(ChArgs A) {
   if (threadIdx.x == 0) heads = 0;
   __syncthreads();
   const int64_t T = ch_tracks(A);
+  const int64_t H = A.trk_counts[1] < A.cap_hits ? A.trk_counts[1] : A.cap_hits;
   bool bad = false;
   for (int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x; t < T; t += int64_t(gridDim.x) * TPB) {
-    int n = 0;
-    if (A.prev[t] < 0 && A.next[t] >= 0) {
+    const int nt = A.n_hits[t];
+    const int64_t ft = A.first_hit[t];
+    const int32_t nx = A.next[t], pv = A.prev[t];
+    if (nt < 0 || ft < 0 || ft + nt > H) bad = true;
+    if ((nx >= 0 && (nx >= T || A.prev[nx] != t)) || (pv >= 0 && (pv >= T || A.next[pv] != t))) bad = true;
+    if ((nx >= 0 || pv >= 0) && (A.unit[t] < 0 || A.unit[t] >= A.n_units)) bad = true;
+    if (pv >= 0 && !bad) {
+      int32_t q = pv;
+      for (int g = 1; q >= 0 && q < T && g < MAX_CHAIN; ++g) q = A.prev[q];
+      if (q >= 0) bad = true;
+    }
+    int64_t n = 0;
+    if (pv < 0 && nx >= 0) {
       int nseg = 0;
       for (int32_t q = int32_t(t); q >= 0; q = A.next[q], ++nseg) {
         if (q >= T || nseg >= MAX_CHAIN) {
@@ -513,12 +534,16 @@ __global__ void __launch_bounds__(TPB) k_ch_len(ChArgs A) {
         }
         n += A.n_hits[q];
       }
+      if (n > INT32_MAX) {
+        bad = true;
+        n = 0;
+      }
       if (n > 0) {
-        atomicAdd(&h[bucket_of(n)], 1);
+        atomicAdd(&h[bucket_of(int(n))], 1);
         atomicAdd(&heads, 1);
       }
     }
-    A.n_chain[t] = n;
+    A.n_chain[t] = int32_t(n);
   }
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&A.bucket[threadIdx.x], h[threadIdx.x]);
@@ -734,6 +759,7 @@ extern "C" int tpc_fit_chains(const tpc_clusters_t *clusters, const tpc_geometry
   A.unit = tracks->unit;
   A.trk_counts = tracks->counts;
   A.cap_tracks = tracks->cap_tracks;
+  A.cap_hits = tracks->cap_hits;
   A.next = merged->next;
   A.prev = merged->prev;
   A.mg_status = merged->status;

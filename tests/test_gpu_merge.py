@@ -192,8 +192,9 @@ def test_merge_after_tracking_on_the_gpu(T):
 
 def test_merge_edge_cases(T):
     """A failed tracking or refit status passes through; more pairs than
-    cap_pairs gives TPC_E_CAPACITY with the count; a unit without a side
-    gives TPC_E_INVALID; no tracks."""
+    cap_pairs gives TPC_E_CAPACITY with the count; a unit without a side,
+    and a track whose hits lie outside the hit list, give TPC_E_INVALID; no
+    tracks."""
     from paper_2106_03636_amd import make_merge_params
     from paper_2106_03636_amd.runtime import TrackingError
     seg = lambda y: [y, 0.0, 0.0, 0.0, 0.0]  # noqa: E731
@@ -213,6 +214,11 @@ def test_merge_edge_cases(T):
     with pytest.raises(TrackingError) as e:
         _gpu_merge(ev, dt, DeviceRefit(dt, r), alpha, np.zeros(1, np.int32)).result(3)
     assert e.value.status == T.TPC_E_INVALID
+    for f2, n2 in ((5, 2), (-1, 2), (4, -1)):  # a track's hits outside the hit list
+        dtb = DeviceTracks(ev.n, np.array([0, 2, f2]), np.array([2, 2, n2]), np.arange(6), unit=np.zeros(3))
+        with pytest.raises(TrackingError) as e:
+            _gpu_merge(ev, dtb, DeviceRefit(dtb, r), alpha, side).result(3)
+        assert e.value.status == T.TPC_E_INVALID, (f2, n2)
     ev0, dt0, r0 = _hand_tracks([], [], np.zeros((0, 5)), np.zeros((0, 5)))
     g = _gpu_merge(ev0, dt0, DeviceRefit(dt0, r0), alpha, side).result(0)
     assert g["n_links"] == 0 and len(g["next"]) == 0
@@ -257,3 +263,73 @@ def test_chain_fit_matches_the_oracle(T, name):
     _say({k: v for k, v in rep.items() if k != "failures"})
     assert rep.ok, rep.get("failures")
 
+
+
+def _chain_fit(ev, dt, next_, prev, alpha, status=0):
+    import torch
+    from paper_2106_03636_amd.runtime import Batch, ChainFitter
+    cf = ChainFitter(dt)
+    cf.launch(Batch.from_event(ev), DeviceMerged(np.asarray(next_), np.asarray(prev), status=status),
+              torch.as_tensor(np.asarray(alpha, np.float32)).cuda())
+    return cf
+
+
+def _chain_status(ev, dt, next_, prev, alpha, status=0):
+    from paper_2106_03636_amd.runtime import TrackingError
+    try:
+        _chain_fit(ev, dt, next_, prev, alpha, status).result(dt.T)
+    except TrackingError as e:
+        return e.status
+    return 0
+
+
+def test_chain_fit_edge_cases(T):
+    """Straight segments of two hits (no field): a chain of three is fitted as
+    the oracle fits it and the other tracks are no heads; unlinked tracks and
+    no tracks at all give no chains.  A failed tracking or merging status
+    passes through.  Links that are not mutual, name no track of the call,
+    close a loop, or make a chain of more than 64 segments (64 is fine), a
+    linked track's unit out of range, a track's hits outside the hit list and
+    a hit naming no cluster give TPC_E_INVALID."""
+    seg = [0.0] * 5
+    ev, dt, _ = _hand_tracks([0, 0, 0], [(0, 10), (11, 40), (50, 60)], [seg] * 3, [seg] * 3)
+    alpha = [0.0]
+    g = {k: v.cpu().numpy() for k, v in _chain_fit(ev, dt, [1, 2, -1], [-1, 0, 1], alpha).result(3).items()}
+    assert g["n_hits"].tolist() == [6, 0, 0] and g["ok"].tolist() == [1, 0, 0]
+    first, nh, hits = np.arange(0, 6, 2), np.full(3, 2), np.arange(6)
+    heads, cf, cn, ch, cu = oracle.chains(np.array([1, 2, -1]), np.array([-1, 0, 1]), first, nh, hits, np.zeros(3))
+    o = oracle.refit_chains(cf, cn, ch, cu, ev.y, ev.z, ev.row, ev.row_x.astype(np.float64), np.zeros(1), 0.0, P)
+    assert heads.tolist() == [0] and o["ok"].tolist() == [1]
+    assert np.allclose(g["params"][0], o["p"][0], rtol=0, atol=1e-5)
+    assert np.allclose(g["cov"][0], o["cov"][0], rtol=1e-3, atol=1e-9)
+    assert g["x_ref"][0] == np.float32(o["x_ref"][0])
+    assert not np.any(g["params"][1:]) and not np.any(g["cov"][1:])
+    g = {k: v.cpu().numpy() for k, v in _chain_fit(ev, dt, [-1] * 3, [-1] * 3, alpha).result(3).items()}
+    assert not np.any(g["n_hits"]) and not np.any(g["ok"])
+    ev0, dt0, _ = _hand_tracks([], [], np.zeros((0, 5)), np.zeros((0, 5)))
+    assert all(len(v) == 0 for v in _chain_fit(ev0, dt0, [], [], alpha).result(0).values())
+    # statuses passed through
+    assert _chain_status(ev, dt, [1, 2, -1], [-1, 0, 1], alpha, status=T.TPC_E_CAPACITY) == T.TPC_E_CAPACITY
+    dtc = DeviceTracks(ev.n, first, nh, hits, unit=np.zeros(3), status=T.TPC_E_CAPACITY)
+    assert _chain_status(ev, dtc, [1, 2, -1], [-1, 0, 1], alpha) == T.TPC_E_CAPACITY
+    # malformed links
+    bad = T.TPC_E_INVALID
+    assert _chain_status(ev, dt, [1, -1, 1], [-1, 0, -1], alpha) == bad  # 2 -> 1, but 1 continues 0
+    assert _chain_status(ev, dt, [5, -1, -1], [-1, -1, -1], alpha) == bad  # a link to no track
+    assert _chain_status(ev, dt, [-1, -1, -1], [-1, -1, 7], alpha) == bad
+    assert _chain_status(ev, dt, [1, 0, -1], [1, 0, -1], alpha) == bad  # 0 -> 1 -> 0: no head
+    for n_seg, want in ((64, 0), (65, bad)):
+        evl, dtl, _ = _hand_tracks([0] * n_seg, [(0, 1)] * n_seg, [seg] * n_seg, [seg] * n_seg)
+        nx = list(range(1, n_seg)) + [-1]
+        pv = [-1] + list(range(n_seg - 1))
+        assert _chain_status(evl, dtl, nx, pv, alpha) == want, n_seg
+    # a linked track's unit out of range (an unlinked one is not read)
+    dtu = DeviceTracks(ev.n, first, nh, hits, unit=np.array([0, 1, 5]))
+    assert _chain_status(ev, dtu, [1, -1, -1], [-1, 0, -1], alpha) == bad
+    assert _chain_status(ev, dtu, [-1, -1, -1], [-1, -1, -1], alpha) == 0
+    # hits outside the list, a hit naming no cluster
+    for f2, n2 in ((5, 2), (-1, 2), (0, -1)):
+        dth = DeviceTracks(ev.n, np.array([0, 2, f2]), np.array([2, 2, n2]), hits, unit=np.zeros(3))
+        assert _chain_status(ev, dth, [1, -1, -1], [-1, 0, -1], alpha) == bad, (f2, n2)
+    dtx = DeviceTracks(ev.n, first, nh, np.array([0, 1, 2, 99, 4, 5]), unit=np.zeros(3))
+    assert _chain_status(ev, dtx, [1, -1, -1], [-1, 0, -1], alpha) == bad

@@ -148,8 +148,9 @@ def test_refit_reads_the_trackers_output(T, name):
 
 def test_refit_edge_cases(T):
     """Tracks of 0, 1 and 2 hits are not refitted; a failed tracking call's
-    status passes through; a hit that names no cluster gives TPC_E_INVALID;
-    no tracks at all is fine."""
+    status passes through; a hit that names no cluster, and a track whose
+    hits lie outside the hit list, give TPC_E_INVALID; no tracks at all is
+    fine."""
     from paper_2106_03636_amd.runtime import TrackingError
     ev = cached_event("pp_sector")
     first, nh, hits, _ = truth_tracks(ev)
@@ -174,5 +175,14 @@ def test_refit_edge_cases(T):
     with pytest.raises(TrackingError) as e:
         rf.result(n)
     assert e.value.status == T.TPC_E_INVALID
+    # a track whose hits lie outside the hit list (past its end, a negative start or count)
+    assert first[-1] + nh[-1] == len(hits)
+    for f2, n2 in ((first[-1] + 1, nh[-1]), (-1, nh[-1]), (first[-1], -1)):
+        fb, nb = first.copy(), nh.copy()
+        fb[-1], nb[-1] = f2, n2
+        rf, n = _gpu_refit(ev, fb, nb, hits)
+        with pytest.raises(TrackingError) as e:
+            rf.result(n)
+        assert e.value.status == T.TPC_E_INVALID, (f2, n2)
     rf, n = _gpu_refit(ev, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
     assert n == 0 and all(len(v) == 0 for v in _host(rf.result(0)).values())
