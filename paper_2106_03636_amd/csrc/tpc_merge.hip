@@ -14,8 +14,9 @@
 //   k_mg_fill   those segments filed by (unit, z' cell);
 //   k_mg_sort   one wave per cell: its segments sorted by first row (bitonic
 //               in LDS up to SORT_MAX; larger cells by one lane), with their
-//               inner z', y, x and first row written next to them in that
-//               order (so the scan below reads contiguous memory);
+//               inner z', y, x and first row written in that order as one
+//               16-byte record each (the scan below reads one record per
+//               candidate, and neighbouring lanes share its cache lines);
 //   k_mg_pairs  one lane per segment a: for each unit on its side within
 //               max_dalpha, its outer state turned into that unit's frame
 //               (parameters, FP64); in each cell its z' window meets, a
@@ -53,6 +54,12 @@ constexpr double KAPPA = 0.00299792458;
 constexpr double TWO_PI = 6.283185307179586476925286766559;
 constexpr unsigned long long NONE64 = ~0ull;
 
+// a filed segment as the scan reads it
+struct __align__(16) Filed {
+  float z, y, x;  // inner z', y and x
+  int32_t fr;     // first row
+};
+
 struct MgArgs {
   // clusters, geometry
   const uint16_t *row;
@@ -85,8 +92,8 @@ struct MgArgs {
   int32_t *bin;  // [nbins + 1] counts, then offsets
   int32_t *cursor;
   int32_t *idx;
-  float *zin, *yin, *xin;  // inner z', y and x of the filed segments, in filing order
-  int32_t *frs;             // their first rows
+  Filed *filed;   // the filed segments, in scan order
+  int32_t *frs;    // their first rows, in filing order (the sort's key)
   int32_t *rows;  // first row | last row << 16
   unsigned long long *ob_chi, *ib_chi;
   int32_t *ob_idx, *ib_idx;
@@ -362,10 +369,12 @@ __device__ __forceinline__ void count(unsigned long long &counter, bool take) {
 
 __device__ __forceinline__ void file_entry(const MgArgs &A, int32_t s, int32_t b, int32_t fr) {
   A.idx[s] = b;
-  A.frs[s] = fr;
-  A.zin[s] = A.p_in[int64_t(b) * 5 + 1];
-  A.yin[s] = A.p_in[int64_t(b) * 5];
-  A.xin[s] = A.x_in[b];
+  Filed f;
+  f.z = A.p_in[int64_t(b) * 5 + 1];
+  f.y = A.p_in[int64_t(b) * 5];
+  f.x = A.x_in[b];
+  f.fr = fr;
+  A.filed[s] = f;
 }
 
 __global__ void __launch_bounds__(64) k_mg_sort(MgArgs A) {
@@ -460,14 +469,14 @@ __global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
         int32_t lo = s0, hi = s1;
         while (lo < hi) {
           const int32_t mid = (lo + hi) >> 1;
-          if (A.frs[mid] <= lr) lo = mid + 1; else hi = mid;
+          if (A.filed[mid].fr <= lr) lo = mid + 1; else hi = mid;
         }
         for (int32_t s = lo; s < s1; ++s) {
-          const int fr = A.frs[s];
-          if (fr > r1) break;
+          const Filed f = A.filed[s];
+          if (f.fr > r1) break;
           double y;
-          if (!(fabs(double(A.zin[s]) - za) <= A.dz_max) || !carry_y(q, xq, double(A.xin[s]), A.k, A.smx, y) ||
-              !(fabs(double(A.yin[s]) - y) <= A.dy_max))
+          if (!(fabs(double(f.z) - za) <= A.dz_max) || !carry_y(q, xq, double(f.x), A.k, A.smx, y) ||
+              !(fabs(double(f.y) - y) <= A.dy_max))
             continue;
           if (nbuf == PAIR_BUF) {
             flush(A, int32_t(a), buf, nbuf);
@@ -562,7 +571,7 @@ __global__ void k_mg_counts(MgArgs A) {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t bin, cursor, idx, zin, yin, xin, frs, rows, ob_chi, ib_chi, ob_idx, ib_idx, pairs, pair_chi, ctr, total;
+  size_t bin, cursor, idx, filed, frs, rows, ob_chi, ib_chi, ob_idx, ib_idx, pairs, pair_chi, ctr, total;
 };
 
 Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
@@ -576,9 +585,7 @@ Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
   L.bin = take(size_t(nbins + 1) * 4);
   L.cursor = take(size_t(nbins) * 4);
   L.idx = take(size_t(cap_tracks) * 4);
-  L.zin = take(size_t(cap_tracks) * 4);
-  L.yin = take(size_t(cap_tracks) * 4);
-  L.xin = take(size_t(cap_tracks) * 4);
+  L.filed = take(size_t(cap_tracks) * sizeof(Filed));
   L.frs = take(size_t(cap_tracks) * 4);
   L.rows = take(size_t(cap_tracks) * 4);
   L.ob_chi = take(size_t(cap_tracks) * 8);
@@ -692,9 +699,7 @@ extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   A.bin = reinterpret_cast<int32_t *>(w + L.bin);
   A.cursor = reinterpret_cast<int32_t *>(w + L.cursor);
   A.idx = reinterpret_cast<int32_t *>(w + L.idx);
-  A.zin = reinterpret_cast<float *>(w + L.zin);
-  A.yin = reinterpret_cast<float *>(w + L.yin);
-  A.xin = reinterpret_cast<float *>(w + L.xin);
+  A.filed = reinterpret_cast<Filed *>(w + L.filed);
   A.frs = reinterpret_cast<int32_t *>(w + L.frs);
   A.rows = reinterpret_cast<int32_t *>(w + L.rows);
   A.ob_chi = reinterpret_cast<unsigned long long *>(w + L.ob_chi);
