@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(TPB) k_ch_len(ChArgs A) {
     if (pv < 0 && nx >= 0) {
       int nseg = 0;
       for (int32_t q = int32_t(t); q >= 0; q = A.next[q], ++nseg) {
-        if (q >= T || nseg >= MAX_CHAIN) {
+        if (q >= T || nseg >= MAX_CHAIN || A.n_hits[q] < 1) {
           bad = true;
           n = 0;
           break;
@@ -587,6 +587,51 @@ __global__ void __launch_bounds__(TPB) k_ch_clear(ChArgs A) {
   }
 }
 
+// A position in a chain: hit j of segment q (records R, nq hits, unit u).
+// Segments have at least one hit (k_ch_len), and the steps below are taken
+// only towards a hit of the chain, so every link they follow is checked.
+struct Cursor {
+  int32_t q;
+  int j, nq, u;
+  const uint64_t *R;
+};
+__device__ __forceinline__ void seg_at(const ChArgs &A, Cursor &c, int32_t q, int j) {
+  c.q = q;
+  c.nq = A.n_hits[q];
+  c.u = A.unit[q];
+  c.R = A.rec + A.first_hit[q];
+  c.j = j;
+}
+__device__ __forceinline__ void step_fwd(const ChArgs &A, Cursor &c) {
+  if (++c.j >= c.nq) seg_at(A, c, A.next[c.q], 0);
+}
+__device__ __forceinline__ void step_bwd(const ChArgs &A, Cursor &c) {
+  if (--c.j < 0) {
+    seg_at(A, c, A.prev[c.q], 0);
+    c.j = c.nq - 1;
+  }
+}
+
+// One hit of a chain: into its unit's frame when it changes (re-based on
+// the hit), then the transport and the update.  False when the state
+// cannot be carried there.
+__device__ __forceinline__ bool chain_step(const ChArgs &A, KStateR &s, const Hit h, int u, int &cu, int &Yr,
+                                           int Zr, float k, float smx, float sy2, float sz2) {
+  const float x = A.row_x[h.row];
+  if (u != cu) {
+    float ya = s.p[0] + float(Yr) * (1.f / 256.f);
+    if (!turn32(s, frame_turn(A, cu, u), ya, k, smx)) return false;
+    cu = u;
+    Yr = h.Y;
+    s.p[0] = ya - float(Yr) * (1.f / 256.f);
+  }
+  Step st;
+  if (!step_prepare(s, x, k, smx, st)) return false;
+  step_apply(s, st, x, k);
+  upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
+  return true;
+}
+
 __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
   if (*A.status != TPC_OK) return;
   if (A.bad[0]) {  // a track hit out of range (the gather's flag): every block sees it
@@ -595,13 +640,14 @@ __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
   }
   const int64_t H = A.bad[1];
   const float k = A.k, smx = A.smx, sy2 = A.sy2, sz2 = A.sz2;
-  for (int64_t i = int64_t(blockIdx.x) * FTB + threadIdx.x; i < H; i += int64_t(gridDim.x) * FTB) {
+  for (int64_t i0 = int64_t(blockIdx.x) * FTB; i0 < H; i0 += int64_t(gridDim.x) * FTB) {
+    const int64_t i = i0 + threadIdx.x;
+    if ((i & ~int64_t(63)) >= H) break;  // whole wave past the heads (wave-uniform)
+    const bool valid = i < H;            // the other lanes stay for the shuffles below
     KStateR s;
-    const int64_t t = A.order[i];
-    const int n = A.n_chain[t];
-    int32_t tail = int32_t(t);
-    for (int32_t q = A.next[t]; q >= 0; q = A.next[q]) tail = q;  // lengths checked by k_ch_len
-    bool ok = n >= 3;
+    const int64_t t = valid ? A.order[i] : 0;
+    const int n = valid ? A.n_chain[t] : 0;
+    bool ok = valid && n >= 3;
     int Yr = 0, Zr = 0, cu = 0;
     if (ok) {  // seed in the first hit's frame
       const CHit h0 = chain_hit(A, int32_t(t), 0), hm = chain_hit_at(A, int32_t(t), n / 2),
@@ -621,67 +667,53 @@ __global__ void __launch_bounds__(FTB) k_ch_fit(ChArgs A) {
       }
       ok = seed3(s, h0.x, xs[0], xs[1], ys[0], ys[1], float(hl.Z - Zr) * (1.f / 256.f), k, smx, A.cov0);
     }
-    // pass 1: the segments in link order, every hit after the first
+    // pass 1: hits 1 .. n-1 in chain order, the next record loaded ahead of the step
+    int nmax = ok ? n : 0;
+    for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, __shfl_xor(nmax, d));
+    Cursor c;
+    uint64_t nxt = 0;
+    int nu = 0;
     if (ok) {
       kf_update(s, 0.f, 0.f, sy2, sz2);
-      int first = 1;
-      for (int32_t q = int32_t(t); ok && q >= 0; q = A.next[q]) {
-        const int nq = A.n_hits[q];
-        for (int j = first; ok && j < nq; ++j) {
-          const CHit h = chain_hit(A, q, j);
-          if (h.u != cu) {  // into the next segment's frame, re-based on this hit
-            float ya = s.p[0] + float(Yr) * (1.f / 256.f);
-            if (!turn32(s, frame_turn(A, cu, h.u), ya, k, smx)) {
-              ok = false;
-              break;
-            }
-            cu = h.u;
-            Yr = h.Y;
-            s.p[0] = ya - float(Yr) * (1.f / 256.f);
-          }
-          Step st;
-          if (!step_prepare(s, h.x, k, smx, st)) {
-            ok = false;
-            break;
-          }
-          step_apply(s, st, h.x, k);
-          upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
-        }
-        first = 0;
+      seg_at(A, c, int32_t(t), 0);
+      step_fwd(A, c);
+      nxt = c.R[c.j];
+      nu = c.u;
+    }
+    for (int i = 1; i < nmax; ++i) {
+      const uint64_t cur = nxt;
+      const int u = nu;
+      if (ok && i + 1 < n) {
+        step_fwd(A, c);
+        nxt = c.R[c.j];
+        nu = c.u;
       }
+      if (!ok || i >= n) continue;
+      if (!chain_step(A, s, unpack(cur), u, cu, Yr, Zr, k, smx, sy2, sz2)) ok = false;
     }
     // pass 2: from the last hit back, covariance reset, turning back at each change of frame
-    if (ok) {
+    if (ok) {  // the cursor is on the last hit
       cov_reset(s, A.cov0);
       s.chi2 = 0.f;
-      const CHit hl = chain_hit(A, tail, A.n_hits[tail] - 1);
+      const Hit hl = unpack(nxt);
       upd_hit(s, make_int2(hl.Y, hl.Z), Yr, Zr, sy2, sz2);
-      int skip = 1, g = 0;
-      for (int32_t q = tail; ok && q >= 0 && g <= MAX_CHAIN; q = A.prev[q], ++g) {
-        for (int j = A.n_hits[q] - 1 - skip; ok && j >= 0; --j) {
-          const CHit h = chain_hit(A, q, j);
-          if (h.u != cu) {
-            float ya = s.p[0] + float(Yr) * (1.f / 256.f);
-            if (!turn32(s, frame_turn(A, cu, h.u), ya, k, smx)) {
-              ok = false;
-              break;
-            }
-            cu = h.u;
-            Yr = h.Y;
-            s.p[0] = ya - float(Yr) * (1.f / 256.f);
-          }
-          Step st;
-          if (!step_prepare(s, h.x, k, smx, st)) {
-            ok = false;
-            break;
-          }
-          step_apply(s, st, h.x, k);
-          upd_hit(s, make_int2(h.Y, h.Z), Yr, Zr, sy2, sz2);
-        }
-        skip = 0;
-        if (q == int32_t(t)) break;
-      }
+      step_bwd(A, c);
+      nxt = c.R[c.j];
+      nu = c.u;
     }
+    for (int i = nmax - 2; i >= 0; --i) {
+      const bool mine = ok && i <= n - 2;
+      const uint64_t cur = nxt;
+      const int u = nu;
+      if (mine && i >= 1) {
+        step_bwd(A, c);
+        nxt = c.R[c.j];
+        nu = c.u;
+      }
+      if (!mine) continue;
+      if (!chain_step(A, s, unpack(cur), u, cu, Yr, Zr, k, smx, sy2, sz2)) ok = false;
+    }
+    if (!valid) continue;
     A.ok[t] = ok ? 1 : 0;
     A.par[t * 5 + 0] = ok ? s.p[0] + float(Yr) * (1.f / 256.f) : 0.f;
     A.par[t * 5 + 1] = ok ? s.p[1] + float(Zr) * (1.f / 256.f) : 0.f;
