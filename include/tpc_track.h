@@ -548,8 +548,8 @@ typedef struct tpc_chain_fit {
                                   range; a track's hits lie outside the first counts[1] entries of
                                   hits; the links do not form chains of at most 64 segments: next
                                   and prev not mutual, a link to no track of the call, a closed
-                                  loop; a linked track's unit outside 0 .. n_units - 1); outputs
-                                  are valid only with TPC_OK */
+                                  loop; a chain segment without hits; a linked track's unit
+                                  outside 0 .. n_units - 1); outputs are valid only with TPC_OK */
 } tpc_chain_fit_t;
 
 /* Fit the chains of a tpc_merge_tracks output: the tracking call's clusters,

@@ -289,8 +289,9 @@ def test_chain_fit_edge_cases(T):
     no tracks at all give no chains.  A failed tracking or merging status
     passes through.  Links that are not mutual, name no track of the call,
     close a loop, or make a chain of more than 64 segments (64 is fine), a
-    linked track's unit out of range, a track's hits outside the hit list and
-    a hit naming no cluster give TPC_E_INVALID."""
+    chain segment without hits, a linked track's unit out of range, a track's
+    hits outside the hit list and a hit naming no cluster give
+    TPC_E_INVALID."""
     seg = [0.0] * 5
     ev, dt, _ = _hand_tracks([0, 0, 0], [(0, 10), (11, 40), (50, 60)], [seg] * 3, [seg] * 3)
     alpha = [0.0]
@@ -333,3 +334,8 @@ def test_chain_fit_edge_cases(T):
         assert _chain_status(ev, dth, [1, -1, -1], [-1, 0, -1], alpha) == bad, (f2, n2)
     dtx = DeviceTracks(ev.n, first, nh, np.array([0, 1, 2, 99, 4, 5]), unit=np.zeros(3))
     assert _chain_status(ev, dtx, [1, -1, -1], [-1, 0, -1], alpha) == bad
+    # a chain segment without hits (at the head, inside, at the tail); unlinked, it is fine
+    dte = DeviceTracks(ev.n, np.array([0, 2, 2]), np.array([2, 0, 4]), hits, unit=np.zeros(3))
+    for nx, pv in (([1, 2, -1], [-1, 0, 1]), ([2, -1, 1], [-1, 2, 0]), ([-1, 0, -1], [1, -1, -1])):
+        assert _chain_status(ev, dte, nx, pv, alpha) == bad, (nx, pv)
+    assert _chain_status(ev, dte, [2, -1, -1], [-1, -1, 0], alpha) == 0
