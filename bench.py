@@ -890,20 +890,35 @@ def merge_bench(dev, tr, batch, ev, reps, workload):
     e1.record()
     torch.cuda.synchronize(dev)
     cms = e0.elapsed_time(e1) / reps
+    c2 = {k: v.cpu().numpy() for k, v in cfit.result(n_tracks).items()}
+    if not all(np.array_equal(c[k], c2[k]) for k in c):
+        raise RuntimeError("graph replay and eager call of the chain fit disagree")
     del graph
     heads = np.nonzero(c["n_hits"] > 0)[0]
     ok = c["ok"][heads].astype(bool)
     h = heads[ok]
     chi2_ndf = c["chi2"][h] / np.maximum(1, 2 * c["n_hits"][h] - 5)
+    cupd = int(2 * c["n_hits"][h].sum())  # every hit is updated once per pass
+    cflops = cupd * FIT_OPS_PER_UPDATE
+    ctfs = cflops / (cms * 1e-3) / 1e12
     # q/pT against the generated particle: the chain fit and its head segment's own refit
     p = maj[h]
     g = p >= 0
     true_qpt = ev.tracks.q[p[g]] / ev.tracks.pt[p[g]]
     seg = rf.result(n_tracks, sync=False)["params"].cpu().numpy()
-    out["chain_fit"] = dict(ms_per_call=cms, chains=int(len(heads)), fitted_fraction=float(ok.mean()) if len(heads) else None,
+    out["chain_fit"] = dict(ms_per_call=cms, chains=int(len(heads)), launches=8,
+                            fitted_fraction=float(ok.mean()) if len(heads) else None,
                             hits=int(c["n_hits"][heads].sum()), chi2_per_ndf_median=float(np.median(chi2_ndf)) if len(h) else None,
                             qpt_rel_error_median=dict(chain=float(np.median(np.abs(c["params"][h][g, 4] / true_qpt - 1))),
-                                                      head_segment=float(np.median(np.abs(seg[h][g, 4] / true_qpt - 1)))))
+                                                      head_segment=float(np.median(np.abs(seg[h][g, 4] / true_qpt - 1)))),
+                            # the method's FP32 operations per hit update, as for the refit; every
+                            # chain's wave is resident at once, so the longest chains' dependent
+                            # steps (latency) set the time, not the issue rate
+                            roofline=dict(bound="alu", kernel="k_ch_fit (whole call timed)", achieved=ctfs,
+                                          peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=ctfs / FP32_PEAK_TFLOPS,
+                                          hit_updates_per_launch=cupd, ops_per_update=FIT_OPS_PER_UPDATE,
+                                          algorithmic_flops_per_launch=cflops, traffic=None,
+                                          limited_by="latency of the longest chains"))
     log("bench: merge " + json.dumps(out))
     return out
 
