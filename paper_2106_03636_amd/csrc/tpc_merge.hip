@@ -59,6 +59,13 @@ struct __align__(16) Filed {
   float z, y, x;  // inner z', y and x
   int32_t fr;     // first row
 };
+// and as the chi2 of a pair reads it: its inner state, unit and track index
+struct __align__(16) Inner {
+  float p[5], x;
+  int32_t unit, b;
+  float c[15], pad;
+};
+static_assert(sizeof(Inner) == 96, "six 16-byte loads");
 
 struct MgArgs {
   // clusters, geometry
@@ -93,6 +100,7 @@ struct MgArgs {
   int32_t *cursor;
   int32_t *idx;
   Filed *filed;   // the filed segments, in scan order
+  Inner *inner;   // their inner states, in the same order
   int32_t *frs;    // their first rows, in filing order (the sort's key)
   int32_t *rows;  // first row | last row << 16
   unsigned long long *ob_chi, *ib_chi;
@@ -129,7 +137,7 @@ __device__ double asin_over_d(double u) {
 // new state at the new plane against the old one (a shift of the track along
 // the old y, taken back to the new plane along the track; a turn of the
 // direction).  False when the direction reaches |sin| >= smx or cos <= 0.
-__device__ bool turn(const double p[5], double x, double d, double k, double smx, double q[5], double &xq,
+__device__ __forceinline__ bool turn(const double p[5], double x, double d, double k, double smx, double q[5], double &xq,
                      double *J) {
 #pragma clang fp contract(off)
   const double cd = cos(d), sd = sin(d);
@@ -145,6 +153,7 @@ __device__ bool turn(const double p[5], double x, double d, double k, double smx
   q[3] = p[3];
   q[4] = p[4];
   if (J) {
+#pragma unroll
     for (int i = 0; i < 25; ++i) J[i] = (i % 6 == 0) ? 1.0 : 0.0;
     J[0] = c / c2;
     J[5] = -sd * p[3] / c2;
@@ -158,7 +167,7 @@ __device__ bool turn(const double p[5], double x, double d, double k, double smx
 // y by dx (sin1 + sin2) / (cos1 + cos2), z by tan(lambda) times the arc
 // length sign(dx) L asin(u)/u (L the chord, u = |C| L / 2).  F (optional):
 // its Jacobian.  False when |sin(phi)| reaches smx at either end or u >= 1.
-__device__ bool carry(const double p[5], double x1, double x2, double k, double smx, double q[5], double *F) {
+__device__ __forceinline__ bool carry(const double p[5], double x1, double x2, double k, double smx, double q[5], double *F) {
 #pragma clang fp contract(off)
   const double dx = x2 - x1;
   const double C = k * p[4];
@@ -179,6 +188,7 @@ __device__ bool carry(const double p[5], double x1, double x2, double k, double 
   q[3] = p[3];
   q[4] = p[4];
   if (F) {
+#pragma unroll
     for (int i = 0; i < 25; ++i) F[i] = (i % 6 == 0) ? 1.0 : 0.0;
     const double a = dx * ((2.0 * D + N * (s1 / c1 + s2 / c2)) / (D * D));
     const double b = dx * (k * dx * (D + N * s2 / c2) / (D * D));
@@ -212,37 +222,49 @@ __device__ bool carry_y(const double p[5], double x1, double x2, double k, doubl
 }
 
 // C <- M C M^T (5x5, full products)
-__device__ void sandwich(const double M[25], double C[25]) {
+__device__ __forceinline__ void sandwich(const double M[25], double C[25]) {
 #pragma clang fp contract(off)
   double T[25];
+#pragma unroll
   for (int i = 0; i < 5; ++i)
+#pragma unroll
     for (int j = 0; j < 5; ++j) {
       double s = 0.0;
+#pragma unroll
       for (int l = 0; l < 5; ++l) s += M[i * 5 + l] * C[l * 5 + j];
       T[i * 5 + j] = s;
     }
+#pragma unroll
   for (int i = 0; i < 5; ++i)
+#pragma unroll
     for (int j = 0; j < 5; ++j) {
       double s = 0.0;
+#pragma unroll
       for (int l = 0; l < 5; ++l) s += T[i * 5 + l] * M[j * 5 + l];
       C[i * 5 + j] = s;
     }
 }
 
-__device__ void load_cov(const float *c15, double C[25]) {
+__device__ __forceinline__ void load_cov(const float *c15, double C[25]) {
   int m = 0;
+#pragma unroll
   for (int i = 0; i < 5; ++i)
+#pragma unroll
     for (int j = 0; j <= i; ++j) C[i * 5 + j] = C[j * 5 + i] = double(c15[m++]);
 }
 
 // r^T S^-1 r by Cholesky; -1 when S is not positive definite
-__device__ double chi2_solve(const double S[25], const double r[5]) {
+__device__ __forceinline__ double chi2_solve(const double S[25], const double r[5]) {
 #pragma clang fp contract(off)
   double L[25];
+#pragma unroll
   for (int i = 0; i < 25; ++i) L[i] = 0.0;
+#pragma unroll
   for (int i = 0; i < 5; ++i)
+#pragma unroll
     for (int j = 0; j <= i; ++j) {
       double v = S[i * 5 + j];
+#pragma unroll
       for (int m = 0; m < j; ++m) v -= L[i * 5 + m] * L[j * 5 + m];
       if (i == j) {
         if (!(v > 0.0)) return -1.0;
@@ -252,8 +274,10 @@ __device__ double chi2_solve(const double S[25], const double r[5]) {
       }
     }
   double w[5], q = 0.0;
+#pragma unroll
   for (int i = 0; i < 5; ++i) {
     double v = r[i];
+#pragma unroll
     for (int m = 0; m < i; ++m) v -= L[i * 5 + m] * w[m];
     w[i] = v / L[i * 5 + i];
     q += w[i] * w[i];
@@ -375,6 +399,14 @@ __device__ __forceinline__ void file_entry(const MgArgs &A, int32_t s, int32_t b
   f.x = A.x_in[b];
   f.fr = fr;
   A.filed[s] = f;
+  Inner r;
+  for (int j = 0; j < 5; ++j) r.p[j] = A.p_in[int64_t(b) * 5 + j];
+  r.x = f.x;
+  r.unit = A.unit[b];
+  r.b = b;
+  for (int j = 0; j < 15; ++j) r.c[j] = A.c_in[int64_t(b) * 15 + j];
+  r.pad = 0.f;
+  A.inner[s] = r;
 }
 
 __global__ void __launch_bounds__(64) k_mg_sort(MgArgs A) {
@@ -482,7 +514,7 @@ __global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
             flush(A, int32_t(a), buf, nbuf);
             nbuf = 0;
           }
-          buf[nbuf++ * TPB] = A.idx[s];
+          buf[nbuf++ * TPB] = s;  // the filed slot; k_mg_chi2 puts the track index in its place
         }
       }
     }
@@ -499,28 +531,33 @@ __global__ void __launch_bounds__(TPB) k_mg_chi2(MgArgs A) {
   }
   for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < int64_t(np); i += int64_t(gridDim.x) * TPB) {
     const int2 pr = A.pairs[i];
-    const int a = pr.x, b = pr.y;
-    const int ua = A.unit[a], ub = A.unit[b];
-    double pa[5], C[25], M[25], q[5], c[5];
+    const int a = pr.x;
+    const Inner bi = A.inner[pr.y];  // b's inner state, filed next to the other candidates of a's cells
+    const int b = bi.b, ub = bi.unit;
+    A.pairs[i].y = b;                // k_mg_pick reads track indices
+    const int ua = A.unit[a];
+    double pa[5], C[25], q[5], c[5];
     for (int j = 0; j < 5; ++j) pa[j] = double(A.p_out[a * 5 + j]);
     load_cov(A.c_out + int64_t(a) * 15, C);
     double xq = double(A.x_out[a]);
     double chi = -1.0;
     bool ok = true;
     if (ua != ub) {
-      ok = turn(pa, double(A.x_out[a]), turn_angle(A, ua, ub), A.k, A.smx, q, xq, M);
-      if (ok) sandwich(M, C);
+      double J[25];
+      ok = turn(pa, double(A.x_out[a]), turn_angle(A, ua, ub), A.k, A.smx, q, xq, J);
+      if (ok) sandwich(J, C);
     } else {
       for (int j = 0; j < 5; ++j) q[j] = pa[j];
     }
-    if (ok) ok = carry(q, xq, double(A.x_in[b]), A.k, A.smx, c, M);
+    double F[25];
+    if (ok) ok = carry(q, xq, double(bi.x), A.k, A.smx, c, F);
     if (ok) {
 #pragma clang fp contract(off)
-      sandwich(M, C);
+      sandwich(F, C);
       double Cb[25], r[5];
-      load_cov(A.c_in + int64_t(b) * 15, Cb);
+      load_cov(bi.c, Cb);
       for (int j = 0; j < 25; ++j) C[j] += Cb[j];
-      for (int j = 0; j < 5; ++j) r[j] = double(A.p_in[b * 5 + j]) - c[j];
+      for (int j = 0; j < 5; ++j) r[j] = double(bi.p[j]) - c[j];
       chi = chi2_solve(C, r);
     }
     A.pair_chi[i] = chi;
@@ -571,7 +608,7 @@ __global__ void k_mg_counts(MgArgs A) {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t bin, cursor, idx, filed, frs, rows, ob_chi, ib_chi, ob_idx, ib_idx, pairs, pair_chi, ctr, total;
+  size_t bin, cursor, idx, filed, inner, frs, rows, ob_chi, ib_chi, ob_idx, ib_idx, pairs, pair_chi, ctr, total;
 };
 
 Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
@@ -586,6 +623,7 @@ Layout layout(int64_t nbins, int64_t cap_tracks, int64_t cap_pairs) {
   L.cursor = take(size_t(nbins) * 4);
   L.idx = take(size_t(cap_tracks) * 4);
   L.filed = take(size_t(cap_tracks) * sizeof(Filed));
+  L.inner = take(size_t(cap_tracks) * sizeof(Inner));
   L.frs = take(size_t(cap_tracks) * 4);
   L.rows = take(size_t(cap_tracks) * 4);
   L.ob_chi = take(size_t(cap_tracks) * 8);
@@ -700,6 +738,7 @@ extern "C" int tpc_merge_tracks(const tpc_clusters_t *clusters, const tpc_geomet
   A.cursor = reinterpret_cast<int32_t *>(w + L.cursor);
   A.idx = reinterpret_cast<int32_t *>(w + L.idx);
   A.filed = reinterpret_cast<Filed *>(w + L.filed);
+  A.inner = reinterpret_cast<Inner *>(w + L.inner);
   A.frs = reinterpret_cast<int32_t *>(w + L.frs);
   A.rows = reinterpret_cast<int32_t *>(w + L.rows);
   A.ob_chi = reinterpret_cast<unsigned long long *>(w + L.ob_chi);
