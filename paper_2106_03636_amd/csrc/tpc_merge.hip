@@ -19,10 +19,10 @@
 //               candidate, and neighbouring lanes share its cache lines);
 //   k_mg_pairs  one lane per segment a: for each unit on its side within
 //               max_dalpha, its outer state turned into that unit's frame
-//               (parameters, FP64); in each cell its z' window meets, a
-//               binary search finds the first segment starting after a's
-//               last row, and the segments up to max_gap rows later are
-//               checked: z' window, then y carried along the helix
+//               (parameters, FP64); in each cell its z' window meets, two
+//               binary searches find the segments starting 1 .. max_gap rows
+//               after a's last row, whose records are loaded a few at a time
+//               and checked: z' window, then y carried along the helix
 //               (parameters only); pairs that pass are buffered per lane in
 //               LDS and go to a list with one atomic per lane at the end (an
 //               atomic per pair would make each wave wait on its return);
@@ -466,6 +466,17 @@ __device__ __forceinline__ void flush(const MgArgs &A, int32_t a, const int32_t 
     if (base + i < (unsigned long long)A.cap_pairs) A.pairs[base + i] = make_int2(a, buf[i * TPB]);
 }
 
+// first position in [lo, hi) of a cell (sorted by first row) whose first row is above r
+__device__ __forceinline__ int32_t after_row(const MgArgs &A, int32_t lo, int32_t hi, int r) {
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (A.filed[mid].fr <= r) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+constexpr int SCAN_B = 4;  // candidate records loaded together
+
 __global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
   // each lane's pair buffer: a column of a [PAIR_BUF][TPB] block (lanes side by side)
   __shared__ int32_t pbuf[PAIR_BUF * TPB];
@@ -497,24 +508,28 @@ __global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
       for (int cz = c0; cz <= c1; ++cz) {
         const int32_t s0 = A.bin[w * A.nzc + cz], s1 = A.bin[w * A.nzc + cz + 1];
         if (s0 == s1) continue;
-        // the cell is sorted by first row: the first segment starting after row lr
-        int32_t lo = s0, hi = s1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (A.filed[mid].fr <= lr) lo = mid + 1; else hi = mid;
-        }
-        for (int32_t s = lo; s < s1; ++s) {
-          const Filed f = A.filed[s];
-          if (f.fr > r1) break;
-          double y;
-          if (!(fabs(double(f.z) - za) <= A.dz_max) || !carry_y(q, xq, double(f.x), A.k, A.smx, y) ||
-              !(fabs(double(f.y) - y) <= A.dy_max))
-            continue;
-          if (nbuf == PAIR_BUF) {
-            flush(A, int32_t(a), buf, nbuf);
-            nbuf = 0;
+        // the cell is sorted by first row: the segments starting in rows lr+1 .. r1,
+        // their records loaded SCAN_B at a time (the range is known, so no load
+        // waits on the one before)
+        const int32_t lo = after_row(A, s0, s1, lr), hi = after_row(A, lo, s1, r1);
+        for (int32_t s = lo; s < hi; s += SCAN_B) {
+          Filed f[SCAN_B];
+#pragma unroll
+          for (int e = 0; e < SCAN_B; ++e)
+            if (s + e < hi) f[e] = A.filed[s + e];
+#pragma unroll
+          for (int e = 0; e < SCAN_B; ++e) {
+            if (s + e >= hi) break;
+            double y;
+            if (!(fabs(double(f[e].z) - za) <= A.dz_max) || !carry_y(q, xq, double(f[e].x), A.k, A.smx, y) ||
+                !(fabs(double(f[e].y) - y) <= A.dy_max))
+              continue;
+            if (nbuf == PAIR_BUF) {
+              flush(A, int32_t(a), buf, nbuf);
+              nbuf = 0;
+            }
+            buf[nbuf++ * TPB] = s + e;  // the filed slot; k_mg_chi2 puts the track index in its place
           }
-          buf[nbuf++ * TPB] = s;  // the filed slot; k_mg_chi2 puts the track index in its place
         }
       }
     }
