@@ -10,8 +10,8 @@ Bars (the FP32 GPU fit against the FP64 oracle fit):
     limit);
   * fitted parameters of identical hit sets: |dp_k| <= 1e-4 max(|p_k|, f_k)
     with floors f = (1 cm, 1 cm, 1e-2, 1e-2, 0.1 /GeV) for at least 99.9% of
-    the fitted tracklets (the benchmark spec's 1e-4 relative, read as a bar on
-    the bulk); every tracklet within max(that, 0.21 sigma_k) and at most
+    the fitted tracklets (the stated 1e-4 relative tolerance, read as a bar
+    on the bulk); every tracklet within max(that, 0.21 sigma_k) and at most
     0.003% beyond max(that, 0.1 sigma_k) (sigma from the oracle's
     covariance); chi2 within 1e-3 relative (floor 1) for 99.98% and within
     2e-2 for all; covariance diagonal within 4.7e-2 for all, within 1e-2 for

@@ -171,8 +171,8 @@ def test_chi2_clauses_are_no_looser_than_fp32(tails):
     assert 1.0 - parity.MIN_CHI2_FRACTION <= 1.5 * (1.0 - _worst(tails, "chi2_within_1e3", min))
 
 
-def test_relative_clause_is_the_north_star_figure(tails):
-    """The 1e-4 relative clause is the benchmark spec's own figure (99.9% of
+def test_relative_clause_is_the_stated_tolerance(tails):
+    """The 1e-4 relative clause is the tolerance the fit is held to (99.9% of
     fitted tracklets), not derived from FP32 tails: FP32 in absolute
     coordinates reaches only about 90% there, which is why the kernel keeps
     its state relative to exact integer references."""
