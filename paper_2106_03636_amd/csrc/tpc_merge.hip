@@ -383,12 +383,17 @@ __global__ void __launch_bounds__(TPB) k_mg_fill(MgArgs A) {
   }
 }
 
-// Adds the number of active lanes with `take` to a counter: one atomic per
-// wave, whose result nobody waits for.
-__device__ __forceinline__ void count(unsigned long long &counter, bool take) {
-  const unsigned long long m = __ballot(take);
-  const int leader = __ffsll((long long)__ballot(1)) - 1;  // lowest active lane
-  if (__lane_id() == leader && m) atomicAdd(&counter, (unsigned long long)__popcll(m));
+// Adds the block's total of the threads' v to a counter with one atomic per
+// block (the counter is shared by the whole grid: an atomic per wave on the
+// one address serialized thousands of them).  Called by every thread of the
+// block, after its loop.
+__device__ __forceinline__ void block_count(unsigned long long &counter, unsigned v) {
+  __shared__ unsigned s;
+  if (threadIdx.x == 0) s = 0u;
+  __syncthreads();
+  if (v) atomicAdd(&s, v);
+  __syncthreads();
+  if (threadIdx.x == 0 && s) atomicAdd(&counter, (unsigned long long)s);
 }
 
 __device__ __forceinline__ void file_entry(const MgArgs &A, int32_t s, int32_t b, int32_t fr) {
@@ -544,6 +549,7 @@ __global__ void __launch_bounds__(TPB) k_mg_chi2(MgArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *A.status = TPC_E_CAPACITY;
     return;
   }
+  unsigned n_cand = 0;
   for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < int64_t(np); i += int64_t(gridDim.x) * TPB) {
     const int2 pr = A.pairs[i];
     const int a = pr.x;
@@ -582,8 +588,9 @@ __global__ void __launch_bounds__(TPB) k_mg_chi2(MgArgs A) {
       atomicMin(&A.ob_chi[a], bits);
       atomicMin(&A.ib_chi[b], bits);
     }
-    count(A.ctr[1], cand);
+    n_cand += cand;
   }
+  block_count(A.ctr[1], n_cand);
 }
 
 __global__ void __launch_bounds__(TPB) k_mg_pick(MgArgs A) {
@@ -602,6 +609,7 @@ __global__ void __launch_bounds__(TPB) k_mg_pick(MgArgs A) {
 __global__ void __launch_bounds__(TPB) k_mg_link(MgArgs A) {
   if (*A.status != TPC_OK) return;
   const int64_t T = n_tracks(A);
+  unsigned n_link = 0;
   for (int64_t a = int64_t(blockIdx.x) * TPB + threadIdx.x; a < T; a += int64_t(gridDim.x) * TPB) {
     const int32_t b = A.ob_idx[a];
     const bool link = b != INT32_MAX && A.ib_idx[b] == int32_t(a);
@@ -610,8 +618,9 @@ __global__ void __launch_bounds__(TPB) k_mg_link(MgArgs A) {
       A.prev[b] = int32_t(a);
       A.link_chi2[a] = __longlong_as_double((long long)A.ob_chi[a]);
     }
-    count(A.ctr[2], link);
+    n_link += link;
   }
+  block_count(A.ctr[2], n_link);
 }
 
 __global__ void k_mg_counts(MgArgs A) {
