@@ -24,8 +24,10 @@
 //               after a's last row, whose records are loaded a few at a time
 //               and checked: z' window, then y carried along the helix
 //               (parameters only); pairs that pass are buffered per lane in
-//               LDS and go to a list with one atomic per lane at the end (an
-//               atomic per pair would make each wave wait on its return);
+//               LDS, and one atomic per wave reserves the list ranges of all
+//               its lanes at the end (an atomic per pair, or per lane, on the
+//               one counter would serialize them; a full buffer is flushed
+//               by its lane alone);
 //   k_mg_chi2   one lane per pair: the turn with its Jacobian, the helix
 //               transport with its Jacobian, both covariances summed, chi2
 //               by Cholesky (FP64); candidates take the least chi2 per
@@ -482,65 +484,87 @@ __device__ __forceinline__ int32_t after_row(const MgArgs &A, int32_t lo, int32_
 
 constexpr int SCAN_B = 4;  // candidate records loaded together
 
+// The candidates of segment a (refitted, its last row below the last row):
+// pairs into the lane's buffer, a full buffer flushed on its own.
+__device__ __forceinline__ void scan_segment(const MgArgs &A, int64_t a, int lr, int32_t *buf, int &nbuf) {
+  const int ua = A.unit[a];
+  const int r1 = min(lr + A.max_gap, A.n_rows - 1);
+  double pa[5];
+  for (int i = 0; i < 5; ++i) pa[i] = double(A.p_out[a * 5 + i]);
+  const double xa = double(A.x_out[a]);
+  const double za = pa[1];
+  for (int w = 0; w < A.n_units; ++w) {
+    if (A.side[w] != A.side[ua]) continue;
+    const double d = turn_angle(A, ua, w);
+    if (!(fabs(d) <= A.max_dalpha)) continue;
+    double q[5], xq = xa;
+    if (w == ua) {
+      for (int i = 0; i < 5; ++i) q[i] = pa[i];
+    } else if (!turn(pa, xa, d, A.k, A.smx, q, xq, nullptr)) {
+      continue;
+    }
+    const int c0 = zcell(A, za - A.dz_max), c1 = zcell(A, za + A.dz_max);
+    for (int cz = c0; cz <= c1; ++cz) {
+      const int32_t s0 = A.bin[w * A.nzc + cz], s1 = A.bin[w * A.nzc + cz + 1];
+      if (s0 == s1) continue;
+      // the cell is sorted by first row: the segments starting in rows lr+1 .. r1,
+      // their records loaded SCAN_B at a time (the range is known, so no load
+      // waits on the one before)
+      const int32_t lo = after_row(A, s0, s1, lr), hi = after_row(A, lo, s1, r1);
+      for (int32_t s = lo; s < hi; s += SCAN_B) {
+        Filed f[SCAN_B];
+#pragma unroll
+        for (int e = 0; e < SCAN_B; ++e)
+          if (s + e < hi) f[e] = A.filed[s + e];
+#pragma unroll
+        for (int e = 0; e < SCAN_B; ++e) {
+          if (s + e >= hi) break;
+          double y;
+          if (!(fabs(double(f[e].z) - za) <= A.dz_max) || !carry_y(q, xq, double(f[e].x), A.k, A.smx, y) ||
+              !(fabs(double(f[e].y) - y) <= A.dy_max))
+            continue;
+          if (nbuf == PAIR_BUF) {
+            flush(A, int32_t(a), buf, nbuf);
+            nbuf = 0;
+          }
+          buf[nbuf++ * TPB] = s + e;  // the filed slot; k_mg_chi2 puts the track index in its place
+        }
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(TPB) k_mg_pairs(MgArgs A) {
   // each lane's pair buffer: a column of a [PAIR_BUF][TPB] block (lanes side by side)
   __shared__ int32_t pbuf[PAIR_BUF * TPB];
   int32_t *buf = pbuf + threadIdx.x;
   if (*A.status != TPC_OK) return;
   const int64_t T = n_tracks(A);
-  for (int64_t a = int64_t(blockIdx.x) * TPB + threadIdx.x; a < T; a += int64_t(gridDim.x) * TPB) {
-    if (!A.ok[a]) continue;
+  const int lane = __lane_id();
+  for (int64_t a0 = int64_t(blockIdx.x) * TPB; a0 < T; a0 += int64_t(gridDim.x) * TPB) {
+    const int64_t a = a0 + threadIdx.x;
+    if ((a & ~int64_t(63)) >= T) break;  // whole wave past the tracks (wave-uniform)
     int nbuf = 0;
-    const int ua = A.unit[a];
-    const int lr = A.rows[a] >> 16;
-    if (lr + 1 >= A.n_rows) continue;
-    const int r1 = min(lr + A.max_gap, A.n_rows - 1);
-    double pa[5];
-    for (int i = 0; i < 5; ++i) pa[i] = double(A.p_out[a * 5 + i]);
-    const double xa = double(A.x_out[a]);
-    const double za = pa[1];
-    for (int w = 0; w < A.n_units; ++w) {
-      if (A.side[w] != A.side[ua]) continue;
-      const double d = turn_angle(A, ua, w);
-      if (!(fabs(d) <= A.max_dalpha)) continue;
-      double q[5], xq = xa;
-      if (w == ua) {
-        for (int i = 0; i < 5; ++i) q[i] = pa[i];
-      } else if (!turn(pa, xa, d, A.k, A.smx, q, xq, nullptr)) {
-        continue;
-      }
-      const int c0 = zcell(A, za - A.dz_max), c1 = zcell(A, za + A.dz_max);
-      for (int cz = c0; cz <= c1; ++cz) {
-        const int32_t s0 = A.bin[w * A.nzc + cz], s1 = A.bin[w * A.nzc + cz + 1];
-        if (s0 == s1) continue;
-        // the cell is sorted by first row: the segments starting in rows lr+1 .. r1,
-        // their records loaded SCAN_B at a time (the range is known, so no load
-        // waits on the one before)
-        const int32_t lo = after_row(A, s0, s1, lr), hi = after_row(A, lo, s1, r1);
-        for (int32_t s = lo; s < hi; s += SCAN_B) {
-          Filed f[SCAN_B];
+    const int lr = a < T ? A.rows[a] >> 16 : 0;
+    if (a < T && A.ok[a] && lr + 1 < A.n_rows) scan_segment(A, a, lr, buf, nbuf);
+    // the lanes' buffered pairs: one atomic per wave reserves all their ranges
+    // (an atomic per lane on the one counter would serialize them)
+    int incl = nbuf;
 #pragma unroll
-          for (int e = 0; e < SCAN_B; ++e)
-            if (s + e < hi) f[e] = A.filed[s + e];
-#pragma unroll
-          for (int e = 0; e < SCAN_B; ++e) {
-            if (s + e >= hi) break;
-            double y;
-            if (!(fabs(double(f[e].z) - za) <= A.dz_max) || !carry_y(q, xq, double(f[e].x), A.k, A.smx, y) ||
-                !(fabs(double(f[e].y) - y) <= A.dy_max))
-              continue;
-            if (nbuf == PAIR_BUF) {
-              flush(A, int32_t(a), buf, nbuf);
-              nbuf = 0;
-            }
-            buf[nbuf++ * TPB] = s + e;  // the filed slot; k_mg_chi2 puts the track index in its place
-          }
-        }
-      }
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
     }
-    flush(A, int32_t(a), buf, nbuf);
+    const int total = __shfl(incl, 63, 64);
+    long long base = 0;
+    if (lane == 63 && total) base = (long long)atomicAdd(&A.ctr[0], (unsigned long long)total);
+    base = __shfl(base, 63, 64);
+    const unsigned long long mine = (unsigned long long)base + (unsigned long long)(incl - nbuf);
+    for (int i = 0; i < nbuf; ++i)
+      if (mine + i < (unsigned long long)A.cap_pairs) A.pairs[mine + i] = make_int2(int32_t(a), buf[i * TPB]);
   }
 }
+
 
 __global__ void __launch_bounds__(TPB) k_mg_chi2(MgArgs A) {
   if (*A.status != TPC_OK) return;
